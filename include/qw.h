@@ -1,0 +1,266 @@
+/*
+ * qw.h -- C ABI of libqw, the MI355X (gfx950) prefix-reuse statevector path.
+ *
+ * The path follows the paper's statement of the problem (Sec. I and Fig. 1,
+ * Sec. III-A "Execution"): tasks of a workload share a gate prefix; the
+ * prefix is executed once, the exact boundary state |psi_B> is materialised
+ * as a typed artifact (Sec. IV-B, ArtifactRecord), and every task's suffix is
+ * re-run from it; each continuation first passes the three legality gates of
+ * Sec. IV-B (exactness, backend family, conversion rule of Table II) and is
+ * otherwise refused with the structured record of the EVAL-7 example.
+ *
+ * Conventions for every call
+ *   - Qubit q is bit q of the basis index (little-endian). A state of n
+ *     qubits is 2^n complex64 amplitudes (interleaved re, im; 8 bytes each),
+ *     slot s of a state starting at byte offset s * 8 * 2^n.
+ *   - All device work is enqueued, in call order, on the HIP stream given to
+ *     qw_ctx_create; calls return when the work is enqueued unless stated.
+ *   - Every call returns a status (QW_OK = 0 on success). On failure no
+ *     output is written and qw_last_error() describes the failure.
+ *   - Pointers named host_* or documented as host memory are read during the
+ *     call only; the library keeps no reference to them.
+ *   - Not thread-safe per context: use one context per host thread.
+ */
+#ifndef QW_H
+#define QW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status */
+#define QW_OK 0
+#define QW_E_INVALID_ARG 1  /* bad handle, size, index or gate              */
+#define QW_E_OOM 2          /* device or pinned host allocation failed      */
+#define QW_E_HIP 3          /* a HIP runtime call failed (message attached) */
+#define QW_E_REFUSED 4      /* a continuation failed a legality gate; the
+                               refusal record (JSON) is in qw_last_error()  */
+#define QW_E_UNSUPPORTED 5  /* valid request outside what the library does  */
+
+/* ------------------------------------------------------------ gates */
+/* Gate kinds. Matrices in the computational basis (|0>, |1>):
+ *   X = [[0,1],[1,0]]   Y = [[0,-i],[i,0]]   Z = diag(1,-1)
+ *   H = [[1,1],[1,-1]]/sqrt2   S = diag(1,i)   SDG = diag(1,-i)
+ *   T = diag(1,e^{i pi/4})     TDG = diag(1,e^{-i pi/4})
+ *   RX(t) = exp(-i t X/2)  RY(t) = exp(-i t Y/2)  RZ(t) = exp(-i t Z/2)
+ *   P(t) = diag(1, e^{i t})
+ *   CNOT: control q0, target q1: |b> -> |b xor (b_q0 << q1)>
+ *   CZ:   phase -1 when bits q0 and q1 are both 1
+ *   RENORM: no qubits; the state is divided by its norm (computed in FP64)
+ *           at this point of the gate list. */
+#define QW_GATE_X 0x01
+#define QW_GATE_Y 0x02
+#define QW_GATE_Z 0x03
+#define QW_GATE_H 0x04
+#define QW_GATE_S 0x05
+#define QW_GATE_SDG 0x06
+#define QW_GATE_T 0x07
+#define QW_GATE_TDG 0x08
+#define QW_GATE_RX 0x21
+#define QW_GATE_RY 0x22
+#define QW_GATE_RZ 0x23
+#define QW_GATE_P 0x24
+#define QW_GATE_CNOT 0x41
+#define QW_GATE_CZ 0x42
+#define QW_GATE_RENORM 0x81
+
+typedef struct qw_gate {
+    uint32_t kind;     /* QW_GATE_*                                     */
+    uint32_t q0;       /* qubit (control of CNOT)                       */
+    uint32_t q1;       /* second qubit (target of CNOT); else ignored   */
+    uint32_t reserved; /* must be 0                                     */
+    double param;      /* angle of RX/RY/RZ/P in radians; else ignored  */
+} qw_gate;             /* 24 bytes */
+
+/* ------------------------------------------------------------ artifacts */
+/* Typed artifact metadata (Sec. IV-B: kind, exactness class, provenance
+ * hash, producing backend family, size). */
+#define QW_KIND_STATEVECTOR 1 /* STATEVECTOR_BOUNDARY_STATE */
+#define QW_KIND_TABLEAU 2     /* TABLEAU_BOUNDARY_STATE     */
+
+#define QW_EXACTNESS_UNKNOWN 0
+#define QW_EXACT 1
+#define QW_APPROX 2
+
+#define QW_BACKEND_UNKNOWN 0
+#define QW_BACKEND_SV 1        /* this library: MI355X_SV_C64, statevector    */
+#define QW_BACKEND_STAB_ONLY 2 /* a stabilizer-only (tableau) backend family */
+
+typedef struct qw_artifact {
+    uint32_t kind;          /* QW_KIND_*                                  */
+    uint32_t exactness;     /* QW_EXACT / QW_APPROX / QW_EXACTNESS_UNKNOWN */
+    uint32_t backend;       /* producing backend family, QW_BACKEND_*     */
+    uint32_t n_qubits;
+    uint64_t bytes;         /* payload size                               */
+    uint8_t provenance[32]; /* Eq. (1) fingerprint of the producing prefix */
+} qw_artifact;
+
+/* Snapshot modes. COPY: the boundary state is copied into a buffer of its
+ * own (one read and one write of the state). FREEZE: the slot itself becomes
+ * the artifact (no data moves) and may not be written until the snapshot is
+ * freed. */
+#define QW_SNAP_COPY 0
+#define QW_SNAP_FREEZE 1
+
+typedef struct qw_ctx qw_ctx;
+typedef struct qw_state qw_state;
+typedef struct qw_snap qw_snap; /* a boundary snapshot (artifact) */
+
+/* One continuation: the suffix gates of a task and where its state goes. */
+typedef struct qw_task {
+    const qw_gate *gates;    /* host array of n_gates gates (may be NULL if 0) */
+    uint64_t n_gates;
+    uint32_t dst_slot;       /* slot of the destination state              */
+    uint32_t reserved;       /* must be 0                                  */
+    uint8_t expect_prov[32]; /* provenance the task expects of its source  */
+} qw_task;
+
+/* Optional expectation epilogue of qw_run_suffix_batch: for task k,
+ * out[k] = sum_j coeff[j] <psi_k| P_j |psi_k>, P_j given by (x_mask[j],
+ * z_mask[j]) as in qw_expect_pauli. Masks and coefficients are host arrays. */
+typedef struct qw_reduce {
+    const uint64_t *x_mask;
+    const uint64_t *z_mask;
+    const double *coeff;
+    uint32_t n_terms;
+    int32_t out_is_host;    /* 1: out is host memory (call synchronises)  */
+    double *out;            /* n_tasks doubles                             */
+} qw_reduce;
+
+/* ------------------------------------------------------------ context */
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). The stream is not owned. The
+ * context owns its plan/scratch buffers and the last-error text. */
+int qw_ctx_create(int device, void *hip_stream, qw_ctx **out);
+int qw_ctx_destroy(qw_ctx *ctx);
+/* Text of the last error of this context ("" if none); valid until the next
+ * call on it. For QW_E_REFUSED it is the refusal JSON record. */
+const char *qw_last_error(const qw_ctx *ctx);
+/* Block until all work enqueued by this context has finished. */
+int qw_ctx_sync(qw_ctx *ctx);
+
+/* Tunables (defaults in brackets):
+ *   QW_OPT_TILE_BITS      max local bits per pass tile, 10..14 [14]
+ *   QW_OPT_PROFILE        1: time every pass/reducer launch with HIP events
+ *                         (read with qw_ctx_kernel_stats) [0]
+ *   QW_OPT_FUSED_EPILOGUE 1: evaluate expectation terms whose X/Y support is
+ *                         local to the last suffix pass inside that pass [1]
+ *   QW_OPT_XCD_REMAP      1: map workgroups so that the tiles of one source
+ *                         state run on one XCD [1] */
+#define QW_OPT_TILE_BITS 1
+#define QW_OPT_PROFILE 2
+#define QW_OPT_FUSED_EPILOGUE 3
+#define QW_OPT_XCD_REMAP 4
+int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
+
+/* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.
+ * kernel: 0 = gate pass, 1 = expectation reducer, 2 = sampler, 3 = copy.
+ * Writes launch count, total milliseconds and total algorithmic bytes
+ * (read + write of every amplitude the launches touch). Resets on read when
+ * reset != 0. Synchronises the stream. */
+int qw_ctx_kernel_stats(qw_ctx *ctx, int kernel, uint64_t *launches,
+                        double *total_ms, double *total_bytes, int reset);
+
+/* ------------------------------------------------------------ states */
+/* qw_state_alloc: a state of n_qubits (1..30) with n_slots slots, every
+ * slot set to |0...0>. If dev_buf is non-NULL it must be device memory of at
+ * least n_slots * 8 * 2^n bytes (dev_buf_bytes), 256-byte aligned; the state
+ * is then a view and the caller keeps the buffer alive until qw_state_free.
+ * If dev_buf is NULL the library allocates (hipMalloc) and frees it. */
+int qw_state_alloc(qw_ctx *ctx, uint32_t n_qubits, uint32_t n_slots,
+                   void *dev_buf, uint64_t dev_buf_bytes, qw_state **out);
+int qw_state_free(qw_state *st);
+/* Set slots [first, first + count) to |0...0>. */
+int qw_state_reset(qw_state *st, uint32_t first, uint32_t count);
+/* Device address of slot `slot` (for copies by the caller). */
+int qw_state_slot_ptr(const qw_state *st, uint32_t slot, void **dev_ptr);
+
+/* ------------------------------------------------------------ the path */
+/* qw_apply_prefix: apply `gates` (host array) in order to slot `slot`, in
+ * place. This is the execution of a shared prefix (Sec. III-A, executed
+ * once); the direct path calls it for a task's prefix and then its suffix,
+ * so both paths cut the pass plan at the same boundary and produce bitwise
+ * identical states. */
+int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates,
+                    uint64_t n_gates);
+
+/* qw_snapshot: materialise slot `slot` as an immutable EXACT statevector
+ * artifact (Sec. IV-B ArtifactRecord) with the given 32-byte provenance
+ * (the Eq. (1) fingerprint computed by the caller). mode QW_SNAP_COPY copies
+ * the state into copy_buf (device memory, >= 8 * 2^n bytes) or, if copy_buf
+ * is NULL, into a buffer the library allocates; QW_SNAP_FREEZE moves no data
+ * and freezes the slot. `parent` (may be NULL) links prefix-tree levels and
+ * must be a snapshot of the same qubit count. Free with qw_snapshot_free
+ * (which unfreezes a FREEZE slot). */
+int qw_snapshot(qw_state *st, uint32_t slot, const uint8_t provenance[32],
+                int mode, const qw_snap *parent, void *copy_buf,
+                uint64_t copy_buf_bytes, qw_snap **out);
+int qw_snapshot_free(qw_snap *snap);
+int qw_snapshot_info(const qw_snap *snap, qw_artifact *out);
+
+/* qw_run_suffix_batch: run n_tasks continuations into state `dst`.
+ * src[k] is task k's boundary snapshot; src == NULL or src[k] == NULL means
+ * the direct path (the suffix runs in place on dst slot tasks[k].dst_slot).
+ * Before any device work every task with a snapshot passes the legality
+ * gates of Sec. IV-B in order: (1) exactness (artifact must be EXACT),
+ * (2) backend family (artifact produced by a known statevector family that
+ * this target accepts), (3) conversion rule of Table II (statevector ->
+ * statevector only), plus the artifact's qubit count and its provenance
+ * against tasks[k].expect_prov. If any gate fails nothing is enqueued and
+ * QW_E_REFUSED is returned with the refusal record (fields reason, detail,
+ * source_kind, target_kind, source_backend, target_backend) as
+ * qw_last_error(); the caller then falls back to the direct path.
+ * Destination slots must be distinct and not frozen. If `epilogue` is
+ * non-NULL its expectations are written for every task. */
+int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src,
+                        const qw_task *tasks, uint32_t n_tasks, qw_state *dst,
+                        const qw_reduce *epilogue);
+
+/* qw_expect_pauli: for each slot s in [first, first + count):
+ *   out[s - first] = sum_j coeff[j] * Re sum_i conj(psi[i ^ x_j]) *
+ *                    i^{popcount(x_j & z_j)} * (-1)^{popcount(i & z_j)} psi[i]
+ * i.e. sum_j c_j <P_j> with X on the bits of x_j only, Z on bits of z_j only
+ * and Y on bits set in both. Masks and coefficients are host arrays; out is
+ * host memory (out_is_host = 1; the call then synchronises) or device
+ * memory. Products and sums are in FP64 with a fixed reduction order, so the
+ * result does not depend on batch composition. */
+int qw_expect_pauli(const qw_state *st, uint32_t first, uint32_t count,
+                    const uint64_t *x_mask, const uint64_t *z_mask,
+                    const double *coeff, uint32_t n_terms, double *out,
+                    int out_is_host);
+
+/* qw_sample: `shots` Z-basis outcomes per slot. For slot first + k and shot
+ * s, u = (SplitMix64(seed ^ ((task_base + k) * 2^32 + s)) >> 11) * 2^-53 and
+ * the outcome is the smallest basis index i with CDF_i > u * total, where
+ * CDF_i is the FP64 running sum of |psi_j|^2 over j <= i and total = CDF of
+ * the last index. out[k * shots + s] receives the index (uint32); out is
+ * host (out_is_host = 1, call synchronises) or device memory. */
+int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
+              uint64_t seed, uint64_t task_base, uint32_t shots,
+              uint32_t *out, int out_is_host);
+
+/* ------------------------------------------------------------ host-only */
+/* Legality of continuing `src` on a target of kind `target_kind` and
+ * backend family `target_backend` (Sec. IV-B, Table II). Returns QW_OK when
+ * the continuation is EXACT, QW_E_REFUSED otherwise and then writes the
+ * refusal JSON record (NUL-terminated, truncated to cap) into json_out.
+ * No device is needed. */
+int qw_legality_check(const qw_artifact *src, uint32_t target_kind,
+                      uint32_t target_backend, char *json_out, uint64_t cap);
+
+/* Pass plan the library would execute for `gates` on n qubits, as JSON
+ * (passes, local bit sets and fused operations), for inspection. No device
+ * is needed. Returns QW_E_INVALID_ARG (message in json_out) for bad gates. */
+int qw_plan_describe(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
+                     uint32_t tile_bits, char *json_out, uint64_t cap);
+
+/* Library version string. */
+const char *qw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QW_H */

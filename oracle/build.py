@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "_qwo.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-           "-fno-fast-math", "-ffp-contract=off", SRC, "-o", OUT + ".tmp", "-lm"]
+           "-fno-fast-math", "-ffp-contract=off", "-fcx-limited-range", SRC, "-o", OUT + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

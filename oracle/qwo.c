@@ -148,15 +148,7 @@ int qwo_apply_gates(cplx *psi, int n, int64_t ng, const int32_t *code,
     return 0;
 }
 
-static int popcount64(uint64_t v)
-{
-    int c = 0;
-    while (v) {
-        c += (int)(v & 1ull);
-        v >>= 1;
-    }
-    return c;
-}
+static int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 
 /* <P> for the Pauli string with masks (x, z). */
 double qwo_expect_pauli(const cplx *psi, int n, uint64_t x, uint64_t z)

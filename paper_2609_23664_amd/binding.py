@@ -1,0 +1,390 @@
+"""ctypes binding of libqw (include/qw.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels. PyTorch provides device memory (state buffers are torch tensors)
+and the HIP stream (torch's current stream). The binding raises if the
+built library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqw.so")
+
+QW_OK = 0
+QW_E_INVALID_ARG = 1
+QW_E_OOM = 2
+QW_E_HIP = 3
+QW_E_REFUSED = 4
+QW_E_UNSUPPORTED = 5
+
+GATE_KIND = {
+    "X": 0x01, "Y": 0x02, "Z": 0x03, "H": 0x04, "S": 0x05, "SDG": 0x06,
+    "T": 0x07, "TDG": 0x08, "RX": 0x21, "RY": 0x22, "RZ": 0x23, "P": 0x24,
+    "CNOT": 0x41, "CZ": 0x42, "RENORM": 0x81,
+}
+
+QW_KIND_STATEVECTOR = 1
+QW_KIND_TABLEAU = 2
+QW_EXACTNESS_UNKNOWN = 0
+QW_EXACT = 1
+QW_APPROX = 2
+QW_BACKEND_UNKNOWN = 0
+QW_BACKEND_SV = 1
+QW_BACKEND_STAB_ONLY = 2
+QW_SNAP_COPY = 0
+QW_SNAP_FREEZE = 1
+
+QW_OPT_TILE_BITS = 1
+QW_OPT_PROFILE = 2
+QW_OPT_FUSED_EPILOGUE = 3
+QW_OPT_XCD_REMAP = 4
+
+EXPORTED = (
+    "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",
+    "qw_ctx_set_option", "qw_ctx_kernel_stats", "qw_state_alloc", "qw_state_free",
+    "qw_state_reset", "qw_state_slot_ptr", "qw_apply_prefix", "qw_snapshot",
+    "qw_snapshot_free", "qw_snapshot_info", "qw_run_suffix_batch",
+    "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
+    "qw_version",
+)
+
+
+class QwGate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("q0", ctypes.c_uint32), ("q1", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("param", ctypes.c_double)]
+
+
+class QwArtifact(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("exactness", ctypes.c_uint32),
+                ("backend", ctypes.c_uint32), ("n_qubits", ctypes.c_uint32),
+                ("bytes", ctypes.c_uint64), ("provenance", ctypes.c_uint8 * 32)]
+
+
+class QwTask(ctypes.Structure):
+    _fields_ = [("gates", ctypes.POINTER(QwGate)), ("n_gates", ctypes.c_uint64),
+                ("dst_slot", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("expect_prov", ctypes.c_uint8 * 32)]
+
+
+class QwReduce(ctypes.Structure):
+    _fields_ = [("x_mask", ctypes.POINTER(ctypes.c_uint64)),
+                ("z_mask", ctypes.POINTER(ctypes.c_uint64)),
+                ("coeff", ctypes.POINTER(ctypes.c_double)),
+                ("n_terms", ctypes.c_uint32), ("out_is_host", ctypes.c_int32),
+                ("out", ctypes.POINTER(ctypes.c_double))]
+
+
+assert ctypes.sizeof(QwGate) == 24
+
+
+class QwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libqw error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class QwRefused(QwError):
+    """A continuation failed a legality gate; ``record`` is the refusal JSON."""
+
+    @property
+    def record(self) -> dict:
+        import json
+        return json.loads(self.msg)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libqw.so not built at {LIB_PATH}: run "
+                          "`python -m paper_2609_23664_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "qw_ctx_create": ([i32, vp, pp], i32),
+        "qw_ctx_destroy": ([vp], i32),
+        "qw_last_error": ([vp], ctypes.c_char_p),
+        "qw_ctx_sync": ([vp], i32),
+        "qw_ctx_set_option": ([vp, i32, ctypes.c_int64], i32),
+        "qw_ctx_kernel_stats": ([vp, i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), i32], i32),
+        "qw_state_alloc": ([vp, u32, u32, vp, u64, pp], i32),
+        "qw_state_free": ([vp], i32),
+        "qw_state_reset": ([vp, u32, u32], i32),
+        "qw_state_slot_ptr": ([vp, u32, pp], i32),
+        "qw_apply_prefix": ([vp, u32, ctypes.POINTER(QwGate), u64], i32),
+        "qw_snapshot": ([vp, u32, ctypes.POINTER(ctypes.c_uint8), i32, vp, vp, u64, pp], i32),
+        "qw_snapshot_free": ([vp], i32),
+        "qw_snapshot_info": ([vp, ctypes.POINTER(QwArtifact)], i32),
+        "qw_run_suffix_batch": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(QwTask), u32,
+                                 vp, ctypes.POINTER(QwReduce)], i32),
+        "qw_expect_pauli": ([vp, u32, u32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                             ctypes.POINTER(ctypes.c_double), u32, vp, i32], i32),
+        "qw_sample": ([vp, u32, u32, u64, u64, u32, vp, i32], i32),
+        "qw_legality_check": ([ctypes.POINTER(QwArtifact), u32, u32, ctypes.c_char_p, u64], i32),
+        "qw_plan_describe": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
+        "qw_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def gate_array(gates: Sequence[Tuple[str, Tuple[int, ...], float]]):
+    """Marshal (name, qubits, param) records into a qw_gate array."""
+    arr = (QwGate * max(1, len(gates)))()
+    for k, (name, qs, p) in enumerate(gates):
+        g = arr[k]
+        g.kind = GATE_KIND[name]
+        g.q0 = qs[0] if len(qs) > 0 else 0
+        g.q1 = qs[1] if len(qs) > 1 else 0
+        g.reserved = 0
+        g.param = float(p)
+    return arr
+
+
+def _u64_array(vals):
+    a = (ctypes.c_uint64 * max(1, len(vals)))()
+    for i, v in enumerate(vals):
+        a[i] = int(v)
+    return a
+
+
+def _f64_array(vals):
+    a = (ctypes.c_double * max(1, len(vals)))()
+    for i, v in enumerate(vals):
+        a[i] = float(v)
+    return a
+
+
+def _prov(b: bytes):
+    assert len(b) == 32
+    return (ctypes.c_uint8 * 32)(*b)
+
+
+def legality_check(kind: int, exactness: int, backend: int, n_qubits: int,
+                   target_kind: int, target_backend: int) -> Tuple[int, str]:
+    """Host-only legality gates; returns (status, refusal JSON or '')."""
+    art = QwArtifact(kind, exactness, backend, n_qubits, 0, (ctypes.c_uint8 * 32)())
+    buf = ctypes.create_string_buffer(1024)
+    rc = lib().qw_legality_check(ctypes.byref(art), target_kind, target_backend, buf, 1024)
+    return rc, buf.value.decode()
+
+
+def plan_describe(n: int, gates, tile_bits: int = 14) -> dict:
+    """Host-only: the pass plan for `gates` as a dict."""
+    import json
+    arr = gate_array(gates)
+    cap = 1 << 16
+    while True:
+        buf = ctypes.create_string_buffer(cap)
+        rc = lib().qw_plan_describe(n, arr, len(gates), tile_bits, buf, cap)
+        if rc == QW_OK:
+            return json.loads(buf.value.decode())
+        if buf.value.startswith(b'{"error"'):
+            raise QwError(rc, json.loads(buf.value.decode())["error"])
+        cap *= 4
+        if cap > (1 << 30):
+            raise QwError(rc, "plan too large")
+
+
+class Ctx:
+    """A libqw context on torch's current HIP stream of `device`."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib().qw_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != QW_OK:
+            raise QwError(rc, "qw_ctx_create failed")
+        self.h = h
+
+    def check(self, rc: int):
+        if rc == QW_OK:
+            return
+        msg = lib().qw_last_error(self.h).decode()
+        if rc == QW_E_REFUSED:
+            raise QwRefused(rc, msg)
+        raise QwError(rc, msg)
+
+    def set_option(self, key: int, value: int):
+        self.check(lib().qw_ctx_set_option(self.h, key, int(value)))
+
+    def sync(self):
+        self.check(lib().qw_ctx_sync(self.h))
+
+    def kernel_stats(self, kernel: int, reset: bool = True):
+        n = ctypes.c_uint64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        self.check(lib().qw_ctx_kernel_stats(self.h, kernel, ctypes.byref(n), ctypes.byref(ms),
+                                             ctypes.byref(by), 1 if reset else 0))
+        return int(n.value), float(ms.value), float(by.value)
+
+    def close(self):
+        if self.h:
+            lib().qw_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """n-qubit state with `slots` slots; memory is a torch complex64 tensor."""
+
+    def __init__(self, ctx: Ctx, n: int, slots: int):
+        torch = ctx.torch
+        self.ctx, self.n, self.slots = ctx, n, slots
+        self.buf = torch.empty((slots, 1 << n), dtype=torch.complex64, device=f"cuda:{ctx.device}")
+        h = ctypes.c_void_p()
+        ctx.check(lib().qw_state_alloc(ctx.h, n, slots, ctypes.c_void_p(self.buf.data_ptr()),
+                                       self.buf.numel() * 8, ctypes.byref(h)))
+        self.h = h
+
+    def reset(self, first: int = 0, count: Optional[int] = None):
+        count = self.slots - first if count is None else count
+        self.ctx.check(lib().qw_state_reset(self.h, first, count))
+
+    def apply(self, slot: int, gates):
+        arr = gate_array(gates)
+        self.ctx.check(lib().qw_apply_prefix(self.h, slot, arr, len(gates)))
+
+    def snapshot(self, slot: int, provenance: bytes, mode: int = QW_SNAP_FREEZE,
+                 parent: "Optional[Snapshot]" = None) -> "Snapshot":
+        return Snapshot(self, slot, provenance, mode, parent)
+
+    def expect(self, first: int, count: int, terms) -> List[float]:
+        x = _u64_array([t[1] for t in terms])
+        z = _u64_array([t[2] for t in terms])
+        c = _f64_array([t[0] for t in terms])
+        out = (ctypes.c_double * max(1, count))()
+        self.ctx.check(lib().qw_expect_pauli(self.h, first, count, x, z, c, len(terms),
+                                             ctypes.cast(out, ctypes.c_void_p), 1))
+        return [out[i] for i in range(count)]
+
+    def sample(self, first: int, count: int, seed: int, task_base: int, shots: int):
+        import numpy as np
+        out = np.empty(count * shots, dtype=np.uint32)
+        self.ctx.check(lib().qw_sample(self.h, first, count, seed, task_base, shots,
+                                       ctypes.c_void_p(out.ctypes.data), 1))
+        return out.reshape(count, shots)
+
+    def host(self, slot: int):
+        """Copy of slot `slot` as a numpy complex64 array (synchronises)."""
+        self.ctx.sync()
+        return self.buf[slot].cpu().numpy()
+
+    def free(self):
+        if self.h:
+            rc = lib().qw_state_free(self.h)
+            self.h = None
+            self.ctx.check(rc)
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().qw_state_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Snapshot:
+    """Typed boundary artifact (ArtifactRecord) of one state slot."""
+
+    def __init__(self, state: State, slot: int, provenance: bytes, mode: int, parent=None):
+        self.state = state
+        self.provenance = bytes(provenance)
+        self.copy_buf = None
+        h = ctypes.c_void_p()
+        copy_ptr, copy_bytes = None, 0
+        if mode == QW_SNAP_COPY:
+            torch = state.ctx.torch
+            self.copy_buf = torch.empty(1 << state.n, dtype=torch.complex64,
+                                        device=f"cuda:{state.ctx.device}")
+            copy_ptr, copy_bytes = ctypes.c_void_p(self.copy_buf.data_ptr()), 8 << state.n
+        state.ctx.check(lib().qw_snapshot(state.h, slot, _prov(self.provenance), mode,
+                                          parent.h if parent is not None else None,
+                                          copy_ptr, copy_bytes, ctypes.byref(h)))
+        self.h = h
+
+    def info(self) -> dict:
+        a = QwArtifact()
+        self.state.ctx.check(lib().qw_snapshot_info(self.h, ctypes.byref(a)))
+        return {"kind": a.kind, "exactness": a.exactness, "backend": a.backend,
+                "n_qubits": a.n_qubits, "bytes": a.bytes, "provenance": bytes(a.provenance)}
+
+    def free(self):
+        if self.h:
+            lib().qw_snapshot_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def run_suffix_batch(ctx: Ctx, srcs: Sequence[Optional[Snapshot]], suffixes, dst: State,
+                     dst_slots: Sequence[int], expect_provs: Sequence[bytes] = None,
+                     terms=None):
+    """qw_run_suffix_batch; returns the per-task expectations if `terms`."""
+    nt = len(suffixes)
+    arrs = [gate_array(s) for s in suffixes]
+    tasks = (QwTask * max(1, nt))()
+    for k in range(nt):
+        tasks[k].gates = ctypes.cast(arrs[k], ctypes.POINTER(QwGate))
+        tasks[k].n_gates = len(suffixes[k])
+        tasks[k].dst_slot = int(dst_slots[k])
+        tasks[k].reserved = 0
+        prov = expect_provs[k] if expect_provs is not None else (
+            srcs[k].provenance if srcs and srcs[k] is not None else bytes(32))
+        tasks[k].expect_prov = (ctypes.c_uint8 * 32)(*prov)
+    src_arr = None
+    if srcs is not None:
+        src_arr = (ctypes.c_void_p * max(1, nt))()
+        for k in range(nt):
+            src_arr[k] = srcs[k].h.value if srcs[k] is not None else None
+    red = None
+    out = None
+    keep = []
+    if terms is not None:
+        x = _u64_array([t[1] for t in terms])
+        z = _u64_array([t[2] for t in terms])
+        c = _f64_array([t[0] for t in terms])
+        out = (ctypes.c_double * max(1, nt))()
+        keep += [x, z, c]
+        red = QwReduce(ctypes.cast(x, ctypes.POINTER(ctypes.c_uint64)),
+                       ctypes.cast(z, ctypes.POINTER(ctypes.c_uint64)),
+                       ctypes.cast(c, ctypes.POINTER(ctypes.c_double)),
+                       len(terms), 1, ctypes.cast(out, ctypes.POINTER(ctypes.c_double)))
+    rc = lib().qw_run_suffix_batch(ctx.h, src_arr, tasks, nt, dst.h,
+                                   ctypes.byref(red) if red is not None else None)
+    ctx.check(rc)
+    if out is not None:
+        return [out[i] for i in range(nt)]
+    return None

@@ -1,0 +1,847 @@
+// C ABI of libqw (include/qw.h): contexts, states, typed boundary
+// snapshots, legality gates and the execution of pass plans on a HIP stream.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/qw.h"
+#include "qw_internal.h"
+#include "qw_kernels.h"
+
+using namespace qw;
+
+namespace {
+
+const char *kVersion = "libqw 0.1 (gfx950)";
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct ProfRec {
+    int kind;
+    double bytes;
+    hipEvent_t e0, e1;
+};
+
+struct KStats {
+    uint64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+
+}  // namespace
+
+struct qw_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int tile_bits = kMaxTileBits;
+    bool profile = false;
+    bool fused_epilogue = true;
+    bool xcd_remap = true;
+    DevBuf plan;     // uploaded descriptors/ops
+    DevBuf scratch;  // partial sums, sampler buffers
+    void *staging = nullptr;
+    size_t staging_cap = 0;
+    hipEvent_t staging_ev = nullptr;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    KStats stats[4];
+};
+
+struct qw_state {
+    qw_ctx *ctx = nullptr;
+    uint32_t n = 0, n_slots = 0;
+    char *base = nullptr;
+    bool owned = false;
+    uint64_t slot_bytes = 0;
+    std::vector<uint32_t> frozen;
+};
+
+struct qw_snap {
+    qw_ctx *ctx = nullptr;
+    qw_artifact art{};
+    const void *data = nullptr;
+    void *owned = nullptr;
+    qw_state *fstate = nullptr;
+    uint32_t fslot = 0;
+    const qw_snap *parent = nullptr;
+    int mode = QW_SNAP_COPY;
+};
+
+namespace {
+
+int fail(qw_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(qw_ctx *ctx, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? QW_E_OOM : QW_E_HIP, m);
+}
+
+#define HIP_TRY(ctx, call, what)                       \
+    do {                                               \
+        hipError_t _e = (call);                        \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+    } while (0)
+
+int ensure(qw_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
+    if (b.cap >= bytes) return QW_OK;
+    size_t want = std::max(bytes, b.cap * 2);
+    want = (want + 4095) & ~size_t(4095);
+    if (b.p) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync before regrow");
+        HIP_TRY(ctx, hipFree(b.p), "free scratch");
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    b.p = p;
+    b.cap = want;
+    return QW_OK;
+}
+
+// Copy a host blob to ctx->plan (device) through the pinned staging buffer.
+int upload(qw_ctx *ctx, const std::vector<uint8_t> &blob) {
+    if (blob.empty()) return QW_OK;
+    int rc = ensure(ctx, ctx->plan, blob.size(), "plan buffer");
+    if (rc) return rc;
+    // the previous copy out of the staging buffer must have completed
+    HIP_TRY(ctx, hipEventSynchronize(ctx->staging_ev), "staging wait");
+    if (ctx->staging_cap < blob.size()) {
+        if (ctx->staging) HIP_TRY(ctx, hipHostFree(ctx->staging), "free staging");
+        ctx->staging = nullptr;
+        size_t want = std::max(blob.size(), ctx->staging_cap * 2);
+        HIP_TRY(ctx, hipHostMalloc(&ctx->staging, want, hipHostMallocDefault), "staging alloc");
+        ctx->staging_cap = want;
+    }
+    std::memcpy(ctx->staging, blob.data(), blob.size());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->plan.p, ctx->staging, blob.size(), hipMemcpyHostToDevice,
+                                ctx->stream),
+            "plan upload");
+    HIP_TRY(ctx, hipEventRecord(ctx->staging_ev, ctx->stream), "staging event");
+    return QW_OK;
+}
+
+// Bump layout of a blob: offsets aligned to 64 bytes.
+struct Layout {
+    size_t size = 0;
+    size_t take(size_t bytes, size_t align = 64) {
+        size = (size + align - 1) & ~(align - 1);
+        size_t off = size;
+        size += bytes;
+        return off;
+    }
+};
+
+hipEvent_t get_event(qw_ctx *ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    qw_ctx *ctx;
+    int kind;
+    double bytes;
+    hipEvent_t e0 = nullptr;
+    ProfScope(qw_ctx *c, int k, double b) : ctx(c), kind(k), bytes(b) {
+        if (!ctx->profile) return;
+        e0 = get_event(ctx);
+        if (e0) hipEventRecord(e0, ctx->stream);
+    }
+    ~ProfScope() {
+        if (!ctx->profile || !e0) return;
+        hipEvent_t e1 = get_event(ctx);
+        if (!e1) return;
+        hipEventRecord(e1, ctx->stream);
+        ctx->prof.push_back({kind, bytes, e0, e1});
+    }
+};
+
+const char *kind_name(uint32_t k) {
+    switch (k) {
+    case QW_KIND_STATEVECTOR: return "STATEVECTOR_BOUNDARY_STATE";
+    case QW_KIND_TABLEAU: return "TABLEAU_BOUNDARY_STATE";
+    default: return "UNKNOWN_KIND";
+    }
+}
+
+const char *backend_name(uint32_t b) {
+    switch (b) {
+    case QW_BACKEND_SV: return "MI355X_SV_C64";
+    case QW_BACKEND_STAB_ONLY: return "STABILIZER_ONLY";
+    default: return "UNKNOWN";
+    }
+}
+
+std::string json_escape(const std::string &s) {
+    std::string o;
+    for (char c : s) {
+        if (c == '"' || c == '\\') o += '\\';
+        o += c;
+    }
+    return o;
+}
+
+std::string refusal_json(const char *reason, const std::string &detail, uint32_t sk,
+                         uint32_t tk, uint32_t sb, uint32_t tb, long task = -1) {
+    std::ostringstream o;
+    o << "{\"reason\": \"" << reason << "\", \"detail\": \"" << json_escape(detail)
+      << "\", \"source_kind\": \"" << kind_name(sk) << "\", \"target_kind\": \"" << kind_name(tk)
+      << "\", \"source_backend\": \"" << backend_name(sb) << "\", \"target_backend\": \""
+      << backend_name(tb) << "\"";
+    if (task >= 0) o << ", \"task\": " << task;
+    o << "}";
+    return o.str();
+}
+
+// The three gates of Sec. IV-B in order; Table II decides gate 3.
+// Returns true if the continuation is EXACT; otherwise fills *json.
+bool legal(const qw_artifact &a, uint32_t tk, uint32_t tb, std::string *json, long task = -1) {
+    const uint32_t sk = a.kind, sb = a.backend;
+    // gate 1: exactness validation
+    if (a.exactness != QW_EXACT) {
+        *json = refusal_json("NON_EXACT_ARTIFACT",
+                             a.exactness == QW_APPROX ? "artifact exactness class is not EXACT."
+                                                      : "artifact exactness class is unknown.",
+                             sk, tk, sb, tb, task);
+        return false;
+    }
+    // gate 2: backend-family validation
+    const bool sb_known = (sb == QW_BACKEND_SV || sb == QW_BACKEND_STAB_ONLY);
+    const bool tb_known = (tb == QW_BACKEND_SV || tb == QW_BACKEND_STAB_ONLY);
+    const bool kinds_known = (sk == QW_KIND_STATEVECTOR || sk == QW_KIND_TABLEAU) &&
+                             (tk == QW_KIND_STATEVECTOR || tk == QW_KIND_TABLEAU);
+    if (!sb_known || !tb_known || !kinds_known) {
+        *json = refusal_json("UNKNOWN_BACKEND", "producing or target backend family is unknown.",
+                             sk, tk, sb, tb, task);
+        return false;
+    }
+    // gate 3: conversion-rule lookup (Table II)
+    if (sk == QW_KIND_TABLEAU && tk == QW_KIND_TABLEAU) {
+        if (tb == QW_BACKEND_STAB_ONLY) return true;                 // STAB -> STAB
+        *json = refusal_json("FORBIDDEN_CONVERSION", "tableau continuation needs a tableau backend.",
+                             sk, tk, sb, tb, task);
+        return false;
+    }
+    if (sk == QW_KIND_TABLEAU && tk == QW_KIND_STATEVECTOR) {
+        if (tb == QW_BACKEND_SV) return true;                        // STAB -> SV (dense export)
+        *json = refusal_json("FORBIDDEN_CONVERSION", "SV on stabilizer-only backend not supported.",
+                             sk, tk, sb, tb, task);
+        return false;
+    }
+    if (sk == QW_KIND_STATEVECTOR && tk == QW_KIND_TABLEAU) {      // SV -> STAB
+        *json = refusal_json("FORBIDDEN_CONVERSION", "statevector to tableau handoff not supported.",
+                             sk, tk, sb, tb, task);
+        return false;
+    }
+    // SV -> SV: exact within a statevector-capable family only
+    if (sb == QW_BACKEND_SV && tb == QW_BACKEND_SV) return true;
+    *json = refusal_json("FORBIDDEN_CONVERSION", "SV on stabilizer-only backend not supported.",
+                         sk, tk, sb, tb, task);
+    return false;
+}
+
+bool slot_ok(const qw_state *st, uint32_t first, uint32_t count) {
+    return (uint64_t)first + count <= st->n_slots;
+}
+
+char *slot_ptr(const qw_state *st, uint32_t s) { return st->base + (uint64_t)s * st->slot_bytes; }
+
+// One task of an execution: its plan, source, destination.
+struct Exec {
+    Plan plan;
+    const void *src = nullptr;  // first-pass source (snapshot) or nullptr
+    void *dst = nullptr;
+};
+
+int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
+    if (ex.empty()) return QW_OK;
+    const int m = ex[0].plan.m;
+    const uint32_t tiles = (m >= kMinTileBits) ? (1u << (n - m)) : 1u;
+    size_t steps = 0;
+    for (Exec &e : ex) steps = std::max(steps, e.plan.passes.size());
+    // tasks with a snapshot and no pass: plain copy of the boundary state
+    const uint64_t state_bytes = 8ull << n;
+    for (Exec &e : ex) {
+        if (e.src && e.plan.passes.empty()) {
+            ProfScope ps(ctx, 3, 2.0 * state_bytes);
+            hipError_t er = launch_copy(ctx->stream, e.dst, e.src, state_bytes);
+            if (er != hipSuccess) return hip_fail(ctx, er, "copy launch");
+        }
+    }
+    if (steps == 0) return QW_OK;
+    // scratch: per task norm partials [tiles] and one scale
+    bool any_norm = false;
+    for (Exec &e : ex)
+        for (HostPass &p : e.plan.passes) any_norm |= p.norm_out;
+    const size_t norm_bytes = any_norm ? ex.size() * (tiles + 1) * sizeof(double) : 0;
+    if (norm_bytes) {
+        int rc = ensure(ctx, ctx->scratch, norm_bytes, "norm scratch");
+        if (rc) return rc;
+    }
+    double *norm_base = static_cast<double *>(ctx->scratch.p);
+    // blob layout
+    Layout L;
+    std::vector<size_t> step_off(steps), step_cnt(steps, 0);
+    for (size_t k = 0; k < steps; ++k) {
+        for (Exec &e : ex) step_cnt[k] += (k < e.plan.passes.size());
+        step_off[k] = L.take(step_cnt[k] * sizeof(PassDesc));
+    }
+    std::vector<std::vector<std::pair<size_t, size_t>>> op_off(ex.size());
+    for (size_t t = 0; t < ex.size(); ++t) {
+        for (HostPass &p : ex[t].plan.passes) {
+            size_t oo = L.take(std::max<size_t>(1, p.dev_ops.size()) * sizeof(DevOp));
+            size_t po = L.take(std::max<size_t>(1, p.dev_phases.size()) * sizeof(DevPhase));
+            op_off[t].push_back({oo, po});
+        }
+    }
+    int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
+    if (rc) return rc;
+    uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
+    std::vector<uint8_t> blob(L.size, 0);
+    for (size_t t = 0; t < ex.size(); ++t) {
+        for (size_t k = 0; k < ex[t].plan.passes.size(); ++k) {
+            HostPass &p = ex[t].plan.passes[k];
+            std::memcpy(blob.data() + op_off[t][k].first, p.dev_ops.data(),
+                        p.dev_ops.size() * sizeof(DevOp));
+            std::memcpy(blob.data() + op_off[t][k].second, p.dev_phases.data(),
+                        p.dev_phases.size() * sizeof(DevPhase));
+        }
+    }
+    std::vector<char> step_norm(steps, 0);
+    for (size_t k = 0; k < steps; ++k) {
+        size_t c = 0;
+        for (size_t t = 0; t < ex.size(); ++t) {
+            Exec &e = ex[t];
+            if (k >= e.plan.passes.size()) continue;
+            HostPass &p = e.plan.passes[k];
+            PassDesc d{};
+            d.src = (k == 0 && e.src) ? e.src : e.dst;
+            d.dst = e.dst;
+            d.ops = reinterpret_cast<const DevOp *>(dbase + op_off[t][k].first);
+            d.phases = reinterpret_cast<const DevPhase *>(dbase + op_off[t][k].second);
+            d.local_mask = p.local_mask;
+            double *nb = norm_base ? norm_base + t * (tiles + 1) : nullptr;
+            d.scale_in = nb ? nb + tiles : nullptr;
+            d.norm_part = nb;
+            d.scale_out = nb ? nb + tiles : nullptr;
+            d.n_ops = (uint32_t)p.dev_ops.size();
+            d.n_phases = (uint32_t)p.dev_phases.size();
+            d.flags = (p.scale_in ? PD_SCALE_IN : 0u) | (p.norm_out ? PD_NORM_OUT : 0u);
+            if (p.norm_out) step_norm[k] = 1;
+            std::memcpy(blob.data() + step_off[k] + c * sizeof(PassDesc), &d, sizeof d);
+            ++c;
+        }
+    }
+    rc = upload(ctx, blob);
+    if (rc) return rc;
+    for (size_t k = 0; k < steps; ++k) {
+        const PassDesc *dd = reinterpret_cast<const PassDesc *>(dbase + step_off[k]);
+        {
+            ProfScope ps(ctx, 0, (double)step_cnt[k] * 2.0 * (double)state_bytes);
+            hipError_t er = launch_pass(ctx->stream, dd, (uint32_t)step_cnt[k], n, (uint32_t)m,
+                                        ctx->xcd_remap ? 1 : 0);
+            if (er != hipSuccess) return hip_fail(ctx, er, "pass launch");
+        }
+        if (step_norm[k]) {
+            hipError_t er = launch_norm_finalize(ctx->stream, dd, (uint32_t)step_cnt[k], tiles);
+            if (er != hipSuccess) return hip_fail(ctx, er, "norm finalize launch");
+        }
+    }
+    return QW_OK;
+}
+
+// Expectations for a list of slot pointers of one n-qubit layout.
+int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots,
+                 const uint64_t *x, const uint64_t *z, const double *c, uint32_t n_terms,
+                 double *out, int out_is_host) {
+    const uint32_t ns = (uint32_t)slots.size();
+    if (ns == 0) return QW_OK;
+    const uint64_t full = (1ull << n) - 1;
+    for (uint32_t j = 0; j < n_terms; ++j)
+        if ((x[j] & ~full) || (z[j] & ~full))
+            return fail(ctx, QW_E_INVALID_ARG, "Pauli mask has bits >= n");
+    if (n_terms == 0) {
+        std::vector<double> zero(ns, 0.0);
+        if (out_is_host) {
+            std::memcpy(out, zero.data(), ns * sizeof(double));
+            return QW_OK;
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(out, zero.data(), ns * sizeof(double), hipMemcpyHostToDevice,
+                                    ctx->stream), "zero out");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+        return QW_OK;
+    }
+    const int m = tile_bits_for((int)n, ctx->tile_bits);
+    const uint32_t tiles = 1u << (n - m);
+    std::vector<TermGroup> groups = group_terms((int)n, m, x, n_terms);
+    Layout L;
+    std::vector<size_t> g_off(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) g_off[g] = L.take(groups[g].terms.size() * sizeof(TermDev));
+    const size_t coeff_off = L.take(n_terms * sizeof(double));
+    const size_t desc_off = L.take(ns * groups.size() * sizeof(ReduceDesc));
+    int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
+    if (rc) return rc;
+    const size_t part_bytes = (size_t)ns * tiles * n_terms * sizeof(double);
+    const size_t out_bytes = ns * sizeof(double);
+    rc = ensure(ctx, ctx->scratch, part_bytes + out_bytes + 256, "reduce scratch");
+    if (rc) return rc;
+    uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
+    double *part = static_cast<double *>(ctx->scratch.p);
+    double *dout = out_is_host ? reinterpret_cast<double *>(
+                                     static_cast<uint8_t *>(ctx->scratch.p) +
+                                     ((part_bytes + 255) & ~size_t(255)))
+                               : out;
+    std::vector<uint8_t> blob(L.size, 0);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const uint64_t lm = groups[g].local_mask;
+        for (size_t i = 0; i < groups[g].terms.size(); ++i) {
+            const uint32_t j = groups[g].terms[i];
+            TermDev t{};
+            t.x_local = (uint32_t)pext64(x[j], lm);
+            t.z_local = (uint32_t)pext64(z[j], lm);
+            t.z_global = z[j] & ~lm;
+            t.ny_mod4 = (uint32_t)(popc64(x[j] & z[j]) & 3);
+            t.out_index = j;
+            std::memcpy(blob.data() + g_off[g] + i * sizeof(TermDev), &t, sizeof t);
+        }
+    }
+    std::memcpy(blob.data() + coeff_off, c, n_terms * sizeof(double));
+    size_t di = 0;
+    for (uint32_t s = 0; s < ns; ++s) {
+        for (size_t g = 0; g < groups.size(); ++g) {
+            ReduceDesc d{};
+            d.psi = slots[s];
+            d.terms = reinterpret_cast<const TermDev *>(dbase + g_off[g]);
+            d.part = part + (size_t)s * tiles * n_terms;
+            d.local_mask = groups[g].local_mask;
+            d.n_terms = (uint32_t)groups[g].terms.size();
+            d.n_terms_total = n_terms;
+            std::memcpy(blob.data() + desc_off + di * sizeof(ReduceDesc), &d, sizeof d);
+            ++di;
+        }
+    }
+    rc = upload(ctx, blob);
+    if (rc) return rc;
+    {
+        ProfScope ps(ctx, 1, (double)ns * groups.size() * (double)(8ull << n));
+        hipError_t er = launch_reduce(ctx->stream,
+                                      reinterpret_cast<const ReduceDesc *>(dbase + desc_off),
+                                      (uint32_t)di, n, (uint32_t)m);
+        if (er != hipSuccess) return hip_fail(ctx, er, "reduce launch");
+    }
+    hipError_t er = launch_expect_finalize(ctx->stream, part,
+                                           reinterpret_cast<const double *>(dbase + coeff_off),
+                                           n_terms, tiles, ns, dout);
+    if (er != hipSuccess) return hip_fail(ctx, er, "finalize launch");
+    if (out_is_host) {
+        HIP_TRY(ctx, hipMemcpyAsync(out, dout, out_bytes, hipMemcpyDeviceToHost, ctx->stream),
+                "result copy");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    }
+    return QW_OK;
+}
+
+}  // namespace
+
+// ================================================================= ABI
+extern "C" {
+
+const char *qw_version(void) { return kVersion; }
+
+int qw_ctx_create(int device, void *hip_stream, qw_ctx **out) {
+    if (!out) return QW_E_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return QW_E_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return QW_E_HIP;
+    qw_ctx *c = new (std::nothrow) qw_ctx();
+    if (!c) return QW_E_OOM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(c->staging_ev, c->stream) != hipSuccess || kernels_init() != hipSuccess) {
+        delete c;
+        return QW_E_HIP;
+    }
+    *out = c;
+    return QW_OK;
+}
+
+int qw_ctx_destroy(qw_ctx *ctx) {
+    if (!ctx) return QW_E_INVALID_ARG;
+    hipStreamSynchronize(ctx->stream);
+    for (ProfRec &r : ctx->prof) {
+        hipEventDestroy(r.e0);
+        hipEventDestroy(r.e1);
+    }
+    for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+    if (ctx->plan.p) (void)hipFree(ctx->plan.p);
+    if (ctx->scratch.p) hipFree(ctx->scratch.p);
+    if (ctx->staging) hipHostFree(ctx->staging);
+    if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
+    delete ctx;
+    return QW_OK;
+}
+
+const char *qw_last_error(const qw_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int qw_ctx_sync(qw_ctx *ctx) {
+    if (!ctx) return QW_E_INVALID_ARG;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+    return QW_OK;
+}
+
+int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
+    if (!ctx) return QW_E_INVALID_ARG;
+    switch (key) {
+    case QW_OPT_TILE_BITS:
+        if (value < kMinTileBits || value > kMaxTileBits)
+            return fail(ctx, QW_E_INVALID_ARG, "tile bits must be 10..14");
+        ctx->tile_bits = (int)value;
+        return QW_OK;
+    case QW_OPT_PROFILE: ctx->profile = value != 0; return QW_OK;
+    case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
+    case QW_OPT_XCD_REMAP: ctx->xcd_remap = value != 0; return QW_OK;
+    default: return fail(ctx, QW_E_INVALID_ARG, "unknown option");
+    }
+}
+
+int qw_ctx_kernel_stats(qw_ctx *ctx, int kernel, uint64_t *launches, double *total_ms,
+                        double *total_bytes, int reset) {
+    if (!ctx || kernel < 0 || kernel > 3) return QW_E_INVALID_ARG;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+    for (ProfRec &r : ctx->prof) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+            KStats &s = ctx->stats[r.kind];
+            s.launches += 1;
+            s.ms += ms;
+            s.bytes += r.bytes;
+        }
+        ctx->ev_pool.push_back(r.e0);
+        ctx->ev_pool.push_back(r.e1);
+    }
+    ctx->prof.clear();
+    KStats &s = ctx->stats[kernel];
+    if (launches) *launches = s.launches;
+    if (total_ms) *total_ms = s.ms;
+    if (total_bytes) *total_bytes = s.bytes;
+    if (reset) s = KStats{};
+    return QW_OK;
+}
+
+int qw_state_alloc(qw_ctx *ctx, uint32_t n, uint32_t n_slots, void *dev_buf,
+                   uint64_t dev_buf_bytes, qw_state **out) {
+    if (!ctx || !out) return QW_E_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || n > (uint32_t)kMaxQubits) return fail(ctx, QW_E_INVALID_ARG, "n_qubits must be 1..30");
+    if (n_slots < 1) return fail(ctx, QW_E_INVALID_ARG, "n_slots must be >= 1");
+    const uint64_t slot_bytes = 8ull << n;
+    const uint64_t need = slot_bytes * n_slots;
+    if (dev_buf) {
+        if (dev_buf_bytes < need) return fail(ctx, QW_E_INVALID_ARG, "dev_buf too small");
+        if (reinterpret_cast<uintptr_t>(dev_buf) & 255u)
+            return fail(ctx, QW_E_INVALID_ARG, "dev_buf must be 256-byte aligned");
+    }
+    std::unique_ptr<qw_state> st(new (std::nothrow) qw_state());
+    if (!st) return fail(ctx, QW_E_OOM, "host allocation");
+    st->ctx = ctx;
+    st->n = n;
+    st->n_slots = n_slots;
+    st->slot_bytes = slot_bytes;
+    st->frozen.assign(n_slots, 0);
+    if (dev_buf) {
+        st->base = static_cast<char *>(dev_buf);
+    } else {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) return hip_fail(ctx, e, "state allocation");
+        st->base = static_cast<char *>(p);
+        st->owned = true;
+    }
+    hipError_t e = launch_init(ctx->stream, st->base, n, n_slots);
+    if (e != hipSuccess) {
+        if (st->owned) hipFree(st->base);
+        return hip_fail(ctx, e, "init launch");
+    }
+    *out = st.release();
+    return QW_OK;
+}
+
+int qw_state_free(qw_state *st) {
+    if (!st) return QW_E_INVALID_ARG;
+    for (uint32_t f : st->frozen)
+        if (f) return fail(st->ctx, QW_E_INVALID_ARG, "state has frozen slots (free the snapshots first)");
+    if (st->owned) {
+        hipStreamSynchronize(st->ctx->stream);
+        hipFree(st->base);
+    }
+    delete st;
+    return QW_OK;
+}
+
+int qw_state_reset(qw_state *st, uint32_t first, uint32_t count) {
+    if (!st) return QW_E_INVALID_ARG;
+    if (!slot_ok(st, first, count)) return fail(st->ctx, QW_E_INVALID_ARG, "slot range out of bounds");
+    for (uint32_t s = first; s < first + count; ++s)
+        if (st->frozen[s]) return fail(st->ctx, QW_E_INVALID_ARG, "slot is frozen by a snapshot");
+    if (count == 0) return QW_OK;
+    hipError_t e = launch_init(st->ctx->stream, slot_ptr(st, first), st->n, count);
+    if (e != hipSuccess) return hip_fail(st->ctx, e, "init launch");
+    return QW_OK;
+}
+
+int qw_state_slot_ptr(const qw_state *st, uint32_t slot, void **dev_ptr) {
+    if (!st || !dev_ptr || slot >= st->n_slots) return QW_E_INVALID_ARG;
+    *dev_ptr = slot_ptr(st, slot);
+    return QW_OK;
+}
+
+int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t n_gates) {
+    if (!st) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = st->ctx;
+    if (slot >= st->n_slots) return fail(ctx, QW_E_INVALID_ARG, "slot out of range");
+    if (st->frozen[slot]) return fail(ctx, QW_E_INVALID_ARG, "slot is frozen by a snapshot");
+    std::vector<Exec> ex(1);
+    std::string e = build_plan((int)st->n, gates, (size_t)n_gates, ctx->tile_bits, &ex[0].plan);
+    if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
+    ex[0].dst = slot_ptr(st, slot);
+    return execute(ctx, st->n, ex);
+}
+
+int qw_snapshot(qw_state *st, uint32_t slot, const uint8_t provenance[32], int mode,
+                const qw_snap *parent, void *copy_buf, uint64_t copy_buf_bytes,
+                qw_snap **out) {
+    if (!st || !out || !provenance) return st ? fail(st->ctx, QW_E_INVALID_ARG, "null argument") : QW_E_INVALID_ARG;
+    qw_ctx *ctx = st->ctx;
+    *out = nullptr;
+    if (slot >= st->n_slots) return fail(ctx, QW_E_INVALID_ARG, "slot out of range");
+    if (mode != QW_SNAP_COPY && mode != QW_SNAP_FREEZE) return fail(ctx, QW_E_INVALID_ARG, "bad mode");
+    if (parent && parent->art.n_qubits != st->n)
+        return fail(ctx, QW_E_INVALID_ARG, "parent snapshot has another qubit count");
+    std::unique_ptr<qw_snap> s(new (std::nothrow) qw_snap());
+    if (!s) return fail(ctx, QW_E_OOM, "host allocation");
+    s->ctx = ctx;
+    s->art.kind = QW_KIND_STATEVECTOR;
+    s->art.exactness = QW_EXACT;
+    s->art.backend = QW_BACKEND_SV;
+    s->art.n_qubits = st->n;
+    s->art.bytes = st->slot_bytes;
+    std::memcpy(s->art.provenance, provenance, 32);
+    s->parent = parent;
+    s->mode = mode;
+    if (mode == QW_SNAP_FREEZE) {
+        s->data = slot_ptr(st, slot);
+        s->fstate = st;
+        s->fslot = slot;
+        st->frozen[slot] += 1;
+    } else {
+        void *dst = copy_buf;
+        if (dst) {
+            if (copy_buf_bytes < st->slot_bytes) return fail(ctx, QW_E_INVALID_ARG, "copy_buf too small");
+            if (reinterpret_cast<uintptr_t>(dst) & 255u)
+                return fail(ctx, QW_E_INVALID_ARG, "copy_buf must be 256-byte aligned");
+        } else {
+            hipError_t e = hipMalloc(&dst, st->slot_bytes);
+            if (e != hipSuccess) return hip_fail(ctx, e, "snapshot allocation");
+            s->owned = dst;
+        }
+        ProfScope ps(ctx, 3, 2.0 * (double)st->slot_bytes);
+        hipError_t e = launch_copy(ctx->stream, dst, slot_ptr(st, slot), st->slot_bytes);
+        if (e != hipSuccess) {
+            if (s->owned) hipFree(s->owned);
+            return hip_fail(ctx, e, "snapshot copy");
+        }
+        s->data = dst;
+    }
+    *out = s.release();
+    return QW_OK;
+}
+
+int qw_snapshot_free(qw_snap *s) {
+    if (!s) return QW_E_INVALID_ARG;
+    if (s->fstate && s->fstate->frozen[s->fslot] > 0) s->fstate->frozen[s->fslot] -= 1;
+    if (s->owned) {
+        hipStreamSynchronize(s->ctx->stream);
+        hipFree(s->owned);
+    }
+    delete s;
+    return QW_OK;
+}
+
+int qw_snapshot_info(const qw_snap *s, qw_artifact *out) {
+    if (!s || !out) return QW_E_INVALID_ARG;
+    *out = s->art;
+    return QW_OK;
+}
+
+int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *tasks,
+                        uint32_t n_tasks, qw_state *dst, const qw_reduce *epi) {
+    if (!ctx || !dst) return ctx ? fail(ctx, QW_E_INVALID_ARG, "null state") : QW_E_INVALID_ARG;
+    if (dst->ctx != ctx) return fail(ctx, QW_E_INVALID_ARG, "state belongs to another context");
+    if (n_tasks > 0 && !tasks) return fail(ctx, QW_E_INVALID_ARG, "tasks == NULL");
+    std::vector<char> seen(dst->n_slots, 0);
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        const uint32_t s = tasks[k].dst_slot;
+        char buf[128];
+        if (s >= dst->n_slots) {
+            snprintf(buf, sizeof buf, "task %u: dst_slot %u out of range", k, s);
+            return fail(ctx, QW_E_INVALID_ARG, buf);
+        }
+        if (seen[s]) {
+            snprintf(buf, sizeof buf, "task %u: dst_slot %u used twice", k, s);
+            return fail(ctx, QW_E_INVALID_ARG, buf);
+        }
+        if (dst->frozen[s]) {
+            snprintf(buf, sizeof buf, "task %u: dst_slot %u is frozen by a snapshot", k, s);
+            return fail(ctx, QW_E_INVALID_ARG, buf);
+        }
+        if (tasks[k].reserved != 0) return fail(ctx, QW_E_INVALID_ARG, "task reserved field must be 0");
+        seen[s] = 1;
+    }
+    // legality gates before any device work (Sec. IV-B)
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        const qw_snap *sn = src ? src[k] : nullptr;
+        if (!sn) continue;
+        std::string js;
+        if (!legal(sn->art, QW_KIND_STATEVECTOR, QW_BACKEND_SV, &js, k))
+            return fail(ctx, QW_E_REFUSED, js);
+        if (sn->art.n_qubits != dst->n)
+            return fail(ctx, QW_E_REFUSED,
+                        refusal_json("QUBIT_COUNT_MISMATCH", "artifact qubit count differs from the target state.",
+                                     sn->art.kind, QW_KIND_STATEVECTOR, sn->art.backend, QW_BACKEND_SV, k));
+        if (std::memcmp(sn->art.provenance, tasks[k].expect_prov, 32) != 0)
+            return fail(ctx, QW_E_REFUSED,
+                        refusal_json("PROVENANCE_MISMATCH", "artifact provenance hash differs from the task's prefix fingerprint.",
+                                     sn->art.kind, QW_KIND_STATEVECTOR, sn->art.backend, QW_BACKEND_SV, k));
+        if (sn->ctx != ctx) return fail(ctx, QW_E_INVALID_ARG, "snapshot belongs to another context");
+    }
+    std::vector<Exec> ex(n_tasks);
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        std::string e = build_plan((int)dst->n, tasks[k].gates, (size_t)tasks[k].n_gates,
+                                   ctx->tile_bits, &ex[k].plan);
+        if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
+        ex[k].src = (src && src[k]) ? src[k]->data : nullptr;
+        ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);
+    }
+    int rc = execute(ctx, dst->n, ex);
+    if (rc) return rc;
+    if (epi) {
+        if (epi->n_terms > 0 && (!epi->x_mask || !epi->z_mask || !epi->coeff))
+            return fail(ctx, QW_E_INVALID_ARG, "epilogue arrays are NULL");
+        if (!epi->out) return fail(ctx, QW_E_INVALID_ARG, "epilogue out is NULL");
+        std::vector<const void *> slots(n_tasks);
+        for (uint32_t k = 0; k < n_tasks; ++k) slots[k] = slot_ptr(dst, tasks[k].dst_slot);
+        return expect_slots(ctx, dst->n, slots, epi->x_mask, epi->z_mask, epi->coeff,
+                            epi->n_terms, epi->out, epi->out_is_host);
+    }
+    return QW_OK;
+}
+
+int qw_expect_pauli(const qw_state *st, uint32_t first, uint32_t count, const uint64_t *x,
+                    const uint64_t *z, const double *c, uint32_t n_terms, double *out,
+                    int out_is_host) {
+    if (!st) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = st->ctx;
+    if (!slot_ok(st, first, count)) return fail(ctx, QW_E_INVALID_ARG, "slot range out of bounds");
+    if (n_terms > 0 && (!x || !z || !c)) return fail(ctx, QW_E_INVALID_ARG, "term arrays are NULL");
+    if (!out && count > 0) return fail(ctx, QW_E_INVALID_ARG, "out is NULL");
+    std::vector<const void *> slots(count);
+    for (uint32_t k = 0; k < count; ++k) slots[k] = slot_ptr(st, first + k);
+    return expect_slots(ctx, st->n, slots, x, z, c, n_terms, out, out_is_host);
+}
+
+int qw_sample(const qw_state *st, uint32_t first, uint32_t count, uint64_t seed,
+              uint64_t task_base, uint32_t shots, uint32_t *out, int out_is_host) {
+    if (!st) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = st->ctx;
+    if (!slot_ok(st, first, count)) return fail(ctx, QW_E_INVALID_ARG, "slot range out of bounds");
+    if (count == 0 || shots == 0) return QW_OK;
+    if (!out) return fail(ctx, QW_E_INVALID_ARG, "out is NULL");
+    const uint32_t n = st->n;
+    const uint32_t C = sample_chunk_bits(n);
+    const uint64_t chunks = 1ull << (n - C);
+    std::vector<const void *> ptrs(count);
+    for (uint32_t k = 0; k < count; ++k) ptrs[k] = slot_ptr(st, first + k);
+    std::vector<uint8_t> blob(count * sizeof(void *));
+    std::memcpy(blob.data(), ptrs.data(), blob.size());
+    int rc = upload(ctx, blob);
+    if (rc) return rc;
+    const size_t cs = (size_t)count * chunks * sizeof(double);
+    const size_t tot = (size_t)count * sizeof(double);
+    const size_t ob = (size_t)count * shots * sizeof(uint32_t);
+    const size_t a1 = (cs + 255) & ~size_t(255), a2 = (tot + 255) & ~size_t(255);
+    rc = ensure(ctx, ctx->scratch, 2 * a1 + a2 + (out_is_host ? ob : 0) + 256, "sample scratch");
+    if (rc) return rc;
+    uint8_t *sb = static_cast<uint8_t *>(ctx->scratch.p);
+    double *csum = reinterpret_cast<double *>(sb);
+    double *cpre = reinterpret_cast<double *>(sb + a1);
+    double *total = reinterpret_cast<double *>(sb + 2 * a1);
+    uint32_t *dout = out_is_host ? reinterpret_cast<uint32_t *>(sb + 2 * a1 + a2) : out;
+    {
+        ProfScope ps(ctx, 2, (double)count * (double)(8ull << n));
+        hipError_t e = launch_sample(ctx->stream, reinterpret_cast<const float2 *const *>(ctx->plan.p),
+                                     count, n, csum, cpre, total, seed, task_base, shots, dout);
+        if (e != hipSuccess) return hip_fail(ctx, e, "sample launch");
+    }
+    if (out_is_host) {
+        HIP_TRY(ctx, hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, ctx->stream), "result copy");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    }
+    return QW_OK;
+}
+
+int qw_legality_check(const qw_artifact *src, uint32_t target_kind, uint32_t target_backend,
+                      char *json_out, uint64_t cap) {
+    if (!src) return QW_E_INVALID_ARG;
+    std::string js;
+    if (legal(*src, target_kind, target_backend, &js)) {
+        if (json_out && cap) json_out[0] = 0;
+        return QW_OK;
+    }
+    if (json_out && cap) {
+        size_t k = std::min<size_t>(js.size(), cap - 1);
+        std::memcpy(json_out, js.data(), k);
+        json_out[k] = 0;
+    }
+    return QW_E_REFUSED;
+}
+
+int qw_plan_describe(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
+                     char *json_out, uint64_t cap) {
+    Plan p;
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    std::string js = e.empty() ? plan_json(p) : ("{\"error\": \"" + json_escape(e) + "\"}");
+    if (json_out && cap) {
+        size_t k = std::min<size_t>(js.size(), cap - 1);
+        std::memcpy(json_out, js.data(), k);
+        json_out[k] = 0;
+    }
+    if (!e.empty()) return QW_E_INVALID_ARG;
+    return js.size() + 1 > cap ? QW_E_INVALID_ARG : QW_OK;
+}
+
+}  // extern "C"

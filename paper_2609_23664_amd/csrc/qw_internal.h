@@ -1,0 +1,171 @@
+// Internal types shared by the host planner, the C ABI and the gfx950
+// kernels of libqw. Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qw {
+
+// ---------------------------------------------------------------- limits
+constexpr int kMaxQubits = 30;      // 8 GiB per complex64 state
+constexpr int kRegBits = 4;         // amplitudes per thread = 2^kRegBits
+constexpr int kMinTileBits = 10;    // register/lane/wave layout needs >= 10
+constexpr int kMaxTileBits = 14;    // 2^14 complex64 = 128 KiB of LDS
+constexpr int kIoLaneLo = 1;        // lanes cover local bits 1..6 at I/O
+constexpr int kIoLaneHi = 6;
+
+// ---------------------------------------------------------------- ops
+// Operations executed on a tile. Bit operands are *local* bit positions
+// (0..m-1) unless the matching GLOBAL flag is set, in which case they are
+// global qubit indices (bits that are constant over the tile).
+enum OpType : uint8_t {
+    OP_U = 1,     // 2x2 complex matrix on local bit a (register slot s)
+    OP_DIAG = 2,  // diag(d0, d1) on bit a
+    OP_PERM = 3,  // [[0, p01], [p10, 0]] on local bit a (register slot s)
+    OP_CX = 4,    // swap the pair on local target a (slot s) where control b is 1
+    OP_CZ = 5,    // negate where bits a and b are both 1
+};
+
+// Where an operand bit lives inside a phase of the register kernel.
+enum BitLoc : uint8_t {
+    LOC_REG = 0,     // register slot (index in `slot` fields)
+    LOC_THREAD = 1,  // a thread-index bit (local bit number in a/b)
+    LOC_GLOBAL = 2,  // non-local: global qubit index in a/b
+};
+
+struct alignas(16) DevOp {
+    uint8_t type;
+    uint8_t a, b;          // local or global bit numbers (see loc)
+    uint8_t sa, sb;        // register slots of a and b when LOC_REG
+    uint8_t la, lb;        // BitLoc of a and b
+    uint8_t pad0;
+    uint32_t pad1[2];
+    float m[8];            // U: m00 m01 m10 m11 (re, im); DIAG: d0 d1;
+                           // PERM: p01 p10
+};
+static_assert(sizeof(DevOp) == 48, "DevOp layout");
+
+// One phase of a pass: the 4 local bits held in registers and the ops run
+// while that mapping is live. Phase 0 and the last phase are I/O capable:
+// register slot 0 is local bit 0 and no register bit lies in the lane bits.
+struct alignas(8) DevPhase {
+    uint8_t reg[4];        // local bit of register slot 0..3 (ascending)
+    uint16_t op_begin;
+    uint16_t op_end;
+};
+static_assert(sizeof(DevPhase) == 8, "DevPhase layout");
+
+// Pass descriptor flags
+enum : uint32_t {
+    PD_SCALE_IN = 1u,    // multiply loaded amplitudes by *scale (FP64)
+    PD_NORM_OUT = 2u,    // write per-tile FP64 sums of |psi|^2
+};
+
+// One (task, pass): a tile sweep over a state slot.
+struct alignas(16) PassDesc {
+    const void *src;       // float2 amplitudes read (may equal dst)
+    void *dst;             // float2 amplitudes written
+    const DevOp *ops;
+    const DevPhase *phases;
+    uint64_t local_mask;   // global bits that are local to a tile
+    const double *scale_in;  // PD_SCALE_IN: factor applied on load
+    double *norm_part;     // PD_NORM_OUT: [tiles] FP64 sums of |psi|^2
+    double *scale_out;     // PD_NORM_OUT: 1/sqrt(sum) written by finalize
+    uint32_t n_ops;
+    uint32_t n_phases;
+    uint32_t flags;
+    uint32_t pad;
+};
+static_assert(sizeof(PassDesc) % 16 == 0, "PassDesc layout");
+
+// Expectation reducer: one group = terms whose X/Y support is local to the
+// tile; one descriptor per (slot, group).
+struct alignas(16) TermDev {
+    uint32_t x_local;      // X/Y support in local bits
+    uint32_t z_local;      // Z/Y support in local bits
+    uint64_t z_global;     // Z/Y support outside the tile
+    uint32_t ny_mod4;      // number of Y factors mod 4
+    uint32_t out_index;    // column of the term in the partial array
+};
+static_assert(sizeof(TermDev) == 24 || sizeof(TermDev) == 32, "TermDev layout");
+
+struct alignas(16) ReduceDesc {
+    const void *psi;       // float2 state slot
+    const TermDev *terms;
+    double *part;          // [tiles][n_terms_total] of this slot
+    uint64_t local_mask;
+    uint32_t n_terms;      // terms of this group
+    uint32_t n_terms_total;
+};
+
+// ---------------------------------------------------------------- host plan
+struct HostOp {
+    OpType type;
+    int a = -1, b = -1;         // global qubits
+    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // FP64 complex entries
+};
+
+struct HostPass {
+    uint64_t local_mask = 0;
+    std::vector<HostOp> ops;    // global-qubit form, execution order
+    bool scale_in = false;
+    bool norm_out = false;
+    // filled by lower_pass():
+    std::vector<DevOp> dev_ops;
+    std::vector<DevPhase> dev_phases;
+};
+
+struct Plan {
+    int n = 0;
+    int m = 0;                  // tile bits
+    std::vector<HostPass> passes;
+    size_t n_gates = 0;
+};
+
+// Validates and plans `gates` on n qubits with at most tile_bits local bits
+// per pass. Returns "" on success, otherwise an error message.
+std::string build_plan(int n, const void *gates /* qw_gate* */, size_t n_gates,
+                       int tile_bits, Plan *out);
+
+// JSON form of a plan (for qw_plan_describe).
+std::string plan_json(const Plan &p);
+
+// Effective tile bits for an n-qubit state.
+inline int tile_bits_for(int n, int max_bits) {
+    return n < max_bits ? n : max_bits;
+}
+
+// Term grouping for the reducer: splits terms into groups whose X/Y support
+// fits one local set. Each group lists term indices and its local mask.
+struct TermGroup {
+    uint64_t local_mask;
+    std::vector<uint32_t> terms;
+};
+std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_terms);
+
+// bit helpers
+inline uint64_t pdep64(uint64_t v, uint64_t mask) {
+    uint64_t r = 0;
+    for (uint64_t bb = 1; mask; bb <<= 1) {
+        uint64_t low = mask & (~mask + 1);
+        if (v & bb) r |= low;
+        mask &= mask - 1;
+    }
+    return r;
+}
+inline uint64_t pext64(uint64_t v, uint64_t mask) {
+    uint64_t r = 0, bb = 1;
+    while (mask) {
+        uint64_t low = mask & (~mask + 1);
+        if (v & low) r |= bb;
+        bb <<= 1;
+        mask &= mask - 1;
+    }
+    return r;
+}
+inline int popc64(uint64_t v) { return __builtin_popcountll(v); }
+
+}  // namespace qw

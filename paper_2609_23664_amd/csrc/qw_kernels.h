@@ -1,0 +1,40 @@
+// Launch wrappers of the gfx950 kernels (qw_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "qw_internal.h"
+
+
+namespace qw {
+
+// Gate pass over n_descs (task, pass) descriptors of one n-qubit layout with
+// tile bits m (m < 10: whole-state kernel). remap: XCD-aware tile order.
+hipError_t launch_pass(hipStream_t st, const PassDesc *d, uint32_t n_descs, uint32_t n,
+                       uint32_t m, int remap);
+// scale_out = 1/sqrt(sum norm_part) for descriptors flagged PD_NORM_OUT.
+hipError_t launch_norm_finalize(hipStream_t st, const PassDesc *d, uint32_t n_descs,
+                                uint32_t tiles);
+// Every slot of [base, base + n_slots * 2^n) set to |0...0>.
+hipError_t launch_init(hipStream_t st, void *base, uint32_t n, uint32_t n_slots);
+// Device-to-device copy of `bytes` (multiple of 16).
+hipError_t launch_copy(hipStream_t st, void *dst, const void *src, uint64_t bytes);
+// Expectation partials for n_descs (slot, term group) descriptors.
+hipError_t launch_reduce(hipStream_t st, const ReduceDesc *d, uint32_t n_descs, uint32_t n,
+                         uint32_t M);
+// Per-slot sum over tiles and terms of the partials.
+hipError_t launch_expect_finalize(hipStream_t st, const double *part, const double *coeff,
+                                  uint32_t n_terms, uint32_t tiles, uint32_t n_slots,
+                                  double *out);
+// Inverse-CDF sampling of `shots` outcomes for n_slots slots (device array
+// of slot pointers). csum/cpre: n_slots * chunks doubles; total: n_slots.
+hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
+                         uint32_t n, double *csum, double *cpre, double *total, uint64_t seed,
+                         uint64_t task_base, uint32_t shots, uint32_t *out);
+inline uint32_t sample_chunk_bits(uint32_t n) { return n < 10 ? n : 10; }
+// One-time kernel attributes (dynamic LDS limits).
+hipError_t kernels_init();
+
+}  // namespace qw

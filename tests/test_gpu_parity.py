@@ -1,0 +1,304 @@
+"""GPU parity of the HIP path against the CPU complex128 oracle.
+
+Bars (from the target statement): state fidelity 1 - |<psi_o|psi_g>|^2 <= 1e-6
+(normalised), expectation error <= 1e-5 * sum_j |c_j|, and the reuse path
+bitwise equal to the direct path. Every case prints its name before running.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+FID_TOL = 1e-6
+EXP_TOL = 1e-5
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2609_23664_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    import torch
+    assert torch.cuda.is_available()
+    c = B.Ctx(0)
+    yield c
+    c.sync()
+
+
+def _fid(a, b):
+    return oracle.fidelity(a.astype(np.complex128), b)
+
+
+def _random_gates(n, g, count, renorm=0.0):
+    names1 = ["X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P"]
+    gates = []
+    for _ in range(count):
+        if n == 1 or g.random() < 0.65:
+            gates.append((names1[g.integers(len(names1))], (int(g.integers(n)),), float(g.uniform(0, 6.3))))
+        else:
+            a, b = g.choice(n, 2, replace=False)
+            gates.append((("CNOT", "CZ")[int(g.integers(2))], (int(a), int(b)), 0.0))
+        if g.random() < renorm:
+            gates.append(("RENORM", (), 0.0))
+    return gates
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 10, 12, 14, 15, 16, 18])
+def test_random_circuits_match_oracle(ctx, B, n):
+    say("random circuit", n)
+    g = np.random.default_rng(1000 + n)
+    gates = _random_gates(n, g, 200, renorm=0.02)
+    st = B.State(ctx, n, 2)
+    st.apply(1, gates)
+    psi = st.host(1)
+    ref = oracle.simulate(n, gates)
+    assert 1 - _fid(psi, ref) <= FID_TOL
+    assert np.array_equal(st.host(0)[:1], np.array([1], dtype=np.complex64))  # slot 0 untouched
+    st.free()
+
+
+@pytest.mark.parametrize("tile", [10, 11, 12, 13, 14])
+def test_tile_bits_sweep_17q(ctx, B, tile):
+    say("tile sweep", tile)
+    n = 17
+    w = gen.small_vqe(n, 2, 1, 1, 9, seed=77)
+    gates = w.task_gates(0)
+    ctx.set_option(B.QW_OPT_TILE_BITS, tile)
+    try:
+        st = B.State(ctx, n, 1)
+        st.apply(0, gates)
+        psi = st.host(0)
+        e = st.expect(0, 1, w.terms)[0]
+    finally:
+        ctx.set_option(B.QW_OPT_TILE_BITS, 14)
+    ref = oracle.simulate(n, gates)
+    assert 1 - _fid(psi, ref) <= FID_TOL
+    assert abs(e - oracle.expect(ref, n, w.terms)) <= EXP_TOL * sum(abs(c) for c, _, _ in w.terms)
+    st.free()
+
+
+def run_reuse(B, ctx, w, terms=None, mode=None):
+    from paper_2609_23664_amd.planner import fingerprint
+    mode = B.QW_SNAP_FREEZE if mode is None else mode
+    st = B.State(ctx, w.n, w.n_tasks + 1)
+    st.apply(0, w.prefix)
+    prov = fingerprint(w.n, w.prefix)
+    snap = st.snapshot(0, prov, mode)
+    e = B.run_suffix_batch(ctx, [snap] * w.n_tasks, w.suffixes, st,
+                           list(range(1, w.n_tasks + 1)), terms=terms)
+    return st, snap, e
+
+
+def run_direct(B, ctx, w, terms=None):
+    st = B.State(ctx, w.n, w.n_tasks)
+    slots = list(range(w.n_tasks))
+    B.run_suffix_batch(ctx, None, [w.prefix] * w.n_tasks, st, slots)
+    e = B.run_suffix_batch(ctx, None, w.suffixes, st, slots, terms=terms)
+    return st, e
+
+
+def _check_vqe(B, ctx, w, oracle_tasks, mode=None):
+    ctot = sum(abs(c) for c, _, _ in w.terms)
+    st_r, snap, e_r = run_reuse(B, ctx, w, w.terms, mode)
+    st_d, e_d = run_direct(B, ctx, w, w.terms)
+    ctx.sync()
+    import torch
+    for t in range(w.n_tasks):
+        assert torch.equal(st_r.buf[t + 1], st_d.buf[t]), f"task {t}: reuse != direct"
+    assert e_r == e_d
+    base = oracle.simulate(w.n, w.prefix)
+    for t in oracle_tasks:
+        ref = oracle.apply_gates(base.copy(), w.n, w.suffixes[t])
+        psi = st_r.host(t + 1)
+        assert 1 - _fid(psi, ref) <= FID_TOL, t
+        assert abs(e_r[t] - oracle.expect(ref, w.n, w.terms)) <= EXP_TOL * ctot, t
+    snap.free()
+    st_r.free()
+    st_d.free()
+    return e_r
+
+
+def test_config1_full(ctx, B):
+    say("config1 10q x16 full")
+    w = gen.config1()
+    _check_vqe(B, ctx, w, range(w.n_tasks))
+
+
+@pytest.mark.parametrize("mode", ["COPY", "FREEZE"])
+def test_vqe_16q_ragged(ctx, B, mode):
+    say("vqe 16q ragged", mode)
+    w = gen.small_vqe(16, 3, 2, 7, 13, seed=91)
+    _check_vqe(B, ctx, w, range(7), getattr(B, "QW_SNAP_" + mode))
+
+
+def test_vqe_20q_weight4(ctx, B):
+    say("vqe 20q")
+    w = gen.small_vqe(20, 4, 2, 5, 50, seed=92)
+    _check_vqe(B, ctx, w, [0, 4])
+
+
+def test_config2_full_24q(ctx, B):
+    say("config2 24q x64 full")
+    w = gen.config2()
+    e = _check_vqe(B, ctx, w, [0, 63])
+    assert all(math.isfinite(x) for x in e)
+
+
+def test_product_state_expectations_24q(ctx, B):
+    # closed form at full size: <P> = prod_q Bloch_q(P_q) for a product state
+    say("product state 24q")
+    n = 24
+    w = gen.config2()
+    g = np.random.default_rng(5)
+    ang = g.uniform(0, 2 * math.pi, 2 * n)
+    gates = [gg for gg in gen.hea_layer(n, ang) if gg[0] != "CNOT"]
+    st = B.State(ctx, n, 1)
+    st.apply(0, gates)
+    vals = st.expect(0, 1, [(1.0, x, z) for _, x, z in w.terms[:1]])
+    ev = []
+    for c, x, z in w.terms:
+        ev.append(st.expect(0, 1, [(1.0, x, z)])[0])
+    for (c, x, z), v in zip(w.terms, ev):
+        s = gen.pauli_string((c, x, z), n)
+        e = 1.0
+        for q, ch in enumerate(s):
+            th, ph = ang[2 * q], ang[2 * q + 1]
+            e *= {"X": math.sin(th) * math.cos(ph), "Y": math.sin(th) * math.sin(ph),
+                  "Z": math.cos(th), "I": 1.0}[ch]
+        assert abs(v - e) <= 1e-5
+    assert abs(vals[0] - ev[0]) <= 1e-12
+    st.free()
+
+
+def test_ghz_24q(ctx, B):
+    say("ghz 24q")
+    n = 24
+    ang = [0.0] * (2 * n)
+    ang[0] = math.pi / 2
+    st = B.State(ctx, n, 1)
+    st.apply(0, gen.hea_layer(n, ang))
+    psi = st.host(0)
+    r = 1 / math.sqrt(2)
+    assert abs(psi[0] - r) < 1e-6 and abs(psi[-1] - r) < 1e-6
+    nz = np.count_nonzero(psi)
+    assert nz == 2
+    out = st.sample(0, 1, 7, 0, 1000)
+    assert set(np.unique(out).tolist()) <= {0, (1 << n) - 1}
+    st.free()
+
+
+@pytest.mark.parametrize("n,shots", [(8, 1000), (14, 1024), (20, 777)])
+def test_sampling_matches_oracle(ctx, B, n, shots):
+    say("sampling", n, shots)
+    w = gen.small_vqe(n, 3, 1, 3, 1, seed=500 + n)
+    st_r, snap, _ = run_reuse(B, ctx, w)
+    out = st_r.sample(1, 3, 12345, 10, shots)
+    base = oracle.simulate(n, w.prefix)
+    same = 0
+    for t in range(3):
+        ref = oracle.apply_gates(base.copy(), n, w.suffixes[t])
+        o = oracle.sample(ref, n, 12345, 10 + t, shots)
+        same += int(np.sum(o == out[t]))
+        # every GPU outcome must have non-zero probability
+        assert np.all(np.abs(ref[out[t]]) > 0)
+    assert same >= 0.999 * 3 * shots
+    snap.free()
+    st_r.free()
+
+
+def test_noisy_trajectories_match_oracle(ctx, B):
+    say("noisy 14q")
+    w = gen.small_noisy(14, 3, 2, 12, 0.02, seed=7, shots=0)
+    assert sum(t != w.suffix for t in w.trajectories) >= 3
+    from paper_2609_23664_amd.planner import fingerprint
+    st = B.State(ctx, w.n, len(w.trajectories) + 1)
+    st.apply(0, w.prefix)
+    snap = st.snapshot(0, fingerprint(w.n, w.prefix), B.QW_SNAP_FREEZE)
+    B.run_suffix_batch(ctx, [snap] * len(w.trajectories), w.trajectories, st,
+                       list(range(1, len(w.trajectories) + 1)))
+    base = oracle.simulate(w.n, w.prefix)
+    for t, traj in enumerate(w.trajectories):
+        ref = oracle.apply_gates(base.copy(), w.n, traj)
+        psi = st.host(t + 1)
+        assert 1 - _fid(psi, ref) <= FID_TOL
+        norm = float(np.vdot(psi.astype(np.complex128), psi.astype(np.complex128)).real)
+        assert abs(norm - 1.0) < 1e-5
+    snap.free()
+    st.free()
+
+
+def test_refusal_then_direct_fallback(ctx, B):
+    say("refusal")
+    from paper_2609_23664_amd.planner import fingerprint
+    w = gen.small_vqe(12, 2, 1, 3, 4, seed=3)
+    st = B.State(ctx, w.n, 4)
+    st.apply(0, w.prefix)
+    snap = st.snapshot(0, fingerprint(w.n, w.prefix), B.QW_SNAP_COPY)
+    bad = [bytes(32)] * 3
+    with pytest.raises(B.QwRefused) as ei:
+        B.run_suffix_batch(ctx, [snap] * 3, w.suffixes, st, [1, 2, 3], expect_provs=bad)
+    rec = ei.value.record
+    assert rec["reason"] == "PROVENANCE_MISMATCH"
+    for f in ("detail", "source_kind", "target_kind", "source_backend", "target_backend"):
+        assert f in rec
+    # nothing ran: slots 1..3 still |0...0>
+    for s in (1, 2, 3):
+        h = st.host(s)
+        assert h[0] == 1 and np.count_nonzero(h) == 1
+    # fallback: direct rerun from scratch equals the reuse result
+    st_d, _ = run_direct(B, ctx, w)
+    st_r, snap2, _ = run_reuse(B, ctx, w)
+    import torch
+    for t in range(3):
+        assert torch.equal(st_d.buf[t], st_r.buf[t + 1])
+    for o in (snap, snap2):
+        o.free()
+    for o in (st, st_d, st_r):
+        o.free()
+
+
+def test_empty_suffix_copies_snapshot(ctx, B):
+    say("empty suffix")
+    from paper_2609_23664_amd.planner import fingerprint
+    n = 16
+    w = gen.small_vqe(n, 2, 1, 1, 1, seed=4)
+    st = B.State(ctx, n, 3)
+    st.apply(0, w.prefix)
+    snap = st.snapshot(0, fingerprint(n, w.prefix), B.QW_SNAP_FREEZE)
+    B.run_suffix_batch(ctx, [snap, snap], [[], w.suffixes[0]], st, [1, 2])
+    B.run_suffix_batch(ctx, [], [], st, [])  # zero tasks is a no-op
+    import torch
+    ctx.sync()
+    assert torch.equal(st.buf[0], st.buf[1])
+    with pytest.raises(B.QwError):  # frozen slot cannot be a destination
+        B.run_suffix_batch(ctx, None, [w.suffixes[0]], st, [0])
+    snap.free()
+    st.free()
+
+
+def test_run_twice_bitwise(ctx, B):
+    say("determinism")
+    w = gen.small_vqe(18, 2, 2, 4, 20, seed=11)
+    st1, s1, e1 = run_reuse(B, ctx, w, w.terms)
+    st2, s2, e2 = run_reuse(B, ctx, w, w.terms)
+    import torch
+    ctx.sync()
+    assert torch.equal(st1.buf, st2.buf) and e1 == e2
+    for o in (s1, s2):
+        o.free()
+    for o in (st1, st2):
+        o.free()

@@ -1,0 +1,144 @@
+"""Host checks of the pass planner (no GPU).
+
+The plan that libqw would execute (qw_plan_describe) is interpreted here with
+numpy, op by op with the kernel's op semantics, and compared with the oracle;
+this checks fusion, gate reordering, local-bit mapping and phase grouping
+independently of the GPU. Structural properties (passes per HEA layer, I/O
+phases, register sets) are checked too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_23664_amd import binding as B
+from workloads import gen
+
+LOC_REG, LOC_THREAD, LOC_GLOBAL = 0, 1, 2
+OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ = 1, 2, 3, 4, 5
+
+
+def _local_bits(mask):
+    return [q for q in range(64) if (mask >> q) & 1]
+
+
+def interpret(n, plan, psi):
+    psi = psi.astype(np.complex128).copy()
+    idx = np.arange(1 << n)
+    for p in plan["passes"]:
+        lb = _local_bits(p["local_mask"])
+        assert len(lb) == plan["tile_bits"]
+        if p["scale_in"]:
+            psi /= np.sqrt(np.vdot(psi, psi).real)
+        for op in p["ops"]:
+            def gbit(loc, b):
+                return b if loc == LOC_GLOBAL else lb[b]
+            m = op["m"]
+            t = op["type"]
+            if t in (OP_U, OP_PERM):
+                assert op["la"] != LOC_GLOBAL
+                g = gbit(op["la"], op["a"])
+                i0 = idx[((idx >> g) & 1) == 0]
+                i1 = i0 | (1 << g)
+                x, y = psi[i0].copy(), psi[i1].copy()
+                if t == OP_U:
+                    a, b, c, d = (m[0] + 1j * m[1], m[2] + 1j * m[3], m[4] + 1j * m[5], m[6] + 1j * m[7])
+                    psi[i0], psi[i1] = a * x + b * y, c * x + d * y
+                else:
+                    psi[i0], psi[i1] = (m[0] + 1j * m[1]) * y, (m[2] + 1j * m[3]) * x
+            elif t == OP_DIAG:
+                g = gbit(op["la"], op["a"])
+                d = np.where((idx >> g) & 1, m[2] + 1j * m[3], m[0] + 1j * m[1])
+                psi *= d
+            elif t == OP_CX:
+                assert op["la"] != LOC_GLOBAL
+                g = gbit(op["la"], op["a"])
+                c = gbit(op["lb"], op["b"])
+                sel = (((idx >> c) & 1) == 1) & (((idx >> g) & 1) == 0)
+                i0 = idx[sel]
+                i1 = i0 | (1 << g)
+                psi[i0], psi[i1] = psi[i1].copy(), psi[i0].copy()
+            elif t == OP_CZ:
+                a = gbit(op["la"], op["a"])
+                b = gbit(op["lb"], op["b"])
+                psi[((idx >> a) & 1) & ((idx >> b) & 1) == 1] *= -1
+            else:
+                raise AssertionError(t)
+    return psi
+
+
+def _check_phases(plan):
+    m = plan["tile_bits"]
+    if m < 10:
+        return
+    for p in plan["passes"]:
+        ph = p["phases"]
+        assert ph[0]["op_begin"] == 0 and ph[-1]["op_end"] == len(p["ops"])
+        for a, b in zip(ph, ph[1:]):
+            assert a["op_end"] == b["op_begin"]
+        for k, f in enumerate(ph):
+            reg = f["reg"]
+            assert len(set(reg)) == 4 and reg == sorted(reg) and max(reg) < m
+            if k == 0 or k == len(ph) - 1:
+                assert reg[0] == 0 and not any(1 <= r <= 6 for r in reg)
+            for op in p["ops"][f["op_begin"]:f["op_end"]]:
+                if op["type"] in (OP_U, OP_PERM, OP_CX):
+                    assert op["la"] == LOC_REG and reg[op["sa"]] == op["a"]
+                for loc, b, s in ((op["la"], op["a"], op["sa"]), (op["lb"], op["b"], op["sb"])):
+                    if loc == LOC_REG:
+                        assert reg[s] == b
+
+
+@pytest.mark.parametrize("n,tile", [(6, 14), (10, 14), (12, 10), (13, 11), (16, 12), (16, 14), (18, 10)])
+def test_plan_matches_oracle_hea(n, tile):
+    w = gen.small_vqe(n, 3, 2, 1, 1, seed=40 + n)
+    gates = w.task_gates(0)
+    plan = B.plan_describe(n, gates, tile)
+    _check_phases(plan)
+    psi = interpret(n, plan, oracle.zero_state(n))
+    ref = oracle.simulate(n, gates)
+    assert np.max(np.abs(psi - ref)) < 2e-5
+
+
+@pytest.mark.parametrize("n,tile", [(11, 10), (15, 12)])
+def test_plan_matches_oracle_random_gates(n, tile):
+    g = np.random.default_rng(n)
+    names1 = ["X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P"]
+    gates = []
+    for _ in range(300):
+        if g.random() < 0.65:
+            gates.append((names1[g.integers(len(names1))], (int(g.integers(n)),), float(g.uniform(0, 6.3))))
+        else:
+            a, b = g.choice(n, 2, replace=False)
+            gates.append((("CNOT", "CZ")[int(g.integers(2))], (int(a), int(b)), 0.0))
+        if g.random() < 0.02:
+            gates.append(("RENORM", (), 0.0))
+    plan = B.plan_describe(n, gates, tile)
+    _check_phases(plan)
+    psi = interpret(n, plan, oracle.zero_state(n))
+    ref = oracle.simulate(n, gates)
+    assert np.max(np.abs(psi - ref)) < 5e-5
+
+
+def test_hea_24q_two_passes_per_layer():
+    w = gen.config2()
+    pre = B.plan_describe(24, w.prefix)
+    suf = B.plan_describe(24, w.suffixes[0])
+    assert len(suf["passes"]) == 4
+    assert len(pre["passes"]) <= 12
+    for p in pre["passes"] + suf["passes"]:
+        assert p["local_mask"] & 0xF == 0xF   # 128-byte runs
+
+
+def test_renorm_marks_norm_and_scale():
+    gates = [("RY", (0,), 0.3), ("RENORM", (), 0.0), ("RY", (1,), 0.2), ("RENORM", (), 0.0)]
+    plan = B.plan_describe(12, gates)
+    ps = plan["passes"]
+    assert ps[0]["norm_out"] == 1 and ps[1]["scale_in"] == 1 and ps[1]["norm_out"] == 1
+    assert ps[-1]["scale_in"] == 1
+
+
+def test_plan_is_deterministic():
+    w = gen.small_vqe(20, 2, 2, 1, 1, seed=3)
+    a = B.plan_describe(20, w.task_gates(0))
+    b = B.plan_describe(20, w.task_gates(0))
+    assert a == b
