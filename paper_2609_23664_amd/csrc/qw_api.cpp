@@ -309,13 +309,27 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         step_off[k] = L.take(step_cnt[k] * sizeof(PassDesc));
     }
     std::vector<std::vector<std::pair<size_t, size_t>>> op_off(ex.size());
+    std::vector<std::vector<size_t>> io_off(ex.size());
     for (size_t t = 0; t < ex.size(); ++t) {
         for (HostPass &p : ex[t].plan.passes) {
             size_t oo = L.take(std::max<size_t>(1, p.dev_ops.size()) * sizeof(DevOp));
             size_t po = L.take(std::max<size_t>(1, p.dev_phases.size()) * sizeof(DevPhase));
             op_off[t].push_back({oo, po});
+            io_off[t].push_back(L.take(2 * sizeof(IoRec)));
         }
     }
+    // per distinct local mask: table of the global index of each tile's origin
+    std::vector<std::pair<uint64_t, size_t>> tb_off;
+    auto tile_table = [&](uint64_t lmask) -> size_t {
+        for (auto &e : tb_off)
+            if (e.first == lmask) return e.second;
+        size_t off = L.take((size_t)tiles * sizeof(uint32_t));
+        tb_off.push_back({lmask, off});
+        return off;
+    };
+    std::vector<std::vector<size_t>> tb_of(ex.size());
+    for (size_t t = 0; t < ex.size(); ++t)
+        for (HostPass &p : ex[t].plan.passes) tb_of[t].push_back(tile_table(p.local_mask));
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
     uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
@@ -327,9 +341,19 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                         p.dev_ops.size() * sizeof(DevOp));
             std::memcpy(blob.data() + op_off[t][k].second, p.dev_phases.data(),
                         p.dev_phases.size() * sizeof(DevPhase));
+            std::memcpy(blob.data() + io_off[t][k], &p.io_in, sizeof(IoRec));
+            std::memcpy(blob.data() + io_off[t][k] + sizeof(IoRec), &p.io_out, sizeof(IoRec));
         }
     }
-    std::vector<char> step_norm(steps, 0);
+    {
+        const uint64_t full = (1ull << n) - 1;
+        for (auto &e : tb_off) {
+            uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
+            const uint64_t nl = full & ~e.first;
+            for (uint32_t ti = 0; ti < tiles; ++ti) tb[ti] = (uint32_t)pdep64(ti, nl);
+        }
+    }
+    std::vector<char> step_norm(steps, 0), step_lds(steps, 0);
     for (size_t k = 0; k < steps; ++k) {
         size_t c = 0;
         for (size_t t = 0; t < ex.size(); ++t) {
@@ -346,10 +370,14 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             d.scale_in = nb ? nb + tiles : nullptr;
             d.norm_part = nb;
             d.scale_out = nb ? nb + tiles : nullptr;
+            d.tile_base = reinterpret_cast<const uint32_t *>(dbase + tb_of[t][k]);
+            d.io_in = reinterpret_cast<const IoRec *>(dbase + io_off[t][k]);
+            d.io_out = reinterpret_cast<const IoRec *>(dbase + io_off[t][k] + sizeof(IoRec));
             d.n_ops = (uint32_t)p.dev_ops.size();
             d.n_phases = (uint32_t)p.dev_phases.size();
             d.flags = (p.scale_in ? PD_SCALE_IN : 0u) | (p.norm_out ? PD_NORM_OUT : 0u);
             if (p.norm_out) step_norm[k] = 1;
+            if (p.norm_out || p.dev_phases.size() > 1) step_lds[k] = 1;
             std::memcpy(blob.data() + step_off[k] + c * sizeof(PassDesc), &d, sizeof d);
             ++c;
         }
@@ -361,7 +389,7 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         {
             ProfScope ps(ctx, 0, (double)step_cnt[k] * 2.0 * (double)state_bytes);
             hipError_t er = launch_pass(ctx->stream, dd, (uint32_t)step_cnt[k], n, (uint32_t)m,
-                                        ctx->xcd_remap ? 1 : 0);
+                                        ctx->xcd_remap ? 1 : 0, step_lds[k] != 0);
             if (er != hipSuccess) return hip_fail(ctx, er, "pass launch");
         }
         if (step_norm[k]) {
@@ -394,13 +422,27 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
         return QW_OK;
     }
     const int m = tile_bits_for((int)n, ctx->tile_bits);
-    const uint32_t tiles = 1u << (n - m);
+    const bool small = m < kMinTileBits;
+    const uint32_t tiles = small ? 1u : (1u << (n - m));
     std::vector<TermGroup> groups = group_terms((int)n, m, x, n_terms);
+    std::vector<RedPlan> rplans;
+    if (!small)
+        for (const TermGroup &g : groups) rplans.push_back(plan_reduce_group((int)n, m, g, x, z));
     Layout L;
-    std::vector<size_t> g_off(groups.size());
-    for (size_t g = 0; g < groups.size(); ++g) g_off[g] = L.take(groups[g].terms.size() * sizeof(TermDev));
+    std::vector<size_t> t_off(groups.size()), p_off(groups.size()), c_off(groups.size());
+    size_t small_terms_off = 0;
+    if (small) {
+        small_terms_off = L.take(n_terms * sizeof(TermSmall));
+    } else {
+        for (size_t g = 0; g < groups.size(); ++g) {
+            t_off[g] = L.take(rplans[g].terms.size() * sizeof(TermDev));
+            p_off[g] = L.take(rplans[g].phases.size() * sizeof(RedPhase));
+            c_off[g] = L.take(rplans[g].cols.size() * sizeof(uint32_t));
+        }
+    }
     const size_t coeff_off = L.take(n_terms * sizeof(double));
-    const size_t desc_off = L.take(ns * groups.size() * sizeof(ReduceDesc));
+    const size_t n_desc = small ? ns : ns * groups.size();
+    const size_t desc_off = L.take(n_desc * (small ? sizeof(ReduceDescSmall) : sizeof(ReduceDesc)));
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
     const size_t part_bytes = (size_t)ns * tiles * n_terms * sizeof(double);
@@ -414,41 +456,58 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
                                      ((part_bytes + 255) & ~size_t(255)))
                                : out;
     std::vector<uint8_t> blob(L.size, 0);
-    for (size_t g = 0; g < groups.size(); ++g) {
-        const uint64_t lm = groups[g].local_mask;
-        for (size_t i = 0; i < groups[g].terms.size(); ++i) {
-            const uint32_t j = groups[g].terms[i];
-            TermDev t{};
-            t.x_local = (uint32_t)pext64(x[j], lm);
-            t.z_local = (uint32_t)pext64(z[j], lm);
-            t.z_global = z[j] & ~lm;
+    std::memcpy(blob.data() + coeff_off, c, n_terms * sizeof(double));
+    if (small) {
+        for (uint32_t j = 0; j < n_terms; ++j) {
+            TermSmall t{};
+            t.x = (uint32_t)x[j];
+            t.z = (uint32_t)z[j];
             t.ny_mod4 = (uint32_t)(popc64(x[j] & z[j]) & 3);
             t.out_index = j;
-            std::memcpy(blob.data() + g_off[g] + i * sizeof(TermDev), &t, sizeof t);
+            std::memcpy(blob.data() + small_terms_off + j * sizeof(TermSmall), &t, sizeof t);
         }
-    }
-    std::memcpy(blob.data() + coeff_off, c, n_terms * sizeof(double));
-    size_t di = 0;
-    for (uint32_t s = 0; s < ns; ++s) {
-        for (size_t g = 0; g < groups.size(); ++g) {
-            ReduceDesc d{};
+        for (uint32_t s = 0; s < ns; ++s) {
+            ReduceDescSmall d{};
             d.psi = slots[s];
-            d.terms = reinterpret_cast<const TermDev *>(dbase + g_off[g]);
-            d.part = part + (size_t)s * tiles * n_terms;
-            d.local_mask = groups[g].local_mask;
-            d.n_terms = (uint32_t)groups[g].terms.size();
-            d.n_terms_total = n_terms;
-            std::memcpy(blob.data() + desc_off + di * sizeof(ReduceDesc), &d, sizeof d);
-            ++di;
+            d.terms = reinterpret_cast<const TermSmall *>(dbase + small_terms_off);
+            d.part = part + (size_t)s * n_terms;
+            d.n_terms = n_terms;
+            std::memcpy(blob.data() + desc_off + s * sizeof(ReduceDescSmall), &d, sizeof d);
+        }
+    } else {
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const RedPlan &rp = rplans[g];
+            std::memcpy(blob.data() + t_off[g], rp.terms.data(), rp.terms.size() * sizeof(TermDev));
+            std::memcpy(blob.data() + p_off[g], rp.phases.data(), rp.phases.size() * sizeof(RedPhase));
+            std::memcpy(blob.data() + c_off[g], rp.cols.data(), rp.cols.size() * sizeof(uint32_t));
+        }
+        size_t di = 0;
+        for (uint32_t s = 0; s < ns; ++s) {
+            for (size_t g = 0; g < groups.size(); ++g) {
+                ReduceDesc d{};
+                d.psi = slots[s];
+                d.terms = reinterpret_cast<const TermDev *>(dbase + t_off[g]);
+                d.phases = reinterpret_cast<const RedPhase *>(dbase + p_off[g]);
+                d.cols = reinterpret_cast<const uint32_t *>(dbase + c_off[g]);
+                d.part = part + (size_t)s * tiles * n_terms;
+                d.local_mask = groups[g].local_mask;
+                d.n_phases = (uint32_t)rplans[g].phases.size();
+                d.n_terms = (uint32_t)rplans[g].terms.size();
+                d.n_terms_total = n_terms;
+                std::memcpy(blob.data() + desc_off + di * sizeof(ReduceDesc), &d, sizeof d);
+                ++di;
+            }
         }
     }
     rc = upload(ctx, blob);
     if (rc) return rc;
     {
         ProfScope ps(ctx, 1, (double)ns * groups.size() * (double)(8ull << n));
-        hipError_t er = launch_reduce(ctx->stream,
-                                      reinterpret_cast<const ReduceDesc *>(dbase + desc_off),
-                                      (uint32_t)di, n, (uint32_t)m);
+        hipError_t er = small
+            ? launch_reduce_small(ctx->stream, reinterpret_cast<const ReduceDescSmall *>(dbase + desc_off),
+                                  ns, n)
+            : launch_reduce(ctx->stream, reinterpret_cast<const ReduceDesc *>(dbase + desc_off),
+                            (uint32_t)n_desc, n, (uint32_t)m);
         if (er != hipSuccess) return hip_fail(ctx, er, "reduce launch");
     }
     hipError_t er = launch_expect_finalize(ctx->stream, part,

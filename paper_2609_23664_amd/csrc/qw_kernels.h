@@ -12,8 +12,10 @@ namespace qw {
 
 // Gate pass over n_descs (task, pass) descriptors of one n-qubit layout with
 // tile bits m (m < 10: whole-state kernel). remap: XCD-aware tile order.
+// use_lds = false is valid only when every descriptor has one phase and no
+// PD_NORM_OUT; the kernel then runs without LDS at higher occupancy.
 hipError_t launch_pass(hipStream_t st, const PassDesc *d, uint32_t n_descs, uint32_t n,
-                       uint32_t m, int remap);
+                       uint32_t m, int remap, bool use_lds);
 // scale_out = 1/sqrt(sum norm_part) for descriptors flagged PD_NORM_OUT.
 hipError_t launch_norm_finalize(hipStream_t st, const PassDesc *d, uint32_t n_descs,
                                 uint32_t tiles);
@@ -24,6 +26,8 @@ hipError_t launch_copy(hipStream_t st, void *dst, const void *src, uint64_t byte
 // Expectation partials for n_descs (slot, term group) descriptors.
 hipError_t launch_reduce(hipStream_t st, const ReduceDesc *d, uint32_t n_descs, uint32_t n,
                          uint32_t M);
+hipError_t launch_reduce_small(hipStream_t st, const ReduceDescSmall *d, uint32_t n_descs,
+                               uint32_t n);
 // Per-slot sum over tiles and terms of the partials.
 hipError_t launch_expect_finalize(hipStream_t st, const double *part, const double *coeff,
                                   uint32_t n_terms, uint32_t tiles, uint32_t n_slots,

@@ -160,34 +160,123 @@ std::vector<std::vector<int>> greedy_passes(int n, int m, const std::vector<G> &
     return passes;
 }
 
+// Split a 2x2 unitary M into D2 * R * D1 with R real and D1, D2 diagonal;
+// returns false if no such split was found (M is then kept complex).
+bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
+    auto ph = [](cd z) { return z / std::abs(z); };
+    auto small = [](double x) { return std::fabs(x) < 1e-13; };
+    // row phases: M = diag(p0, p1) * R
+    {
+        cd p0 = std::abs(M.a) >= std::abs(M.b) ? ph(M.a) : ph(M.b);
+        cd p1 = std::abs(M.c) >= std::abs(M.d) ? ph(M.c) : ph(M.d);
+        cd r00 = M.a / p0, r01 = M.b / p0, r10 = M.c / p1, r11 = M.d / p1;
+        if (small(r00.imag()) && small(r01.imag()) && small(r10.imag()) && small(r11.imag())) {
+            *D2 = {p0, 0.0, 0.0, p1};
+            *R = {r00.real(), r01.real(), r10.real(), r11.real()};
+            *D1 = {1.0, 0.0, 0.0, 1.0};
+            return true;
+        }
+    }
+    // column phases: M = R * diag(q0, q1)
+    {
+        cd q0 = std::abs(M.a) >= std::abs(M.c) ? ph(M.a) : ph(M.c);
+        cd q1 = std::abs(M.b) >= std::abs(M.d) ? ph(M.b) : ph(M.d);
+        cd r00 = M.a / q0, r01 = M.b / q1, r10 = M.c / q0, r11 = M.d / q1;
+        if (small(r00.imag()) && small(r01.imag()) && small(r10.imag()) && small(r11.imag())) {
+            *D2 = {1.0, 0.0, 0.0, 1.0};
+            *R = {r00.real(), r01.real(), r10.real(), r11.real()};
+            *D1 = {q0, 0.0, 0.0, q1};
+            return true;
+        }
+    }
+    // general: c = |M00|, s = |M10|, D2 = diag(M00/c, M10/s), D1 = diag(1, e)
+    const double c = std::abs(M.a), s = std::abs(M.c);
+    if (c < 1e-12 || s < 1e-12) return false;
+    const cd p0 = M.a / c, p1 = M.c / s;
+    const cd e = M.d / (p1 * c);
+    *D2 = {p0, 0.0, 0.0, p1};
+    *R = {c, -s, s, c};
+    *D1 = {1.0, 0.0, 0.0, e};
+    const M2 chk = mul(mul(*D2, *R), *D1);
+    return std::abs(chk.a - M.a) + std::abs(chk.b - M.b) + std::abs(chk.c - M.c) +
+               std::abs(chk.d - M.d) < 1e-12;
+}
+
+bool is_identity(const M2 &u) { return u.a == 1.0 && u.d == 1.0 && u.b == 0.0 && u.c == 0.0; }
+
 // Fuse runs of single-qubit gates per qubit (FP64 products, rounded once to
 // FP32 when lowered) and emit ops in an order equivalent to the gate order.
+// Each mixing run becomes a real 2x2 rotation framed by diagonal factors;
+// diagonal factors stay pending (they commute with each other, with CZ and
+// with CNOT controls) and are emitted together as one OP_DSET at the first
+// op that does not commute with one of them.
 std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<int> &idx) {
     std::vector<HostOp> ops;
     std::vector<M2> pend(n);
     std::vector<char> has(n, 0);
+    std::vector<M2> dpend(n);      // pending diagonal factor per qubit
+    std::vector<char> dhas(n, 0);
+    auto add_diag = [&](int q, const M2 &d) {
+        if (is_identity(d)) return;
+        if (dhas[q]) {
+            dpend[q] = mul(d, dpend[q]);
+        } else {
+            dpend[q] = d;
+            dhas[q] = 1;
+        }
+    };
+    auto emit_dset = [&]() {
+        HostOp set;
+        set.type = OP_DSET;
+        for (int q = 0; q < n; ++q) {
+            if (!dhas[q]) continue;
+            dhas[q] = 0;
+            if (is_identity(dpend[q])) continue;
+            HostOp d;
+            d.type = OP_DIAG;
+            d.a = q;
+            d.m[0] = dpend[q].a.real(); d.m[1] = dpend[q].a.imag();
+            d.m[2] = dpend[q].d.real(); d.m[3] = dpend[q].d.imag();
+            set.members.push_back(d);
+        }
+        if (set.members.size() == 1) ops.push_back(set.members[0]);
+        else if (!set.members.empty()) ops.push_back(set);
+    };
     auto flush = [&](int q) {
         if (!has[q]) return;
         has[q] = 0;
         const M2 &u = pend[q];
+        if (u.b == 0.0 && u.c == 0.0) {  // diagonal run
+            add_diag(q, u);
+            return;
+        }
         HostOp op;
         op.a = q;
-        if (u.b == 0.0 && u.c == 0.0) {
-            if (u.a == 1.0 && u.d == 1.0) return;  // exact identity
-            op.type = OP_DIAG;
-            op.m[0] = u.a.real(); op.m[1] = u.a.imag();
-            op.m[2] = u.d.real(); op.m[3] = u.d.imag();
-        } else if (u.a == 0.0 && u.d == 0.0) {
+        if (u.a == 0.0 && u.d == 0.0) {  // exact swap with phases
+            if (dhas[q]) emit_dset();
             op.type = OP_PERM;
             op.m[0] = u.b.real(); op.m[1] = u.b.imag();
             op.m[2] = u.c.real(); op.m[3] = u.c.imag();
-        } else {
-            op.type = OP_U;
-            op.m[0] = u.a.real(); op.m[1] = u.a.imag();
-            op.m[2] = u.b.real(); op.m[3] = u.b.imag();
-            op.m[4] = u.c.real(); op.m[5] = u.c.imag();
-            op.m[6] = u.d.real(); op.m[7] = u.d.imag();
+            ops.push_back(op);
+            return;
         }
+        M2 D2, R, D1;
+        if (split_real(u, &D2, &R, &D1)) {
+            add_diag(q, D1);
+            if (dhas[q]) emit_dset();
+            op.type = OP_UR;
+            op.m[0] = R.a.real(); op.m[1] = R.b.real();
+            op.m[2] = R.c.real(); op.m[3] = R.d.real();
+            ops.push_back(op);
+            add_diag(q, D2);
+            return;
+        }
+        if (dhas[q]) emit_dset();
+        op.type = OP_U;
+        op.m[0] = u.a.real(); op.m[1] = u.a.imag();
+        op.m[2] = u.b.real(); op.m[3] = u.b.imag();
+        op.m[4] = u.c.real(); op.m[5] = u.c.imag();
+        op.m[6] = u.d.real(); op.m[7] = u.d.imag();
         ops.push_back(op);
     };
     for (int i : idx) {
@@ -196,11 +285,13 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
             flush(g.q0);
             flush(g.q1);
             HostOp op;
-            op.type = (g.cls == C_CX) ? OP_CX : OP_CZ;
             if (g.cls == C_CX) {
+                if (dhas[g.q1]) emit_dset();  // a diagonal on the target does not commute
+                op.type = OP_CX;
                 op.a = g.q1;  // target
                 op.b = g.q0;  // control
             } else {
+                op.type = OP_CZ;
                 op.a = g.q0;
                 op.b = g.q1;
             }
@@ -216,132 +307,243 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
         }
     }
     for (int q = 0; q < n; ++q) flush(q);
+    emit_dset();
     return ops;
 }
 
 int local_index(uint64_t mask, int g) { return popc64(mask & ((1ull << g) - 1)); }
 
-bool io_ok(const std::vector<int> &R) {
-    // slot 0 is local bit 0; no register bit among the lane bits 1..6
-    bool has0 = false;
-    for (int b : R) {
-        if (b == 0) has0 = true;
-        if (b >= kIoLaneLo && b <= kIoLaneHi) return false;
-    }
-    return has0 || (int)R.size() < kRegBits;
+// Layout helpers (see IoKind in qw_internal.h).
+uint32_t lane_bits_of(int m, uint32_t R) {
+    uint32_t lanes = 0;
+    int c = 0;
+    for (int b = 0; b < m && c < 6; ++b)
+        if (!((R >> b) & 1u)) {
+            lanes |= 1u << b;
+            ++c;
+        }
+    return lanes;
 }
 
-// Split a lowered pass into register phases (register kernel only, m >= 10).
-void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops) {
-    // Per op: register need (local bit or -1) and blocking bits (local).
-    struct Info { int need; uint32_t bits; };
-    std::vector<Info> info(lops.size());
-    for (size_t i = 0; i < lops.size(); ++i) {
-        const DevOp &o = lops[i];
-        Info in{-1, 0};
-        bool a_loc = o.la != LOC_GLOBAL, b_loc = o.lb != LOC_GLOBAL;
-        switch (o.type) {
-        case OP_U: case OP_PERM: in.need = o.a; in.bits = 1u << o.a; break;
-        case OP_CX: in.need = o.a; in.bits = (1u << o.a) | (b_loc ? (1u << o.b) : 0u); break;
-        case OP_DIAG: in.bits = a_loc ? (1u << o.a) : 0u; break;
-        case OP_CZ: in.bits = (a_loc ? (1u << o.a) : 0u) | (b_loc ? (1u << o.b) : 0u); break;
-        default: break;
+uint8_t io_kind_of(int m, uint32_t R) {
+    const uint32_t lanes = lane_bits_of(m, R);
+    if ((R & 1u) && lanes == 0x7Eu) return IO_F4;
+    if (lanes == 0x3Fu) return IO_F2;
+    return IO_NONE;
+}
+
+// Fill R up to 4 bits with the highest unused local bits (keeps the lowest
+// bits as lanes, which makes the layout I/O capable when possible).
+uint32_t pad_high(int m, uint32_t R) {
+    for (int b = m - 1; b >= 0 && popc64(R) < kRegBits; --b) R |= 1u << b;
+    return R;
+}
+
+// Split a lowered pass into phases (register kernel only, m >= 10). In a
+// phase, an op whose target bit is a register or lane bit runs without any
+// data exchange; moving to a layout with other wave bits costs one LDS
+// exchange. Greedy: ops are taken in order, a blocked op blocks its bits.
+void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vector<int> &unit_len) {
+    // units: a single op, or an OP_DSET header with its members
+    std::vector<size_t> ustart;
+    {
+        size_t pos = 0;
+        for (int len : unit_len) {
+            ustart.push_back(pos);
+            pos += (size_t)len;
         }
-        info[i] = in;
     }
-    std::vector<int> remaining(lops.size());
-    for (size_t i = 0; i < lops.size(); ++i) remaining[i] = (int)i;
+    struct Info { int need; uint32_t bits; };
+    std::vector<Info> info(unit_len.size());
+    for (size_t u = 0; u < unit_len.size(); ++u) {
+        Info in{-1, 0};
+        for (int j = 0; j < unit_len[u]; ++j) {
+            const DevOp &o = lops_in[ustart[u] + j];
+            bool a_loc = o.la != LOC_GLOBAL, b_loc = o.lb != LOC_GLOBAL;
+            switch (o.type) {
+            case OP_U: case OP_PERM: case OP_UR: in.need = o.a; in.bits |= 1u << o.a; break;
+            case OP_CX: in.need = o.a; in.bits |= (1u << o.a) | (b_loc ? (1u << o.b) : 0u); break;
+            case OP_DIAG: in.bits |= a_loc ? (1u << o.a) : 0u; break;
+            case OP_CZ: in.bits |= (a_loc ? (1u << o.a) : 0u) | (b_loc ? (1u << o.b) : 0u); break;
+            default: break;
+            }
+        }
+        info[u] = in;
+    }
+    std::vector<DevOp> lops;  // emitted in phase order
+    // Accept ops for layout R from `rem`; returns accepted / deferred.
+    auto run = [&](uint32_t R, const std::vector<int> &rem, std::vector<int> *acc,
+                   std::vector<int> *def) {
+        const uint32_t intra = R | lane_bits_of(m, R);
+        uint32_t blocked = 0;
+        acc->clear();
+        def->clear();
+        for (int i : rem) {
+            const Info &in = info[i];
+            if ((in.bits & blocked) || (in.need >= 0 && !((intra >> in.need) & 1u))) {
+                def->push_back(i);
+                blocked |= in.bits;
+            } else {
+                acc->push_back(i);
+            }
+        }
+    };
+    const uint32_t R_F4 = (1u << 0) | (1u << 7) | (1u << 8) | (1u << 9);
+    const uint32_t R_F2 = (1u << (m - 1)) | (1u << (m - 2)) | (1u << (m - 3)) | (1u << (m - 4));
+    std::vector<int> remaining(unit_len.size());
+    for (size_t i = 0; i < unit_len.size(); ++i) remaining[i] = (int)i;
     std::vector<std::vector<int>> phase_ops;
-    std::vector<std::vector<int>> phase_regs;
+    std::vector<uint32_t> phase_R;
     bool first = true;
     while (!remaining.empty() || first) {
-        std::vector<int> R;
-        if (first) R.push_back(0);
-        uint32_t blocked = 0;
-        std::vector<int> acc, def;
-        for (int i : remaining) {
-            const Info &in = info[i];
-            if (in.bits & blocked) {
-                def.push_back(i);
-                blocked |= in.bits;
-                continue;
+        std::vector<uint32_t> cands;
+        if (first) {
+            cands = {R_F4, R_F2};
+        } else {
+            // register bits = the first needed bits outside the lanes
+            uint32_t want = 0;
+            for (int i : remaining) {
+                const int nb = info[i].need;
+                if (nb >= 6 && !((want >> nb) & 1u) && popc64(want) < kRegBits) want |= 1u << nb;
             }
-            if (in.need < 0 || std::find(R.begin(), R.end(), in.need) != R.end()) {
-                acc.push_back(i);
-                continue;
-            }
-            bool allowed = !first || in.need < kIoLaneLo || in.need > kIoLaneHi;
-            if ((int)R.size() < kRegBits && allowed) {
-                R.push_back(in.need);
-                acc.push_back(i);
-            } else {
-                def.push_back(i);
-                blocked |= in.bits;
+            cands = {pad_high(m, want), R_F2, R_F4};
+        }
+        std::vector<int> best_acc, best_def, acc, def;
+        uint32_t best_R = cands[0];
+        for (uint32_t R : cands) {
+            run(R, remaining, &acc, &def);
+            if (acc.size() > best_acc.size() || best_acc.empty()) {
+                best_acc = acc;
+                best_def = def;
+                best_R = R;
             }
         }
-        phase_ops.push_back(acc);
-        phase_regs.push_back(R);
-        remaining.swap(def);
+        if (!first && best_acc.empty() && !remaining.empty()) {
+            // cannot happen: every target is intra-wave for some layout
+            best_R = pad_high(m, 1u << info[remaining[0]].need);
+            run(best_R, remaining, &best_acc, &best_def);
+        }
+        phase_ops.push_back(best_acc);
+        phase_R.push_back(best_R);
+        remaining.swap(best_def);
         first = false;
     }
-    // The last phase must be I/O capable; otherwise append an empty one.
-    if (!io_ok(phase_regs.back())) {
+    // The last phase must be able to store; otherwise add an empty one.
+    if (io_kind_of(m, phase_R.back()) == IO_NONE) {
         phase_ops.push_back({});
-        phase_regs.push_back({0});
-    } else if (std::find(phase_regs.back().begin(), phase_regs.back().end(), 0) ==
-               phase_regs.back().end()) {
-        phase_regs.back().push_back(0);
+        phase_R.push_back(R_F2);
     }
-    // Pad every phase to 4 register bits. I/O phases (first and last) take
-    // pads from bits >= 7; others from any free bit.
-    const size_t np = phase_regs.size();
-    for (size_t ph = 0; ph < np; ++ph) {
-        std::vector<int> &R = phase_regs[ph];
-        bool io = (ph == 0 || ph + 1 == np);
-        for (int b = 0; b < m && (int)R.size() < kRegBits; ++b) {
-            if (std::find(R.begin(), R.end(), b) != R.end()) continue;
-            if (io && b >= kIoLaneLo && b <= kIoLaneHi) continue;
-            R.push_back(b);
-        }
-        std::sort(R.begin(), R.end());
-    }
-    // Emit ops grouped by phase with register slots resolved.
+    // Emit ops grouped by phase with operand locations resolved.
     std::vector<DevOp> out;
     p.dev_phases.clear();
-    for (size_t ph = 0; ph < np; ++ph) {
-        const std::vector<int> &R = phase_regs[ph];
+    for (size_t ph = 0; ph < phase_R.size(); ++ph) {
+        const uint32_t R = phase_R[ph];
+        int reg[4], k = 0;
+        for (int b = 0; b < m; ++b)
+            if ((R >> b) & 1u) reg[k++] = b;
+        const uint32_t lanes = lane_bits_of(m, R);
+        int lane_idx[32];
+        {
+            int j = 0;
+            for (int b = 0; b < m; ++b)
+                if ((lanes >> b) & 1u) lane_idx[b] = j++;
+        }
         DevPhase dp{};
-        for (int s = 0; s < kRegBits; ++s) dp.reg[s] = (uint8_t)R[s];
+        for (int s2 = 0; s2 < kRegBits; ++s2) dp.reg[s2] = (uint8_t)reg[s2];
+        dp.io = io_kind_of(m, R);
+        for (int kk = 0; kk < 16; ++kk) {
+            uint32_t l = 0;
+            for (int s2 = 0; s2 < 4; ++s2)
+                if ((kk >> s2) & 1) l |= 1u << reg[s2];
+            dp.lds_off[kk] = lds_swizzle(l) << 3;
+        }
         dp.op_begin = (uint16_t)out.size();
-        for (int i : phase_ops[ph]) {
-            DevOp o = lops[i];
+        for (int ui : phase_ops[ph])
+        for (int uj = 0; uj < unit_len[ui]; ++uj) {
+            DevOp o = lops_in[ustart[ui] + uj];
+            if (o.type == OP_DSET) {
+                out.push_back(o);
+                continue;
+            }
             auto slot_of = [&](int b) -> int {
-                for (int s = 0; s < kRegBits; ++s)
-                    if (R[s] == b) return s;
+                for (int s2 = 0; s2 < kRegBits; ++s2)
+                    if (reg[s2] == b) return s2;
                 return -1;
             };
+            const bool target_op =
+                (o.type == OP_U || o.type == OP_PERM || o.type == OP_CX || o.type == OP_UR);
             if (o.la != LOC_GLOBAL) {
-                int s = slot_of(o.a);
-                o.la = s >= 0 ? LOC_REG : LOC_THREAD;
-                o.sa = (uint8_t)(s >= 0 ? s : 0);
+                int sl = slot_of(o.a);
+                if (sl >= 0) {
+                    o.la = LOC_REG;
+                    o.sa = (uint8_t)sl;
+                } else if (target_op) {
+                    o.la = LOC_LANE;  // planner invariant: intra-wave target
+                    o.sa = (uint8_t)lane_idx[o.a];
+                } else {
+                    o.la = LOC_THREAD;
+                    o.sa = 0;
+                }
             }
             if ((o.type == OP_CX || o.type == OP_CZ) && o.lb != LOC_GLOBAL) {
-                int s = slot_of(o.b);
-                o.lb = s >= 0 ? LOC_REG : LOC_THREAD;
-                o.sb = (uint8_t)(s >= 0 ? s : 0);
+                int sl = slot_of(o.b);
+                o.lb = sl >= 0 ? LOC_REG : LOC_THREAD;
+                o.sb = (uint8_t)(sl >= 0 ? sl : 0);
             }
             out.push_back(o);
         }
         dp.op_end = (uint16_t)out.size();
         p.dev_phases.push_back(dp);
     }
-    lops.swap(out);
+    lops_in.swap(out);
+    (void)lops;
 }
 
-// Convert a pass's ops to local bit numbers and device form.
+// Host form of the uniform address arithmetic of an I/O phase.
+IoRec make_iorec(int m, uint64_t lmask, const DevPhase &ph) {
+    IoRec r{};
+    r.kind = ph.io;
+    std::vector<int> gpos;
+    for (int q = 0; q < 64; ++q)
+        if ((lmask >> q) & 1ull) gpos.push_back(q);
+    r.g4 = (uint8_t)gpos[4];
+    r.g5 = (uint8_t)gpos[5];
+    r.g6 = (uint8_t)gpos[6];
+    uint32_t R = 0;
+    for (int s = 0; s < 4; ++s) R |= 1u << ph.reg[s];
+    for (int k = 0; k < 16; ++k) {
+        uint32_t off = 0;
+        for (int s = 0; s < 4; ++s)
+            if ((k >> s) & 1) off |= 1u << gpos[ph.reg[s]];
+        r.reg_off[k] = off;
+    }
+    // wave bits: non-register local bits above the 6 lanes, ascending
+    std::vector<int> wbits;
+    int lanes = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((R >> b) & 1u) continue;
+        if (lanes < 6) {
+            ++lanes;
+            continue;
+        }
+        wbits.push_back(b);
+    }
+    for (int w = 0; w < 16; ++w) {
+        uint32_t off = 0;
+        for (size_t j = 0; j < wbits.size(); ++j)
+            if ((w >> j) & 1) off |= 1u << gpos[wbits[j]];
+        r.wave_off[w] = off;
+    }
+    return r;
+}
+
+// Convert a pass's ops to local bit numbers and device form. An OP_DSET
+// becomes a header (b = member count) followed by its OP_DIAG members.
 void lower_pass(int n, int m, HostPass &p) {
+    (void)n;
     std::vector<DevOp> lops;
-    for (const HostOp &h : p.ops) {
+    std::vector<int> unit_len;
+    auto lower_one = [&](const HostOp &h) {
         DevOp o{};
         o.type = h.type;
         for (int k = 0; k < 8; ++k) o.m[k] = (float)h.m[k];
@@ -358,10 +560,27 @@ void lower_pass(int n, int m, HostPass &p) {
         put(h.a, &o.a, &o.la);
         if (h.type == OP_CX || h.type == OP_CZ) put(h.b, &o.b, &o.lb);
         else o.lb = LOC_GLOBAL;
-        lops.push_back(o);
+        return o;
+    };
+    for (const HostOp &h : p.ops) {
+        if (h.type == OP_DSET) {
+            DevOp hd{};
+            hd.type = OP_DSET;
+            hd.la = LOC_GLOBAL;
+            hd.lb = LOC_GLOBAL;
+            hd.b = (uint8_t)h.members.size();
+            lops.push_back(hd);
+            for (const HostOp &mm : h.members) lops.push_back(lower_one(mm));
+            unit_len.push_back(1 + (int)h.members.size());
+        } else {
+            lops.push_back(lower_one(h));
+            unit_len.push_back(1);
+        }
     }
     if (m >= kMinTileBits) {
-        plan_phases(m, p, lops);
+        plan_phases(m, p, lops, unit_len);
+        p.io_in = make_iorec(m, p.local_mask, p.dev_phases.front());
+        p.io_out = make_iorec(m, p.local_mask, p.dev_phases.back());
     } else {
         // small-state kernel: whole state is one tile, no phases needed
         p.dev_phases.clear();
@@ -490,7 +709,7 @@ std::string plan_json(const Plan &p) {
             if (k) o << ",";
             o << "{\"reg\":[" << (int)d.reg[0] << "," << (int)d.reg[1] << "," << (int)d.reg[2]
               << "," << (int)d.reg[3] << "],\"op_begin\":" << d.op_begin
-              << ",\"op_end\":" << d.op_end << "}";
+              << ",\"op_end\":" << d.op_end << ",\"io\":" << (int)d.io << "}";
         }
         o << "]}";
     }
@@ -502,9 +721,12 @@ std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_ter
     std::vector<TermGroup> groups;
     const uint64_t all = (1ull << n) - 1;
     if (n <= m) {
-        TermGroup g{all, {}};
-        for (size_t i = 0; i < n_terms; ++i) g.terms.push_back((uint32_t)i);
-        if (n_terms) groups.push_back(g);
+        for (size_t i = 0; i < n_terms; i += kMaxGroupTerms) {
+            TermGroup g{all, {}};
+            for (size_t k = i; k < std::min(n_terms, i + (size_t)kMaxGroupTerms); ++k)
+                g.terms.push_back((uint32_t)k);
+            groups.push_back(g);
+        }
         return groups;
     }
     const uint64_t low = (1ull << std::min(n, 4)) - 1;
@@ -518,7 +740,7 @@ std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_ter
         uint64_t L = low;
         std::vector<uint32_t> take, left;
         for (uint32_t t : rem) {
-            if (popc64(L | x[t]) <= m) {
+            if (take.size() < (size_t)kMaxGroupTerms && popc64(L | x[t]) <= m) {
                 L |= x[t];
                 take.push_back(t);
             } else {
@@ -531,6 +753,87 @@ std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_ter
         rem.swap(left);
     }
     return groups;
+}
+
+RedPlan plan_reduce_group(int n, int m, const TermGroup &g, const uint64_t *x,
+                          const uint64_t *z) {
+    (void)n;
+    RedPlan rp;
+    const uint64_t L = g.local_mask;
+    const size_t nt = g.terms.size();
+    std::vector<uint32_t> xl(nt), zl(nt);
+    for (size_t i = 0; i < nt; ++i) {
+        xl[i] = (uint32_t)pext64(x[g.terms[i]], L);
+        zl[i] = (uint32_t)pext64(z[g.terms[i]], L);
+    }
+    // first-fit decreasing packing of X/Y supports into 4-bit register sets
+    std::vector<size_t> order(nt);
+    for (size_t i = 0; i < nt; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return popc64(xl[a]) > popc64(xl[b]); });
+    std::vector<uint32_t> R;
+    std::vector<std::vector<size_t>> mem;
+    std::vector<size_t> diag;
+    for (size_t i : order) {
+        if (xl[i] == 0) {
+            diag.push_back(i);
+            continue;
+        }
+        int best = -1, best_sz = 99;
+        for (size_t p = 0; p < R.size(); ++p) {
+            int sz = popc64(R[p] | xl[i]);
+            if (sz <= kRegBits && sz < best_sz) {
+                best = (int)p;
+                best_sz = sz;
+            }
+        }
+        if (best < 0) {
+            R.push_back(xl[i]);
+            mem.push_back({i});
+        } else {
+            R[best] |= xl[i];
+            mem[best].push_back(i);
+        }
+    }
+    // diagonal terms: one phase in the I/O layout (register bits 0, 7, 8, 9)
+    std::vector<char> is_diag(R.size(), 0);
+    if (!diag.empty()) {
+        R.insert(R.begin(), (1u << 0) | (1u << 7) | (1u << 8) | (1u << 9));
+        mem.insert(mem.begin(), diag);
+        is_diag.insert(is_diag.begin(), 1);
+    }
+    for (size_t p = 0; p < R.size(); ++p) {
+        for (int b = 0; b < m && popc64(R[p]) < kRegBits; ++b) R[p] |= 1u << b;
+        int reg[4], k = 0;
+        for (int b = 0; b < m; ++b)
+            if ((R[p] >> b) & 1u) reg[k++] = b;
+        RedPhase ph{};
+        for (int s = 0; s < 4; ++s) ph.reg[s] = (uint8_t)reg[s];
+        ph.t_begin = (uint16_t)rp.terms.size();
+        for (size_t i : mem[p]) {
+            TermDev t{};
+            for (int s = 0; s < 4; ++s)
+                if ((xl[i] >> reg[s]) & 1u) t.xr |= (uint8_t)(1u << s);
+            for (int kk = 0; kk < 16; ++kk) {
+                uint32_t l = 0;
+                for (int s = 0; s < 4; ++s)
+                    if ((kk >> s) & 1) l |= 1u << reg[s];
+                if (popc64(l & zl[i]) & 1) t.smask |= (uint16_t)(1u << kk);
+            }
+            const int ny = popc64(x[g.terms[i]] & z[g.terms[i]]) & 3;
+            t.odd = (uint8_t)(ny & 1);
+            t.neg = (uint8_t)((ny == 1 || ny == 2) ? 1 : 0);
+            t.zt = zl[i] & ~R[p];
+            t.zg = z[g.terms[i]] & ~L;
+            t.col = (uint16_t)i;
+            rp.terms.push_back(t);
+        }
+        ph.t_end = (uint16_t)rp.terms.size();
+        ph.diag = is_diag[p] ? 1u : 0u;
+        rp.phases.push_back(ph);
+    }
+    rp.cols.assign(g.terms.begin(), g.terms.end());
+    return rp;
 }
 
 }  // namespace qw

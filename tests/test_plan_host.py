@@ -13,8 +13,8 @@ import oracle
 from paper_2609_23664_amd import binding as B
 from workloads import gen
 
-LOC_REG, LOC_THREAD, LOC_GLOBAL = 0, 1, 2
-OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ = 1, 2, 3, 4, 5
+LOC_REG, LOC_THREAD, LOC_GLOBAL, LOC_LANE = 0, 1, 2, 3
+OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ, OP_UR, OP_DSET = 1, 2, 3, 4, 5, 6, 7
 
 
 def _local_bits(mask):
@@ -34,13 +34,17 @@ def interpret(n, plan, psi):
                 return b if loc == LOC_GLOBAL else lb[b]
             m = op["m"]
             t = op["type"]
-            if t in (OP_U, OP_PERM):
+            if t == OP_DSET:
+                continue          # its diagonal members follow
+            if t in (OP_U, OP_PERM, OP_UR):
                 assert op["la"] != LOC_GLOBAL
                 g = gbit(op["la"], op["a"])
                 i0 = idx[((idx >> g) & 1) == 0]
                 i1 = i0 | (1 << g)
                 x, y = psi[i0].copy(), psi[i1].copy()
-                if t == OP_U:
+                if t == OP_UR:
+                    psi[i0], psi[i1] = m[0] * x + m[1] * y, m[2] * x + m[3] * y
+                elif t == OP_U:
                     a, b, c, d = (m[0] + 1j * m[1], m[2] + 1j * m[3], m[4] + 1j * m[5], m[6] + 1j * m[7])
                     psi[i0], psi[i1] = a * x + b * y, c * x + d * y
                 else:
@@ -66,7 +70,13 @@ def interpret(n, plan, psi):
     return psi
 
 
+def _lanes(m, reg):
+    return [b for b in range(m) if b not in reg][:6]
+
+
 def _check_phases(plan):
+    """Layout invariants of the register kernel: 4 register bits per phase,
+    first/last phases I/O capable, gate targets in a register or lane bit."""
     m = plan["tile_bits"]
     if m < 10:
         return
@@ -78,14 +88,21 @@ def _check_phases(plan):
         for k, f in enumerate(ph):
             reg = f["reg"]
             assert len(set(reg)) == 4 and reg == sorted(reg) and max(reg) < m
+            lanes = _lanes(m, reg)
+            kind = 1 if (0 in reg and lanes == [1, 2, 3, 4, 5, 6]) else (2 if lanes == list(range(6)) else 0)
+            assert f["io"] == kind
             if k == 0 or k == len(ph) - 1:
-                assert reg[0] == 0 and not any(1 <= r <= 6 for r in reg)
+                assert kind != 0
             for op in p["ops"][f["op_begin"]:f["op_end"]]:
-                if op["type"] in (OP_U, OP_PERM, OP_CX):
-                    assert op["la"] == LOC_REG and reg[op["sa"]] == op["a"]
-                for loc, b, s in ((op["la"], op["a"], op["sa"]), (op["lb"], op["b"], op["sb"])):
+                if op["type"] in (OP_U, OP_PERM, OP_CX, OP_UR):
+                    assert op["la"] in (LOC_REG, LOC_LANE)
+                    if op["la"] == LOC_REG:
+                        assert reg[op["sa"]] == op["a"]
+                    else:
+                        assert lanes[op["sa"]] == op["a"]
+                for loc, b, s_ in ((op["la"], op["a"], op["sa"]), (op["lb"], op["b"], op["sb"])):
                     if loc == LOC_REG:
-                        assert reg[s] == b
+                        assert reg[s_] == b
 
 
 @pytest.mark.parametrize("n,tile", [(6, 14), (10, 14), (12, 10), (13, 11), (16, 12), (16, 14), (18, 10)])
