@@ -149,11 +149,19 @@ int qw_ctx_sync(qw_ctx *ctx);
  *   QW_OPT_FUSED_EPILOGUE 1: evaluate expectation terms whose X/Y support is
  *                         local to the last suffix pass inside that pass [1]
  *   QW_OPT_XCD_REMAP      1: map workgroups so that the tiles of one source
- *                         state run on one XCD [1] */
+ *                         state run on one XCD [1]
+ *   QW_OPT_JIT            1: run gate passes of states with >= 10 qubits with
+ *                         kernels generated for each pass structure and
+ *                         compiled at run time with hipRTC (cached in memory,
+ *                         and on disk under $QW_JIT_CACHE, default
+ *                         ~/.cache/qw_jit; QW_JIT_CACHE=off disables the disk
+ *                         cache); 0: interpreted pass kernels. Both forms
+ *                         give bit-identical states. [1] */
 #define QW_OPT_TILE_BITS 1
 #define QW_OPT_PROFILE 2
 #define QW_OPT_FUSED_EPILOGUE 3
 #define QW_OPT_XCD_REMAP 4
+#define QW_OPT_JIT 5
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.
@@ -256,6 +264,20 @@ int qw_legality_check(const qw_artifact *src, uint32_t target_kind,
  * is needed. Returns QW_E_INVALID_ARG (message in json_out) for bad gates. */
 int qw_plan_describe(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
                      uint32_t tile_bits, char *json_out, uint64_t cap);
+
+/* Generate and compile (hipRTC) the pass kernels that QW_OPT_JIT would use
+ * for `gates` on n qubits with at most tile_bits local bits per pass, and
+ * keep the code objects in the process cache and the disk cache, without
+ * loading them on a device: a warm-up for later runs, usable where there is
+ * no GPU. States below 10 qubits need no generated kernels (QW_OK). On a
+ * compile failure returns QW_E_HIP with the compiler log in log (truncated
+ * to cap, NUL-terminated); QW_E_INVALID_ARG for bad gates. */
+int qw_jit_precompile(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
+                      uint32_t tile_bits, char *log, uint64_t cap);
+
+/* Generated-kernel counters of this process: kernels compiled, kernels taken
+ * from the disk cache, and seconds spent compiling. Any pointer may be NULL. */
+int qw_jit_stats(uint64_t *compiled, uint64_t *disk_hits, double *compile_seconds);
 
 /* Library version string. */
 const char *qw_version(void);

@@ -42,6 +42,7 @@ QW_OPT_TILE_BITS = 1
 QW_OPT_PROFILE = 2
 QW_OPT_FUSED_EPILOGUE = 3
 QW_OPT_XCD_REMAP = 4
+QW_OPT_JIT = 5
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",
@@ -49,7 +50,7 @@ EXPORTED = (
     "qw_state_reset", "qw_state_slot_ptr", "qw_apply_prefix", "qw_snapshot",
     "qw_snapshot_free", "qw_snapshot_info", "qw_run_suffix_batch",
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
-    "qw_version",
+    "qw_jit_precompile", "qw_jit_stats", "qw_version",
 )
 
 
@@ -134,6 +135,9 @@ def lib() -> ctypes.CDLL:
         "qw_sample": ([vp, u32, u32, u64, u64, u32, vp, i32], i32),
         "qw_legality_check": ([ctypes.POINTER(QwArtifact), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_plan_describe": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
+        "qw_jit_precompile": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
+        "qw_jit_stats": ([ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)],
+                         i32),
         "qw_version": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -200,6 +204,24 @@ def plan_describe(n: int, gates, tile_bits: int = 14) -> dict:
         cap *= 4
         if cap > (1 << 30):
             raise QwError(rc, "plan too large")
+
+
+def jit_precompile(n: int, gates, tile_bits: int = 14) -> None:
+    """Host-only: compile the generated pass kernels of `gates` into the
+    process and disk caches (no GPU needed)."""
+    arr = gate_array(gates)
+    cap = 1 << 20
+    buf = ctypes.create_string_buffer(cap)
+    rc = lib().qw_jit_precompile(n, arr, len(gates), tile_bits, buf, cap)
+    if rc != QW_OK:
+        raise QwError(rc, buf.value.decode(errors="replace"))
+
+
+def jit_stats() -> dict:
+    """Generated-kernel counters of this process."""
+    c, h, s = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+    lib().qw_jit_stats(ctypes.byref(c), ctypes.byref(h), ctypes.byref(s))
+    return {"compiled": c.value, "disk_hits": h.value, "compile_s": s.value}
 
 
 class Ctx:

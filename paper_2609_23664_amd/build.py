@@ -20,12 +20,36 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [
-    "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
     "-I", INCLUDE, "-I", CSRC,
 ]
 # device code: gfx950 only; packed FP32 ops disabled
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["qw_kernels.hip", "qw_api.cpp", "qw_plan.cpp"]
+SOURCES = ["qw_kernels.hip", "qw_api.cpp", "qw_plan.cpp", "qw_jit.cpp"]
+# headers compiled again at run time by hipRTC (embedded as text)
+EMBED = [("kEmbedDescH", "qw_desc.h"), ("kEmbedDevH", "qw_dev.h")]
+
+
+def _embed() -> None:
+    """Write the device headers as C++ string literals for the run-time
+    compiler (qw_jit.cpp includes the result)."""
+    os.makedirs(BUILD, exist_ok=True)
+    out = ["// written by build.py: device headers for hipRTC"]
+    for name, fn in EMBED:
+        with open(os.path.join(CSRC, fn)) as f:
+            text = f.read()
+        if ")QWEMBED\"" in text:
+            raise RuntimeError("embed delimiter inside " + fn)
+        out.append(f'static const char {name}[] = R"QWEMBED({text})QWEMBED";')
+    path = os.path.join(BUILD, "qw_embed.inc")
+    data = "\n".join(out) + "\n"
+    old = None
+    if os.path.exists(path):
+        with open(path) as f:
+            old = f.read()
+    if old != data:
+        with open(path, "w") as f:
+            f.write(data)
 
 
 def _compile(src: str) -> str:
@@ -35,7 +59,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *DEVICE, *COMMON, "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-x", "c++",
+        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-I", BUILD, "-x", "c++",
                "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -44,10 +68,12 @@ def _compile(src: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
+    _embed()
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
         objs = list(pool.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, *DEVICE, "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, *DEVICE, "-shared", "-fPIC", *objs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

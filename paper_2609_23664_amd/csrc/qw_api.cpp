@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,7 @@
 #include "../../include/qw.h"
 #include "qw_internal.h"
 #include "qw_kernels.h"
+#include "qw_jit.h"
 
 using namespace qw;
 
@@ -49,6 +51,8 @@ struct qw_ctx {
     bool profile = false;
     bool fused_epilogue = true;
     bool xcd_remap = true;
+    bool jit = true;
+    uint32_t n_cu = 256;
     DevBuf plan;     // uploaded descriptors/ops
     DevBuf scratch;  // partial sums, sampler buffers
     void *staging = nullptr;
@@ -353,12 +357,60 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             for (uint32_t ti = 0; ti < tiles; ++ti) tb[ti] = (uint32_t)pdep64(ti, nl);
         }
     }
+    // Order of the tasks in each step's descriptor array. With generated
+    // kernels, the tasks of one pass structure are consecutive and form one
+    // launch (groups[k]: kernel, first descriptor, count).
+    struct Group {
+        const JitKernel *k;
+        uint32_t first, count;
+    };
+    std::vector<std::vector<size_t>> order(steps);
+    std::vector<std::vector<Group>> groups(steps);
+    const bool use_jit = ctx->jit && m >= kMinTileBits;
+    if (use_jit) {
+        std::vector<JitReq> reqs;
+        std::vector<std::vector<std::pair<size_t, std::vector<size_t>>>> members(steps);
+        for (size_t k = 0; k < steps; ++k) {
+            std::map<std::string, size_t> gi;
+            for (size_t t = 0; t < ex.size(); ++t) {
+                if (k >= ex[t].plan.passes.size()) continue;
+                const HostPass &p = ex[t].plan.passes[k];
+                const bool lds = p.norm_out || p.dev_phases.size() > 1;
+                std::string key = jit_pass_key((int)n, m, p, lds);
+                auto it = gi.find(key);
+                if (it == gi.end()) {
+                    it = gi.emplace(key, members[k].size()).first;
+                    members[k].push_back({reqs.size(), {}});
+                    JitReq r;
+                    r.key = std::move(key);
+                    r.pass = &p;
+                    r.n = (int)n;
+                    r.m = m;
+                    r.use_lds = lds;
+                    reqs.push_back(std::move(r));
+                }
+                members[k][it->second].second.push_back(t);
+            }
+        }
+        std::vector<const JitKernel *> kern;
+        const std::string err = jit_get(ctx->device, reqs, &kern);
+        if (!err.empty()) return fail(ctx, QW_E_HIP, err);
+        for (size_t k = 0; k < steps; ++k) {
+            for (auto &gm : members[k]) {
+                groups[k].push_back({kern[gm.first], (uint32_t)order[k].size(), (uint32_t)gm.second.size()});
+                for (size_t t : gm.second) order[k].push_back(t);
+            }
+        }
+    } else {
+        for (size_t k = 0; k < steps; ++k)
+            for (size_t t = 0; t < ex.size(); ++t)
+                if (k < ex[t].plan.passes.size()) order[k].push_back(t);
+    }
     std::vector<char> step_norm(steps, 0), step_lds(steps, 0);
     for (size_t k = 0; k < steps; ++k) {
         size_t c = 0;
-        for (size_t t = 0; t < ex.size(); ++t) {
+        for (size_t t : order[k]) {
             Exec &e = ex[t];
-            if (k >= e.plan.passes.size()) continue;
             HostPass &p = e.plan.passes[k];
             PassDesc d{};
             d.src = (k == 0 && e.src) ? e.src : e.dst;
@@ -386,7 +438,14 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     if (rc) return rc;
     for (size_t k = 0; k < steps; ++k) {
         const PassDesc *dd = reinterpret_cast<const PassDesc *>(dbase + step_off[k]);
-        {
+        if (use_jit) {
+            for (const Group &g : groups[k]) {
+                ProfScope ps(ctx, 0, (double)g.count * 2.0 * (double)state_bytes);
+                hipError_t er = jit_launch(ctx->stream, *g.k, dd + g.first, g.count, tiles,
+                                           ctx->xcd_remap ? 1 : 0, ctx->n_cu);
+                if (er != hipSuccess) return hip_fail(ctx, er, "generated pass launch");
+            }
+        } else {
             ProfScope ps(ctx, 0, (double)step_cnt[k] * 2.0 * (double)state_bytes);
             hipError_t er = launch_pass(ctx->stream, dd, (uint32_t)step_cnt[k], n, (uint32_t)m,
                                         ctx->xcd_remap ? 1 : 0, step_lds[k] != 0);
@@ -540,6 +599,12 @@ int qw_ctx_create(int device, void *hip_stream, qw_ctx **out) {
     if (!c) return QW_E_OOM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            ncu > 0)
+            c->n_cu = (uint32_t)ncu;
+    }
     if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(c->staging_ev, c->stream) != hipSuccess || kernels_init() != hipSuccess) {
         delete c;
@@ -584,6 +649,7 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
     case QW_OPT_PROFILE: ctx->profile = value != 0; return QW_OK;
     case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
     case QW_OPT_XCD_REMAP: ctx->xcd_remap = value != 0; return QW_OK;
+    case QW_OPT_JIT: ctx->jit = value != 0; return QW_OK;
     default: return fail(ctx, QW_E_INVALID_ARG, "unknown option");
     }
 }
@@ -887,6 +953,46 @@ int qw_legality_check(const qw_artifact *src, uint32_t target_kind, uint32_t tar
         json_out[k] = 0;
     }
     return QW_E_REFUSED;
+}
+
+int qw_jit_precompile(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
+                      char *log, uint64_t cap) {
+    auto put = [&](const std::string &msg) {
+        if (log && cap) {
+            size_t k = std::min<size_t>(msg.size(), cap - 1);
+            std::memcpy(log, msg.data(), k);
+            log[k] = 0;
+        }
+    };
+    Plan p;
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    if (!e.empty()) {
+        put(e);
+        return QW_E_INVALID_ARG;
+    }
+    put("");
+    if (p.m < kMinTileBits) return QW_OK;
+    std::vector<JitReq> reqs;
+    for (const HostPass &h : p.passes) {
+        JitReq r;
+        r.use_lds = h.norm_out || h.dev_phases.size() > 1;
+        r.key = jit_pass_key((int)n, p.m, h, r.use_lds);
+        r.pass = &h;
+        r.n = (int)n;
+        r.m = p.m;
+        reqs.push_back(std::move(r));
+    }
+    e = jit_precompile(reqs);
+    if (!e.empty()) {
+        put(e);
+        return QW_E_HIP;
+    }
+    return QW_OK;
+}
+
+int qw_jit_stats(uint64_t *compiled, uint64_t *disk_hits, double *compile_seconds) {
+    jit_stats(compiled, disk_hits, compile_seconds);
+    return QW_OK;
 }
 
 int qw_plan_describe(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,

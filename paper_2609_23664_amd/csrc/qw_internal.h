@@ -7,171 +7,9 @@
 #include <string>
 #include <vector>
 
+#include "qw_desc.h"
+
 namespace qw {
-
-// ---------------------------------------------------------------- limits
-constexpr int kMaxQubits = 30;      // 8 GiB per complex64 state
-constexpr int kRegBits = 4;         // amplitudes per thread = 2^kRegBits
-constexpr int kMinTileBits = 10;    // register/lane/wave layout needs >= 10
-constexpr int kMaxTileBits = 14;    // 2^14 complex64 = 128 KiB of LDS
-constexpr int kIoLaneLo = 1;        // lanes cover local bits 1..6 at I/O
-constexpr int kIoLaneHi = 6;
-
-// ---------------------------------------------------------------- ops
-// Operations executed on a tile. Bit operands are *local* bit positions
-// (0..m-1) unless the matching GLOBAL flag is set, in which case they are
-// global qubit indices (bits that are constant over the tile).
-enum OpType : uint8_t {
-    OP_U = 1,     // 2x2 complex matrix on local bit a (register slot s)
-    OP_DIAG = 2,  // diag(d0, d1) on bit a
-    OP_PERM = 3,  // [[0, p01], [p10, 0]] on local bit a (register slot s)
-    OP_CX = 4,    // swap the pair on local target a (slot s) where control b is 1
-    OP_CZ = 5,    // negate where bits a and b are both 1
-    OP_UR = 6,    // real 2x2 matrix [[m0, m1], [m2, m3]] on local bit a
-    OP_DSET = 7,  // header of a set of b OP_DIAG ops that follow; the set is
-                  // applied at once (the factors of thread and global bits are
-                  // combined into one per-thread factor)
-};
-
-// Where an operand bit lives inside a phase of the register kernel.
-enum BitLoc : uint8_t {
-    LOC_REG = 0,     // register slot (index in `slot` fields)
-    LOC_THREAD = 1,  // a thread-index bit (local bit number in a/b)
-    LOC_GLOBAL = 2,  // non-local: global qubit index in a/b
-    LOC_LANE = 3,    // target on a lane bit: lane index bit in `sa` (0..5)
-};
-
-// Layout of a phase: 4 register bits R; the 6 lowest local bits not in R
-// are the lane bits of the 64-wide wavefront; the rest are wave bits.
-// I/O kinds: IO_F4 = R holds local bit 0 and the lanes are local bits
-// 1..6 (16-byte accesses); IO_F2 = the lanes are local bits 0..5 (8-byte
-// accesses). Loads happen in phase 0 and stores in the last phase, both of
-// which must have an I/O kind.
-enum IoKind : uint8_t { IO_NONE = 0, IO_F4 = 1, IO_F2 = 2 };
-
-struct alignas(16) DevOp {
-    uint8_t type;
-    uint8_t a, b;          // local or global bit numbers (see loc)
-    uint8_t sa, sb;        // register slots of a and b when LOC_REG
-    uint8_t la, lb;        // BitLoc of a and b
-    uint8_t pad0;
-    uint32_t pad1[2];
-    float m[8];            // U: m00 m01 m10 m11 (re, im); DIAG: d0 d1;
-                           // PERM: p01 p10
-};
-static_assert(sizeof(DevOp) == 48, "DevOp layout");
-
-// One phase of a pass: the 4 local bits held in registers and the ops run
-// while that mapping is live. Phase 0 and the last phase are I/O capable:
-// register slot 0 is local bit 0 and no register bit lies in the lane bits.
-struct alignas(16) DevPhase {
-    uint8_t reg[4];        // local bit of register slot 0..3 (ascending)
-    uint16_t op_begin;
-    uint16_t op_end;
-    uint8_t io;            // IoKind
-    uint8_t pad[7];
-    uint32_t lds_off[16];  // byte offset in LDS of register k (swizzled)
-};
-static_assert(sizeof(DevPhase) == 80, "DevPhase layout");
-
-// LDS element swizzle (see the kernels): the low 5 bits of the element index
-// are XORed with bits 5..9 and 10..13. It is linear over GF(2).
-inline uint32_t lds_swizzle(uint32_t l) { return l ^ (((l >> 5) ^ (l >> 10)) & 31u); }
-
-// Pass descriptor flags
-enum : uint32_t {
-    PD_SCALE_IN = 1u,    // multiply loaded amplitudes by *scale (FP64)
-    PD_NORM_OUT = 2u,    // write per-tile FP64 sums of |psi|^2
-};
-
-// Uniform address record of an I/O phase, computed on the host: global
-// index bits of the lane part (shifts), of each register and of each wave.
-struct alignas(16) IoRec {
-    uint8_t kind;          // IoKind
-    uint8_t g4, g5, g6;    // global positions of local bits 4, 5, 6
-    uint32_t pad[3];
-    uint32_t reg_off[16];  // global index bits of register k
-    uint32_t wave_off[16]; // global index bits of wave w (tile bits >= 10)
-};
-static_assert(sizeof(IoRec) == 144, "IoRec layout");
-
-// One (task, pass): a tile sweep over a state slot.
-struct alignas(16) PassDesc {
-    const void *src;       // float2 amplitudes read (may equal dst)
-    void *dst;             // float2 amplitudes written
-    const DevOp *ops;
-    const DevPhase *phases;
-    uint64_t local_mask;   // global bits that are local to a tile
-    const double *scale_in;  // PD_SCALE_IN: factor applied on load
-    double *norm_part;     // PD_NORM_OUT: [tiles] FP64 sums of |psi|^2
-    double *scale_out;     // PD_NORM_OUT: 1/sqrt(sum) written by finalize
-    const uint32_t *tile_base;  // global index of local index 0, per tile
-    const IoRec *io_in;    // address record of phase 0
-    const IoRec *io_out;   // address record of the last phase
-    uint32_t n_ops;
-    uint32_t n_phases;
-    uint32_t flags;
-    uint32_t pad;
-};
-static_assert(sizeof(PassDesc) % 16 == 0, "PassDesc layout");
-
-// Expectation reducer, small states (n < 10): the whole state is one tile
-// staged in LDS; one descriptor per slot.
-struct alignas(16) TermSmall {
-    uint32_t x;            // X/Y support
-    uint32_t z;            // Z/Y support
-    uint32_t ny_mod4;      // number of Y factors mod 4
-    uint32_t out_index;    // column of the term in the partial array
-};
-
-struct alignas(16) ReduceDescSmall {
-    const void *psi;
-    const TermSmall *terms;
-    double *part;          // [n_terms] of this slot
-    uint32_t n_terms;
-    uint32_t pad;
-};
-
-// Expectation reducer, register kernel (tile bits >= 10). A term group is a
-// set of terms whose X/Y support lies in the group's local bits; its terms
-// are split into phases whose 4 register bits contain each term's X/Y
-// support, so every pair (l, l ^ x) of a term is inside one thread.
-constexpr int kMaxGroupTerms = 64;
-
-struct alignas(16) TermDev {
-    uint8_t xr;            // X/Y support as register-slot mask
-    uint8_t neg;           // 1: negate the pair sum (phase i^ny)
-    uint8_t odd;           // 1: ny odd, use Im(conj(b) a)
-    uint8_t pad0;
-    uint16_t smask;        // bit k: parity of the Z/Y bits at register index k
-    uint16_t col;          // group-local column (0..n_terms-1)
-    uint32_t zt;           // Z/Y support on the phase's thread bits (local numbering)
-    uint32_t pad1;
-    uint64_t zg;           // Z/Y support on global (non-local) bits
-};
-static_assert(sizeof(TermDev) == 32, "TermDev layout");
-
-struct alignas(16) RedPhase {
-    uint8_t reg[4];        // local bits of register slots 0..3 (ascending)
-    uint16_t t_begin;
-    uint16_t t_end;
-    uint32_t diag;         // 1: diagonal terms only, evaluated in the I/O layout
-    uint32_t pad;
-};
-static_assert(sizeof(RedPhase) == 16, "RedPhase layout");
-
-struct alignas(16) ReduceDesc {
-    const void *psi;       // float2 state slot
-    const TermDev *terms;
-    const RedPhase *phases;
-    const uint32_t *cols;  // group-local column -> column of the partial array
-    double *part;          // [tiles][n_terms_total] of this slot
-    uint64_t local_mask;
-    uint32_t n_phases;
-    uint32_t n_terms;      // terms of this group
-    uint32_t n_terms_total;
-    uint32_t pad;
-};
 
 // ---------------------------------------------------------------- host plan
 struct HostOp {

@@ -1,0 +1,635 @@
+// Generated pass kernels: source generation, hipRTC compilation, caching
+// and launch. See qw_jit.h.
+#include "qw_jit.h"
+
+#include <hip/hiprtc.h>
+
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <thread>
+#include <unordered_map>
+
+#include <sys/stat.h>
+
+namespace qw {
+namespace {
+
+// Text of qw_desc.h and qw_dev.h (written into the build folder by the
+// package build step), handed to hipRTC as named headers.
+#include "qw_embed.inc"
+
+// Options of every generated kernel: the flags of the ahead-of-time build.
+const char *const kOpts[] = {
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+};
+constexpr int kNumOpts = sizeof(kOpts) / sizeof(kOpts[0]);
+
+// ---------------------------------------------------------------- source
+struct Gen {
+    std::ostringstream o;
+    template <typename T>
+    Gen &operator<<(const T &v) {
+        o << v;
+        return *this;
+    }
+};
+
+std::string hex(uint64_t v) {
+    char b[32];
+    std::snprintf(b, sizeof b, "0x%llxull", (unsigned long long)v);
+    return b;
+}
+
+// Lane part (amplitude units) and wave bit positions of an I/O layout.
+void emit_io_helpers(Gen &g, const char *name, const IoRec &r, int m) {
+    g << "__device__ __forceinline__ uint32_t " << name << "_lane(uint32_t lane) {\n";
+    if (r.kind == IO_F4)
+        g << "    return (((lane & 7u) << 1) | (((lane >> 3) & 1u) << " << (int)r.g4
+          << ") | (((lane >> 4) & 1u) << " << (int)r.g5 << ") | (((lane >> 5) & 1u) << "
+          << (int)r.g6 << ")) * 8u;\n";
+    else
+        g << "    return ((lane & 15u) | (((lane >> 4) & 1u) << " << (int)r.g4
+          << ") | (((lane >> 5) & 1u) << " << (int)r.g5 << ")) * 8u;\n";
+    g << "}\n";
+    g << "__device__ __forceinline__ uint64_t " << name << "_wave(uint32_t w) {\n    return 0ull";
+    const int nw = m - 10;
+    for (int j = 0; j < nw; ++j) g << " | ((uint64_t)((w >> " << j << ") & 1u) * " << hex(r.wave_off[1u << j]) << ")";
+    g << ";\n}\n";
+}
+
+void emit_load(Gen &g, const IoRec &r) {
+    g << "__device__ __forceinline__ void load_in(float2 (&v)[16], const void *src, uint64_t ub, "
+         "uint32_t lb) {\n";
+    if (r.kind == IO_F4) {
+        for (int k2 = 0; k2 < 8; ++k2)
+            g << "    { const float4 q = buf_ld4(src, ub + " << hex(r.reg_off[2 * k2]) << ", lb); v["
+              << 2 * k2 << "] = make_float2(q.x, q.y); v[" << 2 * k2 + 1
+              << "] = make_float2(q.z, q.w); }\n";
+    } else {
+        for (int k = 0; k < 16; ++k)
+            g << "    v[" << k << "] = buf_ld2(src, ub + " << hex(r.reg_off[k]) << ", lb);\n";
+    }
+    g << "}\n";
+}
+
+void emit_store(Gen &g, const IoRec &r) {
+    g << "__device__ __forceinline__ void store_out(const float2 (&v)[16], void *dst, uint64_t ub, "
+         "uint32_t lb) {\n";
+    if (r.kind == IO_F4) {
+        for (int k2 = 0; k2 < 8; ++k2)
+            g << "    buf_st4(dst, ub + " << hex(r.reg_off[2 * k2]) << ", lb, v[" << 2 * k2 << "], v["
+              << 2 * k2 + 1 << "]);\n";
+    } else {
+        for (int k = 0; k < 16; ++k)
+            g << "    buf_st2(dst, ub + " << hex(r.reg_off[k]) << ", lb, v[" << k << "]);\n";
+    }
+    g << "}\n";
+}
+
+// Value of a thread or global operand bit in phase ph.
+std::string bitval(uint8_t loc, uint8_t bit, size_t ph) {
+    std::ostringstream s;
+    if (loc == LOC_THREAD)
+        s << "(((tl" << ph << " >> " << (int)bit << ") & 1u) != 0u)";
+    else
+        s << "(((base >> " << (int)bit << ") & 1ull) != 0ull)";
+    return s.str();
+}
+
+std::string mr(size_t j) {  // 4 real entries of record j
+    std::ostringstream s;
+    s << "opm(ops, " << j << ", 0), opm(ops, " << j << ", 1), opm(ops, " << j << ", 2), opm(ops, "
+      << j << ", 3)";
+    return s.str();
+}
+std::string mc(size_t j, int n) {  // n complex entries of record j
+    std::ostringstream s;
+    for (int i = 0; i < n; ++i) s << (i ? ", " : "") << "opc(ops, " << j << ", " << i << ")";
+    return s.str();
+}
+
+// Ops per basic block of a generated body. A long pass would otherwise be
+// one basic block of tens of thousands of instructions, whose instruction
+// selection and scheduling time grows faster than linearly; the blocks are
+// separated by a branch on an opaque always-true scalar (one SALU move and a
+// uniform branch at run time).
+constexpr int kOpsPerBlock = 8;
+const char *kBlockOpen = "    { uint32_t qw_g; __asm__ volatile(\"s_mov_b32 %0, 1\" : \"=s\"(qw_g)); if (qw_g) {\n";
+const char *kBlockClose = "    } }\n";
+
+// Straight-line code of ops [b, e) of a pass in phase ph.
+std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t ph) {
+    std::ostringstream g;
+    int in_block = 0;
+    for (size_t j = b; j < e;) {
+        const DevOp &o = ops[j];
+        if (in_block == kOpsPerBlock) {
+            g << kBlockClose;
+            in_block = 0;
+        }
+        if (in_block == 0) g << kBlockOpen;
+        ++in_block;
+        const bool lane = o.la == LOC_LANE;
+        switch (o.type) {
+        case OP_UR:
+            if (lane) g << "    ur_l<" << (int)o.sa << ">(v, " << mr(j) << ", lane);\n";
+            else g << "    ur_r<" << (int)o.sa << ">(v, " << mr(j) << ");\n";
+            ++j;
+            break;
+        case OP_U:
+            if (lane) g << "    u_l<" << (int)o.sa << ">(v, " << mc(j, 4) << ", lane);\n";
+            else g << "    u_r<" << (int)o.sa << ">(v, " << mc(j, 4) << ");\n";
+            ++j;
+            break;
+        case OP_PERM:
+            if (lane) g << "    perm_l<" << (int)o.sa << ">(v, " << mc(j, 2) << ", lane);\n";
+            else g << "    perm_r<" << (int)o.sa << ">(v, " << mc(j, 2) << ");\n";
+            ++j;
+            break;
+        case OP_CX:
+            if (lane) {
+                if (o.lb == LOC_REG) g << "    cx_lr<" << (int)o.sa << ", " << (int)o.sb << ">(v);\n";
+                else g << "    cx_lb<" << (int)o.sa << ">(v, " << bitval(o.lb, o.b, ph) << ");\n";
+            } else {
+                if (o.lb == LOC_REG) g << "    cx_rr<" << (int)o.sa << ", " << (int)o.sb << ">(v);\n";
+                else g << "    cx_rb<" << (int)o.sa << ">(v, " << bitval(o.lb, o.b, ph) << ");\n";
+            }
+            ++j;
+            break;
+        case OP_DIAG:
+            if (o.la == LOC_REG) g << "    diag_r<" << (int)o.sa << ">(v, " << mc(j, 2) << ");\n";
+            else g << "    diag_b(v, " << bitval(o.la, o.a, ph) << ", " << mc(j, 2) << ");\n";
+            ++j;
+            break;
+        case OP_CZ:
+            if (o.la == LOC_REG && o.lb == LOC_REG)
+                g << "    cz_rr<" << (int)o.sa << ", " << (int)o.sb << ">(v);\n";
+            else if (o.la == LOC_REG)
+                g << "    cz_rb<" << (int)o.sa << ">(v, " << bitval(o.lb, o.b, ph) << ");\n";
+            else if (o.lb == LOC_REG)
+                g << "    cz_rb<" << (int)o.sb << ">(v, " << bitval(o.la, o.a, ph) << ");\n";
+            else
+                g << "    cz_bb(v, " << bitval(o.la, o.a, ph) << " && " << bitval(o.lb, o.b, ph)
+                  << ");\n";
+            ++j;
+            break;
+        case OP_DSET: {
+            const size_t m0 = j + 1 + o.sb;
+            g << "    {\n        float2 ft = make_float2(1.0f, 0.0f);\n";
+            for (size_t q = 0; q < o.b; ++q) {
+                const DevOp &mm = ops[m0 + q];
+                g << "        ft = dset_fold(ft, " << bitval(mm.la, mm.a, ph) << ", " << mc(m0 + q, 2)
+                  << ");\n";
+            }
+            if (o.sb)
+                g << "        dset_apply(v, ops + " << j + 1 << ", true, ft, " << (o.b ? "true" : "false")
+                  << ");\n";
+            else
+                g << "        dset_apply(v, ops, false, ft, true);\n";
+            g << "    }\n";
+            j = m0 + o.b;
+            break;
+        }
+        default:
+            ++j;
+            break;
+        }
+    }
+    if (in_block) g << kBlockClose;
+    return g.str();
+}
+
+std::string emit_body(int m, const HostPass &p) {
+    std::ostringstream g;
+    g << "__device__ __forceinline__ void body(float2 (&v)[16], const DevOp *__restrict__ ops, "
+         "uint32_t tid, uint32_t lane, uint64_t base, char *lb) {\n";
+    g << "    (void)lane; (void)base; (void)lb;\n";
+    const auto &ph = p.dev_phases;
+    for (size_t k = 0; k < ph.size(); ++k)
+        g << "    const uint32_t tl" << k << " = thread_local_index(tid, " << (int)ph[k].reg[0] << "u, "
+          << (int)ph[k].reg[1] << "u, " << (int)ph[k].reg[2] << "u, " << (int)ph[k].reg[3]
+          << "u); (void)tl" << k << ";\n";
+    for (size_t k = 0; k < ph.size(); ++k) {
+        if (k > 0) {
+            g << "    {   // exchange " << k - 1 << " -> " << k << "\n";
+            g << "        const uint32_t s8 = swz(tl" << k - 1 << ") << 3;\n";
+            g << "        lds_barrier();\n";
+            for (int r = 0; r < 16; ++r)
+                g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << ph[k - 1].lds_off[r] << "u)) = v["
+                  << r << "];\n";
+            g << "        lds_barrier();\n";
+            g << "        const uint32_t t8 = swz(tl" << k << ") << 3;\n";
+            for (int r = 0; r < 16; ++r)
+                g << "        v[" << r << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ "
+                  << ph[k].lds_off[r] << "u));\n";
+            g << "    }\n";
+        }
+        g << "    // phase " << k << ": registers " << (int)ph[k].reg[0] << "," << (int)ph[k].reg[1] << ","
+          << (int)ph[k].reg[2] << "," << (int)ph[k].reg[3] << "\n";
+        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k);
+    }
+    g << "}\n";
+    (void)m;
+    return g.str();
+}
+
+const char *kScaleIn =
+    "    {\n"
+    "        const double s = *gin<double>(ldu(&d->scale_in));\n"
+    "        #pragma unroll\n"
+    "        for (int k = 0; k < 16; ++k)\n"
+    "            v[k] = make_float2((float)((double)v[k].x * s), (float)((double)v[k].y * s));\n"
+    "    }\n";
+
+}  // namespace
+
+std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
+    std::string k;
+    k.reserve(64 + 8 * p.dev_ops.size() + 12 * p.dev_phases.size());
+    auto put = [&](uint64_t v, int bytes) {
+        for (int i = 0; i < bytes; ++i) k.push_back((char)((v >> (8 * i)) & 0xFF));
+    };
+    put((uint64_t)n, 1);
+    put((uint64_t)m, 1);
+    put(use_lds ? 1 : 0, 1);
+    put((p.scale_in ? 1 : 0) | (p.norm_out ? 2 : 0), 1);
+    put(p.local_mask, 8);
+    put(p.dev_phases.size(), 2);
+    for (const DevPhase &f : p.dev_phases) {
+        for (int s = 0; s < 4; ++s) put(f.reg[s], 1);
+        put(f.io, 1);
+        put(f.op_begin, 2);
+        put(f.op_end, 2);
+    }
+    put(p.dev_ops.size(), 2);
+    for (const DevOp &o : p.dev_ops) {
+        put(o.type, 1);
+        put(o.a, 1);
+        put(o.b, 1);
+        put(o.sa, 1);
+        put(o.sb, 1);
+        put(o.la, 1);
+        put(o.lb, 1);
+    }
+    return k;
+}
+
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
+    Gen g;
+    const int T = 1 << (m - 4);
+    const int WG = T < 256 ? T : 256;
+    g << "// generated pass kernel: " << n << " qubits, tile bits " << m << ", " << p.dev_ops.size()
+      << " op records, " << p.dev_phases.size() << " phases, "
+      << (use_lds ? "persistent LDS form" : "flat form") << "\n";
+    g << "#include \"qw_dev.h\"\nusing namespace qw;\n";
+    g << "constexpr int M = " << m << ", T = " << T << ", WG = " << WG << ", PARTS = T / WG;\n";
+    emit_io_helpers(g, "io_in", p.io_in, m);
+    emit_io_helpers(g, "io_out", p.io_out, m);
+    emit_load(g, p.io_in);
+    emit_store(g, p.io_out);
+    g << emit_body(m, p);
+    if (!use_lds) {
+        g << "extern \"C\" __global__ __launch_bounds__(WG) void qw_pass(const PassDesc *__restrict__ "
+             "descs, uint32_t n_descs, uint32_t items, int remap) {\n"
+             "    const uint32_t wg_item = item_of(blockIdx.x, gridDim.x, remap);\n"
+             "    const uint32_t item = wg_item / PARTS;\n"
+             "    if (item >= items) return;\n"
+             "    const uint32_t part = wg_item % PARTS;\n"
+             "    const uint32_t p = item % n_descs, tile = item / n_descs;\n"
+             "    const PassDesc *d = descs + p;\n"
+             "    const uint64_t base = uni(ldu(ldu(&d->tile_base) + tile));\n"
+             "    const uint32_t tid = part * WG + threadIdx.x;\n"
+             "    const uint32_t lane = threadIdx.x & 63u;\n"
+             "    const uint32_t wave = uni(tid >> 6);\n"
+             "    float2 v[16];\n"
+             "    load_in(v, ldu(&d->src), base | io_in_wave(wave), io_in_lane(lane));\n";
+        if (p.scale_in) g << kScaleIn;
+        g << "    body(v, ldu(&d->ops), tid, lane, base, nullptr);\n"
+             "    store_out(v, ldu(&d->dst), base | io_out_wave(wave), io_out_lane(lane));\n"
+             "}\n";
+    } else {
+        g << "extern \"C\" __global__ __launch_bounds__(T) void qw_pass(const PassDesc *__restrict__ "
+             "descs, uint32_t n_descs, uint32_t items, int remap) {\n"
+             "    (void)remap;\n"
+             "    __shared__ float2 lds[1 << M];\n"
+             "    __shared__ double red[T / 64 + 1];\n"
+             "    (void)red;\n"
+             "    const uint32_t w = blockIdx.x, x = w & 7u, j = w >> 3, wpx = gridDim.x >> 3;\n"
+             "    const uint32_t per = (items + 7u) >> 3;\n"
+             "    const uint32_t first = x * per;\n"
+             "    const uint32_t last = (first + per < items) ? first + per : items;\n"
+             "    uint32_t item = first + j;\n"
+             "    if (item >= last) return;\n"
+             "    const uint32_t tid = threadIdx.x;\n"
+             "    const uint32_t lane = tid & 63u;\n"
+             "    const uint32_t wave = uni(tid >> 6);\n"
+             "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave);\n"
+             "    const uint32_t li = io_in_lane(lane), lo = io_out_lane(lane);\n"
+             "    char *lb = reinterpret_cast<char *>(lds);\n"
+             "    float2 nv[16];\n"
+             "    {\n"
+             "        const PassDesc *d0 = descs + item % n_descs;\n"
+             "        load_in(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + item / n_descs)) | wi, li);\n"
+             "    }\n"
+             "    while (true) {\n"
+             "        float2 v[16];\n"
+             "        #pragma unroll\n"
+             "        for (int k = 0; k < 16; ++k) v[k] = nv[k];\n"
+             "        const uint32_t p = item % n_descs, tile = item / n_descs;\n"
+             "        const PassDesc *d = descs + p;\n"
+             "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tile));\n"
+             "        const uint32_t next = item + wpx;\n"
+             "        const bool has_next = next < last;\n"
+             "        if (has_next) {\n"
+             "            const PassDesc *dn = descs + next % n_descs;\n"
+             "            load_in(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + next / n_descs)) | wi, li);\n"
+             "        }\n";
+        if (p.scale_in) g << kScaleIn;
+        g << "        body(v, ldu(&d->ops), tid, lane, base, lb);\n";
+        if (p.norm_out)
+            g << "        {\n"
+                 "            double s = 0.0;\n"
+                 "            #pragma unroll\n"
+                 "            for (int k = 0; k < 16; ++k) {\n"
+                 "                const double xx = v[k].x, yy = v[k].y;\n"
+                 "                s = fma(xx, xx, s);\n"
+                 "                s = fma(yy, yy, s);\n"
+                 "            }\n"
+                 "            s = block_sum<T>(s, red);\n"
+                 "            if (tid == 0) gout<double>(ldu(&d->norm_part))[tile] = s;\n"
+                 "        }\n";
+        g << "        store_out(v, ldu(&d->dst), base | wo, lo);\n"
+             "        if (!has_next) break;\n"
+             "        item = next;\n"
+             "    }\n"
+             "}\n";
+    }
+    return g.o.str();
+}
+
+// ---------------------------------------------------------------- compile
+namespace {
+
+struct Registry {
+    std::mutex mu;
+    // (device, key) -> kernel
+    std::map<std::pair<int, std::string>, std::unique_ptr<JitKernel>> kernels;
+    // key -> code object
+    std::unordered_map<std::string, std::vector<char>> code;
+};
+
+Registry &reg() {
+    static Registry *r = new Registry();  // never destroyed: modules live until exit
+    return *r;
+}
+
+std::atomic<uint64_t> g_compiled{0}, g_hits{0};
+std::atomic<uint64_t> g_compile_us{0};
+
+uint64_t fnv1a(const std::string &s, uint64_t h) {
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+std::string cache_dir() {
+    const char *e = std::getenv("QW_JIT_CACHE");
+    if (e) {
+        if (!std::strcmp(e, "off") || !*e) return "";
+        return e;
+    }
+    const char *h = std::getenv("HOME");
+    if (!h || !*h) return "";
+    return std::string(h) + "/.cache/qw_jit";
+}
+
+std::string cache_path(const std::string &dir, const std::string &src) {
+    char b[64];
+    std::snprintf(b, sizeof b, "/%016llx%016llx.co",
+                  (unsigned long long)fnv1a(src, 0xcbf29ce484222325ull),
+                  (unsigned long long)fnv1a(src, 0x84222325cbf29ce4ull));
+    return dir + b;
+}
+
+// Disk cache entry: source length, source text, code object. The stored
+// source must equal the requested one (no trust in the hash alone).
+bool cache_load(const std::string &src, std::vector<char> *code) {
+    const std::string dir = cache_dir();
+    if (dir.empty()) return false;
+    std::ifstream f(cache_path(dir, src), std::ios::binary);
+    if (!f) return false;
+    uint64_t len = 0;
+    if (!f.read(reinterpret_cast<char *>(&len), sizeof len) || len != src.size()) return false;
+    std::string s(len, '\0');
+    if (!f.read(&s[0], (std::streamsize)len) || s != src) return false;
+    std::vector<char> c((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    if (c.empty()) return false;
+    code->swap(c);
+    return true;
+}
+
+void cache_store(const std::string &src, const std::vector<char> &code) {
+    const std::string dir = cache_dir();
+    if (dir.empty()) return;
+    std::string cmd_dir = dir;
+    // create the directory chain (best effort, no shell)
+    for (size_t i = 1; i <= cmd_dir.size(); ++i) {
+        if (i == cmd_dir.size() || cmd_dir[i] == '/') {
+            std::string part = cmd_dir.substr(0, i);
+            ::mkdir(part.c_str(), 0755);
+        }
+    }
+    const std::string path = cache_path(dir, src);
+    const std::string tmp = path + ".tmp" + std::to_string((unsigned long long)std::hash<std::thread::id>()(std::this_thread::get_id()));
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        if (!f) return;
+        const uint64_t len = src.size();
+        f.write(reinterpret_cast<const char *>(&len), sizeof len);
+        f.write(src.data(), (std::streamsize)src.size());
+        f.write(code.data(), (std::streamsize)code.size());
+        if (!f) return;
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+std::string compile_one(const std::string &src, std::vector<char> *code) {
+    hiprtcProgram prog = nullptr;
+    const char *hdr_src[2] = {kEmbedDescH, kEmbedDevH};
+    const char *hdr_name[2] = {"qw_desc.h", "qw_dev.h"};
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qw_pass.hip", 2, hdr_src, hdr_name);
+    if (r != HIPRTC_SUCCESS) return std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
+    r = hiprtcCompileProgram(prog, kNumOpts, kOpts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r) + "\n" + log;
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    code->resize(cs);
+    hiprtcGetCode(prog, code->data());
+    hiprtcDestroyProgram(&prog);
+    return "";
+}
+
+}  // namespace
+
+std::string jit_precompile(const std::vector<JitReq> &ks) {
+    Registry &R = reg();
+    // code objects still missing (in memory): disk cache, else compile in parallel
+    std::vector<size_t> need;
+    {
+        std::lock_guard<std::mutex> lk(R.mu);
+        for (size_t i = 0; i < ks.size(); ++i) {
+            if (R.code.count(ks[i].key)) continue;
+            bool dup = false;
+            for (size_t q : need) dup |= ks[q].key == ks[i].key;
+            if (!dup) need.push_back(i);
+        }
+    }
+    if (need.empty()) return "";
+    std::vector<std::vector<char>> codes(need.size());
+    std::vector<std::string> errs(need.size());
+    std::vector<std::string> srcs(need.size());
+    const char *dump = std::getenv("QW_JIT_DUMP");  // debugging: write sources to this folder
+    for (size_t q = 0; q < need.size(); ++q) {
+        const JitReq &r = ks[need[q]];
+        srcs[q] = jit_pass_source(r.n, r.m, *r.pass, r.use_lds);
+        if (dump && *dump) {
+            std::ofstream f(cache_path(dump, srcs[q]) + ".hip");
+            f << srcs[q];
+        }
+    }
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t q; (q = next.fetch_add(1)) < need.size();) {
+            const std::string &src = srcs[q];
+            if (cache_load(src, &codes[q])) {
+                g_hits.fetch_add(1);
+                continue;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            errs[q] = compile_one(src, &codes[q]);
+            const auto t1 = std::chrono::steady_clock::now();
+            g_compile_us.fetch_add(
+                (uint64_t)std::chrono::duration_cast<std::chrono::microseconds>(t1 - t0).count());
+            if (errs[q].empty()) {
+                g_compiled.fetch_add(1);
+                cache_store(src, codes[q]);
+            }
+        }
+    };
+    const unsigned hw = std::thread::hardware_concurrency();
+    const size_t nth = std::min<size_t>(need.size(), std::max(1u, std::min(hw, 16u)));
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nth; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+    std::lock_guard<std::mutex> lk(R.mu);
+    for (size_t q = 0; q < need.size(); ++q) {
+        if (!errs[q].empty()) return "generated kernel failed to compile: " + errs[q];
+        R.code[ks[need[q]].key] = std::move(codes[q]);
+    }
+    return "";
+}
+
+std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<const JitKernel *> *out) {
+    Registry &R = reg();
+    const std::vector<JitReq> &ks = reqs;
+    out->assign(ks.size(), nullptr);
+    {
+        // fast path: every kernel already loaded on this device
+        std::lock_guard<std::mutex> lk(R.mu);
+        bool all = true;
+        for (size_t i = 0; i < ks.size(); ++i) {
+            auto it = R.kernels.find({device, ks[i].key});
+            if (it == R.kernels.end()) {
+                all = false;
+                continue;
+            }
+            (*out)[i] = it->second.get();
+        }
+        if (all) return "";
+    }
+    {
+        std::vector<JitReq> miss;
+        for (size_t i = 0; i < ks.size(); ++i)
+            if (!(*out)[i]) miss.push_back(ks[i]);
+        const std::string e = jit_precompile(miss);
+        if (!e.empty()) return e;
+    }
+    std::lock_guard<std::mutex> lk(R.mu);
+    for (size_t i = 0; i < ks.size(); ++i) {
+        if ((*out)[i]) continue;
+        auto it = R.kernels.find({device, ks[i].key});
+        if (it != R.kernels.end()) {
+            (*out)[i] = it->second.get();
+            continue;
+        }
+        const std::vector<char> &code = R.code[ks[i].key];
+        const int m = ks[i].m;
+        const bool use_lds = ks[i].use_lds;
+        hipModule_t mod = nullptr;
+        hipError_t e = hipModuleLoadData(&mod, code.data());
+        if (e != hipSuccess) return std::string("hipModuleLoadData: ") + hipGetErrorString(e);
+        auto k = std::make_unique<JitKernel>();
+        e = hipModuleGetFunction(&k->fn, mod, "qw_pass");
+        if (e != hipSuccess) return std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
+        const int T = 1 << (m - 4);
+        k->use_lds = use_lds;
+        k->m = m;
+        k->wg = use_lds ? T : (T < 256 ? T : 256);
+        k->parts = use_lds ? 1 : T / k->wg;
+        k->blocks_per_cu = 1;
+        if (use_lds) {
+            int nb = 0;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, k->wg, 0) == hipSuccess &&
+                nb > 0)
+                k->blocks_per_cu = nb;
+        }
+        (*out)[i] = k.get();
+        R.kernels[{device, ks[i].key}] = std::move(k);
+    }
+    return "";
+}
+
+hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs, uint32_t n_descs,
+                      uint32_t tiles, int remap, uint32_t cu_count) {
+    const uint32_t items = n_descs * tiles;
+    uint32_t grid;
+    if (k.use_lds) {
+        const uint32_t full = cu_count * (uint32_t)k.blocks_per_cu;
+        const uint32_t want = ((items + 7u) / 8u) * 8u;
+        grid = want < full ? want : (full / 8u) * 8u;
+        if (grid < 8u) grid = 8u;
+    } else {
+        grid = items * (uint32_t)k.parts;
+        if (remap && (grid & 7u)) remap = 0;
+    }
+    uint32_t items_arg = items;
+    void *args[] = {&descs, &n_descs, &items_arg, &remap};
+    return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
+}
+
+void jit_stats(uint64_t *compiled, uint64_t *cache_hits, double *compile_s) {
+    if (compiled) *compiled = g_compiled.load();
+    if (cache_hits) *cache_hits = g_hits.load();
+    if (compile_s) *compile_s = (double)g_compile_us.load() * 1e-6;
+}
+
+}  // namespace qw

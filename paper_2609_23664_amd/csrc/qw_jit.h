@@ -1,0 +1,63 @@
+// Pass kernels generated from a plan and compiled at run time (hipRTC).
+//
+// The interpreted pass kernels decode every op record on every tile. A
+// generated kernel has the op sequence, the register/lane slots, the phase
+// layouts, the I/O address constants and the pass flags of one lowered pass
+// fixed at compile time; only the matrix entries (and the tile table, source
+// and destination) are read at run time, from the same records. All tasks
+// whose passes lower to the same structure (for example the tasks of one
+// parameterised circuit) share one kernel. The op code is the one of
+// qw_dev.h, so a generated kernel rounds exactly as the interpreter does.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "qw_internal.h"
+
+namespace qw {
+
+// Exact structural key of a lowered pass: op types, bit locations, slots,
+// phase layouts, flags, tile bits and kernel form. Two passes with the same
+// key run the same generated kernel.
+std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds);
+
+// Full HIP source of the generated kernel for a key's pass.
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds);
+
+struct JitKernel {
+    hipFunction_t fn = nullptr;
+    bool use_lds = false;
+    int m = 0;
+    int wg = 0;            // threads per workgroup
+    int parts = 1;         // workgroups per tile (flat form)
+    int blocks_per_cu = 1; // resident workgroups per CU (LDS form)
+};
+
+// One requested kernel: its key and the pass it was computed from.
+struct JitReq {
+    std::string key;
+    const HostPass *pass = nullptr;
+    int n = 0, m = 0;
+    bool use_lds = false;
+};
+
+// Compiled kernels for the requests on `device`: loaded from memory, from
+// the disk cache, or compiled (in parallel). Returns "" or an error message.
+std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<const JitKernel *> *out);
+
+// Compile (or load from the disk cache) the code objects of the requests
+// without loading them on a device; no GPU is needed.
+std::string jit_precompile(const std::vector<JitReq> &reqs);
+
+// Launch a generated pass kernel over n_descs descriptors (all of its key).
+hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs, uint32_t n_descs,
+                      uint32_t tiles, int remap, uint32_t cu_count);
+
+// Number of generated kernels compiled (not loaded from cache) and seconds
+// spent compiling, since the process started.
+void jit_stats(uint64_t *compiled, uint64_t *cache_hits, double *compile_s);
+
+}  // namespace qw

@@ -22,35 +22,15 @@
 #include <cstdint>
 
 #include "qw_internal.h"
+#include "qw_dev.h"
 #include "qw_kernels.h"
 
 namespace qw {
 
-// ------------------------------------------------------------- helpers
-// Descriptors, ops, phases and terms are written by a host-to-device copy
-// before a launch and only read during it; reading them through the
-// constant address space lets uniform accesses use scalar loads.
-#if defined(__HIP_DEVICE_COMPILE__)
-#define QW_CONST __attribute__((address_space(4)))
-#define QW_GLOBAL __attribute__((address_space(1)))
-#else
-#define QW_CONST
-#define QW_GLOBAL
-#endif
-
-template <typename T>
-__device__ __forceinline__ T ldu(const T *p) {
-    return *(const QW_CONST T *)(p);
-}
-
-// Force a wave-uniform 32-bit value into a scalar register.
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float unif(float v) {
-    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
-}
-__device__ __forceinline__ uint64_t uni64(uint64_t v) {
-    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
-}
+// ------------------------------------------------------------- interpreter
+// The interpreted pass kernels read each op record at run time and branch to
+// the matching tile operation of qw_dev.h; generated kernels call the same
+// operations with the record contents fixed at compile time.
 
 // Uniform loads of the small plan records, kept in scalar registers.
 struct PhaseHead {
@@ -71,27 +51,6 @@ __device__ __forceinline__ PhaseHead ld_phase_head(const DevPhase *p) {
     h.op_end = (uint16_t)(w1 >> 16);
     h.io = (uint8_t)w2;
     return h;
-}
-
-template <typename T>
-__device__ __forceinline__ T ld_words(const T *p) {
-    static_assert(sizeof(T) % 4 == 0, "word record");
-    uint32_t w[sizeof(T) / 4];
-    #pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = uni(((const QW_CONST uint32_t *)p)[i]);
-    T r;
-    __builtin_memcpy(&r, w, sizeof r);
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ const QW_GLOBAL T *gin(const void *p) {
-    return (const QW_GLOBAL T *)(p);
-}
-
-template <typename T>
-__device__ __forceinline__ QW_GLOBAL T *gout(void *p) {
-    return (QW_GLOBAL T *)(p);
 }
 
 __device__ __forceinline__ uint64_t dpdep(uint64_t v, uint64_t mask) {
@@ -118,256 +77,78 @@ __device__ __forceinline__ uint32_t dpdep32(uint32_t v, uint32_t mask) {
     return r;
 }
 
-// LDS address swizzle: the low 5 bits of the element index are XORed with
-// bits 5..9 and 10..13, which keeps every phase's 64 lanes on distinct bank
-// groups for the phase layouts the planner produces.
-__device__ __forceinline__ uint32_t swz(uint32_t l) {
-    return l ^ (((l >> 5) ^ (l >> 10)) & 31u);
+// Value of a thread or global operand bit (never a register bit).
+__device__ __forceinline__ bool opbit_tg(uint8_t loc, uint8_t bit, uint32_t tl, uint64_t base) {
+    return loc == LOC_THREAD ? ((tl >> bit) & 1u) : ((uint32_t)(base >> bit) & 1u);
 }
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// u * x + v * y for complex u, v, x, y
-__device__ __forceinline__ float2 cmad2(float2 u, float2 x, float2 v, float2 y) {
-    float re = u.x * x.x;
-    re = fmaf(-u.y, x.y, re);
-    re = fmaf(v.x, y.x, re);
-    re = fmaf(-v.y, y.y, re);
-    float im = u.x * x.y;
-    im = fmaf(u.y, x.x, im);
-    im = fmaf(v.x, y.y, im);
-    im = fmaf(v.y, y.x, im);
-    return make_float2(re, im);
-}
-
-// Item index for workgroup b: with remapping, the workgroups that the
-// hardware places on one XCD (b mod 8) process consecutive items.
-__device__ __forceinline__ uint32_t item_of(uint32_t b, uint32_t grid, int remap) {
-    if (!remap) return b;
-    uint32_t per = grid >> 3;
-    return (b & 7u) * per + (b >> 3);
-}
-
-// Fixed-order block sum of one double per thread; result valid in thread 0.
-template <int T>
-__device__ double block_sum(double v, double *red) {
-    #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    constexpr int W = (T + 63) / 64;
-    if constexpr (W == 1) {
-        return v;
-    } else {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        __syncthreads();
-        if (lane == 0) red[w] = v;
-        __syncthreads();
-        double s = 0.0;
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < W; ++k) s += red[k];
-        }
-        return s;
+#define QW_SLOT4(FN, SEL, ...)                                    \
+    switch (SEL) {                                                \
+    case 0: FN<0>(__VA_ARGS__); break;                            \
+    case 1: FN<1>(__VA_ARGS__); break;                            \
+    case 2: FN<2>(__VA_ARGS__); break;                            \
+    default: FN<3>(__VA_ARGS__); break;                           \
     }
-}
+#define QW_LANE6(FN, SEL, ...)                                    \
+    switch (SEL) {                                                \
+    case 0: FN<0>(__VA_ARGS__); break;                            \
+    case 1: FN<1>(__VA_ARGS__); break;                            \
+    case 2: FN<2>(__VA_ARGS__); break;                            \
+    case 3: FN<3>(__VA_ARGS__); break;                            \
+    case 4: FN<4>(__VA_ARGS__); break;                            \
+    default: FN<5>(__VA_ARGS__); break;                           \
+    }
 
-// ------------------------------------------------------------- register ops
+// CX / CZ with a register control slot chosen at run time.
 template <int S>
-__device__ __forceinline__ void op_u(float2 (&v)[16], const float *m) {
-    const float2 a = make_float2(m[0], m[1]), b = make_float2(m[2], m[3]);
-    const float2 c = make_float2(m[4], m[5]), d = make_float2(m[6], m[7]);
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k & (1 << S)) continue;
-        const float2 x = v[k], y = v[k | (1 << S)];
-        v[k] = cmad2(a, x, b, y);
-        v[k | (1 << S)] = cmad2(c, x, d, y);
+__device__ __forceinline__ void cx_rr_s(float2 (&v)[16], uint32_t c) {
+    switch (c) {
+    case 0: cx_rr<S, 0>(v); break;
+    case 1: cx_rr<S, 1>(v); break;
+    case 2: cx_rr<S, 2>(v); break;
+    default: cx_rr<S, 3>(v); break;
     }
 }
-
-// Real 2x2 matrix on a register slot: 4 FP32 ops per output amplitude.
+template <int J>
+__device__ __forceinline__ void cx_lr_s(float2 (&v)[16], uint32_t c) {
+    switch (c) {
+    case 0: cx_lr<J, 0>(v); break;
+    case 1: cx_lr<J, 1>(v); break;
+    case 2: cx_lr<J, 2>(v); break;
+    default: cx_lr<J, 3>(v); break;
+    }
+}
 template <int S>
-__device__ __forceinline__ void op_ur(float2 (&v)[16], const float *m) {
-    const float a = m[0], b = m[1], c = m[2], d = m[3];
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k & (1 << S)) continue;
-        const float2 x = v[k], y = v[k | (1 << S)];
-        v[k] = make_float2(fmaf(a, x.x, b * y.x), fmaf(a, x.y, b * y.y));
-        v[k | (1 << S)] = make_float2(fmaf(c, x.x, d * y.x), fmaf(c, x.y, d * y.y));
+__device__ __forceinline__ void cz_rr_s(float2 (&v)[16], uint32_t c) {
+    switch (c) {
+    case 0: cz_rr<S, 0>(v); break;
+    case 1: cz_rr<S, 1>(v); break;
+    case 2: cz_rr<S, 2>(v); break;
+    default: cz_rr<S, 3>(v); break;
     }
 }
 
-template <int S>
-__device__ __forceinline__ void op_perm(float2 (&v)[16], const float *m) {
-    const float2 p01 = make_float2(m[0], m[1]), p10 = make_float2(m[2], m[3]);
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k & (1 << S)) continue;
-        const float2 x = v[k], y = v[k | (1 << S)];
-        v[k] = cmul(p01, y);
-        v[k | (1 << S)] = cmul(p10, x);
-    }
-}
-
-// Value (0/1) of operand bit for register k.
-__device__ __forceinline__ uint32_t opbit(uint8_t loc, uint8_t bit, uint8_t slot, int k,
-                                          uint32_t tl, uint64_t base) {
-    if (loc == LOC_REG) return ((uint32_t)k >> slot) & 1u;
-    if (loc == LOC_THREAD) return (tl >> bit) & 1u;
-    return (uint32_t)(base >> bit) & 1u;
-}
-
-template <int S>
-__device__ __forceinline__ void op_cx(float2 (&v)[16], const DevOp &op, uint32_t tl,
-                                      uint64_t base) {
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k & (1 << S)) continue;
-        const uint32_t c = opbit(op.lb, op.b, op.sb, k, tl, base);
-        const float2 x = v[k], y = v[k | (1 << S)];
-        v[k] = c ? y : x;
-        v[k | (1 << S)] = c ? x : y;
-    }
-}
-
-__device__ __forceinline__ void op_diag(float2 (&v)[16], const DevOp &op, uint32_t tl,
-                                        uint64_t base) {
-    const float2 d0 = make_float2(op.m[0], op.m[1]), d1 = make_float2(op.m[2], op.m[3]);
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t b = opbit(op.la, op.a, op.sa, k, tl, base);
-        v[k] = cmul(b ? d1 : d0, v[k]);
-    }
-}
-
-__device__ __forceinline__ void op_cz(float2 (&v)[16], const DevOp &op, uint32_t tl,
-                                      uint64_t base) {
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t b = opbit(op.la, op.a, op.sa, k, tl, base) &
-                           opbit(op.lb, op.b, op.sb, k, tl, base);
-        if (b) v[k] = make_float2(-v[k].x, -v[k].y);
-    }
-}
-
-// Value of lane (lane ^ 2^J) for the 64-wide wavefront: DPP for J < 4
-// (quad permutes and row mirrors), cross-row shuffles for J = 4, 5.
-template <int J>
-__device__ __forceinline__ float lane_xor(float x) {
-    int v = __float_as_int(x);
-    if constexpr (J == 0) {
-        v = __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
-    } else if constexpr (J == 1) {
-        v = __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
-    } else if constexpr (J == 2) {
-        v = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror: ^7
-        v = __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, true);   // quad_perm 3,2,1,0: ^3
-    } else if constexpr (J == 3) {
-        v = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);  // row_mirror: ^15
-        v = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror: ^7
-    } else {
-        v = __shfl_xor(v, 1 << J, 64);
-    }
-    return __int_as_float(v);
-}
-
-template <int J>
-__device__ __forceinline__ float2 lane_xor2(float2 a) {
-    return make_float2(lane_xor<J>(a.x), lane_xor<J>(a.y));
-}
-
-// 2x2 op on a lane bit: each lane keeps its own component of the pair.
-template <int J>
-__device__ __forceinline__ void op_u_lane(float2 (&v)[16], const float *m, uint32_t lane) {
-    const bool b = (lane >> J) & 1u;
-    // the matrix entries are wave-uniform; select per lane between scalars
-    const float m0 = unif(m[0]), m1 = unif(m[1]), m2 = unif(m[2]), m3 = unif(m[3]);
-    const float m4 = unif(m[4]), m5 = unif(m[5]), m6 = unif(m[6]), m7 = unif(m[7]);
-    const float2 cs = make_float2(b ? m6 : m0, b ? m7 : m1);
-    const float2 co = make_float2(b ? m4 : m2, b ? m5 : m3);
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const float2 pk = lane_xor2<J>(v[k]);
-        v[k] = cmad2(cs, v[k], co, pk);
-    }
-}
-
-template <int J>
-__device__ __forceinline__ void op_ur_lane(float2 (&v)[16], const float *m, uint32_t lane) {
-    const bool b = (lane >> J) & 1u;
-    const float m0 = unif(m[0]), m1 = unif(m[1]), m2 = unif(m[2]), m3 = unif(m[3]);
-    const float cs = b ? m3 : m0, co = b ? m2 : m1;
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const float2 pk = lane_xor2<J>(v[k]);
-        v[k] = make_float2(fmaf(cs, v[k].x, co * pk.x), fmaf(cs, v[k].y, co * pk.y));
-    }
-}
-
-template <int J>
-__device__ __forceinline__ void op_perm_lane(float2 (&v)[16], const float *m, uint32_t lane) {
-    const bool b = (lane >> J) & 1u;
-    const float m0 = unif(m[0]), m1 = unif(m[1]), m2 = unif(m[2]), m3 = unif(m[3]);
-    const float2 co = make_float2(b ? m2 : m0, b ? m3 : m1);
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = cmul(co, lane_xor2<J>(v[k]));
-}
-
-template <int J>
-__device__ __forceinline__ void op_cx_lane(float2 (&v)[16], const DevOp &op, uint32_t tl,
-                                           uint64_t base) {
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t c = opbit(op.lb, op.b, op.sb, k, tl, base);
-        const float2 pk = lane_xor2<J>(v[k]);
-        v[k] = c ? pk : v[k];
-    }
-}
-
-__device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, uint32_t tl,
-                                       uint64_t base) {
+// One op record (not OP_DSET) on the registers of a phase.
+__device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, const DevOp *ops,
+                                       uint32_t j, uint32_t tl, uint64_t base) {
     const uint32_t lane = threadIdx.x & 63u;
     if (op.la == LOC_LANE) {
         switch (op.type) {
         case OP_U:
-            switch (op.sa) {
-            case 0: op_u_lane<0>(v, op.m, lane); break;
-            case 1: op_u_lane<1>(v, op.m, lane); break;
-            case 2: op_u_lane<2>(v, op.m, lane); break;
-            case 3: op_u_lane<3>(v, op.m, lane); break;
-            case 4: op_u_lane<4>(v, op.m, lane); break;
-            default: op_u_lane<5>(v, op.m, lane); break;
-            }
+            QW_LANE6(u_l, op.sa, v, opc(ops, j, 0), opc(ops, j, 1), opc(ops, j, 2), opc(ops, j, 3), lane)
             return;
         case OP_UR:
-            switch (op.sa) {
-            case 0: op_ur_lane<0>(v, op.m, lane); break;
-            case 1: op_ur_lane<1>(v, op.m, lane); break;
-            case 2: op_ur_lane<2>(v, op.m, lane); break;
-            case 3: op_ur_lane<3>(v, op.m, lane); break;
-            case 4: op_ur_lane<4>(v, op.m, lane); break;
-            default: op_ur_lane<5>(v, op.m, lane); break;
-            }
+            QW_LANE6(ur_l, op.sa, v, opm(ops, j, 0), opm(ops, j, 1), opm(ops, j, 2), opm(ops, j, 3), lane)
             return;
         case OP_PERM:
-            switch (op.sa) {
-            case 0: op_perm_lane<0>(v, op.m, lane); break;
-            case 1: op_perm_lane<1>(v, op.m, lane); break;
-            case 2: op_perm_lane<2>(v, op.m, lane); break;
-            case 3: op_perm_lane<3>(v, op.m, lane); break;
-            case 4: op_perm_lane<4>(v, op.m, lane); break;
-            default: op_perm_lane<5>(v, op.m, lane); break;
-            }
+            QW_LANE6(perm_l, op.sa, v, opc(ops, j, 0), opc(ops, j, 1), lane)
             return;
         case OP_CX:
-            switch (op.sa) {
-            case 0: op_cx_lane<0>(v, op, tl, base); break;
-            case 1: op_cx_lane<1>(v, op, tl, base); break;
-            case 2: op_cx_lane<2>(v, op, tl, base); break;
-            case 3: op_cx_lane<3>(v, op, tl, base); break;
-            case 4: op_cx_lane<4>(v, op, tl, base); break;
-            default: op_cx_lane<5>(v, op, tl, base); break;
+            if (op.lb == LOC_REG) {
+                QW_LANE6(cx_lr_s, op.sa, v, op.sb)
+            } else {
+                const bool c = opbit_tg(op.lb, op.b, tl, base);
+                QW_LANE6(cx_lb, op.sa, v, c)
             }
             return;
         default: return;
@@ -375,65 +156,59 @@ __device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, uint32_
     }
     switch (op.type) {
     case OP_UR:
-        switch (op.sa) {
-        case 0: op_ur<0>(v, op.m); break;
-        case 1: op_ur<1>(v, op.m); break;
-        case 2: op_ur<2>(v, op.m); break;
-        default: op_ur<3>(v, op.m); break;
-        }
+        QW_SLOT4(ur_r, op.sa, v, opm(ops, j, 0), opm(ops, j, 1), opm(ops, j, 2), opm(ops, j, 3))
         break;
     case OP_U:
-        switch (op.sa) {
-        case 0: op_u<0>(v, op.m); break;
-        case 1: op_u<1>(v, op.m); break;
-        case 2: op_u<2>(v, op.m); break;
-        default: op_u<3>(v, op.m); break;
-        }
+        QW_SLOT4(u_r, op.sa, v, opc(ops, j, 0), opc(ops, j, 1), opc(ops, j, 2), opc(ops, j, 3))
         break;
     case OP_PERM:
-        switch (op.sa) {
-        case 0: op_perm<0>(v, op.m); break;
-        case 1: op_perm<1>(v, op.m); break;
-        case 2: op_perm<2>(v, op.m); break;
-        default: op_perm<3>(v, op.m); break;
-        }
+        QW_SLOT4(perm_r, op.sa, v, opc(ops, j, 0), opc(ops, j, 1))
         break;
     case OP_CX:
-        switch (op.sa) {
-        case 0: op_cx<0>(v, op, tl, base); break;
-        case 1: op_cx<1>(v, op, tl, base); break;
-        case 2: op_cx<2>(v, op, tl, base); break;
-        default: op_cx<3>(v, op, tl, base); break;
+        if (op.lb == LOC_REG) {
+            QW_SLOT4(cx_rr_s, op.sa, v, op.sb)
+        } else {
+            const bool c = opbit_tg(op.lb, op.b, tl, base);
+            QW_SLOT4(cx_rb, op.sa, v, c)
         }
         break;
-    case OP_DIAG: op_diag(v, op, tl, base); break;
-    case OP_CZ: op_cz(v, op, tl, base); break;
+    case OP_DIAG:
+        if (op.la == LOC_REG) {
+            QW_SLOT4(diag_r, op.sa, v, opc(ops, j, 0), opc(ops, j, 1))
+        } else {
+            diag_b(v, opbit_tg(op.la, op.a, tl, base), opc(ops, j, 0), opc(ops, j, 1));
+        }
+        break;
+    case OP_CZ:
+        if (op.la == LOC_REG && op.lb == LOC_REG) {
+            QW_SLOT4(cz_rr_s, op.sa, v, op.sb)
+        } else if (op.la == LOC_REG) {
+            const bool c = opbit_tg(op.lb, op.b, tl, base);
+            QW_SLOT4(cz_rb, op.sa, v, c)
+        } else if (op.lb == LOC_REG) {
+            const bool c = opbit_tg(op.la, op.a, tl, base);
+            QW_SLOT4(cz_rb, op.sb, v, c)
+        } else {
+            cz_bb(v, opbit_tg(op.la, op.a, tl, base) && opbit_tg(op.lb, op.b, tl, base));
+        }
+        break;
     default: break;
     }
 }
 
-// Local index offset of register k for a phase with register bits reg[].
-__device__ __forceinline__ uint32_t roff(const uint8_t *reg, int k) {
-    return ((k & 1) ? (1u << reg[0]) : 0u) | ((k & 2) ? (1u << reg[1]) : 0u) |
-           ((k & 4) ? (1u << reg[2]) : 0u) | ((k & 8) ? (1u << reg[3]) : 0u);
-}
-
-__device__ __forceinline__ uint32_t regmask(const uint8_t *reg) {
-    return (1u << reg[0]) | (1u << reg[1]) | (1u << reg[2]) | (1u << reg[3]);
-}
-
 // ------------------------------------------------------------- pass kernel
-// Insert a zero bit at each register position (ascending) of tid: the
-// phase's local index of the thread's register 0.
 __device__ __forceinline__ uint32_t thread_local_index(uint32_t tid, const uint8_t *reg) {
-    uint32_t x = tid;
-    #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const uint32_t r = reg[s];
-        x = ((x >> r) << (r + 1)) | (x & ((1u << r) - 1u));
-    }
-    return x;
+    return thread_local_index(tid, reg[0], reg[1], reg[2], reg[3]);
 }
+
+// Global offsets of an I/O layout. IO_F4: register slot 0 = local bit 0,
+// lanes = local bits 1..6, one 16-byte access per register pair. IO_F2:
+// lanes = local bits 0..5, one 8-byte access per register. Waves are the
+// remaining non-register local bits.
+struct IoLayout {
+    uint32_t lane_off;     // global index bits contributed by the lane
+    uint32_t uni_off[16];  // tile base | wave part | register part, per register
+};
 
 // Position of the k-th set bit of mask (k counted from 0). Called with
 // wave-uniform arguments, so it compiles to scalar code.
@@ -441,16 +216,6 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t mask, uint32_t k) {
     for (uint32_t i = 0; i < k; ++i) mask &= mask - 1;
     return (uint32_t)__builtin_ctzll(mask);
 }
-
-// Global offsets of an I/O layout. IO_F4: register slot 0 = local bit 0,
-// lanes = local bits 1..6, one 16-byte access per register pair. IO_F2:
-// lanes = local bits 0..5, one 8-byte access per register. Waves are the
-// remaining non-register local bits. The per-lane part is computed in vector
-// registers, everything else is wave-uniform.
-struct IoLayout {
-    uint32_t lane_off;     // global index bits contributed by the lane
-    uint32_t uni_off[16];  // tile base | wave part | register part, per register
-};
 
 __device__ __forceinline__ IoLayout io_layout(uint64_t lmask, const uint8_t *reg, uint8_t kind,
                                               uint32_t lane, uint32_t wave, uint32_t m,
@@ -482,7 +247,19 @@ __device__ __forceinline__ IoLayout io_layout(uint64_t lmask, const uint8_t *reg
     return io;
 }
 
-// I/O layout from a host-computed record: 8 VALU for the lane part, the
+// Local index offset of register k for a phase with register bits reg[].
+__device__ __forceinline__ uint32_t roff(const uint8_t *reg, int k) {
+    return ((k & 1) ? (1u << reg[0]) : 0u) | ((k & 2) ? (1u << reg[1]) : 0u) |
+           ((k & 4) ? (1u << reg[2]) : 0u) | ((k & 8) ? (1u << reg[3]) : 0u);
+}
+
+// LDS byte address of register k of a thread: swz is linear over GF(2), so
+// swz(tl | roff(k)) = swz(tl) ^ swz(roff(k)) with the second part uniform.
+__device__ __forceinline__ uint32_t lds_off(uint32_t stl8, const uint8_t *reg, int k) {
+    return stl8 ^ (swz(roff(reg, k)) << 3);
+}
+
+// I/O layout from a host-computed record: a few VALU for the lane part, the
 // rest is uniform (scalar loads from the record).
 __device__ __forceinline__ IoLayout io_from_rec(const IoRec *rec, uint32_t lane, uint32_t wave,
                                                 uint32_t base) {
@@ -501,51 +278,32 @@ __device__ __forceinline__ IoLayout io_from_rec(const IoRec *rec, uint32_t lane,
     return io;
 }
 
-__device__ __forceinline__ void io_load(float2 (&v)[16], const void *src_v, const IoLayout &io,
+__device__ __forceinline__ void io_load(float2 (&v)[16], const void *src, const IoLayout &io,
                                         uint8_t kind) {
+    const uint32_t lb = io.lane_off * 8u;
     if (kind == IO_F4) {
-        const QW_GLOBAL float4 *src = gin<float4>(src_v);
-        float4 q[8];
-        #pragma unroll
-        for (int k2 = 0; k2 < 8; ++k2) q[k2] = src[(io.uni_off[2 * k2] >> 1) + (io.lane_off >> 1)];
         #pragma unroll
         for (int k2 = 0; k2 < 8; ++k2) {
-            v[2 * k2] = make_float2(q[k2].x, q[k2].y);
-            v[2 * k2 + 1] = make_float2(q[k2].z, q[k2].w);
+            const float4 q = buf_ld4(src, io.uni_off[2 * k2], lb);
+            v[2 * k2] = make_float2(q.x, q.y);
+            v[2 * k2 + 1] = make_float2(q.z, q.w);
         }
     } else {
-        const QW_GLOBAL float2 *src = gin<float2>(src_v);
         #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = src[io.uni_off[k] + io.lane_off];
+        for (int k = 0; k < 16; ++k) v[k] = buf_ld2(src, io.uni_off[k], lb);
     }
 }
 
-__device__ __forceinline__ void io_store(const float2 (&v)[16], void *dst_v, const IoLayout &io,
+__device__ __forceinline__ void io_store(const float2 (&v)[16], void *dst, const IoLayout &io,
                                          uint8_t kind) {
+    const uint32_t lb = io.lane_off * 8u;
     if (kind == IO_F4) {
-        QW_GLOBAL float4 *dst = gout<float4>(dst_v);
         #pragma unroll
-        for (int k2 = 0; k2 < 8; ++k2)
-            dst[(io.uni_off[2 * k2] >> 1) + (io.lane_off >> 1)] =
-                make_float4(v[2 * k2].x, v[2 * k2].y, v[2 * k2 + 1].x, v[2 * k2 + 1].y);
+        for (int k2 = 0; k2 < 8; ++k2) buf_st4(dst, io.uni_off[2 * k2], lb, v[2 * k2], v[2 * k2 + 1]);
     } else {
-        QW_GLOBAL float2 *dst = gout<float2>(dst_v);
         #pragma unroll
-        for (int k = 0; k < 16; ++k) dst[io.uni_off[k] + io.lane_off] = v[k];
+        for (int k = 0; k < 16; ++k) buf_st2(dst, io.uni_off[k], lb, v[k]);
     }
-}
-
-// LDS byte address of register k of a thread: swz is linear over GF(2), so
-// swz(tl | roff(k)) = swz(tl) ^ swz(roff(k)) with the second part uniform.
-__device__ __forceinline__ uint32_t lds_off(uint32_t stl8, const uint8_t *reg, int k) {
-    return stl8 ^ (swz(roff(reg, k)) << 3);
-}
-
-// Workgroup barrier for LDS exchanges only: waits for this wave's LDS
-// operations, not for its global loads/stores, so prefetched loads stay in
-// flight across exchanges.
-__device__ __forceinline__ void lds_barrier() {
-    __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // Run the ops of one op range [o, end) on the registers. The next op record
@@ -556,37 +314,27 @@ __device__ __forceinline__ void run_ops(float2 (&v)[16], const DevOp *ops, uint3
     DevOp nxt = ld_words(ops + o);
     while (o < end) {
         const DevOp op = nxt;
-        const uint32_t step = (op.type == OP_DSET) ? 1u + op.b : 1u;
+        const uint32_t step = (op.type == OP_DSET) ? 1u + op.sb + op.b : 1u;
         if (o + step < end) nxt = ld_words(ops + o + step);
         if (op.type == OP_DSET) {
-            // diagonal set: register-bit factors per amplitude, all other
-            // factors folded into one per-thread complex factor
             float2 ft = make_float2(1.0f, 0.0f);
-            DevOp mn = ld_words(ops + o + 1);
-            for (uint32_t j = 1; j <= op.b; ++j) {
-                const DevOp mm = mn;
-                if (j < op.b) mn = ld_words(ops + o + j + 1);
-                if (mm.la == LOC_REG) {
-                    op_diag(v, mm, tl, base);
-                } else {
-                    const uint32_t bit = (mm.la == LOC_THREAD) ? ((tl >> mm.a) & 1u)
-                                                               : ((uint32_t)(base >> mm.a) & 1u);
-                    const float2 f = bit ? make_float2(mm.m[2], mm.m[3])
-                                         : make_float2(mm.m[0], mm.m[1]);
-                    ft = cmul(f, ft);
-                }
+            const uint32_t m0 = o + 1 + op.sb;
+            for (uint32_t j = 0; j < op.b; ++j) {
+                const DevOp mm = ld_words(ops + m0 + j);
+                ft = dset_fold(ft, opbit_tg(mm.la, mm.a, tl, base), opc(ops, m0 + j, 0),
+                               opc(ops, m0 + j, 1));
             }
-            #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = cmul(ft, v[k]);
+            if (op.sb)
+                dset_apply(v, ops + o + 1, true, ft, op.b != 0);
+            else
+                dset_apply(v, ops, false, ft, true);
         } else {
-            run_op(v, op, tl, base);
+            run_op(v, op, ops, o, tl, base);
         }
         o += step;
     }
 }
 
-// One-phase passes: no LDS, 256-thread workgroups (a tile is split over
-// several workgroups since no data crosses threads), high occupancy.
 template <int M>
 __global__ __launch_bounds__((1 << (M - 4)) < 256 ? (1 << (M - 4)) : 256)
 void pass_kernel_flat(const PassDesc *__restrict__ descs, uint32_t n_descs, uint32_t n,

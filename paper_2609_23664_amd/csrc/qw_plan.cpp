@@ -16,6 +16,8 @@
 // the direct path therefore execute the same arithmetic on the same values
 // as long as both cut the gate list at the same prefix boundary.
 #include <algorithm>
+#include <array>
+#include <complex>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -343,7 +345,8 @@ uint32_t pad_high(int m, uint32_t R) {
 // phase, an op whose target bit is a register or lane bit runs without any
 // data exchange; moving to a layout with other wave bits costs one LDS
 // exchange. Greedy: ops are taken in order, a blocked op blocks its bits.
-void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vector<int> &unit_len) {
+void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vector<int> &unit_len,
+                 const std::vector<std::array<double, 8>> &md_in) {
     // units: a single op, or an OP_DSET header with its members
     std::vector<size_t> ustart;
     {
@@ -458,18 +461,56 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
             dp.lds_off[kk] = lds_swizzle(l) << 3;
         }
         dp.op_begin = (uint16_t)out.size();
-        for (int ui : phase_ops[ph])
+        auto slot_of = [&](int b) -> int {
+            for (int s2 = 0; s2 < kRegBits; ++s2)
+                if (reg[s2] == b) return s2;
+            return -1;
+        };
+        for (int ui : phase_ops[ph]) {
+        if (lops_in[ustart[ui]].type == OP_DSET) {
+            // register-bit members -> 16-entry FP64 product table; the
+            // others stay members (thread or global bit)
+            std::complex<double> tab[16];
+            for (auto &t : tab) t = 1.0;
+            bool has_tab = false;
+            std::vector<DevOp> rest;
+            for (int uj = 1; uj < unit_len[ui]; ++uj) {
+                DevOp o = lops_in[ustart[ui] + uj];
+                const auto &md = md_in[ustart[ui] + uj];
+                const int sl = (o.la != LOC_GLOBAL) ? slot_of(o.a) : -1;
+                if (sl >= 0) {
+                    const std::complex<double> d0(md[0], md[1]), d1(md[2], md[3]);
+                    for (int kk = 0; kk < 16; ++kk) tab[kk] *= ((kk >> sl) & 1) ? d1 : d0;
+                    has_tab = true;
+                } else {
+                    if (o.la != LOC_GLOBAL) {
+                        o.la = LOC_THREAD;
+                        o.sa = 0;
+                    }
+                    rest.push_back(o);
+                }
+            }
+            DevOp hd = lops_in[ustart[ui]];
+            hd.b = (uint8_t)rest.size();
+            hd.sb = has_tab ? 4 : 0;
+            out.push_back(hd);
+            if (has_tab) {
+                for (int r = 0; r < 4; ++r) {
+                    DevOp t{};
+                    t.type = OP_DTAB;
+                    t.la = t.lb = LOC_GLOBAL;
+                    for (int e = 0; e < 4; ++e) {
+                        t.m[2 * e] = (float)tab[4 * r + e].real();
+                        t.m[2 * e + 1] = (float)tab[4 * r + e].imag();
+                    }
+                    out.push_back(t);
+                }
+            }
+            for (const DevOp &o : rest) out.push_back(o);
+            continue;
+        }
         for (int uj = 0; uj < unit_len[ui]; ++uj) {
             DevOp o = lops_in[ustart[ui] + uj];
-            if (o.type == OP_DSET) {
-                out.push_back(o);
-                continue;
-            }
-            auto slot_of = [&](int b) -> int {
-                for (int s2 = 0; s2 < kRegBits; ++s2)
-                    if (reg[s2] == b) return s2;
-                return -1;
-            };
             const bool target_op =
                 (o.type == OP_U || o.type == OP_PERM || o.type == OP_CX || o.type == OP_UR);
             if (o.la != LOC_GLOBAL) {
@@ -491,6 +532,7 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
                 o.sb = (uint8_t)(sl >= 0 ? sl : 0);
             }
             out.push_back(o);
+        }
         }
         dp.op_end = (uint16_t)out.size();
         p.dev_phases.push_back(dp);
@@ -542,6 +584,7 @@ IoRec make_iorec(int m, uint64_t lmask, const DevPhase &ph) {
 void lower_pass(int n, int m, HostPass &p) {
     (void)n;
     std::vector<DevOp> lops;
+    std::vector<std::array<double, 8>> lmd;  // FP64 entries, parallel to lops
     std::vector<int> unit_len;
     auto lower_one = [&](const HostOp &h) {
         DevOp o{};
@@ -570,15 +613,24 @@ void lower_pass(int n, int m, HostPass &p) {
             hd.lb = LOC_GLOBAL;
             hd.b = (uint8_t)h.members.size();
             lops.push_back(hd);
-            for (const HostOp &mm : h.members) lops.push_back(lower_one(mm));
+            lmd.push_back({});
+            for (const HostOp &mm : h.members) {
+                lops.push_back(lower_one(mm));
+                std::array<double, 8> md;
+                for (int k = 0; k < 8; ++k) md[k] = mm.m[k];
+                lmd.push_back(md);
+            }
             unit_len.push_back(1 + (int)h.members.size());
         } else {
             lops.push_back(lower_one(h));
+            std::array<double, 8> md;
+            for (int k = 0; k < 8; ++k) md[k] = h.m[k];
+            lmd.push_back(md);
             unit_len.push_back(1);
         }
     }
     if (m >= kMinTileBits) {
-        plan_phases(m, p, lops, unit_len);
+        plan_phases(m, p, lops, unit_len, lmd);
         p.io_in = make_iorec(m, p.local_mask, p.dev_phases.front());
         p.io_out = make_iorec(m, p.local_mask, p.dev_phases.back());
     } else {

@@ -1,0 +1,131 @@
+"""Generated (run-time compiled) pass kernels against the interpreted ones.
+
+Both forms run the same tile operations with the same rounding, so the states
+must be bit-identical; the oracle bar is checked too. Every case prints its
+name before running.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+FID_TOL = 1e-6
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2609_23664_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    import torch
+    assert torch.cuda.is_available()
+    c = B.Ctx(0)
+    yield c
+    c.set_option(B.QW_OPT_JIT, 1)
+    c.sync()
+
+
+def _random_gates(n, g, count, renorm=0.0):
+    names1 = ["X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P"]
+    gates = []
+    for _ in range(count):
+        if g.random() < 0.6:
+            gates.append((names1[g.integers(len(names1))], (int(g.integers(n)),), float(g.uniform(0, 6.3))))
+        else:
+            a, b = g.choice(n, 2, replace=False)
+            gates.append((("CNOT", "CZ")[int(g.integers(2))], (int(a), int(b)), 0.0))
+        if g.random() < renorm:
+            gates.append(("RENORM", (), 0.0))
+    return gates
+
+
+def _both(B, ctx, n, gates, slots=1):
+    out = []
+    for jit in (0, 1):
+        ctx.set_option(B.QW_OPT_JIT, jit)
+        st = B.State(ctx, n, slots)
+        st.apply(slots - 1, gates)
+        out.append(st.host(slots - 1))
+        st.free()
+    ctx.set_option(B.QW_OPT_JIT, 1)
+    return out
+
+
+@pytest.mark.parametrize("n,tile", [(10, 14), (12, 11), (15, 14), (16, 12), (18, 14), (20, 14)])
+def test_generated_equals_interpreted_random(ctx, B, n, tile):
+    say("jit vs interpreter random", n, tile)
+    g = np.random.default_rng(5000 + n)
+    gates = _random_gates(n, g, 160, renorm=0.02)
+    ctx.set_option(B.QW_OPT_TILE_BITS, tile)
+    try:
+        a, b = _both(B, ctx, n, gates)
+    finally:
+        ctx.set_option(B.QW_OPT_TILE_BITS, 14)
+    assert np.array_equal(a, b)
+    ref = oracle.simulate(n, gates)
+    assert 1 - oracle.fidelity(b.astype(np.complex128), ref) <= FID_TOL
+
+
+def test_generated_equals_interpreted_hea_22q(ctx, B):
+    say("jit vs interpreter hea 22q")
+    w = gen.small_vqe(22, 3, 2, 1, 1, seed=91)
+    a, b = _both(B, ctx, 22, w.task_gates(0))
+    assert np.array_equal(a, b)
+    ref = oracle.simulate(22, w.task_gates(0))
+    assert 1 - oracle.fidelity(b.astype(np.complex128), ref) <= FID_TOL
+
+
+def test_generated_batch_mixed_structures(ctx, B):
+    """Tasks of two different suffix structures in one batch: one launch per
+    structure, each task bitwise equal to its interpreted result."""
+    say("jit mixed batch 16q")
+    n = 16
+    w1 = gen.small_vqe(n, 2, 1, 3, 4, seed=5)
+    g = np.random.default_rng(11)
+    other = _random_gates(n, g, 60)
+    sufs = list(w1.suffixes) + [other, other]
+    res = []
+    for jit in (0, 1):
+        ctx.set_option(B.QW_OPT_JIT, jit)
+        st = B.State(ctx, n, 1 + len(sufs))
+        st.apply(0, w1.prefix)
+        snap = st.snapshot(0, bytes(32), B.QW_SNAP_COPY)
+        B.run_suffix_batch(ctx, [snap] * len(sufs), sufs, st, list(range(1, 1 + len(sufs))))
+        res.append([st.host(1 + t) for t in range(len(sufs))])
+        snap.free()
+        st.free()
+    ctx.set_option(B.QW_OPT_JIT, 1)
+    base = oracle.simulate(n, w1.prefix)
+    for t in range(len(sufs)):
+        assert np.array_equal(res[0][t], res[1][t]), t
+        ref = oracle.apply_gates(base.copy(), n, sufs[t])
+        assert 1 - oracle.fidelity(res[1][t].astype(np.complex128), ref) <= FID_TOL
+
+
+def test_precompile_then_run(ctx, B):
+    say("jit precompile 14q")
+    n = 14
+    g = np.random.default_rng(3)
+    gates = _random_gates(n, g, 80)
+    B.jit_precompile(n, gates)
+    before = B.jit_stats()
+    st = B.State(ctx, n, 1)
+    st.apply(0, gates)
+    after = B.jit_stats()
+    assert after["compiled"] == before["compiled"]   # nothing new to compile
+    ref = oracle.simulate(n, gates)
+    assert 1 - oracle.fidelity(st.host(0).astype(np.complex128), ref) <= FID_TOL
+    st.free()

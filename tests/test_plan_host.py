@@ -14,7 +14,7 @@ from paper_2609_23664_amd import binding as B
 from workloads import gen
 
 LOC_REG, LOC_THREAD, LOC_GLOBAL, LOC_LANE = 0, 1, 2, 3
-OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ, OP_UR, OP_DSET = 1, 2, 3, 4, 5, 6, 7
+OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ, OP_UR, OP_DSET, OP_DTAB = 1, 2, 3, 4, 5, 6, 7, 8
 
 
 def _local_bits(mask):
@@ -29,13 +29,32 @@ def interpret(n, plan, psi):
         assert len(lb) == plan["tile_bits"]
         if p["scale_in"]:
             psi /= np.sqrt(np.vdot(psi, psi).real)
-        for op in p["ops"]:
+        phase_of = {}
+        for f in p["phases"]:
+            for j in range(f["op_begin"], f["op_end"]):
+                phase_of[j] = f
+        for j, op in enumerate(p["ops"]):
             def gbit(loc, b):
                 return b if loc == LOC_GLOBAL else lb[b]
             m = op["m"]
             t = op["type"]
+            if t == OP_DTAB:
+                continue          # read with its OP_DSET header
             if t == OP_DSET:
-                continue          # its diagonal members follow
+                if op["sb"]:
+                    # register table: entry k = product of the register-bit
+                    # factors for register index k of the phase
+                    reg = phase_of[j]["reg"]
+                    tab = []
+                    for r in range(op["sb"]):
+                        mm = p["ops"][j + 1 + r]["m"]
+                        assert p["ops"][j + 1 + r]["type"] == OP_DTAB
+                        tab += [mm[2 * e] + 1j * mm[2 * e + 1] for e in range(4)]
+                    k = np.zeros(1 << n, dtype=np.int64)
+                    for s_, rb in enumerate(reg):
+                        k |= ((idx >> lb[rb]) & 1) << s_
+                    psi *= np.asarray(tab)[k]
+                continue          # thread/global members follow as OP_DIAG
             if t in (OP_U, OP_PERM, OP_UR):
                 assert op["la"] != LOC_GLOBAL
                 g = gbit(op["la"], op["a"])
