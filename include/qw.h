@@ -275,6 +275,11 @@ int qw_plan_describe(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
 int qw_jit_precompile(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
                       uint32_t tile_bits, char *log, uint64_t cap);
 
+/* Same for the generated expectation reducers of the Pauli terms (x, z)
+ * (the term groups and register phases that qw_expect_pauli would use). */
+int qw_jit_precompile_terms(uint32_t n_qubits, const uint64_t *x, const uint64_t *z,
+                            uint32_t n_terms, uint32_t tile_bits, char *log, uint64_t cap);
+
 /* Generated-kernel counters of this process: kernels compiled, kernels taken
  * from the disk cache, and seconds spent compiling. Any pointer may be NULL. */
 int qw_jit_stats(uint64_t *compiled, uint64_t *disk_hits, double *compile_seconds);

@@ -50,7 +50,7 @@ EXPORTED = (
     "qw_state_reset", "qw_state_slot_ptr", "qw_apply_prefix", "qw_snapshot",
     "qw_snapshot_free", "qw_snapshot_info", "qw_run_suffix_batch",
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
-    "qw_jit_precompile", "qw_jit_stats", "qw_version",
+    "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_stats", "qw_version",
 )
 
 
@@ -136,6 +136,8 @@ def lib() -> ctypes.CDLL:
         "qw_legality_check": ([ctypes.POINTER(QwArtifact), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_plan_describe": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
         "qw_jit_precompile": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
+        "qw_jit_precompile_terms": ([u32, ctypes.POINTER(u64), ctypes.POINTER(u64), u32, u32,
+                                     ctypes.c_char_p, u64], i32),
         "qw_jit_stats": ([ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)],
                          i32),
         "qw_version": ([], ctypes.c_char_p),
@@ -213,6 +215,19 @@ def jit_precompile(n: int, gates, tile_bits: int = 14) -> None:
     cap = 1 << 20
     buf = ctypes.create_string_buffer(cap)
     rc = lib().qw_jit_precompile(n, arr, len(gates), tile_bits, buf, cap)
+    if rc != QW_OK:
+        raise QwError(rc, buf.value.decode(errors="replace"))
+
+
+def jit_precompile_terms(n: int, terms, tile_bits: int = 14) -> None:
+    """Host-only: compile the generated expectation reducers of the Pauli
+    terms [(coeff, x_mask, z_mask), ...] into the caches (no GPU needed)."""
+    nt = len(terms)
+    xs = (ctypes.c_uint64 * max(1, nt))(*[int(t[1]) for t in terms])
+    zs = (ctypes.c_uint64 * max(1, nt))(*[int(t[2]) for t in terms])
+    cap = 1 << 20
+    buf = ctypes.create_string_buffer(cap)
+    rc = lib().qw_jit_precompile_terms(n, xs, zs, nt, tile_bits, buf, cap)
     if rc != QW_OK:
         raise QwError(rc, buf.value.decode(errors="replace"))
 

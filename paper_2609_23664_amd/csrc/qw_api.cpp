@@ -499,6 +499,10 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
             c_off[g] = L.take(rplans[g].cols.size() * sizeof(uint32_t));
         }
     }
+    const bool use_jit = ctx->jit && !small;
+    std::vector<size_t> tb_off(groups.size(), 0);
+    if (use_jit)
+        for (size_t g = 0; g < groups.size(); ++g) tb_off[g] = L.take((size_t)tiles * sizeof(uint32_t));
     const size_t coeff_off = L.take(n_terms * sizeof(double));
     const size_t n_desc = small ? ns : ns * groups.size();
     const size_t desc_off = L.take(n_desc * (small ? sizeof(ReduceDescSmall) : sizeof(ReduceDesc)));
@@ -540,9 +544,15 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
             std::memcpy(blob.data() + p_off[g], rp.phases.data(), rp.phases.size() * sizeof(RedPhase));
             std::memcpy(blob.data() + c_off[g], rp.cols.data(), rp.cols.size() * sizeof(uint32_t));
         }
-        size_t di = 0;
+        for (size_t g = 0; g < groups.size() && use_jit; ++g) {
+            uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + tb_off[g]);
+            const uint64_t nl = full & ~groups[g].local_mask;
+            for (uint32_t ti = 0; ti < tiles; ++ti) tb[ti] = (uint32_t)pdep64(ti, nl);
+        }
         for (uint32_t s = 0; s < ns; ++s) {
             for (size_t g = 0; g < groups.size(); ++g) {
+                // generated reducers: one launch per group, descriptors [group][slot]
+                const size_t di = use_jit ? g * ns + s : (size_t)s * groups.size() + g;
                 ReduceDesc d{};
                 d.psi = slots[s];
                 d.terms = reinterpret_cast<const TermDev *>(dbase + t_off[g]);
@@ -553,14 +563,34 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
                 d.n_phases = (uint32_t)rplans[g].phases.size();
                 d.n_terms = (uint32_t)rplans[g].terms.size();
                 d.n_terms_total = n_terms;
+                d.tile_base = use_jit ? reinterpret_cast<const uint32_t *>(dbase + tb_off[g]) : nullptr;
                 std::memcpy(blob.data() + desc_off + di * sizeof(ReduceDesc), &d, sizeof d);
-                ++di;
             }
         }
     }
+    std::vector<const JitKernel *> rk;
+    if (use_jit) {
+        std::vector<JitReq> reqs(groups.size());
+        for (size_t g = 0; g < groups.size(); ++g) {
+            reqs[g].key = jit_reduce_key((int)n, m, groups[g], rplans[g]);
+            reqs[g].group = &groups[g];
+            reqs[g].rplan = &rplans[g];
+            reqs[g].n = (int)n;
+            reqs[g].m = m;
+        }
+        const std::string err = jit_get(ctx->device, reqs, &rk);
+        if (!err.empty()) return fail(ctx, QW_E_HIP, err);
+    }
     rc = upload(ctx, blob);
     if (rc) return rc;
-    {
+    if (use_jit) {
+        const ReduceDesc *dd = reinterpret_cast<const ReduceDesc *>(dbase + desc_off);
+        for (size_t g = 0; g < groups.size(); ++g) {
+            ProfScope ps(ctx, 1, (double)ns * (double)(8ull << n));
+            hipError_t er = jit_launch_reduce(ctx->stream, *rk[g], dd + g * ns, ns, tiles, ctx->n_cu);
+            if (er != hipSuccess) return hip_fail(ctx, er, "generated reduce launch");
+        }
+    } else {
         ProfScope ps(ctx, 1, (double)ns * groups.size() * (double)(8ull << n));
         hipError_t er = small
             ? launch_reduce_small(ctx->stream, reinterpret_cast<const ReduceDescSmall *>(dbase + desc_off),
@@ -983,6 +1013,48 @@ int qw_jit_precompile(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32
         reqs.push_back(std::move(r));
     }
     e = jit_precompile(reqs);
+    if (!e.empty()) {
+        put(e);
+        return QW_E_HIP;
+    }
+    return QW_OK;
+}
+
+int qw_jit_precompile_terms(uint32_t n, const uint64_t *x, const uint64_t *z, uint32_t n_terms,
+                            uint32_t tile_bits, char *log, uint64_t cap) {
+    auto put = [&](const std::string &msg) {
+        if (log && cap) {
+            size_t k = std::min<size_t>(msg.size(), cap - 1);
+            std::memcpy(log, msg.data(), k);
+            log[k] = 0;
+        }
+    };
+    put("");
+    if (n < 1 || n > (uint32_t)kMaxQubits || tile_bits < (uint32_t)kMinTileBits ||
+        tile_bits > (uint32_t)kMaxTileBits || (n_terms && (!x || !z))) {
+        put("bad arguments");
+        return QW_E_INVALID_ARG;
+    }
+    const uint64_t full = (1ull << n) - 1;
+    for (uint32_t j = 0; j < n_terms; ++j)
+        if ((x[j] & ~full) || (z[j] & ~full)) {
+            put("Pauli mask has bits >= n");
+            return QW_E_INVALID_ARG;
+        }
+    const int m = tile_bits_for((int)n, (int)tile_bits);
+    if (m < kMinTileBits || n_terms == 0) return QW_OK;
+    std::vector<TermGroup> groups = group_terms((int)n, m, x, n_terms);
+    std::vector<RedPlan> rplans;
+    for (const TermGroup &g : groups) rplans.push_back(plan_reduce_group((int)n, m, g, x, z));
+    std::vector<JitReq> reqs(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        reqs[g].key = jit_reduce_key((int)n, m, groups[g], rplans[g]);
+        reqs[g].group = &groups[g];
+        reqs[g].rplan = &rplans[g];
+        reqs[g].n = (int)n;
+        reqs[g].m = m;
+    }
+    const std::string e = jit_precompile(reqs);
     if (!e.empty()) {
         put(e);
         return QW_E_HIP;

@@ -178,6 +178,7 @@ struct alignas(16) ReduceDesc {
     const RedPhase *phases;
     const uint32_t *cols;  // group-local column -> column of the partial array
     double *part;          // [tiles][n_terms_total] of this slot
+    const uint32_t *tile_base;  // global index of local index 0, per tile
     uint64_t local_mask;
     uint32_t n_phases;
     uint32_t n_terms;      // terms of this group

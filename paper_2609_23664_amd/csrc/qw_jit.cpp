@@ -49,6 +49,8 @@ std::string hex(uint64_t v) {
     return b;
 }
 
+uint32_t swz_host(uint32_t l) { return l ^ (((l >> 5) ^ (l >> 10)) & 31u); }
+
 // Lane part (amplitude units) and wave bit positions of an I/O layout.
 void emit_io_helpers(Gen &g, const char *name, const IoRec &r, int m) {
     g << "__device__ __forceinline__ uint32_t " << name << "_lane(uint32_t lane) {\n";
@@ -376,6 +378,186 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
     return g.o.str();
 }
 
+
+// ---------------------------------------------------------------- reducer
+std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp) {
+    std::string k = "R";
+    auto put = [&](uint64_t v, int bytes) {
+        for (int i = 0; i < bytes; ++i) k.push_back((char)((v >> (8 * i)) & 0xFF));
+    };
+    put((uint64_t)n, 1);
+    put((uint64_t)m, 1);
+    put(g.local_mask, 8);
+    put(rp.phases.size(), 2);
+    for (const RedPhase &f : rp.phases) {
+        for (int s = 0; s < 4; ++s) put(f.reg[s], 1);
+        put(f.t_begin, 2);
+        put(f.t_end, 2);
+        put(f.diag, 1);
+    }
+    put(rp.terms.size(), 2);
+    for (const TermDev &t : rp.terms) {
+        put(t.xr, 1);
+        put(t.neg, 1);
+        put(t.odd, 1);
+        put(t.smask, 2);
+        put(t.col, 2);
+        put(t.zt, 4);
+        put(t.zg, 8);
+    }
+    for (uint32_t c : rp.cols) put(c, 4);
+    return k;
+}
+
+std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &rp) {
+    std::ostringstream o;
+    const int T = 1 << (m - 4);
+    const size_t NT = rp.cols.size();
+    bool any_lds = false;
+    for (const RedPhase &f : rp.phases) any_lds |= !f.diag;
+    o << "// generated expectation reducer: " << n << " qubits, tile bits " << m << ", " << NT
+      << " terms, " << rp.phases.size() << " phases\n";
+    o << "#include \"qw_dev.h\"\nusing namespace qw;\n";
+    o << "constexpr int M = " << m << ", T = " << T << ", W = T / 64, NT = " << NT << ";\n";
+    // I/O layout of the tile: register slots = local bits {0, 7, 8, 9}
+    std::vector<int> gpos;
+    for (int q = 0; q < 64; ++q)
+        if ((g.local_mask >> q) & 1ull) gpos.push_back(q);
+    auto gbit = [&](int l) { return 1ull << gpos[l]; };
+    const int io_reg[4] = {0, 7, 8, 9};
+    o << "__device__ __forceinline__ uint32_t io_lane(uint32_t lane) {\n"
+      << "    return (((lane & 7u) << 1) | (((lane >> 3) & 1u) << " << gpos[4] << ") | (((lane >> 4) & 1u) << "
+      << gpos[5] << ") | (((lane >> 5) & 1u) << " << gpos[6] << ")) * 8u;\n}\n";
+    {
+        // wave bits: local bits >= 10 (not registers, above the lanes 1..6)
+        o << "__device__ __forceinline__ uint64_t io_wave(uint32_t w) {\n    return 0ull";
+        for (int j = 0; j < m - 10; ++j) o << " | ((uint64_t)((w >> " << j << ") & 1u) * " << hex(gbit(10 + j)) << ")";
+        o << ";\n}\n";
+    }
+    o << "__device__ __forceinline__ void load_in(float2 (&v)[16], const void *src, uint64_t ub, uint32_t lb) {\n";
+    for (int k2 = 0; k2 < 8; ++k2) {
+        uint64_t off = 0;
+        for (int s = 1; s < 4; ++s)
+            if (((2 * k2) >> s) & 1) off |= gbit(io_reg[s]);
+        o << "    { const float4 q = buf_ld4(src, ub + " << hex(off) << ", lb); v[" << 2 * k2
+          << "] = make_float2(q.x, q.y); v[" << 2 * k2 + 1 << "] = make_float2(q.z, q.w); }\n";
+    }
+    o << "}\n";
+    o << "__device__ __forceinline__ void tile(float2 (&v)[16], uint32_t tid, uint32_t lane, uint64_t base, "
+         "char *lb, double *red) {\n";
+    o << "    const uint32_t wave = tid >> 6;\n    (void)lb; (void)base;\n";
+    const uint32_t io_tl_regs[4] = {0, 7, 8, 9};
+    o << "    const uint32_t tlio = thread_local_index(tid, " << io_tl_regs[0] << "u, " << io_tl_regs[1] << "u, "
+      << io_tl_regs[2] << "u, " << io_tl_regs[3] << "u);\n";
+    if (any_lds) {
+        o << "    {\n        const uint32_t s8 = swz(tlio) << 3;\n";
+        for (int k = 0; k < 16; ++k) {
+            uint32_t l = 0;
+            for (int s = 0; s < 4; ++s)
+                if ((k >> s) & 1) l |= 1u << io_reg[s];
+            o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (swz_host(l) << 3) << "u)) = v[" << k << "];\n";
+        }
+        o << "    }\n    lds_barrier();\n";
+    }
+    for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
+        const RedPhase &f = rp.phases[pi];
+        o << "    {   // phase " << pi << (f.diag ? " (diagonal terms, I/O layout)" : "") << "\n";
+        o << "        const uint32_t tl = thread_local_index(tid, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
+          << "u, " << (int)f.reg[2] << "u, " << (int)f.reg[3] << "u); (void)tl;\n";
+        if (!f.diag) {
+            o << "        const uint32_t t8 = swz(tl) << 3;\n";
+            for (int k = 0; k < 16; ++k) {
+                uint32_t l = 0;
+                for (int s = 0; s < 4; ++s)
+                    if ((k >> s) & 1) l |= 1u << f.reg[s];
+                o << "        v[" << k << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ " << (swz_host(l) << 3)
+                  << "u));\n";
+            }
+        } else {
+            o << "        float pr[16];\n        #pragma unroll\n        for (int k = 0; k < 16; ++k) pr[k] = "
+                 "fmaf(v[k].x, v[k].x, v[k].y * v[k].y);\n";
+        }
+        for (uint32_t j0 = f.t_begin; j0 < f.t_end; j0 += 8) {
+            const uint32_t nb = std::min<uint32_t>(8u, f.t_end - j0);
+            o << "        {\n            float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
+            for (uint32_t j = 0; j < nb; ++j) {
+                const TermDev &t = rp.terms[j0 + j];
+                o << "            {\n";
+                if (f.diag)
+                    o << "                float a = diag_sum(pr, " << t.smask << "u);\n";
+                else
+                    o << "                float a = pair_sum<" << (int)t.xr << ", " << (t.odd ? "true" : "false")
+                      << ">(v, " << t.smask << "u);\n                a *= 2.0f;\n";
+                o << "                const uint32_t par = (" << (int)t.neg << "u";
+                if (t.zt) o << " ^ (uint32_t)__popc(tl & " << t.zt << "u)";
+                if (t.zg) o << " ^ (uint32_t)__popcll(base & " << hex(t.zg) << ")";
+                o << ") & 1u;\n                if (par) a = -a;\n";
+                o << "                #pragma unroll\n                for (int i = 7; i > 0; --i) q[i] = q[i - 1];\n"
+                     "                q[0] = a;\n            }\n";
+            }
+            o << "            const double h = wave_reduce8(q, lane);\n";
+            o << "            if (lane < 8u) {\n                const uint32_t pos = 4u * (lane & 1u) + 2u * ((lane >> 1) & 1u) + "
+                 "((lane >> 2) & 1u);\n";
+            for (uint32_t j = 0; j < nb; ++j)
+                o << "                if (pos == " << nb - 1 - j << "u) red[wave * NT + " << rp.terms[j0 + j].col
+                  << "] = h;\n";
+            o << "            }\n        }\n";
+        }
+        o << "    }\n";
+    }
+    o << "}\n";
+    o << "__device__ const uint32_t kCols[NT] = {";
+    for (size_t c = 0; c < NT; ++c) o << (c ? ", " : "") << rp.cols[c] << "u";
+    o << "};\n";
+    o << "extern \"C\" __global__ __launch_bounds__(T) void qw_reduce(const ReduceDesc *__restrict__ descs, "
+         "uint32_t n_descs, uint32_t items) {\n"
+         "    __shared__ float2 lds[1 << M];\n"
+         "    __shared__ double red[W * NT];\n"
+         "    const uint32_t w = blockIdx.x, x = w & 7u, j = w >> 3, wpx = gridDim.x >> 3;\n"
+         "    const uint32_t per = (items + 7u) >> 3;\n"
+         "    const uint32_t first = x * per;\n"
+         "    const uint32_t last = (first + per < items) ? first + per : items;\n"
+         "    uint32_t item = first + j;\n"
+         "    if (item >= last) return;\n"
+         "    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = uni(tid >> 6);\n"
+         "    const uint64_t wi = io_wave(wave);\n"
+         "    const uint32_t li = io_lane(lane);\n"
+         "    char *lb = reinterpret_cast<char *>(lds);\n"
+         "    float2 nv[16];\n"
+         "    {\n"
+         "        const ReduceDesc *d0 = descs + item % n_descs;\n"
+         "        load_in(nv, ldu(&d0->psi), uni(ldu(ldu(&d0->tile_base) + item / n_descs)) | wi, li);\n"
+         "    }\n"
+         "    while (true) {\n"
+         "        float2 v[16];\n"
+         "        #pragma unroll\n"
+         "        for (int k = 0; k < 16; ++k) v[k] = nv[k];\n"
+         "        const uint32_t p = item % n_descs, tl_ = item / n_descs;\n"
+         "        const ReduceDesc *d = descs + p;\n"
+         "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tl_));\n"
+         "        const uint32_t next = item + wpx;\n"
+         "        const bool has_next = next < last;\n"
+         "        if (has_next) {\n"
+         "            const ReduceDesc *dn = descs + next % n_descs;\n"
+         "            load_in(nv, ldu(&dn->psi), uni(ldu(ldu(&dn->tile_base) + next / n_descs)) | wi, li);\n"
+         "        }\n"
+         "        __syncthreads();  // the previous tile's LDS and partial reads are done\n"
+         "        tile(v, tid, lane, base, lb, red);\n"
+         "        __syncthreads();\n"
+         "        double *part = ldu(&d->part);\n"
+         "        const uint32_t ntt = ldu(&d->n_terms_total);\n"
+         "        for (uint32_t c = tid; c < (uint32_t)NT; c += T) {\n"
+         "            double s = 0.0;\n"
+         "            for (int ww = 0; ww < W; ++ww) s += red[ww * NT + c];\n"
+         "            gout<double>(part)[(uint64_t)tl_ * ntt + kCols[c]] = s;\n"
+         "        }\n"
+         "        if (!has_next) break;\n"
+         "        item = next;\n"
+         "    }\n"
+         "}\n";
+    return o.str();
+}
+
 // ---------------------------------------------------------------- compile
 namespace {
 
@@ -509,7 +691,8 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
     const char *dump = std::getenv("QW_JIT_DUMP");  // debugging: write sources to this folder
     for (size_t q = 0; q < need.size(); ++q) {
         const JitReq &r = ks[need[q]];
-        srcs[q] = jit_pass_source(r.n, r.m, *r.pass, r.use_lds);
+        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds)
+                         : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
         if (dump && *dump) {
             std::ofstream f(cache_path(dump, srcs[q]) + ".hip");
             f << srcs[q];
@@ -583,12 +766,12 @@ std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<con
         }
         const std::vector<char> &code = R.code[ks[i].key];
         const int m = ks[i].m;
-        const bool use_lds = ks[i].use_lds;
+        const bool use_lds = ks[i].use_lds || !ks[i].pass;
         hipModule_t mod = nullptr;
         hipError_t e = hipModuleLoadData(&mod, code.data());
         if (e != hipSuccess) return std::string("hipModuleLoadData: ") + hipGetErrorString(e);
         auto k = std::make_unique<JitKernel>();
-        e = hipModuleGetFunction(&k->fn, mod, "qw_pass");
+        e = hipModuleGetFunction(&k->fn, mod, ks[i].pass ? "qw_pass" : "qw_reduce");
         if (e != hipSuccess) return std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
         const int T = 1 << (m - 4);
         k->use_lds = use_lds;
@@ -623,6 +806,18 @@ hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs,
     }
     uint32_t items_arg = items;
     void *args[] = {&descs, &n_descs, &items_arg, &remap};
+    return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
+}
+
+hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDesc *descs,
+                             uint32_t n_descs, uint32_t tiles, uint32_t cu_count) {
+    const uint32_t items = n_descs * tiles;
+    const uint32_t full = cu_count * (uint32_t)k.blocks_per_cu;
+    const uint32_t want = ((items + 7u) / 8u) * 8u;
+    uint32_t grid = want < full ? want : (full / 8u) * 8u;
+    if (grid < 8u) grid = 8u;
+    uint32_t items_arg = items;
+    void *args[] = {&descs, &n_descs, &items_arg};
     return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
 }
 

@@ -36,13 +36,27 @@ struct JitKernel {
     int blocks_per_cu = 1; // resident workgroups per CU (LDS form)
 };
 
-// One requested kernel: its key and the pass it was computed from.
+// Exact structural key and source of the generated expectation reducer of
+// one term group (its terms, register phases and columns are fixed at
+// compile time; the state slot, partial-sum array and tile table are read at
+// run time).
+std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp);
+std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &rp);
+
+// One requested kernel: its key and what it was computed from (a pass, or a
+// reducer term group).
 struct JitReq {
     std::string key;
     const HostPass *pass = nullptr;
+    const TermGroup *group = nullptr;
+    const RedPlan *rplan = nullptr;
     int n = 0, m = 0;
-    bool use_lds = false;
+    bool use_lds = false;  // pass kernels: persistent LDS form
 };
+
+// Launch a generated reducer over n_descs descriptors of its term group.
+hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDesc *descs,
+                             uint32_t n_descs, uint32_t tiles, uint32_t cu_count);
 
 // Compiled kernels for the requests on `device`: loaded from memory, from
 // the disk cache, or compiled (in parallel). Returns "" or an error message.

@@ -589,27 +589,6 @@ __global__ __launch_bounds__(64) void reduce_small_kernel(const ReduceDescSmall 
     }
 }
 
-// Sum over one thread's register pairs of sign_k * Re or Im of
-// conj(v[k ^ X]) v[k]; each unordered pair is counted once (the caller
-// doubles it). FP32 products and an FP32 sum over at most 16 values.
-template <int X, bool ODD>
-__device__ __forceinline__ float pair_sum(const float2 (&v)[16], uint32_t smask) {
-    static_assert(X > 0 && X < 16, "off-diagonal register mask");
-    constexpr int lead = (X & 8) ? 8 : (X & 4) ? 4 : (X & 2) ? 2 : 1;
-    float acc = 0.0f;
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k & lead) continue;
-        const float2 a = v[k], b = v[k ^ X];
-        float t;
-        if constexpr (ODD) t = fmaf(b.x, a.y, -(b.y * a.x));
-        else t = fmaf(b.x, a.x, b.y * a.y);
-        const float sg = ((smask >> k) & 1u) ? -1.0f : 1.0f;
-        acc = fmaf(sg, t, acc);
-    }
-    return acc;
-}
-
 template <bool ODD>
 __device__ __forceinline__ float pair_sum_x(uint32_t xr, const float2 (&v)[16], uint32_t smask) {
     switch (xr) {
@@ -629,51 +608,6 @@ __device__ __forceinline__ float pair_sum_x(uint32_t xr, const float2 (&v)[16], 
     case 14: return pair_sum<14, ODD>(v, smask);
     default: return pair_sum<15, ODD>(v, smask);
     }
-}
-
-// Signed sum of |v[k]|^2 (diagonal terms).
-__device__ __forceinline__ float diag_sum(const float (&pr)[16], uint32_t smask) {
-    float acc = 0.0f;
-    #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const float sg = ((smask >> k) & 1u) ? -1.0f : 1.0f;
-        acc = fmaf(sg, pr[k], acc);
-    }
-    return acc;
-}
-
-// Butterfly reduction of 8 per-lane partials (positions 0..7) across the
-// wave in FP64: after the xor 1/2/4 steps lane l holds position
-// 4(l&1) + 2((l>>1)&1) + ((l>>2)&1); xor 8/16/32 complete the wave sum.
-__device__ __forceinline__ double wave_reduce8(const float (&q)[8], uint32_t lane) {
-    double e[8];
-    #pragma unroll
-    for (int i = 0; i < 8; ++i) e[i] = (double)q[i];
-    const bool b0 = lane & 1u, b1 = lane & 2u, b2 = lane & 4u;
-    double f[4];
-    #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const double mine = b0 ? e[4 + i] : e[i];
-        const double other = b0 ? e[i] : e[4 + i];
-        f[i] = mine + __shfl_xor(other, 1, 64);
-    }
-    double g[2];
-    #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double mine = b1 ? f[2 + i] : f[i];
-        const double other = b1 ? f[i] : f[2 + i];
-        g[i] = mine + __shfl_xor(other, 2, 64);
-    }
-    double h;
-    {
-        const double mine = b2 ? g[1] : g[0];
-        const double other = b2 ? g[0] : g[1];
-        h = mine + __shfl_xor(other, 4, 64);
-    }
-    h += __shfl_xor(h, 8, 64);
-    h += __shfl_xor(h, 16, 64);
-    h += __shfl_xor(h, 32, 64);
-    return h;
 }
 
 

@@ -129,3 +129,29 @@ def test_precompile_then_run(ctx, B):
     ref = oracle.simulate(n, gates)
     assert 1 - oracle.fidelity(st.host(0).astype(np.complex128), ref) <= FID_TOL
     st.free()
+
+
+@pytest.mark.parametrize("n,tile", [(12, 10), (16, 14), (20, 13), (22, 14)])
+def test_generated_reducer_equals_interpreted(ctx, B, n, tile):
+    say("jit reducer vs interpreter", n, tile)
+    g = np.random.default_rng(7000 + n)
+    terms = gen.random_pauli_terms(g, n, 40) + gen.zz_terms(g, n, 12)
+    w = gen.small_vqe(n, 2, 1, 3, 4, seed=8 + n)
+    st = B.State(ctx, n, 3)
+    for t in range(3):
+        st.apply(t, w.task_gates(t))
+    ctx.set_option(B.QW_OPT_TILE_BITS, tile)
+    try:
+        res = []
+        for jit in (0, 1):
+            ctx.set_option(B.QW_OPT_JIT, jit)
+            res.append(np.asarray(st.expect(0, 3, terms)))
+    finally:
+        ctx.set_option(B.QW_OPT_JIT, 1)
+        ctx.set_option(B.QW_OPT_TILE_BITS, 14)
+    assert np.array_equal(res[0], res[1])
+    scale = sum(abs(t[0]) for t in terms)
+    for t in range(3):
+        ref = oracle.expect(oracle.simulate(n, w.task_gates(t)), n, terms)
+        assert abs(res[1][t] - ref) <= 1e-5 * scale
+    st.free()

@@ -44,3 +44,10 @@ def test_vqe_suffix_kernels_compile_and_cache():
     # same structure, other angles: no new kernels
     B.jit_precompile(24, w.suffixes[1])
     assert B.jit_stats()["compiled"] == s1["compiled"]
+
+
+@pytest.mark.parametrize("n,tile", [(12, 10), (24, 14)])
+def test_reducer_kernels_compile(n, tile):
+    g = np.random.default_rng(n)
+    terms = gen.random_pauli_terms(g, n, 30) + gen.zz_terms(g, n, 10)
+    B.jit_precompile_terms(n, terms, tile)
