@@ -33,14 +33,25 @@ enum OpType : uint8_t {
     OP_CX = 4,    // swap the pair on local target a (slot s) where control b is 1
     OP_CZ = 5,    // negate where bits a and b are both 1
     OP_UR = 6,    // real 2x2 matrix [[m0, m1], [m2, m3]] on local bit a
-    OP_DSET = 7,  // header of a diagonal set applied at once. Register
-                  // kernel: sb = number of OP_DTAB records that follow (0 or
-                  // 4: the 16 products of the factors on register bits, one
-                  // per register, computed in FP64 on the host), then b OP_DIAG
-                  // members on thread or global bits, whose factors are
-                  // multiplied into one per-thread factor. Small-state kernel:
-                  // sb = 0 and the b members are plain OP_DIAG ops.
+    OP_DSET = 7,  // header of a diagonal set applied at once: a product of
+                  // parity factors d[parity(index & mask)]. Register kernel:
+                  // sb = number of OP_DTAB records that follow (0 or 4: for
+                  // each register k, the product of the factors whose mask
+                  // lies in the register bits, computed in FP64 on the host),
+                  // then b OP_PDIAG members without register bits (folded into
+                  // one per-thread factor), then a OP_PDIAG members with both
+                  // register and other bits. Small-state kernel: sb = a = 0 and
+                  // the b members are applied one by one.
     OP_DTAB = 8,  // 4 complex entries (m[0..7]) of an OP_DSET register table
+    OP_URT = 10,  // real rotation or reflection with its factor p dropped
+                  // (the pass folds the product of the factors into one of
+                  // its diagonal ops): target local bit a (slot sa), form b,
+                  // t = m[0]:  0: [[1, -t], [t, 1]]   1: [[1, t], [t, -1]]
+                  // one FMA per output component
+    OP_PDIAG = 9, // parity factor (member of an OP_DSET): d0 = m[0..1] where
+                  // the parity of (index & mask) is even, d1 = m[2..3] where odd;
+                  // mask = register slots rmask + thread bits tmask (local bit
+                  // numbers) + non-local bits gmask (qubit numbers)
 };
 
 // Where an operand bit lives inside a phase of the register kernel.
@@ -64,9 +75,10 @@ struct alignas(16) DevOp {
     uint8_t a, b;          // local or global bit numbers (see loc)
     uint8_t sa, sb;        // register slots of a and b when LOC_REG
     uint8_t la, lb;        // BitLoc of a and b
-    uint8_t pad0;
-    uint32_t pad1[2];
-    float m[8];            // U: m00 m01 m10 m11 (re, im); DIAG: d0 d1;
+    uint8_t rmask;         // OP_PDIAG: register-slot part of the mask
+    uint32_t tmask;        // OP_PDIAG: thread part (local bit numbers)
+    uint32_t gmask;        // OP_PDIAG: non-local part (qubit numbers)
+    float m[8];            // U: m00 m01 m10 m11 (re, im); DIAG/PDIAG: d0 d1;
                            // PERM: p01 p10
 };
 static_assert(sizeof(DevOp) == 48, "DevOp layout");

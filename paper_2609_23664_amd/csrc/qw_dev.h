@@ -236,6 +236,28 @@ __device__ __forceinline__ void ur_r(float2 (&v)[16], float a, float b, float c,
     }
 }
 
+// Forms of OP_URT on one pair: 0 = [[1, -t], [t, 1]], 1 = [[1, t], [t, -1]].
+template <int F>
+__device__ __forceinline__ void urt_pair(float t, float2 &x, float2 &y) {
+    const float2 a = x, b = y;
+    if constexpr (F == 0) {
+        x = make_float2(fmaf(-t, b.x, a.x), fmaf(-t, b.y, a.y));
+        y = make_float2(fmaf(t, a.x, b.x), fmaf(t, a.y, b.y));
+    } else {
+        x = make_float2(fmaf(t, b.x, a.x), fmaf(t, b.y, a.y));
+        y = make_float2(fmaf(t, a.x, -b.x), fmaf(t, a.y, -b.y));
+    }
+}
+
+template <int S, int F>
+__device__ __forceinline__ void urt_r(float2 (&v)[16], float t) {
+    #pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k & (1 << S)) continue;
+        urt_pair<F>(t, v[k], v[k | (1 << S)]);
+    }
+}
+
 // Anti-diagonal [[0, p01], [p10, 0]].
 template <int S>
 __device__ __forceinline__ void perm_r(float2 (&v)[16], float2 p01, float2 p10) {
@@ -339,6 +361,25 @@ __device__ __forceinline__ void ur_l(float2 (&v)[16], float a, float b, float c,
     }
 }
 
+// OP_URT forms on lane bit J: the lane with bit J clear computes the first
+// output component, the other the second, with the partner's value from
+// lane ^ 2^J; each lane performs the same FMA as urt_pair.
+template <int J, int F>
+__device__ __forceinline__ void urt_l(float2 (&v)[16], float t, uint32_t lane) {
+    const bool hi = (lane >> J) & 1u;
+    #pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const float2 pk = lane_xor2<J>(v[k]);
+        const float2 o = v[k];
+        if constexpr (F == 0) {  // x' = x - t y ; y' = y + t x
+            const float c = hi ? t : -t;
+            v[k] = make_float2(fmaf(c, pk.x, o.x), fmaf(c, pk.y, o.y));
+        } else {  // x' = x + t y ; y' = t x - y
+            v[k] = make_float2(fmaf(t, pk.x, hi ? -o.x : o.x), fmaf(t, pk.y, hi ? -o.y : o.y));
+        }
+    }
+}
+
 template <int J>
 __device__ __forceinline__ void perm_l(float2 (&v)[16], float2 p01, float2 p10, uint32_t lane) {
     const bool hi = (lane >> J) & 1u;
@@ -370,6 +411,27 @@ __device__ __forceinline__ void cx_lb(float2 (&v)[16], bool c) {
 // in member order starting from 1.
 __device__ __forceinline__ float2 dset_fold(float2 ft, bool bit, float2 d0, float2 d1) {
     return cmul(bit ? d1 : d0, ft);
+}
+
+// Parity of the thread and global part of a parity factor's mask.
+__device__ __forceinline__ bool pdiag_tg(uint32_t tl, uint64_t base, uint32_t tmask, uint32_t gmask) {
+    return ((__popc(tl & tmask) ^ __popcll(base & (uint64_t)gmask)) & 1u) != 0u;
+}
+
+// Parity factor with register bits (slots rmask) and thread/global bits of
+// parity pt: register k gets d[pt ^ parity(k & rmask)].
+__device__ __forceinline__ void pdiag_mixed(float2 (&v)[16], bool pt, float2 d0, float2 d1,
+                                            uint32_t rmask) {
+    const float2 a = pt ? d1 : d0, b = pt ? d0 : d1;
+    #pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = cmul((__popc((uint32_t)k & rmask) & 1u) ? b : a, v[k]);
+}
+
+template <int RM>
+__device__ __forceinline__ void pdiag_mixed_c(float2 (&v)[16], bool pt, float2 d0, float2 d1) {
+    const float2 a = pt ? d1 : d0, b = pt ? d0 : d1;
+    #pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = cmul((__builtin_popcount(k & RM) & 1) ? b : a, v[k]);
 }
 
 // Apply a diagonal set: table entries T[k] (register-bit part) and/or the

@@ -15,6 +15,7 @@ namespace qw {
 struct HostOp {
     OpType type;
     int a = -1, b = -1;         // global qubits
+    uint64_t mask = 0;          // OP_PDIAG: qubit mask of the parity factor
     double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // FP64 complex entries
     std::vector<HostOp> members;  // OP_DSET: the OP_DIAG ops of the set
 };

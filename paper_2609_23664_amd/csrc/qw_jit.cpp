@@ -107,6 +107,16 @@ std::string bitval(uint8_t loc, uint8_t bit, size_t ph) {
     return s.str();
 }
 
+// Parity of the thread/global part of a parity member in phase ph.
+std::string pbit(const DevOp &mm, size_t ph) {
+    std::ostringstream s;
+    s << "((0u";
+    if (mm.tmask) s << " ^ (uint32_t)__popc(tl" << ph << " & " << mm.tmask << "u)";
+    if (mm.gmask) s << " ^ (uint32_t)__popcll(base & " << hex(mm.gmask) << ")";
+    s << ") & 1u) != 0u";
+    return s.str();
+}
+
 std::string mr(size_t j) {  // 4 real entries of record j
     std::ostringstream s;
     s << "opm(ops, " << j << ", 0), opm(ops, " << j << ", 1), opm(ops, " << j << ", 2), opm(ops, "
@@ -142,6 +152,13 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
         ++in_block;
         const bool lane = o.la == LOC_LANE;
         switch (o.type) {
+        case OP_URT:
+            if (lane)
+                g << "    urt_l<" << (int)o.sa << ", " << (int)o.b << ">(v, opm(ops, " << j << ", 0), lane);\n";
+            else
+                g << "    urt_r<" << (int)o.sa << ", " << (int)o.b << ">(v, opm(ops, " << j << ", 0));\n";
+            ++j;
+            break;
         case OP_UR:
             if (lane) g << "    ur_l<" << (int)o.sa << ">(v, " << mr(j) << ", lane);\n";
             else g << "    ur_r<" << (int)o.sa << ">(v, " << mr(j) << ");\n";
@@ -186,19 +203,23 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
             break;
         case OP_DSET: {
             const size_t m0 = j + 1 + o.sb;
-            g << "    {\n        float2 ft = make_float2(1.0f, 0.0f);\n";
+            g << "    {\n        float2 ft = make_float2(1.0f, 0.0f); (void)ft;\n";
             for (size_t q = 0; q < o.b; ++q) {
                 const DevOp &mm = ops[m0 + q];
-                g << "        ft = dset_fold(ft, " << bitval(mm.la, mm.a, ph) << ", " << mc(m0 + q, 2)
-                  << ");\n";
+                g << "        ft = dset_fold(ft, " << pbit(mm, ph) << ", " << mc(m0 + q, 2) << ");\n";
             }
             if (o.sb)
                 g << "        dset_apply(v, ops + " << j + 1 << ", true, ft, " << (o.b ? "true" : "false")
                   << ");\n";
-            else
+            else if (o.b)
                 g << "        dset_apply(v, ops, false, ft, true);\n";
+            for (size_t q = 0; q < o.a; ++q) {
+                const DevOp &mm = ops[m0 + o.b + q];
+                g << "        pdiag_mixed_c<" << (int)mm.rmask << ">(v, " << pbit(mm, ph) << ", "
+                  << mc(m0 + o.b + q, 2) << ");\n";
+            }
             g << "    }\n";
-            j = m0 + o.b;
+            j = m0 + o.b + o.a;
             break;
         }
         default:
@@ -281,6 +302,11 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
         put(o.sb, 1);
         put(o.la, 1);
         put(o.lb, 1);
+        if (o.type == OP_PDIAG) {
+            put(o.rmask, 1);
+            put(o.tmask, 4);
+            put(o.gmask, 4);
+        }
     }
     return k;
 }

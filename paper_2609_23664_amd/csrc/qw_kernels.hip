@@ -128,6 +128,27 @@ __device__ __forceinline__ void cz_rr_s(float2 (&v)[16], uint32_t c) {
     }
 }
 
+template <int F>
+__device__ __forceinline__ void urt_r_s(float2 (&v)[16], uint32_t slot, float t) {
+    switch (slot) {
+    case 0: urt_r<0, F>(v, t); break;
+    case 1: urt_r<1, F>(v, t); break;
+    case 2: urt_r<2, F>(v, t); break;
+    default: urt_r<3, F>(v, t); break;
+    }
+}
+template <int F>
+__device__ __forceinline__ void urt_l_s(float2 (&v)[16], uint32_t j, float t, uint32_t lane) {
+    switch (j) {
+    case 0: urt_l<0, F>(v, t, lane); break;
+    case 1: urt_l<1, F>(v, t, lane); break;
+    case 2: urt_l<2, F>(v, t, lane); break;
+    case 3: urt_l<3, F>(v, t, lane); break;
+    case 4: urt_l<4, F>(v, t, lane); break;
+    default: urt_l<5, F>(v, t, lane); break;
+    }
+}
+
 // One op record (not OP_DSET) on the registers of a phase.
 __device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, const DevOp *ops,
                                        uint32_t j, uint32_t tl, uint64_t base) {
@@ -139,6 +160,10 @@ __device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, const D
             return;
         case OP_UR:
             QW_LANE6(ur_l, op.sa, v, opm(ops, j, 0), opm(ops, j, 1), opm(ops, j, 2), opm(ops, j, 3), lane)
+            return;
+        case OP_URT:
+            if (op.b) urt_l_s<1>(v, op.sa, opm(ops, j, 0), lane);
+            else urt_l_s<0>(v, op.sa, opm(ops, j, 0), lane);
             return;
         case OP_PERM:
             QW_LANE6(perm_l, op.sa, v, opc(ops, j, 0), opc(ops, j, 1), lane)
@@ -155,6 +180,10 @@ __device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, const D
         }
     }
     switch (op.type) {
+    case OP_URT:
+        if (op.b) urt_r_s<1>(v, op.sa, opm(ops, j, 0));
+        else urt_r_s<0>(v, op.sa, opm(ops, j, 0));
+        break;
     case OP_UR:
         QW_SLOT4(ur_r, op.sa, v, opm(ops, j, 0), opm(ops, j, 1), opm(ops, j, 2), opm(ops, j, 3))
         break;
@@ -314,20 +343,26 @@ __device__ __forceinline__ void run_ops(float2 (&v)[16], const DevOp *ops, uint3
     DevOp nxt = ld_words(ops + o);
     while (o < end) {
         const DevOp op = nxt;
-        const uint32_t step = (op.type == OP_DSET) ? 1u + op.sb + op.b : 1u;
+        const uint32_t step = (op.type == OP_DSET) ? 1u + op.sb + op.b + op.a : 1u;
         if (o + step < end) nxt = ld_words(ops + o + step);
         if (op.type == OP_DSET) {
+            // thread/global members -> one factor; table; mixed members
             float2 ft = make_float2(1.0f, 0.0f);
             const uint32_t m0 = o + 1 + op.sb;
             for (uint32_t j = 0; j < op.b; ++j) {
                 const DevOp mm = ld_words(ops + m0 + j);
-                ft = dset_fold(ft, opbit_tg(mm.la, mm.a, tl, base), opc(ops, m0 + j, 0),
+                ft = dset_fold(ft, pdiag_tg(tl, base, mm.tmask, mm.gmask), opc(ops, m0 + j, 0),
                                opc(ops, m0 + j, 1));
             }
             if (op.sb)
                 dset_apply(v, ops + o + 1, true, ft, op.b != 0);
-            else
+            else if (op.b)
                 dset_apply(v, ops, false, ft, true);
+            for (uint32_t j = 0; j < op.a; ++j) {
+                const DevOp mm = ld_words(ops + m0 + op.b + j);
+                pdiag_mixed(v, pdiag_tg(tl, base, mm.tmask, mm.gmask), opc(ops, m0 + op.b + j, 0),
+                            opc(ops, m0 + op.b + j, 1), mm.rmask);
+            }
         } else {
             run_op(v, op, ops, o, tl, base);
         }
@@ -483,8 +518,16 @@ __global__ __launch_bounds__(64) void small_pass_kernel(const PassDesc *__restri
     __syncthreads();
     for (uint32_t o = 0; o < d.n_ops; ++o) {
         const DevOp op = d.ops[o];
-        if (op.type == OP_DSET) continue;  // members follow as plain diagonal ops
-        if (op.type == OP_U || op.type == OP_PERM || op.type == OP_CX || op.type == OP_UR) {
+        if (op.type == OP_DSET) continue;  // members follow as plain parity factors
+        if (op.type == OP_PDIAG) {
+            const float2 d0 = make_float2(op.m[0], op.m[1]), d1 = make_float2(op.m[2], op.m[3]);
+            for (uint32_t i = tid; i < dim; i += 64)
+                s[i] = cmul((__popc(i & op.tmask) & 1u) ? d1 : d0, s[i]);
+            __syncthreads();
+            continue;
+        }
+        if (op.type == OP_U || op.type == OP_PERM || op.type == OP_CX || op.type == OP_UR ||
+            op.type == OP_URT) {
             const uint32_t bit = 1u << op.a;
             for (uint32_t pr = tid; pr < dim / 2; pr += 64) {
                 const uint32_t i0 = ((pr >> op.a) << (op.a + 1)) | (pr & (bit - 1));
@@ -493,6 +536,12 @@ __global__ __launch_bounds__(64) void small_pass_kernel(const PassDesc *__restri
                 if (op.type == OP_U) {
                     s[i0] = cmad2(make_float2(op.m[0], op.m[1]), x, make_float2(op.m[2], op.m[3]), y);
                     s[i1] = cmad2(make_float2(op.m[4], op.m[5]), x, make_float2(op.m[6], op.m[7]), y);
+                } else if (op.type == OP_URT) {
+                    float2 a = x, b = y;
+                    if (op.b) urt_pair<1>(op.m[0], a, b);
+                    else urt_pair<0>(op.m[0], a, b);
+                    s[i0] = a;
+                    s[i1] = b;
                 } else if (op.type == OP_UR) {
                     s[i0] = make_float2(fmaf(op.m[0], x.x, op.m[1] * y.x), fmaf(op.m[0], x.y, op.m[1] * y.y));
                     s[i1] = make_float2(fmaf(op.m[2], x.x, op.m[3] * y.x), fmaf(op.m[2], x.y, op.m[3] * y.y));

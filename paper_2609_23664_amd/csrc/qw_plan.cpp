@@ -17,6 +17,7 @@
 // as long as both cut the gate list at the same prefix boundary.
 #include <algorithm>
 #include <array>
+#include <map>
 #include <complex>
 #include <cmath>
 #include <complex>
@@ -164,13 +165,18 @@ std::vector<std::vector<int>> greedy_passes(int n, int m, const std::vector<G> &
 
 // Split a 2x2 unitary M into D2 * R * D1 with R real and D1, D2 diagonal;
 // returns false if no such split was found (M is then kept complex).
+// The phases are taken from fixed entries (a, d), falling back to the other
+// entry of the row/column only when that one is negligible, so the form of
+// the split (and of the kernels built from it) depends on the gate kinds,
+// not on the angles.
 bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
     auto ph = [](cd z) { return z / std::abs(z); };
     auto small = [](double x) { return std::fabs(x) < 1e-13; };
+    auto pick = [&](cd first, cd other) { return std::abs(first) > 1e-9 ? ph(first) : ph(other); };
     // row phases: M = diag(p0, p1) * R
     {
-        cd p0 = std::abs(M.a) >= std::abs(M.b) ? ph(M.a) : ph(M.b);
-        cd p1 = std::abs(M.c) >= std::abs(M.d) ? ph(M.c) : ph(M.d);
+        cd p0 = pick(M.a, M.b);
+        cd p1 = pick(M.d, M.c);
         cd r00 = M.a / p0, r01 = M.b / p0, r10 = M.c / p1, r11 = M.d / p1;
         if (small(r00.imag()) && small(r01.imag()) && small(r10.imag()) && small(r11.imag())) {
             *D2 = {p0, 0.0, 0.0, p1};
@@ -181,8 +187,8 @@ bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
     }
     // column phases: M = R * diag(q0, q1)
     {
-        cd q0 = std::abs(M.a) >= std::abs(M.c) ? ph(M.a) : ph(M.c);
-        cd q1 = std::abs(M.b) >= std::abs(M.d) ? ph(M.b) : ph(M.d);
+        cd q0 = pick(M.a, M.c);
+        cd q1 = pick(M.d, M.b);
         cd r00 = M.a / q0, r01 = M.b / q1, r10 = M.c / q0, r11 = M.d / q1;
         if (small(r00.imag()) && small(r01.imag()) && small(r10.imag()) && small(r11.imag())) {
             *D2 = {1.0, 0.0, 0.0, 1.0};
@@ -208,41 +214,74 @@ bool is_identity(const M2 &u) { return u.a == 1.0 && u.d == 1.0 && u.b == 0.0 &&
 
 // Fuse runs of single-qubit gates per qubit (FP64 products, rounded once to
 // FP32 when lowered) and emit ops in an order equivalent to the gate order.
-// Each mixing run becomes a real 2x2 rotation framed by diagonal factors;
-// diagonal factors stay pending (they commute with each other, with CZ and
-// with CNOT controls) and are emitted together as one OP_DSET at the first
-// op that does not commute with one of them.
+// Each mixing run becomes a real 2x2 rotation framed by diagonal factors.
+// Diagonal factors stay pending as parity factors d[parity(x & mask)]: they
+// commute with each other and with CZ, and a CNOT (control c, target t) is
+// moved in front of them by rewriting every mask that holds t to mask ^ c
+// (D(x) followed by CNOT equals CNOT followed by D(CNOT x)). All pending
+// factors are emitted together, as one OP_DSET, before the first gate that
+// mixes a qubit of one of their masks.
 std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<int> &idx) {
     std::vector<HostOp> ops;
     std::vector<M2> pend(n);
     std::vector<char> has(n, 0);
-    std::vector<M2> dpend(n);      // pending diagonal factor per qubit
-    std::vector<char> dhas(n, 0);
+    // pending parity factors: mask -> (d0, d1), ordered by mask
+    std::map<uint64_t, std::pair<cd, cd>> terms;
+    auto add_term = [&](uint64_t mask, cd d0, cd d1) {
+        auto it = terms.find(mask);
+        if (it == terms.end()) {
+            terms.emplace(mask, std::make_pair(d0, d1));
+        } else {
+            it->second.first *= d0;
+            it->second.second *= d1;
+        }
+    };
     auto add_diag = [&](int q, const M2 &d) {
         if (is_identity(d)) return;
-        if (dhas[q]) {
-            dpend[q] = mul(d, dpend[q]);
-        } else {
-            dpend[q] = d;
-            dhas[q] = 1;
-        }
+        add_term(1ull << q, d.a, d.d);
+    };
+    auto touches = [&](int q) {
+        for (auto &t : terms)
+            if ((t.first >> q) & 1ull) return true;
+        return false;
     };
     auto emit_dset = [&]() {
         HostOp set;
         set.type = OP_DSET;
-        for (int q = 0; q < n; ++q) {
-            if (!dhas[q]) continue;
-            dhas[q] = 0;
-            if (is_identity(dpend[q])) continue;
+        for (auto &t : terms) {
+            const cd d0 = t.second.first, d1 = t.second.second;
+            if (d0 == 1.0 && d1 == 1.0) continue;
             HostOp d;
-            d.type = OP_DIAG;
-            d.a = q;
-            d.m[0] = dpend[q].a.real(); d.m[1] = dpend[q].a.imag();
-            d.m[2] = dpend[q].d.real(); d.m[3] = dpend[q].d.imag();
+            d.type = OP_PDIAG;
+            d.mask = t.first;
+            d.m[0] = d0.real(); d.m[1] = d0.imag();
+            d.m[2] = d1.real(); d.m[3] = d1.imag();
             set.members.push_back(d);
         }
-        if (set.members.size() == 1) ops.push_back(set.members[0]);
-        else if (!set.members.empty()) ops.push_back(set);
+        terms.clear();
+        if (set.members.size() == 1 && popc64(set.members[0].mask) == 1) {
+            HostOp d = set.members[0];
+            d.type = OP_DIAG;
+            d.a = __builtin_ctzll(d.mask);
+            ops.push_back(d);
+        } else if (!set.members.empty()) {
+            ops.push_back(set);
+        }
+    };
+    // CNOT moved in front of the pending factors
+    auto cx_through = [&](int c, int t) {
+        std::map<uint64_t, std::pair<cd, cd>> next;
+        for (auto &e : terms) {
+            const uint64_t m = ((e.first >> t) & 1ull) ? (e.first ^ (1ull << c)) : e.first;
+            auto it = next.find(m);
+            if (it == next.end()) {
+                next.emplace(m, e.second);
+            } else {
+                it->second.first *= e.second.first;
+                it->second.second *= e.second.second;
+            }
+        }
+        terms.swap(next);
     };
     auto flush = [&](int q) {
         if (!has[q]) return;
@@ -255,7 +294,7 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
         HostOp op;
         op.a = q;
         if (u.a == 0.0 && u.d == 0.0) {  // exact swap with phases
-            if (dhas[q]) emit_dset();
+            if (touches(q)) emit_dset();
             op.type = OP_PERM;
             op.m[0] = u.b.real(); op.m[1] = u.b.imag();
             op.m[2] = u.c.real(); op.m[3] = u.c.imag();
@@ -265,7 +304,7 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
         M2 D2, R, D1;
         if (split_real(u, &D2, &R, &D1)) {
             add_diag(q, D1);
-            if (dhas[q]) emit_dset();
+            if (touches(q)) emit_dset();
             op.type = OP_UR;
             op.m[0] = R.a.real(); op.m[1] = R.b.real();
             op.m[2] = R.c.real(); op.m[3] = R.d.real();
@@ -273,7 +312,7 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
             add_diag(q, D2);
             return;
         }
-        if (dhas[q]) emit_dset();
+        if (touches(q)) emit_dset();
         op.type = OP_U;
         op.m[0] = u.a.real(); op.m[1] = u.a.imag();
         op.m[2] = u.b.real(); op.m[3] = u.b.imag();
@@ -288,7 +327,7 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
             flush(g.q1);
             HostOp op;
             if (g.cls == C_CX) {
-                if (dhas[g.q1]) emit_dset();  // a diagonal on the target does not commute
+                cx_through(g.q0, g.q1);
                 op.type = OP_CX;
                 op.a = g.q1;  // target
                 op.b = g.q0;  // control
@@ -311,6 +350,58 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
     for (int q = 0; q < n; ++q) flush(q);
     emit_dset();
     return ops;
+}
+
+// Rewrite real rotations [[p, -q], [q, p]] as p * [[1, -t], [t, 1]] and
+// reflections [[p, q], [q, -p]] as p * [[1, t], [t, -1]] (t = q / p), and
+// fold the product of the factors p (the same for every amplitude) into the
+// first diagonal op of the pass, in FP64. The form never depends on the
+// angle, so tasks that differ only in angles keep one kernel. A large t
+// costs no accuracy (the FMA rounds x - t y once and t's rounding weighs
+// |q y|, as in the plain product); the only limit is the FP32 range of the
+// intermediate amplitudes, which grow by at most the product of the 1/|p|:
+// ops that would push it past 2^60 (angles within ~1e-18 of pi) keep the
+// plain form.
+void tangent_form(std::vector<HostOp> &ops) {
+    double scale = 1.0, growth = 0.0;  // growth in log2
+    for (HostOp &op : ops) {
+        if (op.type != OP_UR) continue;
+        const double a = op.m[0], b = op.m[1], c = op.m[2], d = op.m[3];
+        const double tol = 1e-14 * (std::fabs(a) + std::fabs(b) + std::fabs(c) + std::fabs(d));
+        int form = -1;
+        double t = 0.0;
+        if (std::fabs(a - d) <= tol && std::fabs(b + c) <= tol) {
+            form = 0;
+            t = c / a;
+        } else if (std::fabs(a + d) <= tol && std::fabs(b - c) <= tol) {
+            form = 1;
+            t = b / a;
+        }
+        if (form < 0 || a == 0.0) continue;
+        const double g = -std::log2(std::fabs(a));
+        if (growth + std::max(g, 0.0) > 60.0) continue;
+        growth += std::max(g, 0.0);
+        op.type = OP_URT;
+        op.b = form;
+        op.m[0] = t;
+        op.m[1] = op.m[2] = op.m[3] = 0.0;
+        scale *= a;
+    }
+    if (scale == 1.0) return;
+    for (HostOp &op : ops) {
+        HostOp *d = op.type == OP_DSET ? &op.members[0] : (op.type == OP_DIAG ? &op : nullptr);
+        if (!d) continue;
+        for (int k = 0; k < 4; ++k) d->m[k] *= scale;
+        return;
+    }
+    HostOp set, d;
+    set.type = OP_DSET;
+    d.type = OP_PDIAG;
+    d.mask = 0;
+    d.m[0] = scale;
+    d.m[2] = scale;
+    set.members.push_back(d);
+    ops.push_back(set);
 }
 
 int local_index(uint64_t mask, int g) { return popc64(mask & ((1ull << g) - 1)); }
@@ -364,9 +455,10 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
             const DevOp &o = lops_in[ustart[u] + j];
             bool a_loc = o.la != LOC_GLOBAL, b_loc = o.lb != LOC_GLOBAL;
             switch (o.type) {
-            case OP_U: case OP_PERM: case OP_UR: in.need = o.a; in.bits |= 1u << o.a; break;
+            case OP_U: case OP_PERM: case OP_UR: case OP_URT: in.need = o.a; in.bits |= 1u << o.a; break;
             case OP_CX: in.need = o.a; in.bits |= (1u << o.a) | (b_loc ? (1u << o.b) : 0u); break;
             case OP_DIAG: in.bits |= a_loc ? (1u << o.a) : 0u; break;
+            case OP_PDIAG: in.bits |= o.tmask; break;
             case OP_CZ: in.bits |= (a_loc ? (1u << o.a) : 0u) | (b_loc ? (1u << o.b) : 0u); break;
             default: break;
             }
@@ -468,30 +560,34 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
         };
         for (int ui : phase_ops[ph]) {
         if (lops_in[ustart[ui]].type == OP_DSET) {
-            // register-bit members -> 16-entry FP64 product table; the
-            // others stay members (thread or global bit)
+            // members split by where their mask bits live in this phase:
+            // register bits only -> 16-entry FP64 product table; no register
+            // bits -> per-thread factor; both -> mixed member
             std::complex<double> tab[16];
             for (auto &t : tab) t = 1.0;
             bool has_tab = false;
-            std::vector<DevOp> rest;
+            std::vector<DevOp> tg, mixed;
             for (int uj = 1; uj < unit_len[ui]; ++uj) {
                 DevOp o = lops_in[ustart[ui] + uj];
                 const auto &md = md_in[ustart[ui] + uj];
-                const int sl = (o.la != LOC_GLOBAL) ? slot_of(o.a) : -1;
-                if (sl >= 0) {
+                uint8_t rmask = 0;
+                for (int s2 = 0; s2 < kRegBits; ++s2)
+                    if ((o.tmask >> reg[s2]) & 1u) rmask |= (uint8_t)(1u << s2);
+                const uint32_t tpart = o.tmask & ~R;
+                if (tpart == 0 && o.gmask == 0) {
                     const std::complex<double> d0(md[0], md[1]), d1(md[2], md[3]);
-                    for (int kk = 0; kk < 16; ++kk) tab[kk] *= ((kk >> sl) & 1) ? d1 : d0;
+                    for (int kk = 0; kk < 16; ++kk) tab[kk] *= (popc64((uint64_t)(kk & rmask)) & 1) ? d1 : d0;
                     has_tab = true;
-                } else {
-                    if (o.la != LOC_GLOBAL) {
-                        o.la = LOC_THREAD;
-                        o.sa = 0;
-                    }
-                    rest.push_back(o);
+                    continue;
                 }
+                o.rmask = rmask;
+                o.tmask = tpart;
+                o.la = o.lb = LOC_GLOBAL;
+                (rmask ? mixed : tg).push_back(o);
             }
             DevOp hd = lops_in[ustart[ui]];
-            hd.b = (uint8_t)rest.size();
+            hd.b = (uint8_t)tg.size();
+            hd.a = (uint8_t)mixed.size();
             hd.sb = has_tab ? 4 : 0;
             out.push_back(hd);
             if (has_tab) {
@@ -506,13 +602,15 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
                     out.push_back(t);
                 }
             }
-            for (const DevOp &o : rest) out.push_back(o);
+            for (const DevOp &o : tg) out.push_back(o);
+            for (const DevOp &o : mixed) out.push_back(o);
             continue;
         }
         for (int uj = 0; uj < unit_len[ui]; ++uj) {
             DevOp o = lops_in[ustart[ui] + uj];
             const bool target_op =
-                (o.type == OP_U || o.type == OP_PERM || o.type == OP_CX || o.type == OP_UR);
+                (o.type == OP_U || o.type == OP_PERM || o.type == OP_CX || o.type == OP_UR ||
+                 o.type == OP_URT);
             if (o.la != LOC_GLOBAL) {
                 int sl = slot_of(o.a);
                 if (sl >= 0) {
@@ -600,9 +698,16 @@ void lower_pass(int n, int m, HostPass &p) {
                 *loc = LOC_GLOBAL;
             }
         };
+        if (h.type == OP_PDIAG) {
+            o.tmask = (uint32_t)pext64(h.mask & p.local_mask, p.local_mask);
+            o.gmask = (uint32_t)(h.mask & ~p.local_mask);
+            o.la = o.lb = LOC_GLOBAL;
+            return o;
+        }
         put(h.a, &o.a, &o.la);
         if (h.type == OP_CX || h.type == OP_CZ) put(h.b, &o.b, &o.lb);
         else o.lb = LOC_GLOBAL;
+        if (h.type == OP_URT) o.b = (uint8_t)h.b;
         return o;
     };
     for (const HostOp &h : p.ops) {
@@ -725,6 +830,7 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
             HostPass hp;
             hp.local_mask = best_masks[k];
             hp.ops = fuse_ops(n, gs, best[k]);
+            tangent_form(hp.ops);
             if (k == 0 && pending_scale) hp.scale_in = true;
             if (k + 1 == best.size() && renorm_after[s]) hp.norm_out = true;
             plan.passes.push_back(std::move(hp));
@@ -751,7 +857,18 @@ std::string plan_json(const Plan &p) {
             if (k) o << ",";
             o << "{\"type\":" << (int)d.type << ",\"a\":" << (int)d.a << ",\"b\":" << (int)d.b
               << ",\"la\":" << (int)d.la << ",\"lb\":" << (int)d.lb << ",\"sa\":" << (int)d.sa
-              << ",\"sb\":" << (int)d.sb << ",\"m\":[";
+              << ",\"sb\":" << (int)d.sb;
+            if (d.type == OP_PDIAG) {
+                // qubit mask of the parity factor (register slots resolved with
+                // the layout of the op's phase)
+                uint64_t q = (uint64_t)d.gmask | pdep64(d.tmask, h.local_mask);
+                for (const DevPhase &f : h.dev_phases)
+                    if (k >= f.op_begin && k < f.op_end)
+                        for (int s2 = 0; s2 < 4; ++s2)
+                            if ((d.rmask >> s2) & 1) q |= pdep64(1ull << f.reg[s2], h.local_mask);
+                o << ",\"qmask\":" << q;
+            }
+            o << ",\"m\":[";
             for (int j = 0; j < 8; ++j) o << (j ? "," : "") << (double)d.m[j];
             o << "]}";
         }

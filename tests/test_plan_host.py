@@ -14,7 +14,7 @@ from paper_2609_23664_amd import binding as B
 from workloads import gen
 
 LOC_REG, LOC_THREAD, LOC_GLOBAL, LOC_LANE = 0, 1, 2, 3
-OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ, OP_UR, OP_DSET, OP_DTAB = 1, 2, 3, 4, 5, 6, 7, 8
+OP_U, OP_DIAG, OP_PERM, OP_CX, OP_CZ, OP_UR, OP_DSET, OP_DTAB, OP_PDIAG, OP_URT = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
 
 def _local_bits(mask):
@@ -54,14 +54,26 @@ def interpret(n, plan, psi):
                     for s_, rb in enumerate(reg):
                         k |= ((idx >> lb[rb]) & 1) << s_
                     psi *= np.asarray(tab)[k]
-                continue          # thread/global members follow as OP_DIAG
-            if t in (OP_U, OP_PERM, OP_UR):
+                continue          # parity members follow as OP_PDIAG
+            if t == OP_PDIAG:
+                par = np.zeros(1 << n, dtype=np.int64)
+                qm = op["qmask"]
+                for q in range(n):
+                    if (qm >> q) & 1:
+                        par ^= (idx >> q) & 1
+                psi *= np.where(par == 1, m[2] + 1j * m[3], m[0] + 1j * m[1])
+                continue
+            if t in (OP_U, OP_PERM, OP_UR, OP_URT):
                 assert op["la"] != LOC_GLOBAL
                 g = gbit(op["la"], op["a"])
                 i0 = idx[((idx >> g) & 1) == 0]
                 i1 = i0 | (1 << g)
                 x, y = psi[i0].copy(), psi[i1].copy()
-                if t == OP_UR:
+                if t == OP_URT:
+                    tt = m[0]
+                    a, b, c, d = {0: (1, -tt, tt, 1), 1: (1, tt, tt, -1)}[op["b"]]
+                    psi[i0], psi[i1] = a * x + b * y, c * x + d * y
+                elif t == OP_UR:
                     psi[i0], psi[i1] = m[0] * x + m[1] * y, m[2] * x + m[3] * y
                 elif t == OP_U:
                     a, b, c, d = (m[0] + 1j * m[1], m[2] + 1j * m[3], m[4] + 1j * m[5], m[6] + 1j * m[7])
@@ -113,7 +125,7 @@ def _check_phases(plan):
             if k == 0 or k == len(ph) - 1:
                 assert kind != 0
             for op in p["ops"][f["op_begin"]:f["op_end"]]:
-                if op["type"] in (OP_U, OP_PERM, OP_CX, OP_UR):
+                if op["type"] in (OP_U, OP_PERM, OP_CX, OP_UR, OP_URT):
                     assert op["la"] in (LOC_REG, LOC_LANE)
                     if op["la"] == LOC_REG:
                         assert reg[op["sa"]] == op["a"]
@@ -178,3 +190,16 @@ def test_plan_is_deterministic():
     a = B.plan_describe(20, w.task_gates(0))
     b = B.plan_describe(20, w.task_gates(0))
     assert a == b
+
+
+def test_vqe_tasks_share_one_pass_structure():
+    """Suffixes that differ only in angles lower to the same ops and layouts
+    (so one generated kernel serves every task)."""
+    w = gen.config2()
+
+    def shape(pl):
+        return [[(o["type"], o["a"], o["b"], o["la"], o["lb"], o["sa"], o["sb"]) for o in p["ops"]]
+                for p in pl["passes"]]
+    ref = shape(B.plan_describe(24, w.suffixes[0]))
+    for t in range(1, w.n_tasks):
+        assert shape(B.plan_describe(24, w.suffixes[t])) == ref
