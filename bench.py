@@ -49,15 +49,21 @@ def main():
     prov = fingerprint(n, w.prefix)
     ctx = B.Ctx(0)
 
+    # gate lists marshalled once (host preparation, outside the timed steps;
+    # the library's plan cache makes later steps skip planning, which the
+    # first, untimed step does)
+    prefix = B.GateArray(w.prefix)
+    suffixes = [B.GateArray(s) for s in w.suffixes]
+
     # ---- reuse path: slot 0 = boundary, slots 1..T = tasks
     st = B.State(ctx, n, T + 1)
     slots = list(range(1, T + 1))
 
     def reuse_step():
         st.reset(0, 1)
-        st.apply(0, w.prefix)
+        st.apply(0, prefix)
         snap = st.snapshot(0, prov, B.QW_SNAP_FREEZE)
-        e = B.run_suffix_batch(ctx, [snap] * T, w.suffixes, st, slots, terms=terms)
+        e = B.run_suffix_batch(ctx, [snap] * T, suffixes, st, slots, terms=terms)
         snap.free()
         return e
 
@@ -67,8 +73,8 @@ def main():
 
     def direct_step():
         dst.reset(0, T)
-        B.run_suffix_batch(ctx, None, [w.prefix] * T, dst, dslots)
-        return B.run_suffix_batch(ctx, None, w.suffixes, dst, dslots, terms=terms)
+        B.run_suffix_batch(ctx, None, [prefix] * T, dst, dslots)
+        return B.run_suffix_batch(ctx, None, suffixes, dst, dslots, terms=terms)
 
     def timed(fn, steps, warmup, profile=False):
         for _ in range(warmup):

@@ -59,6 +59,15 @@ class QwGate(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("param", ctypes.c_double)]
 
 
+def _gate_dtype():
+    import numpy as np
+    return np.dtype([("kind", "<u4"), ("q0", "<u4"), ("q1", "<u4"), ("reserved", "<u4"),
+                     ("param", "<f8")])
+
+
+
+
+
 class QwArtifact(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("exactness", ctypes.c_uint32),
                 ("backend", ctypes.c_uint32), ("n_qubits", ctypes.c_uint32),
@@ -150,17 +159,37 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-def gate_array(gates: Sequence[Tuple[str, Tuple[int, ...], float]]):
-    """Marshal (name, qubits, param) records into a qw_gate array."""
-    arr = (QwGate * max(1, len(gates)))()
-    for k, (name, qs, p) in enumerate(gates):
-        g = arr[k]
-        g.kind = GATE_KIND[name]
-        g.q0 = qs[0] if len(qs) > 0 else 0
-        g.q1 = qs[1] if len(qs) > 1 else 0
-        g.reserved = 0
-        g.param = float(p)
-    return arr
+class GateArray:
+    """Gate records marshalled once into a qw_gate array (reusable across
+    calls; `set_params` rewrites the angles in place). Accepted wherever a
+    gate list is."""
+
+    def __init__(self, gates: Sequence[Tuple[str, Tuple[int, ...], float]]):
+        import numpy as np
+        n = len(gates)
+        rec = np.zeros(max(1, n), dtype=_gate_dtype())
+        if n:
+            rec["kind"][:n] = [GATE_KIND[g[0]] for g in gates]
+            rec["q0"][:n] = [g[1][0] if len(g[1]) > 0 else 0 for g in gates]
+            rec["q1"][:n] = [g[1][1] if len(g[1]) > 1 else 0 for g in gates]
+            rec["param"][:n] = [float(g[2]) for g in gates]
+        self.rec = rec
+        self.n = n
+        self.ptr = rec.ctypes.data_as(ctypes.POINTER(QwGate))
+
+    def set_params(self, params) -> None:
+        self.rec["param"][:self.n] = params
+
+    def __len__(self):
+        return self.n
+
+
+def gate_array(gates):
+    """A qw_gate array for `gates` ((name, qubits, param) records, or a
+    GateArray, returned as is)."""
+    if isinstance(gates, GateArray):
+        return gates
+    return GateArray(gates)
 
 
 def _u64_array(vals):
@@ -198,7 +227,7 @@ def plan_describe(n: int, gates, tile_bits: int = 14) -> dict:
     cap = 1 << 16
     while True:
         buf = ctypes.create_string_buffer(cap)
-        rc = lib().qw_plan_describe(n, arr, len(gates), tile_bits, buf, cap)
+        rc = lib().qw_plan_describe(n, arr.ptr, len(arr), tile_bits, buf, cap)
         if rc == QW_OK:
             return json.loads(buf.value.decode())
         if buf.value.startswith(b'{"error"'):
@@ -214,7 +243,7 @@ def jit_precompile(n: int, gates, tile_bits: int = 14) -> None:
     arr = gate_array(gates)
     cap = 1 << 20
     buf = ctypes.create_string_buffer(cap)
-    rc = lib().qw_jit_precompile(n, arr, len(gates), tile_bits, buf, cap)
+    rc = lib().qw_jit_precompile(n, arr.ptr, len(arr), tile_bits, buf, cap)
     if rc != QW_OK:
         raise QwError(rc, buf.value.decode(errors="replace"))
 
@@ -307,7 +336,7 @@ class State:
 
     def apply(self, slot: int, gates):
         arr = gate_array(gates)
-        self.ctx.check(lib().qw_apply_prefix(self.h, slot, arr, len(gates)))
+        self.ctx.check(lib().qw_apply_prefix(self.h, slot, arr.ptr, len(arr)))
 
     def snapshot(self, slot: int, provenance: bytes, mode: int = QW_SNAP_FREEZE,
                  parent: "Optional[Snapshot]" = None) -> "Snapshot":
@@ -394,8 +423,8 @@ def run_suffix_batch(ctx: Ctx, srcs: Sequence[Optional[Snapshot]], suffixes, dst
     arrs = [gate_array(s) for s in suffixes]
     tasks = (QwTask * max(1, nt))()
     for k in range(nt):
-        tasks[k].gates = ctypes.cast(arrs[k], ctypes.POINTER(QwGate))
-        tasks[k].n_gates = len(suffixes[k])
+        tasks[k].gates = arrs[k].ptr
+        tasks[k].n_gates = len(arrs[k])
         tasks[k].dst_slot = int(dst_slots[k])
         tasks[k].reserved = 0
         prov = expect_provs[k] if expect_provs is not None else (

@@ -11,6 +11,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/qw.h"
@@ -33,6 +34,13 @@ struct ProfRec {
     int kind;
     double bytes;
     hipEvent_t e0, e1;
+};
+
+struct PlanEntry {
+    uint32_t n = 0;
+    int tile_bits = 0;
+    std::vector<char> gates;  // the gate records the plan was built from
+    std::shared_ptr<const qw::Plan> plan;
 };
 
 struct KStats {
@@ -61,6 +69,8 @@ struct qw_ctx {
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
     KStats stats[4];
+    std::unordered_map<uint64_t, std::vector<PlanEntry>> plan_cache;
+    size_t plan_cache_entries = 0;
 };
 
 struct qw_state {
@@ -272,23 +282,68 @@ bool slot_ok(const qw_state *st, uint32_t first, uint32_t count) {
 
 char *slot_ptr(const qw_state *st, uint32_t s) { return st->base + (uint64_t)s * st->slot_bytes; }
 
+// Plans of gate lists seen before on this context, keyed by the exact bytes
+// of the gate records (and n, tile bits): resubmitting a gate list skips
+// planning. Bounded; cleared when full.
+uint64_t fnv64(const void *p, size_t len, uint64_t h = 0xcbf29ce484222325ull) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < len; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_gates,
+                     std::shared_ptr<const Plan> *out) {
+    const size_t bytes = (size_t)n_gates * sizeof(qw_gate);
+    uint64_t h = fnv64(gates, bytes);
+    h = fnv64(&n, sizeof n, h);
+    h = fnv64(&ctx->tile_bits, sizeof ctx->tile_bits, h);
+    auto &bucket = ctx->plan_cache[h];
+    for (const auto &c : bucket) {
+        if (c.n == n && c.tile_bits == ctx->tile_bits && c.gates.size() == bytes &&
+            (bytes == 0 || std::memcmp(c.gates.data(), gates, bytes) == 0)) {
+            *out = c.plan;
+            return "";
+        }
+    }
+    auto p = std::make_shared<Plan>();
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, ctx->tile_bits, p.get());
+    if (!e.empty()) return e;
+    if (ctx->plan_cache_entries >= 4096) {
+        ctx->plan_cache.clear();
+        ctx->plan_cache_entries = 0;
+    }
+    PlanEntry pe;
+    pe.n = n;
+    pe.tile_bits = ctx->tile_bits;
+    pe.gates.assign(reinterpret_cast<const char *>(gates), reinterpret_cast<const char *>(gates) + bytes);
+    pe.plan = p;
+    ctx->plan_cache[h].push_back(std::move(pe));
+    ++ctx->plan_cache_entries;
+    *out = p;
+    return "";
+}
+
 // One task of an execution: its plan, source, destination.
 struct Exec {
-    Plan plan;
+    std::shared_ptr<const Plan> planp;
+    const Plan &plan_ref() const { return *planp; }
     const void *src = nullptr;  // first-pass source (snapshot) or nullptr
     void *dst = nullptr;
 };
 
 int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     if (ex.empty()) return QW_OK;
-    const int m = ex[0].plan.m;
+    const int m = ex[0].planp->m;
     const uint32_t tiles = (m >= kMinTileBits) ? (1u << (n - m)) : 1u;
     size_t steps = 0;
-    for (Exec &e : ex) steps = std::max(steps, e.plan.passes.size());
+    for (Exec &e : ex) steps = std::max(steps, e.planp->passes.size());
     // tasks with a snapshot and no pass: plain copy of the boundary state
     const uint64_t state_bytes = 8ull << n;
     for (Exec &e : ex) {
-        if (e.src && e.plan.passes.empty()) {
+        if (e.src && e.planp->passes.empty()) {
             ProfScope ps(ctx, 3, 2.0 * state_bytes);
             hipError_t er = launch_copy(ctx->stream, e.dst, e.src, state_bytes);
             if (er != hipSuccess) return hip_fail(ctx, er, "copy launch");
@@ -298,7 +353,7 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     // scratch: per task norm partials [tiles] and one scale
     bool any_norm = false;
     for (Exec &e : ex)
-        for (HostPass &p : e.plan.passes) any_norm |= p.norm_out;
+        for (const HostPass &p : e.planp->passes) any_norm |= p.norm_out;
     const size_t norm_bytes = any_norm ? ex.size() * (tiles + 1) * sizeof(double) : 0;
     if (norm_bytes) {
         int rc = ensure(ctx, ctx->scratch, norm_bytes, "norm scratch");
@@ -309,13 +364,13 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     Layout L;
     std::vector<size_t> step_off(steps), step_cnt(steps, 0);
     for (size_t k = 0; k < steps; ++k) {
-        for (Exec &e : ex) step_cnt[k] += (k < e.plan.passes.size());
+        for (Exec &e : ex) step_cnt[k] += (k < e.planp->passes.size());
         step_off[k] = L.take(step_cnt[k] * sizeof(PassDesc));
     }
     std::vector<std::vector<std::pair<size_t, size_t>>> op_off(ex.size());
     std::vector<std::vector<size_t>> io_off(ex.size());
     for (size_t t = 0; t < ex.size(); ++t) {
-        for (HostPass &p : ex[t].plan.passes) {
+        for (const HostPass &p : ex[t].planp->passes) {
             size_t oo = L.take(std::max<size_t>(1, p.dev_ops.size()) * sizeof(DevOp));
             size_t po = L.take(std::max<size_t>(1, p.dev_phases.size()) * sizeof(DevPhase));
             op_off[t].push_back({oo, po});
@@ -333,14 +388,14 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     };
     std::vector<std::vector<size_t>> tb_of(ex.size());
     for (size_t t = 0; t < ex.size(); ++t)
-        for (HostPass &p : ex[t].plan.passes) tb_of[t].push_back(tile_table(p.local_mask));
+        for (const HostPass &p : ex[t].planp->passes) tb_of[t].push_back(tile_table(p.local_mask));
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
     uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
     std::vector<uint8_t> blob(L.size, 0);
     for (size_t t = 0; t < ex.size(); ++t) {
-        for (size_t k = 0; k < ex[t].plan.passes.size(); ++k) {
-            HostPass &p = ex[t].plan.passes[k];
+        for (size_t k = 0; k < ex[t].planp->passes.size(); ++k) {
+            const HostPass &p = ex[t].planp->passes[k];
             std::memcpy(blob.data() + op_off[t][k].first, p.dev_ops.data(),
                         p.dev_ops.size() * sizeof(DevOp));
             std::memcpy(blob.data() + op_off[t][k].second, p.dev_phases.data(),
@@ -373,16 +428,17 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         for (size_t k = 0; k < steps; ++k) {
             std::map<std::string, size_t> gi;
             for (size_t t = 0; t < ex.size(); ++t) {
-                if (k >= ex[t].plan.passes.size()) continue;
-                const HostPass &p = ex[t].plan.passes[k];
+                if (k >= ex[t].planp->passes.size()) continue;
+                const HostPass &p = ex[t].planp->passes[k];
                 const bool lds = p.norm_out || p.dev_phases.size() > 1;
-                std::string key = jit_pass_key((int)n, m, p, lds);
+                if (p.jit_key.empty()) p.jit_key = jit_pass_key((int)n, m, p, lds);
+                const std::string &key = p.jit_key;
                 auto it = gi.find(key);
                 if (it == gi.end()) {
                     it = gi.emplace(key, members[k].size()).first;
                     members[k].push_back({reqs.size(), {}});
                     JitReq r;
-                    r.key = std::move(key);
+                    r.key = key;
                     r.pass = &p;
                     r.n = (int)n;
                     r.m = m;
@@ -404,14 +460,14 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     } else {
         for (size_t k = 0; k < steps; ++k)
             for (size_t t = 0; t < ex.size(); ++t)
-                if (k < ex[t].plan.passes.size()) order[k].push_back(t);
+                if (k < ex[t].planp->passes.size()) order[k].push_back(t);
     }
     std::vector<char> step_norm(steps, 0), step_lds(steps, 0);
     for (size_t k = 0; k < steps; ++k) {
         size_t c = 0;
         for (size_t t : order[k]) {
             Exec &e = ex[t];
-            HostPass &p = e.plan.passes[k];
+            const HostPass &p = e.planp->passes[k];
             PassDesc d{};
             d.src = (k == 0 && e.src) ? e.src : e.dst;
             d.dst = e.dst;
@@ -781,7 +837,7 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
     if (slot >= st->n_slots) return fail(ctx, QW_E_INVALID_ARG, "slot out of range");
     if (st->frozen[slot]) return fail(ctx, QW_E_INVALID_ARG, "slot is frozen by a snapshot");
     std::vector<Exec> ex(1);
-    std::string e = build_plan((int)st->n, gates, (size_t)n_gates, ctx->tile_bits, &ex[0].plan);
+    std::string e = get_plan(ctx, st->n, gates, n_gates, &ex[0].planp);
     if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
     ex[0].dst = slot_ptr(st, slot);
     return execute(ctx, st->n, ex);
@@ -896,8 +952,7 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
     }
     std::vector<Exec> ex(n_tasks);
     for (uint32_t k = 0; k < n_tasks; ++k) {
-        std::string e = build_plan((int)dst->n, tasks[k].gates, (size_t)tasks[k].n_gates,
-                                   ctx->tile_bits, &ex[k].plan);
+        std::string e = get_plan(ctx, dst->n, tasks[k].gates, tasks[k].n_gates, &ex[k].planp);
         if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
         ex[k].src = (src && src[k]) ? src[k]->data : nullptr;
         ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);

@@ -29,6 +29,7 @@ struct HostPass {
     // filled by lower_pass():
     std::vector<DevOp> dev_ops;
     std::vector<DevPhase> dev_phases;
+    mutable std::string jit_key;  // generated-kernel key, computed on first use
 };
 
 struct Plan {
