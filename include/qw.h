@@ -265,6 +265,13 @@ int qw_legality_check(const qw_artifact *src, uint32_t target_kind,
 int qw_plan_describe(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
                      uint32_t tile_bits, char *json_out, uint64_t cap);
 
+/* Cost of `gates` on n qubits in the analytic byte model of the planner
+ * (Sec. IV-C): the number of tile passes the library would run and the HBM
+ * bytes they move (each pass reads and writes the state once: 2 * 8 * 2^n
+ * bytes). No device is needed. */
+int qw_plan_cost(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
+                 uint64_t *n_passes, double *bytes);
+
 /* Generate and compile (hipRTC) the pass kernels that QW_OPT_JIT would use
  * for `gates` on n qubits with at most tile_bits local bits per pass, and
  * keep the code objects in the process cache and the disk cache, without

@@ -50,7 +50,7 @@ EXPORTED = (
     "qw_state_reset", "qw_state_slot_ptr", "qw_apply_prefix", "qw_snapshot",
     "qw_snapshot_free", "qw_snapshot_info", "qw_run_suffix_batch",
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
-    "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_stats", "qw_version",
+    "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_stats", "qw_version",
 )
 
 
@@ -144,6 +144,8 @@ def lib() -> ctypes.CDLL:
         "qw_sample": ([vp, u32, u32, u64, u64, u32, vp, i32], i32),
         "qw_legality_check": ([ctypes.POINTER(QwArtifact), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_plan_describe": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
+        "qw_plan_cost": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.POINTER(u64),
+                          ctypes.POINTER(ctypes.c_double)], i32),
         "qw_jit_precompile": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
         "qw_jit_precompile_terms": ([u32, ctypes.POINTER(u64), ctypes.POINTER(u64), u32, u32,
                                      ctypes.c_char_p, u64], i32),
@@ -235,6 +237,16 @@ def plan_describe(n: int, gates, tile_bits: int = 14) -> dict:
         cap *= 4
         if cap > (1 << 30):
             raise QwError(rc, "plan too large")
+
+
+def plan_cost(n: int, gates, tile_bits: int = 14) -> Tuple[int, float]:
+    """Host-only: (tile passes, HBM bytes) of `gates` on n qubits."""
+    arr = gate_array(gates)
+    npass, by = ctypes.c_uint64(), ctypes.c_double()
+    rc = lib().qw_plan_cost(n, arr.ptr, len(arr), tile_bits, ctypes.byref(npass), ctypes.byref(by))
+    if rc != QW_OK:
+        raise QwError(rc, "plan_cost: invalid gates")
+    return npass.value, by.value
 
 
 def jit_precompile(n: int, gates, tile_bits: int = 14) -> None:

@@ -1040,6 +1040,17 @@ int qw_legality_check(const qw_artifact *src, uint32_t target_kind, uint32_t tar
     return QW_E_REFUSED;
 }
 
+int qw_plan_cost(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
+                 uint64_t *n_passes, double *bytes) {
+    if (n_gates && !gates) return QW_E_INVALID_ARG;
+    Plan p;
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    if (!e.empty()) return QW_E_INVALID_ARG;
+    if (n_passes) *n_passes = p.passes.size();
+    if (bytes) *bytes = (double)p.passes.size() * 2.0 * 8.0 * std::ldexp(1.0, (int)n);
+    return QW_OK;
+}
+
 int qw_jit_precompile(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
                       char *log, uint64_t cap) {
     auto put = [&](const std::string &msg) {

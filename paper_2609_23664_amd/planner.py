@@ -1,20 +1,45 @@
-"""Workload planner (host side): Eq. (1) fingerprints, prefix detection,
-Table II legality, the Eq. (2) reuse rule with an analytic byte-count cost
-model, and the EXPLAIN / CostRecord / ExecutionResult records (Sec. III-A,
-Sec. IV). Execution goes through the C ABI (``binding``); the plan changes
-timing only, never results.
+"""Workload planner (host side) and workload executor.
+
+Implements the planning layer of the method (Sec. III-A and Sec. IV):
+
+* Eq. (1) structural fingerprints, here of every cumulative prefix, used as
+  the provenance of boundary states;
+* shared-prefix detection: a radix trie over the tasks' gate records
+  (longest common prefixes; two gates match when kind, qubits and bound
+  parameter are equal);
+* the Eq. (2) materialize-versus-recompute rule, evaluated top-down over
+  the trie (a bounded search: each node is either materialized or folded
+  into its tasks' suffixes), with an analytic byte-count cost model and
+  the safety margin delta = 0.1 * est_reuse; ABSTAIN when no node
+  survives (a single task, no shared segment, or no profit);
+* execution through the C ABI (``binding``): materialized nodes are run
+  once and frozen as exact boundary snapshots, every task continues from
+  its nearest one; a legality refusal falls back to direct execution;
+* the three output records: ExecutionResult, ExplainTrace, CostRecord.
+
+The plan changes timing only: results are the same for every plan
+(bit-identical to direct execution with the same segment cuts).
 """
 from __future__ import annotations
 
 import hashlib
+import json
+import math
 import struct
-from typing import List, Sequence, Tuple
+import time
+from dataclasses import asdict, dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
 
 from .binding import GATE_KIND
 
 Gate = Tuple[str, Tuple[int, ...], float]
 
+DELTA_GUARD = 0.10  # delta = 0.10 * est_reuse (the 10 % guard)
 
+
+# ---------------------------------------------------------------- Eq. (1)
 def gate_bytes(g: Gate) -> bytes:
     """Byte record of one gate for Eq. (1): u8 kind, u32 q0, u32 q1, f64
     parameter, little-endian (absent qubits are 0xFFFFFFFF)."""
@@ -37,3 +62,417 @@ def fingerprint(n: int, gates: Sequence[Gate]) -> bytes:
     for g in gates:
         h.update(gate_bytes(g))
     return h.digest()
+
+
+# ---------------------------------------------------------------- trie
+@dataclass
+class Node:
+    """A trie node: gates [start, end) of its tasks are shared by all of
+    them (and, for a non-root node, the gate at `start` is where they
+    diverged from their siblings)."""
+    id: int
+    depth: int
+    start: int
+    end: int
+    tasks: List[int]
+    parent: Optional[int]
+    children: List[int] = field(default_factory=list)
+    ending: List[int] = field(default_factory=list)  # tasks whose gates end at `end`
+    # planning
+    seg_bytes: float = 0.0
+    decision: str = "FOLD"
+    reason: str = ""
+    c_prefix: float = 0.0
+    est_direct: float = 0.0
+    est_reuse: float = 0.0
+    delta: float = 0.0
+
+
+def build_trie(tasks: Sequence[Sequence[Gate]]) -> List[Node]:
+    """Radix trie of the task gate lists (exact gate records). Node 0 is
+    the root (start = 0; its segment is the prefix shared by all tasks)."""
+    codes: Dict[Tuple, int] = {}
+    lens = np.array([len(t) for t in tasks], dtype=np.int64)
+    lmax = int(lens.max()) if len(tasks) else 0
+    ids = np.full((len(tasks), lmax + 1), -1, dtype=np.int64)
+    for i, t in enumerate(tasks):
+        for j, (name, qs, p) in enumerate(t):
+            key = (name, tuple(qs), float(p))
+            c = codes.get(key)
+            if c is None:
+                c = codes[key] = len(codes)
+            ids[i, j] = c
+    nodes: List[Node] = []
+
+    def make(group: np.ndarray, start: int, depth: int, parent: Optional[int]) -> int:
+        ref = ids[group[0]]
+        minlen = int(lens[group].min())
+        if len(group) == 1:
+            end = int(lens[group[0]])
+        elif minlen > start:
+            eq = (ids[group, start:minlen] == ref[start:minlen]).all(axis=0)
+            end = start + (int(np.argmin(eq)) if not eq.all() else minlen - start)
+        else:
+            end = start
+        node = Node(id=len(nodes), depth=depth, start=start, end=end,
+                    tasks=[int(t) for t in group], parent=parent)
+        nodes.append(node)
+        if len(group) == 1:
+            node.ending = [int(group[0])]
+            return node.id
+        at_end = group[lens[group] == end]
+        node.ending = [int(t) for t in at_end]
+        rest = group[lens[group] > end]
+        if len(rest):
+            nxt = ids[rest, end]
+            for code in np.unique(nxt):
+                sub = rest[nxt == code]
+                cid = make(sub, end, depth + 1, node.id)
+                node.children.append(cid)
+        return node.id
+
+    if len(tasks):
+        make(np.arange(len(tasks)), 0, 0, None)
+    return nodes
+
+
+def path_to(nodes: List[Node], v: int) -> List[int]:
+    """Node ids from the root to v (inclusive)."""
+    out = []
+    while v is not None:
+        out.append(v)
+        v = nodes[v].parent
+    return out[::-1]
+
+
+# ---------------------------------------------------------------- Eq. (2)
+def eq2(n_tasks: int, c_prefix: float, c_materialize: float, c_reload: float,
+        c_handoff: float, delta: float) -> bool:
+    """Eq. (2): (N - 1) C_prefix > C_materialize + N (C_reload + C_handoff) + delta."""
+    return (n_tasks - 1) * c_prefix > c_materialize + n_tasks * (c_reload + c_handoff) + delta
+
+
+@dataclass
+class CostModel:
+    """Analytic byte-count costs (Sec. IV-C with costs measured in HBM
+    bytes). A segment costs the bytes of the tile passes the library runs
+    for it; materializing a frozen snapshot costs nothing (the boundary
+    slot becomes the artifact); the reload is fused into the first suffix
+    pass (it reads the snapshot instead of the slot), except for a task
+    with nothing left to run, which costs one copy; a same-backend handoff
+    costs nothing."""
+    n: int
+    tile_bits: int = 14
+    _cache: Dict[Tuple, float] = field(default_factory=dict)
+
+    @property
+    def state_bytes(self) -> float:
+        return 8.0 * (1 << self.n)
+
+    def segment(self, gates: Sequence[Gate]) -> float:
+        if not gates:
+            return 0.0
+        key = tuple((g[0], tuple(g[1]), float(g[2])) for g in gates)
+        c = self._cache.get(key)
+        if c is None:
+            from .binding import plan_cost
+            c = plan_cost(self.n, list(gates), self.tile_bits)[1]
+            self._cache[key] = c
+        return c
+
+    def materialize(self) -> float:
+        return 0.0
+
+    def reload(self, remainder_empty: bool) -> float:
+        return 2.0 * self.state_bytes if remainder_empty else 0.0
+
+    def handoff(self) -> float:
+        return 0.0
+
+
+@dataclass
+class Plan:
+    n: int
+    nodes: List[Node]
+    materialized: List[int]
+    anchor: List[Optional[int]]      # per task: nearest materialized node (None: direct)
+    decision: str                    # REUSE or ABSTAIN
+    reason: str
+    est_direct: float
+    est_reuse: float
+    planning_ms: float
+
+
+def plan_workload(n: int, tasks: Sequence[Sequence[Gate]], cost: Optional[CostModel] = None,
+                  guard: float = DELTA_GUARD,
+                  decide: Optional[Callable[[Node, float, float, float], Optional[bool]]] = None,
+                  ) -> Plan:
+    """Bounded top-down search: a node is materialized when Eq. (2) holds
+    for it, C_prefix being the cost from its nearest materialized ancestor.
+    `decide(node, c_prefix, est_direct, est_reuse)` may override the rule
+    (a learned cost model); returning None keeps the analytic decision."""
+    t0 = time.perf_counter()
+    cost = cost or CostModel(n)
+    nodes = build_trie(tasks)
+    B = cost.state_bytes
+    for v in nodes:
+        v.seg_bytes = cost.segment(tasks[v.tasks[0]][v.start:v.end])
+    # cost of each task's gates below a node (sum of segment costs)
+    below: Dict[int, Dict[int, float]] = {}
+
+    def suffix_costs(vid: int) -> Dict[int, float]:
+        if vid in below:
+            return below[vid]
+        v = nodes[vid]
+        out = {t: 0.0 for t in v.ending}
+        for c in v.children:
+            for t, cst in suffix_costs(c).items():
+                out[t] = nodes[c].seg_bytes + cst
+        below[vid] = out
+        return out
+
+    materialized: List[int] = []
+    anchor_of: Dict[int, Optional[int]] = {0: None} if nodes else {}
+    order = sorted(range(len(nodes)), key=lambda i: nodes[i].depth)
+    for vid in order:
+        v = nodes[vid]
+        a = anchor_of.get(vid)
+        # C_prefix: segments from the nearest materialized ancestor to v
+        c_prefix, u = 0.0, vid
+        while u is not None and u != a:
+            c_prefix += nodes[u].seg_bytes
+            u = nodes[u].parent
+        N = len(v.tasks)
+        suf = suffix_costs(vid)
+        c_suffix = sum(suf.values()) / max(1, N)
+        n_empty = len(v.ending)
+        est_direct = N * (c_prefix + c_suffix)
+        est_reuse = c_prefix + cost.materialize() + N * (cost.handoff() + c_suffix) + \
+            n_empty * cost.reload(True)
+        delta = guard * est_reuse
+        v.c_prefix, v.est_direct, v.est_reuse, v.delta = c_prefix, est_direct, est_reuse, delta
+        if N < 2:
+            ok, why = False, "single task below this node"
+        elif v.end == v.start and vid != 0:
+            ok, why = False, "no shared segment"
+        elif c_prefix <= 0.0:
+            ok, why = False, "empty shared prefix"
+        else:
+            c_reload = n_empty * cost.reload(True) / N
+            ok = eq2(N, c_prefix, cost.materialize(), c_reload, cost.handoff(), delta)
+            why = (f"Eq.(2): (N-1)C_prefix = {(N - 1) * c_prefix:.4g} B "
+                   f"{'>' if ok else '<='} C_mat + N(C_reload + C_handoff) + delta = "
+                   f"{cost.materialize() + N * (c_reload + cost.handoff()) + delta:.4g} B")
+            if decide is not None:
+                d = decide(v, c_prefix, est_direct, est_reuse)
+                if d is not None:
+                    why += f"; learned model: {'reuse' if d else 'abstain'}"
+                    ok = bool(d)
+        v.decision = "REUSE" if ok else "ABSTAIN"
+        v.reason = why
+        if ok:
+            materialized.append(vid)
+        for c in v.children:
+            anchor_of[c] = vid if ok else a
+        if ok:
+            anchor_of[vid] = vid
+    anchor: List[Optional[int]] = [None] * len(tasks)
+    for v in nodes:
+        for t in v.ending:
+            anchor[t] = anchor_of.get(v.id) if v.id not in materialized else v.id
+    root = nodes[0] if nodes else None
+    # whole-workload estimates (direct: every task from |0>)
+    est_direct = sum(suffix_costs(0).values()) + (root.seg_bytes * len(tasks) if root else 0.0)
+    est_reuse = 0.0
+    for vid in materialized:
+        est_reuse += nodes[vid].c_prefix
+    for t in range(len(tasks)):
+        a = anchor[t]
+        start = nodes[a].end if a is not None else 0
+        est_reuse += cost.segment(tasks[t][start:]) if start < len(tasks[t]) else cost.reload(True)
+    decision = "REUSE" if materialized else "ABSTAIN"
+    reason = (f"{len(materialized)} boundary state(s) materialized" if materialized else
+              ("no node passes Eq.(2)" if len(tasks) > 1 else "single task"))
+    return Plan(n=n, nodes=nodes, materialized=materialized, anchor=anchor, decision=decision,
+                reason=reason, est_direct=est_direct, est_reuse=est_reuse,
+                planning_ms=(time.perf_counter() - t0) * 1e3)
+
+
+# ---------------------------------------------------------------- records
+@dataclass
+class ExecutionResult:
+    expectations: Optional[List[float]] = None
+    samples: Optional[np.ndarray] = None     # [task, shot] basis indices
+    states: Optional[List[np.ndarray]] = None
+
+    def to_json(self) -> str:
+        d = {"expectations": self.expectations,
+             "samples": None if self.samples is None else self.samples.tolist()}
+        return json.dumps(d)
+
+
+@dataclass
+class ExplainTrace:
+    workload: str
+    decision: str
+    reason: str
+    nodes: List[dict]
+    refusals: List[dict]
+
+    def to_json(self) -> str:
+        return json.dumps(asdict(self))
+
+
+@dataclass
+class CostRecord:
+    plan: str
+    predicted_direct_bytes: float
+    predicted_reuse_bytes: float
+    planning_ms: float
+    realized_ms: Dict[str, float]
+
+    def to_json(self) -> str:
+        return json.dumps(asdict(self))
+
+
+def _explain(name: str, plan: Plan, tasks: Sequence[Sequence[Gate]], n: int,
+             refusals: List[dict]) -> ExplainTrace:
+    rows = []
+    for v in plan.nodes:
+        fp = fingerprint(n, tasks[v.tasks[0]][:v.end]).hex() if v.decision == "REUSE" else None
+        rows.append({"id": v.id, "depth": v.depth, "parent": v.parent, "gates": [v.start, v.end],
+                     "tasks": len(v.tasks), "decision": v.decision, "reason": v.reason,
+                     "c_prefix_bytes": v.c_prefix, "est_direct_bytes": v.est_direct,
+                     "est_reuse_bytes": v.est_reuse, "delta_bytes": v.delta,
+                     "provenance": fp})
+    return ExplainTrace(workload=name, decision=plan.decision, reason=plan.reason, nodes=rows,
+                        refusals=refusals)
+
+
+# ---------------------------------------------------------------- executor
+def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots: int = 0,
+                 seed: int = 0, name: str = "workload", mode: str = "plan",
+                 plan: Optional[Plan] = None, keep_states: bool = False,
+                 cost: Optional[CostModel] = None, decide=None,
+                 ) -> Tuple[ExecutionResult, ExplainTrace, CostRecord]:
+    """Plan and execute a workload of related tasks on the ctx's GPU.
+
+    mode "plan": the planner's decision; "direct": every task from |0...0>
+    with the same segment cuts (the reference for bit-identity); "reuse":
+    materialize every shared node regardless of cost."""
+    from . import binding as B
+    t_plan0 = time.perf_counter()
+    if plan is None:
+        if mode == "reuse":
+            plan = plan_workload(n, tasks, cost, decide=lambda *a: True)
+        else:
+            plan = plan_workload(n, tasks, cost, decide=decide)
+    planning_ms = (time.perf_counter() - t_plan0) * 1e3
+    nodes = plan.nodes
+    T = len(tasks)
+    mats = list(plan.materialized)
+    refusals: List[dict] = []
+    realized: Dict[str, float] = {}
+    slot_of = {vid: i for i, vid in enumerate(mats)}
+    n_slots = len(mats) + T
+    st = B.State(ctx, n, n_slots)
+    task_slots = [len(mats) + t for t in range(T)]
+
+    def anchor_chain(vid: Optional[int]) -> List[int]:
+        """Materialized nodes from the root down to vid."""
+        if vid is None:
+            return []
+        return [u for u in path_to(nodes, vid) if u in slot_of]
+
+    def segment_cuts(t: int) -> List[int]:
+        a = plan.anchor[t]
+        return [nodes[u].end for u in anchor_chain(a)]
+
+    t0 = time.perf_counter()
+    if mode == "direct":
+        # each task alone, cut at the same boundaries as the reuse plan
+        st.reset(len(mats), T)
+        cuts = [segment_cuts(t) for t in range(T)]
+        levels = max((len(c) for c in cuts), default=0)
+        for lev in range(levels + 1):
+            batch, dsts = [], []
+            for t in range(T):
+                if lev > len(cuts[t]):
+                    continue
+                b0 = 0 if lev == 0 else cuts[t][lev - 1]
+                b1 = cuts[t][lev] if lev < len(cuts[t]) else len(tasks[t])
+                if b1 > b0:
+                    batch.append(list(tasks[t][b0:b1]))
+                    dsts.append(task_slots[t])
+            if batch:
+                B.run_suffix_batch(ctx, None, batch, st, dsts)
+        ctx.sync()
+        realized["suffix"] = (time.perf_counter() - t0) * 1e3
+    else:
+        # materialized nodes by depth: each from its nearest materialized ancestor
+        snaps: Dict[int, object] = {}
+        by_depth: Dict[int, List[int]] = {}
+        for vid in mats:
+            by_depth.setdefault(nodes[vid].depth, []).append(vid)
+        for d in sorted(by_depth):
+            srcs, gl, dsts, provs = [], [], [], []
+            for vid in by_depth[d]:
+                chain = anchor_chain(nodes[vid].parent)
+                a = chain[-1] if chain else None
+                b0 = nodes[a].end if a is not None else 0
+                gl.append(list(tasks[nodes[vid].tasks[0]][b0:nodes[vid].end]))
+                dsts.append(slot_of[vid])
+                srcs.append(snaps.get(a))
+                provs.append(snaps[a].provenance if a is not None else bytes(32))
+            for s in dsts:
+                st.reset(s, 1)
+            any_src = any(s is not None for s in srcs)
+            B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
+                               expect_provs=provs if any_src else None)
+            for vid in by_depth[d]:
+                fp = fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end])
+                snaps[vid] = st.snapshot(slot_of[vid], fp, B.QW_SNAP_FREEZE)
+        ctx.sync()
+        realized["prefix"] = (time.perf_counter() - t0) * 1e3
+        t1 = time.perf_counter()
+        srcs, gl, dsts, provs = [], [], [], []
+        for t in range(T):
+            a = plan.anchor[t]
+            b0 = nodes[a].end if a is not None else 0
+            srcs.append(snaps.get(a) if a is not None else None)
+            gl.append(list(tasks[t][b0:]))
+            dsts.append(task_slots[t])
+            provs.append(snaps[a].provenance if a is not None else bytes(32))
+        direct = [t for t in range(T) if srcs[t] is None]
+        if direct:
+            for t in direct:
+                st.reset(task_slots[t], 1)
+        try:
+            B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
+                               expect_provs=provs if len(direct) < T else None)
+        except B.QwRefused as r:
+            # structured refusal: record it and rerun every task from |0...0>
+            refusals.append(r.record)
+            st.reset(len(mats), T)
+            B.run_suffix_batch(ctx, None, [list(tk) for tk in tasks], st, dsts)
+        ctx.sync()
+        realized["suffix"] = (time.perf_counter() - t1) * 1e3
+        for s in snaps.values():
+            s.free()
+    t2 = time.perf_counter()
+    res = ExecutionResult()
+    if terms is not None and T:
+        res.expectations = list(st.expect(len(mats), T, terms))
+    if shots and T:
+        res.samples = st.sample(len(mats), T, seed, 0, shots).reshape(T, shots)
+    if keep_states:
+        res.states = [st.host(s) for s in task_slots]
+    ctx.sync()
+    realized["reduce"] = (time.perf_counter() - t2) * 1e3
+    realized["total"] = (time.perf_counter() - t0) * 1e3
+    st.free()
+    trace = _explain(name, plan, tasks, n, refusals)
+    rec = CostRecord(plan="direct" if mode == "direct" else plan.decision.lower(),
+                     predicted_direct_bytes=plan.est_direct, predicted_reuse_bytes=plan.est_reuse,
+                     planning_ms=planning_ms, realized_ms=realized)
+    return res, trace, rec
