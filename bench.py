@@ -27,6 +27,10 @@ def _parse():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--cpu-tasks", type=int, default=1,
                     help="tasks in the oracle's bounded CPU sample")
+    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep"],
+                    help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "
+                         "tree, 512 leaves, 1024 shots; noisy: 22-qubit 256 trajectories, 1024 "
+                         "shots; sweep: gate-pass HBM bandwidth over qubits and sizes")
     return ap.parse_args()
 
 
@@ -42,6 +46,11 @@ def main():
     from paper_2609_23664_amd.planner import fingerprint
     from workloads import gen
 
+    if args.workload != "vqe":
+        extra = {"trie": bench_trie, "noisy": bench_noisy, "sweep": bench_sweep}[args.workload]
+        print(json.dumps(extra(args)), flush=True)
+        return
+
     assert torch.cuda.is_available(), "no GPU"
     w = gen.config2()
     n, T = w.n, w.n_tasks
@@ -54,6 +63,13 @@ def main():
     # first, untimed step does)
     prefix = B.GateArray(w.prefix)
     suffixes = [B.GateArray(s) for s in w.suffixes]
+    # generated kernels of the workload (compiled, or loaded from the disk
+    # cache) before timing: the compile step, reported separately
+    t_c = time.perf_counter()
+    B.jit_precompile(n, prefix)
+    B.jit_precompile(n, suffixes[0])
+    B.jit_precompile_terms(n, terms)
+    jit_setup_s = time.perf_counter() - t_c
 
     # ---- reuse path: slot 0 = boundary, slots 1..T = tasks
     st = B.State(ctx, n, T + 1)
@@ -113,6 +129,7 @@ def main():
         "data": "synthetic (seeded HEA angles and Pauli terms)",
         "config": {"workload": w.name, "qubits": n, "tasks": T, "prefix_layers": 6,
                    "suffix_layers": 2, "terms": len(terms), "parallelism": "single GPU"},
+        "jit_setup_s": round(jit_setup_s, 3),
     }
     if dst is not None:
         dt_d, e_d, _ = timed(direct_step, args.steps, args.warmup)
@@ -136,6 +153,129 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_tasks)
     print(json.dumps(result), flush=True)
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def bench_sweep(args):
+    """Gate-pass HBM bandwidth: single gates on qubits across the index
+    (low, lane, register, high), passes of 1/8/24 gates, at 20..28 qubits,
+    with enough slots (>= 4 GiB working set, <= 64 slots) to defeat the
+    256 MB last-level cache. GB/s = algorithmic bytes (each pass reads and
+    writes the state once) / kernel time (HIP events around each launch)."""
+    import torch
+    from paper_2609_23664_amd import binding as B
+    ctx = B.Ctx(0)
+    rows = []
+    for n in (20, 22, 24, 26, 28):
+        sb = 8 << n
+        slots = max(1, min(64, (4 << 30) // sb))
+        st = B.State(ctx, n, slots)
+        qs = sorted({0, 1, 2, 3, 4, 8, 12, 16, 20, n - 1} & set(range(n)))
+        cases = [(f"RY q{q}", [("RY", (q,), 0.3)]) for q in qs]
+        cases += [("RY+RZ 8 low", [g for q in range(4) for g in (("RY", (q,), 0.3), ("RZ", (q,), 0.2))]),
+                  ("24 gates HEA slab", [g for q in range(8) for g in (("RY", (q,), 0.3), ("RZ", (q,), 0.2))]
+                   + [("CNOT", (q, q + 1), 0.0) for q in range(7)] + [("RY", (q,), 0.1) for q in range(1)])]
+        for name, gates in cases:
+            ga = B.GateArray(gates)
+            B.run_suffix_batch(ctx, None, [ga] * slots, st, list(range(slots)))
+            torch.cuda.synchronize()
+            ctx.set_option(B.QW_OPT_PROFILE, 1)
+            ctx.kernel_stats(0, True)
+            for _ in range(5):
+                B.run_suffix_batch(ctx, None, [ga] * slots, st, list(range(slots)))
+            nl, ms, by = ctx.kernel_stats(0, True)
+            ctx.set_option(B.QW_OPT_PROFILE, 0)
+            rows.append({"n": n, "case": name, "gates": len(gates), "slots": slots,
+                         "passes_per_call": nl // 5, "GB/s": round(by / (ms * 1e-3) / 1e9, 1)})
+        # copy bandwidth of the same working set (snapshot COPY kernel)
+        snap = st.snapshot(0, bytes(32), B.QW_SNAP_COPY)
+        snap.free()
+        a = torch.empty((slots, 1 << n), dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.copy_(a)
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        rows.append({"n": n, "case": "torch copy (reference)", "slots": slots,
+                     "GB/s": round(2 * a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)})
+        del a, b
+        st.free()
+    gates_rows = [r for r in rows if "passes_per_call" in r]
+    med = _median([r["GB/s"] for r in gates_rows])
+    return {"metric": "gate-sweep HBM GB/s (median over cases)", "value": med, "unit": "GB/s",
+            "n_gpus": 1, "higher_is_better": True, "frac_of_8TBs": round(med / 8000.0, 4),
+            "min": min(r["GB/s"] for r in gates_rows), "max": max(r["GB/s"] for r in gates_rows),
+            "dtype": "c64", "data": "synthetic", "config": {"workload": "gate sweep 20..28q"},
+            "rows": rows}
+
+
+def _run_planned(args, n, tasks, shots, seed, name):
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd import planner as P
+    ctx = B.Ctx(0)
+    plan = P.plan_workload(n, tasks)
+    out = {}
+    for mode in ("plan", "direct"):
+        P.run_workload(ctx, n, tasks, shots=shots, seed=seed, plan=plan, mode=mode)  # warm-up
+        torch.cuda.synchronize()
+        times, res = [], None
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            res, trace, rec = P.run_workload(ctx, n, tasks, shots=shots, seed=seed, plan=plan, mode=mode)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[mode] = (_median(times), res, rec)
+    return plan, out
+
+
+def bench_trie(args):
+    """Config 3: 20 qubits, prefix tree depth 3 x branching 8 (72 shared
+    nodes), 512 leaves with 1..12 extra layers, 1024 Z-basis shots each."""
+    from workloads import gen
+    w = gen.config3()
+    tasks = [w.leaf_path(k) for k in range(len(w.leaves))]
+    plan, out = _run_planned(args, w.n, tasks, w.shots, w.seed, w.name)
+    tp, rp, recp = out["plan"]
+    td, rd, _ = out["direct"]
+    same = bool((rp.samples == rd.samples).all())
+    T = len(tasks)
+    return {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)", "value": round(T / tp, 2),
+            "unit": "tasks/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+            "samples_per_s": round(T * w.shots / tp, 1), "direct_tasks_per_s": round(T / td, 2),
+            "speedup_vs_direct": round(td / tp, 3), "samples_equal_direct": same,
+            "materialized_nodes": len(plan.materialized), "planning_ms": round(plan.planning_ms, 1),
+            "realized_ms": recp.realized_ms, "dtype": "c64", "data": "synthetic",
+            "config": {"workload": w.name, "qubits": w.n, "leaves": T, "shots": w.shots}}
+
+
+def bench_noisy(args):
+    """Config 4: 22 qubits, 10 noiseless shared layers, 256 trajectories of
+    a 4-layer suffix with Pauli jumps (p = 1e-3 per gate and qubit, FP64
+    renormalisation after each jump), 1024 Z-basis shots each."""
+    from workloads import gen
+    w = gen.config4()
+    tasks = [list(w.prefix) + list(t) for t in w.trajectories]
+    plan, out = _run_planned(args, w.n, tasks, w.shots, w.seed, w.name)
+    tp, rp, recp = out["plan"]
+    td, rd, _ = out["direct"]
+    T = len(tasks)
+    jumps = sum(1 for t in w.trajectories for g in t if g[0] == "RENORM")
+    return {"metric": "noisy trajectories/s at 22q (256 x 1024 shots)", "value": round(T / tp, 2),
+            "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+            "direct_trajectories_per_s": round(T / td, 2), "speedup_vs_direct": round(td / tp, 3),
+            "samples_equal_direct": bool((rp.samples == rd.samples).all()), "jumps": jumps,
+            "jump_free": sum(1 for t in w.trajectories if t == list(w.suffix)),
+            "materialized_nodes": len(plan.materialized), "realized_ms": recp.realized_ms,
+            "dtype": "c64", "data": "synthetic",
+            "config": {"workload": w.name, "qubits": w.n, "trajectories": T, "shots": w.shots}}
 
 
 def cpu_baseline(w, k):

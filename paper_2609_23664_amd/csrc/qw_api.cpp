@@ -59,7 +59,7 @@ struct qw_ctx {
     bool profile = false;
     bool fused_epilogue = true;
     bool xcd_remap = true;
-    bool jit = true;
+    int jit = 1;  // 0: interpreted kernels, 1: tiered, 2: always generated
     uint32_t n_cu = 256;
     DevBuf plan;     // uploaded descriptors/ops
     DevBuf scratch;  // partial sums, sampler buffers
@@ -326,6 +326,11 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
     return "";
 }
 
+// Tiered generated kernels: a pass structure not yet compiled is compiled
+// when one launch runs it over at least this many tiles (task-tiles);
+// smaller one-off launches use the interpreted kernels (same results).
+constexpr uint64_t kJitHotTiles = 4096;
+
 // One task of an execution: its plan, source, destination.
 struct Exec {
     std::shared_ptr<const Plan> planp;
@@ -416,8 +421,9 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     // kernels, the tasks of one pass structure are consecutive and form one
     // launch (groups[k]: kernel, first descriptor, count).
     struct Group {
-        const JitKernel *k;
+        const JitKernel *k;  // nullptr: interpreted kernels for this group
         uint32_t first, count;
+        bool lds;
     };
     std::vector<std::vector<size_t>> order(steps);
     std::vector<std::vector<Group>> groups(steps);
@@ -448,12 +454,31 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 members[k][it->second].second.push_back(t);
             }
         }
+        // tiered: generate a kernel when it is available without compiling,
+        // or when the launch carries enough work to pay for compiling it
+        std::vector<char> want(reqs.size(), 1);
+        if (ctx->jit == 1) {
+            std::vector<uint64_t> work(reqs.size(), 0);
+            for (size_t k = 0; k < steps; ++k)
+                for (auto &gm : members[k]) work[gm.first] += (uint64_t)gm.second.size() * tiles;
+            for (size_t i = 0; i < reqs.size(); ++i)
+                want[i] = work[i] >= kJitHotTiles || jit_available(ctx->device, reqs[i]);
+        }
+        std::vector<JitReq> sel;
+        std::vector<size_t> sel_of(reqs.size(), (size_t)-1);
+        for (size_t i = 0; i < reqs.size(); ++i)
+            if (want[i]) {
+                sel_of[i] = sel.size();
+                sel.push_back(reqs[i]);
+            }
         std::vector<const JitKernel *> kern;
-        const std::string err = jit_get(ctx->device, reqs, &kern);
+        const std::string err = jit_get(ctx->device, sel, &kern);
         if (!err.empty()) return fail(ctx, QW_E_HIP, err);
         for (size_t k = 0; k < steps; ++k) {
             for (auto &gm : members[k]) {
-                groups[k].push_back({kern[gm.first], (uint32_t)order[k].size(), (uint32_t)gm.second.size()});
+                const JitKernel *kk = sel_of[gm.first] == (size_t)-1 ? nullptr : kern[sel_of[gm.first]];
+                groups[k].push_back({kk, (uint32_t)order[k].size(), (uint32_t)gm.second.size(),
+                                     reqs[gm.first].use_lds});
                 for (size_t t : gm.second) order[k].push_back(t);
             }
         }
@@ -497,9 +522,11 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         if (use_jit) {
             for (const Group &g : groups[k]) {
                 ProfScope ps(ctx, 0, (double)g.count * 2.0 * (double)state_bytes);
-                hipError_t er = jit_launch(ctx->stream, *g.k, dd + g.first, g.count, tiles,
-                                           ctx->xcd_remap ? 1 : 0, ctx->n_cu);
-                if (er != hipSuccess) return hip_fail(ctx, er, "generated pass launch");
+                hipError_t er = g.k ? jit_launch(ctx->stream, *g.k, dd + g.first, g.count, tiles,
+                                                 ctx->xcd_remap ? 1 : 0, ctx->n_cu)
+                                    : launch_pass(ctx->stream, dd + g.first, g.count, n, (uint32_t)m,
+                                                  ctx->xcd_remap ? 1 : 0, g.lds);
+                if (er != hipSuccess) return hip_fail(ctx, er, "pass launch");
             }
         } else {
             ProfScope ps(ctx, 0, (double)step_cnt[k] * 2.0 * (double)state_bytes);
@@ -555,7 +582,20 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
             c_off[g] = L.take(rplans[g].cols.size() * sizeof(uint32_t));
         }
     }
-    const bool use_jit = ctx->jit && !small;
+    bool use_jit = ctx->jit && !small;
+    if (use_jit && ctx->jit == 1 && (uint64_t)ns * tiles < kJitHotTiles) {
+        // tiered: small one-off reductions use the interpreted reducer unless
+        // every group's kernel is available without compiling
+        for (size_t g = 0; g < groups.size() && use_jit; ++g) {
+            JitReq r;
+            r.key = jit_reduce_key((int)n, m, groups[g], rplans[g]);
+            r.group = &groups[g];
+            r.rplan = &rplans[g];
+            r.n = (int)n;
+            r.m = m;
+            use_jit = jit_available(ctx->device, r);
+        }
+    }
     std::vector<size_t> tb_off(groups.size(), 0);
     if (use_jit)
         for (size_t g = 0; g < groups.size(); ++g) tb_off[g] = L.take((size_t)tiles * sizeof(uint32_t));
@@ -735,7 +775,10 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
     case QW_OPT_PROFILE: ctx->profile = value != 0; return QW_OK;
     case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
     case QW_OPT_XCD_REMAP: ctx->xcd_remap = value != 0; return QW_OK;
-    case QW_OPT_JIT: ctx->jit = value != 0; return QW_OK;
+    case QW_OPT_JIT:
+        if (value < 0 || value > 2) return fail(ctx, QW_E_INVALID_ARG, "jit mode must be 0, 1 or 2");
+        ctx->jit = (int)value;
+        return QW_OK;
     default: return fail(ctx, QW_E_INVALID_ARG, "unknown option");
     }
 }

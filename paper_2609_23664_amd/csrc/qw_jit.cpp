@@ -697,6 +697,20 @@ std::string compile_one(const std::string &src, std::vector<char> *code) {
 
 }  // namespace
 
+bool jit_available(int device, const JitReq &r) {
+    Registry &R = reg();
+    {
+        std::lock_guard<std::mutex> lk(R.mu);
+        if (R.kernels.count({device, r.key}) || R.code.count(r.key)) return true;
+    }
+    const std::string dir = cache_dir();
+    if (dir.empty()) return false;
+    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds)
+                                   : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
+    struct stat sb;
+    return ::stat(cache_path(dir, src).c_str(), &sb) == 0;
+}
+
 std::string jit_precompile(const std::vector<JitReq> &ks) {
     Registry &R = reg();
     // code objects still missing (in memory): disk cache, else compile in parallel

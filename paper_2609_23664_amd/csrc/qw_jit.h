@@ -62,6 +62,10 @@ hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDes
 // the disk cache, or compiled (in parallel). Returns "" or an error message.
 std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<const JitKernel *> *out);
 
+// True when the kernel of a request is loaded on `device` or its code
+// object is in the process or disk cache (no compilation).
+bool jit_available(int device, const JitReq &r);
+
 // Compile (or load from the disk cache) the code objects of the requests
 // without loading them on a device; no GPU is needed.
 std::string jit_precompile(const std::vector<JitReq> &reqs);

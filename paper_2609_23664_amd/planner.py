@@ -201,6 +201,16 @@ class Plan:
     est_direct: float
     est_reuse: float
     planning_ms: float
+    # marshalled gate segments (task, start, end) -> GateArray, filled on use
+    arrays: Dict[Tuple[int, int, int], object] = field(default_factory=dict)
+
+    def segment_array(self, tasks, t: int, b0: int, b1: int):
+        key = (t, b0, b1)
+        a = self.arrays.get(key)
+        if a is None:
+            from .binding import GateArray
+            a = self.arrays[key] = GateArray(list(tasks[t][b0:b1]))
+        return a
 
 
 def plan_workload(n: int, tasks: Sequence[Sequence[Gate]], cost: Optional[CostModel] = None,
@@ -402,7 +412,7 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
                 b0 = 0 if lev == 0 else cuts[t][lev - 1]
                 b1 = cuts[t][lev] if lev < len(cuts[t]) else len(tasks[t])
                 if b1 > b0:
-                    batch.append(list(tasks[t][b0:b1]))
+                    batch.append(plan.segment_array(tasks, t, b0, b1))
                     dsts.append(task_slots[t])
             if batch:
                 B.run_suffix_batch(ctx, None, batch, st, dsts)
@@ -420,7 +430,7 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
                 chain = anchor_chain(nodes[vid].parent)
                 a = chain[-1] if chain else None
                 b0 = nodes[a].end if a is not None else 0
-                gl.append(list(tasks[nodes[vid].tasks[0]][b0:nodes[vid].end]))
+                gl.append(plan.segment_array(tasks, nodes[vid].tasks[0], b0, nodes[vid].end))
                 dsts.append(slot_of[vid])
                 srcs.append(snaps.get(a))
                 provs.append(snaps[a].provenance if a is not None else bytes(32))
@@ -440,7 +450,7 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
             a = plan.anchor[t]
             b0 = nodes[a].end if a is not None else 0
             srcs.append(snaps.get(a) if a is not None else None)
-            gl.append(list(tasks[t][b0:]))
+            gl.append(plan.segment_array(tasks, t, b0, len(tasks[t])))
             dsts.append(task_slots[t])
             provs.append(snaps[a].provenance if a is not None else bytes(32))
         direct = [t for t in range(T) if srcs[t] is None]
@@ -454,7 +464,8 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
             # structured refusal: record it and rerun every task from |0...0>
             refusals.append(r.record)
             st.reset(len(mats), T)
-            B.run_suffix_batch(ctx, None, [list(tk) for tk in tasks], st, dsts)
+            B.run_suffix_batch(ctx, None, [plan.segment_array(tasks, t, 0, len(tasks[t]))
+                                           for t in range(T)], st, dsts)
         ctx.sync()
         realized["suffix"] = (time.perf_counter() - t1) * 1e3
         for s in snaps.values():

@@ -1,4 +1,5 @@
-"""Generated (run-time compiled) pass kernels against the interpreted ones.
+"""Generated (run-time compiled) pass kernels against the interpreted ones
+(QW_OPT_JIT 2 = always generated, 0 = always interpreted).
 
 Both forms run the same tile operations with the same rounding, so the states
 must be bit-identical; the oracle bar is checked too. Every case prints its
@@ -54,7 +55,7 @@ def _random_gates(n, g, count, renorm=0.0):
 
 def _both(B, ctx, n, gates, slots=1):
     out = []
-    for jit in (0, 1):
+    for jit in (0, 2):
         ctx.set_option(B.QW_OPT_JIT, jit)
         st = B.State(ctx, n, slots)
         st.apply(slots - 1, gates)
@@ -98,7 +99,7 @@ def test_generated_batch_mixed_structures(ctx, B):
     other = _random_gates(n, g, 60)
     sufs = list(w1.suffixes) + [other, other]
     res = []
-    for jit in (0, 1):
+    for jit in (0, 2):
         ctx.set_option(B.QW_OPT_JIT, jit)
         st = B.State(ctx, n, 1 + len(sufs))
         st.apply(0, w1.prefix)
@@ -143,7 +144,7 @@ def test_generated_reducer_equals_interpreted(ctx, B, n, tile):
     ctx.set_option(B.QW_OPT_TILE_BITS, tile)
     try:
         res = []
-        for jit in (0, 1):
+        for jit in (0, 2):
             ctx.set_option(B.QW_OPT_JIT, jit)
             res.append(np.asarray(st.expect(0, 3, terms)))
     finally:
@@ -155,3 +156,24 @@ def test_generated_reducer_equals_interpreted(ctx, B, n, tile):
         ref = oracle.expect(oracle.simulate(n, w.task_gates(t)), n, terms)
         assert abs(res[1][t] - ref) <= 1e-5 * scale
     st.free()
+
+
+def test_tiered_mode_mixes_forms_bitwise(ctx, B):
+    """Tiered mode: a batch whose structures are partly compiled and partly
+    interpreted gives the same states as either pure form."""
+    say("jit tiered mixed")
+    n = 15
+    g = np.random.default_rng(77)
+    hot = _random_gates(n, g, 50)          # 8 tasks x 2 tiles... compiled (always mode first)
+    cold = _random_gates(n, g, 50)
+    ctx.set_option(B.QW_OPT_JIT, 2)
+    B.jit_precompile(n, hot)
+    res = []
+    for mode in (1, 0):
+        ctx.set_option(B.QW_OPT_JIT, mode)
+        st = B.State(ctx, n, 2)
+        B.run_suffix_batch(ctx, None, [hot, cold], st, [0, 1])
+        res.append([st.host(0), st.host(1)])
+        st.free()
+    ctx.set_option(B.QW_OPT_JIT, 1)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
