@@ -173,6 +173,13 @@ bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
     auto ph = [](cd z) { return z / std::abs(z); };
     auto small = [](double x) { return std::fabs(x) < 1e-13; };
     auto pick = [&](cd first, cd other) { return std::abs(first) > 1e-9 ? ph(first) : ph(other); };
+    // a real matrix is its own R (no sign-dependent phase factors)
+    if (M.a.imag() == 0.0 && M.b.imag() == 0.0 && M.c.imag() == 0.0 && M.d.imag() == 0.0) {
+        *D2 = {1.0, 0.0, 0.0, 1.0};
+        *R = M;
+        *D1 = {1.0, 0.0, 0.0, 1.0};
+        return true;
+    }
     // row phases: M = diag(p0, p1) * R
     {
         cd p0 = pick(M.a, M.b);
@@ -353,18 +360,31 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
 }
 
 // Rewrite real rotations [[p, -q], [q, p]] as p * [[1, -t], [t, 1]] and
-// reflections [[p, q], [q, -p]] as p * [[1, t], [t, -1]] (t = q / p), and
-// fold the product of the factors p (the same for every amplitude) into the
-// first diagonal op of the pass, in FP64. The form never depends on the
-// angle, so tasks that differ only in angles keep one kernel. A large t
-// costs no accuracy (the FMA rounds x - t y once and t's rounding weighs
-// |q y|, as in the plain product); the only limit is the FP32 range of the
-// intermediate amplitudes, which grow by at most the product of the 1/|p|:
-// ops that would push it past 2^60 (angles within ~1e-18 of pi) keep the
-// plain form.
+// reflections [[p, q], [q, -p]] as p * [[1, t], [t, -1]] (t = q / p). The
+// factors p of the rotations between two diagonal ops are multiplied (in
+// FP64) into the next diagonal op (else the previous one, else a new one at
+// the end of the pass): a global factor, so where it is applied does not
+// matter, and the FP32 amplitudes in between grow by at most the product
+// of those 1/|p|. The form never depends on the angle, so tasks that differ
+// only in angles keep one kernel; a large t costs no accuracy (the FMA
+// rounds x - t y once and t's rounding weighs |q y|, as in the plain
+// product). Only a group whose growth would pass 2^60 (angles within ~1e-9
+// of pi) keeps its remaining rotations in the plain form.
 void tangent_form(std::vector<HostOp> &ops) {
-    double scale = 1.0, growth = 0.0;  // growth in log2
+    double pending = 1.0, growth = 0.0;  // growth in log2, since the last diagonal op
+    HostOp *last_diag = nullptr;
+    auto scale_op = [](HostOp &op, double f) {
+        HostOp *d = op.type == OP_DSET ? &op.members[0] : &op;
+        for (int k = 0; k < 4; ++k) d->m[k] *= f;
+    };
     for (HostOp &op : ops) {
+        if (op.type == OP_DSET || op.type == OP_DIAG) {
+            if (pending != 1.0) scale_op(op, pending);
+            pending = 1.0;
+            growth = 0.0;
+            last_diag = &op;
+            continue;
+        }
         if (op.type != OP_UR) continue;
         const double a = op.m[0], b = op.m[1], c = op.m[2], d = op.m[3];
         const double tol = 1e-14 * (std::fabs(a) + std::fabs(b) + std::fabs(c) + std::fabs(d));
@@ -378,28 +398,26 @@ void tangent_form(std::vector<HostOp> &ops) {
             t = b / a;
         }
         if (form < 0 || a == 0.0) continue;
-        const double g = -std::log2(std::fabs(a));
-        if (growth + std::max(g, 0.0) > 60.0) continue;
-        growth += std::max(g, 0.0);
+        const double g = std::max(-std::log2(std::fabs(a)), 0.0);
+        if (growth + g > 60.0) continue;
+        growth += g;
         op.type = OP_URT;
         op.b = form;
         op.m[0] = t;
         op.m[1] = op.m[2] = op.m[3] = 0.0;
-        scale *= a;
+        pending *= a;
     }
-    if (scale == 1.0) return;
-    for (HostOp &op : ops) {
-        HostOp *d = op.type == OP_DSET ? &op.members[0] : (op.type == OP_DIAG ? &op : nullptr);
-        if (!d) continue;
-        for (int k = 0; k < 4; ++k) d->m[k] *= scale;
+    if (pending == 1.0) return;
+    if (last_diag) {
+        scale_op(*last_diag, pending);
         return;
     }
     HostOp set, d;
     set.type = OP_DSET;
     d.type = OP_PDIAG;
     d.mask = 0;
-    d.m[0] = scale;
-    d.m[2] = scale;
+    d.m[0] = pending;
+    d.m[2] = pending;
     set.members.push_back(d);
     ops.push_back(set);
 }

@@ -203,3 +203,26 @@ def test_vqe_tasks_share_one_pass_structure():
     ref = shape(B.plan_describe(24, w.suffixes[0]))
     for t in range(1, w.n_tasks):
         assert shape(B.plan_describe(24, w.suffixes[t])) == ref
+
+
+def test_trie_leaves_of_equal_length_share_structure():
+    """Leaf segments with the same gate kinds and qubits but different
+    angles lower to the same ops (rotations in a factor-free form whose
+    factors are folded per group into diagonal ops, real matrices split
+    without sign-dependent phases)."""
+    w = gen.small_trie(20, 2, 6, 2, 3, seed=303, shots=0)
+
+    def shape(pl):
+        return [[(o["type"], o["a"], o["b"], o["la"], o["lb"], o["sa"], o["sb"]) for o in p["ops"]]
+                for p in pl["passes"]]
+    by = {}
+    for _, gates in w.leaves:
+        key = tuple((g[0], tuple(g[1])) for g in gates)
+        by.setdefault(key, []).append(gates)
+    checked = 0
+    for group in by.values():
+        ref = shape(B.plan_describe(20, group[0]))
+        for gates in group[1:]:
+            assert shape(B.plan_describe(20, gates)) == ref
+            checked += 1
+    assert checked >= 3
