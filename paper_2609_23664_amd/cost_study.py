@@ -1,0 +1,100 @@
+"""Realized-cost logging for the learned cost model.
+
+For a workload (one shared prefix, T tasks with their own suffixes) this
+module computes the planner features (host-only, from the library's pass
+counts) and realizes the workload on the GPU under both plans: direct per
+task (every task from |0...0> through prefix and suffix, with the same cut)
+and reuse (prefix once, frozen snapshot, suffixes from it). Workloads with
+more than `max_tasks` tasks are realized on their first `max_tasks` tasks
+and scaled linearly:
+    t_direct(T) = t_direct(k) * T / k,
+    t_reuse(T)  = t_prefix + (t_reuse(k) - t_prefix) * T / k.
+Kernels are the interpreted ones (QW_OPT_JIT = 0), so no compile time enters
+a label. Run as a module to log the config-5 study:
+    python -m paper_2609_23664_amd.cost_study --out costs.jsonl --count 2000
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+N_FEATURES = 12
+
+
+def features(n: int, prefix: Sequence, suffixes: Sequence[Sequence], n_tasks: int,
+             tile_bits: int = 14) -> List[float]:
+    """Planner features of a single-prefix workload (all scaled to O(1)):
+    qubits, log2 tasks, prefix passes, mean/max/min suffix passes, suffix
+    spread, log2 state bytes, log analytic direct / reuse bytes, analytic
+    ratio, prefix fraction of the gates, shared-prefix flag."""
+    from .binding import plan_cost
+    pp = plan_cost(n, list(prefix), tile_bits)[0] if prefix else 0
+    sp = [plan_cost(n, list(s), tile_bits)[0] for s in suffixes] or [0]
+    sb = 8.0 * (1 << n)
+    est_direct = n_tasks * (pp + float(np.mean(sp))) * 2 * sb
+    est_reuse = (pp + n_tasks * float(np.mean(sp))) * 2 * sb
+    gates_p = len(prefix)
+    gates_s = float(np.mean([len(s) for s in suffixes])) if suffixes else 0.0
+    return [n / 26.0, math.log2(max(1, n_tasks)) / 8.0, pp / 32.0, float(np.mean(sp)) / 32.0,
+            max(sp) / 32.0, min(sp) / 32.0, (max(sp) - min(sp)) / 16.0, math.log2(sb) / 32.0,
+            math.log(max(est_direct, 1.0)) / 40.0, math.log(max(est_reuse, 1.0)) / 40.0,
+            min(est_direct / max(est_reuse, 1.0), 20.0) / 10.0,
+            gates_p / max(1.0, gates_p + gates_s)]
+
+
+def realize(ctx, n: int, prefix, suffixes, n_tasks: int) -> Dict[str, float]:
+    """Realized ms of direct and reuse execution (scaled to n_tasks)."""
+    from . import binding as B
+    from .planner import run_workload, plan_workload
+    k = len(suffixes)
+    tasks = [list(prefix) + list(s) for s in suffixes]
+    plan = plan_workload(n, tasks, decide=lambda *a: True)   # cuts at the shared prefix
+    ctx.set_option(B.QW_OPT_JIT, 0)
+    try:
+        _, _, rd = run_workload(ctx, n, tasks, plan=plan, mode="direct")
+        _, _, rr = run_workload(ctx, n, tasks, plan=plan, mode="reuse")
+    finally:
+        ctx.set_option(B.QW_OPT_JIT, 1)
+    td = rd.realized_ms["total"] * n_tasks / k
+    tp = rr.realized_ms.get("prefix", 0.0)
+    tr = tp + (rr.realized_ms["total"] - tp) * n_tasks / k
+    return {"t_direct_ms": td, "t_reuse_ms": tr, "t_prefix_ms": tp, "tasks_run": k}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--count", type=int, default=2000)
+    ap.add_argument("--first", type=int, default=0)
+    ap.add_argument("--max-tasks", type=int, default=16)
+    args = ap.parse_args(argv)
+    from . import binding as B
+    from workloads import gen
+    ctx = B.Ctx(0)
+    specs = gen.config5_specs(args.count)[args.first:]
+    t0 = time.time()
+    with open(args.out, "a") as f:
+        for i, s in enumerate(specs):
+            w = gen.config5_workload(s, max_tasks=args.max_tasks)
+            feats = features(w.n, w.prefix, w.suffixes, s.n_tasks)
+            r = realize(ctx, w.n, w.prefix, w.suffixes, s.n_tasks)
+            rec = {"index": s.index, "n": s.n, "tasks": s.n_tasks, "prefix_layers": s.prefix_layers,
+                   "total_layers": s.total_layers, "spread": s.spread, "negative": s.negative,
+                   "features": feats, **r}
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            if i % 50 == 0:
+                print(f"[cost-study] {i + args.first}/{args.count} n={s.n} T={s.n_tasks} "
+                      f"direct={r['t_direct_ms']:.2f}ms reuse={r['t_reuse_ms']:.2f}ms "
+                      f"elapsed={time.time() - t0:.0f}s", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
