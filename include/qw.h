@@ -250,6 +250,34 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
               uint64_t seed, uint64_t task_base, uint32_t shots,
               uint32_t *out, int out_is_host);
 
+/* ------------------------------------------------------------ learned cost model
+ * A 3-layer perceptron predicting (log direct time, log reuse time) from
+ * QW_MLP_IN planner features, used by the planner's reuse decision (with
+ * the analytic Eq. (2) rule as fallback; results never depend on it).
+ * Layout of the FP32 parameter array (QW_MLP_PARAMS floats, device memory):
+ *   W1[12][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2]
+ * (row-major; W[k][j] multiplies input k into output j), ReLU after the two
+ * hidden layers. Every matrix product rounds both inputs to BF16 (round to
+ * nearest even) and accumulates in FP32 on the matrix cores; everything else
+ * is FP32. Inputs are x[B][12] (row-major), targets t[B][2]. All pointers
+ * are device pointers; work is enqueued on the ctx stream; work must hold
+ * qw_mlp_workspace_floats(B) floats. */
+#define QW_MLP_IN 12
+#define QW_MLP_WIDTH 64
+#define QW_MLP_OUT 2
+#define QW_MLP_PARAMS 5122
+uint64_t qw_mlp_workspace_floats(uint32_t batch);
+/* y[B][2] = MLP(x). */
+int qw_mlp_forward(qw_ctx *ctx, const float *params, const float *x, uint32_t batch, float *work,
+                   float *y);
+/* grad = dL/dparams for L = 1/(2B) sum_{b,j} (y[b][j] - t[b][j])^2 (runs the
+ * forward pass into work first). Batch reductions run in a fixed order. */
+int qw_mlp_backward(qw_ctx *ctx, const float *params, const float *x, const float *target,
+                    uint32_t batch, float *work, float *grad);
+/* One Adam step (step counts from 1) on all QW_MLP_PARAMS parameters. */
+int qw_mlp_adam(qw_ctx *ctx, float *params, const float *grad, float *m, float *v, uint32_t step,
+                float lr, float beta1, float beta2, float eps);
+
 /* ------------------------------------------------------------ host-only */
 /* Legality of continuing `src` on a target of kind `target_kind` and
  * backend family `target_backend` (Sec. IV-B, Table II). Returns QW_OK when

@@ -50,6 +50,7 @@ EXPORTED = (
     "qw_state_reset", "qw_state_slot_ptr", "qw_apply_prefix", "qw_snapshot",
     "qw_snapshot_free", "qw_snapshot_info", "qw_run_suffix_batch",
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
+    "qw_mlp_workspace_floats", "qw_mlp_forward", "qw_mlp_backward", "qw_mlp_adam",
     "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_stats", "qw_version",
 )
 
@@ -144,6 +145,11 @@ def lib() -> ctypes.CDLL:
         "qw_sample": ([vp, u32, u32, u64, u64, u32, vp, i32], i32),
         "qw_legality_check": ([ctypes.POINTER(QwArtifact), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_plan_describe": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
+        "qw_mlp_workspace_floats": ([u32], u64),
+        "qw_mlp_forward": ([vp, vp, vp, u32, vp, vp], i32),
+        "qw_mlp_backward": ([vp, vp, vp, vp, u32, vp, vp], i32),
+        "qw_mlp_adam": ([vp, vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float], i32),
         "qw_plan_cost": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.POINTER(u64),
                           ctypes.POINTER(ctypes.c_double)], i32),
         "qw_jit_precompile": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),

@@ -1083,6 +1083,30 @@ int qw_legality_check(const qw_artifact *src, uint32_t target_kind, uint32_t tar
     return QW_E_REFUSED;
 }
 
+uint64_t qw_mlp_workspace_floats(uint32_t batch) { return mlp_workspace_floats(batch); }
+
+int qw_mlp_forward(qw_ctx *ctx, const float *params, const float *x, uint32_t batch, float *work,
+                   float *y) {
+    if (!ctx || !params || (batch && (!x || !work || !y))) return QW_E_INVALID_ARG;
+    hipError_t e = launch_mlp_forward(ctx->stream, params, x, batch, work, y);
+    return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp forward");
+}
+
+int qw_mlp_backward(qw_ctx *ctx, const float *params, const float *x, const float *target,
+                    uint32_t batch, float *work, float *grad) {
+    if (!ctx || !params || !grad || (batch && (!x || !target || !work))) return QW_E_INVALID_ARG;
+    if (batch == 0) return fail(ctx, QW_E_INVALID_ARG, "batch must be >= 1");
+    hipError_t e = launch_mlp_backward(ctx->stream, params, x, target, batch, work, grad);
+    return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp backward");
+}
+
+int qw_mlp_adam(qw_ctx *ctx, float *params, const float *grad, float *m, float *v, uint32_t step,
+                float lr, float beta1, float beta2, float eps) {
+    if (!ctx || !params || !grad || !m || !v || step == 0) return QW_E_INVALID_ARG;
+    hipError_t e = launch_mlp_adam(ctx->stream, params, grad, m, v, step, lr, beta1, beta2, eps);
+    return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp adam");
+}
+
 int qw_plan_cost(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
                  uint64_t *n_passes, double *bytes) {
     if (n_gates && !gates) return QW_E_INVALID_ARG;

@@ -41,4 +41,14 @@ inline uint32_t sample_chunk_bits(uint32_t n) { return n < 10 ? n : 10; }
 // One-time kernel attributes (dynamic LDS limits).
 hipError_t kernels_init();
 
+// Learned cost model (qw_mlp.hip): forward, backward (gradient of
+// L = 1/(2B) sum (y - t)^2 into grad[QW_MLP_PARAMS]) and Adam, all on st.
+size_t mlp_workspace_floats(uint32_t batch);
+hipError_t launch_mlp_forward(hipStream_t st, const float *p, const float *x, uint32_t B, float *ws,
+                              float *y);
+hipError_t launch_mlp_backward(hipStream_t st, const float *p, const float *x, const float *t,
+                               uint32_t B, float *ws, float *grad);
+hipError_t launch_mlp_adam(hipStream_t st, float *p, const float *g, float *m, float *v,
+                           uint32_t step, float lr, float b1, float b2, float eps);
+
 }  // namespace qw
