@@ -28,25 +28,33 @@ import numpy as np
 N_FEATURES = 12
 
 
-def features(n: int, prefix: Sequence, suffixes: Sequence[Sequence], n_tasks: int,
-             tile_bits: int = 14) -> List[float]:
-    """Planner features of a single-prefix workload (all scaled to O(1)):
-    qubits, log2 tasks, prefix passes, mean/max/min suffix passes, suffix
-    spread, log2 state bytes, log analytic direct / reuse bytes, analytic
-    ratio, prefix fraction of the gates, shared-prefix flag."""
-    from .binding import plan_cost
-    pp = plan_cost(n, list(prefix), tile_bits)[0] if prefix else 0
-    sp = [plan_cost(n, list(s), tile_bits)[0] for s in suffixes] or [0]
+def feature_vector(n: int, n_tasks: int, prefix_passes: float, suffix_passes: Sequence[float],
+                   prefix_gates: float, suffix_gates: float) -> List[float]:
+    """The 12 planner features (all scaled to O(1)): qubits, log2 tasks,
+    prefix passes, mean/max/min suffix passes, suffix spread, log2 state
+    bytes, log analytic direct / reuse bytes, analytic ratio (capped at
+    20), prefix fraction of the gates."""
+    sp = list(suffix_passes) or [0.0]
+    pp = float(prefix_passes)
     sb = 8.0 * (1 << n)
-    est_direct = n_tasks * (pp + float(np.mean(sp))) * 2 * sb
-    est_reuse = (pp + n_tasks * float(np.mean(sp))) * 2 * sb
-    gates_p = len(prefix)
-    gates_s = float(np.mean([len(s) for s in suffixes])) if suffixes else 0.0
-    return [n / 26.0, math.log2(max(1, n_tasks)) / 8.0, pp / 32.0, float(np.mean(sp)) / 32.0,
+    msp = float(np.mean(sp))
+    est_direct = n_tasks * (pp + msp) * 2 * sb
+    est_reuse = (pp + n_tasks * msp) * 2 * sb
+    return [n / 26.0, math.log2(max(1, n_tasks)) / 8.0, pp / 32.0, msp / 32.0,
             max(sp) / 32.0, min(sp) / 32.0, (max(sp) - min(sp)) / 16.0, math.log2(sb) / 32.0,
             math.log(max(est_direct, 1.0)) / 40.0, math.log(max(est_reuse, 1.0)) / 40.0,
             min(est_direct / max(est_reuse, 1.0), 20.0) / 10.0,
-            gates_p / max(1.0, gates_p + gates_s)]
+            prefix_gates / max(1.0, prefix_gates + suffix_gates)]
+
+
+def features(n: int, prefix: Sequence, suffixes: Sequence[Sequence], n_tasks: int,
+             tile_bits: int = 14) -> List[float]:
+    """Features of a single-prefix workload from the library's pass counts."""
+    from .binding import plan_cost
+    pp = plan_cost(n, list(prefix), tile_bits)[0] if prefix else 0
+    sp = [plan_cost(n, list(s), tile_bits)[0] for s in suffixes] or [0]
+    gs = float(np.mean([len(s) for s in suffixes])) if suffixes else 0.0
+    return feature_vector(n, n_tasks, pp, sp, len(prefix), gs)
 
 
 def realize(ctx, n: int, prefix, suffixes, n_tasks: int) -> Dict[str, float]:

@@ -215,12 +215,13 @@ class Plan:
 
 def plan_workload(n: int, tasks: Sequence[Sequence[Gate]], cost: Optional[CostModel] = None,
                   guard: float = DELTA_GUARD,
-                  decide: Optional[Callable[[Node, float, float, float], Optional[bool]]] = None,
+                  decide: Optional[Callable[[Node, dict], Optional[bool]]] = None,
                   ) -> Plan:
     """Bounded top-down search: a node is materialized when Eq. (2) holds
     for it, C_prefix being the cost from its nearest materialized ancestor.
-    `decide(node, c_prefix, est_direct, est_reuse)` may override the rule
-    (a learned cost model); returning None keeps the analytic decision."""
+    `decide(node, info)` may override the rule (a learned cost model; info
+    holds n, tasks, c_prefix, suffix_costs, state_bytes, the estimates and
+    gate counts); returning None keeps the analytic decision."""
     t0 = time.perf_counter()
     cost = cost or CostModel(n)
     nodes = build_trie(tasks)
@@ -274,7 +275,11 @@ def plan_workload(n: int, tasks: Sequence[Sequence[Gate]], cost: Optional[CostMo
                    f"{'>' if ok else '<='} C_mat + N(C_reload + C_handoff) + delta = "
                    f"{cost.materialize() + N * (c_reload + cost.handoff()) + delta:.4g} B")
             if decide is not None:
-                d = decide(v, c_prefix, est_direct, est_reuse)
+                info = {"n": n, "tasks": N, "c_prefix": c_prefix, "suffix_costs": list(suf.values()),
+                        "state_bytes": B, "est_direct": est_direct, "est_reuse": est_reuse,
+                        "prefix_gates": v.end - (nodes[a].end if a is not None else 0),
+                        "suffix_gates": float(np.mean([len(tasks[t]) - v.end for t in v.tasks]))}
+                d = decide(v, info)
                 if d is not None:
                     why += f"; learned model: {'reuse' if d else 'abstain'}"
                     ok = bool(d)

@@ -15,7 +15,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 def test_header_symbols_exported():
     hdr = open(os.path.join(ROOT, "include", "qw.h")).read()
-    declared = set(re.findall(r"^(?:int|const char \*)\s*(qw_[a-z_]+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|uint64_t|const char \*)\s*(qw_[a-z0-9_]+)\s*\(", hdr, re.M))
     assert len(declared) >= 20
     L = B.lib()
     for name in sorted(declared):

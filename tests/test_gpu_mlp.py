@@ -1,0 +1,104 @@
+"""GPU tests of the cost-model perceptron kernels against the CPU oracle
+(oracle/mlp_ref.py), and of what the trained network gains over the
+analytic rule on the logged realized costs. Every case prints its name."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2609_23664_amd import binding
+    assert torch.cuda.is_available()
+    c = binding.Ctx(0)
+    yield c
+    c.sync()
+
+
+def _data(seed, B):
+    g = np.random.default_rng(seed)
+    return (g.uniform(0, 1, size=(B, M.IN)).astype(np.float32),
+            g.normal(size=(B, M.OUT)).astype(np.float32))
+
+
+@pytest.mark.parametrize("B", [1, 17, 300])
+def test_forward_matches_bf16_mirror(ctx, B):
+    say("mlp forward", B)
+    from paper_2609_23664_amd import costmodel as CM
+    import torch
+    p = CM.init_params(3)
+    x, _ = _data(B, B)
+    mlp = CM.MLP(ctx, params=p)
+    y = mlp.predict(x)
+    _, _, ref = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_inputs=True)
+    err = np.max(np.abs(y - ref)) / max(1e-6, np.max(np.abs(ref)))
+    assert err <= 2e-5, err
+
+
+@pytest.mark.parametrize("B", [16, 255, 1600])
+def test_backward_matches_oracle(ctx, B):
+    say("mlp backward", B)
+    from paper_2609_23664_amd import costmodel as CM
+    import torch
+    p = CM.init_params(4)
+    x, t = _data(100 + B, B)
+    mlp = CM.MLP(ctx, params=p)
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    g = mlp.backward(xd, td).cpu().numpy().astype(np.float64)
+    g2 = mlp.backward(xd, td).cpu().numpy().astype(np.float64)
+    assert np.array_equal(g, g2)                       # fixed-order reductions
+    gbf = M.backward(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf16_inputs=True)
+    g64 = M.backward(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    rel_bf = np.linalg.norm(g - gbf) / np.linalg.norm(gbf)
+    rel_64 = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    assert rel_bf <= 1e-4, rel_bf          # same rounding points, FP32 vs FP64 sums
+    assert rel_64 <= 3e-2, rel_64          # BF16 inputs vs exact FP64
+    # per block (weights and biases of each layer)
+    o = 0
+    for name, shp in M.SHAPES:
+        k = int(np.prod(shp))
+        a, b = g[o:o + k], gbf[o:o + k]
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b) + 1e-9, name
+        o += k
+
+
+def test_adam_step_matches_oracle(ctx):
+    say("mlp adam")
+    from paper_2609_23664_amd import costmodel as CM
+    import torch
+    p = CM.init_params(5)
+    g = np.random.default_rng(6).normal(size=p.shape).astype(np.float32)
+    mlp = CM.MLP(ctx, params=p)
+    mlp.g.copy_(torch.tensor(g, device="cuda"))
+    ref_p, ref_m, ref_v = p.astype(np.float64), np.zeros(len(p)), np.zeros(len(p))
+    for step in (1, 2, 3):
+        mlp.adam(1e-3)
+        ref_p, ref_m, ref_v = M.adam(ref_p, g.astype(np.float64), ref_m, ref_v, step, 1e-3)
+    assert np.max(np.abs(mlp.p.cpu().numpy() - ref_p)) <= 1e-6
+
+
+def test_trained_model_gains_over_analytic(ctx):
+    """Train on the 1600 logged workloads (GPU kernels), evaluate on the 400
+    held out: lower plan regret than the analytic byte rule, negative
+    controls always abstain."""
+    say("mlp train + evaluate")
+    from paper_2609_23664_amd import costmodel as CM
+    out = CM.train_and_evaluate(ctx, epochs=300)
+    rep = out["report"]
+    print(rep, flush=True)
+    assert rep["train"]["loss_final"] < 0.2 * rep["train"]["loss_initial"]
+    assert rep["mlp"]["negative_control_abstain"] == 1.0
+    assert rep["analytic"]["negative_control_abstain"] == 1.0
+    assert rep["mlp"]["regret_mean"] <= rep["analytic"]["regret_mean"]
+    assert rep["mlp"]["abstain_accuracy"] >= rep["analytic"]["abstain_accuracy"]

@@ -1,0 +1,88 @@
+"""Pins of the cost-model perceptron oracle (CPU): the FP64 gradient against
+central finite differences, closed forms on special inputs, the BF16
+rounding function, and Adam's first step."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+
+
+def _data(seed, B=7):
+    g = np.random.default_rng(seed)
+    return g.uniform(-1, 1, size=(B, M.IN)), g.normal(size=(B, M.OUT))
+
+
+def test_param_count():
+    assert M.N_PARAMS == 5122
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gradient_matches_finite_differences(seed):
+    p = M.init(seed)
+    x, t = _data(seed)
+    g = M.backward(p, x, t)
+    rng = np.random.default_rng(seed + 10)
+    idx = rng.choice(M.N_PARAMS, size=60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        fd = (M.loss(p + e, x, t) - M.loss(p - e, x, t)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-5 * abs(fd), i
+
+
+def test_zero_weights_output_is_bias_and_last_bias_gradient():
+    """With all weights zero the output is b3 and dL/db3 is the mean
+    residual; every other gradient is zero (ReLU(0) has derivative 0)."""
+    p = np.zeros(M.N_PARAMS)
+    d = M.unpack(p)
+    d["b3"] = np.array([0.5, -1.0])
+    p = M.pack(d)
+    x, t = _data(3)
+    _, _, y = M.forward(p, x)
+    assert np.allclose(y, d["b3"])
+    g = M.unpack(M.backward(p, x, t))
+    assert np.allclose(g["b3"], (d["b3"] - t).mean(axis=0))
+    for name in ("W1", "b1", "W2", "b2", "W3"):
+        assert np.all(g[name] == 0.0)
+
+
+def test_linear_region_matches_matrix_product():
+    """With positive weights and inputs every unit is active: the network
+    is the product of its three matrices plus propagated biases."""
+    g = np.random.default_rng(4)
+    d = {n: g.uniform(0.01, 0.1, size=s) for n, s in M.SHAPES}
+    p = M.pack(d)
+    x = g.uniform(0.1, 1.0, size=(5, M.IN))
+    _, _, y = M.forward(p, x)
+    ref = ((x @ d["W1"] + d["b1"]) @ d["W2"] + d["b2"]) @ d["W3"] + d["b3"]
+    assert np.allclose(y, ref, rtol=1e-12)
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -9, -2.5, 3.0e-3])
+    r = M.bf16(vals)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                              # 1 + 2^-8 is a tie -> 1.0 (even)
+    assert r[2] == 1.0 + 2 ** -7                    # above the tie -> up
+    assert r[3] == 1.0                              # below the tie -> down
+    assert r[4] == -2.5
+    assert abs(r[5] - 3.0e-3) <= 2 ** -8 * 3.0e-3   # 8 significant bits
+
+
+def test_bf16_mirror_differs_from_fp64_only_by_rounding():
+    p = M.init(5)
+    x, t = _data(5, B=16)
+    g64 = M.backward(p, x, t)
+    gbf = M.backward(p, x, t, bf16_inputs=True)
+    rel = np.linalg.norm(gbf - g64) / np.linalg.norm(g64)
+    assert 1e-5 < rel < 3e-2
+
+
+def test_adam_first_step_moves_by_lr():
+    p = np.zeros(4)
+    g = np.array([1.0, -2.0, 0.5, 0.0])
+    p1, m, v = M.adam(p, g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    # at step 1 the bias-corrected update is lr * sign(g) (up to eps)
+    assert np.allclose(p1[:3], -0.01 * np.sign(g[:3]), atol=1e-9)
+    assert p1[3] == 0.0
