@@ -146,8 +146,6 @@ int qw_ctx_sync(qw_ctx *ctx);
  *   QW_OPT_TILE_BITS      max local bits per pass tile, 10..14 [14]
  *   QW_OPT_PROFILE        1: time every pass/reducer launch with HIP events
  *                         (read with qw_ctx_kernel_stats) [0]
- *   QW_OPT_FUSED_EPILOGUE 1: evaluate expectation terms whose X/Y support is
- *                         local to the last suffix pass inside that pass [1]
  *   QW_OPT_XCD_REMAP      1: map workgroups so that the tiles of one source
  *                         state run on one XCD [1]
  *   QW_OPT_JIT            1: run gate passes of states with >= 10 qubits with
@@ -156,12 +154,23 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         and on disk under $QW_JIT_CACHE, default
  *                         ~/.cache/qw_jit; QW_JIT_CACHE=off disables the disk
  *                         cache); 0: interpreted pass kernels. Both forms
- *                         give bit-identical states. [1] */
+ *                         give bit-identical states. [1]
+ *   QW_OPT_RELABEL        1: a pass may end with CNOTs whose targets are not
+ *                         local to its tiles, applied as a permutation of
+ *                         its store addresses (one pass fewer for CNOT
+ *                         ladders); such a pass never runs in place, so each
+ *                         task with one gets a second state buffer held by
+ *                         the context. 0: plans without relabelling. Both
+ *                         give the same state up to FP32 rounding. [1]
+ *   QW_OPT_SECOND_BUFFER_CAP  bytes of second state buffers one execution
+ *                         may hold; batches beyond it run in chunks
+ *                         (at least one task per chunk) [16 GiB] */
 #define QW_OPT_TILE_BITS 1
 #define QW_OPT_PROFILE 2
-#define QW_OPT_FUSED_EPILOGUE 3
 #define QW_OPT_XCD_REMAP 4
 #define QW_OPT_JIT 5
+#define QW_OPT_RELABEL 6
+#define QW_OPT_SECOND_BUFFER_CAP 7
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.

@@ -40,9 +40,10 @@ QW_SNAP_FREEZE = 1
 
 QW_OPT_TILE_BITS = 1
 QW_OPT_PROFILE = 2
-QW_OPT_FUSED_EPILOGUE = 3
 QW_OPT_XCD_REMAP = 4
 QW_OPT_JIT = 5
+QW_OPT_RELABEL = 6
+QW_OPT_SECOND_BUFFER_CAP = 7
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",

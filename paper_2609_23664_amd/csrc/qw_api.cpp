@@ -39,6 +39,8 @@ struct ProfRec {
 struct PlanEntry {
     uint32_t n = 0;
     int tile_bits = 0;
+    bool relabel = true;
+    uint64_t pingpong_cap = 16ull << 30;
     std::vector<char> gates;  // the gate records the plan was built from
     std::shared_ptr<const qw::Plan> plan;
 };
@@ -57,12 +59,14 @@ struct qw_ctx {
     std::string err;
     int tile_bits = kMaxTileBits;
     bool profile = false;
-    bool fused_epilogue = true;
     bool xcd_remap = true;
     int jit = 1;  // 0: interpreted kernels, 1: tiered, 2: always generated
     uint32_t n_cu = 256;
     DevBuf plan;     // uploaded descriptors/ops
     DevBuf scratch;  // partial sums, sampler buffers
+    DevBuf pingpong; // second state buffers of tasks with relabelling passes
+    bool relabel = true;
+    uint64_t pingpong_cap = 16ull << 30;
     void *staging = nullptr;
     size_t staging_cap = 0;
     hipEvent_t staging_ev = nullptr;
@@ -300,16 +304,18 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
     uint64_t h = fnv64(gates, bytes);
     h = fnv64(&n, sizeof n, h);
     h = fnv64(&ctx->tile_bits, sizeof ctx->tile_bits, h);
+    h = fnv64(&ctx->relabel, sizeof ctx->relabel, h);
     auto &bucket = ctx->plan_cache[h];
     for (const auto &c : bucket) {
-        if (c.n == n && c.tile_bits == ctx->tile_bits && c.gates.size() == bytes &&
+        if (c.n == n && c.tile_bits == ctx->tile_bits && c.relabel == ctx->relabel &&
+            c.gates.size() == bytes &&
             (bytes == 0 || std::memcmp(c.gates.data(), gates, bytes) == 0)) {
             *out = c.plan;
             return "";
         }
     }
     auto p = std::make_shared<Plan>();
-    std::string e = build_plan((int)n, gates, (size_t)n_gates, ctx->tile_bits, p.get());
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, ctx->tile_bits, p.get(), ctx->relabel);
     if (!e.empty()) return e;
     if (ctx->plan_cache_entries >= 4096) {
         ctx->plan_cache.clear();
@@ -318,6 +324,7 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
     PlanEntry pe;
     pe.n = n;
     pe.tile_bits = ctx->tile_bits;
+    pe.relabel = ctx->relabel;
     pe.gates.assign(reinterpret_cast<const char *>(gates), reinterpret_cast<const char *>(gates) + bytes);
     pe.plan = p;
     ctx->plan_cache[h].push_back(std::move(pe));
@@ -339,7 +346,59 @@ struct Exec {
     void *dst = nullptr;
 };
 
+bool has_relabel(const Plan &p) {
+    for (const HostPass &h : p.passes)
+        if (!h.out_img.empty()) return true;
+    return false;
+}
+
+int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex);
+
 int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
+    const uint64_t state_bytes = 8ull << n;
+    // second state buffers of relabelling tasks are bounded by the
+    // context's cap: larger batches run in chunks
+    const uint64_t per = std::max<uint64_t>(1, ctx->pingpong_cap / state_bytes);
+    uint64_t need = 0;
+    for (const Exec &e : ex) need += has_relabel(*e.planp);
+    if (need <= per) return execute_chunk(ctx, n, ex);
+    std::vector<Exec> part;
+    uint64_t cnt = 0;
+    for (size_t i = 0; i < ex.size(); ++i) {
+        part.push_back(ex[i]);
+        cnt += has_relabel(*ex[i].planp);
+        if (cnt == per || i + 1 == ex.size()) {
+            int rc = execute_chunk(ctx, n, part);
+            if (rc) return rc;
+            part.clear();
+            cnt = 0;
+        }
+    }
+    return QW_OK;
+}
+
+// Buffers of one task's passes: 0 = the task's destination, 1 = its second
+// buffer. A relabelling pass stores to other tiles than the ones it loads,
+// so it never runs in place; the assignment ends in the destination.
+// Returns the buffer pass 0 reads when the task has no external source, or
+// 2 if the destination must first be copied to the second buffer.
+int assign_buffers(const Plan &p, bool external_src, std::vector<int> *db) {
+    const size_t P = p.passes.size();
+    db->assign(P, 0);
+    for (size_t k = P - 1; k >= 1; --k)
+        (*db)[k - 1] = p.passes[k].out_img.empty() ? (*db)[k] : 1 - (*db)[k];
+    if (external_src || p.passes[0].out_img.empty() || (*db)[0] == 1) return 0;
+    // pass 0 would relabel in place: make the first plain pass k >= 1 run
+    // out of place (flips the buffers of passes 0..k-1)
+    for (size_t k = 1; k < P; ++k)
+        if (p.passes[k].out_img.empty()) {
+            for (size_t j = 0; j < k; ++j) (*db)[j] = 1 - (*db)[j];
+            return 0;
+        }
+    return 2;
+}
+
+int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     if (ex.empty()) return QW_OK;
     const int m = ex[0].planp->m;
     const uint32_t tiles = (m >= kMinTileBits) ? (1u << (n - m)) : 1u;
@@ -365,6 +424,42 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         if (rc) return rc;
     }
     double *norm_base = static_cast<double *>(ctx->scratch.p);
+    // second state buffers and per-pass buffer choice of relabelling tasks
+    std::vector<std::vector<int>> bufsel(ex.size());
+    std::vector<void *> second(ex.size(), nullptr);
+    std::vector<char> precopy(ex.size(), 0);
+    {
+        uint64_t cnt = 0;
+        for (Exec &e : ex) cnt += has_relabel(*e.planp);
+        if (cnt) {
+            const size_t want = (size_t)(cnt * state_bytes);
+            if (ctx->pingpong.cap < want) {
+                if (ctx->pingpong.p) {
+                    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync before regrow");
+                    HIP_TRY(ctx, hipFree(ctx->pingpong.p), "free second buffers");
+                    ctx->pingpong.p = nullptr;
+                    ctx->pingpong.cap = 0;
+                }
+                void *pp = nullptr;
+                hipError_t er = hipMalloc(&pp, want);
+                if (er != hipSuccess) return hip_fail(ctx, er, "second state buffers");
+                ctx->pingpong.p = pp;
+                ctx->pingpong.cap = want;
+            }
+            uint64_t i = 0;
+            for (size_t t = 0; t < ex.size(); ++t) {
+                if (!has_relabel(*ex[t].planp)) continue;
+                second[t] = static_cast<char *>(ctx->pingpong.p) + (i++) * state_bytes;
+                const int r = assign_buffers(*ex[t].planp, ex[t].src != nullptr, &bufsel[t]);
+                if (r == 2) {
+                    precopy[t] = 1;
+                    ProfScope ps(ctx, 3, 2.0 * state_bytes);
+                    hipError_t er = launch_copy(ctx->stream, second[t], ex[t].dst, state_bytes);
+                    if (er != hipSuccess) return hip_fail(ctx, er, "copy launch");
+                }
+            }
+        }
+    }
     // blob layout
     Layout L;
     std::vector<size_t> step_off(steps), step_cnt(steps, 0);
@@ -394,6 +489,19 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     std::vector<std::vector<size_t>> tb_of(ex.size());
     for (size_t t = 0; t < ex.size(); ++t)
         for (const HostPass &p : ex[t].planp->passes) tb_of[t].push_back(tile_table(p.local_mask));
+    // per distinct (local mask, relabelling): relabelled tile origins
+    std::vector<std::pair<const HostPass *, size_t>> tbo_off;
+    auto out_table = [&](const HostPass &p) -> size_t {
+        for (auto &e : tbo_off)
+            if (e.first->local_mask == p.local_mask && e.first->out_img == p.out_img) return e.second;
+        size_t off = L.take((size_t)tiles * sizeof(uint32_t));
+        tbo_off.push_back({&p, off});
+        return off;
+    };
+    std::vector<std::vector<size_t>> tbo_of(ex.size());
+    for (size_t t = 0; t < ex.size(); ++t)
+        for (const HostPass &p : ex[t].planp->passes)
+            tbo_of[t].push_back(p.out_img.empty() ? (size_t)-1 : out_table(p));
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
     uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
@@ -415,6 +523,16 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
             const uint64_t nl = full & ~e.first;
             for (uint32_t ti = 0; ti < tiles; ++ti) tb[ti] = (uint32_t)pdep64(ti, nl);
+        }
+        for (auto &e : tbo_off) {
+            uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
+            const uint64_t nl = full & ~e.first->local_mask;
+            const std::vector<uint64_t> &img = e.first->out_img;
+            for (uint32_t ti = 0; ti < tiles; ++ti) {
+                uint64_t g = pdep64(ti, nl), o = 0;
+                for (uint64_t r = g; r; r &= r - 1) o ^= img[__builtin_ctzll(r)];
+                tb[ti] = (uint32_t)o;
+            }
         }
     }
     // Order of the tasks in each step's descriptor array. With generated
@@ -494,8 +612,19 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             Exec &e = ex[t];
             const HostPass &p = e.planp->passes[k];
             PassDesc d{};
-            d.src = (k == 0 && e.src) ? e.src : e.dst;
-            d.dst = e.dst;
+            if (second[t]) {
+                void *buf[2] = {e.dst, second[t]};
+                const std::vector<int> &db = bufsel[t];
+                d.dst = buf[db[k]];
+                d.src = k > 0 ? buf[db[k - 1]] : (e.src ? e.src : buf[precopy[t] ? 1 : 0]);
+            } else {
+                d.src = (k == 0 && e.src) ? e.src : e.dst;
+                d.dst = e.dst;
+            }
+            if (!p.out_img.empty()) {
+                d.tile_base_out = reinterpret_cast<const uint32_t *>(dbase + tbo_of[t][k]);
+                d.flags |= PD_REMAP_OUT;
+            }
             d.ops = reinterpret_cast<const DevOp *>(dbase + op_off[t][k].first);
             d.phases = reinterpret_cast<const DevPhase *>(dbase + op_off[t][k].second);
             d.local_mask = p.local_mask;
@@ -508,7 +637,7 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             d.io_out = reinterpret_cast<const IoRec *>(dbase + io_off[t][k] + sizeof(IoRec));
             d.n_ops = (uint32_t)p.dev_ops.size();
             d.n_phases = (uint32_t)p.dev_phases.size();
-            d.flags = (p.scale_in ? PD_SCALE_IN : 0u) | (p.norm_out ? PD_NORM_OUT : 0u);
+            d.flags |= (p.scale_in ? PD_SCALE_IN : 0u) | (p.norm_out ? PD_NORM_OUT : 0u);
             if (p.norm_out) step_norm[k] = 1;
             if (p.norm_out || p.dev_phases.size() > 1) step_lds[k] = 1;
             std::memcpy(blob.data() + step_off[k] + c * sizeof(PassDesc), &d, sizeof d);
@@ -750,6 +879,7 @@ int qw_ctx_destroy(qw_ctx *ctx) {
     for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
     if (ctx->plan.p) (void)hipFree(ctx->plan.p);
     if (ctx->scratch.p) hipFree(ctx->scratch.p);
+    if (ctx->pingpong.p) hipFree(ctx->pingpong.p);
     if (ctx->staging) hipHostFree(ctx->staging);
     if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
     delete ctx;
@@ -773,11 +903,15 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         ctx->tile_bits = (int)value;
         return QW_OK;
     case QW_OPT_PROFILE: ctx->profile = value != 0; return QW_OK;
-    case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
     case QW_OPT_XCD_REMAP: ctx->xcd_remap = value != 0; return QW_OK;
     case QW_OPT_JIT:
         if (value < 0 || value > 2) return fail(ctx, QW_E_INVALID_ARG, "jit mode must be 0, 1 or 2");
         ctx->jit = (int)value;
+        return QW_OK;
+    case QW_OPT_RELABEL: ctx->relabel = value != 0; return QW_OK;
+    case QW_OPT_SECOND_BUFFER_CAP:
+        if (value <= 0) return fail(ctx, QW_E_INVALID_ARG, "second buffer cap must be > 0");
+        ctx->pingpong_cap = (uint64_t)value;
         return QW_OK;
     default: return fail(ctx, QW_E_INVALID_ARG, "unknown option");
     }

@@ -106,18 +106,29 @@ inline uint32_t lds_swizzle(uint32_t l) { return l ^ (((l >> 5) ^ (l >> 10)) & 3
 enum : uint32_t {
     PD_SCALE_IN = 1u,    // multiply loaded amplitudes by *scale (FP64)
     PD_NORM_OUT = 2u,    // write per-tile FP64 sums of |psi|^2
+    PD_REMAP_OUT = 4u,   // stores go through the pass's output relabelling
 };
 
 // Uniform address record of an I/O phase, computed on the host: global
 // index bits of the lane part (shifts), of each register and of each wave.
+// Output relabelling (a pass whose last gates are CNOTs with non-local
+// targets, applied as a permutation of the store addresses): the amplitude
+// of global index j is stored at index L(j) with L linear over GF(2), equal
+// to the identity on the local bits. L(j) = tile_base_out[tile] ^ reg_xor[k]
+// ^ wave_xor[w] combined with the local part of j, where the two xor terms
+// are the non-local images of the local bits that register k and wave w
+// carry. Lane bits never carry such a bit (the planner keeps relabelling
+// controls out of the lane positions).
 struct alignas(16) IoRec {
     uint8_t kind;          // IoKind
     uint8_t g4, g5, g6;    // global positions of local bits 4, 5, 6
     uint32_t pad[3];
     uint32_t reg_off[16];  // global index bits of register k
     uint32_t wave_off[16]; // global index bits of wave w (tile bits >= 10)
+    uint32_t reg_xor[16];  // output relabelling: non-local bits flipped by register k
+    uint32_t wave_xor[16]; // output relabelling: non-local bits flipped by wave w
 };
-static_assert(sizeof(IoRec) == 144, "IoRec layout");
+static_assert(sizeof(IoRec) == 272, "IoRec layout");
 
 // One (task, pass): a tile sweep over a state slot.
 struct alignas(16) PassDesc {
@@ -130,6 +141,7 @@ struct alignas(16) PassDesc {
     double *norm_part;     // PD_NORM_OUT: [tiles] FP64 sums of |psi|^2
     double *scale_out;     // PD_NORM_OUT: 1/sqrt(sum) written by finalize
     const uint32_t *tile_base;  // global index of local index 0, per tile
+    const uint32_t *tile_base_out;  // PD_REMAP_OUT: L(tile_base), per tile
     const IoRec *io_in;    // address record of phase 0
     const IoRec *io_out;   // address record of the last phase
     uint32_t n_ops;
@@ -137,7 +149,7 @@ struct alignas(16) PassDesc {
     uint32_t flags;
     uint32_t pad;
 };
-static_assert(sizeof(PassDesc) % 16 == 0, "PassDesc layout");
+static_assert(sizeof(PassDesc) == 112, "PassDesc layout");
 
 // Expectation reducer, small states (n < 10): the whole state is one tile
 // staged in LDS; one descriptor per slot.

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "qw_desc.h"
@@ -26,6 +27,11 @@ struct HostPass {
     std::vector<HostOp> ops;    // global-qubit form, execution order
     bool scale_in = false;
     bool norm_out = false;
+    // Output relabelling: CNOTs (control, target) with non-local targets that
+    // end the pass, applied as a linear map L of the store addresses.
+    // out_img[q] = L(e_q) for every qubit q (empty: no relabelling).
+    std::vector<std::pair<int, int>> out_cx;
+    std::vector<uint64_t> out_img;
     // filled by lower_pass():
     std::vector<DevOp> dev_ops;
     std::vector<DevPhase> dev_phases;
@@ -40,9 +46,11 @@ struct Plan {
 };
 
 // Validates and plans `gates` on n qubits with at most tile_bits local bits
-// per pass. Returns "" on success, otherwise an error message.
+// per pass; `relabel` allows output relabelling (trailing CNOTs with
+// non-local targets applied as store-address maps). Returns "" on success,
+// otherwise an error message.
 std::string build_plan(int n, const void *gates /* qw_gate* */, size_t n_gates,
-                       int tile_bits, Plan *out);
+                       int tile_bits, Plan *out, bool relabel = true);
 
 // JSON form of a plan (for qw_plan_describe).
 std::string plan_json(const Plan &p);

@@ -83,18 +83,33 @@ void emit_load(Gen &g, const IoRec &r) {
     g << "}\n";
 }
 
-void emit_store(Gen &g, const IoRec &r) {
+// Store of the last phase. `ub` is the tile's output base with the wave
+// part; with output relabelling a register's non-local xor term is applied
+// to it before its local offset is added (the two never share bits).
+void emit_store(Gen &g, const IoRec &r, bool remap, int m) {
+    auto idx = [&](int k) {
+        std::string e = "ub";
+        if (remap && r.reg_xor[k]) e = "(ub ^ " + hex(r.reg_xor[k]) + ")";
+        return e + " + " + hex(r.reg_off[k]);
+    };
     g << "__device__ __forceinline__ void store_out(const float2 (&v)[16], void *dst, uint64_t ub, "
          "uint32_t lb) {\n";
     if (r.kind == IO_F4) {
         for (int k2 = 0; k2 < 8; ++k2)
-            g << "    buf_st4(dst, ub + " << hex(r.reg_off[2 * k2]) << ", lb, v[" << 2 * k2 << "], v["
-              << 2 * k2 + 1 << "]);\n";
+            g << "    buf_st4(dst, " << idx(2 * k2) << ", lb, v[" << 2 * k2 << "], v[" << 2 * k2 + 1
+              << "]);\n";
     } else {
         for (int k = 0; k < 16; ++k)
-            g << "    buf_st2(dst, ub + " << hex(r.reg_off[k]) << ", lb, v[" << k << "]);\n";
+            g << "    buf_st2(dst, " << idx(k) << ", lb, v[" << k << "]);\n";
     }
     g << "}\n";
+    // per-wave xor term of the output relabelling
+    g << "__device__ __forceinline__ uint64_t io_out_wxor(uint32_t w) {\n    (void)w;\n    return 0ull";
+    if (remap)
+        for (int j = 0; j < m - 10; ++j)
+            if (r.wave_xor[1u << j])
+                g << " ^ ((uint64_t)((w >> " << j << ") & 1u) * " << hex(r.wave_xor[1u << j]) << ")";
+    g << ";\n}\n";
 }
 
 // Value of a thread or global operand bit in phase ph.
@@ -284,8 +299,14 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
     put((uint64_t)n, 1);
     put((uint64_t)m, 1);
     put(use_lds ? 1 : 0, 1);
-    put((p.scale_in ? 1 : 0) | (p.norm_out ? 2 : 0), 1);
+    put((p.scale_in ? 1 : 0) | (p.norm_out ? 2 : 0) | (p.out_img.empty() ? 0 : 4), 1);
     put(p.local_mask, 8);
+    if (!p.out_img.empty()) {
+        // the local-bit part of the relabelling is compiled in; its tile
+        // part comes from the per-tile output bases
+        for (int k = 0; k < 16; ++k) put(p.io_out.reg_xor[k], 4);
+        for (int w = 0; w < 16; ++w) put(p.io_out.wave_xor[w], 4);
+    }
     put(p.dev_phases.size(), 2);
     for (const DevPhase &f : p.dev_phases) {
         for (int s = 0; s < 4; ++s) put(f.reg[s], 1);
@@ -322,8 +343,11 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
     g << "constexpr int M = " << m << ", T = " << T << ", WG = " << WG << ", PARTS = T / WG;\n";
     emit_io_helpers(g, "io_in", p.io_in, m);
     emit_io_helpers(g, "io_out", p.io_out, m);
+    const bool remap = !p.out_img.empty();
     emit_load(g, p.io_in);
-    emit_store(g, p.io_out);
+    emit_store(g, p.io_out, remap, m);
+    // output base of the tile: the relabelled one, or the load base
+    const char *obase = remap ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
     g << emit_body(m, p);
     if (!use_lds) {
         g << "extern \"C\" __global__ __launch_bounds__(WG) void qw_pass(const PassDesc *__restrict__ "
@@ -342,7 +366,7 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
              "    load_in(v, ldu(&d->src), base | io_in_wave(wave), io_in_lane(lane));\n";
         if (p.scale_in) g << kScaleIn;
         g << "    body(v, ldu(&d->ops), tid, lane, base, nullptr);\n"
-             "    store_out(v, ldu(&d->dst), base | io_out_wave(wave), io_out_lane(lane));\n"
+             "    store_out(v, ldu(&d->dst), ((uint64_t)" << obase << " ^ io_out_wxor(wave)) | io_out_wave(wave), io_out_lane(lane));\n"
              "}\n";
     } else {
         g << "extern \"C\" __global__ __launch_bounds__(T) void qw_pass(const PassDesc *__restrict__ "
@@ -360,7 +384,7 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
              "    const uint32_t tid = threadIdx.x;\n"
              "    const uint32_t lane = tid & 63u;\n"
              "    const uint32_t wave = uni(tid >> 6);\n"
-             "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave);\n"
+             "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave), wx = io_out_wxor(wave);\n"
              "    const uint32_t li = io_in_lane(lane), lo = io_out_lane(lane);\n"
              "    char *lb = reinterpret_cast<char *>(lds);\n"
              "    float2 nv[16];\n"
@@ -395,7 +419,7 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
                  "            s = block_sum<T>(s, red);\n"
                  "            if (tid == 0) gout<double>(ldu(&d->norm_part))[tile] = s;\n"
                  "        }\n";
-        g << "        store_out(v, ldu(&d->dst), base | wo, lo);\n"
+        g << "        store_out(v, ldu(&d->dst), ((uint64_t)" << obase << " ^ wx) | wo, lo);\n"
              "        if (!has_next) break;\n"
              "        item = next;\n"
              "    }\n"
@@ -622,20 +646,39 @@ std::string cache_dir() {
     return std::string(h) + "/.cache/qw_jit";
 }
 
+// Identity of a code object: the kernel source plus fingerprints of the two
+// headers it includes and of the compile options, so that a library built
+// with other record layouts never loads a stale entry.
+std::string cache_text(const std::string &src) {
+    static const std::string tag = [] {
+        std::string opts;
+        for (int i = 0; i < kNumOpts; ++i) opts += std::string(kOpts[i]) + " ";
+        char b[96];
+        std::snprintf(b, sizeof b, "\n// qw headers %016llx %016llx options %016llx\n",
+                      (unsigned long long)fnv1a(kEmbedDescH, 0xcbf29ce484222325ull),
+                      (unsigned long long)fnv1a(kEmbedDevH, 0xcbf29ce484222325ull),
+                      (unsigned long long)fnv1a(opts, 0xcbf29ce484222325ull));
+        return std::string(b);
+    }();
+    return src + tag;
+}
+
 std::string cache_path(const std::string &dir, const std::string &src) {
+    const std::string t = cache_text(src);
     char b[64];
     std::snprintf(b, sizeof b, "/%016llx%016llx.co",
-                  (unsigned long long)fnv1a(src, 0xcbf29ce484222325ull),
-                  (unsigned long long)fnv1a(src, 0x84222325cbf29ce4ull));
+                  (unsigned long long)fnv1a(t, 0xcbf29ce484222325ull),
+                  (unsigned long long)fnv1a(t, 0x84222325cbf29ce4ull));
     return dir + b;
 }
 
-// Disk cache entry: source length, source text, code object. The stored
-// source must equal the requested one (no trust in the hash alone).
-bool cache_load(const std::string &src, std::vector<char> *code) {
+// Disk cache entry: text length, identity text (cache_text), code object.
+// The stored text must equal the requested one (no trust in the hash alone).
+bool cache_load(const std::string &src_in, std::vector<char> *code) {
     const std::string dir = cache_dir();
     if (dir.empty()) return false;
-    std::ifstream f(cache_path(dir, src), std::ios::binary);
+    const std::string src = cache_text(src_in);
+    std::ifstream f(cache_path(dir, src_in), std::ios::binary);
     if (!f) return false;
     uint64_t len = 0;
     if (!f.read(reinterpret_cast<char *>(&len), sizeof len) || len != src.size()) return false;
@@ -647,9 +690,10 @@ bool cache_load(const std::string &src, std::vector<char> *code) {
     return true;
 }
 
-void cache_store(const std::string &src, const std::vector<char> &code) {
+void cache_store(const std::string &src_in, const std::vector<char> &code) {
     const std::string dir = cache_dir();
     if (dir.empty()) return;
+    const std::string src = cache_text(src_in);
     std::string cmd_dir = dir;
     // create the directory chain (best effort, no shell)
     for (size_t i = 1; i <= cmd_dir.size(); ++i) {
@@ -658,7 +702,7 @@ void cache_store(const std::string &src, const std::vector<char> &code) {
             ::mkdir(part.c_str(), 0755);
         }
     }
-    const std::string path = cache_path(dir, src);
+    const std::string path = cache_path(dir, src_in);
     const std::string tmp = path + ".tmp" + std::to_string((unsigned long long)std::hash<std::thread::id>()(std::this_thread::get_id()));
     {
         std::ofstream f(tmp, std::ios::binary);

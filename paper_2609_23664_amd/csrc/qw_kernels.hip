@@ -307,6 +307,19 @@ __device__ __forceinline__ IoLayout io_from_rec(const IoRec *rec, uint32_t lane,
     return io;
 }
 
+// Store layout of a pass: with PD_REMAP_OUT the non-local bits follow the
+// pass's output relabelling (tile_base_out, and the per-wave and
+// per-register xor terms of the record), otherwise those of the load.
+__device__ __forceinline__ IoLayout io_out_layout(const PassDesc &d, uint32_t tile, uint32_t lane,
+                                                  uint32_t wave, uint32_t base) {
+    if (!(d.flags & PD_REMAP_OUT)) return io_from_rec(d.io_out, lane, wave, base);
+    const uint32_t bo = uni(ldu(d.tile_base_out + tile)) ^ uni(ldu(d.io_out->wave_xor + wave));
+    IoLayout io = io_from_rec(d.io_out, lane, wave, bo);
+    #pragma unroll
+    for (int k = 0; k < 16; ++k) io.uni_off[k] ^= uni(ldu(d.io_out->reg_xor + k));
+    return io;
+}
+
 __device__ __forceinline__ void io_load(float2 (&v)[16], const void *src, const IoLayout &io,
                                         uint8_t kind) {
     const uint32_t lb = io.lane_off * 8u;
@@ -400,7 +413,7 @@ void pass_kernel_flat(const PassDesc *__restrict__ descs, uint32_t n_descs, uint
             v[k] = make_float2((float)((double)v[k].x * s), (float)((double)v[k].y * s));
     }
     run_ops(v, d.ops, ph.op_begin, ph.op_end, tl, base);
-    io_store(v, d.dst, io_from_rec(d.io_out, lane, wave, base), ph.io);
+    io_store(v, d.dst, io_out_layout(d, tile, lane, wave, base), ph.io);
 }
 
 // Multi-phase passes: one 1024-thread workgroup per CU owns a whole tile in
@@ -490,7 +503,7 @@ __global__ __launch_bounds__(1 << (M - 4)) void pass_kernel_lds(const PassDesc *
             s = block_sum<T>(s, red);
             if (tid == 0) gout<double>(d.norm_part)[tile] = s;
         }
-        io_store(v, d.dst, io_from_rec(d.io_out, lane, wave, base), ph.io);
+        io_store(v, d.dst, io_out_layout(d, tile, lane, wave, base), ph.io);
         if (!has_next) break;
         item = next;
         lds_barrier();  // the next tile's first exchange reuses the LDS buffer

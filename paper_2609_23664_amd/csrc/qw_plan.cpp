@@ -103,6 +103,19 @@ uint64_t local_need(const G &g) {
     }
 }
 
+// One pass picked by the greedy construction: the gates run inside the tile
+// (in order), the CNOTs applied as the output relabelling after them, and
+// the local set.
+struct PassPick {
+    std::vector<int> gates;
+    std::vector<int> out_cx;
+    uint64_t mask = 0;
+};
+
+// Lowest local position a relabelling control may take: positions 0..6 can
+// be lane bits of an I/O layout, whose addresses are per-lane, not uniform.
+constexpr int kMinRelabelPos = 7;
+
 // Greedy pass construction over one RENORM-free segment. Gates are taken in
 // order; a gate that cannot run in the current pass is deferred and blocks
 // its qubits, so later gates on those qubits are deferred too (this keeps
@@ -110,18 +123,29 @@ uint64_t local_need(const G &g) {
 // overtake a deferred gate, which is valid since they act on disjoint
 // qubits. `horizon` bounds how many gates are scanned past the first
 // deferral (a negative horizon means no bound).
-std::vector<std::vector<int>> greedy_passes(int n, int m, const std::vector<G> &gs,
-                                            long horizon, std::vector<uint64_t> *masks) {
-    std::vector<std::vector<int>> passes;
-    masks->clear();
+//
+// With `relabel`, a CNOT whose target cannot be made local is taken as an
+// output relabelling gate instead of being deferred: the pass stores the
+// amplitude of index j at C(j) = j ^ (j_c << t), which is exactly the CNOT
+// applied after everything the pass computes. Such a gate must therefore
+// follow every in-tile gate of the pass on its two qubits: its qubits are
+// closed to in-tile gates from then on (later relabelling CNOTs on them are
+// still taken, composing the map in order), its target stays non-local
+// (the padding skips it), and its control, if local, must sit at a local
+// position >= kMinRelabelPos; a relabelling gate that fails that last test
+// is deferred after all, with every later relabelling gate that shares a
+// qubit with it.
+std::vector<PassPick> greedy_passes(int n, int m, const std::vector<G> &gs, long horizon,
+                                    bool relabel) {
+    std::vector<PassPick> passes;
     std::vector<int> remaining(gs.size());
     for (size_t i = 0; i < gs.size(); ++i) remaining[i] = (int)i;
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
     const int low = std::min(n, 4);
     while (!remaining.empty()) {
         uint64_t L = (n <= m) ? all : ((1ull << low) - 1);
-        uint64_t blocked = 0;
-        std::vector<int> acc, def;
+        uint64_t blocked = 0, closed = 0, targets = 0;
+        std::vector<int> acc, def, rel;
         long since_defer = -1;
         for (int idx : remaining) {
             const G &g = gs[idx];
@@ -142,22 +166,62 @@ std::vector<std::vector<int>> greedy_passes(int n, int m, const std::vector<G> &
                 blocked |= qm;
                 continue;
             }
+            const uint64_t tbit = (g.cls == C_CX) ? (1ull << g.q1) : 0;
+            if (qm & closed) {
+                // only a further relabelling CNOT may touch a closed qubit
+                if (tbit && !(tbit & L) && popc64(targets | tbit) <= n - m) {
+                    rel.push_back(idx);
+                    closed |= qm;
+                    targets |= tbit;
+                } else {
+                    def.push_back(idx);
+                    blocked |= qm;
+                    if (since_defer < 0) since_defer = 0;
+                }
+                continue;
+            }
             uint64_t need = local_need(g);
             if ((need & ~L) == 0) {
                 acc.push_back(idx);
-            } else if (popc64(L | need) <= m) {
+            } else if (!(need & targets) && popc64(L | need) <= m) {
                 L |= need;
                 acc.push_back(idx);
+            } else if (relabel && tbit && !(tbit & L) && popc64(targets | tbit) <= n - m) {
+                rel.push_back(idx);
+                closed |= qm;
+                targets |= tbit;
             } else {
                 def.push_back(idx);
                 blocked |= qm;
                 if (since_defer < 0) since_defer = 0;
             }
         }
-        // Pad the local set to exactly m bits with the lowest free bits.
-        for (int q = 0; q < n && popc64(L) < m; ++q) L |= 1ull << q;
-        passes.push_back(acc);
-        masks->push_back(L);
+        // Pad the local set to exactly m bits with the lowest free bits that
+        // are not relabelling targets.
+        for (int q = 0; q < n && popc64(L) < m; ++q)
+            if (!((targets >> q) & 1ull)) L |= 1ull << q;
+        // Relabelling controls must not be local bits at lane positions.
+        std::vector<int> keep;
+        uint64_t dropped = 0;
+        for (int idx : rel) {
+            const G &g = gs[idx];
+            const uint64_t qm = qubit_mask(g);
+            bool ok = !(qm & dropped);
+            if (ok && ((L >> g.q0) & 1ull))
+                ok = popc64(L & ((1ull << g.q0) - 1)) >= kMinRelabelPos;
+            if (ok) {
+                keep.push_back(idx);
+            } else {
+                dropped |= qm;
+                def.push_back(idx);
+            }
+        }
+        std::sort(def.begin(), def.end());
+        PassPick pk;
+        pk.gates.swap(acc);
+        pk.out_cx.swap(keep);
+        pk.mask = L;
+        passes.push_back(std::move(pk));
         remaining.swap(def);
     }
     return passes;
@@ -695,9 +759,48 @@ IoRec make_iorec(int m, uint64_t lmask, const DevPhase &ph) {
     return r;
 }
 
+// Output relabelling terms of the store record: the non-local part of the
+// image of each local bit, combined per register index and per wave.
+// Returns false if a lane bit would need one (the planner prevents that).
+bool fill_relabel(int m, const HostPass &p, const DevPhase &ph, IoRec *r) {
+    std::vector<int> gpos;
+    for (int q = 0; q < 64; ++q)
+        if ((p.local_mask >> q) & 1ull) gpos.push_back(q);
+    auto dpart = [&](int b) -> uint32_t {
+        const int q = gpos[b];
+        return (uint32_t)(p.out_img[q] ^ (1ull << q));
+    };
+    uint32_t R = 0;
+    for (int s = 0; s < 4; ++s) R |= 1u << ph.reg[s];
+    std::vector<int> wbits;
+    int lanes = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((R >> b) & 1u) continue;
+        if (lanes < 6) {
+            ++lanes;
+            if (dpart(b)) return false;
+            continue;
+        }
+        wbits.push_back(b);
+    }
+    for (int k = 0; k < 16; ++k) {
+        uint32_t x = 0;
+        for (int s = 0; s < 4; ++s)
+            if ((k >> s) & 1) x ^= dpart(ph.reg[s]);
+        r->reg_xor[k] = x;
+    }
+    for (int w = 0; w < 16; ++w) {
+        uint32_t x = 0;
+        for (size_t j = 0; j < wbits.size(); ++j)
+            if ((w >> j) & 1) x ^= dpart(wbits[j]);
+        r->wave_xor[w] = x;
+    }
+    return true;
+}
+
 // Convert a pass's ops to local bit numbers and device form. An OP_DSET
 // becomes a header (b = member count) followed by its OP_DIAG members.
-void lower_pass(int n, int m, HostPass &p) {
+bool lower_pass(int n, int m, HostPass &p) {
     (void)n;
     std::vector<DevOp> lops;
     std::vector<std::array<double, 8>> lmd;  // FP64 entries, parallel to lops
@@ -756,6 +859,8 @@ void lower_pass(int n, int m, HostPass &p) {
         plan_phases(m, p, lops, unit_len, lmd);
         p.io_in = make_iorec(m, p.local_mask, p.dev_phases.front());
         p.io_out = make_iorec(m, p.local_mask, p.dev_phases.back());
+        if (!p.out_img.empty() && !fill_relabel(m, p, p.dev_phases.back(), &p.io_out))
+            return false;
     } else {
         // small-state kernel: whole state is one tile, no phases needed
         p.dev_phases.clear();
@@ -765,11 +870,13 @@ void lower_pass(int n, int m, HostPass &p) {
         p.dev_phases.push_back(dp);
     }
     p.dev_ops.swap(lops);
+    return true;
 }
 
 }  // namespace
 
-std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits, Plan *out) {
+std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits, Plan *out,
+                       bool relabel) {
     const qw_gate *gates = static_cast<const qw_gate *>(gates_v);
     if (n < 1 || n > kMaxQubits) return "qubit count out of range 1..30";
     if (tile_bits < kMinTileBits || tile_bits > kMaxTileBits) return "tile bits out of range 10..14";
@@ -825,37 +932,44 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
     bool pending_scale = false;
     for (size_t s = 0; s < segs.size(); ++s) {
         const std::vector<G> &gs = segs[s];
-        std::vector<std::vector<int>> best;
-        std::vector<uint64_t> best_masks;
+        std::vector<PassPick> best;
         if (!gs.empty()) {
             const long horizons[] = {-1, 0, 8, 32, 128, 512};
             for (long h : horizons) {
-                std::vector<uint64_t> masks;
-                auto ps = greedy_passes(n, m, gs, h, &masks);
-                if (best.empty() || ps.size() < best.size()) {
-                    best = ps;
-                    best_masks = masks;
-                }
+                auto ps = greedy_passes(n, m, gs, h, relabel);
+                if (best.empty() || ps.size() < best.size()) best.swap(ps);
             }
         }
         // A segment with no gates still needs a pass if it must carry a
         // scale (renorm right after renorm / at the end) or a norm.
         if (best.empty() && (pending_scale || renorm_after[s])) {
-            best.push_back({});
-            best_masks.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
+            PassPick pk;
+            pk.mask = n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1);
+            best.push_back(pk);
         }
         for (size_t k = 0; k < best.size(); ++k) {
             HostPass hp;
-            hp.local_mask = best_masks[k];
-            hp.ops = fuse_ops(n, gs, best[k]);
+            hp.local_mask = best[k].mask;
+            hp.ops = fuse_ops(n, gs, best[k].gates);
             tangent_form(hp.ops);
+            if (!best[k].out_cx.empty()) {
+                hp.out_img.resize(n);
+                for (int q = 0; q < n; ++q) hp.out_img[q] = 1ull << q;
+                for (int gi : best[k].out_cx) {
+                    const G &g = gs[gi];
+                    hp.out_cx.push_back({g.q0, g.q1});
+                    for (int q = 0; q < n; ++q)
+                        hp.out_img[q] ^= ((hp.out_img[q] >> g.q0) & 1ull) << g.q1;
+                }
+            }
             if (k == 0 && pending_scale) hp.scale_in = true;
             if (k + 1 == best.size() && renorm_after[s]) hp.norm_out = true;
             plan.passes.push_back(std::move(hp));
         }
         pending_scale = renorm_after[s] != 0;
     }
-    for (HostPass &p : plan.passes) lower_pass(n, m, p);
+    for (HostPass &p : plan.passes)
+        if (!lower_pass(n, m, p)) return "internal: relabelling control on a lane bit";
     *out = std::move(plan);
     return "";
 }
@@ -869,7 +983,23 @@ std::string plan_json(const Plan &p) {
         const HostPass &h = p.passes[i];
         if (i) o << ",";
         o << "{\"local_mask\":" << h.local_mask << ",\"scale_in\":" << (h.scale_in ? 1 : 0)
-          << ",\"norm_out\":" << (h.norm_out ? 1 : 0) << ",\"ops\":[";
+          << ",\"norm_out\":" << (h.norm_out ? 1 : 0) << ",\"out_cx\":[";
+        for (size_t k = 0; k < h.out_cx.size(); ++k)
+            o << (k ? "," : "") << "[" << h.out_cx[k].first << "," << h.out_cx[k].second << "]";
+        o << "],\"out_img\":[";
+        for (size_t k = 0; k < h.out_img.size(); ++k) o << (k ? "," : "") << h.out_img[k];
+        // store record of the register kernel (address arithmetic of the last phase)
+        const IoRec &r = h.io_out;
+        o << "],\"io_out\":{\"kind\":" << (int)r.kind << ",\"g\":[" << (int)r.g4 << ","
+          << (int)r.g5 << "," << (int)r.g6 << "]";
+        const uint32_t *arrs[4] = {r.reg_off, r.wave_off, r.reg_xor, r.wave_xor};
+        const char *names[4] = {"reg_off", "wave_off", "reg_xor", "wave_xor"};
+        for (int a = 0; a < 4; ++a) {
+            o << ",\"" << names[a] << "\":[";
+            for (int k = 0; k < 16; ++k) o << (k ? "," : "") << arrs[a][k];
+            o << "]";
+        }
+        o << "},\"ops\":[";
         for (size_t k = 0; k < h.dev_ops.size(); ++k) {
             const DevOp &d = h.dev_ops[k];
             if (k) o << ",";

@@ -51,3 +51,11 @@ def test_reducer_kernels_compile(n, tile):
     g = np.random.default_rng(n)
     terms = gen.random_pauli_terms(g, n, 30) + gen.zz_terms(g, n, 10)
     B.jit_precompile_terms(n, terms, tile)
+
+
+@pytest.mark.parametrize("n,tile,seed", [(16, 10, 1), (18, 12, 2), (22, 14, 4)])
+def test_relabel_kernels_compile(n, tile, seed):
+    from tests.test_gpu_relabel import _ladder_circuit
+    gates = _ladder_circuit(n, np.random.default_rng(7100 + seed), 3)
+    assert any(p["out_cx"] for p in B.plan_describe(n, gates, tile)["passes"])
+    B.jit_precompile(n, gates, tile)

@@ -98,6 +98,14 @@ def interpret(n, plan, psi):
                 psi[((idx >> a) & 1) & ((idx >> b) & 1) == 1] *= -1
             else:
                 raise AssertionError(t)
+        # output relabelling: the pass stores amplitude j at C(j) for each
+        # trailing CNOT C, i.e. the CNOTs act after the pass, in order
+        for c, t in p.get("out_cx", []):
+            assert not (p["local_mask"] >> t) & 1
+            sel = (((idx >> c) & 1) == 1) & (((idx >> t) & 1) == 0)
+            i0 = idx[sel]
+            i1 = i0 | (1 << t)
+            psi[i0], psi[i1] = psi[i1].copy(), psi[i0].copy()
     return psi
 
 
@@ -114,6 +122,11 @@ def _check_phases(plan):
     for p in plan["passes"]:
         ph = p["phases"]
         assert ph[0]["op_begin"] == 0 and ph[-1]["op_end"] == len(p["ops"])
+        lb = _local_bits(p["local_mask"])
+        for c, t in p.get("out_cx", []):
+            assert t not in lb                  # relabelling targets are non-local
+            if c in lb:
+                assert lb.index(c) >= 7         # never a lane bit of the store
         for a, b in zip(ph, ph[1:]):
             assert a["op_end"] == b["op_begin"]
         for k, f in enumerate(ph):
@@ -167,11 +180,15 @@ def test_plan_matches_oracle_random_gates(n, tile):
     assert np.max(np.abs(psi - ref)) < 5e-5
 
 
-def test_hea_24q_two_passes_per_layer():
+def test_hea_24q_pass_counts():
+    """Two HEA layers on 24 qubits with 14 local bits take 3 passes: the
+    trailing CNOT of the chain becomes an output relabelling (4 passes
+    without it)."""
     w = gen.config2()
     pre = B.plan_describe(24, w.prefix)
     suf = B.plan_describe(24, w.suffixes[0])
-    assert len(suf["passes"]) == 4
+    assert len(suf["passes"]) == 3
+    assert suf["passes"][-1]["out_cx"]
     assert len(pre["passes"]) <= 12
     for p in pre["passes"] + suf["passes"]:
         assert p["local_mask"] & 0xF == 0xF   # 128-byte runs
@@ -224,5 +241,69 @@ def test_trie_leaves_of_equal_length_share_structure():
         ref = shape(B.plan_describe(20, group[0]))
         for gates in group[1:]:
             assert shape(B.plan_describe(20, gates)) == ref
+            checked += 1
+    assert checked >= 3
+
+
+def _store_addresses(n, m, p, tile_bases_out):
+    """Store index of every element (tile, wave, lane, register) by the
+    register kernel's address arithmetic with output relabelling, and the
+    element's logical index (the same arithmetic without it)."""
+    io = p["io_out"]
+    g4, g5, g6 = io["g"]
+    lane = np.arange(64)
+    if io["kind"] == 1:
+        lane_off = ((lane & 7) << 1) | (((lane >> 3) & 1) << g4) | (((lane >> 4) & 1) << g5) | (((lane >> 5) & 1) << g6)
+    else:
+        lane_off = (lane & 15) | (((lane >> 4) & 1) << g4) | (((lane >> 5) & 1) << g5)
+    nl = [q for q in range(n) if not (p["local_mask"] >> q) & 1]
+    waves = 1 << (m - 10)
+    addr, logical = [], []
+    for ti in range(1 << (n - m)):
+        base = sum(1 << nl[b] for b in range(len(nl)) if (ti >> b) & 1)
+        for w in range(waves):
+            for k in range(16):
+                lo = io["wave_off"][w] | io["reg_off"][k]
+                logical.append(base | lo | lane_off)
+                hi = tile_bases_out[ti] ^ io["wave_xor"][w] ^ io["reg_xor"][k]
+                addr.append(hi | lo | lane_off)
+    return np.concatenate(addr), np.concatenate(logical)
+
+
+def test_relabel_store_addresses_are_the_cnot_permutation():
+    """For passes with output relabelling, the store index computed from the
+    plan's store record and relabelled tile origins equals L(j), the image
+    of the element's logical index under the pass's trailing CNOTs, and the
+    stores are a permutation of the state."""
+    from tests.test_gpu_relabel import _ladder_circuit
+    checked = 0
+    for n, tile, seed in [(16, 10, 1), (18, 12, 2), (20, 14, 3)]:
+        gates = _ladder_circuit(n, np.random.default_rng(7100 + seed), 3)
+        plan = B.plan_describe(n, gates, tile)
+        m = plan["tile_bits"]
+        for p in plan["passes"]:
+            if not p["out_cx"]:
+                continue
+            img = p["out_img"]
+            assert len(img) == n
+            nl = [q for q in range(n) if not (p["local_mask"] >> q) & 1]
+            tbo = []
+            for ti in range(1 << (n - m)):
+                o = 0
+                for b, q in enumerate(nl):
+                    if (ti >> b) & 1:
+                        o ^= img[q]
+                tbo.append(o)
+            addr, logical = _store_addresses(n, m, p, tbo)
+            assert np.array_equal(np.sort(addr), np.arange(1 << n))
+            want = np.zeros_like(logical)
+            for q in range(n):
+                want ^= np.where((logical >> q) & 1, img[q], 0)
+            # L from the CNOT list directly
+            ref = logical.copy()
+            for c, t in p["out_cx"]:
+                ref ^= ((ref >> c) & 1) << t
+            assert np.array_equal(want, ref)
+            assert np.array_equal(addr, ref)
             checked += 1
     assert checked >= 3
