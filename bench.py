@@ -25,13 +25,65 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--tile-bits", type=int, default=14,
+                    help="local bits per pass tile (QW_OPT_TILE_BITS, 10..14)")
     ap.add_argument("--cpu-tasks", type=int, default=1,
                     help="tasks in the oracle's bounded CPU sample")
-    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep"],
+    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy"],
                     help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "
                          "tree, 512 leaves, 1024 shots; noisy: 22-qubit 256 trajectories, 1024 "
-                         "shots; sweep: gate-pass HBM bandwidth over qubits and sizes")
+                         "shots; sweep: gate-pass HBM bandwidth over qubits and sizes; copy: "
+                         "5 plain 1 GiB device copies (the reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_fingerprint() -> str:
+    """Hash of the library's kernel, planner and generator sources: a
+    counter-based traffic figure is valid only for the code it was taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2609_23664_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(summary: str):
+    """HBM bytes per launch of the pass kernels from a committed counter
+    summary (lines `fingerprint: X` and `traffic_bytes_per_launch: N`), or
+    None when the summary is missing or was taken on other sources."""
+    import re
+    p = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        txt = f.read()
+    fp = re.search(r"^fingerprint:\s*([0-9a-f]+)", txt, re.M)
+    tb = re.search(r"^traffic_bytes_per_launch:\s*([0-9.e+]+)", txt, re.M)
+    if not fp or not tb or fp.group(1) != kernel_fingerprint():
+        return None
+    return float(tb.group(1))
+
+
+def bench_copy(args):
+    import torch
+    n = 1 << 27                       # complex64 elements: 1 GiB
+    a = torch.ones(n, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    return {"metric": "device copy GB/s", "value": round(2 * 8 * n / dt / 1e9, 1), "unit": "GB/s",
+            "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n, "copies": 5}
 
 
 def main():
@@ -47,7 +99,8 @@ def main():
     from workloads import gen
 
     if args.workload != "vqe":
-        extra = {"trie": bench_trie, "noisy": bench_noisy, "sweep": bench_sweep}[args.workload]
+        extra = {"trie": bench_trie, "noisy": bench_noisy, "sweep": bench_sweep,
+                 "copy": bench_copy}[args.workload]
         print(json.dumps(extra(args)), flush=True)
         return
 
@@ -57,6 +110,7 @@ def main():
     terms = w.terms
     prov = fingerprint(n, w.prefix)
     ctx = B.Ctx(0)
+    ctx.set_option(B.QW_OPT_TILE_BITS, args.tile_bits)
 
     # gate lists marshalled once (host preparation, outside the timed steps;
     # the library's plan cache makes later steps skip planning, which the
@@ -66,9 +120,9 @@ def main():
     # generated kernels of the workload (compiled, or loaded from the disk
     # cache) before timing: the compile step, reported separately
     t_c = time.perf_counter()
-    B.jit_precompile(n, prefix)
-    B.jit_precompile(n, suffixes[0])
-    B.jit_precompile_terms(n, terms)
+    B.jit_precompile(n, prefix, args.tile_bits)
+    B.jit_precompile(n, suffixes[0], args.tile_bits)
+    B.jit_precompile_terms(n, terms, args.tile_bits)
     jit_setup_s = time.perf_counter() - t_c
 
     # ---- reuse path: slot 0 = boundary, slots 1..T = tasks
@@ -142,10 +196,13 @@ def main():
     n_l, ms, by = stats[0]
     peak = 8000.0
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = measured_traffic("vqe_24q_64t_pass_traffic.md")
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak,
-                          "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": None,
-                          "kernel": "pass_kernel<14>", "launches": n_l,
-                          "avg_launch_ms": round(ms / max(1, n_l), 4)}
+                          "unit": "GB/s", "frac": round(achieved / peak, 4),
+                          "traffic": None if traffic is None else round(traffic),
+                          "kernel": f"qw_pass (generated gate-pass kernels, {args.tile_bits} tile bits)",
+                          "launches": n_l, "avg_launch_ms": round(ms / max(1, n_l), 4),
+                          "algorithmic_bytes_per_launch": round(by / max(1, n_l))}
     red = stats[1]
     if red[0]:
         result["reducer"] = {"launches": red[0], "avg_launch_ms": round(red[1] / red[0], 4),

@@ -133,6 +133,13 @@ __device__ __forceinline__ void lds_barrier() {
     __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Exchange inside one wave (the wave holds the same amplitudes before and
+// after it): the wave's own LDS writes must have completed before it reads;
+// no other wave touches those addresses, so no workgroup barrier is needed.
+__device__ __forceinline__ void lds_wave_sync() {
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 // ------------------------------------------------------------- lanes
 // Value of lane (lane ^ 2^J) of the 64-wide wavefront: DPP quad permutes and
 // row mirrors for J < 4, cross-row shuffles for J = 4, 5.
@@ -455,7 +462,9 @@ __device__ __forceinline__ void dset_apply(float2 (&v)[16], const DevOp *tab, bo
 // ------------------------------------------------------------- reducer
 // Sum over one thread's register pairs of sign_k * Re or Im of
 // conj(v[k ^ X]) v[k]; each unordered pair is counted once (the caller
-// doubles it). FP32 products and an FP32 sum over at most 16 values.
+// doubles it). Two FP32 FMAs per pair into one FP32 sum (the sign is
+// applied to a factor, which is exact): Re = b.x a.x + b.y a.y and
+// Im = b.x a.y - b.y a.x with b = v[k ^ X], a = v[k].
 template <int X, bool ODD>
 __device__ __forceinline__ float pair_sum(const float2 (&v)[16], uint32_t smask) {
     static_assert(X > 0 && X < 16, "off-diagonal register mask");
@@ -465,11 +474,15 @@ __device__ __forceinline__ float pair_sum(const float2 (&v)[16], uint32_t smask)
     for (int k = 0; k < 16; ++k) {
         if (k & lead) continue;
         const float2 a = v[k], b = v[k ^ X];
-        float t;
-        if constexpr (ODD) t = fmaf(b.x, a.y, -(b.y * a.x));
-        else t = fmaf(b.x, a.x, b.y * a.y);
-        const float sg = ((smask >> k) & 1u) ? -1.0f : 1.0f;
-        acc = fmaf(sg, t, acc);
+        const bool neg = (smask >> k) & 1u;
+        const float bx = neg ? -b.x : b.x, by = neg ? -b.y : b.y;
+        if constexpr (ODD) {
+            acc = fmaf(bx, a.y, acc);
+            acc = fmaf(-by, a.x, acc);
+        } else {
+            acc = fmaf(bx, a.x, acc);
+            acc = fmaf(by, a.y, acc);
+        }
     }
     return acc;
 }

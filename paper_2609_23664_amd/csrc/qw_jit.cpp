@@ -68,17 +68,18 @@ void emit_io_helpers(Gen &g, const char *name, const IoRec &r, int m) {
     g << ";\n}\n";
 }
 
-void emit_load(Gen &g, const IoRec &r) {
-    g << "__device__ __forceinline__ void load_in(float2 (&v)[16], const void *src, uint64_t ub, "
-         "uint32_t lb) {\n";
+// Loads of registers [k0, k1) of the first phase (k0, k1 even) into v[k - k0].
+void emit_load(Gen &g, const IoRec &r, const char *name, int k0, int k1) {
+    g << "__device__ __forceinline__ void " << name << "(float2 (&v)[" << std::max(1, k1 - k0)
+      << "], const void *src, uint64_t ub, uint32_t lb) {\n    (void)v; (void)src; (void)ub; (void)lb;\n";
     if (r.kind == IO_F4) {
-        for (int k2 = 0; k2 < 8; ++k2)
-            g << "    { const float4 q = buf_ld4(src, ub + " << hex(r.reg_off[2 * k2]) << ", lb); v["
-              << 2 * k2 << "] = make_float2(q.x, q.y); v[" << 2 * k2 + 1
+        for (int k = k0; k < k1; k += 2)
+            g << "    { const float4 q = buf_ld4(src, ub + " << hex(r.reg_off[k]) << ", lb); v["
+              << k - k0 << "] = make_float2(q.x, q.y); v[" << k + 1 - k0
               << "] = make_float2(q.z, q.w); }\n";
     } else {
-        for (int k = 0; k < 16; ++k)
-            g << "    v[" << k << "] = buf_ld2(src, ub + " << hex(r.reg_off[k]) << ", lb);\n";
+        for (int k = k0; k < k1; ++k)
+            g << "    v[" << k - k0 << "] = buf_ld2(src, ub + " << hex(r.reg_off[k]) << ", lb);\n";
     }
     g << "}\n";
 }
@@ -246,25 +247,56 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
     return g.str();
 }
 
+// Local bits of a phase that select the wave (above the register and lane bits).
+uint32_t wave_bits(int m, const DevPhase &f) {
+    uint32_t R = 0, w = 0;
+    for (int s = 0; s < 4; ++s) R |= 1u << f.reg[s];
+    int lanes = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((R >> b) & 1u) continue;
+        if (lanes < 6) {
+            ++lanes;
+            continue;
+        }
+        w |= 1u << b;
+    }
+    return w;
+}
+
 std::string emit_body(int m, const HostPass &p) {
     std::ostringstream g;
     g << "__device__ __forceinline__ void body(float2 (&v)[16], const DevOp *__restrict__ ops, "
          "uint32_t tid, uint32_t lane, uint64_t base, char *lb) {\n";
     g << "    (void)lane; (void)base; (void)lb;\n";
     const auto &ph = p.dev_phases;
-    for (size_t k = 0; k < ph.size(); ++k)
-        g << "    const uint32_t tl" << k << " = thread_local_index(tid, " << (int)ph[k].reg[0] << "u, "
-          << (int)ph[k].reg[1] << "u, " << (int)ph[k].reg[2] << "u, " << (int)ph[k].reg[3]
-          << "u); (void)tl" << k << ";\n";
+    // A phase's thread index (and the LDS addresses derived from it) is
+    // computed when the phase starts, from a copy of tid that the compiler
+    // must treat as new: otherwise it hoists the index arithmetic of every
+    // phase out of the persistent tile loop and keeps it in VGPRs, which
+    // pushes the prefetched tile into scratch.
+    auto tl_def = [&](size_t k) {
+        std::ostringstream t;
+        t << "    uint32_t tid" << k << " = tid; __asm__ volatile(\"\" : \"+v\"(tid" << k << "));\n"
+          << "    const uint32_t tl" << k << " = thread_local_index(tid" << k << ", " << (int)ph[k].reg[0] << "u, "
+          << (int)ph[k].reg[1] << "u, " << (int)ph[k].reg[2] << "u, " << (int)ph[k].reg[3] << "u); (void)tl"
+          << k << ";\n";
+        return t.str();
+    };
+    g << tl_def(0);
     for (size_t k = 0; k < ph.size(); ++k) {
+        if (k > 0) g << tl_def(k);
         if (k > 0) {
-            g << "    {   // exchange " << k - 1 << " -> " << k << "\n";
+            // an exchange between layouts with the same wave bits moves data
+            // only within each wave (the first exchange of a tile stays a
+            // full one: the previous tile's reads may still be in flight)
+            const bool local = k > 1 && wave_bits(m, ph[k - 1]) == wave_bits(m, ph[k]);
+            g << "    {   // exchange " << k - 1 << " -> " << k << (local ? " (within waves)" : "") << "\n";
             g << "        const uint32_t s8 = swz(tl" << k - 1 << ") << 3;\n";
-            g << "        lds_barrier();\n";
+            g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
             for (int r = 0; r < 16; ++r)
                 g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << ph[k - 1].lds_off[r] << "u)) = v["
                   << r << "];\n";
-            g << "        lds_barrier();\n";
+            g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
             g << "        const uint32_t t8 = swz(tl" << k << ") << 3;\n";
             for (int r = 0; r < 16; ++r)
                 g << "        v[" << r << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ "
@@ -332,7 +364,7 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
     return k;
 }
 
-std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch) {
     Gen g;
     const int T = 1 << (m - 4);
     const int WG = T < 256 ? T : 256;
@@ -344,7 +376,12 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
     emit_io_helpers(g, "io_in", p.io_in, m);
     emit_io_helpers(g, "io_out", p.io_out, m);
     const bool remap = !p.out_img.empty();
-    emit_load(g, p.io_in);
+    // persistent form: registers [0, PF) of the next tile are loaded while
+    // the current one is worked on, the rest when it starts
+    const int PF = use_lds ? prefetch : 0;
+    emit_load(g, p.io_in, "load_in", 0, 16);
+    emit_load(g, p.io_in, "load_pre", 0, PF);
+    emit_load(g, p.io_in, "load_rest", PF, 16);
     emit_store(g, p.io_out, remap, m);
     // output base of the tile: the relabelled one, or the load base
     const char *obase = remap ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
@@ -387,23 +424,29 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds) {
              "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave), wx = io_out_wxor(wave);\n"
              "    const uint32_t li = io_in_lane(lane), lo = io_out_lane(lane);\n"
              "    char *lb = reinterpret_cast<char *>(lds);\n"
-             "    float2 nv[16];\n"
+             "    float2 nv[" << std::max(1, PF) << "];\n"
              "    {\n"
              "        const PassDesc *d0 = descs + item % n_descs;\n"
-             "        load_in(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + item / n_descs)) | wi, li);\n"
+             "        load_pre(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + item / n_descs)) | wi, li);\n"
              "    }\n"
              "    while (true) {\n"
              "        float2 v[16];\n"
              "        #pragma unroll\n"
-             "        for (int k = 0; k < 16; ++k) v[k] = nv[k];\n"
+             "        for (int k = 0; k < " << PF << "; ++k) v[k] = nv[k];\n"
              "        const uint32_t p = item % n_descs, tile = item / n_descs;\n"
              "        const PassDesc *d = descs + p;\n"
              "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tile));\n"
+             "        {\n"
+             "            float2 rest[" << std::max(1, 16 - PF) << "];\n"
+             "            load_rest(rest, ldu(&d->src), base | wi, li);\n"
+             "            #pragma unroll\n"
+             "            for (int k = " << PF << "; k < 16; ++k) v[k] = rest[k - " << PF << "];\n"
+             "        }\n"
              "        const uint32_t next = item + wpx;\n"
              "        const bool has_next = next < last;\n"
              "        if (has_next) {\n"
              "            const PassDesc *dn = descs + next % n_descs;\n"
-             "            load_in(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + next / n_descs)) | wi, li);\n"
+             "            load_pre(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + next / n_descs)) | wi, li);\n"
              "        }\n";
         if (p.scale_in) g << kScaleIn;
         g << "        body(v, ldu(&d->ops), tid, lane, base, lb);\n";
@@ -509,10 +552,28 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
         }
         o << "    }\n    lds_barrier();\n";
     }
+    // Per-thread FP32 term values are shifted into q[0..7] across phases and
+    // summed over the wave 8 at a time (each term's wave sum uses the same
+    // butterfly whatever its position, so the packing does not change it).
+    std::vector<uint32_t> pending;
+    auto flush = [&](const char *ind) {
+        const size_t nb = pending.size();
+        o << ind << "{\n" << ind << "    const double h = wave_reduce8(q, lane);\n";
+        o << ind << "    if (lane < 8u) {\n" << ind << "        const uint32_t pos = 4u * (lane & 1u) + "
+          << "2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);\n";
+        for (size_t j = 0; j < nb; ++j)
+            o << ind << "        if (pos == " << nb - 1 - j << "u) red[wave * NT + " << pending[j] << "] = h;\n";
+        o << ind << "    }\n" << ind << "    #pragma unroll\n" << ind << "    for (int i = 0; i < 8; ++i) q[i] = 0.f;\n"
+          << ind << "}\n";
+        pending.clear();
+    };
+    o << "    float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
     for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
         const RedPhase &f = rp.phases[pi];
         o << "    {   // phase " << pi << (f.diag ? " (diagonal terms, I/O layout)" : "") << "\n";
-        o << "        const uint32_t tl = thread_local_index(tid, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
+        // (an opaque copy of tid keeps the index arithmetic inside the tile loop)
+        o << "        uint32_t tidp = tid; __asm__ volatile(\"\" : \"+v\"(tidp));\n";
+        o << "        const uint32_t tl = thread_local_index(tidp, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
           << "u, " << (int)f.reg[2] << "u, " << (int)f.reg[3] << "u); (void)tl;\n";
         if (!f.diag) {
             o << "        const uint32_t t8 = swz(tl) << 3;\n";
@@ -527,34 +588,26 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
             o << "        float pr[16];\n        #pragma unroll\n        for (int k = 0; k < 16; ++k) pr[k] = "
                  "fmaf(v[k].x, v[k].x, v[k].y * v[k].y);\n";
         }
-        for (uint32_t j0 = f.t_begin; j0 < f.t_end; j0 += 8) {
-            const uint32_t nb = std::min<uint32_t>(8u, f.t_end - j0);
-            o << "        {\n            float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
-            for (uint32_t j = 0; j < nb; ++j) {
-                const TermDev &t = rp.terms[j0 + j];
-                o << "            {\n";
-                if (f.diag)
-                    o << "                float a = diag_sum(pr, " << t.smask << "u);\n";
-                else
-                    o << "                float a = pair_sum<" << (int)t.xr << ", " << (t.odd ? "true" : "false")
-                      << ">(v, " << t.smask << "u);\n                a *= 2.0f;\n";
-                o << "                const uint32_t par = (" << (int)t.neg << "u";
-                if (t.zt) o << " ^ (uint32_t)__popc(tl & " << t.zt << "u)";
-                if (t.zg) o << " ^ (uint32_t)__popcll(base & " << hex(t.zg) << ")";
-                o << ") & 1u;\n                if (par) a = -a;\n";
-                o << "                #pragma unroll\n                for (int i = 7; i > 0; --i) q[i] = q[i - 1];\n"
-                     "                q[0] = a;\n            }\n";
-            }
-            o << "            const double h = wave_reduce8(q, lane);\n";
-            o << "            if (lane < 8u) {\n                const uint32_t pos = 4u * (lane & 1u) + 2u * ((lane >> 1) & 1u) + "
-                 "((lane >> 2) & 1u);\n";
-            for (uint32_t j = 0; j < nb; ++j)
-                o << "                if (pos == " << nb - 1 - j << "u) red[wave * NT + " << rp.terms[j0 + j].col
-                  << "] = h;\n";
-            o << "            }\n        }\n";
+        for (uint32_t j = f.t_begin; j < f.t_end; ++j) {
+            const TermDev &t = rp.terms[j];
+            o << "        {\n";
+            if (f.diag)
+                o << "            float a = diag_sum(pr, " << t.smask << "u);\n";
+            else
+                o << "            float a = pair_sum<" << (int)t.xr << ", " << (t.odd ? "true" : "false")
+                  << ">(v, " << t.smask << "u);\n            a *= 2.0f;\n";
+            o << "            const uint32_t par = (" << (int)t.neg << "u";
+            if (t.zt) o << " ^ (uint32_t)__popc(tl & " << t.zt << "u)";
+            if (t.zg) o << " ^ (uint32_t)__popcll(base & " << hex(t.zg) << ")";
+            o << ") & 1u;\n            if (par) a = -a;\n";
+            o << "            #pragma unroll\n            for (int i = 7; i > 0; --i) q[i] = q[i - 1];\n"
+                 "            q[0] = a;\n        }\n";
+            pending.push_back(t.col);
+            if (pending.size() == 8) flush("        ");
         }
         o << "    }\n";
     }
+    if (!pending.empty()) flush("    ");
     o << "}\n";
     o << "__device__ const uint32_t kCols[NT] = {";
     for (size_t c = 0; c < NT; ++c) o << (c ? ", " : "") << rp.cols[c] << "u";
@@ -739,6 +792,38 @@ std::string compile_one(const std::string &src, std::vector<char> *code) {
     return "";
 }
 
+// Private segment (scratch) bytes per lane of the kernel `name` in an
+// AMDGPU code object: field 1 (offset 4) of its kernel descriptor `name.kd`.
+// Returns -1 if the descriptor is not found.
+long code_scratch_bytes(const std::vector<char> &code, const char *name) {
+    auto rd = [&](size_t off, size_t n) -> uint64_t {
+        uint64_t v = 0;
+        if (off + n > code.size()) return 0;
+        std::memcpy(&v, code.data() + off, n);
+        return v;
+    };
+    if (code.size() < 64 || std::memcmp(code.data(), "\x7f" "ELF", 4) != 0) return -1;
+    const uint64_t shoff = rd(0x28, 8), shentsize = rd(0x3A, 2), shnum = rd(0x3C, 2);
+    const std::string want = std::string(name) + ".kd";
+    for (uint64_t i = 0; i < shnum; ++i) {
+        const size_t sh = shoff + i * shentsize;
+        if (rd(sh + 4, 4) != 2) continue;  // SHT_SYMTAB
+        const uint64_t off = rd(sh + 0x18, 8), size = rd(sh + 0x20, 8), link = rd(sh + 0x28, 4);
+        const uint64_t stroff = rd(shoff + link * shentsize + 0x18, 8);
+        for (uint64_t j = 0; j + 24 <= size; j += 24) {
+            const uint64_t nm = stroff + rd(off + j, 4);
+            if (nm >= code.size()) continue;
+            const char *sname = code.data() + nm;
+            if (std::strncmp(sname, want.c_str(), code.size() - nm) != 0) continue;
+            const uint64_t shndx = rd(off + j + 6, 2), value = rd(off + j + 8, 8);
+            const size_t ds = shoff + shndx * shentsize;
+            const uint64_t fo = value - rd(ds + 0x10, 8) + rd(ds + 0x18, 8);
+            return (long)rd(fo + 4, 4);
+        }
+    }
+    return -1;
+}
+
 }  // namespace
 
 bool jit_available(int device, const JitReq &r) {
@@ -749,7 +834,7 @@ bool jit_available(int device, const JitReq &r) {
     }
     const std::string dir = cache_dir();
     if (dir.empty()) return false;
-    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds)
+    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16)
                                    : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
     struct stat sb;
     return ::stat(cache_path(dir, src).c_str(), &sb) == 0;
@@ -775,7 +860,7 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
     const char *dump = std::getenv("QW_JIT_DUMP");  // debugging: write sources to this folder
     for (size_t q = 0; q < need.size(); ++q) {
         const JitReq &r = ks[need[q]];
-        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds)
+        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16)
                          : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
         if (dump && *dump) {
             std::ofstream f(cache_path(dump, srcs[q]) + ".hip");
@@ -792,6 +877,19 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
             }
             const auto t0 = std::chrono::steady_clock::now();
             errs[q] = compile_one(src, &codes[q]);
+            // persistent pass kernels: if the full register prefetch of the
+            // next tile spills, prefetch half of it, else none (stored under
+            // the identity of the requested source)
+            const JitReq &r = ks[need[q]];
+            if (errs[q].empty() && r.pass && r.use_lds && code_scratch_bytes(codes[q], "qw_pass") > 0) {
+                for (int pf : {8, 0}) {
+                    std::vector<char> c2;
+                    const std::string e2 = compile_one(jit_pass_source(r.n, r.m, *r.pass, true, pf), &c2);
+                    if (!e2.empty()) break;
+                    codes[q].swap(c2);
+                    if (code_scratch_bytes(codes[q], "qw_pass") == 0) break;
+                }
+            }
             const auto t1 = std::chrono::steady_clock::now();
             g_compile_us.fetch_add(
                 (uint64_t)std::chrono::duration_cast<std::chrono::microseconds>(t1 - t0).count());

@@ -24,8 +24,10 @@ namespace qw {
 // key run the same generated kernel.
 std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds);
 
-// Full HIP source of the generated kernel for a key's pass.
-std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds);
+// Full HIP source of the generated kernel for a key's pass; `prefetch`
+// (0..16, even) is the number of registers of the next tile the persistent
+// form loads while working on the current one.
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch = 16);
 
 struct JitKernel {
     hipFunction_t fn = nullptr;

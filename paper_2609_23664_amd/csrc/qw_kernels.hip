@@ -713,6 +713,29 @@ __global__ __launch_bounds__(1 << (M - 4)) void reduce_kernel(const ReduceDesc *
     }
     __syncthreads();
 
+    // term values are shifted into q across phases and summed over the wave
+    // 8 at a time (each term's wave sum is the same butterfly whatever its
+    // position); pc holds the pending terms' columns, newest first
+    float q[8];
+    uint32_t pc[8];
+    #pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        q[i] = 0.0f;
+        pc[i] = 0u;
+    }
+    uint32_t np = 0;
+    auto flush = [&]() {
+        const double h = wave_reduce8(q, lane);
+        if (lane < 8u) {
+            const uint32_t pos = 4u * (lane & 1u) + 2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);
+            #pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (pos == (uint32_t)i && (uint32_t)i < np) red[wave * kMaxGroupTerms + pc[i]] = h;
+        }
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) q[i] = 0.0f;
+        np = 0;
+    };
     for (uint32_t pi = 0; pi < d.n_phases; ++pi) {
         const RedPhase ph = ld_words(d.phases + pi);
         const uint32_t tl = thread_local_index(tid, ph.reg);
@@ -728,37 +751,29 @@ __global__ __launch_bounds__(1 << (M - 4)) void reduce_kernel(const ReduceDesc *
             #pragma unroll
             for (int k = 0; k < 16; ++k) pr[k] = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
         }
-        for (uint32_t j0 = ph.t_begin; j0 < ph.t_end; j0 += 8) {
-            const uint32_t nb = (ph.t_end - j0 < 8u) ? (ph.t_end - j0) : 8u;
-            float q[8];
+        for (uint32_t j = ph.t_begin; j < ph.t_end; ++j) {
+            const TermDev t = ld_words(d.terms + j);
+            float a;
+            if (ph.diag) {
+                a = diag_sum(pr, t.smask);
+            } else {
+                a = t.odd ? pair_sum_x<true>(t.xr, v, t.smask)
+                          : pair_sum_x<false>(t.xr, v, t.smask);
+                a *= 2.0f;
+            }
+            const uint32_t par = (t.neg ^ __popc(tl & t.zt) ^ (uint32_t)__popcll(base & t.zg)) & 1u;
+            if (par) a = -a;
             #pragma unroll
-            for (int i = 0; i < 8; ++i) q[i] = 0.0f;
-            for (uint32_t j = 0; j < nb; ++j) {
-                const TermDev t = ld_words(d.terms + j0 + j);
-                float a;
-                if (ph.diag) {
-                    a = diag_sum(pr, t.smask);
-                } else {
-                    a = t.odd ? pair_sum_x<true>(t.xr, v, t.smask)
-                              : pair_sum_x<false>(t.xr, v, t.smask);
-                    a *= 2.0f;
-                }
-                const uint32_t par = (t.neg ^ __popc(tl & t.zt) ^ (uint32_t)__popcll(base & t.zg)) & 1u;
-                if (par) a = -a;
-                #pragma unroll
-                for (int i = 7; i > 0; --i) q[i] = q[i - 1];
-                q[0] = a;
+            for (int i = 7; i > 0; --i) {
+                q[i] = q[i - 1];
+                pc[i] = pc[i - 1];
             }
-            const double h = wave_reduce8(q, lane);
-            if (lane < 8u) {
-                const uint32_t pos = 4u * (lane & 1u) + 2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);
-                if (pos < nb) {
-                    const uint32_t j = nb - 1u - pos;
-                    red[wave * kMaxGroupTerms + gin<TermDev>(d.terms)[j0 + j].col] = h;
-                }
-            }
+            q[0] = a;
+            pc[0] = t.col;
+            if (++np == 8u) flush();
         }
     }
+    if (np) flush();
     __syncthreads();
     for (uint32_t c = tid; c < d.n_terms; c += T) {
         double s = 0.0;

@@ -517,7 +517,9 @@ uint32_t pad_high(int m, uint32_t R) {
 // Split a lowered pass into phases (register kernel only, m >= 10). In a
 // phase, an op whose target bit is a register or lane bit runs without any
 // data exchange; moving to a layout with other wave bits costs one LDS
-// exchange. Greedy: ops are taken in order, a blocked op blocks its bits.
+// exchange. Within a phase ops are taken in order and a blocked op blocks
+// its bits; the sequence of layouts comes from a small beam search under an
+// instruction-count cost model (below).
 void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vector<int> &unit_len,
                  const std::vector<std::array<double, 8>> &md_in) {
     // units: a single op, or an OP_DSET header with its members
@@ -547,11 +549,12 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
         }
         info[u] = in;
     }
-    std::vector<DevOp> lops;  // emitted in phase order
-    // Accept ops for layout R from `rem`; returns accepted / deferred.
-    auto run = [&](uint32_t R, const std::vector<int> &rem, std::vector<int> *acc,
+    // Accept ops for layout R from `rem`; returns accepted / deferred. With
+    // lanes_ok false only ops whose target is a register bit are taken (ops
+    // without a target always are).
+    auto run = [&](uint32_t R, bool lanes_ok, const std::vector<int> &rem, std::vector<int> *acc,
                    std::vector<int> *def) {
-        const uint32_t intra = R | lane_bits_of(m, R);
+        const uint32_t intra = lanes_ok ? (R | lane_bits_of(m, R)) : R;
         uint32_t blocked = 0;
         acc->clear();
         def->clear();
@@ -565,51 +568,144 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
             }
         }
     };
+    // Cost model (thread instructions per tile pass, 16 amplitudes per
+    // thread): a register-target op costs its arithmetic; a lane target adds
+    // the partner fetch of 32 floats (DPP for lane bits 0..3, twice that for
+    // the ds_bpermute of bits 4..5); a CNOT on registers is a renaming, a
+    // register target with a non-register control a select; each layout
+    // change costs one LDS exchange (32 LDS accesses, address arithmetic and
+    // two barriers).
+    constexpr double kExchange = 100.0;
+    constexpr double kWaveExchange = 50.0;  // same wave bits: no workgroup barrier
+    auto wave_of = [&](uint32_t R) {
+        return ((1u << m) - 1u) & ~R & ~lane_bits_of(m, R);
+    };
+    auto unit_cost = [&](int u, uint32_t R) -> double {
+        const uint32_t lanes = lane_bits_of(m, R);
+        double c = 0.0;
+        for (int j = 0; j < unit_len[u]; ++j) {
+            const DevOp &o = lops_in[ustart[u] + j];
+            auto lane_extra = [&](int bit) -> double {
+                if ((R >> bit) & 1u) return 0.0;
+                int J = 0;
+                for (int b = 0; b < bit; ++b) J += (lanes >> b) & 1u;
+                return J < 4 ? 32.0 : 64.0;
+            };
+            switch (o.type) {
+            case OP_URT: case OP_UR: c += 32.0 + lane_extra(o.a); break;
+            case OP_U: c += 64.0 + lane_extra(o.a); break;
+            case OP_PERM: c += 16.0 + lane_extra(o.a); break;
+            case OP_CX: {
+                const bool creg = o.lb != LOC_GLOBAL && ((R >> o.b) & 1u);
+                if ((R >> o.a) & 1u) c += creg ? 0.0 : 32.0;
+                else c += 32.0 + lane_extra(o.a);
+                break;
+            }
+            case OP_DIAG: c += 32.0; break;
+            case OP_CZ: c += 16.0; break;
+            case OP_DSET: c += 64.0; break;
+            case OP_PDIAG: c += 16.0; break;
+            default: break;
+            }
+        }
+        return c;
+    };
     const uint32_t R_F4 = (1u << 0) | (1u << 7) | (1u << 8) | (1u << 9);
     const uint32_t R_F2 = (1u << (m - 1)) | (1u << (m - 2)) | (1u << (m - 3)) | (1u << (m - 4));
-    std::vector<int> remaining(unit_len.size());
-    for (size_t i = 0; i < unit_len.size(); ++i) remaining[i] = (int)i;
-    std::vector<std::vector<int>> phase_ops;
-    std::vector<uint32_t> phase_R;
-    bool first = true;
-    while (!remaining.empty() || first) {
-        std::vector<uint32_t> cands;
-        if (first) {
-            cands = {R_F4, R_F2};
-        } else {
-            // register bits = the first needed bits outside the lanes
-            uint32_t want = 0;
-            for (int i : remaining) {
-                const int nb = info[i].need;
-                if (nb >= 6 && !((want >> nb) & 1u) && popc64(want) < kRegBits) want |= 1u << nb;
-            }
-            cands = {pad_high(m, want), R_F2, R_F4};
-        }
-        std::vector<int> best_acc, best_def, acc, def;
-        uint32_t best_R = cands[0];
-        for (uint32_t R : cands) {
-            run(R, remaining, &acc, &def);
-            if (acc.size() > best_acc.size() || best_acc.empty()) {
-                best_acc = acc;
-                best_def = def;
-                best_R = R;
-            }
-        }
-        if (!first && best_acc.empty() && !remaining.empty()) {
-            // cannot happen: every target is intra-wave for some layout
-            best_R = pad_high(m, 1u << info[remaining[0]].need);
-            run(best_R, remaining, &best_acc, &best_def);
-        }
-        phase_ops.push_back(best_acc);
-        phase_R.push_back(best_R);
-        remaining.swap(best_def);
-        first = false;
+    // Beam search over phase sequences: each step tries candidate layouts
+    // (the I/O layouts, the registers wanted next in program order, with or
+    // without the lane positions) under both acceptance policies; states
+    // are ranked by cost so far plus the register-only cost of what remains.
+    struct St {
+        std::vector<int> rem;
+        std::vector<std::vector<int>> ops;
+        std::vector<uint32_t> R;
+        double cost = 0.0;
+        double rank = 0.0;
+    };
+    std::vector<double> reg_cost(unit_len.size());
+    for (size_t i = 0; i < unit_len.size(); ++i) {
+        const int nb = info[i].need;
+        reg_cost[i] = unit_cost((int)i, nb >= 0 ? pad_high(m, 1u << nb) : R_F2);
     }
-    // The last phase must be able to store; otherwise add an empty one.
-    if (io_kind_of(m, phase_R.back()) == IO_NONE) {
-        phase_ops.push_back({});
-        phase_R.push_back(R_F2);
+    auto lower_bound = [&](const std::vector<int> &rem) {
+        double c = 0.0;
+        for (int i : rem) c += reg_cost[i];
+        return c;
+    };
+    const size_t beam = unit_len.size() > 512 ? 1 : 6;
+    std::vector<St> states(1), done;
+    for (size_t i = 0; i < unit_len.size(); ++i) states[0].rem.push_back((int)i);
+    while (!states.empty()) {
+        std::vector<St> next;
+        for (const St &st : states) {
+            const bool first = st.R.empty();
+            std::vector<uint32_t> cands;
+            if (first) {
+                cands = {R_F4, R_F2};
+            } else {
+                uint32_t want_hi = 0, want_any = 0;
+                for (int i : st.rem) {
+                    const int nb = info[i].need;
+                    if (nb < 0) continue;
+                    if (nb >= 6 && !((want_hi >> nb) & 1u) && popc64(want_hi) < kRegBits) want_hi |= 1u << nb;
+                    if (!((want_any >> nb) & 1u) && popc64(want_any) < kRegBits) want_any |= 1u << nb;
+                }
+                cands = {pad_high(m, want_hi), pad_high(m, want_any), R_F2, R_F4};
+                for (int i : st.rem)
+                    if (info[i].need >= 0) {
+                        cands.push_back(pad_high(m, 1u << info[i].need));
+                        break;
+                    }
+            }
+            std::sort(cands.begin(), cands.end());
+            cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+            std::vector<int> acc, def;
+            for (uint32_t R : cands) {
+                for (int pol = 0; pol < 2; ++pol) {
+                    run(R, pol == 0, st.rem, &acc, &def);
+                    if (acc.empty() && !(first && st.rem.empty())) continue;
+                    St ns;
+                    ns.rem = def;
+                    ns.ops = st.ops;
+                    ns.ops.push_back(acc);
+                    ns.R = st.R;
+                    ns.R.push_back(R);
+                    ns.cost = st.cost;
+                    if (!first)
+                        ns.cost += (st.R.size() > 1 && wave_of(st.R.back()) == wave_of(R)) ? kWaveExchange
+                                                                                      : kExchange;
+                    for (int i : acc) ns.cost += unit_cost(i, R);
+                    if (ns.rem.empty()) {
+                        if (io_kind_of(m, R) == IO_NONE) {
+                            ns.ops.push_back({});
+                            ns.R.push_back(R_F2);
+                            ns.cost += kExchange;
+                        }
+                        done.push_back(std::move(ns));
+                    } else {
+                        ns.rank = ns.cost + lower_bound(ns.rem);
+                        next.push_back(std::move(ns));
+                    }
+                }
+            }
+        }
+        std::stable_sort(next.begin(), next.end(), [](const St &a, const St &b) { return a.rank < b.rank; });
+        // one state per remaining set (the cheapest), then the best `beam`
+        std::vector<St> keep;
+        for (St &st : next) {
+            bool dup = false;
+            for (const St &k : keep) dup |= k.rem == st.rem && k.R.back() == st.R.back();
+            if (!dup) keep.push_back(std::move(st));
+            if (keep.size() == beam) break;
+        }
+        states.swap(keep);
     }
+    size_t bi = 0;
+    for (size_t i = 1; i < done.size(); ++i)
+        if (done[i].cost < done[bi].cost) bi = i;
+    std::vector<std::vector<int>> phase_ops = std::move(done[bi].ops);
+    std::vector<uint32_t> phase_R = std::move(done[bi].R);
     // Emit ops grouped by phase with operand locations resolved.
     std::vector<DevOp> out;
     p.dev_phases.clear();
@@ -718,7 +814,6 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
         p.dev_phases.push_back(dp);
     }
     lops_in.swap(out);
-    (void)lops;
 }
 
 // Host form of the uniform address arithmetic of an I/O phase.

@@ -136,3 +136,35 @@ def test_explain_trace_is_json():
     root = d["nodes"][0]
     assert root["provenance"] == P.fingerprint(12, w.prefix).hex()
     assert "Eq.(2)" in root["reason"]
+
+
+class _StubModel:
+    """Stands in for the trained perceptron: predicts a fixed correction of
+    the analytic log ratio (and log t_reuse)."""
+
+    def __init__(self, pred, lo=-1e9, hi=1e9):
+        self.pred, self.lo, self.hi = np.asarray(pred, dtype=np.float32), lo, hi
+        self.delta = 0.1
+
+    def in_range(self, f):
+        return bool(np.all(np.asarray(f) >= self.lo) and np.all(np.asarray(f) <= self.hi))
+
+    def predict(self, x):
+        return np.tile(self.pred, (len(x), 1))
+
+
+def test_learned_hook_drives_eq2_decision():
+    """The learned model's decision replaces Eq. (2) at each trie node; out of
+    its training range the analytic rule decides (hook returns None)."""
+    from paper_2609_23664_amd import costmodel as CM
+    from paper_2609_23664_amd.planner import plan_workload
+    w = gen.small_vqe(12, 3, 1, 6, 4, seed=11)
+    tasks = [w.task_gates(t) for t in range(w.n_tasks)]
+    analytic = plan_workload(w.n, tasks)
+    assert analytic.materialized                       # the byte rule reuses here
+    never = plan_workload(w.n, tasks, decide=CM.planner_hook(_StubModel([-9.0, 0.0])))
+    assert not never.materialized                      # predicted ratio e^-9 x the analytic one
+    always = plan_workload(w.n, tasks, decide=CM.planner_hook(_StubModel([5.0, 0.0])))
+    assert always.materialized == analytic.materialized
+    out_of_range = plan_workload(w.n, tasks, decide=CM.planner_hook(_StubModel([-9.0, 0.0], 0.0, 0.0)))
+    assert out_of_range.materialized == analytic.materialized
