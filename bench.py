@@ -27,7 +27,7 @@ def _parse():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--tile-bits", type=int, default=14,
                     help="local bits per pass tile (QW_OPT_TILE_BITS, 10..14)")
-    ap.add_argument("--cpu-tasks", type=int, default=1,
+    ap.add_argument("--cpu-tasks", type=int, default=8,
                     help="tasks in the oracle's bounded CPU sample")
     ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy"],
                     help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "

@@ -1245,7 +1245,7 @@ int qw_plan_cost(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t ti
                  uint64_t *n_passes, double *bytes) {
     if (n_gates && !gates) return QW_E_INVALID_ARG;
     Plan p;
-    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p, true, false);
     if (!e.empty()) return QW_E_INVALID_ARG;
     if (n_passes) *n_passes = p.passes.size();
     if (bytes) *bytes = (double)p.passes.size() * 2.0 * 8.0 * std::ldexp(1.0, (int)n);

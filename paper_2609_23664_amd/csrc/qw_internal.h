@@ -47,10 +47,11 @@ struct Plan {
 
 // Validates and plans `gates` on n qubits with at most tile_bits local bits
 // per pass; `relabel` allows output relabelling (trailing CNOTs with
-// non-local targets applied as store-address maps). Returns "" on success,
-// otherwise an error message.
+// non-local targets applied as store-address maps). Without `lower` the
+// passes keep their host ops only (no device records or phases: enough to
+// count passes). Returns "" on success, otherwise an error message.
 std::string build_plan(int n, const void *gates /* qw_gate* */, size_t n_gates,
-                       int tile_bits, Plan *out, bool relabel = true);
+                       int tile_bits, Plan *out, bool relabel = true, bool lower = true);
 
 // JSON form of a plan (for qw_plan_describe).
 std::string plan_json(const Plan &p);

@@ -971,7 +971,7 @@ bool lower_pass(int n, int m, HostPass &p) {
 }  // namespace
 
 std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits, Plan *out,
-                       bool relabel) {
+                       bool relabel, bool lower) {
     const qw_gate *gates = static_cast<const qw_gate *>(gates_v);
     if (n < 1 || n > kMaxQubits) return "qubit count out of range 1..30";
     if (tile_bits < kMinTileBits || tile_bits > kMaxTileBits) return "tile bits out of range 10..14";
@@ -1063,8 +1063,9 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
         }
         pending_scale = renorm_after[s] != 0;
     }
-    for (HostPass &p : plan.passes)
-        if (!lower_pass(n, m, p)) return "internal: relabelling control on a lane bit";
+    if (lower)
+        for (HostPass &p : plan.passes)
+            if (!lower_pass(n, m, p)) return "internal: relabelling control on a lane bit";
     *out = std::move(plan);
     return "";
 }
