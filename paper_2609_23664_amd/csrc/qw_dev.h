@@ -167,6 +167,17 @@ __device__ __forceinline__ float2 lane_xor2(float2 a) {
     return make_float2(lane_xor<J>(a.x), lane_xor<J>(a.y));
 }
 
+// The same exchange for an FP64 value (its two 32-bit halves moved alike).
+template <int J>
+__device__ __forceinline__ double lane_xor_d(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const float lo = lane_xor<J>(__int_as_float((int)(unsigned)b));
+    const float hi = lane_xor<J>(__int_as_float((int)(unsigned)(b >> 32)));
+    const unsigned long long r = (unsigned long long)(unsigned)__float_as_int(lo) |
+                                 ((unsigned long long)(unsigned)__float_as_int(hi) << 32);
+    return __longlong_as_double((long long)r);
+}
+
 // ------------------------------------------------------------- buffer I/O
 // Global loads and stores use buffer instructions: a resource built in
 // scalar registers from a wave-uniform base address plus the lane's 32-bit
@@ -499,7 +510,8 @@ __device__ __forceinline__ float diag_sum(const float (&pr)[16], uint32_t smask)
 }
 
 // Butterfly reduction of 8 per-lane partials (positions 0..7) across the
-// wave in FP64: after the xor 1/2/4 steps lane l holds position
+// wave in FP64 (values moved by DPP within rows of 16 lanes, by
+// ds_bpermute across them): after the xor 1/2/4 steps lane l holds position
 // 4(l&1) + 2((l>>1)&1) + ((l>>2)&1); xor 8/16/32 complete the wave sum.
 __device__ __forceinline__ double wave_reduce8(const float (&q)[8], uint32_t lane) {
     double e[8];
@@ -511,24 +523,24 @@ __device__ __forceinline__ double wave_reduce8(const float (&q)[8], uint32_t lan
     for (int i = 0; i < 4; ++i) {
         const double mine = b0 ? e[4 + i] : e[i];
         const double other = b0 ? e[i] : e[4 + i];
-        f[i] = mine + __shfl_xor(other, 1, 64);
+        f[i] = mine + lane_xor_d<0>(other);
     }
     double g[2];
     #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const double mine = b1 ? f[2 + i] : f[i];
         const double other = b1 ? f[i] : f[2 + i];
-        g[i] = mine + __shfl_xor(other, 2, 64);
+        g[i] = mine + lane_xor_d<1>(other);
     }
     double h;
     {
         const double mine = b2 ? g[1] : g[0];
         const double other = b2 ? g[0] : g[1];
-        h = mine + __shfl_xor(other, 4, 64);
+        h = mine + lane_xor_d<2>(other);
     }
-    h += __shfl_xor(h, 8, 64);
-    h += __shfl_xor(h, 16, 64);
-    h += __shfl_xor(h, 32, 64);
+    h += lane_xor_d<3>(h);
+    h += lane_xor_d<4>(h);
+    h += lane_xor_d<5>(h);
     return h;
 }
 
