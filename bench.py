@@ -121,8 +121,8 @@ def main():
     # cache) before timing: the compile step, reported separately
     t_c = time.perf_counter()
     B.jit_precompile(n, prefix, args.tile_bits)
-    B.jit_precompile(n, suffixes[0], args.tile_bits)
-    B.jit_precompile_terms(n, terms, args.tile_bits)
+    B.jit_precompile_suffix(n, w.suffixes[0], terms, args.tile_bits)   # passes, fused epilogue, reducers
+    B.jit_precompile_terms(n, terms, args.tile_bits)                   # reducers without fusion
     jit_setup_s = time.perf_counter() - t_c
 
     # ---- reuse path: slot 0 = boundary, slots 1..T = tasks

@@ -164,13 +164,22 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         give the same state up to FP32 rounding. [1]
  *   QW_OPT_SECOND_BUFFER_CAP  bytes of second state buffers one execution
  *                         may hold; batches beyond it run in chunks
- *                         (at least one task per chunk) [16 GiB] */
+ *                         (at least one task per chunk) [16 GiB]
+ *   QW_OPT_FUSED_EPILOGUE 1: in qw_run_suffix_batch with an expectation
+ *                         epilogue, the Pauli terms that the tasks' common
+ *                         last pass can evaluate on its own tiles (after
+ *                         conjugation through its output relabelling) are
+ *                         reduced inside that pass (generated kernels),
+ *                         when that saves a reducer sweep over the states;
+ *                         the results agree with separate reduction up to
+ *                         FP32 rounding of the per-thread partial sums. [1] */
 #define QW_OPT_TILE_BITS 1
 #define QW_OPT_PROFILE 2
 #define QW_OPT_XCD_REMAP 4
 #define QW_OPT_JIT 5
 #define QW_OPT_RELABEL 6
 #define QW_OPT_SECOND_BUFFER_CAP 7
+#define QW_OPT_FUSED_EPILOGUE 8
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.
@@ -323,6 +332,16 @@ int qw_jit_precompile(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
  * (the term groups and register phases that qw_expect_pauli would use). */
 int qw_jit_precompile_terms(uint32_t n_qubits, const uint64_t *x, const uint64_t *z,
                             uint32_t n_terms, uint32_t tile_bits, char *log, uint64_t cap);
+
+/* Compile (hipRTC, no GPU needed) the generated kernels that
+ * qw_run_suffix_batch uses for `gates` as the suffix of a batch of hot tasks
+ * with the expectation epilogue x/z[n_terms]: the passes, the last pass with
+ * its fused expectation epilogue when that applies (QW_OPT_FUSED_EPILOGUE),
+ * and the reducers of the remaining terms. Same arguments, log and results
+ * as qw_jit_precompile / qw_jit_precompile_terms. */
+int qw_jit_precompile_suffix(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
+                             const uint64_t *x_mask, const uint64_t *z_mask, uint32_t n_terms,
+                             uint32_t tile_bits, char *log, uint64_t cap);
 
 /* Generated-kernel counters of this process: kernels compiled, kernels taken
  * from the disk cache, and seconds spent compiling. Any pointer may be NULL. */

@@ -44,6 +44,7 @@ QW_OPT_XCD_REMAP = 4
 QW_OPT_JIT = 5
 QW_OPT_RELABEL = 6
 QW_OPT_SECOND_BUFFER_CAP = 7
+QW_OPT_FUSED_EPILOGUE = 8
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",
@@ -52,7 +53,8 @@ EXPORTED = (
     "qw_snapshot_free", "qw_snapshot_info", "qw_run_suffix_batch",
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
     "qw_mlp_workspace_floats", "qw_mlp_forward", "qw_mlp_backward", "qw_mlp_adam",
-    "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_stats", "qw_version",
+    "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_precompile_suffix",
+    "qw_jit_stats", "qw_version",
 )
 
 
@@ -156,6 +158,8 @@ def lib() -> ctypes.CDLL:
         "qw_jit_precompile": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
         "qw_jit_precompile_terms": ([u32, ctypes.POINTER(u64), ctypes.POINTER(u64), u32, u32,
                                      ctypes.c_char_p, u64], i32),
+        "qw_jit_precompile_suffix": ([u32, ctypes.POINTER(QwGate), u64, ctypes.POINTER(u64),
+                                      ctypes.POINTER(u64), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_jit_stats": ([ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)],
                          i32),
         "qw_version": ([], ctypes.c_char_p),
@@ -276,6 +280,20 @@ def jit_precompile_terms(n: int, terms, tile_bits: int = 14) -> None:
     cap = 1 << 20
     buf = ctypes.create_string_buffer(cap)
     rc = lib().qw_jit_precompile_terms(n, xs, zs, nt, tile_bits, buf, cap)
+    if rc != QW_OK:
+        raise QwError(rc, buf.value.decode(errors="replace"))
+
+
+def jit_precompile_suffix(n: int, gates, terms, tile_bits: int = 14) -> None:
+    """Host-only: compile the generated kernels of a suffix batch with an
+    expectation epilogue (passes, fused last pass, remaining reducers)."""
+    ga = gate_array(gates)
+    nt = len(terms)
+    xs = (ctypes.c_uint64 * max(1, nt))(*[int(t[1]) for t in terms])
+    zs = (ctypes.c_uint64 * max(1, nt))(*[int(t[2]) for t in terms])
+    cap = 1 << 20
+    buf = ctypes.create_string_buffer(cap)
+    rc = lib().qw_jit_precompile_suffix(n, ga.ptr, len(ga), xs, zs, nt, tile_bits, buf, cap)
     if rc != QW_OK:
         raise QwError(rc, buf.value.decode(errors="replace"))
 

@@ -40,6 +40,7 @@ struct PlanEntry {
     uint32_t n = 0;
     int tile_bits = 0;
     bool relabel = true;
+    bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
     std::vector<char> gates;  // the gate records the plan was built from
     std::shared_ptr<const qw::Plan> plan;
@@ -66,6 +67,7 @@ struct qw_ctx {
     DevBuf scratch;  // partial sums, sampler buffers
     DevBuf pingpong; // second state buffers of tasks with relabelling passes
     bool relabel = true;
+    bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
     void *staging = nullptr;
     size_t staging_cap = 0;
@@ -344,6 +346,11 @@ struct Exec {
     const Plan &plan_ref() const { return *planp; }
     const void *src = nullptr;  // first-pass source (snapshot) or nullptr
     void *dst = nullptr;
+    // fused expectation epilogue of the last pass (generated kernels only)
+    const RedPlan *epi = nullptr;
+    const std::string *epi_key = nullptr;
+    double *epi_part = nullptr;  // this task's [tiles][epi_nt] partials
+    uint32_t epi_nt = 0;
 };
 
 bool has_relabel(const Plan &p) {
@@ -554,9 +561,10 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             for (size_t t = 0; t < ex.size(); ++t) {
                 if (k >= ex[t].planp->passes.size()) continue;
                 const HostPass &p = ex[t].planp->passes[k];
-                const bool lds = p.norm_out || p.dev_phases.size() > 1;
-                if (p.jit_key.empty()) p.jit_key = jit_pass_key((int)n, m, p, lds);
-                const std::string &key = p.jit_key;
+                const bool with_epi = ex[t].epi && k + 1 == ex[t].planp->passes.size();
+                const bool lds = p.norm_out || p.dev_phases.size() > 1 || with_epi;
+                if (p.jit_key.empty()) p.jit_key = jit_pass_key((int)n, m, p, p.norm_out || p.dev_phases.size() > 1);
+                const std::string key = with_epi ? jit_pass_key((int)n, m, p, true) + *ex[t].epi_key : p.jit_key;
                 auto it = gi.find(key);
                 if (it == gi.end()) {
                     it = gi.emplace(key, members[k].size()).first;
@@ -564,6 +572,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                     JitReq r;
                     r.key = key;
                     r.pass = &p;
+                    r.epi = with_epi ? ex[t].epi : nullptr;
                     r.n = (int)n;
                     r.m = m;
                     r.use_lds = lds;
@@ -580,7 +589,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             for (size_t k = 0; k < steps; ++k)
                 for (auto &gm : members[k]) work[gm.first] += (uint64_t)gm.second.size() * tiles;
             for (size_t i = 0; i < reqs.size(); ++i)
-                want[i] = work[i] >= kJitHotTiles || jit_available(ctx->device, reqs[i]);
+                want[i] = reqs[i].epi || work[i] >= kJitHotTiles || jit_available(ctx->device, reqs[i]);
         }
         std::vector<JitReq> sel;
         std::vector<size_t> sel_of(reqs.size(), (size_t)-1);
@@ -624,6 +633,10 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             if (!p.out_img.empty()) {
                 d.tile_base_out = reinterpret_cast<const uint32_t *>(dbase + tbo_of[t][k]);
                 d.flags |= PD_REMAP_OUT;
+            }
+            if (e.epi && k + 1 == e.planp->passes.size()) {
+                d.red_part = e.epi_part;
+                d.red_nt = e.epi_nt;
             }
             d.ops = reinterpret_cast<const DevOp *>(dbase + op_off[t][k].first);
             d.phases = reinterpret_cast<const DevPhase *>(dbase + op_off[t][k].second);
@@ -671,10 +684,87 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     return QW_OK;
 }
 
+// Pauli string (X/Y support x, Z/Y support z, Y where both) conjugated by
+// CNOT(c, t): P -> C P C. The update of the support and of the sign is the
+// tableau rule of Aaronson and Gottesman (Phys. Rev. A 70, 052328, 2004).
+void conj_cnot(uint64_t *x, uint64_t *z, int *neg, int c, int t) {
+    const int xc = (int)((*x >> c) & 1ull), zc = (int)((*z >> c) & 1ull);
+    const int xt = (int)((*x >> t) & 1ull), zt = (int)((*z >> t) & 1ull);
+    *neg ^= xc & zt & (xt ^ zc ^ 1);
+    *x ^= (uint64_t)xc << t;
+    *z ^= (uint64_t)zt << c;
+}
+
+struct FusedEpi {
+    bool active = false;
+    std::vector<char> fused;  // per term: reduced in the last pass
+    RedPlan rplan;
+    std::string key;
+};
+
+void plan_fused_last(int n, int m, const HostPass &lp, const uint64_t *x, const uint64_t *z,
+                     uint32_t n_terms, FusedEpi *fe);
+
+// Decides the fused epilogue of a batch: every task's last pass must have
+// the same local set and relabelling, no pass may renormalize, the last
+// passes must run as generated kernels, and the terms left for the reducer
+// must need fewer sweeps than all of them.
+void plan_fused(qw_ctx *ctx, uint32_t n, const std::vector<Exec> &ex, const uint64_t *x,
+                const uint64_t *z, uint32_t n_terms, FusedEpi *fe) {
+    if (!ctx->fused_epilogue || ex.empty() || ctx->jit == 0) return;
+    const int m = ex[0].planp->m;
+    if (m < kMinTileBits || (int)n <= m) return;
+    const HostPass *last = nullptr;
+    for (const Exec &e : ex) {
+        const Plan &p = *e.planp;
+        if (p.passes.empty()) return;
+        for (const HostPass &h : p.passes)
+            if (h.norm_out || h.scale_in) return;
+        const HostPass &l = p.passes.back();
+        if (!last) last = &l;
+        else if (l.local_mask != last->local_mask || l.out_cx != last->out_cx) return;
+    }
+    const uint64_t tiles = 1ull << (n - m);
+    if (ctx->jit == 1 && (uint64_t)ex.size() * tiles < kJitHotTiles) return;
+    plan_fused_last((int)n, m, *last, x, z, n_terms, fe);
+}
+
+// The fused epilogue of a last pass: its terms (conjugated through the
+// pass's relabelling CNOTs) and their reducer plan, if that saves a sweep.
+void plan_fused_last(int n, int m, const HostPass &lp, const uint64_t *x, const uint64_t *z,
+                     uint32_t n_terms, FusedEpi *fe) {
+    const HostPass *last = &lp;
+    std::vector<uint64_t> xc(x, x + n_terms), zc(z, z + n_terms);
+    std::vector<int> neg(n_terms, 0);
+    std::vector<char> fused(n_terms, 0);
+    TermGroup g{last->local_mask, {}};
+    for (uint32_t j = 0; j < n_terms; ++j) {
+        for (size_t i = last->out_cx.size(); i-- > 0;)
+            conj_cnot(&xc[j], &zc[j], &neg[j], last->out_cx[i].first, last->out_cx[i].second);
+        if ((xc[j] & ~last->local_mask) == 0 && g.terms.size() < (size_t)kMaxGroupTerms) {
+            fused[j] = 1;
+            g.terms.push_back(j);
+        }
+    }
+    if (g.terms.empty()) return;
+    std::vector<uint64_t> rest;
+    for (uint32_t j = 0; j < n_terms; ++j)
+        if (!fused[j]) rest.push_back(x[j]);
+    const size_t before = group_terms(n, m, x, n_terms).size();
+    const size_t after = rest.empty() ? 0 : group_terms(n, m, rest.data(), rest.size()).size();
+    if (after >= before) return;
+    fe->rplan = plan_reduce_group(n, m, g, xc.data(), zc.data());
+    for (TermDev &t : fe->rplan.terms)
+        if (neg[fe->rplan.cols[t.col]]) t.neg ^= 1;
+    fe->fused = fused;
+    fe->key = jit_epilogue_key(n, m, *last, fe->rplan);
+    fe->active = true;
+}
+
 // Expectations for a list of slot pointers of one n-qubit layout.
 int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots,
                  const uint64_t *x, const uint64_t *z, const double *c, uint32_t n_terms,
-                 double *out, int out_is_host) {
+                 double *out, int out_is_host, const std::vector<char> *fused = nullptr) {
     const uint32_t ns = (uint32_t)slots.size();
     if (ns == 0) return QW_OK;
     const uint64_t full = (1ull << n) - 1;
@@ -695,7 +785,22 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     const int m = tile_bits_for((int)n, ctx->tile_bits);
     const bool small = m < kMinTileBits;
     const uint32_t tiles = small ? 1u : (1u << (n - m));
-    std::vector<TermGroup> groups = group_terms((int)n, m, x, n_terms);
+    // terms whose partials a fused pass epilogue already wrote are left out
+    std::vector<TermGroup> groups;
+    if (fused && !small) {
+        std::vector<uint32_t> idx;
+        std::vector<uint64_t> xs;
+        for (uint32_t j = 0; j < n_terms; ++j)
+            if (!(*fused)[j]) {
+                idx.push_back(j);
+                xs.push_back(x[j]);
+            }
+        if (!idx.empty()) groups = group_terms((int)n, m, xs.data(), xs.size());
+        for (TermGroup &g : groups)
+            for (uint32_t &t : g.terms) t = idx[t];
+    } else {
+        groups = group_terms((int)n, m, x, n_terms);
+    }
     std::vector<RedPlan> rplans;
     if (!small)
         for (const TermGroup &g : groups) rplans.push_back(plan_reduce_group((int)n, m, g, x, z));
@@ -815,7 +920,7 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
             hipError_t er = jit_launch_reduce(ctx->stream, *rk[g], dd + g * ns, ns, tiles, ctx->n_cu);
             if (er != hipSuccess) return hip_fail(ctx, er, "generated reduce launch");
         }
-    } else {
+    } else if (small || !groups.empty()) {
         ProfScope ps(ctx, 1, (double)ns * groups.size() * (double)(8ull << n));
         hipError_t er = small
             ? launch_reduce_small(ctx->stream, reinterpret_cast<const ReduceDescSmall *>(dbase + desc_off),
@@ -909,6 +1014,7 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         ctx->jit = (int)value;
         return QW_OK;
     case QW_OPT_RELABEL: ctx->relabel = value != 0; return QW_OK;
+    case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
     case QW_OPT_SECOND_BUFFER_CAP:
         if (value <= 0) return fail(ctx, QW_E_INVALID_ARG, "second buffer cap must be > 0");
         ctx->pingpong_cap = (uint64_t)value;
@@ -1134,16 +1240,43 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         ex[k].src = (src && src[k]) ? src[k]->data : nullptr;
         ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);
     }
-    int rc = execute(ctx, dst->n, ex);
-    if (rc) return rc;
     if (epi) {
         if (epi->n_terms > 0 && (!epi->x_mask || !epi->z_mask || !epi->coeff))
             return fail(ctx, QW_E_INVALID_ARG, "epilogue arrays are NULL");
         if (!epi->out) return fail(ctx, QW_E_INVALID_ARG, "epilogue out is NULL");
+        const uint64_t full = (1ull << dst->n) - 1;
+        for (uint32_t j = 0; j < epi->n_terms; ++j)
+            if ((epi->x_mask[j] & ~full) || (epi->z_mask[j] & ~full))
+                return fail(ctx, QW_E_INVALID_ARG, "Pauli mask has bits >= n");
+    }
+    // Fused expectation epilogue: terms that the last pass can evaluate on
+    // its own tile (after conjugation through its output relabelling) are
+    // reduced inside that pass, which saves a reducer sweep when the others
+    // then need fewer term groups.
+    FusedEpi fe;
+    if (epi && epi->n_terms > 0)
+        plan_fused(ctx, dst->n, ex, epi->x_mask, epi->z_mask, epi->n_terms, &fe);
+    if (fe.active) {
+        const int m = ex[0].planp->m;
+        const uint64_t tiles = 1ull << (dst->n - m);
+        const size_t part_bytes = (size_t)n_tasks * tiles * epi->n_terms * sizeof(double);
+        int rc0 = ensure(ctx, ctx->scratch, part_bytes + n_tasks * sizeof(double) + 256, "reduce scratch");
+        if (rc0) return rc0;
+        double *part = static_cast<double *>(ctx->scratch.p);
+        for (uint32_t k = 0; k < n_tasks; ++k) {
+            ex[k].epi = &fe.rplan;
+            ex[k].epi_key = &fe.key;
+            ex[k].epi_part = part + (size_t)k * tiles * epi->n_terms;
+            ex[k].epi_nt = epi->n_terms;
+        }
+    }
+    int rc = execute(ctx, dst->n, ex);
+    if (rc) return rc;
+    if (epi) {
         std::vector<const void *> slots(n_tasks);
         for (uint32_t k = 0; k < n_tasks; ++k) slots[k] = slot_ptr(dst, tasks[k].dst_slot);
         return expect_slots(ctx, dst->n, slots, epi->x_mask, epi->z_mask, epi->coeff,
-                            epi->n_terms, epi->out, epi->out_is_host);
+                            epi->n_terms, epi->out, epi->out_is_host, fe.active ? &fe.fused : nullptr);
     }
     return QW_OK;
 }
@@ -1322,6 +1455,83 @@ int qw_jit_precompile_terms(uint32_t n, const uint64_t *x, const uint64_t *z, ui
         reqs[g].m = m;
     }
     const std::string e = jit_precompile(reqs);
+    if (!e.empty()) {
+        put(e);
+        return QW_E_HIP;
+    }
+    return QW_OK;
+}
+
+int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates, const uint64_t *x,
+                             const uint64_t *z, uint32_t n_terms, uint32_t tile_bits, char *log,
+                             uint64_t cap) {
+    auto put = [&](const std::string &msg) {
+        if (log && cap) {
+            size_t k = std::min<size_t>(msg.size(), cap - 1);
+            std::memcpy(log, msg.data(), k);
+            log[k] = 0;
+        }
+    };
+    put("");
+    if (n_terms && (!x || !z)) {
+        put("term arrays are NULL");
+        return QW_E_INVALID_ARG;
+    }
+    Plan p;
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    if (!e.empty()) {
+        put(e);
+        return QW_E_INVALID_ARG;
+    }
+    if (p.m < kMinTileBits) return QW_OK;
+    const uint64_t full = (1ull << n) - 1;
+    for (uint32_t j = 0; j < n_terms; ++j)
+        if ((x[j] & ~full) || (z[j] & ~full)) {
+            put("Pauli mask has bits >= n");
+            return QW_E_INVALID_ARG;
+        }
+    FusedEpi fe;
+    bool norm = false;
+    for (const HostPass &h : p.passes) norm |= h.norm_out || h.scale_in;
+    if (n_terms && !p.passes.empty() && !norm && (int)n > p.m)
+        plan_fused_last((int)n, p.m, p.passes.back(), x, z, n_terms, &fe);
+    std::vector<JitReq> reqs;
+    for (size_t k = 0; k < p.passes.size(); ++k) {
+        const HostPass &h = p.passes[k];
+        const bool with_epi = fe.active && k + 1 == p.passes.size();
+        JitReq r;
+        r.use_lds = h.norm_out || h.dev_phases.size() > 1 || with_epi;
+        r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (with_epi ? fe.key : std::string());
+        r.pass = &h;
+        r.epi = with_epi ? &fe.rplan : nullptr;
+        r.n = (int)n;
+        r.m = p.m;
+        reqs.push_back(std::move(r));
+    }
+    // the reducer groups of the remaining terms, built as expect_slots builds them
+    std::vector<uint32_t> idx;
+    std::vector<uint64_t> xs;
+    for (uint32_t j = 0; j < n_terms; ++j)
+        if (!fe.active || !fe.fused[j]) {
+            idx.push_back(j);
+            xs.push_back(x[j]);
+        }
+    std::vector<TermGroup> groups;
+    if (!xs.empty()) groups = group_terms((int)n, p.m, xs.data(), xs.size());
+    for (TermGroup &g : groups)
+        for (uint32_t &t : g.terms) t = idx[t];
+    std::vector<RedPlan> rplans;
+    for (const TermGroup &g : groups) rplans.push_back(plan_reduce_group((int)n, p.m, g, x, z));
+    for (size_t g = 0; g < groups.size(); ++g) {
+        JitReq r;
+        r.key = jit_reduce_key((int)n, p.m, groups[g], rplans[g]);
+        r.group = &groups[g];
+        r.rplan = &rplans[g];
+        r.n = (int)n;
+        r.m = p.m;
+        reqs.push_back(std::move(r));
+    }
+    e = jit_precompile(reqs);
     if (!e.empty()) {
         put(e);
         return QW_E_HIP;

@@ -144,12 +144,13 @@ struct alignas(16) PassDesc {
     const uint32_t *tile_base_out;  // PD_REMAP_OUT: L(tile_base), per tile
     const IoRec *io_in;    // address record of phase 0
     const IoRec *io_out;   // address record of the last phase
+    double *red_part;      // fused expectation epilogue: [tiles][red_nt] FP64 partials
     uint32_t n_ops;
     uint32_t n_phases;
     uint32_t flags;
-    uint32_t pad;
+    uint32_t red_nt;       // fused expectation epilogue: columns per tile (all terms)
 };
-static_assert(sizeof(PassDesc) == 112, "PassDesc layout");
+static_assert(sizeof(PassDesc) == 128, "PassDesc layout");
 
 // Expectation reducer, small states (n < 10): the whole state is one tile
 // staged in LDS; one descriptor per slot.

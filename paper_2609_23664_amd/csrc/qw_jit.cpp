@@ -263,6 +263,90 @@ uint32_t wave_bits(int m, const DevPhase &f) {
     return w;
 }
 
+// LDS address map of one exchange: element l is stored at l ^ T(l) with
+// T(l) = XOR of terms ((l >> s) & mask), s >= 1 and mask within the low 5
+// bits. Every term moves a bit to a lower position, so the map is bijective
+// (triangular), and it keeps every bit >= 5: wave bits (all >= 6) are kept
+// and wave-local exchanges stay race-free. T is chosen so that the 64-bit
+// accesses of both layouts of the exchange spread over the banks: the first
+// 5 (and the first 4) lane bits of each layout map to independent bank bits
+// (the low 5, and the low 4, bits of the address).
+struct ExSwz {
+    std::vector<std::pair<int, uint32_t>> terms;
+    uint32_t apply(uint32_t l) const {
+        uint32_t t = 0;
+        for (const auto &x : terms) t ^= (l >> x.first) & x.second;
+        return l ^ t;
+    }
+};
+
+int gf2_rank(std::vector<uint32_t> v) {
+    int r = 0;
+    for (int bit = 4; bit >= 0; --bit) {
+        size_t piv = v.size();
+        for (size_t i = (size_t)r; i < v.size(); ++i)
+            if ((v[i] >> bit) & 1u) {
+                piv = i;
+                break;
+            }
+        if (piv == v.size()) continue;
+        std::swap(v[(size_t)r], v[piv]);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (i != (size_t)r && ((v[i] >> bit) & 1u)) v[i] ^= v[(size_t)r];
+        ++r;
+    }
+    return r;
+}
+
+std::vector<int> lane_list(int m, const DevPhase &f) {
+    uint32_t R = 0;
+    for (int s = 0; s < 4; ++s) R |= 1u << f.reg[s];
+    std::vector<int> lanes;
+    for (int b = 0; b < m && lanes.size() < 6; ++b)
+        if (!((R >> b) & 1u)) lanes.push_back(b);
+    return lanes;
+}
+
+// The kernels' fixed swizzle in this form: bits 5..9 and 10..13 folded
+// onto bits 0..4.
+ExSwz fixed_swizzle() {
+    ExSwz d;
+    d.terms = {{5, 31u}, {10, 31u}};
+    return d;
+}
+
+ExSwz choose_swizzle(int m, const DevPhase &a, const DevPhase &b) {
+    const std::vector<int> la = lane_list(m, a), lb = lane_list(m, b);
+    auto good = [&](const ExSwz &x) {
+        for (const std::vector<int> *ln : {&la, &lb}) {
+            std::vector<uint32_t> v5, v4;
+            for (size_t j = 0; j < 5; ++j) {
+                const uint32_t bank = x.apply(1u << (*ln)[j]) & 31u;
+                v5.push_back(bank);
+                if (j < 4) v4.push_back(bank & 15u);
+            }
+            if (gf2_rank(v5) < 5 || gf2_rank(v4) < 4) return false;
+        }
+        return true;
+    };
+    const ExSwz d = fixed_swizzle();
+    if (good(d)) return d;
+    std::vector<std::pair<int, uint32_t>> cands;
+    for (int sh = 1; sh < m; ++sh)
+        for (uint32_t mk = 1; mk < 32; ++mk) cands.push_back({sh, mk});
+    ExSwz x;
+    for (const auto &c : cands) {
+        x.terms = {c};
+        if (good(x)) return x;
+    }
+    for (size_t i = 0; i < cands.size(); ++i)
+        for (size_t j = i + 1; j < cands.size(); ++j) {
+            x.terms = {cands[i], cands[j]};
+            if (good(x)) return x;
+        }
+    return d;
+}
+
 std::string emit_body(int m, const HostPass &p) {
     std::ostringstream g;
     g << "__device__ __forceinline__ void body(float2 (&v)[16], const DevOp *__restrict__ ops, "
@@ -283,6 +367,12 @@ std::string emit_body(int m, const HostPass &p) {
         return t.str();
     };
     g << tl_def(0);
+    auto roff = [&](const DevPhase &f, int r) {
+        uint32_t l = 0;
+        for (int s2 = 0; s2 < 4; ++s2)
+            if ((r >> s2) & 1) l |= 1u << f.reg[s2];
+        return l;
+    };
     for (size_t k = 0; k < ph.size(); ++k) {
         if (k > 0) g << tl_def(k);
         if (k > 0) {
@@ -290,17 +380,26 @@ std::string emit_body(int m, const HostPass &p) {
             // only within each wave (the first exchange of a tile stays a
             // full one: the previous tile's reads may still be in flight)
             const bool local = k > 1 && wave_bits(m, ph[k - 1]) == wave_bits(m, ph[k]);
+            const ExSwz x = choose_swizzle(m, ph[k - 1], ph[k]);
+            auto thread_addr = [&](const std::string &t) {
+                std::ostringstream e;
+                e << "((" << t << " ^ (0u";
+                for (const auto &tm : x.terms)
+                    e << " ^ ((" << t << " >> " << tm.first << ") & " << tm.second << "u)";
+                e << ")) << 3)";
+                return e.str();
+            };
             g << "    {   // exchange " << k - 1 << " -> " << k << (local ? " (within waves)" : "") << "\n";
-            g << "        const uint32_t s8 = swz(tl" << k - 1 << ") << 3;\n";
+            g << "        const uint32_t s8 = " << thread_addr("tl" + std::to_string(k - 1)) << ";\n";
             g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
             for (int r = 0; r < 16; ++r)
-                g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << ph[k - 1].lds_off[r] << "u)) = v["
-                  << r << "];\n";
+                g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(roff(ph[k - 1], r)) << 3)
+                  << "u)) = v[" << r << "];\n";
             g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
-            g << "        const uint32_t t8 = swz(tl" << k << ") << 3;\n";
+            g << "        const uint32_t t8 = " << thread_addr("tl" + std::to_string(k)) << ";\n";
             for (int r = 0; r < 16; ++r)
                 g << "        v[" << r << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ "
-                  << ph[k].lds_off[r] << "u));\n";
+                  << (x.apply(roff(ph[k], r)) << 3) << "u));\n";
             g << "    }\n";
         }
         g << "    // phase " << k << ": registers " << (int)ph[k].reg[0] << "," << (int)ph[k].reg[1] << ","
@@ -364,7 +463,16 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
     return k;
 }
 
-std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch) {
+static void emit_reduce_tile(std::ostringstream &o, const RedPlan &rp, const DevPhase *stage,
+                             const char *name);
+
+std::string jit_epilogue_key(int n, int m, const HostPass &p, const RedPlan &epi) {
+    TermGroup g{p.local_mask, {}};
+    return "E" + jit_reduce_key(n, m, g, epi);
+}
+
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch,
+                            const RedPlan *epi) {
     Gen g;
     const int T = 1 << (m - 4);
     const int WG = T < 256 ? T : 256;
@@ -386,6 +494,17 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
     // output base of the tile: the relabelled one, or the load base
     const char *obase = remap ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
     g << emit_body(m, p);
+    if (epi) {
+        // fused expectation epilogue: the tile's terms, evaluated after the
+        // store from the last phase's registers (staged through LDS)
+        std::ostringstream e;
+        e << "constexpr int ENT = " << epi->cols.size() << ";\n#define NT ENT\n";
+        emit_reduce_tile(e, *epi, &p.dev_phases.back(), "epi_tile");
+        e << "#undef NT\n__device__ const uint32_t kECols[ENT] = {";
+        for (size_t c = 0; c < epi->cols.size(); ++c) e << (c ? ", " : "") << epi->cols[c] << "u";
+        e << "};\n";
+        g << e.str();
+    }
     if (!use_lds) {
         g << "extern \"C\" __global__ __launch_bounds__(WG) void qw_pass(const PassDesc *__restrict__ "
              "descs, uint32_t n_descs, uint32_t items, int remap) {\n"
@@ -410,7 +529,7 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "descs, uint32_t n_descs, uint32_t items, int remap) {\n"
              "    (void)remap;\n"
              "    __shared__ float2 lds[1 << M];\n"
-             "    __shared__ double red[T / 64 + 1];\n"
+             "    __shared__ double red[" << (epi ? "(T / 64) * ENT + 1" : "T / 64 + 1") << "];\n"
              "    (void)red;\n"
              "    const uint32_t w = blockIdx.x, x = w & 7u, j = w >> 3, wpx = gridDim.x >> 3;\n"
              "    const uint32_t per = (items + 7u) >> 3;\n"
@@ -462,8 +581,19 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
                  "            s = block_sum<T>(s, red);\n"
                  "            if (tid == 0) gout<double>(ldu(&d->norm_part))[tile] = s;\n"
                  "        }\n";
-        g << "        store_out(v, ldu(&d->dst), ((uint64_t)" << obase << " ^ wx) | wo, lo);\n"
-             "        if (!has_next) break;\n"
+        g << "        store_out(v, ldu(&d->dst), ((uint64_t)" << obase << " ^ wx) | wo, lo);\n";
+        if (epi)
+            g << "        epi_tile(v, tid, lane, base, lb, red);\n"
+                 "        __syncthreads();\n"
+                 "        {\n"
+                 "            double *part = ldu(&d->red_part) + (uint64_t)tile * ldu(&d->red_nt);\n"
+                 "            for (uint32_t c = tid; c < (uint32_t)ENT; c += T) {\n"
+                 "                double s = 0.0;\n"
+                 "                for (int ww = 0; ww < T / 64; ++ww) s += red[ww * ENT + c];\n"
+                 "                gout<double>(part)[kECols[c]] = s;\n"
+                 "            }\n"
+                 "        }\n";
+        g << "        if (!has_next) break;\n"
              "        item = next;\n"
              "    }\n"
              "}\n";
@@ -502,12 +632,108 @@ std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp) 
     return k;
 }
 
+// Term evaluation of one tile for a reducer plan (shared by the generated
+// reducers and the fused expectation epilogue of pass kernels): writes each
+// term's per-wave FP64 sum into red[wave * NT + column]. Without `stage`, v
+// holds the tile in the I/O layout (register slots = local bits 0, 7, 8, 9)
+// and the diagonal phase uses it directly; with `stage`, v holds the tile in
+// that phase layout (the last phase of a pass): the tile is staged in LDS
+// first and every phase reads it from there.
+static void emit_reduce_tile(std::ostringstream &o, const RedPlan &rp, const DevPhase *stage,
+                             const char *name) {
+    const int io_reg[4] = {0, 7, 8, 9};
+    bool any_lds = stage != nullptr;
+    for (const RedPhase &f : rp.phases) any_lds |= !f.diag;
+    o << "__device__ __forceinline__ void " << name << "(float2 (&v)[16], uint32_t tid, uint32_t lane, "
+         "uint64_t base, char *lb, double *red) {\n";
+    o << "    const uint32_t wave = tid >> 6;\n    (void)lb; (void)base;\n";
+    if (stage) {
+        o << "    {\n        uint32_t tids = tid; __asm__ volatile(\"\" : \"+v\"(tids));\n"
+          << "        const uint32_t s8 = swz(thread_local_index(tids, " << (int)stage->reg[0] << "u, "
+          << (int)stage->reg[1] << "u, " << (int)stage->reg[2] << "u, " << (int)stage->reg[3] << "u)) << 3;\n"
+          << "        lds_barrier();\n";
+        for (int k = 0; k < 16; ++k)
+            o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << stage->lds_off[k] << "u)) = v[" << k << "];\n";
+        o << "    }\n    lds_barrier();\n";
+    } else {
+        o << "    const uint32_t tlio = thread_local_index(tid, " << io_reg[0] << "u, " << io_reg[1] << "u, "
+          << io_reg[2] << "u, " << io_reg[3] << "u);\n";
+        if (any_lds) {
+            o << "    {\n        const uint32_t s8 = swz(tlio) << 3;\n";
+            for (int k = 0; k < 16; ++k) {
+                uint32_t l = 0;
+                for (int s2 = 0; s2 < 4; ++s2)
+                    if ((k >> s2) & 1) l |= 1u << io_reg[s2];
+                o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (swz_host(l) << 3) << "u)) = v[" << k
+                  << "];\n";
+            }
+            o << "    }\n    lds_barrier();\n";
+        }
+    }
+    // Per-thread FP32 term values are shifted into q[0..7] across phases and
+    // summed over the wave 8 at a time (each term's wave sum uses the same
+    // butterfly whatever its position, so the packing does not change it).
+    std::vector<uint32_t> pending;
+    auto flush = [&](const char *ind) {
+        const size_t nb = pending.size();
+        o << ind << "{\n" << ind << "    const double h = wave_reduce8(q, lane);\n";
+        o << ind << "    if (lane < 8u) {\n" << ind << "        const uint32_t pos = 4u * (lane & 1u) + "
+          << "2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);\n";
+        for (size_t j = 0; j < nb; ++j)
+            o << ind << "        if (pos == " << nb - 1 - j << "u) red[wave * NT + " << pending[j] << "] = h;\n";
+        o << ind << "    }\n" << ind << "    #pragma unroll\n" << ind << "    for (int i = 0; i < 8; ++i) q[i] = 0.f;\n"
+          << ind << "}\n";
+        pending.clear();
+    };
+    o << "    float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
+    for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
+        const RedPhase &f = rp.phases[pi];
+        const bool from_lds = !f.diag || stage != nullptr;
+        o << "    {   // phase " << pi << (f.diag ? " (diagonal terms)" : "") << "\n";
+        // (an opaque copy of tid keeps the index arithmetic inside the tile loop)
+        o << "        uint32_t tidp = tid; __asm__ volatile(\"\" : \"+v\"(tidp));\n";
+        o << "        const uint32_t tl = thread_local_index(tidp, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
+          << "u, " << (int)f.reg[2] << "u, " << (int)f.reg[3] << "u); (void)tl;\n";
+        if (from_lds) {
+            o << "        const uint32_t t8 = swz(tl) << 3;\n";
+            for (int k = 0; k < 16; ++k) {
+                uint32_t l = 0;
+                for (int s2 = 0; s2 < 4; ++s2)
+                    if ((k >> s2) & 1) l |= 1u << f.reg[s2];
+                o << "        v[" << k << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ " << (swz_host(l) << 3)
+                  << "u));\n";
+            }
+        }
+        if (f.diag)
+            o << "        float pr[16];\n        #pragma unroll\n        for (int k = 0; k < 16; ++k) pr[k] = "
+                 "fmaf(v[k].x, v[k].x, v[k].y * v[k].y);\n";
+        for (uint32_t j = f.t_begin; j < f.t_end; ++j) {
+            const TermDev &t = rp.terms[j];
+            o << "        {\n";
+            if (f.diag)
+                o << "            float a = diag_sum(pr, " << t.smask << "u);\n";
+            else
+                o << "            float a = pair_sum<" << (int)t.xr << ", " << (t.odd ? "true" : "false")
+                  << ">(v, " << t.smask << "u);\n            a *= 2.0f;\n";
+            o << "            const uint32_t par = (" << (int)t.neg << "u";
+            if (t.zt) o << " ^ (uint32_t)__popc(tl & " << t.zt << "u)";
+            if (t.zg) o << " ^ (uint32_t)__popcll(base & " << hex(t.zg) << ")";
+            o << ") & 1u;\n            if (par) a = -a;\n";
+            o << "            #pragma unroll\n            for (int i = 7; i > 0; --i) q[i] = q[i - 1];\n"
+                 "            q[0] = a;\n        }\n";
+            pending.push_back(t.col);
+            if (pending.size() == 8) flush("        ");
+        }
+        o << "    }\n";
+    }
+    if (!pending.empty()) flush("    ");
+    o << "}\n";
+}
+
 std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &rp) {
     std::ostringstream o;
     const int T = 1 << (m - 4);
     const size_t NT = rp.cols.size();
-    bool any_lds = false;
-    for (const RedPhase &f : rp.phases) any_lds |= !f.diag;
     o << "// generated expectation reducer: " << n << " qubits, tile bits " << m << ", " << NT
       << " terms, " << rp.phases.size() << " phases\n";
     o << "#include \"qw_dev.h\"\nusing namespace qw;\n";
@@ -536,79 +762,7 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
           << "] = make_float2(q.x, q.y); v[" << 2 * k2 + 1 << "] = make_float2(q.z, q.w); }\n";
     }
     o << "}\n";
-    o << "__device__ __forceinline__ void tile(float2 (&v)[16], uint32_t tid, uint32_t lane, uint64_t base, "
-         "char *lb, double *red) {\n";
-    o << "    const uint32_t wave = tid >> 6;\n    (void)lb; (void)base;\n";
-    const uint32_t io_tl_regs[4] = {0, 7, 8, 9};
-    o << "    const uint32_t tlio = thread_local_index(tid, " << io_tl_regs[0] << "u, " << io_tl_regs[1] << "u, "
-      << io_tl_regs[2] << "u, " << io_tl_regs[3] << "u);\n";
-    if (any_lds) {
-        o << "    {\n        const uint32_t s8 = swz(tlio) << 3;\n";
-        for (int k = 0; k < 16; ++k) {
-            uint32_t l = 0;
-            for (int s = 0; s < 4; ++s)
-                if ((k >> s) & 1) l |= 1u << io_reg[s];
-            o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (swz_host(l) << 3) << "u)) = v[" << k << "];\n";
-        }
-        o << "    }\n    lds_barrier();\n";
-    }
-    // Per-thread FP32 term values are shifted into q[0..7] across phases and
-    // summed over the wave 8 at a time (each term's wave sum uses the same
-    // butterfly whatever its position, so the packing does not change it).
-    std::vector<uint32_t> pending;
-    auto flush = [&](const char *ind) {
-        const size_t nb = pending.size();
-        o << ind << "{\n" << ind << "    const double h = wave_reduce8(q, lane);\n";
-        o << ind << "    if (lane < 8u) {\n" << ind << "        const uint32_t pos = 4u * (lane & 1u) + "
-          << "2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);\n";
-        for (size_t j = 0; j < nb; ++j)
-            o << ind << "        if (pos == " << nb - 1 - j << "u) red[wave * NT + " << pending[j] << "] = h;\n";
-        o << ind << "    }\n" << ind << "    #pragma unroll\n" << ind << "    for (int i = 0; i < 8; ++i) q[i] = 0.f;\n"
-          << ind << "}\n";
-        pending.clear();
-    };
-    o << "    float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
-    for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
-        const RedPhase &f = rp.phases[pi];
-        o << "    {   // phase " << pi << (f.diag ? " (diagonal terms, I/O layout)" : "") << "\n";
-        // (an opaque copy of tid keeps the index arithmetic inside the tile loop)
-        o << "        uint32_t tidp = tid; __asm__ volatile(\"\" : \"+v\"(tidp));\n";
-        o << "        const uint32_t tl = thread_local_index(tidp, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
-          << "u, " << (int)f.reg[2] << "u, " << (int)f.reg[3] << "u); (void)tl;\n";
-        if (!f.diag) {
-            o << "        const uint32_t t8 = swz(tl) << 3;\n";
-            for (int k = 0; k < 16; ++k) {
-                uint32_t l = 0;
-                for (int s = 0; s < 4; ++s)
-                    if ((k >> s) & 1) l |= 1u << f.reg[s];
-                o << "        v[" << k << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ " << (swz_host(l) << 3)
-                  << "u));\n";
-            }
-        } else {
-            o << "        float pr[16];\n        #pragma unroll\n        for (int k = 0; k < 16; ++k) pr[k] = "
-                 "fmaf(v[k].x, v[k].x, v[k].y * v[k].y);\n";
-        }
-        for (uint32_t j = f.t_begin; j < f.t_end; ++j) {
-            const TermDev &t = rp.terms[j];
-            o << "        {\n";
-            if (f.diag)
-                o << "            float a = diag_sum(pr, " << t.smask << "u);\n";
-            else
-                o << "            float a = pair_sum<" << (int)t.xr << ", " << (t.odd ? "true" : "false")
-                  << ">(v, " << t.smask << "u);\n            a *= 2.0f;\n";
-            o << "            const uint32_t par = (" << (int)t.neg << "u";
-            if (t.zt) o << " ^ (uint32_t)__popc(tl & " << t.zt << "u)";
-            if (t.zg) o << " ^ (uint32_t)__popcll(base & " << hex(t.zg) << ")";
-            o << ") & 1u;\n            if (par) a = -a;\n";
-            o << "            #pragma unroll\n            for (int i = 7; i > 0; --i) q[i] = q[i - 1];\n"
-                 "            q[0] = a;\n        }\n";
-            pending.push_back(t.col);
-            if (pending.size() == 8) flush("        ");
-        }
-        o << "    }\n";
-    }
-    if (!pending.empty()) flush("    ");
-    o << "}\n";
+    emit_reduce_tile(o, rp, nullptr, "tile");
     o << "__device__ const uint32_t kCols[NT] = {";
     for (size_t c = 0; c < NT; ++c) o << (c ? ", " : "") << rp.cols[c] << "u";
     o << "};\n";
@@ -834,7 +988,7 @@ bool jit_available(int device, const JitReq &r) {
     }
     const std::string dir = cache_dir();
     if (dir.empty()) return false;
-    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16)
+    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi)
                                    : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
     struct stat sb;
     return ::stat(cache_path(dir, src).c_str(), &sb) == 0;
@@ -860,7 +1014,7 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
     const char *dump = std::getenv("QW_JIT_DUMP");  // debugging: write sources to this folder
     for (size_t q = 0; q < need.size(); ++q) {
         const JitReq &r = ks[need[q]];
-        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16)
+        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi)
                          : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
         if (dump && *dump) {
             std::ofstream f(cache_path(dump, srcs[q]) + ".hip");
@@ -884,7 +1038,7 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
             if (errs[q].empty() && r.pass && r.use_lds && code_scratch_bytes(codes[q], "qw_pass") > 0) {
                 for (int pf : {8, 0}) {
                     std::vector<char> c2;
-                    const std::string e2 = compile_one(jit_pass_source(r.n, r.m, *r.pass, true, pf), &c2);
+                    const std::string e2 = compile_one(jit_pass_source(r.n, r.m, *r.pass, true, pf, r.epi), &c2);
                     if (!e2.empty()) break;
                     codes[q].swap(c2);
                     if (code_scratch_bytes(codes[q], "qw_pass") == 0) break;

@@ -27,7 +27,11 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds);
 // Full HIP source of the generated kernel for a key's pass; `prefetch`
 // (0..16, even) is the number of registers of the next tile the persistent
 // form loads while working on the current one.
-std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch = 16);
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch = 16,
+                            const RedPlan *epi = nullptr);
+
+// Key suffix of a pass kernel with a fused expectation epilogue.
+std::string jit_epilogue_key(int n, int m, const HostPass &p, const RedPlan &epi);
 
 struct JitKernel {
     hipFunction_t fn = nullptr;
@@ -52,6 +56,7 @@ struct JitReq {
     const HostPass *pass = nullptr;
     const TermGroup *group = nullptr;
     const RedPlan *rplan = nullptr;
+    const RedPlan *epi = nullptr;  // pass kernels: fused expectation epilogue (persistent form)
     int n = 0, m = 0;
     bool use_lds = false;  // pass kernels: persistent LDS form
 };

@@ -1130,25 +1130,13 @@ std::string plan_json(const Plan &p) {
     return o.str();
 }
 
-std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_terms) {
+// Greedy grouping of terms taken in `order`: each group takes every term
+// (in order) whose X/Y support still fits m local bits with the group's.
+std::vector<TermGroup> group_in_order(int n, int m, const uint64_t *x, const std::vector<uint32_t> &order) {
     std::vector<TermGroup> groups;
     const uint64_t all = (1ull << n) - 1;
-    if (n <= m) {
-        for (size_t i = 0; i < n_terms; i += kMaxGroupTerms) {
-            TermGroup g{all, {}};
-            for (size_t k = i; k < std::min(n_terms, i + (size_t)kMaxGroupTerms); ++k)
-                g.terms.push_back((uint32_t)k);
-            groups.push_back(g);
-        }
-        return groups;
-    }
     const uint64_t low = (1ull << std::min(n, 4)) - 1;
-    std::vector<uint32_t> rem(n_terms);
-    for (size_t i = 0; i < n_terms; ++i) rem[i] = (uint32_t)i;
-    // hardest terms (most high X/Y bits) first
-    std::stable_sort(rem.begin(), rem.end(), [&](uint32_t a, uint32_t b) {
-        return popc64(x[a] & ~low) > popc64(x[b] & ~low);
-    });
+    std::vector<uint32_t> rem = order;
     while (!rem.empty()) {
         uint64_t L = low;
         std::vector<uint32_t> take, left;
@@ -1164,6 +1152,43 @@ std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_ter
         std::sort(take.begin(), take.end());
         groups.push_back({L & all, take});
         rem.swap(left);
+    }
+    return groups;
+}
+
+std::vector<TermGroup> group_terms(int n, int m, const uint64_t *x, size_t n_terms) {
+    std::vector<TermGroup> groups;
+    const uint64_t all = (1ull << n) - 1;
+    if (n <= m) {
+        for (size_t i = 0; i < n_terms; i += kMaxGroupTerms) {
+            TermGroup g{all, {}};
+            for (size_t k = i; k < std::min(n_terms, i + (size_t)kMaxGroupTerms); ++k)
+                g.terms.push_back((uint32_t)k);
+            groups.push_back(g);
+        }
+        return groups;
+    }
+    const uint64_t low = (1ull << std::min(n, 4)) - 1;
+    std::vector<uint32_t> order(n_terms);
+    for (size_t i = 0; i < n_terms; ++i) order[i] = (uint32_t)i;
+    // hardest terms (most high X/Y bits) first
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return popc64(x[a] & ~low) > popc64(x[b] & ~low);
+    });
+    groups = group_in_order(n, m, x, order);
+    // Every group is one sweep over the states: retry with seeded shuffles
+    // of the order and keep the first grouping with fewer groups.
+    uint32_t st = 0x2545F491u;
+    for (int trial = 0; trial < 256 && groups.size() > 1; ++trial) {
+        std::vector<uint32_t> o = order;
+        for (size_t i = o.size(); i > 1; --i) {
+            st ^= st << 13;
+            st ^= st >> 17;
+            st ^= st << 5;
+            std::swap(o[i - 1], o[st % i]);
+        }
+        std::vector<TermGroup> g2 = group_in_order(n, m, x, o);
+        if (g2.size() < groups.size()) groups.swap(g2);
     }
     return groups;
 }
