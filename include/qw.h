@@ -240,7 +240,9 @@ int qw_snapshot_info(const qw_snap *snap, qw_artifact *out);
  * source_kind, target_kind, source_backend, target_backend) as
  * qw_last_error(); the caller then falls back to the direct path.
  * Destination slots must be distinct and not frozen. If `epilogue` is
- * non-NULL its expectations are written for every task. */
+ * non-NULL its expectations are written for every task; part of its terms
+ * may be reduced inside the batch's last pass (QW_OPT_FUSED_EPILOGUE), the
+ * rest by reducer sweeps over the destination states. */
 int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src,
                         const qw_task *tasks, uint32_t n_tasks, qw_state *dst,
                         const qw_reduce *epilogue);
