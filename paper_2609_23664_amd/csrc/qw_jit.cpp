@@ -145,26 +145,30 @@ std::string mc(size_t j, int n) {  // n complex entries of record j
     return s.str();
 }
 
-// Ops per basic block of a generated body. A long pass would otherwise be
-// one basic block of tens of thousands of instructions, whose instruction
-// selection and scheduling time grows faster than linearly; the blocks are
-// separated by a branch on an opaque always-true scalar (one SALU move and a
-// uniform branch at run time).
-constexpr int kOpsPerBlock = 8;
+// Basic blocks of a generated body. A very long pass would be one basic
+// block of tens of thousands of instructions, whose instruction selection
+// and scheduling time grows faster than linearly; such passes are cut into
+// blocks of kOpsPerBlock ops separated by a branch on an opaque always-true
+// scalar. The cut costs register copies where the block's values merge with
+// the untaken path's (about 5 % of a pass's VALU at 8-op blocks), so passes
+// of up to kSplitAbove ops stay one block (at most a few seconds to compile).
+constexpr int kOpsPerBlock = 32;
+constexpr size_t kSplitAbove = 320;
 const char *kBlockOpen = "    { uint32_t qw_g; __asm__ volatile(\"s_mov_b32 %0, 1\" : \"=s\"(qw_g)); if (qw_g) {\n";
 const char *kBlockClose = "    } }\n";
 
-// Straight-line code of ops [b, e) of a pass in phase ph.
-std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t ph) {
+// Straight-line code of ops [b, e) of a pass in phase ph (`split`: cut into
+// opaque blocks).
+std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t ph, bool split) {
     std::ostringstream g;
     int in_block = 0;
     for (size_t j = b; j < e;) {
         const DevOp &o = ops[j];
-        if (in_block == kOpsPerBlock) {
+        if (split && in_block == kOpsPerBlock) {
             g << kBlockClose;
             in_block = 0;
         }
-        if (in_block == 0) g << kBlockOpen;
+        if (split && in_block == 0) g << kBlockOpen;
         ++in_block;
         const bool lane = o.la == LOC_LANE;
         switch (o.type) {
@@ -243,7 +247,7 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
             break;
         }
     }
-    if (in_block) g << kBlockClose;
+    if (split && in_block) g << kBlockClose;
     return g.str();
 }
 
@@ -404,7 +408,7 @@ std::string emit_body(int m, const HostPass &p) {
         }
         g << "    // phase " << k << ": registers " << (int)ph[k].reg[0] << "," << (int)ph[k].reg[1] << ","
           << (int)ph[k].reg[2] << "," << (int)ph[k].reg[3] << "\n";
-        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k);
+        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k, p.dev_ops.size() > kSplitAbove);
     }
     g << "}\n";
     (void)m;
