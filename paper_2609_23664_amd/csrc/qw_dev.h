@@ -431,6 +431,18 @@ __device__ __forceinline__ float2 dset_fold(float2 ft, bool bit, float2 d0, floa
     return cmul(bit ? d1 : d0, ft);
 }
 
+// dset_fold with the member's parity given as a mask (all ones: d1, zero:
+// d0); the entry is picked by bit operations, which select exactly the same
+// bits (the opaque copy of the mask keeps the compiler from turning them
+// back into two-operand selects, which need the entries moved to VGPRs).
+__device__ __forceinline__ float2 dset_fold_m(float2 ft, uint32_t m, float2 d0, float2 d1) {
+    __asm__ volatile("" : "+v"(m));
+    const uint32_t x0 = __float_as_uint(d0.x), y0 = __float_as_uint(d0.y);
+    const uint32_t dx = x0 ^ __float_as_uint(d1.x), dy = y0 ^ __float_as_uint(d1.y);
+    const float2 d = make_float2(__uint_as_float(x0 ^ (m & dx)), __uint_as_float(y0 ^ (m & dy)));
+    return cmul(d, ft);
+}
+
 // Parity of the thread and global part of a parity factor's mask.
 __device__ __forceinline__ bool pdiag_tg(uint32_t tl, uint64_t base, uint32_t tmask, uint32_t gmask) {
     return ((__popc(tl & tmask) ^ __popcll(base & (uint64_t)gmask)) & 1u) != 0u;
@@ -465,6 +477,30 @@ __device__ __forceinline__ void dset_apply(float2 (&v)[16], const DevOp *tab, bo
             w = has_ft ? cmul(t, ft) : t;
         } else {
             w = ft;
+        }
+        v[k] = cmul(w, v[k]);
+    }
+}
+
+// Apply a diagonal set together with its first mixed member (register slots
+// rmask, thread/global parity pt, entries d0, d1): the member's two values
+// are folded into two per-thread factors f0 = cmul(pt ? d1 : d0, ft) and
+// f1 = cmul(pt ? d0 : d1, ft), and register k gets
+// cmul(cmul(T[k], f[parity(k & rmask)]), v[k]) (without a table, the chosen
+// factor alone). One complex product per register instead of two.
+__device__ __forceinline__ void dset_apply_m(float2 (&v)[16], const DevOp *tab, bool has_tab,
+                                             float2 ft, bool pt, float2 d0, float2 d1,
+                                             uint32_t rmask) {
+    const float2 f0 = cmul(pt ? d1 : d0, ft), f1 = cmul(pt ? d0 : d1, ft);
+    #pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const float2 f = (__popc((uint32_t)k & rmask) & 1u) ? f1 : f0;
+        float2 w;
+        if (has_tab) {
+            const float2 t = make_float2(opm(tab, k >> 2, 2 * (k & 3)), opm(tab, k >> 2, 2 * (k & 3) + 1));
+            w = cmul(t, f);
+        } else {
+            w = f;
         }
         v[k] = cmul(w, v[k]);
     }

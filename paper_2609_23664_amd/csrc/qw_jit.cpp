@@ -124,12 +124,43 @@ std::string bitval(uint8_t loc, uint8_t bit, size_t ph) {
 }
 
 // Parity of the thread/global part of a parity member in phase ph.
+// Parity of the thread and global part of a parity factor (the boolean of
+// pdiag_tg). A thread mask of one bit, or of two adjacent bits (the parities
+// a CNOT ladder leaves), is read as one bit of tl or of tl ^ (tl >> 1).
 std::string pbit(const DevOp &mm, size_t ph) {
     std::ostringstream s;
     s << "((0u";
-    if (mm.tmask) s << " ^ (uint32_t)__popc(tl" << ph << " & " << mm.tmask << "u)";
+    const uint32_t t = mm.tmask;
+    const int lo = t ? __builtin_ctz(t) : 0;
+    if (t && (t & (t - 1)) == 0)
+        s << " ^ (tl" << ph << " >> " << lo << ")";
+    else if (t && t == (3u << lo))
+        s << " ^ ((tl" << ph << " ^ (tl" << ph << " >> 1)) >> " << lo << ")";
+    else if (t)
+        s << " ^ (uint32_t)__popc(tl" << ph << " & " << t << "u)";
     if (mm.gmask) s << " ^ (uint32_t)__popcll(base & " << hex(mm.gmask) << ")";
     s << ") & 1u) != 0u";
+    return s.str();
+}
+
+// The same parity as an all-ones / zero mask (for dset_fold_m): one signed
+// bit-field extract for the one- and two-adjacent-bit thread masks.
+std::string pmask(const DevOp &mm, size_t ph) {
+    std::ostringstream s;
+    const uint32_t t = mm.tmask;
+    const int lo = t ? __builtin_ctz(t) : 0;
+    std::string src;
+    if (t && (t & (t - 1)) == 0)
+        src = "tl" + std::to_string(ph);
+    else if (t && t == (3u << lo))
+        src = "(tl" + std::to_string(ph) + " ^ (tl" + std::to_string(ph) + " >> 1))";
+    s << "(0u";
+    if (!src.empty())
+        s << " ^ (uint32_t)((int32_t)(" << src << " << " << 31 - lo << ") >> 31)";
+    else if (t)
+        s << " ^ (0u - ((uint32_t)__popc(tl" << ph << " & " << t << "u) & 1u))";
+    if (mm.gmask) s << " ^ (0u - ((uint32_t)__popcll(base & " << hex(mm.gmask) << ") & 1u))";
+    s << ")";
     return s.str();
 }
 
@@ -226,14 +257,23 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
             g << "    {\n        float2 ft = make_float2(1.0f, 0.0f); (void)ft;\n";
             for (size_t q = 0; q < o.b; ++q) {
                 const DevOp &mm = ops[m0 + q];
-                g << "        ft = dset_fold(ft, " << pbit(mm, ph) << ", " << mc(m0 + q, 2) << ");\n";
+                g << "        ft = dset_fold_m(ft, " << pmask(mm, ph) << ", " << mc(m0 + q, 2) << ");\n";
             }
-            if (o.sb)
+            // with a table or thread members, the first mixed member is
+            // merged into the application (the interpreted kernels do the same)
+            const size_t merged = (o.a && (o.sb || o.b)) ? 1 : 0;
+            if (merged) {
+                const DevOp &mm = ops[m0 + o.b];
+                g << "        dset_apply_m(v, " << (o.sb ? "ops + " + std::to_string(j + 1) : std::string("ops"))
+                  << ", " << (o.sb ? "true" : "false") << ", ft, " << pbit(mm, ph) << ", "
+                  << mc(m0 + o.b, 2) << ", " << (int)mm.rmask << "u);\n";
+            } else if (o.sb) {
                 g << "        dset_apply(v, ops + " << j + 1 << ", true, ft, " << (o.b ? "true" : "false")
                   << ");\n";
-            else if (o.b)
+            } else if (o.b) {
                 g << "        dset_apply(v, ops, false, ft, true);\n";
-            for (size_t q = 0; q < o.a; ++q) {
+            }
+            for (size_t q = merged; q < o.a; ++q) {
                 const DevOp &mm = ops[m0 + o.b + q];
                 g << "        pdiag_mixed_c<" << (int)mm.rmask << ">(v, " << pbit(mm, ph) << ", "
                   << mc(m0 + o.b + q, 2) << ");\n";

@@ -367,11 +367,20 @@ __device__ __forceinline__ void run_ops(float2 (&v)[16], const DevOp *ops, uint3
                 ft = dset_fold(ft, pdiag_tg(tl, base, mm.tmask, mm.gmask), opc(ops, m0 + j, 0),
                                opc(ops, m0 + j, 1));
             }
-            if (op.sb)
+            // with a table or thread members, the first mixed member is
+            // merged into the application
+            const uint32_t merged = (op.a && (op.sb || op.b)) ? 1u : 0u;
+            if (merged) {
+                const DevOp mm = ld_words(ops + m0 + op.b);
+                dset_apply_m(v, op.sb ? ops + o + 1 : ops, op.sb != 0, ft,
+                             pdiag_tg(tl, base, mm.tmask, mm.gmask), opc(ops, m0 + op.b, 0),
+                             opc(ops, m0 + op.b, 1), mm.rmask);
+            } else if (op.sb) {
                 dset_apply(v, ops + o + 1, true, ft, op.b != 0);
-            else if (op.b)
+            } else if (op.b) {
                 dset_apply(v, ops, false, ft, true);
-            for (uint32_t j = 0; j < op.a; ++j) {
+            }
+            for (uint32_t j = merged; j < op.a; ++j) {
                 const DevOp mm = ld_words(ops + m0 + op.b + j);
                 pdiag_mixed(v, pdiag_tg(tl, base, mm.tmask, mm.gmask), opc(ops, m0 + op.b + j, 0),
                             opc(ops, m0 + op.b + j, 1), mm.rmask);
