@@ -49,7 +49,6 @@ std::string hex(uint64_t v) {
     return b;
 }
 
-uint32_t swz_host(uint32_t l) { return l ^ (((l >> 5) ^ (l >> 10)) & 31u); }
 
 // Lane part (amplitude units) and wave bit positions of an I/O layout.
 void emit_io_helpers(Gen &g, const char *name, const IoRec &r, int m) {
@@ -342,9 +341,9 @@ int gf2_rank(std::vector<uint32_t> v) {
     return r;
 }
 
-std::vector<int> lane_list(int m, const DevPhase &f) {
+std::vector<int> lane_list(int m, const uint8_t *reg) {
     uint32_t R = 0;
-    for (int s = 0; s < 4; ++s) R |= 1u << f.reg[s];
+    for (int s = 0; s < 4; ++s) R |= 1u << reg[s];
     std::vector<int> lanes;
     for (int b = 0; b < m && lanes.size() < 6; ++b)
         if (!((R >> b) & 1u)) lanes.push_back(b);
@@ -359,13 +358,16 @@ ExSwz fixed_swizzle() {
     return d;
 }
 
-ExSwz choose_swizzle(int m, const DevPhase &a, const DevPhase &b) {
-    const std::vector<int> la = lane_list(m, a), lb = lane_list(m, b);
+// A map for which every layout in `regs` (register slots of each layout
+// that writes or reads the LDS copy) spreads its accesses over the banks.
+ExSwz choose_swizzle_for(int m, const std::vector<const uint8_t *> &regs) {
+    std::vector<std::vector<int>> lanes;
+    for (const uint8_t *r : regs) lanes.push_back(lane_list(m, r));
     auto good = [&](const ExSwz &x) {
-        for (const std::vector<int> *ln : {&la, &lb}) {
+        for (const std::vector<int> &ln : lanes) {
             std::vector<uint32_t> v5, v4;
             for (size_t j = 0; j < 5; ++j) {
-                const uint32_t bank = x.apply(1u << (*ln)[j]) & 31u;
+                const uint32_t bank = x.apply(1u << ln[j]) & 31u;
                 v5.push_back(bank);
                 if (j < 4) v4.push_back(bank & 15u);
             }
@@ -389,6 +391,27 @@ ExSwz choose_swizzle(int m, const DevPhase &a, const DevPhase &b) {
             if (good(x)) return x;
         }
     return d;
+}
+
+ExSwz choose_swizzle(int m, const DevPhase &a, const DevPhase &b) {
+    return choose_swizzle_for(m, {a.reg, b.reg});
+}
+
+// Address expression (bytes) of thread-local index t under map x.
+std::string swz_addr(const ExSwz &x, const std::string &t) {
+    std::ostringstream e;
+    e << "((" << t << " ^ (0u";
+    for (const auto &tm : x.terms) e << " ^ ((" << t << " >> " << tm.first << ") & " << tm.second << "u)";
+    e << ")) << 3)";
+    return e.str();
+}
+
+// Local offset of register k of a layout.
+uint32_t reg_off(const uint8_t *reg, int k) {
+    uint32_t l = 0;
+    for (int s2 = 0; s2 < 4; ++s2)
+        if ((k >> s2) & 1) l |= 1u << reg[s2];
+    return l;
 }
 
 std::string emit_body(int m, const HostPass &p) {
@@ -425,14 +448,7 @@ std::string emit_body(int m, const HostPass &p) {
             // full one: the previous tile's reads may still be in flight)
             const bool local = k > 1 && wave_bits(m, ph[k - 1]) == wave_bits(m, ph[k]);
             const ExSwz x = choose_swizzle(m, ph[k - 1], ph[k]);
-            auto thread_addr = [&](const std::string &t) {
-                std::ostringstream e;
-                e << "((" << t << " ^ (0u";
-                for (const auto &tm : x.terms)
-                    e << " ^ ((" << t << " >> " << tm.first << ") & " << tm.second << "u)";
-                e << ")) << 3)";
-                return e.str();
-            };
+            auto thread_addr = [&](const std::string &t) { return swz_addr(x, t); };
             g << "    {   // exchange " << k - 1 << " -> " << k << (local ? " (within waves)" : "") << "\n";
             g << "        const uint32_t s8 = " << thread_addr("tl" + std::to_string(k - 1)) << ";\n";
             g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
@@ -507,7 +523,7 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
     return k;
 }
 
-static void emit_reduce_tile(std::ostringstream &o, const RedPlan &rp, const DevPhase *stage,
+static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, const DevPhase *stage,
                              const char *name);
 
 std::string jit_epilogue_key(int n, int m, const HostPass &p, const RedPlan &epi) {
@@ -543,7 +559,7 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
         // store from the last phase's registers (staged through LDS)
         std::ostringstream e;
         e << "constexpr int ENT = " << epi->cols.size() << ";\n#define NT ENT\n";
-        emit_reduce_tile(e, *epi, &p.dev_phases.back(), "epi_tile");
+        emit_reduce_tile(e, m, *epi, &p.dev_phases.back(), "epi_tile");
         e << "#undef NT\n__device__ const uint32_t kECols[ENT] = {";
         for (size_t c = 0; c < epi->cols.size(); ++c) e << (c ? ", " : "") << epi->cols[c] << "u";
         e << "};\n";
@@ -683,34 +699,37 @@ std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp) 
 // and the diagonal phase uses it directly; with `stage`, v holds the tile in
 // that phase layout (the last phase of a pass): the tile is staged in LDS
 // first and every phase reads it from there.
-static void emit_reduce_tile(std::ostringstream &o, const RedPlan &rp, const DevPhase *stage,
+static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, const DevPhase *stage,
                              const char *name) {
-    const int io_reg[4] = {0, 7, 8, 9};
+    static const uint8_t io_reg[4] = {0, 7, 8, 9};
     bool any_lds = stage != nullptr;
     for (const RedPhase &f : rp.phases) any_lds |= !f.diag;
+    // one LDS address map for the writing layout and every reading phase
+    std::vector<const uint8_t *> lay{stage ? stage->reg : io_reg};
+    for (const RedPhase &f : rp.phases)
+        if (!f.diag || stage) lay.push_back(f.reg);
+    const ExSwz x = choose_swizzle_for(m, lay);
     o << "__device__ __forceinline__ void " << name << "(float2 (&v)[16], uint32_t tid, uint32_t lane, "
          "uint64_t base, char *lb, double *red) {\n";
     o << "    const uint32_t wave = tid >> 6;\n    (void)lb; (void)base;\n";
     if (stage) {
         o << "    {\n        uint32_t tids = tid; __asm__ volatile(\"\" : \"+v\"(tids));\n"
-          << "        const uint32_t s8 = swz(thread_local_index(tids, " << (int)stage->reg[0] << "u, "
-          << (int)stage->reg[1] << "u, " << (int)stage->reg[2] << "u, " << (int)stage->reg[3] << "u)) << 3;\n"
+          << "        const uint32_t tls = thread_local_index(tids, " << (int)stage->reg[0] << "u, "
+          << (int)stage->reg[1] << "u, " << (int)stage->reg[2] << "u, " << (int)stage->reg[3] << "u);\n"
+          << "        const uint32_t s8 = " << swz_addr(x, "tls") << ";\n"
           << "        lds_barrier();\n";
         for (int k = 0; k < 16; ++k)
-            o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << stage->lds_off[k] << "u)) = v[" << k << "];\n";
+            o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(reg_off(stage->reg, k)) << 3)
+              << "u)) = v[" << k << "];\n";
         o << "    }\n    lds_barrier();\n";
     } else {
-        o << "    const uint32_t tlio = thread_local_index(tid, " << io_reg[0] << "u, " << io_reg[1] << "u, "
-          << io_reg[2] << "u, " << io_reg[3] << "u);\n";
+        o << "    const uint32_t tlio = thread_local_index(tid, " << (int)io_reg[0] << "u, " << (int)io_reg[1] << "u, "
+          << (int)io_reg[2] << "u, " << (int)io_reg[3] << "u);\n";
         if (any_lds) {
-            o << "    {\n        const uint32_t s8 = swz(tlio) << 3;\n";
-            for (int k = 0; k < 16; ++k) {
-                uint32_t l = 0;
-                for (int s2 = 0; s2 < 4; ++s2)
-                    if ((k >> s2) & 1) l |= 1u << io_reg[s2];
-                o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (swz_host(l) << 3) << "u)) = v[" << k
-                  << "];\n";
-            }
+            o << "    {\n        const uint32_t s8 = " << swz_addr(x, "tlio") << ";\n";
+            for (int k = 0; k < 16; ++k)
+                o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(reg_off(io_reg, k)) << 3)
+                  << "u)) = v[" << k << "];\n";
             o << "    }\n    lds_barrier();\n";
         }
     }
@@ -739,14 +758,10 @@ static void emit_reduce_tile(std::ostringstream &o, const RedPlan &rp, const Dev
         o << "        const uint32_t tl = thread_local_index(tidp, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
           << "u, " << (int)f.reg[2] << "u, " << (int)f.reg[3] << "u); (void)tl;\n";
         if (from_lds) {
-            o << "        const uint32_t t8 = swz(tl) << 3;\n";
-            for (int k = 0; k < 16; ++k) {
-                uint32_t l = 0;
-                for (int s2 = 0; s2 < 4; ++s2)
-                    if ((k >> s2) & 1) l |= 1u << f.reg[s2];
-                o << "        v[" << k << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ " << (swz_host(l) << 3)
-                  << "u));\n";
-            }
+            o << "        const uint32_t t8 = " << swz_addr(x, "tl") << ";\n";
+            for (int k = 0; k < 16; ++k)
+                o << "        v[" << k << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ "
+                  << (x.apply(reg_off(f.reg, k)) << 3) << "u));\n";
         }
         if (f.diag)
             o << "        float pr[16];\n        #pragma unroll\n        for (int k = 0; k < 16; ++k) pr[k] = "
@@ -806,7 +821,7 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
           << "] = make_float2(q.x, q.y); v[" << 2 * k2 + 1 << "] = make_float2(q.z, q.w); }\n";
     }
     o << "}\n";
-    emit_reduce_tile(o, rp, nullptr, "tile");
+    emit_reduce_tile(o, m, rp, nullptr, "tile");
     o << "__device__ const uint32_t kCols[NT] = {";
     for (size_t c = 0; c < NT; ++c) o << (c ? ", " : "") << rp.cols[c] << "u";
     o << "};\n";
