@@ -753,7 +753,9 @@ void plan_fused_last(int n, int m, const HostPass &lp, const uint64_t *x, const 
     const size_t before = group_terms(n, m, x, n_terms).size();
     const size_t after = rest.empty() ? 0 : group_terms(n, m, rest.data(), rest.size()).size();
     if (after >= before) return;
-    fe->rplan = plan_reduce_group(n, m, g, xc.data(), zc.data());
+    // the diagonal terms are evaluated in the layout the pass ends in
+    fe->rplan = plan_reduce_group(n, m, g, xc.data(), zc.data(),
+                                  last->dev_phases.empty() ? nullptr : last->dev_phases.back().reg);
     for (TermDev &t : fe->rplan.terms)
         if (neg[fe->rplan.cols[t.col]]) t.neg ^= 1;
     fe->fused = fused;

@@ -75,8 +75,10 @@ struct RedPlan {
     std::vector<TermDev> terms;   // ordered by phase
     std::vector<uint32_t> cols;   // group-local column -> global term index
 };
+// `diag_reg` (optional): register slots of the diagonal phase (default: the
+// I/O layout, local bits 0, 7, 8, 9).
 RedPlan plan_reduce_group(int n, int m, const TermGroup &g, const uint64_t *x,
-                          const uint64_t *z);
+                          const uint64_t *z, const uint8_t *diag_reg = nullptr);
 
 // bit helpers
 inline uint64_t pdep64(uint64_t v, uint64_t mask) {

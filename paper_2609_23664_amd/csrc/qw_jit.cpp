@@ -2,6 +2,7 @@
 // and launch. See qw_jit.h.
 #include "qw_jit.h"
 
+#include <algorithm>
 #include <hip/hiprtc.h>
 
 #include <atomic>
@@ -695,24 +696,31 @@ std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp) 
 // Term evaluation of one tile for a reducer plan (shared by the generated
 // reducers and the fused expectation epilogue of pass kernels): writes each
 // term's per-wave FP64 sum into red[wave * NT + column]. Without `stage`, v
-// holds the tile in the I/O layout (register slots = local bits 0, 7, 8, 9)
-// and the diagonal phase uses it directly; with `stage`, v holds the tile in
-// that phase layout (the last phase of a pass): the tile is staged in LDS
-// first and every phase reads it from there.
+// holds the tile in the I/O layout (register slots = local bits 0, 7, 8, 9);
+// with `stage`, v holds the tile in that phase layout (the last phase of a
+// pass). A diagonal phase (the first phase, when there is one) in the layout
+// v already holds is evaluated on v; the other phases read the tile from an
+// LDS copy staged first.
 static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, const DevPhase *stage,
                              const char *name) {
     static const uint8_t io_reg[4] = {0, 7, 8, 9};
-    bool any_lds = stage != nullptr;
-    for (const RedPhase &f : rp.phases) any_lds |= !f.diag;
+    const uint8_t *held = stage ? stage->reg : io_reg;
+    std::vector<char> from_lds(rp.phases.size(), 1);
+    for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
+        const RedPhase &f = rp.phases[pi];
+        if (pi == 0 && f.diag && std::equal(f.reg, f.reg + 4, held)) from_lds[pi] = 0;
+    }
+    bool any_lds = false;
+    for (char c : from_lds) any_lds |= c != 0;
     // one LDS address map for the writing layout and every reading phase
-    std::vector<const uint8_t *> lay{stage ? stage->reg : io_reg};
-    for (const RedPhase &f : rp.phases)
-        if (!f.diag || stage) lay.push_back(f.reg);
+    std::vector<const uint8_t *> lay{held};
+    for (size_t pi = 0; pi < rp.phases.size(); ++pi)
+        if (from_lds[pi]) lay.push_back(rp.phases[pi].reg);
     const ExSwz x = choose_swizzle_for(m, lay);
     o << "__device__ __forceinline__ void " << name << "(float2 (&v)[16], uint32_t tid, uint32_t lane, "
          "uint64_t base, char *lb, double *red) {\n";
     o << "    const uint32_t wave = tid >> 6;\n    (void)lb; (void)base;\n";
-    if (stage) {
+    if (stage && any_lds) {
         o << "    {\n        uint32_t tids = tid; __asm__ volatile(\"\" : \"+v\"(tids));\n"
           << "        const uint32_t tls = thread_local_index(tids, " << (int)stage->reg[0] << "u, "
           << (int)stage->reg[1] << "u, " << (int)stage->reg[2] << "u, " << (int)stage->reg[3] << "u);\n"
@@ -722,7 +730,7 @@ static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, co
             o << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(reg_off(stage->reg, k)) << 3)
               << "u)) = v[" << k << "];\n";
         o << "    }\n    lds_barrier();\n";
-    } else {
+    } else if (!stage) {
         o << "    const uint32_t tlio = thread_local_index(tid, " << (int)io_reg[0] << "u, " << (int)io_reg[1] << "u, "
           << (int)io_reg[2] << "u, " << (int)io_reg[3] << "u);\n";
         if (any_lds) {
@@ -751,13 +759,12 @@ static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, co
     o << "    float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
     for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
         const RedPhase &f = rp.phases[pi];
-        const bool from_lds = !f.diag || stage != nullptr;
         o << "    {   // phase " << pi << (f.diag ? " (diagonal terms)" : "") << "\n";
         // (an opaque copy of tid keeps the index arithmetic inside the tile loop)
         o << "        uint32_t tidp = tid; __asm__ volatile(\"\" : \"+v\"(tidp));\n";
         o << "        const uint32_t tl = thread_local_index(tidp, " << (int)f.reg[0] << "u, " << (int)f.reg[1]
           << "u, " << (int)f.reg[2] << "u, " << (int)f.reg[3] << "u); (void)tl;\n";
-        if (from_lds) {
+        if (from_lds[pi]) {
             o << "        const uint32_t t8 = " << swz_addr(x, "tl") << ";\n";
             for (int k = 0; k < 16; ++k)
                 o << "        v[" << k << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ "

@@ -1220,7 +1220,7 @@ static std::vector<TermGroup> group_terms_search(int n, int m, const uint64_t *x
 }
 
 RedPlan plan_reduce_group(int n, int m, const TermGroup &g, const uint64_t *x,
-                          const uint64_t *z) {
+                          const uint64_t *z, const uint8_t *diag_reg) {
     (void)n;
     RedPlan rp;
     const uint64_t L = g.local_mask;
@@ -1259,10 +1259,16 @@ RedPlan plan_reduce_group(int n, int m, const TermGroup &g, const uint64_t *x,
             mem[best].push_back(i);
         }
     }
-    // diagonal terms: one phase in the I/O layout (register bits 0, 7, 8, 9)
+    // diagonal terms: one phase, first, in the I/O layout (register bits 0,
+    // 7, 8, 9) or the given one
     std::vector<char> is_diag(R.size(), 0);
     if (!diag.empty()) {
-        R.insert(R.begin(), (1u << 0) | (1u << 7) | (1u << 8) | (1u << 9));
+        uint32_t dr = (1u << 0) | (1u << 7) | (1u << 8) | (1u << 9);
+        if (diag_reg) {
+            dr = 0;
+            for (int s2 = 0; s2 < 4; ++s2) dr |= 1u << diag_reg[s2];
+        }
+        R.insert(R.begin(), dr);
         mem.insert(mem.begin(), diag);
         is_diag.insert(is_diag.begin(), 1);
     }
