@@ -27,6 +27,10 @@ def _parse():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--tile-bits", type=int, default=14,
                     help="local bits per pass tile (QW_OPT_TILE_BITS, 10..14)")
+    ap.add_argument("--tile-order", type=int, default=1, choices=[0, 1, 2],
+                    help="QW_OPT_TILE_ORDER: 0 descriptor-major items always, 1 tile-major for "
+                         "relabelling passes (default), 2 tile-major for all launches over "
+                         "distinct states")
     ap.add_argument("--cpu-tasks", type=int, default=8,
                     help="tasks in the oracle's bounded CPU sample")
     ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy"],
@@ -111,6 +115,7 @@ def main():
     prov = fingerprint(n, w.prefix)
     ctx = B.Ctx(0)
     ctx.set_option(B.QW_OPT_TILE_BITS, args.tile_bits)
+    ctx.set_option(B.QW_OPT_TILE_ORDER, args.tile_order)
 
     # gate lists marshalled once (host preparation, outside the timed steps;
     # the library's plan cache makes later steps skip planning, which the

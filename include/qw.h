@@ -172,7 +172,20 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         reduced inside that pass (generated kernels),
  *                         when that saves a reducer sweep over the states;
  *                         the results agree with separate reduction up to
- *                         FP32 rounding of the per-thread partial sums. [1] */
+ *                         FP32 rounding of the per-thread partial sums. [1]
+ *   QW_OPT_TILE_ORDER     order in which the persistent generated kernels
+ *                         (multi-phase passes, reducers) take the
+ *                         (task, tile) items of a launch: the tasks of one
+ *                         tile together (descriptor-major) or consecutive
+ *                         tiles of one task (tile-major). 0: always
+ *                         descriptor-major; 1: tile-major for passes with
+ *                         output relabelling, descriptor-major otherwise;
+ *                         2: tile-major for every pass and reducer launch.
+ *                         Launches whose tasks all read one source state (a
+ *                         shared snapshot) stay descriptor-major, so the
+ *                         tasks of a tile share its reads in L2. Results do
+ *                         not depend on it; on config-2-like batches mode 1
+ *                         measured fastest. [1] */
 #define QW_OPT_TILE_BITS 1
 #define QW_OPT_PROFILE 2
 #define QW_OPT_XCD_REMAP 4
@@ -180,6 +193,7 @@ int qw_ctx_sync(qw_ctx *ctx);
 #define QW_OPT_RELABEL 6
 #define QW_OPT_SECOND_BUFFER_CAP 7
 #define QW_OPT_FUSED_EPILOGUE 8
+#define QW_OPT_TILE_ORDER 9
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.

@@ -67,6 +67,7 @@ struct qw_ctx {
     DevBuf scratch;  // partial sums, sampler buffers
     DevBuf pingpong; // second state buffers of tasks with relabelling passes
     bool relabel = true;
+    int tile_order = 1;          // QW_OPT_TILE_ORDER
     bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
     void *staging = nullptr;
@@ -664,8 +665,19 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         if (use_jit) {
             for (const Group &g : groups[k]) {
                 ProfScope ps(ctx, 0, (double)g.count * 2.0 * (double)state_bytes);
+                // item order (QW_OPT_TILE_ORDER); descriptor-major whenever
+                // every task of the group reads one source
+                bool tile_major = false;
+                {
+                    const PassDesc *hd = reinterpret_cast<const PassDesc *>(blob.data() + step_off[k]);
+                    bool shared_src = true;
+                    for (uint32_t i = 1; i < g.count && shared_src; ++i)
+                        shared_src = hd[g.first + i].src == hd[g.first].src;
+                    const bool relabel = (hd[g.first].flags & PD_REMAP_OUT) != 0;
+                    tile_major = !shared_src && (ctx->tile_order == 2 || (ctx->tile_order == 1 && relabel));
+                }
                 hipError_t er = g.k ? jit_launch(ctx->stream, *g.k, dd + g.first, g.count, tiles,
-                                                 ctx->xcd_remap ? 1 : 0, ctx->n_cu)
+                                                 ctx->xcd_remap ? 1 : 0, ctx->n_cu, tile_major)
                                     : launch_pass(ctx->stream, dd + g.first, g.count, n, (uint32_t)m,
                                                   ctx->xcd_remap ? 1 : 0, g.lds);
                 if (er != hipSuccess) return hip_fail(ctx, er, "pass launch");
@@ -919,7 +931,8 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
         const ReduceDesc *dd = reinterpret_cast<const ReduceDesc *>(dbase + desc_off);
         for (size_t g = 0; g < groups.size(); ++g) {
             ProfScope ps(ctx, 1, (double)ns * (double)(8ull << n));
-            hipError_t er = jit_launch_reduce(ctx->stream, *rk[g], dd + g * ns, ns, tiles, ctx->n_cu);
+            hipError_t er = jit_launch_reduce(ctx->stream, *rk[g], dd + g * ns, ns, tiles, ctx->n_cu,
+                                              ctx->tile_order == 2);
             if (er != hipSuccess) return hip_fail(ctx, er, "generated reduce launch");
         }
     } else if (small || !groups.empty()) {
@@ -1017,6 +1030,10 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         return QW_OK;
     case QW_OPT_RELABEL: ctx->relabel = value != 0; return QW_OK;
     case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
+    case QW_OPT_TILE_ORDER:
+        if (value < 0 || value > 2) return fail(ctx, QW_E_INVALID_ARG, "tile order must be 0, 1 or 2");
+        ctx->tile_order = (int)value;
+        return QW_OK;
     case QW_OPT_SECOND_BUFFER_CAP:
         if (value <= 0) return fail(ctx, QW_E_INVALID_ARG, "second buffer cap must be > 0");
         ctx->pingpong_cap = (uint64_t)value;

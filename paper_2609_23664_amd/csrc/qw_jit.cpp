@@ -568,7 +568,8 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
     }
     if (!use_lds) {
         g << "extern \"C\" __global__ __launch_bounds__(WG) void qw_pass(const PassDesc *__restrict__ "
-             "descs, uint32_t n_descs, uint32_t items, int remap) {\n"
+             "descs, uint32_t n_descs, uint32_t items, int remap, uint32_t tmaj) {\n"
+             "    (void)tmaj;\n"
              "    const uint32_t wg_item = item_of(blockIdx.x, gridDim.x, remap);\n"
              "    const uint32_t item = wg_item / PARTS;\n"
              "    if (item >= items) return;\n"
@@ -587,8 +588,13 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "}\n";
     } else {
         g << "extern \"C\" __global__ __launch_bounds__(T) void qw_pass(const PassDesc *__restrict__ "
-             "descs, uint32_t n_descs, uint32_t items, int remap) {\n"
+             "descs, uint32_t n_descs, uint32_t items, int remap, uint32_t tmaj) {\n"
              "    (void)remap;\n"
+             "    // item -> (descriptor, tile): tmaj = 0 descriptor-fastest, else\n"
+             "    // tile-fastest with 1 << (tmaj - 1) tiles per descriptor\n"
+             "    const uint32_t tg = tmaj ? tmaj - 1u : 0u;\n"
+             "    auto desc_of = [=](uint32_t it) { return tmaj ? (it >> tg) : (it % n_descs); };\n"
+             "    auto tile_of = [=](uint32_t it) { return tmaj ? (it & ((1u << tg) - 1u)) : (it / n_descs); };\n"
              "    __shared__ float2 lds[1 << M];\n"
              "    __shared__ double red[" << (epi ? "(T / 64) * ENT + 1" : "T / 64 + 1") << "];\n"
              "    (void)red;\n"
@@ -606,14 +612,14 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "    char *lb = reinterpret_cast<char *>(lds);\n"
              "    float2 nv[" << std::max(1, PF) << "];\n"
              "    {\n"
-             "        const PassDesc *d0 = descs + item % n_descs;\n"
-             "        load_pre(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + item / n_descs)) | wi, li);\n"
+             "        const PassDesc *d0 = descs + desc_of(item);\n"
+             "        load_pre(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + tile_of(item))) | wi, li);\n"
              "    }\n"
              "    while (true) {\n"
              "        float2 v[16];\n"
              "        #pragma unroll\n"
              "        for (int k = 0; k < " << PF << "; ++k) v[k] = nv[k];\n"
-             "        const uint32_t p = item % n_descs, tile = item / n_descs;\n"
+             "        const uint32_t p = desc_of(item), tile = tile_of(item);\n"
              "        const PassDesc *d = descs + p;\n"
              "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tile));\n"
              "        {\n"
@@ -625,8 +631,8 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "        const uint32_t next = item + wpx;\n"
              "        const bool has_next = next < last;\n"
              "        if (has_next) {\n"
-             "            const PassDesc *dn = descs + next % n_descs;\n"
-             "            load_pre(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + next / n_descs)) | wi, li);\n"
+             "            const PassDesc *dn = descs + desc_of(next);\n"
+             "            load_pre(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + tile_of(next))) | wi, li);\n"
              "        }\n";
         if (p.scale_in) g << kScaleIn;
         g << "        body(v, ldu(&d->ops), tid, lane, base, lb);\n";
@@ -833,9 +839,12 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
     for (size_t c = 0; c < NT; ++c) o << (c ? ", " : "") << rp.cols[c] << "u";
     o << "};\n";
     o << "extern \"C\" __global__ __launch_bounds__(T) void qw_reduce(const ReduceDesc *__restrict__ descs, "
-         "uint32_t n_descs, uint32_t items) {\n"
+         "uint32_t n_descs, uint32_t items, uint32_t tmaj) {\n"
          "    __shared__ float2 lds[1 << M];\n"
          "    __shared__ double red[W * NT];\n"
+         "    const uint32_t tg = tmaj ? tmaj - 1u : 0u;\n"
+         "    auto desc_of = [=](uint32_t it) { return tmaj ? (it >> tg) : (it % n_descs); };\n"
+         "    auto tile_of = [=](uint32_t it) { return tmaj ? (it & ((1u << tg) - 1u)) : (it / n_descs); };\n"
          "    const uint32_t w = blockIdx.x, x = w & 7u, j = w >> 3, wpx = gridDim.x >> 3;\n"
          "    const uint32_t per = (items + 7u) >> 3;\n"
          "    const uint32_t first = x * per;\n"
@@ -848,21 +857,21 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
          "    char *lb = reinterpret_cast<char *>(lds);\n"
          "    float2 nv[16];\n"
          "    {\n"
-         "        const ReduceDesc *d0 = descs + item % n_descs;\n"
-         "        load_in(nv, ldu(&d0->psi), uni(ldu(ldu(&d0->tile_base) + item / n_descs)) | wi, li);\n"
+         "        const ReduceDesc *d0 = descs + desc_of(item);\n"
+         "        load_in(nv, ldu(&d0->psi), uni(ldu(ldu(&d0->tile_base) + tile_of(item))) | wi, li);\n"
          "    }\n"
          "    while (true) {\n"
          "        float2 v[16];\n"
          "        #pragma unroll\n"
          "        for (int k = 0; k < 16; ++k) v[k] = nv[k];\n"
-         "        const uint32_t p = item % n_descs, tl_ = item / n_descs;\n"
+         "        const uint32_t p = desc_of(item), tl_ = tile_of(item);\n"
          "        const ReduceDesc *d = descs + p;\n"
          "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tl_));\n"
          "        const uint32_t next = item + wpx;\n"
          "        const bool has_next = next < last;\n"
          "        if (has_next) {\n"
-         "            const ReduceDesc *dn = descs + next % n_descs;\n"
-         "            load_in(nv, ldu(&dn->psi), uni(ldu(ldu(&dn->tile_base) + next / n_descs)) | wi, li);\n"
+         "            const ReduceDesc *dn = descs + desc_of(next);\n"
+         "            load_in(nv, ldu(&dn->psi), uni(ldu(ldu(&dn->tile_base) + tile_of(next))) | wi, li);\n"
          "        }\n"
          "        __syncthreads();  // the previous tile's LDS and partial reads are done\n"
          "        tile(v, tid, lane, base, lb, red);\n"
@@ -1193,9 +1202,17 @@ std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<con
     return "";
 }
 
+// Item-order argument of the persistent kernels: 0 for descriptor-fastest,
+// else 1 + log2(tiles) for tile-fastest (tiles is a power of two).
+static uint32_t tile_order_arg(uint32_t tiles, bool tile_major) {
+    if (!tile_major || tiles == 0 || (tiles & (tiles - 1)) != 0) return 0u;
+    return 1u + (uint32_t)__builtin_ctz(tiles);
+}
+
 hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs, uint32_t n_descs,
-                      uint32_t tiles, int remap, uint32_t cu_count) {
+                      uint32_t tiles, int remap, uint32_t cu_count, bool tile_major) {
     const uint32_t items = n_descs * tiles;
+    uint32_t tmaj = k.use_lds ? tile_order_arg(tiles, tile_major) : 0u;
     uint32_t grid;
     if (k.use_lds) {
         const uint32_t full = cu_count * (uint32_t)k.blocks_per_cu;
@@ -1207,19 +1224,20 @@ hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs,
         if (remap && (grid & 7u)) remap = 0;
     }
     uint32_t items_arg = items;
-    void *args[] = {&descs, &n_descs, &items_arg, &remap};
+    void *args[] = {&descs, &n_descs, &items_arg, &remap, &tmaj};
     return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
 }
 
 hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDesc *descs,
-                             uint32_t n_descs, uint32_t tiles, uint32_t cu_count) {
+                             uint32_t n_descs, uint32_t tiles, uint32_t cu_count, bool tile_major) {
+    uint32_t tmaj = tile_order_arg(tiles, tile_major);
     const uint32_t items = n_descs * tiles;
     const uint32_t full = cu_count * (uint32_t)k.blocks_per_cu;
     const uint32_t want = ((items + 7u) / 8u) * 8u;
     uint32_t grid = want < full ? want : (full / 8u) * 8u;
     if (grid < 8u) grid = 8u;
     uint32_t items_arg = items;
-    void *args[] = {&descs, &n_descs, &items_arg};
+    void *args[] = {&descs, &n_descs, &items_arg, &tmaj};
     return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
 }
 

@@ -63,7 +63,7 @@ struct JitReq {
 
 // Launch a generated reducer over n_descs descriptors of its term group.
 hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDesc *descs,
-                             uint32_t n_descs, uint32_t tiles, uint32_t cu_count);
+                             uint32_t n_descs, uint32_t tiles, uint32_t cu_count, bool tile_major);
 
 // Compiled kernels for the requests on `device`: loaded from memory, from
 // the disk cache, or compiled (in parallel). Returns "" or an error message.
@@ -78,8 +78,10 @@ bool jit_available(int device, const JitReq &r);
 std::string jit_precompile(const std::vector<JitReq> &reqs);
 
 // Launch a generated pass kernel over n_descs descriptors (all of its key).
+// `tile_major`: the persistent form takes consecutive tiles of one
+// descriptor (else the descriptors of one tile) as consecutive items.
 hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs, uint32_t n_descs,
-                      uint32_t tiles, int remap, uint32_t cu_count);
+                      uint32_t tiles, int remap, uint32_t cu_count, bool tile_major);
 
 // Number of generated kernels compiled (not loaded from cache) and seconds
 // spent compiling, since the process started.
