@@ -8,6 +8,8 @@ seeded input generator package ``workloads``.
 
 Contents
   * ``simulate / apply_gates``   gate-by-gate statevector (C, ``qwo.c``)
+  * ``simulate_measured``        the same with mid-circuit Z measurements and
+                                 resets (Born rule, collapse, renormalise)
   * ``expect / expect_terms``    Pauli-sum expectation, plain definition
   * ``sample / uniform``         inverse-CDF Z-basis sampling, SplitMix64 hash
   * ``brute``                    numpy dense-unitary brute force (<= 8 qubits)
@@ -87,11 +89,53 @@ def _encode(gates: Sequence[Tuple[str, Tuple[int, ...], float]]):
     return code, q0, q1, par
 
 
+def _measure(psi: np.ndarray, n: int, q: int, u: float, reset: bool) -> int:
+    """Projective Z measurement of qubit q in place (the measurement barrier
+    that Sec. III-A's segmenter cuts at; the update is the textbook
+    projective-measurement rule). With S = ||psi||^2 and S1 the probability
+    mass on bit q = 1, the outcome is 1 iff u < S1 / S; the state becomes
+    the projection onto that outcome divided by its norm. RESET then applies
+    X on q when the outcome was 1."""
+    idx = np.arange(1 << n, dtype=np.int64)
+    one = ((idx >> q) & 1).astype(bool)
+    w = psi.real ** 2 + psi.imag ** 2
+    S = float(np.sum(w))
+    S1 = float(np.sum(w[one]))
+    b = 1 if u < S1 / S else 0
+    keep = one if b else ~one
+    psi[~keep] = 0.0
+    psi /= np.sqrt(S1 if b else S - S1)
+    if reset and b:
+        psi[:] = psi[idx ^ (1 << q)]
+    return b
+
+
+def simulate_measured(n: int, gates):
+    """(psi, outcomes) of ``gates`` from |0...0>, where ``MEASURE`` and
+    ``RESET`` (qubit q, param u) measure as in ``_measure`` and every other
+    gate is applied as in ``apply_gates``."""
+    psi = zero_state(n)
+    outs = []
+    seg = []
+    for g in gates:
+        if g[0] in ("MEASURE", "RESET"):
+            apply_gates(psi, n, seg)
+            seg = []
+            outs.append(_measure(psi, n, int(g[1][0]), float(g[2]), g[0] == "RESET"))
+        else:
+            seg.append(g)
+    apply_gates(psi, n, seg)
+    return psi, outs
+
+
 def apply_gates(psi: np.ndarray, n: int, gates) -> np.ndarray:
-    """Apply ``gates`` to ``psi`` in place, one at a time, in order."""
+    """Apply ``gates`` to ``psi`` in place, one at a time, in order
+    (measurements: ``simulate_measured``)."""
     assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.size == (1 << n)
     if len(gates) == 0:
         return psi
+    if any(g[0] in ("MEASURE", "RESET") for g in gates):
+        raise ValueError("oracle: measurements go through simulate_measured")
     lib = _load()
     code, q0, q1, par = _encode(gates)
     rc = lib.qwo_apply_gates(psi.ctypes.data, n, len(gates), code.ctypes.data,
