@@ -33,11 +33,12 @@ def _parse():
                          "distinct states")
     ap.add_argument("--cpu-tasks", type=int, default=8,
                     help="tasks in the oracle's bounded CPU sample")
-    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy"],
+    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy", "qec"],
                     help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "
                          "tree, 512 leaves, 1024 shots; noisy: 22-qubit 256 trajectories, 1024 "
                          "shots; sweep: gate-pass HBM bandwidth over qubits and sizes; copy: "
-                         "5 plain 1 GiB device copies (the reference kernel for HBM counters)")
+                         "5 plain 1 GiB device copies (the reference kernel for HBM counters); "
+                         "qec: 23-qubit repetition code, 64 tasks with mid-circuit measurements")
     return ap.parse_args()
 
 
@@ -104,7 +105,7 @@ def main():
 
     if args.workload != "vqe":
         extra = {"trie": bench_trie, "noisy": bench_noisy, "sweep": bench_sweep,
-                 "copy": bench_copy}[args.workload]
+                 "copy": bench_copy, "qec": bench_qec}[args.workload]
         print(json.dumps(extra(args)), flush=True)
         return
 
@@ -338,6 +339,72 @@ def bench_noisy(args):
             "materialized_nodes": len(plan.materialized), "realized_ms": recp.realized_ms,
             "dtype": "c64", "data": "synthetic",
             "config": {"workload": w.name, "qubits": w.n, "trajectories": T, "shots": w.shots}}
+
+
+def bench_qec(args):
+    """Repetition-code memory experiment with mid-circuit measurements: 23
+    qubits (12 data, 11 ancillas), a shared prefix (encoding + one syndrome
+    round of 11 measure-and-reset gates), 64 tasks (a coherent error + one
+    more syndrome round each), 12 parity expectations per task. Reuse: the
+    prefix once, snapshot, the 64 suffixes as one batch; direct: the 64 full
+    gate lists as one batch from |0...0>. Each measurement is one FP64 sum
+    sweep, a host decision and a projector folded into the next segment."""
+    import numpy as np
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd.planner import fingerprint
+    from workloads import gen
+    w = gen.qec_repetition()
+    n, T = w.n, w.n_tasks
+    ctx = B.Ctx(0)
+    ctx.set_option(B.QW_OPT_TILE_BITS, args.tile_bits)
+    prov = fingerprint(n, w.prefix)
+    prefix = B.GateArray(w.prefix)
+    sufs = [B.GateArray(s) for s in w.suffixes]
+    full = [B.GateArray(list(w.prefix) + list(s)) for s in w.suffixes]
+    st = B.State(ctx, n, T + 1)
+    slots = list(range(1, T + 1))
+
+    def reuse_step():
+        st.reset(0, 1)
+        st.apply(0, prefix)
+        pre = B.outcomes(ctx)
+        snap = st.snapshot(0, prov, B.QW_SNAP_FREEZE)
+        e = B.run_suffix_batch(ctx, [snap] * T, sufs, st, slots, terms=w.terms)
+        snap.free()
+        return e, pre, B.outcomes(ctx)
+
+    def direct_step():
+        st.reset(1, T)
+        e = B.run_suffix_batch(ctx, None, full, st, slots, terms=w.terms)
+        return e, B.outcomes(ctx)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, r
+
+    tr, (er, pre, sufo) = timed(reuse_step)
+    td, (ed, dout) = timed(direct_step)
+    # direct outcomes per task = the prefix's then the suffix's
+    m_pre, m_suf = len(pre), len(sufo) // T
+    same_out = all(list(dout[k * (m_pre + m_suf):k * (m_pre + m_suf) + m_pre]) == list(pre) and
+                   list(dout[k * (m_pre + m_suf) + m_pre:(k + 1) * (m_pre + m_suf)]) ==
+                   list(sufo[k * m_suf:(k + 1) * m_suf]) for k in range(T))
+    st.free()
+    return {"metric": "QEC repetition tasks/s at 23q (mid-circuit measurements, reuse)",
+            "value": round(T / tr, 2), "unit": "tasks/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(tr * 1e3, 3), "higher_is_better": True,
+            "direct_tasks_per_s": round(T / td, 2), "speedup_vs_direct": round(td / tr, 3),
+            "reuse_equals_direct": bool(np.array_equal(np.asarray(er), np.asarray(ed))) and same_out,
+            "measurements_per_task": m_pre + m_suf, "dtype": "c64 (fp32 amplitudes, fp64 sums)",
+            "data": "synthetic (seeded angles and draws)",
+            "config": {"workload": w.name, "qubits": n, "tasks": T, "terms": len(w.terms)}}
 
 
 def cpu_baseline(w, k):

@@ -50,7 +50,24 @@ extern "C" {
  *   CNOT: control q0, target q1: |b> -> |b xor (b_q0 << q1)>
  *   CZ:   phase -1 when bits q0 and q1 are both 1
  *   RENORM: no qubits; the state is divided by its norm (computed in FP64)
- *           at this point of the gate list. */
+ *           at this point of the gate list.
+ *   PROJ0(f) = diag(f, 0), PROJ1(f) = diag(0, f) on q0 (f = param, real):
+ *           a projector onto q0 = 0 / 1 with a real factor (not unitary).
+ *   MEASURE (mid-circuit Z measurement of q0, the measurement barrier of
+ *           Sec. III-A's segmenter): param = u in [0, 1), the caller's
+ *           uniform draw for this measurement. With S = sum_i |psi_i|^2 and
+ *           S1 the same sum over the indices with bit q0 set (FP64 sums of
+ *           the FP32 amplitudes, fixed order), the outcome is b = 1 if
+ *           u < S1 / S (FP64), else b = 0, and the state becomes
+ *           P_b psi / sqrt(S_b) (S_0 = S - S1). The outcome is recorded
+ *           (qw_outcomes).
+ *   RESET:  a MEASURE of q0 followed by X on q0 when b = 1 (q0 ends in |0>);
+ *           param = u as for MEASURE, and the outcome is recorded.
+ * A gate list with MEASURE or RESET runs in segments: the gates up to the
+ * measurement, then an FP64 sum pass over the state, a host decision (the
+ * call synchronises the stream once per measurement), and the next segment
+ * starting with PROJ_b(1 / sqrt(S_b)) (and X for a RESET with b = 1), which
+ * fuses into that segment's first pass. */
 #define QW_GATE_X 0x01
 #define QW_GATE_Y 0x02
 #define QW_GATE_Z 0x03
@@ -66,13 +83,18 @@ extern "C" {
 #define QW_GATE_CNOT 0x41
 #define QW_GATE_CZ 0x42
 #define QW_GATE_RENORM 0x81
+#define QW_GATE_MEASURE 0x82
+#define QW_GATE_RESET 0x83
+#define QW_GATE_PROJ0 0x84
+#define QW_GATE_PROJ1 0x85
 
 typedef struct qw_gate {
     uint32_t kind;     /* QW_GATE_*                                     */
     uint32_t q0;       /* qubit (control of CNOT)                       */
     uint32_t q1;       /* second qubit (target of CNOT); else ignored   */
     uint32_t reserved; /* must be 0                                     */
-    double param;      /* angle of RX/RY/RZ/P in radians; else ignored  */
+    double param;      /* angle of RX/RY/RZ/P in radians; u of MEASURE
+                          and RESET; factor of PROJ0/PROJ1; else ignored */
 } qw_gate;             /* 24 bytes */
 
 /* ------------------------------------------------------------ artifacts */
@@ -261,6 +283,14 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src,
                         const qw_task *tasks, uint32_t n_tasks, qw_state *dst,
                         const qw_reduce *epilogue);
 
+/* qw_outcomes: the measurement outcomes (0 or 1, one byte each) of the
+ * MEASURE and RESET gates of the most recent qw_apply_prefix or
+ * qw_run_suffix_batch on this context, task by task in task order and, within
+ * a task, in gate order (a call without measurements leaves none). Writes
+ * min(count, cap) bytes to out (host memory; may be NULL when cap is 0) and
+ * the total to *count. The record stays until the next such call. */
+int qw_outcomes(const qw_ctx *ctx, uint8_t *out, uint64_t cap, uint64_t *count);
+
 /* qw_expect_pauli: for each slot s in [first, first + count):
  *   out[s - first] = sum_j coeff[j] * Re sum_i conj(psi[i ^ x_j]) *
  *                    i^{popcount(x_j & z_j)} * (-1)^{popcount(i & z_j)} psi[i]
@@ -330,7 +360,10 @@ int qw_plan_describe(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates,
 /* Cost of `gates` on n qubits in the analytic byte model of the planner
  * (Sec. IV-C): the number of tile passes the library would run and the HBM
  * bytes they move (each pass reads and writes the state once: 2 * 8 * 2^n
- * bytes). No device is needed. */
+ * bytes). No device is needed. A list with MEASURE or RESET is costed as
+ * its segments (each planned alone, the projector folded into the next
+ * segment's first pass, or one pass of its own if that segment is empty)
+ * plus one read of the state (8 * 2^n bytes, no pass) per measurement. */
 int qw_plan_cost(uint32_t n_qubits, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
                  uint64_t *n_passes, double *bytes);
 

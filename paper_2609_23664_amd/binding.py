@@ -24,7 +24,8 @@ QW_E_UNSUPPORTED = 5
 GATE_KIND = {
     "X": 0x01, "Y": 0x02, "Z": 0x03, "H": 0x04, "S": 0x05, "SDG": 0x06,
     "T": 0x07, "TDG": 0x08, "RX": 0x21, "RY": 0x22, "RZ": 0x23, "P": 0x24,
-    "CNOT": 0x41, "CZ": 0x42, "RENORM": 0x81,
+    "CNOT": 0x41, "CZ": 0x42, "RENORM": 0x81, "MEASURE": 0x82, "RESET": 0x83,
+    "PROJ0": 0x84, "PROJ1": 0x85,
 }
 
 QW_KIND_STATEVECTOR = 1
@@ -55,7 +56,7 @@ EXPORTED = (
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
     "qw_mlp_workspace_floats", "qw_mlp_forward", "qw_mlp_backward", "qw_mlp_adam",
     "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_precompile_suffix",
-    "qw_jit_stats", "qw_version",
+    "qw_jit_stats", "qw_version", "qw_outcomes",
 )
 
 
@@ -161,6 +162,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.c_char_p, u64], i32),
         "qw_jit_precompile_suffix": ([u32, ctypes.POINTER(QwGate), u64, ctypes.POINTER(u64),
                                       ctypes.POINTER(u64), u32, u32, ctypes.c_char_p, u64], i32),
+        "qw_outcomes": ([ctypes.c_void_p, ctypes.c_void_p, u64, ctypes.POINTER(u64)], i32),
         "qw_jit_stats": ([ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)],
                          i32),
         "qw_version": ([], ctypes.c_char_p),
@@ -304,6 +306,18 @@ def jit_stats() -> dict:
     c, h, s = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
     lib().qw_jit_stats(ctypes.byref(c), ctypes.byref(h), ctypes.byref(s))
     return {"compiled": c.value, "disk_hits": h.value, "compile_s": s.value}
+
+
+def outcomes(ctx) -> "np.ndarray":
+    """qw_outcomes: measurement outcomes (uint8, task order then gate order)
+    of the context's last qw_apply_prefix / qw_run_suffix_batch."""
+    import numpy as np
+    cnt = ctypes.c_uint64()
+    ctx.check(lib().qw_outcomes(ctx.h, None, 0, ctypes.byref(cnt)))
+    out = np.zeros(cnt.value, dtype=np.uint8)
+    if cnt.value:
+        ctx.check(lib().qw_outcomes(ctx.h, ctypes.c_void_p(out.ctypes.data), cnt.value, ctypes.byref(cnt)))
+    return out
 
 
 class Ctx:

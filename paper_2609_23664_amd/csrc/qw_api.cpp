@@ -66,6 +66,8 @@ struct qw_ctx {
     DevBuf plan;     // uploaded descriptors/ops
     DevBuf scratch;  // partial sums, sampler buffers
     DevBuf pingpong; // second state buffers of tasks with relabelling passes
+    DevBuf meas;     // measurement sums: slot pointers, qubits, partials, results
+    std::vector<uint8_t> outcomes;  // outcome record of the last measured call
     bool relabel = true;
     int tile_order = 1;          // QW_OPT_TILE_ORDER
     bool fused_epilogue = true;
@@ -956,6 +958,141 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     return QW_OK;
 }
 
+bool is_measure(uint32_t kind) { return kind == QW_GATE_MEASURE || kind == QW_GATE_RESET; }
+
+bool has_measure(const qw_gate *g, uint64_t n) {
+    for (uint64_t i = 0; i < n; ++i)
+        if (is_measure(g[i].kind)) return true;
+    return false;
+}
+
+// One task of a measured execution.
+struct MeasTask {
+    const qw_gate *g = nullptr;
+    uint64_t n = 0, pos = 0;     // gates; next gate to run
+    const void *src = nullptr;   // the first segment's source (a snapshot), or null
+    void *dst = nullptr;
+    std::vector<qw_gate> head;   // projector (and X) that opens the next segment
+    std::vector<uint8_t> outc;
+    bool done = false;
+};
+
+// Gate lists with MEASURE / RESET gates run in rounds. A round runs every
+// unfinished task's next segment as one batch (the gates up to its next
+// measurement, after the projector the previous measurement left; the first
+// round reads the tasks' snapshots, later rounds run in place). The tasks
+// that stopped at a measurement then get their FP64 sums S and S1 in one
+// launch; the host picks b = (u < S1 / S) and the next segment opens with
+// PROJ_b(1 / sqrt(S_b)), plus X for a RESET with b = 1. Outcomes are
+// recorded per task in gate order (qw_outcomes).
+int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
+    for (size_t k = 0; k < mt.size(); ++k)
+        for (uint64_t i = 0; i < mt[k].n; ++i) {
+            const qw_gate &q = mt[k].g[i];
+            if (!is_measure(q.kind)) continue;
+            if (q.q0 >= n || q.reserved != 0 || !(q.param >= 0.0 && q.param < 1.0)) {
+                char buf[160];
+                snprintf(buf, sizeof buf,
+                         "task %zu gate %llu: a measurement needs a qubit < n and u in [0, 1)", k,
+                         (unsigned long long)i);
+                return fail(ctx, QW_E_INVALID_ARG, buf);
+            }
+        }
+    const uint32_t T = (uint32_t)mt.size();
+    const uint32_t C = n < 14 ? n : 14;
+    const uint64_t chunks = 1ull << (n - C);
+    const size_t ptr_bytes = ((size_t)T * sizeof(void *) + 255) & ~(size_t)255;
+    const size_t q_bytes = ((size_t)T * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t part_bytes = (size_t)2 * T * chunks * sizeof(double);
+    int rc = ensure(ctx, ctx->meas, ptr_bytes + q_bytes + part_bytes + 2 * (size_t)T * sizeof(double),
+                    "measure buffer");
+    if (rc) return rc;
+    char *mb = static_cast<char *>(ctx->meas.p);
+    double *part = reinterpret_cast<double *>(mb + ptr_bytes + q_bytes);
+    double *dsum = part + 2 * (size_t)T * chunks;
+    bool first = true;
+    while (true) {
+        std::vector<Exec> ex;
+        std::vector<size_t> who;
+        std::vector<std::vector<qw_gate>> segs(mt.size());
+        for (size_t k = 0; k < mt.size(); ++k) {
+            MeasTask &t = mt[k];
+            if (t.done) continue;
+            uint64_t e = t.pos;
+            while (e < t.n && !is_measure(t.g[e].kind)) ++e;
+            segs[k] = t.head;
+            segs[k].insert(segs[k].end(), t.g + t.pos, t.g + e);
+            t.head.clear();
+            Exec x;
+            std::string err = get_plan(ctx, n, segs[k].data(), segs[k].size(), &x.planp);
+            if (!err.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + err);
+            x.src = first ? t.src : nullptr;
+            x.dst = t.dst;
+            ex.push_back(x);
+            who.push_back(k);
+            t.pos = e;
+        }
+        first = false;
+        if (ex.empty()) break;
+        rc = execute(ctx, n, ex);
+        if (rc) return rc;
+        std::vector<size_t> meas;
+        for (size_t k : who) {
+            if (mt[k].pos < mt[k].n) meas.push_back(k);
+            else mt[k].done = true;
+        }
+        if (meas.empty()) break;
+        const uint32_t M = (uint32_t)meas.size();
+        std::vector<const void *> ptrs(M);
+        std::vector<uint32_t> qs(M);
+        for (uint32_t i = 0; i < M; ++i) {
+            ptrs[i] = mt[meas[i]].dst;
+            qs[i] = mt[meas[i]].g[mt[meas[i]].pos].q0;
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(mb, ptrs.data(), M * sizeof(void *), hipMemcpyHostToDevice, ctx->stream),
+                "measure upload");
+        HIP_TRY(ctx, hipMemcpyAsync(mb + ptr_bytes, qs.data(), M * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                    ctx->stream),
+                "measure upload");
+        {
+            ProfScope ps(ctx, 1, (double)M * (double)(8ull << n));
+            hipError_t er = launch_measure_sums(ctx->stream, reinterpret_cast<const float2 *const *>(mb),
+                                                reinterpret_cast<const uint32_t *>(mb + ptr_bytes), M, n, part,
+                                                dsum);
+            if (er != hipSuccess) return hip_fail(ctx, er, "measure launch");
+        }
+        std::vector<double> sums(2 * (size_t)M);
+        HIP_TRY(ctx, hipMemcpyAsync(sums.data(), dsum, sums.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                    ctx->stream),
+                "measure copy");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+        for (uint32_t i = 0; i < M; ++i) {
+            MeasTask &t = mt[meas[i]];
+            const qw_gate &mg = t.g[t.pos];
+            const double S = sums[2 * i], S1 = sums[2 * i + 1];
+            if (!(S > 0.0)) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
+            const int b = mg.param < S1 / S ? 1 : 0;
+            const double Sb = b ? S1 : S - S1;
+            qw_gate pg{};
+            pg.kind = b ? QW_GATE_PROJ1 : QW_GATE_PROJ0;
+            pg.q0 = mg.q0;
+            pg.param = 1.0 / std::sqrt(Sb);
+            t.head.push_back(pg);
+            if (mg.kind == QW_GATE_RESET && b) {
+                qw_gate xg{};
+                xg.kind = QW_GATE_X;
+                xg.q0 = mg.q0;
+                t.head.push_back(xg);
+            }
+            t.outc.push_back((uint8_t)b);
+            t.pos += 1;
+        }
+    }
+    ctx->outcomes.clear();
+    for (const MeasTask &t : mt) ctx->outcomes.insert(ctx->outcomes.end(), t.outc.begin(), t.outc.end());
+    return QW_OK;
+}
+
 }  // namespace
 
 // ================================================================= ABI
@@ -1000,6 +1137,7 @@ int qw_ctx_destroy(qw_ctx *ctx) {
     if (ctx->plan.p) (void)hipFree(ctx->plan.p);
     if (ctx->scratch.p) hipFree(ctx->scratch.p);
     if (ctx->pingpong.p) hipFree(ctx->pingpong.p);
+    if (ctx->meas.p) hipFree(ctx->meas.p);
     if (ctx->staging) hipHostFree(ctx->staging);
     if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
     delete ctx;
@@ -1138,6 +1276,15 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
     qw_ctx *ctx = st->ctx;
     if (slot >= st->n_slots) return fail(ctx, QW_E_INVALID_ARG, "slot out of range");
     if (st->frozen[slot]) return fail(ctx, QW_E_INVALID_ARG, "slot is frozen by a snapshot");
+    if (n_gates && !gates) return fail(ctx, QW_E_INVALID_ARG, "gates == NULL");
+    ctx->outcomes.clear();
+    if (has_measure(gates, n_gates)) {
+        std::vector<MeasTask> mt(1);
+        mt[0].g = gates;
+        mt[0].n = n_gates;
+        mt[0].dst = slot_ptr(st, slot);
+        return run_measured(ctx, st->n, mt);
+    }
     std::vector<Exec> ex(1);
     std::string e = get_plan(ctx, st->n, gates, n_gates, &ex[0].planp);
     if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
@@ -1252,13 +1399,6 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
                                      sn->art.kind, QW_KIND_STATEVECTOR, sn->art.backend, QW_BACKEND_SV, k));
         if (sn->ctx != ctx) return fail(ctx, QW_E_INVALID_ARG, "snapshot belongs to another context");
     }
-    std::vector<Exec> ex(n_tasks);
-    for (uint32_t k = 0; k < n_tasks; ++k) {
-        std::string e = get_plan(ctx, dst->n, tasks[k].gates, tasks[k].n_gates, &ex[k].planp);
-        if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
-        ex[k].src = (src && src[k]) ? src[k]->data : nullptr;
-        ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);
-    }
     if (epi) {
         if (epi->n_terms > 0 && (!epi->x_mask || !epi->z_mask || !epi->coeff))
             return fail(ctx, QW_E_INVALID_ARG, "epilogue arrays are NULL");
@@ -1267,6 +1407,35 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         for (uint32_t j = 0; j < epi->n_terms; ++j)
             if ((epi->x_mask[j] & ~full) || (epi->z_mask[j] & ~full))
                 return fail(ctx, QW_E_INVALID_ARG, "Pauli mask has bits >= n");
+    }
+    ctx->outcomes.clear();
+    bool measured = false;
+    for (uint32_t k = 0; k < n_tasks && !measured; ++k) {
+        if (tasks[k].n_gates && !tasks[k].gates) return fail(ctx, QW_E_INVALID_ARG, "task gates == NULL");
+        measured = has_measure(tasks[k].gates, tasks[k].n_gates);
+    }
+    if (measured) {
+        // segments between measurements; the expectations after the last one
+        std::vector<MeasTask> mt(n_tasks);
+        for (uint32_t k = 0; k < n_tasks; ++k) {
+            mt[k].g = tasks[k].gates;
+            mt[k].n = tasks[k].n_gates;
+            mt[k].src = (src && src[k]) ? src[k]->data : nullptr;
+            mt[k].dst = slot_ptr(dst, tasks[k].dst_slot);
+        }
+        int rc = run_measured(ctx, dst->n, mt);
+        if (rc || !epi) return rc;
+        std::vector<const void *> slots(n_tasks);
+        for (uint32_t k = 0; k < n_tasks; ++k) slots[k] = slot_ptr(dst, tasks[k].dst_slot);
+        return expect_slots(ctx, dst->n, slots, epi->x_mask, epi->z_mask, epi->coeff, epi->n_terms,
+                            epi->out, epi->out_is_host, nullptr);
+    }
+    std::vector<Exec> ex(n_tasks);
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        std::string e = get_plan(ctx, dst->n, tasks[k].gates, tasks[k].n_gates, &ex[k].planp);
+        if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
+        ex[k].src = (src && src[k]) ? src[k]->data : nullptr;
+        ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);
     }
     // Fused expectation epilogue: terms that the last pass can evaluate on
     // its own tile (after conjugation through its output relabelling) are
@@ -1393,14 +1562,44 @@ int qw_mlp_adam(qw_ctx *ctx, float *params, const float *grad, float *m, float *
     return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp adam");
 }
 
+int qw_outcomes(const qw_ctx *ctx, uint8_t *out, uint64_t cap, uint64_t *count) {
+    if (!ctx || (cap && !out)) return QW_E_INVALID_ARG;
+    const uint64_t m = std::min<uint64_t>(cap, ctx->outcomes.size());
+    if (m) std::memcpy(out, ctx->outcomes.data(), m);
+    if (count) *count = ctx->outcomes.size();
+    return QW_OK;
+}
+
 int qw_plan_cost(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_t tile_bits,
                  uint64_t *n_passes, double *bytes) {
     if (n_gates && !gates) return QW_E_INVALID_ARG;
-    Plan p;
-    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p, true, false);
-    if (!e.empty()) return QW_E_INVALID_ARG;
-    if (n_passes) *n_passes = p.passes.size();
-    if (bytes) *bytes = (double)p.passes.size() * 2.0 * 8.0 * std::ldexp(1.0, (int)n);
+    // segments between measurements are planned alone; each measurement
+    // reads the state once and leaves a projector for the next segment
+    uint64_t passes = 0, reads = 0;
+    std::vector<qw_gate> seg;
+    for (uint64_t i = 0; i <= n_gates; ++i) {
+        if (i < n_gates && !is_measure(gates[i].kind)) {
+            seg.push_back(gates[i]);
+            continue;
+        }
+        if (i < n_gates && (gates[i].q0 >= n || !(gates[i].param >= 0.0 && gates[i].param < 1.0)))
+            return QW_E_INVALID_ARG;
+        Plan p;
+        if (!build_plan((int)n, seg.data(), seg.size(), (int)tile_bits, &p, true, false).empty())
+            return QW_E_INVALID_ARG;
+        passes += p.passes.size();
+        if (i == n_gates) break;
+        ++reads;
+        seg.clear();
+        qw_gate pg{};
+        pg.kind = QW_GATE_PROJ0;
+        pg.q0 = gates[i].q0;
+        pg.param = 1.0;
+        seg.push_back(pg);
+    }
+    const double sb = 8.0 * std::ldexp(1.0, (int)n);
+    if (n_passes) *n_passes = passes;
+    if (bytes) *bytes = (double)passes * 2.0 * sb + (double)reads * sb;
     return QW_OK;
 }
 

@@ -34,6 +34,12 @@ hipError_t launch_expect_finalize(hipStream_t st, const double *part, const doub
                                   double *out);
 // Inverse-CDF sampling of `shots` outcomes for n_slots slots (device array
 // of slot pointers). csum/cpre: n_slots * chunks doubles; total: n_slots.
+// Measurement sums (FP64, fixed order) of n_slots states: out[2 s] = sum of
+// |psi_i|^2, out[2 s + 1] = the same over indices with bit qubit[s] set.
+// slots and qubit are device arrays; part holds 2 * n_slots * 2^(n - 14)
+// doubles (2 * n_slots for n <= 14).
+hipError_t launch_measure_sums(hipStream_t st, const float2 *const *slots, const uint32_t *qubit,
+                               uint32_t n_slots, uint32_t n, double *part, double *out);
 hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
                          uint32_t n, double *csum, double *cpre, double *total, uint64_t seed,
                          uint64_t task_base, uint32_t shots, uint32_t *out);

@@ -839,6 +839,57 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(const float2 *const *__r
     if (threadIdx.x == 0) csum[(uint64_t)s * chunks + c] = acc;
 }
 
+// Measurement sums of slot s over chunk c of 2^C amplitudes: the FP64 sum
+// of |psi_i|^2 and the same sum over the indices with bit qubit[s] set
+// (fixed order: per thread in index order, then the block sum).
+__global__ __launch_bounds__(256) void measure_sum_kernel(const float2 *const *__restrict__ slots,
+                                                          const uint32_t *__restrict__ qubit,
+                                                          uint32_t C, uint32_t chunks,
+                                                          double *__restrict__ part) {
+    __shared__ double red[5];
+    const uint32_t c = blockIdx.x, s = blockIdx.y;
+    const uint64_t first = (uint64_t)c << C;
+    const float2 *psi = slots[s] + first;
+    const uint32_t q = qubit[s];
+    const uint32_t len = 1u << C;
+    double acc = 0.0, acc1 = 0.0;
+    for (uint32_t i = threadIdx.x; i < len; i += 256) {
+        const double x = psi[i].x, y = psi[i].y;
+        const double w = fma(x, x, y * y);
+        acc += w;
+        if (((first + i) >> q) & 1ull) acc1 += w;
+    }
+    acc = block_sum<256>(acc, red);
+    acc1 = block_sum<256>(acc1, red);
+    if (threadIdx.x == 0) {
+        part[2 * ((uint64_t)s * chunks + c)] = acc;
+        part[2 * ((uint64_t)s * chunks + c) + 1] = acc1;
+    }
+}
+
+// Chunk sums of slot s added in a fixed order: out[2 s] = S, out[2 s + 1] = S1.
+__global__ __launch_bounds__(256) void measure_finalize_kernel(const double *__restrict__ part,
+                                                               uint32_t chunks,
+                                                               double *__restrict__ out) {
+    __shared__ double red[5];
+    const uint32_t s = blockIdx.x;
+    const double *in = part + 2 * (uint64_t)s * chunks;
+    const uint32_t per = (chunks + 255) / 256;
+    const uint32_t b0 = threadIdx.x * per;
+    const uint32_t b1 = (b0 + per < chunks) ? b0 + per : chunks;
+    double a = 0.0, a1 = 0.0;
+    for (uint32_t c = b0; c < b1; ++c) {
+        a += in[2 * c];
+        a1 += in[2 * c + 1];
+    }
+    a = block_sum<256>(a, red);
+    a1 = block_sum<256>(a1, red);
+    if (threadIdx.x == 0) {
+        out[2 * s] = a;
+        out[2 * s + 1] = a1;
+    }
+}
+
 // exclusive prefix of chunk sums per slot (in place into cpre) + total
 __global__ __launch_bounds__(256) void chunk_scan_kernel(const double *__restrict__ csum,
                                                          uint32_t chunks,
@@ -1066,6 +1117,19 @@ hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_
     if (threads == 0) return hipSuccess;
     hipLaunchKernelGGL(draw_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st,
                        slots, n_slots, n, C, chunks, cpre, total, seed, task_base, shots, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_sums(hipStream_t st, const float2 *const *slots, const uint32_t *qubit,
+                               uint32_t n_slots, uint32_t n, double *part, double *out) {
+    if (n_slots == 0) return hipSuccess;
+    const uint32_t C = n < 14 ? n : 14;
+    const uint32_t chunks = 1u << (n - C);
+    hipLaunchKernelGGL(measure_sum_kernel, dim3(chunks, n_slots), dim3(256), 0, st, slots, qubit, C,
+                       chunks, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(measure_finalize_kernel, dim3(n_slots), dim3(256), 0, st, part, chunks, out);
     return hipGetLastError();
 }
 

@@ -70,6 +70,8 @@ M2 gate_matrix(int kind, double t) {
     case QW_GATE_RY: return {c, -s, s, c};
     case QW_GATE_RZ: return {std::polar(1.0, -0.5 * t), 0.0, 0.0, std::polar(1.0, 0.5 * t)};
     case QW_GATE_P: return {1.0, 0.0, 0.0, std::polar(1.0, t)};
+    case QW_GATE_PROJ0: return {t, 0.0, 0.0, 0.0};
+    case QW_GATE_PROJ1: return {0.0, 0.0, 0.0, t};
     default: return {1.0, 0.0, 0.0, 1.0};
     }
 }
@@ -79,7 +81,8 @@ bool classify(int kind, GClass *cls) {
     case QW_GATE_H: case QW_GATE_RX: case QW_GATE_RY: *cls = C_MIX; return true;
     case QW_GATE_X: case QW_GATE_Y: *cls = C_PERM; return true;
     case QW_GATE_Z: case QW_GATE_S: case QW_GATE_SDG: case QW_GATE_T:
-    case QW_GATE_TDG: case QW_GATE_RZ: case QW_GATE_P: *cls = C_DIAG; return true;
+    case QW_GATE_TDG: case QW_GATE_RZ: case QW_GATE_P:
+    case QW_GATE_PROJ0: case QW_GATE_PROJ1: *cls = C_DIAG; return true;
     case QW_GATE_CNOT: *cls = C_CX; return true;
     case QW_GATE_CZ: *cls = C_CZ; return true;
     case QW_GATE_RENORM: *cls = C_RENORM; return true;
@@ -984,6 +987,11 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
         const qw_gate &q = gates[i];
         G g{(int)q.kind, (int)q.q0, (int)q.q1, q.param, C_MIX};
         char buf[160];
+        if (q.kind == QW_GATE_MEASURE || q.kind == QW_GATE_RESET) {
+            // executed between segments (qw_apply_prefix, qw_run_suffix_batch)
+            snprintf(buf, sizeof buf, "gate %zu: a measurement cannot be inside a pass plan", i);
+            return buf;
+        }
         if (!classify(g.kind, &g.cls)) {
             snprintf(buf, sizeof buf, "gate %zu: unknown kind 0x%x", i, (unsigned)q.kind);
             return buf;

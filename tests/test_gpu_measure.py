@@ -1,0 +1,205 @@
+"""Mid-circuit Z measurement and reset on the GPU (segments between
+measurements, FP64 measurement sums, host decision, projector folded into the
+next segment) against the oracle, and reuse against direct.
+
+Covers batches whose tasks measure different qubits at different points
+(some tasks without any measurement), RESET, a measured shared prefix cut by
+a snapshot, an expectation epilogue after the last measurement, the outcome
+record order and a repetition-code syndrome round whose outcomes the code
+fixes. Draws u are moved at least 1e-3 away from the oracle's outcome
+probability, so that FP32 and FP64 states pick the same outcome. Every case
+prints its name."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import _measure
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2609_23664_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    import torch
+    assert torch.cuda.is_available()
+    c = B.Ctx(0)
+    yield c
+    c.set_option(B.QW_OPT_TILE_BITS, 14)
+    c.sync()
+
+
+def _safe(n, gates, psi=None):
+    """The gate list with every measurement's u at least 1e-3 from the
+    oracle's P(1) at that point; returns (gates, oracle state, outcomes)."""
+    psi = oracle.zero_state(n) if psi is None else psi.copy()
+    out, outs, seg = [], [], []
+    for g in gates:
+        if g[0] not in ("MEASURE", "RESET"):
+            seg.append(g)
+            out.append(g)
+            continue
+        oracle.apply_gates(psi, n, seg)
+        seg = []
+        q, u = g[1][0], g[2]
+        idx = np.arange(1 << n)
+        w = np.abs(psi) ** 2
+        p1 = float(w[((idx >> q) & 1) == 1].sum() / w.sum())
+        if abs(u - p1) < 1e-3:
+            u = p1 + 0.01 if p1 + 0.01 < 1.0 else p1 - 0.01
+        out.append((g[0], g[1], float(u)))
+        outs.append(_measure(psi, n, q, u, g[0] == "RESET"))
+    oracle.apply_gates(psi, n, seg)
+    return out, psi, outs
+
+
+def _random_measured(n, rng, layers, n_meas):
+    g = []
+    for _ in range(layers):
+        g += gen.hea_layer(n, gen.random_angles(rng, 2 * n))
+    for _ in range(n_meas):
+        pos = int(rng.integers(0, len(g) + 1))
+        kind = "RESET" if rng.random() < 0.3 else "MEASURE"
+        g.insert(pos, (kind, (int(rng.integers(n)),), float(rng.random())))
+    return g
+
+
+def _fid(a, b):
+    a = a.astype(np.complex128)
+    return abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+@pytest.mark.parametrize("n,tile", [(16, 12), (20, 14)])
+def test_measured_batch_matches_oracle(ctx, B, n, tile):
+    say("measured batch", n, tile)
+    rng = np.random.default_rng(1000 + n)
+    T = 6
+    tasks, refs, outs = [], [], []
+    for k in range(T):
+        g = _random_measured(n, rng, 2, [0, 1, 2, 3, 1, 2][k])
+        g, psi, o = _safe(n, g)
+        tasks.append(g)
+        refs.append(psi)
+        outs += o
+    ctx.set_option(B.QW_OPT_TILE_BITS, tile)
+    try:
+        st = B.State(ctx, n, T)
+        st.reset(0, T)
+        B.run_suffix_batch(ctx, None, tasks, st, list(range(T)))
+        got = B.outcomes(ctx)
+        states = [st.host(k) for k in range(T)]
+        st.free()
+    finally:
+        ctx.set_option(B.QW_OPT_TILE_BITS, 14)
+    assert list(got) == outs
+    for k in range(T):
+        f = _fid(states[k], refs[k])
+        assert 1.0 - f <= 1e-6, (k, f)
+        s64 = states[k].astype(np.complex128)
+        assert abs(np.vdot(s64, s64).real - 1.0) <= 1e-5
+
+
+def test_reset_and_apply_prefix(ctx, B):
+    n = 14
+    say("reset apply_prefix", n)
+    g = [("RY", (0,), math.pi / 2)] + [("CNOT", (q, q + 1), 0.0) for q in range(n - 1)]
+    for u, b in ((0.25, 1), (0.75, 0)):
+        st = B.State(ctx, n, 1)
+        st.reset(0, 1)
+        st.apply(0, g + [("RESET", (3,), u)])
+        assert list(B.outcomes(ctx)) == [b]
+        psi = st.host(0)
+        full = (1 << n) - 1
+        idx = (full ^ (1 << 3)) if b else 0
+        assert abs(abs(psi[idx]) - 1.0) <= 1e-6
+        st.free()
+
+
+def test_measured_prefix_reuse_equals_direct(ctx, B):
+    """A prefix with measurements, snapshotted after its last gate, and
+    measured suffixes: the reuse path and the direct path give bitwise equal
+    states and outcomes."""
+    n, T = 18, 5
+    say("measured reuse vs direct", n)
+    rng = np.random.default_rng(2024)
+    prefix, _, _ = _safe(n, _random_measured(n, rng, 2, 2))
+    psi_p, _ = oracle.simulate_measured(n, prefix)
+    sufs = [_safe(n, _random_measured(n, rng, 1, 1 + k % 2), psi_p)[0] for k in range(T)]
+    prov = b"measured-prefix".ljust(32, b"\0")
+    st = B.State(ctx, n, T + 1)
+    st.reset(0, T + 1)
+    st.apply(0, prefix)
+    out_pre = list(B.outcomes(ctx))
+    snap = st.snapshot(0, prov)
+    B.run_suffix_batch(ctx, [snap] * T, sufs, st, list(range(1, T + 1)))
+    out_reuse = list(B.outcomes(ctx))
+    reuse = [st.host(k) for k in range(1, T + 1)]
+    snap.free()
+    st.free()
+    direct, out_dir = [], []
+    st = B.State(ctx, n, T)
+    st.reset(0, T)
+    for k in range(T):
+        st.apply(k, prefix)
+        assert list(B.outcomes(ctx)) == out_pre
+    B.run_suffix_batch(ctx, None, sufs, st, list(range(T)))
+    out_dir = list(B.outcomes(ctx))
+    direct = [st.host(k) for k in range(T)]
+    st.free()
+    assert out_reuse == out_dir
+    for a, b in zip(reuse, direct):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    for k in range(T):
+        ref, _ = oracle.simulate_measured(n, prefix + sufs[k])
+        assert 1.0 - _fid(reuse[k], ref) <= 1e-6, k
+
+
+def test_expectation_after_measurement(ctx, B):
+    n, T = 16, 4
+    say("measured expectation", n)
+    rng = np.random.default_rng(77)
+    tasks = [_safe(n, _random_measured(n, rng, 2, 2))[0] for _ in range(T)]
+    w = gen.small_vqe(n, 1, 1, 1, 20, seed=5, layer="hea")
+    st = B.State(ctx, n, T)
+    st.reset(0, T)
+    e = B.run_suffix_batch(ctx, None, tasks, st, list(range(T)), terms=w.terms)
+    st.free()
+    scale = sum(abs(t[0]) for t in w.terms)
+    for k in range(T):
+        psi, _ = oracle.simulate_measured(n, tasks[k])
+        ref = oracle.expect(psi, n, w.terms)
+        assert abs(e[k] - ref) <= 1e-5 * scale, (k, e[k], ref)
+
+
+@pytest.mark.parametrize("err,syn", [(None, [0, 0]), (0, [1, 0]), (1, [1, 1]), (2, [0, 1])])
+def test_repetition_syndromes(ctx, B, err, syn):
+    n = 12
+    say("repetition syndromes", err)
+    g = [("RY", (0,), 1.3), ("CNOT", (0, 1), 0.0), ("CNOT", (1, 2), 0.0)]
+    if err is not None:
+        g.append(("X", (err,), 0.0))
+    g += [("CNOT", (0, 3), 0.0), ("CNOT", (1, 3), 0.0), ("MEASURE", (3,), 0.5),
+          ("CNOT", (1, 4), 0.0), ("CNOT", (2, 4), 0.0), ("RESET", (4,), 0.5)]
+    st = B.State(ctx, n, 1)
+    st.reset(0, 1)
+    st.apply(0, g)
+    assert list(B.outcomes(ctx)) == syn
+    psi = st.host(0)
+    st.free()
+    ref, o = oracle.simulate_measured(n, g)
+    assert o == syn
+    assert 1.0 - _fid(psi, ref) <= 1e-6

@@ -10,6 +10,10 @@ A gate record is a tuple ``(name, qubits, param)``:
 ``RENORM`` is a marker with no qubits: the state is renormalised at that
 point of the gate list (used after inserted noise jumps).
 
+``MEASURE`` and ``RESET`` act on one qubit; their ``param`` is the uniform
+draw u in [0, 1) that decides the outcome (1 iff u < P(qubit = 1)); RESET
+then flips the qubit back to 0 when the outcome is 1.
+
 A Pauli term is ``(coeff, x_mask, z_mask)``: bit q of ``x_mask`` is set when
 the term has X or Y on qubit q, bit q of ``z_mask`` when it has Z or Y.
 
@@ -33,6 +37,7 @@ GATE_NAMES = (
     "RX", "RY", "RZ", "P",
     "CNOT", "CZ",
     "RENORM",
+    "MEASURE", "RESET",
 )
 
 Gate = Tuple[str, Tuple[int, ...], float]
@@ -353,3 +358,36 @@ def config5_workload(spec: Config5Spec, max_tasks: int | None = None) -> Workloa
         suffixes.append(_hea_layers(gt, n, spec.total_layers - spec.prefix_layers + extra))
     terms = random_pauli_terms(rng(505, 3, spec.index), n, 8)
     return Workload(f"cm_{spec.index}", n, prefix, suffixes, terms, seed=505)
+
+
+def syndrome_round(d: int, draws: Sequence[float]) -> List[Gate]:
+    """One syndrome-extraction round of a distance-d bit-flip repetition code:
+    data qubits 0..d-1, ancilla d+i measures Z_i Z_{i+1} through CNOT(i, d+i)
+    and CNOT(i+1, d+i), then a RESET of the ancilla with draw draws[i]."""
+    g: List[Gate] = []
+    for i in range(d - 1):
+        g += [("CNOT", (i, d + i), 0.0), ("CNOT", (i + 1, d + i), 0.0),
+              ("RESET", (d + i,), float(draws[i]))]
+    return g
+
+
+def qec_repetition(d: int = 12, n_tasks: int = 64, seed: int = 606) -> Workload:
+    """Repetition-code memory experiment with mid-circuit measurements
+    (2d - 1 qubits). Shared prefix: encode cos(t/2)|0..0> + sin(t/2)|1..1>
+    on the data (RY on qubit 0 and a CNOT chain), then one syndrome round.
+    Task k: a coherent error RX(e_k) on data qubit k mod d (e_k uniform on
+    [0.05, 0.3]), then one more syndrome round with its own draws. Terms: the
+    data parities Z_i Z_{i+1} and Z_0, coefficient 1."""
+    n = 2 * d - 1
+    g = rng(seed, 0)
+    theta = float(g.uniform(0.3, 1.2))
+    prefix: List[Gate] = [("RY", (0,), theta)] + [("CNOT", (i, i + 1), 0.0) for i in range(d - 1)]
+    prefix += syndrome_round(d, g.uniform(0.0, 1.0, size=d - 1))
+    suffixes = []
+    for k in range(n_tasks):
+        gk = rng(seed, 1, k)
+        e = float(gk.uniform(0.05, 0.3))
+        suffixes.append([("RX", (k % d,), e)] + syndrome_round(d, gk.uniform(0.0, 1.0, size=d - 1)))
+    terms = [(1.0, 0, (1 << i) | (1 << (i + 1))) for i in range(d - 1)] + [(1.0, 0, 1)]
+    return Workload(name=f"qec_repetition_d{d}_{n}q_{n_tasks}t", n=n, prefix=prefix,
+                    suffixes=suffixes, terms=terms)
