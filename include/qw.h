@@ -63,11 +63,19 @@ extern "C" {
  *           (qw_outcomes).
  *   RESET:  a MEASURE of q0 followed by X on q0 when b = 1 (q0 ends in |0>);
  *           param = u as for MEASURE, and the outcome is recorded.
- * A gate list with MEASURE or RESET runs in segments: the gates up to the
- * measurement, then an FP64 sum pass over the state, a host decision (the
- * call synchronises the stream once per measurement), and the next segment
- * starting with PROJ_b(1 / sqrt(S_b)) (and X for a RESET with b = 1), which
- * fuses into that segment's first pass. */
+ * A gate list with MEASURE or RESET runs in segments. A measurement commutes
+ * with gates on other qubits, so a segment runs the gates up to a
+ * measurement and every later gate that touches no qubit measured so far;
+ * the measurements met on the way (up to 12, on distinct qubits, a RENORM or
+ * a gate on a measured qubit ends the segment) are then decided together
+ * from one FP64 sweep over the state: a single measurement from S and S1 as
+ * above; several (all on qubits >= 8) from the FP64 masses of their 2^k
+ * outcome bins, in gate order, each by the rule above applied to the masses
+ * that agree with the earlier outcomes (the sequential rule, with the
+ * probabilities it would see). The call synchronises the stream once per
+ * such decision. The next segment starts with the projectors (PROJ_b, the
+ * first with the factor 1 / sqrt of the chosen outcome's mass) and an X for
+ * each RESET with outcome 1; they fuse into that segment's first pass. */
 #define QW_GATE_X 0x01
 #define QW_GATE_Y 0x02
 #define QW_GATE_Z 0x03

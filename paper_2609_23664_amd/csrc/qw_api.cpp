@@ -68,6 +68,7 @@ struct qw_ctx {
     DevBuf pingpong; // second state buffers of tasks with relabelling passes
     DevBuf meas;     // measurement sums: slot pointers, qubits, partials, results
     std::vector<uint8_t> outcomes;  // outcome record of the last measured call
+    std::unordered_map<std::string, uint64_t> jit_heat;  // task-tiles run per pass structure
     bool relabel = true;
     int tile_order = 1;          // QW_OPT_TILE_ORDER
     bool fused_epilogue = true;
@@ -339,8 +340,11 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
 }
 
 // Tiered generated kernels: a pass structure not yet compiled is compiled
-// when one launch runs it over at least this many tiles (task-tiles);
-// smaller one-off launches use the interpreted kernels (same results).
+// when the launches of it on this context have run it over at least this
+// many tiles (task-tiles, counted across calls: a structure that recurs in
+// small groups, such as one error position of a batch, becomes hot too);
+// until then, and for one-off structures, the interpreted kernels run
+// (same results).
 constexpr uint64_t kJitHotTiles = 4096;
 
 // One task of an execution: its plan, source, destination.
@@ -585,14 +589,19 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             }
         }
         // tiered: generate a kernel when it is available without compiling,
-        // or when the launch carries enough work to pay for compiling it
+        // or when its structure has run enough work on this context to pay
+        // for compiling it
         std::vector<char> want(reqs.size(), 1);
         if (ctx->jit == 1) {
             std::vector<uint64_t> work(reqs.size(), 0);
             for (size_t k = 0; k < steps; ++k)
                 for (auto &gm : members[k]) work[gm.first] += (uint64_t)gm.second.size() * tiles;
-            for (size_t i = 0; i < reqs.size(); ++i)
-                want[i] = reqs[i].epi || work[i] >= kJitHotTiles || jit_available(ctx->device, reqs[i]);
+            for (size_t i = 0; i < reqs.size(); ++i) {
+                uint64_t &heat = ctx->jit_heat[reqs[i].key];
+                heat += work[i];
+                want[i] = reqs[i].epi || heat >= kJitHotTiles || jit_available(ctx->device, reqs[i]);
+            }
+            if (ctx->jit_heat.size() > 65536) ctx->jit_heat.clear();
         }
         std::vector<JitReq> sel;
         std::vector<size_t> sel_of(reqs.size(), (size_t)-1);
@@ -968,124 +977,236 @@ bool has_measure(const qw_gate *g, uint64_t n) {
 
 // One task of a measured execution.
 struct MeasTask {
-    const qw_gate *g = nullptr;
-    uint64_t n = 0, pos = 0;     // gates; next gate to run
+    std::vector<qw_gate> rest;   // gates not yet run
     const void *src = nullptr;   // the first segment's source (a snapshot), or null
     void *dst = nullptr;
-    std::vector<qw_gate> head;   // projector (and X) that opens the next segment
+    std::vector<qw_gate> head;   // projectors (and X) that open the next segment
+    std::vector<qw_gate> cluster;  // measurements decided after this round's segment
     std::vector<uint8_t> outc;
     bool done = false;
 };
 
+// Largest number of measurements decided jointly (2^k outcome bins).
+constexpr size_t kMaxJoint = 12;
+// Joint decisions need every measured qubit >= this (a 256-amplitude chunk
+// then lies in one outcome bin).
+constexpr uint32_t kJointMinQubit = 8;
+
+uint64_t gate_qubits(const qw_gate &g) {
+    if (g.kind == QW_GATE_RENORM) return 0;
+    uint64_t m = 1ull << g.q0;
+    if (g.kind == QW_GATE_CNOT || g.kind == QW_GATE_CZ) m |= 1ull << g.q1;
+    return m;
+}
+
+// Splits off the next segment of a task: the gates up to its next
+// measurement, plus every later gate that touches none of the qubits
+// measured so far (a measurement commutes with gates on other qubits, so it
+// is decided after them), collecting the measurements met on the way; stops
+// at a gate on a measured qubit, a second measurement of one, a RENORM after
+// a measurement, kMaxJoint measurements, or (for a joint decision) a
+// measurement of a qubit below kJointMinQubit.
+void next_segment(MeasTask &t, std::vector<qw_gate> *seg) {
+    *seg = t.head;
+    t.head.clear();
+    t.cluster.clear();
+    uint64_t pend = 0;
+    bool low = false;
+    size_t i = 0;
+    for (; i < t.rest.size(); ++i) {
+        const qw_gate &g = t.rest[i];
+        if (is_measure(g.kind)) {
+            const bool q_low = g.q0 < kJointMinQubit;
+            if ((pend >> g.q0) & 1ull) break;
+            if (!t.cluster.empty() && (low || q_low)) break;
+            t.cluster.push_back(g);
+            pend |= 1ull << g.q0;
+            low = low || q_low;
+            if (t.cluster.size() == kMaxJoint) {
+                ++i;
+                break;
+            }
+            continue;
+        }
+        if (g.kind == QW_GATE_RENORM && !t.cluster.empty()) break;
+        if (gate_qubits(g) & pend) break;
+        seg->push_back(g);
+    }
+    t.rest.erase(t.rest.begin(), t.rest.begin() + (std::ptrdiff_t)i);
+}
+
+// The outcomes of a cluster from its outcome-bin masses (bin bits = the
+// measured qubits in ascending order): measurement j (gate order) takes
+// b_j = (u_j < M(bit = 1 | earlier outcomes) / M(earlier outcomes)), FP64
+// sums in ascending bin order; then the bins are halved along that bit.
+// Returns the mass of the chosen bin.
+double decide_cluster(MeasTask &t, std::vector<double> mass, std::vector<uint32_t> *outs) {
+    std::vector<uint32_t> qs;
+    for (const qw_gate &g : t.cluster) qs.push_back(g.q0);
+    std::vector<uint32_t> asc = qs;
+    std::sort(asc.begin(), asc.end());
+    std::vector<uint32_t> alive = asc;  // qubits still bits of `mass`, ascending
+    outs->clear();
+    for (const qw_gate &g : t.cluster) {
+        const uint32_t p = (uint32_t)(std::find(alive.begin(), alive.end(), g.q0) - alive.begin());
+        double tot = 0.0, one = 0.0;
+        for (size_t b = 0; b < mass.size(); ++b) {
+            tot += mass[b];
+            if ((b >> p) & 1u) one += mass[b];
+        }
+        const uint32_t bit = g.param < one / tot ? 1u : 0u;
+        outs->push_back(bit);
+        std::vector<double> half(mass.size() / 2);
+        for (size_t b = 0, h = 0; b < mass.size(); ++b)
+            if (((b >> p) & 1u) == bit) half[h++] = mass[b];
+        mass.swap(half);
+        alive.erase(alive.begin() + p);
+    }
+    return mass[0];
+}
+
 // Gate lists with MEASURE / RESET gates run in rounds. A round runs every
-// unfinished task's next segment as one batch (the gates up to its next
-// measurement, after the projector the previous measurement left; the first
-// round reads the tasks' snapshots, later rounds run in place). The tasks
-// that stopped at a measurement then get their FP64 sums S and S1 in one
-// launch; the host picks b = (u < S1 / S) and the next segment opens with
-// PROJ_b(1 / sqrt(S_b)), plus X for a RESET with b = 1. Outcomes are
-// recorded per task in gate order (qw_outcomes).
+// unfinished task's next segment (next_segment) as one batch (the first
+// round reads the tasks' snapshots, later rounds run in place). The
+// measurements collected with the segments are then decided: a single one
+// from its FP64 sums S and S1, a cluster from the FP64 masses of its 2^k
+// outcome bins (decide_cluster), with the caller's draws; the next segment
+// opens with the projectors (the first one carrying 1 / sqrt of the chosen
+// mass) and an X for each RESET with outcome 1. Outcomes are recorded per
+// task in gate order (qw_outcomes).
 int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
     for (size_t k = 0; k < mt.size(); ++k)
-        for (uint64_t i = 0; i < mt[k].n; ++i) {
-            const qw_gate &q = mt[k].g[i];
+        for (size_t i = 0; i < mt[k].rest.size(); ++i) {
+            const qw_gate &q = mt[k].rest[i];
             if (!is_measure(q.kind)) continue;
             if (q.q0 >= n || q.reserved != 0 || !(q.param >= 0.0 && q.param < 1.0)) {
                 char buf[160];
-                snprintf(buf, sizeof buf,
-                         "task %zu gate %llu: a measurement needs a qubit < n and u in [0, 1)", k,
-                         (unsigned long long)i);
+                snprintf(buf, sizeof buf, "task %zu gate %zu: a measurement needs a qubit < n and u in [0, 1)",
+                         k, i);
                 return fail(ctx, QW_E_INVALID_ARG, buf);
             }
         }
     const uint32_t T = (uint32_t)mt.size();
-    const uint32_t C = n < 14 ? n : 14;
-    const uint64_t chunks = 1ull << (n - C);
+    const uint32_t kStride = 1u << kMaxJoint;
+    const uint64_t chunks_max = 1ull << (n > kJointMinQubit ? n - kJointMinQubit : 0);
     const size_t ptr_bytes = ((size_t)T * sizeof(void *) + 255) & ~(size_t)255;
-    const size_t q_bytes = ((size_t)T * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t part_bytes = (size_t)2 * T * chunks * sizeof(double);
-    int rc = ensure(ctx, ctx->meas, ptr_bytes + q_bytes + part_bytes + 2 * (size_t)T * sizeof(double),
+    const size_t q_bytes = ((size_t)T * sizeof(uint64_t) + 255) & ~(size_t)255;
+    const size_t part_doubles = std::max<size_t>((size_t)2 * T * chunks_max, 2 * (size_t)T);
+    const size_t out_doubles = (size_t)T * kStride;
+    int rc = ensure(ctx, ctx->meas, ptr_bytes + q_bytes + (part_doubles + out_doubles) * sizeof(double),
                     "measure buffer");
     if (rc) return rc;
     char *mb = static_cast<char *>(ctx->meas.p);
     double *part = reinterpret_cast<double *>(mb + ptr_bytes + q_bytes);
-    double *dsum = part + 2 * (size_t)T * chunks;
+    double *dout = part + part_doubles;
     bool first = true;
+    std::vector<std::vector<qw_gate>> segs(mt.size());
     while (true) {
         std::vector<Exec> ex;
-        std::vector<size_t> who;
-        std::vector<std::vector<qw_gate>> segs(mt.size());
         for (size_t k = 0; k < mt.size(); ++k) {
             MeasTask &t = mt[k];
             if (t.done) continue;
-            uint64_t e = t.pos;
-            while (e < t.n && !is_measure(t.g[e].kind)) ++e;
-            segs[k] = t.head;
-            segs[k].insert(segs[k].end(), t.g + t.pos, t.g + e);
-            t.head.clear();
+            next_segment(t, &segs[k]);
             Exec x;
             std::string err = get_plan(ctx, n, segs[k].data(), segs[k].size(), &x.planp);
             if (!err.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + err);
             x.src = first ? t.src : nullptr;
             x.dst = t.dst;
             ex.push_back(x);
-            who.push_back(k);
-            t.pos = e;
+            if (t.cluster.empty() && t.rest.empty()) t.done = true;
         }
         first = false;
         if (ex.empty()) break;
         rc = execute(ctx, n, ex);
         if (rc) return rc;
-        std::vector<size_t> meas;
-        for (size_t k : who) {
-            if (mt[k].pos < mt[k].n) meas.push_back(k);
-            else mt[k].done = true;
-        }
-        if (meas.empty()) break;
-        const uint32_t M = (uint32_t)meas.size();
-        std::vector<const void *> ptrs(M);
-        std::vector<uint32_t> qs(M);
-        for (uint32_t i = 0; i < M; ++i) {
-            ptrs[i] = mt[meas[i]].dst;
-            qs[i] = mt[meas[i]].g[mt[meas[i]].pos].q0;
-        }
-        HIP_TRY(ctx, hipMemcpyAsync(mb, ptrs.data(), M * sizeof(void *), hipMemcpyHostToDevice, ctx->stream),
-                "measure upload");
-        HIP_TRY(ctx, hipMemcpyAsync(mb + ptr_bytes, qs.data(), M * sizeof(uint32_t), hipMemcpyHostToDevice,
-                                    ctx->stream),
-                "measure upload");
-        {
-            ProfScope ps(ctx, 1, (double)M * (double)(8ull << n));
-            hipError_t er = launch_measure_sums(ctx->stream, reinterpret_cast<const float2 *const *>(mb),
-                                                reinterpret_cast<const uint32_t *>(mb + ptr_bytes), M, n, part,
-                                                dsum);
-            if (er != hipSuccess) return hip_fail(ctx, er, "measure launch");
-        }
-        std::vector<double> sums(2 * (size_t)M);
-        HIP_TRY(ctx, hipMemcpyAsync(sums.data(), dsum, sums.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                    ctx->stream),
-                "measure copy");
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
-        for (uint32_t i = 0; i < M; ++i) {
-            MeasTask &t = mt[meas[i]];
-            const qw_gate &mg = t.g[t.pos];
-            const double S = sums[2 * i], S1 = sums[2 * i + 1];
-            if (!(S > 0.0)) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
-            const int b = mg.param < S1 / S ? 1 : 0;
-            const double Sb = b ? S1 : S - S1;
-            qw_gate pg{};
-            pg.kind = b ? QW_GATE_PROJ1 : QW_GATE_PROJ0;
-            pg.q0 = mg.q0;
-            pg.param = 1.0 / std::sqrt(Sb);
-            t.head.push_back(pg);
-            if (mg.kind == QW_GATE_RESET && b) {
-                qw_gate xg{};
-                xg.kind = QW_GATE_X;
-                xg.q0 = mg.q0;
-                t.head.push_back(xg);
+        // decision groups: single measurements (bit split, any qubit), and
+        // joint clusters by chunk size C (the lowest measured qubit, <= 14)
+        std::map<uint32_t, std::vector<size_t>> groups;  // C (0 = single) -> tasks
+        for (size_t k = 0; k < mt.size(); ++k) {
+            const MeasTask &t = mt[k];
+            if (t.done || t.cluster.empty()) continue;
+            uint32_t C = 0;
+            if (t.cluster.size() > 1) {
+                C = std::min<uint32_t>(14, n);
+                for (const qw_gate &g : t.cluster) C = std::min(C, g.q0);
             }
-            t.outc.push_back((uint8_t)b);
-            t.pos += 1;
+            groups[C].push_back(k);
+        }
+        if (groups.empty()) break;
+        for (auto &gr : groups) {
+            const uint32_t C = gr.first;
+            const std::vector<size_t> &who = gr.second;
+            const uint32_t M = (uint32_t)who.size();
+            std::vector<const void *> ptrs(M);
+            std::vector<uint64_t> qs(M);
+            for (uint32_t i = 0; i < M; ++i) {
+                const MeasTask &t = mt[who[i]];
+                ptrs[i] = t.dst;
+                uint64_t m = 0;
+                for (const qw_gate &g : t.cluster) m |= 1ull << g.q0;
+                qs[i] = C ? (m >> C) : (uint64_t)t.cluster[0].q0;
+            }
+            HIP_TRY(ctx, hipMemcpyAsync(mb, ptrs.data(), M * sizeof(void *), hipMemcpyHostToDevice,
+                                        ctx->stream), "measure upload");
+            std::vector<uint32_t> q32(M);
+            for (uint32_t i = 0; i < M; ++i) q32[i] = (uint32_t)qs[i];
+            if (C == 0)
+                HIP_TRY(ctx, hipMemcpyAsync(mb + ptr_bytes, q32.data(), M * sizeof(uint32_t),
+                                            hipMemcpyHostToDevice, ctx->stream), "measure upload");
+            else
+                HIP_TRY(ctx, hipMemcpyAsync(mb + ptr_bytes, qs.data(), M * sizeof(uint64_t),
+                                            hipMemcpyHostToDevice, ctx->stream), "measure upload");
+            std::vector<double> h;
+            {
+                ProfScope ps(ctx, 1, (double)M * (double)(8ull << n));
+                hipError_t er = C == 0
+                    ? launch_measure_sums(ctx->stream, reinterpret_cast<const float2 *const *>(mb),
+                                          reinterpret_cast<const uint32_t *>(mb + ptr_bytes), M, n, part,
+                                          dout)
+                    : launch_joint_masses(ctx->stream, reinterpret_cast<const float2 *const *>(mb),
+                                          reinterpret_cast<const uint64_t *>(mb + ptr_bytes), M, n, C, part,
+                                          kStride, dout);
+                if (er != hipSuccess) return hip_fail(ctx, er, "measure launch");
+            }
+            h.resize(C == 0 ? 2 * (size_t)M : (size_t)M * kStride);
+            HIP_TRY(ctx, hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                        ctx->stream), "measure copy");
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+            for (uint32_t i = 0; i < M; ++i) {
+                MeasTask &t = mt[who[i]];
+                std::vector<uint32_t> outs;
+                double Sb;
+                if (C == 0) {
+                    const double S = h[2 * i], S1 = h[2 * i + 1];
+                    if (!(S > 0.0)) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
+                    const uint32_t b = t.cluster[0].param < S1 / S ? 1u : 0u;
+                    outs.push_back(b);
+                    Sb = b ? S1 : S - S1;
+                } else {
+                    const size_t bins = (size_t)1 << t.cluster.size();
+                    std::vector<double> mass(h.begin() + (size_t)i * kStride, h.begin() + (size_t)i * kStride + bins);
+                    double tot = 0.0;
+                    for (double v : mass) tot += v;
+                    if (!(tot > 0.0)) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
+                    Sb = decide_cluster(t, mass, &outs);
+                }
+                for (size_t j = 0; j < t.cluster.size(); ++j) {
+                    qw_gate pg{};
+                    pg.kind = outs[j] ? QW_GATE_PROJ1 : QW_GATE_PROJ0;
+                    pg.q0 = t.cluster[j].q0;
+                    pg.param = j == 0 ? 1.0 / std::sqrt(Sb) : 1.0;
+                    t.head.push_back(pg);
+                }
+                for (size_t j = 0; j < t.cluster.size(); ++j)
+                    if (t.cluster[j].kind == QW_GATE_RESET && outs[j]) {
+                        qw_gate xg{};
+                        xg.kind = QW_GATE_X;
+                        xg.q0 = t.cluster[j].q0;
+                        t.head.push_back(xg);
+                    }
+                for (uint32_t b : outs) t.outc.push_back((uint8_t)b);
+                t.cluster.clear();
+            }
         }
     }
     ctx->outcomes.clear();
@@ -1280,8 +1401,7 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
     ctx->outcomes.clear();
     if (has_measure(gates, n_gates)) {
         std::vector<MeasTask> mt(1);
-        mt[0].g = gates;
-        mt[0].n = n_gates;
+        mt[0].rest.assign(gates, gates + n_gates);
         mt[0].dst = slot_ptr(st, slot);
         return run_measured(ctx, st->n, mt);
     }
@@ -1418,8 +1538,7 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         // segments between measurements; the expectations after the last one
         std::vector<MeasTask> mt(n_tasks);
         for (uint32_t k = 0; k < n_tasks; ++k) {
-            mt[k].g = tasks[k].gates;
-            mt[k].n = tasks[k].n_gates;
+            if (tasks[k].n_gates) mt[k].rest.assign(tasks[k].gates, tasks[k].gates + tasks[k].n_gates);
             mt[k].src = (src && src[k]) ? src[k]->data : nullptr;
             mt[k].dst = slot_ptr(dst, tasks[k].dst_slot);
         }

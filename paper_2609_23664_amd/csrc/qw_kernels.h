@@ -40,6 +40,14 @@ hipError_t launch_expect_finalize(hipStream_t st, const double *part, const doub
 // doubles (2 * n_slots for n <= 14).
 hipError_t launch_measure_sums(hipStream_t st, const float2 *const *slots, const uint32_t *qubit,
                                uint32_t n_slots, uint32_t n, double *part, double *out);
+// Joint measurement masses of n_slots states whose measured qubits are all
+// >= C (8 <= C <= 14): out[s * bin_stride + b] = FP64 mass of outcome bin b
+// (measured bits of slot s in ascending qubit order), summed in a fixed
+// order. mq[s] = measured-qubit mask >> C (device); csum holds
+// n_slots * 2^(n - C) doubles.
+hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const uint64_t *mq,
+                               uint32_t n_slots, uint32_t n, uint32_t C, double *csum,
+                               uint32_t bin_stride, double *out);
 hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
                          uint32_t n, double *csum, double *cpre, double *total, uint64_t seed,
                          uint64_t task_base, uint32_t shots, uint32_t *out);

@@ -890,6 +890,43 @@ __global__ __launch_bounds__(256) void measure_finalize_kernel(const double *__r
     }
 }
 
+// Joint measurement masses: chunk c of slot s (2^C amplitudes, FP64 sum
+// csum[s * chunks + c]) lies in one outcome bin when every measured qubit is
+// >= C; bin b of slot s (its measured bits in ascending qubit order) is the
+// sum of its chunks in increasing chunk order. mq[s]: measured-qubit mask of
+// slot s shifted down by C (a mask over chunk-index bits).
+__global__ __launch_bounds__(256) void bin_mass_kernel(const double *__restrict__ csum,
+                                                       uint32_t chunks_log2,
+                                                       const uint64_t *__restrict__ mq,
+                                                       uint32_t bin_stride,
+                                                       double *__restrict__ out) {
+    const uint32_t s = blockIdx.x;
+    const uint64_t M = mq[s];
+    const uint32_t k = (uint32_t)__popcll(M);
+    const uint64_t all = (chunks_log2 >= 64) ? ~0ull : ((1ull << chunks_log2) - 1ull);
+    const uint64_t F = all & ~M;
+    const uint64_t nfree = 1ull << (chunks_log2 - k);
+    const double *in = csum + ((uint64_t)s << chunks_log2);
+    for (uint32_t b = threadIdx.x; b < (1u << k); b += 256) {
+        // chunk bits of the bin: deposit b into M
+        uint64_t cb = 0;
+        {
+            uint32_t j = 0;
+            for (uint32_t p = 0; p < chunks_log2; ++p)
+                if ((M >> p) & 1ull) cb |= (uint64_t)((b >> j++) & 1u) << p;
+        }
+        double a = 0.0;
+        for (uint64_t f = 0; f < nfree; ++f) {
+            uint64_t c = cb;
+            uint32_t j = 0;
+            for (uint32_t p = 0; p < chunks_log2; ++p)
+                if ((F >> p) & 1ull) c |= ((f >> j++) & 1ull) << p;
+            a += in[c];
+        }
+        out[(uint64_t)s * bin_stride + b] = a;
+    }
+}
+
 // exclusive prefix of chunk sums per slot (in place into cpre) + total
 __global__ __launch_bounds__(256) void chunk_scan_kernel(const double *__restrict__ csum,
                                                          uint32_t chunks,
@@ -1130,6 +1167,20 @@ hipError_t launch_measure_sums(hipStream_t st, const float2 *const *slots, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(measure_finalize_kernel, dim3(n_slots), dim3(256), 0, st, part, chunks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const uint64_t *mq,
+                               uint32_t n_slots, uint32_t n, uint32_t C, double *csum,
+                               uint32_t bin_stride, double *out) {
+    if (n_slots == 0) return hipSuccess;
+    const uint32_t chunks = 1u << (n - C);
+    hipLaunchKernelGGL(chunk_sum_kernel, dim3(chunks, n_slots), dim3(256), 0, st, slots, C, chunks,
+                       csum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_mass_kernel, dim3(n_slots), dim3(256), 0, st, csum, n - C, mq, bin_stride,
+                       out);
     return hipGetLastError();
 }
 
