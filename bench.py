@@ -33,12 +33,13 @@ def _parse():
                          "distinct states")
     ap.add_argument("--cpu-tasks", type=int, default=8,
                     help="tasks in the oracle's bounded CPU sample")
-    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy", "qec"],
+    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy", "qec", "stab"],
                     help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "
                          "tree, 512 leaves, 1024 shots; noisy: 22-qubit 256 trajectories, 1024 "
                          "shots; sweep: gate-pass HBM bandwidth over qubits and sizes; copy: "
                          "5 plain 1 GiB device copies (the reference kernel for HBM counters); "
-                         "qec: 23-qubit repetition code, 64 tasks with mid-circuit measurements")
+                         "qec: 23-qubit repetition code, 64 tasks with mid-circuit measurements; "
+                         "stab: 24-qubit Clifford prefix handed from a tableau to the VQE suffixes")
     return ap.parse_args()
 
 
@@ -105,7 +106,7 @@ def main():
 
     if args.workload != "vqe":
         extra = {"trie": bench_trie, "noisy": bench_noisy, "sweep": bench_sweep,
-                 "copy": bench_copy, "qec": bench_qec}[args.workload]
+                 "copy": bench_copy, "qec": bench_qec, "stab": bench_stab}[args.workload]
         print(json.dumps(extra(args)), flush=True)
         return
 
@@ -426,6 +427,87 @@ def bench_qec(args):
             "dtype": "c64 (fp32 amplitudes, fp64 sums)",
             "data": "synthetic (seeded angles and draws)",
             "config": {"workload": w.name, "qubits": n, "tasks": T, "terms": len(w.terms)}}
+
+
+def bench_stab(args):
+    """Clifford prefix handed from a stabilizer tableau to statevector
+    suffixes (Table II's STAB -> SV row): 24 qubits, a 564-gate Clifford
+    prefix (12 layers of random single-qubit Cliffords and the CNOT
+    ladder), the 64 two-layer HEA suffixes and 50 terms of the VQE
+    configuration. Reuse with the handoff: tableau prefix (host), dense
+    export (one kernel), snapshot, suffix batch. Reuse on statevectors: the
+    prefix as gate passes instead. Direct: every task's prefix and suffix as
+    gate passes."""
+    import numpy as np
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd.planner import fingerprint
+    from workloads import gen
+    w = gen.clifford_prefix_vqe()
+    n, T = w.n, w.n_tasks
+    ctx = B.Ctx(0)
+    ctx.set_option(B.QW_OPT_TILE_BITS, args.tile_bits)
+    prov = fingerprint(n, w.prefix)
+    prefix = B.GateArray(w.prefix)
+    sufs = [B.GateArray(s) for s in w.suffixes]
+    st = B.State(ctx, n, T + 1)
+    slots = list(range(1, T + 1))
+    B.jit_precompile(n, prefix, args.tile_bits)
+    B.jit_precompile_suffix(n, w.suffixes[0], w.terms, args.tile_bits)
+    B.jit_precompile_terms(n, w.terms, args.tile_bits)
+
+    def handoff_prefix():
+        tb = B.Tableau(n)
+        tb.apply(prefix)
+        tb.export(st, 0)
+        tb.free()
+
+    def sv_prefix():
+        st.reset(0, 1)
+        st.apply(0, prefix)
+
+    def reuse(prefix_fn):
+        def step():
+            prefix_fn()
+            snap = st.snapshot(0, prov, B.QW_SNAP_FREEZE)
+            e = B.run_suffix_batch(ctx, [snap] * T, sufs, st, slots, terms=w.terms)
+            snap.free()
+            return e
+        return step
+
+    def direct():
+        st.reset(1, T)
+        for s in slots:
+            st.apply(s, prefix)
+        return B.run_suffix_batch(ctx, None, sufs, st, slots, terms=w.terms)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, r
+
+    t_h, _ = timed(handoff_prefix, 20)
+    t_p, _ = timed(sv_prefix, 20)
+    t_rh, e_h = timed(reuse(handoff_prefix), args.steps)
+    t_rs, e_s = timed(reuse(sv_prefix), args.steps)
+    t_d, e_d = timed(direct, max(1, args.steps // 2))
+    st.free()
+    scale = sum(abs(t[0]) for t in w.terms)
+    return {"metric": "Clifford-prefix VQE tasks/s at 24q (tableau handoff, reuse)",
+            "value": round(T / t_rh, 2), "unit": "tasks/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(t_rh * 1e3, 3), "higher_is_better": True,
+            "sv_prefix_reuse_tasks_per_s": round(T / t_rs, 2), "direct_tasks_per_s": round(T / t_d, 2),
+            "speedup_vs_direct": round(t_d / t_rh, 3),
+            "handoff_ms": round(t_h * 1e3, 3), "sv_prefix_ms": round(t_p * 1e3, 3),
+            "max_expectation_diff_handoff_vs_sv": float(np.max(np.abs(np.asarray(e_h) - np.asarray(e_s))) / scale),
+            "dtype": "c64 (fp32 amplitudes, fp64 accumulation)", "data": "synthetic",
+            "config": {"workload": w.name, "qubits": n, "tasks": T, "prefix_gates": len(w.prefix),
+                       "terms": len(w.terms)}}
 
 
 def cpu_baseline(w, k):

@@ -359,6 +359,38 @@ int qw_mlp_adam(qw_ctx *ctx, float *params, const float *grad, float *m, float *
 int qw_legality_check(const qw_artifact *src, uint32_t target_kind,
                       uint32_t target_backend, char *json_out, uint64_t cap);
 
+/* ------------------------------------------------------------ tableau */
+/* Stabilizer tableau (the STAB rows of Table II): the state of a Clifford
+ * circuit as 2n rows (destabilizers, then stabilizer generators) of X bits,
+ * Z bits and a sign, updated gate by gate by the rules of Aaronson and
+ * Gottesman (Phys. Rev. A 70, 052328, 2004). Host memory only; no device is
+ * needed except for qw_tableau_export.
+ * qw_tableau_create: |0...0> on n_qubits (1..30). */
+typedef struct qw_tableau qw_tableau;
+int qw_tableau_create(uint32_t n_qubits, qw_tableau **out);
+int qw_tableau_free(qw_tableau *tb);
+/* Apply Clifford gates (X Y Z H S SDG CNOT CZ) in order. Another kind gives
+ * QW_E_UNSUPPORTED and leaves the tableau unchanged; bad qubits give
+ * QW_E_INVALID_ARG. */
+int qw_tableau_apply(qw_tableau *tb, const qw_gate *gates, uint64_t n_gates);
+/* The 2n rows: x[i], z[i] (bit q = qubit q; X where only x is set, Z where
+ * only z, Y where both) and sign r[i] (1 = minus); rows n..2n-1 are the
+ * stabilizer generators. Host arrays of 2n entries each. */
+int qw_tableau_rows(const qw_tableau *tb, uint64_t *x, uint64_t *z, uint8_t *r);
+/* Artifact record of the tableau as a boundary state (Sec. IV-B: kind
+ * TABLEAU, exactness EXACT, stabilizer-only backend family), for the
+ * legality check of a continuation. */
+int qw_tableau_artifact(const qw_tableau *tb, const uint8_t provenance[32], qw_artifact *out);
+/* qw_tableau_export: the STAB -> SV conversion of Table II (exact): writes
+ * the tableau's state into slot `slot` of `st` (same qubit count; slot not
+ * frozen) as 2^n complex64 amplitudes. With the generators in reduced
+ * echelon form on their X bits (r of them X-type) and x0 a basis state of
+ * the support, the state is 2^{-r/2} sum_c (prod_{i: c_i} g_i)|x0>, so every
+ * amplitude is 0 or 2^{-r/2} times a power of i; the global phase makes the
+ * amplitude at x0 real and positive. One kernel, enqueued on the state's
+ * context stream. */
+int qw_tableau_export(const qw_tableau *tb, qw_state *st, uint32_t slot);
+
 /* Pass plan the library would execute for `gates` on n qubits, as JSON
  * (passes, local bit sets and fused operations), for inspection. No device
  * is needed. Returns QW_E_INVALID_ARG (message in json_out) for bad gates. */

@@ -56,7 +56,8 @@ EXPORTED = (
     "qw_expect_pauli", "qw_sample", "qw_legality_check", "qw_plan_describe",
     "qw_mlp_workspace_floats", "qw_mlp_forward", "qw_mlp_backward", "qw_mlp_adam",
     "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_precompile_suffix",
-    "qw_jit_stats", "qw_version", "qw_outcomes",
+    "qw_jit_stats", "qw_version", "qw_outcomes", "qw_tableau_create", "qw_tableau_free",
+    "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
 )
 
 
@@ -162,6 +163,12 @@ def lib() -> ctypes.CDLL:
                                      ctypes.c_char_p, u64], i32),
         "qw_jit_precompile_suffix": ([u32, ctypes.POINTER(QwGate), u64, ctypes.POINTER(u64),
                                       ctypes.POINTER(u64), u32, u32, ctypes.c_char_p, u64], i32),
+        "qw_tableau_create": ([u32, ctypes.POINTER(ctypes.c_void_p)], i32),
+        "qw_tableau_free": ([ctypes.c_void_p], i32),
+        "qw_tableau_apply": ([ctypes.c_void_p, ctypes.POINTER(QwGate), u64], i32),
+        "qw_tableau_rows": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], i32),
+        "qw_tableau_artifact": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(QwArtifact)], i32),
+        "qw_tableau_export": ([ctypes.c_void_p, ctypes.c_void_p, u32], i32),
         "qw_outcomes": ([ctypes.c_void_p, ctypes.c_void_p, u64, ctypes.POINTER(u64)], i32),
         "qw_jit_stats": ([ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)],
                          i32),
@@ -318,6 +325,58 @@ def outcomes(ctx) -> "np.ndarray":
     if cnt.value:
         ctx.check(lib().qw_outcomes(ctx.h, ctypes.c_void_p(out.ctypes.data), cnt.value, ctypes.byref(cnt)))
     return out
+
+
+class Tableau:
+    """qw_tableau: stabilizer tableau of a Clifford circuit (host memory)."""
+
+    def __init__(self, n: int):
+        h = ctypes.c_void_p()
+        rc = lib().qw_tableau_create(n, ctypes.byref(h))
+        if rc:
+            raise QwError(rc, "qw_tableau_create")
+        self.h, self.n = h, n
+
+    def apply(self, gates):
+        arr = gate_array(gates)
+        rc = lib().qw_tableau_apply(self.h, arr.ptr, len(arr))
+        if rc:
+            raise QwError(rc, "qw_tableau_apply: non-Clifford or bad gate")
+
+    def rows(self):
+        """(x, z, r) arrays of the 2n rows (stabilizer generators last)."""
+        import numpy as np
+        x = np.zeros(2 * self.n, dtype=np.uint64)
+        z = np.zeros(2 * self.n, dtype=np.uint64)
+        r = np.zeros(2 * self.n, dtype=np.uint8)
+        rc = lib().qw_tableau_rows(self.h, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(z.ctypes.data),
+                                   ctypes.c_void_p(r.ctypes.data))
+        if rc:
+            raise QwError(rc, "qw_tableau_rows")
+        return x, z, r
+
+    def artifact(self, provenance: bytes) -> dict:
+        a = QwArtifact()
+        rc = lib().qw_tableau_artifact(self.h, _prov(provenance), ctypes.byref(a))
+        if rc:
+            raise QwError(rc, "qw_tableau_artifact")
+        return {"kind": a.kind, "exactness": a.exactness, "backend": a.backend,
+                "n_qubits": a.n_qubits, "bytes": a.bytes, "provenance": bytes(a.provenance)}
+
+    def export(self, st: "State", slot: int):
+        """qw_tableau_export into slot `slot` of `st`."""
+        st.ctx.check(lib().qw_tableau_export(self.h, st.h, slot))
+
+    def free(self):
+        if self.h:
+            lib().qw_tableau_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Ctx:

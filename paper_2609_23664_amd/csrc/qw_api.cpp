@@ -1641,6 +1641,95 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count, uint64_t seed,
     return QW_OK;
 }
 
+struct qw_tableau {
+    qw::Tableau t;
+    explicit qw_tableau(int n) : t(n) {}
+};
+
+int qw_tableau_create(uint32_t n_qubits, qw_tableau **out) {
+    if (!out || n_qubits < 1 || n_qubits > 30) return QW_E_INVALID_ARG;
+    *out = new qw_tableau((int)n_qubits);
+    return QW_OK;
+}
+
+int qw_tableau_free(qw_tableau *tb) {
+    if (!tb) return QW_E_INVALID_ARG;
+    delete tb;
+    return QW_OK;
+}
+
+int qw_tableau_apply(qw_tableau *tb, const qw_gate *gates, uint64_t n_gates) {
+    if (!tb || (n_gates && !gates)) return QW_E_INVALID_ARG;
+    qw::Tableau t = tb->t;  // unchanged on error
+    const std::string e = t.apply(gates, n_gates);
+    if (!e.empty()) return e.find("Clifford") != std::string::npos ? QW_E_UNSUPPORTED : QW_E_INVALID_ARG;
+    tb->t = std::move(t);
+    return QW_OK;
+}
+
+int qw_tableau_rows(const qw_tableau *tb, uint64_t *x, uint64_t *z, uint8_t *r) {
+    if (!tb || !x || !z || !r) return QW_E_INVALID_ARG;
+    for (int i = 0; i < 2 * tb->t.n; ++i) {
+        x[i] = tb->t.x[i];
+        z[i] = tb->t.z[i];
+        r[i] = tb->t.r[i];
+    }
+    return QW_OK;
+}
+
+int qw_tableau_artifact(const qw_tableau *tb, const uint8_t provenance[32], qw_artifact *out) {
+    if (!tb || !provenance || !out) return QW_E_INVALID_ARG;
+    qw_artifact a{};
+    a.kind = QW_KIND_TABLEAU;
+    a.exactness = QW_EXACT;
+    a.backend = QW_BACKEND_STAB_ONLY;
+    a.n_qubits = (uint32_t)tb->t.n;
+    a.bytes = (uint64_t)tb->t.n * 2 * (2 * sizeof(uint64_t) + 1);
+    std::memcpy(a.provenance, provenance, 32);
+    *out = a;
+    return QW_OK;
+}
+
+int qw_tableau_export(const qw_tableau *tb, qw_state *st, uint32_t slot) {
+    if (!tb || !st) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = st->ctx;
+    if (slot >= st->n_slots) return fail(ctx, QW_E_INVALID_ARG, "slot out of range");
+    if (st->frozen[slot]) return fail(ctx, QW_E_INVALID_ARG, "slot is frozen by a snapshot");
+    if ((uint32_t)tb->t.n != st->n) return fail(ctx, QW_E_INVALID_ARG, "tableau and state qubit counts differ");
+    // the conversion rule of Table II (tableau -> statevector, exact export)
+    qw_artifact a{};
+    uint8_t prov[32] = {0};
+    qw_tableau_artifact(tb, prov, &a);
+    std::string js;
+    if (!legal(a, QW_KIND_STATEVECTOR, QW_BACKEND_SV, &js)) return fail(ctx, QW_E_REFUSED, js);
+    const qw::StabExport e = tb->t.export_form();
+    const uint32_t r = (uint32_t)e.x.size();
+    std::vector<uint8_t> blob(r * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) + 64);
+    uint64_t *hx = reinterpret_cast<uint64_t *>(blob.data());
+    uint64_t *hz = hx + r;
+    uint32_t *hp = reinterpret_cast<uint32_t *>(hz + r);
+    uint32_t *hv = hp + r;
+    for (uint32_t i = 0; i < r; ++i) {
+        hx[i] = e.x[i];
+        hz[i] = e.z[i];
+        hp[i] = e.phase[i];
+        hv[i] = e.pivot[i];
+    }
+    int rc = upload(ctx, blob);
+    if (rc) return rc;
+    const char *d = static_cast<const char *>(ctx->plan.p);
+    const uint64_t *dx = reinterpret_cast<const uint64_t *>(d);
+    const uint64_t *dz = dx + r;
+    const uint32_t *dp = reinterpret_cast<const uint32_t *>(dz + r);
+    const uint32_t *dv = dp + r;
+    const double nd = std::pow(2.0, -0.5 * (double)r);
+    ProfScope ps(ctx, 3, (double)(8ull << st->n));
+    hipError_t er = launch_stab_export(ctx->stream, reinterpret_cast<float2 *>(slot_ptr(st, slot)), st->n, e.x0, r,
+                                       dx, dz, dp, dv, (float)nd);
+    if (er != hipSuccess) return hip_fail(ctx, er, "export launch");
+    return QW_OK;
+}
+
 int qw_legality_check(const qw_artifact *src, uint32_t target_kind, uint32_t target_backend,
                       char *json_out, uint64_t cap) {
     if (!src) return QW_E_INVALID_ARG;

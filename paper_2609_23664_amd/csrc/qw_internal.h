@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "qw_desc.h"
+#include "../../include/qw.h"
 
 namespace qw {
 
@@ -79,6 +80,30 @@ struct RedPlan {
 // I/O layout, local bits 0, 7, 8, 9).
 RedPlan plan_reduce_group(int n, int m, const TermGroup &g, const uint64_t *x,
                           const uint64_t *z, const uint8_t *diag_reg = nullptr);
+
+// Stabilizer tableau (qw_tableau.cpp): rows (x, z, r) of the destabilizers
+// (0..n-1) and stabilizer generators (n..2n-1), n <= 63.
+struct StabExport {
+    uint64_t x0 = 0;                 // a basis state of the support
+    std::vector<uint64_t> x, z;      // X-type generators in reduced echelon form
+    std::vector<uint8_t> phase;      // their i-powers: 2 r + |x & z| (mod 4)
+    std::vector<uint32_t> pivot;     // X pivot qubit of each
+};
+struct Tableau {
+    int n = 0;
+    std::vector<uint64_t> x, z;
+    std::vector<uint8_t> r;
+    explicit Tableau(int n_);
+    void rowsum(int h, int i);
+    void h(int a);
+    void s(int a);
+    void cx(int a, int b);
+    void pauli(uint64_t px, uint64_t pz);
+    // Applies Clifford gates (X Y Z H S SDG CNOT CZ); "" or an error.
+    std::string apply(const qw_gate *g, uint64_t count);
+    // The data of the dense export.
+    StabExport export_form() const;
+};
 
 // bit helpers
 inline uint64_t pdep64(uint64_t v, uint64_t mask) {

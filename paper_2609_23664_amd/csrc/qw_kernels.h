@@ -48,6 +48,12 @@ hipError_t launch_measure_sums(hipStream_t st, const float2 *const *slots, const
 hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const uint64_t *mq,
                                uint32_t n_slots, uint32_t n, uint32_t C, double *csum,
                                uint32_t bin_stride, double *out);
+// Dense export of a stabilizer state into psi (2^n amplitudes): x0, r X-type
+// generators (device arrays xs, zs, ph = i-power, piv = pivot qubit), norm =
+// 2^{-r/2}. r <= 64.
+hipError_t launch_stab_export(hipStream_t st, float2 *psi, uint32_t n, uint64_t x0, uint32_t r,
+                              const uint64_t *xs, const uint64_t *zs, const uint32_t *ph,
+                              const uint32_t *piv, float norm);
 hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
                          uint32_t n, double *csum, double *cpre, double *total, uint64_t seed,
                          uint64_t task_base, uint32_t shots, uint32_t *out);

@@ -19,6 +19,7 @@
 // depend on how many tasks share a launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "qw_internal.h"
@@ -927,6 +928,50 @@ __global__ __launch_bounds__(256) void bin_mass_kernel(const double *__restrict_
     }
 }
 
+// Dense export of a stabilizer state (STAB -> SV): amplitude k is
+// 2^{-r/2} i^e when k = x0 ^ (sum of the X parts x_i of the generators whose
+// pivot bit p_i is set in k ^ x0), e collecting each such generator's phase
+// (ph_i, then (-1)^{z_i . cur} as it acts on the current basis state cur in
+// increasing i), else 0.
+__global__ __launch_bounds__(256) void stab_export_kernel(float2 *__restrict__ psi, uint32_t n,
+                                                          uint64_t x0, uint32_t r,
+                                                          const uint64_t *__restrict__ xs,
+                                                          const uint64_t *__restrict__ zs,
+                                                          const uint32_t *__restrict__ ph,
+                                                          const uint32_t *__restrict__ piv,
+                                                          float norm) {
+    __shared__ uint64_t sx[64], sz[64];
+    __shared__ uint32_t sp[64], sv[64];
+    for (uint32_t i = threadIdx.x; i < r; i += 256) {
+        sx[i] = xs[i];
+        sz[i] = zs[i];
+        sp[i] = ph[i];
+        sv[i] = piv[i];
+    }
+    __syncthreads();
+    const uint64_t total = 1ull << n;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (uint64_t)gridDim.x * 256) {
+        const uint64_t d = k ^ x0;
+        uint64_t cur = x0;
+        uint32_t e = 0;
+        for (uint32_t i = 0; i < r; ++i)
+            if ((d >> sv[i]) & 1ull) {
+                e += sp[i] + 2u * (uint32_t)__popcll(sz[i] & cur);
+                cur ^= sx[i];
+            }
+        float2 a = make_float2(0.0f, 0.0f);
+        if (cur == k) {
+            switch (e & 3u) {
+            case 0: a = make_float2(norm, 0.0f); break;
+            case 1: a = make_float2(0.0f, norm); break;
+            case 2: a = make_float2(-norm, 0.0f); break;
+            default: a = make_float2(0.0f, -norm); break;
+            }
+        }
+        psi[k] = a;
+    }
+}
+
 // exclusive prefix of chunk sums per slot (in place into cpre) + total
 __global__ __launch_bounds__(256) void chunk_scan_kernel(const double *__restrict__ csum,
                                                          uint32_t chunks,
@@ -1181,6 +1226,16 @@ hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bin_mass_kernel, dim3(n_slots), dim3(256), 0, st, csum, n - C, mq, bin_stride,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stab_export(hipStream_t st, float2 *psi, uint32_t n, uint64_t x0, uint32_t r,
+                              const uint64_t *xs, const uint64_t *zs, const uint32_t *ph,
+                              const uint32_t *piv, float norm) {
+    const uint64_t total = 1ull << n;
+    const uint64_t blocks = std::min<uint64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(stab_export_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, psi, n, x0, r, xs, zs,
+                       ph, piv, norm);
     return hipGetLastError();
 }
 

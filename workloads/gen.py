@@ -391,3 +391,22 @@ def qec_repetition(d: int = 12, n_tasks: int = 64, seed: int = 606) -> Workload:
     terms = [(1.0, 0, (1 << i) | (1 << (i + 1))) for i in range(d - 1)] + [(1.0, 0, 1)]
     return Workload(name=f"qec_repetition_d{d}_{n}q_{n_tasks}t", n=n, prefix=prefix,
                     suffixes=suffixes, terms=terms)
+
+
+CLIFFORD_1Q = ("H", "S", "SDG", "X", "Y", "Z")
+
+
+def clifford_prefix_vqe(n: int = 24, layers: int = 12, n_tasks: int = 64, seed: int = 707) -> Workload:
+    """A Clifford prefix (layers of one random single-qubit Clifford per
+    qubit, then the CNOT ladder) shared by n_tasks tasks whose suffixes and
+    terms are those of the 24-qubit VQE configuration (2 HEA layers, 50
+    Pauli terms)."""
+    g = rng(seed, 0)
+    prefix: List[Gate] = []
+    for _ in range(layers):
+        for q in range(n):
+            prefix.append((CLIFFORD_1Q[int(g.integers(len(CLIFFORD_1Q)))], (q,), 0.0))
+        prefix += [("CNOT", (q, q + 1), 0.0) for q in range(n - 1)]
+    base = config2()
+    return Workload(name=f"clifford_prefix_{n}q_{layers}l_{n_tasks}t", n=n, prefix=prefix,
+                    suffixes=[list(s) for s in base.suffixes[:n_tasks]], terms=list(base.terms))
