@@ -322,6 +322,45 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
               uint64_t seed, uint64_t task_base, uint32_t shots,
               uint32_t *out, int out_is_host);
 
+/* ------------------------------------------------------------ graphs
+ * A workload's device work recorded once and replayed as one HIP graph
+ * launch: the batched suffix scheduling of Sec. III-A (tasks that branch
+ * from one snapshot or from a tree of snapshots, Fig. 1) without the host
+ * planning, plan uploads and per-pass launches of every repetition.
+ *
+ * qw_graph_begin: the calls that follow on this context (qw_state_alloc,
+ *   qw_state_reset, qw_apply_prefix, qw_snapshot, qw_run_suffix_batch,
+ *   qw_expect_pauli, qw_sample, qw_tableau_export, the qw_mlp_* calls) are
+ *   planned, checked (legality gates included) and their plans uploaded
+ *   now, but their device work is recorded instead of run. The call first
+ *   synchronises the context's stream. While recording, these return
+ *   QW_E_UNSUPPORTED: host outputs (out_is_host = 1 or an epilogue with
+ *   out_is_host = 1), an expectation with no terms, MEASURE and RESET gates
+ *   (their decisions need the host), qw_ctx_sync, qw_ctx_kernel_stats,
+ *   qw_snapshot_free, qw_state_free, qw_graph_launch and qw_graph_free.
+ *   QW_OPT_PROFILE timing is suspended. A call that fails while recording
+ *   leaves the recording open; qw_graph_end then reports the failure.
+ * qw_graph_end: closes the recording and returns the instantiated graph in
+ *   *out. The graph owns the plan records and scratch buffers its nodes
+ *   read; it does NOT own the states, snapshots and device outputs named in
+ *   the recorded calls: the caller keeps them allocated (and frozen slots
+ *   frozen) until qw_graph_free. On failure *out is NULL and the recording
+ *   is closed.
+ * qw_graph_launch: enqueues one replay on the context's stream (asynchronous).
+ *   A replay performs exactly the recorded device work, in order, on the
+ *   recorded buffers, so its results are bitwise those of the recorded calls
+ *   run directly. Replays and direct calls of one context are ordered by
+ *   its stream; they share no buffer except the caller's states and outputs.
+ * qw_graph_nodes: number of nodes (kernels and copies) in the graph.
+ * qw_graph_free: synchronises the context's stream and releases the graph
+ *   and its buffers. */
+typedef struct qw_graph qw_graph;
+int qw_graph_begin(qw_ctx *ctx);
+int qw_graph_end(qw_ctx *ctx, qw_graph **out);
+int qw_graph_launch(qw_graph *g);
+int qw_graph_nodes(const qw_graph *g, uint64_t *nodes);
+int qw_graph_free(qw_graph *g);
+
 /* ------------------------------------------------------------ learned cost model
  * A 3-layer perceptron predicting (log direct time, log reuse time) from
  * QW_MLP_IN planner features, used by the planner's reuse decision (with

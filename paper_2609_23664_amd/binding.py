@@ -58,6 +58,7 @@ EXPORTED = (
     "qw_plan_cost", "qw_jit_precompile", "qw_jit_precompile_terms", "qw_jit_precompile_suffix",
     "qw_jit_stats", "qw_version", "qw_outcomes", "qw_tableau_create", "qw_tableau_free",
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
+    "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
 )
 
 
@@ -173,6 +174,11 @@ def lib() -> ctypes.CDLL:
         "qw_jit_stats": ([ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)],
                          i32),
         "qw_version": ([], ctypes.c_char_p),
+        "qw_graph_begin": ([vp], i32),
+        "qw_graph_end": ([vp, ctypes.POINTER(ctypes.c_void_p)], i32),
+        "qw_graph_launch": ([vp], i32),
+        "qw_graph_nodes": ([vp, ctypes.POINTER(u64)], i32),
+        "qw_graph_free": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -417,6 +423,16 @@ class Ctx:
                                              ctypes.byref(by), 1 if reset else 0))
         return int(n.value), float(ms.value), float(by.value)
 
+    def begin_graph(self):
+        """qw_graph_begin: the following calls' device work is recorded."""
+        self.check(lib().qw_graph_begin(self.h))
+
+    def end_graph(self) -> "Graph":
+        """qw_graph_end: the recorded work as a replayable Graph."""
+        g = ctypes.c_void_p()
+        self.check(lib().qw_graph_end(self.h, ctypes.byref(g)))
+        return Graph(self, g)
+
     def close(self):
         if self.h:
             lib().qw_ctx_destroy(self.h)
@@ -453,17 +469,31 @@ class State:
                  parent: "Optional[Snapshot]" = None) -> "Snapshot":
         return Snapshot(self, slot, provenance, mode, parent)
 
-    def expect(self, first: int, count: int, terms) -> List[float]:
+    def expect(self, first: int, count: int, terms, out_dev=None) -> Optional[List[float]]:
+        """qw_expect_pauli. With `out_dev` (a float64 device tensor of
+        `count` elements) the values go there and nothing is returned."""
         x = _u64_array([t[1] for t in terms])
         z = _u64_array([t[2] for t in terms])
         c = _f64_array([t[0] for t in terms])
+        if out_dev is not None:
+            _check_dev(out_dev, self.ctx.torch.float64, count)
+            self.ctx.check(lib().qw_expect_pauli(self.h, first, count, x, z, c, len(terms),
+                                                 ctypes.c_void_p(out_dev.data_ptr()), 0))
+            return None
         out = (ctypes.c_double * max(1, count))()
         self.ctx.check(lib().qw_expect_pauli(self.h, first, count, x, z, c, len(terms),
                                              ctypes.cast(out, ctypes.c_void_p), 1))
         return [out[i] for i in range(count)]
 
-    def sample(self, first: int, count: int, seed: int, task_base: int, shots: int):
+    def sample(self, first: int, count: int, seed: int, task_base: int, shots: int, out_dev=None):
+        """qw_sample. With `out_dev` (an int32 device tensor of count * shots
+        elements, read as uint32) the indices go there and nothing is returned."""
         import numpy as np
+        if out_dev is not None:
+            _check_dev(out_dev, self.ctx.torch.int32, count * shots)
+            self.ctx.check(lib().qw_sample(self.h, first, count, seed, task_base, shots,
+                                           ctypes.c_void_p(out_dev.data_ptr()), 0))
+            return None
         out = np.empty(count * shots, dtype=np.uint32)
         self.ctx.check(lib().qw_sample(self.h, first, count, seed, task_base, shots,
                                        ctypes.c_void_p(out.ctypes.data), 1))
@@ -526,10 +556,47 @@ class Snapshot:
             pass
 
 
+def _check_dev(t, dtype, numel):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"expected a contiguous {dtype} device tensor of >= {numel} elements")
+
+
+class Graph:
+    """A recorded workload (qw_graph_*): replay() enqueues it once."""
+
+    def __init__(self, ctx: Ctx, h):
+        self.ctx, self.h = ctx, h
+        self.keep = []  # objects the recorded calls reference (states, outputs)
+
+    def replay(self):
+        self.ctx.check(lib().qw_graph_launch(self.h))
+
+    def nodes(self) -> int:
+        n = ctypes.c_uint64()
+        self.ctx.check(lib().qw_graph_nodes(self.h, ctypes.byref(n)))
+        return int(n.value)
+
+    def free(self):
+        if self.h:
+            rc = lib().qw_graph_free(self.h)
+            self.h = None
+            self.ctx.check(rc)
+        self.keep = []
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().qw_graph_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
 def run_suffix_batch(ctx: Ctx, srcs: Sequence[Optional[Snapshot]], suffixes, dst: State,
                      dst_slots: Sequence[int], expect_provs: Sequence[bytes] = None,
-                     terms=None):
-    """qw_run_suffix_batch; returns the per-task expectations if `terms`."""
+                     terms=None, out_dev=None):
+    """qw_run_suffix_batch; returns the per-task expectations if `terms`
+    (or writes them to `out_dev`, a float64 device tensor, and returns None)."""
     nt = len(suffixes)
     arrs = [gate_array(s) for s in suffixes]
     tasks = (QwTask * max(1, nt))()
@@ -553,12 +620,20 @@ def run_suffix_batch(ctx: Ctx, srcs: Sequence[Optional[Snapshot]], suffixes, dst
         x = _u64_array([t[1] for t in terms])
         z = _u64_array([t[2] for t in terms])
         c = _f64_array([t[0] for t in terms])
-        out = (ctypes.c_double * max(1, nt))()
         keep += [x, z, c]
-        red = QwReduce(ctypes.cast(x, ctypes.POINTER(ctypes.c_uint64)),
-                       ctypes.cast(z, ctypes.POINTER(ctypes.c_uint64)),
-                       ctypes.cast(c, ctypes.POINTER(ctypes.c_double)),
-                       len(terms), 1, ctypes.cast(out, ctypes.POINTER(ctypes.c_double)))
+        if out_dev is not None:
+            _check_dev(out_dev, ctx.torch.float64, nt)
+            red = QwReduce(ctypes.cast(x, ctypes.POINTER(ctypes.c_uint64)),
+                           ctypes.cast(z, ctypes.POINTER(ctypes.c_uint64)),
+                           ctypes.cast(c, ctypes.POINTER(ctypes.c_double)),
+                           len(terms), 0, ctypes.cast(ctypes.c_void_p(out_dev.data_ptr()),
+                                                      ctypes.POINTER(ctypes.c_double)))
+        else:
+            out = (ctypes.c_double * max(1, nt))()
+            red = QwReduce(ctypes.cast(x, ctypes.POINTER(ctypes.c_uint64)),
+                           ctypes.cast(z, ctypes.POINTER(ctypes.c_uint64)),
+                           ctypes.cast(c, ctypes.POINTER(ctypes.c_double)),
+                           len(terms), 1, ctypes.cast(out, ctypes.POINTER(ctypes.c_double)))
     rc = lib().qw_run_suffix_batch(ctx.h, src_arr, tasks, nt, dst.h,
                                    ctypes.byref(red) if red is not None else None)
     ctx.check(rc)

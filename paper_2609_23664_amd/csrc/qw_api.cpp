@@ -52,7 +52,27 @@ struct KStats {
     double bytes = 0.0;
 };
 
+// State of a context while it records a graph (qw_graph_begin .. end): the
+// device work of the calls goes into a stream capture, and every device
+// buffer those calls use is kept for the graph's lifetime.
+struct GraphRec {
+    hipStream_t cap = nullptr;    // captured stream (non-blocking, default priority)
+    hipStream_t up = nullptr;     // plan uploads, synchronous, outside the capture
+    hipStream_t saved_stream = nullptr;
+    DevBuf saved_plan, saved_scratch, saved_pingpong, saved_meas;
+    std::vector<void *> owned;    // buffers replaced during the recording
+    bool plan_used = false;       // ctx->plan already holds an uploaded blob
+};
+
 }  // namespace
+
+struct qw_graph {
+    qw_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> owned;  // plan blobs and scratch the recorded nodes read
+    uint64_t nodes = 0;
+};
 
 struct qw_ctx {
     int device = 0;
@@ -81,6 +101,7 @@ struct qw_ctx {
     KStats stats[4];
     std::unordered_map<uint64_t, std::vector<PlanEntry>> plan_cache;
     size_t plan_cache_entries = 0;
+    GraphRec *rec = nullptr;  // non-null while a graph is being recorded
 };
 
 struct qw_state {
@@ -110,6 +131,13 @@ int fail(qw_ctx *ctx, int code, const std::string &msg) {
     return code;
 }
 
+// Calls that wait for the device or free memory cannot run while the
+// context records a graph.
+int recording_unsupported(qw_ctx *ctx, const char *what) {
+    return fail(ctx, QW_E_UNSUPPORTED,
+                std::string(what) + " is not available while a graph is being recorded");
+}
+
 int hip_fail(qw_ctx *ctx, hipError_t e, const char *what) {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     return fail(ctx, e == hipErrorOutOfMemory ? QW_E_OOM : QW_E_HIP, m);
@@ -121,7 +149,27 @@ int hip_fail(qw_ctx *ctx, hipError_t e, const char *what) {
         if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
     } while (0)
 
+// While recording, a buffer is never freed or rewritten behind the graph's
+// back: a buffer that is too small (or a plan buffer that already holds an
+// uploaded blob) is set aside for the graph and replaced by a new one.
+int ensure_recording(qw_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
+    const bool is_plan = &b == &ctx->plan;
+    if (b.cap >= bytes && !(is_plan && ctx->rec->plan_used)) return QW_OK;
+    if (b.p) ctx->rec->owned.push_back(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t want = (std::max<size_t>(bytes, 256) + 4095) & ~size_t(4095);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    b.p = p;
+    b.cap = want;
+    if (is_plan) ctx->rec->plan_used = false;
+    return QW_OK;
+}
+
 int ensure(qw_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
+    if (ctx->rec) return ensure_recording(ctx, b, bytes, what);
     if (b.cap >= bytes) return QW_OK;
     size_t want = std::max(bytes, b.cap * 2);
     want = (want + 4095) & ~size_t(4095);
@@ -144,6 +192,16 @@ int upload(qw_ctx *ctx, const std::vector<uint8_t> &blob) {
     if (blob.empty()) return QW_OK;
     int rc = ensure(ctx, ctx->plan, blob.size(), "plan buffer");
     if (rc) return rc;
+    if (ctx->rec) {
+        // recording: the blob is copied now, once, into a buffer the graph
+        // keeps (its nodes read it on every replay)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->plan.p, blob.data(), blob.size(), hipMemcpyHostToDevice,
+                                    ctx->rec->up),
+                "plan upload (recording)");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->rec->up), "plan upload (recording)");
+        ctx->rec->plan_used = true;
+        return QW_OK;
+    }
     // the previous copy out of the staging buffer must have completed
     HIP_TRY(ctx, hipEventSynchronize(ctx->staging_ev), "staging wait");
     if (ctx->staging_cap < blob.size()) {
@@ -189,12 +247,12 @@ struct ProfScope {
     double bytes;
     hipEvent_t e0 = nullptr;
     ProfScope(qw_ctx *c, int k, double b) : ctx(c), kind(k), bytes(b) {
-        if (!ctx->profile) return;
+        if (!ctx->profile || ctx->rec) return;
         e0 = get_event(ctx);
         if (e0) hipEventRecord(e0, ctx->stream);
     }
     ~ProfScope() {
-        if (!ctx->profile || !e0) return;
+        if (!ctx->profile || ctx->rec || !e0) return;
         hipEvent_t e1 = get_event(ctx);
         if (!e1) return;
         hipEventRecord(e1, ctx->stream);
@@ -447,6 +505,10 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         for (Exec &e : ex) cnt += has_relabel(*e.planp);
         if (cnt) {
             const size_t want = (size_t)(cnt * state_bytes);
+            if (ctx->rec && ctx->pingpong.cap < want) {
+                int rc0 = ensure_recording(ctx, ctx->pingpong, want, "second state buffers");
+                if (rc0) return rc0;
+            }
             if (ctx->pingpong.cap < want) {
                 if (ctx->pingpong.p) {
                     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync before regrow");
@@ -796,6 +858,8 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     for (uint32_t j = 0; j < n_terms; ++j)
         if ((x[j] & ~full) || (z[j] & ~full))
             return fail(ctx, QW_E_INVALID_ARG, "Pauli mask has bits >= n");
+    if (ctx->rec && (out_is_host || n_terms == 0))
+        return recording_unsupported(ctx, out_is_host ? "a host output" : "an empty term list");
     if (n_terms == 0) {
         std::vector<double> zero(ns, 0.0);
         if (out_is_host) {
@@ -1249,6 +1313,11 @@ int qw_ctx_create(int device, void *hip_stream, qw_ctx **out) {
 
 int qw_ctx_destroy(qw_ctx *ctx) {
     if (!ctx) return QW_E_INVALID_ARG;
+    if (ctx->rec) {
+        qw_graph *g = nullptr;
+        (void)qw_graph_end(ctx, &g);
+        if (g) (void)qw_graph_free(g);
+    }
     hipStreamSynchronize(ctx->stream);
     for (ProfRec &r : ctx->prof) {
         hipEventDestroy(r.e0);
@@ -1269,6 +1338,7 @@ const char *qw_last_error(const qw_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 
 int qw_ctx_sync(qw_ctx *ctx) {
     if (!ctx) return QW_E_INVALID_ARG;
+    if (ctx->rec) return recording_unsupported(ctx, "qw_ctx_sync");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
     return QW_OK;
 }
@@ -1304,6 +1374,7 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
 int qw_ctx_kernel_stats(qw_ctx *ctx, int kernel, uint64_t *launches, double *total_ms,
                         double *total_bytes, int reset) {
     if (!ctx || kernel < 0 || kernel > 3) return QW_E_INVALID_ARG;
+    if (ctx->rec) return recording_unsupported(ctx, "qw_ctx_kernel_stats");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
     for (ProfRec &r : ctx->prof) {
         float ms = 0.0f;
@@ -1365,6 +1436,7 @@ int qw_state_alloc(qw_ctx *ctx, uint32_t n, uint32_t n_slots, void *dev_buf,
 
 int qw_state_free(qw_state *st) {
     if (!st) return QW_E_INVALID_ARG;
+    if (st->ctx->rec) return recording_unsupported(st->ctx, "qw_state_free");
     for (uint32_t f : st->frozen)
         if (f) return fail(st->ctx, QW_E_INVALID_ARG, "state has frozen slots (free the snapshots first)");
     if (st->owned) {
@@ -1400,6 +1472,7 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
     if (n_gates && !gates) return fail(ctx, QW_E_INVALID_ARG, "gates == NULL");
     ctx->outcomes.clear();
     if (has_measure(gates, n_gates)) {
+        if (ctx->rec) return recording_unsupported(ctx, "a mid-circuit measurement");
         std::vector<MeasTask> mt(1);
         mt[0].rest.assign(gates, gates + n_gates);
         mt[0].dst = slot_ptr(st, slot);
@@ -1463,6 +1536,7 @@ int qw_snapshot(qw_state *st, uint32_t slot, const uint8_t provenance[32], int m
 
 int qw_snapshot_free(qw_snap *s) {
     if (!s) return QW_E_INVALID_ARG;
+    if (s->ctx->rec) return recording_unsupported(s->ctx, "qw_snapshot_free");
     if (s->fstate && s->fstate->frozen[s->fslot] > 0) s->fstate->frozen[s->fslot] -= 1;
     if (s->owned) {
         hipStreamSynchronize(s->ctx->stream);
@@ -1534,6 +1608,8 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         if (tasks[k].n_gates && !tasks[k].gates) return fail(ctx, QW_E_INVALID_ARG, "task gates == NULL");
         measured = has_measure(tasks[k].gates, tasks[k].n_gates);
     }
+    if (ctx->rec && measured) return recording_unsupported(ctx, "a mid-circuit measurement");
+    if (ctx->rec && epi && epi->out_is_host) return recording_unsupported(ctx, "a host output");
     if (measured) {
         // segments between measurements; the expectations after the last one
         std::vector<MeasTask> mt(n_tasks);
@@ -1608,6 +1684,7 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count, uint64_t seed,
     if (!slot_ok(st, first, count)) return fail(ctx, QW_E_INVALID_ARG, "slot range out of bounds");
     if (count == 0 || shots == 0) return QW_OK;
     if (!out) return fail(ctx, QW_E_INVALID_ARG, "out is NULL");
+    if (ctx->rec && out_is_host) return recording_unsupported(ctx, "a host output");
     const uint32_t n = st->n;
     const uint32_t C = sample_chunk_bits(n);
     const uint64_t chunks = 1ull << (n - C);
@@ -1982,6 +2059,131 @@ int qw_plan_describe(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32_
     }
     if (!e.empty()) return QW_E_INVALID_ARG;
     return js.size() + 1 > cap ? QW_E_INVALID_ARG : QW_OK;
+}
+
+// ------------------------------------------------------------ graphs
+namespace {
+
+// Leave recording mode: the capture ends, the context gets its own buffers
+// and stream back, and the buffers of the recording are returned.
+void end_recording(qw_ctx *ctx, hipGraph_t *graph, std::vector<void *> *owned) {
+    GraphRec *r = ctx->rec;
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(r->cap, &gr);
+    if (e != hipSuccess) gr = nullptr;
+    *graph = gr;
+    *owned = std::move(r->owned);
+    for (DevBuf *b : {&ctx->plan, &ctx->scratch, &ctx->pingpong, &ctx->meas})
+        if (b->p) owned->push_back(b->p);
+    ctx->plan = r->saved_plan;
+    ctx->scratch = r->saved_scratch;
+    ctx->pingpong = r->saved_pingpong;
+    ctx->meas = r->saved_meas;
+    ctx->stream = r->saved_stream;
+    (void)hipStreamDestroy(r->cap);
+    (void)hipStreamDestroy(r->up);
+    delete r;
+    ctx->rec = nullptr;
+}
+
+void free_owned(std::vector<void *> &owned) {
+    for (void *p : owned) (void)hipFree(p);
+    owned.clear();
+}
+
+}  // namespace
+
+int qw_graph_begin(qw_ctx *ctx) {
+    if (!ctx) return QW_E_INVALID_ARG;
+    if (ctx->rec) return fail(ctx, QW_E_INVALID_ARG, "a graph is already being recorded");
+    // earlier work of the context's stream, and the staging buffer, are done
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+    std::unique_ptr<GraphRec> r(new (std::nothrow) GraphRec());
+    if (!r) return fail(ctx, QW_E_OOM, "host allocation");
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&r->cap, hipStreamNonBlocking), "capture stream");
+    hipError_t e = hipStreamCreateWithFlags(&r->up, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(r->cap);
+        return hip_fail(ctx, e, "upload stream");
+    }
+    e = hipStreamBeginCapture(r->cap, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(r->cap);
+        (void)hipStreamDestroy(r->up);
+        return hip_fail(ctx, e, "begin capture");
+    }
+    r->saved_stream = ctx->stream;
+    r->saved_plan = ctx->plan;
+    r->saved_scratch = ctx->scratch;
+    r->saved_pingpong = ctx->pingpong;
+    r->saved_meas = ctx->meas;
+    ctx->plan = DevBuf{};
+    ctx->scratch = DevBuf{};
+    ctx->pingpong = DevBuf{};
+    ctx->meas = DevBuf{};
+    ctx->stream = r->cap;
+    ctx->rec = r.release();
+    return QW_OK;
+}
+
+int qw_graph_end(qw_ctx *ctx, qw_graph **out) {
+    if (!ctx || !out) return QW_E_INVALID_ARG;
+    *out = nullptr;
+    if (!ctx->rec) return fail(ctx, QW_E_INVALID_ARG, "no graph is being recorded");
+    hipGraph_t gr = nullptr;
+    std::vector<void *> owned;
+    end_recording(ctx, &gr, &owned);
+    if (!gr) {
+        free_owned(owned);
+        return fail(ctx, QW_E_HIP, "stream capture ended without a graph (a recorded call failed)");
+    }
+    std::unique_ptr<qw_graph> g(new (std::nothrow) qw_graph());
+    if (!g) {
+        (void)hipGraphDestroy(gr);
+        free_owned(owned);
+        return fail(ctx, QW_E_OOM, "host allocation");
+    }
+    size_t nn = 0;
+    (void)hipGraphGetNodes(gr, nullptr, &nn);
+    hipError_t e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        free_owned(owned);
+        return hip_fail(ctx, e, "graph instantiate");
+    }
+    g->ctx = ctx;
+    g->graph = gr;
+    g->owned = std::move(owned);
+    g->nodes = nn;
+    *out = g.release();
+    return QW_OK;
+}
+
+int qw_graph_launch(qw_graph *g) {
+    if (!g) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = g->ctx;
+    if (ctx->rec) return recording_unsupported(ctx, "qw_graph_launch");
+    HIP_TRY(ctx, hipGraphLaunch(g->exec, ctx->stream), "graph launch");
+    return QW_OK;
+}
+
+int qw_graph_nodes(const qw_graph *g, uint64_t *nodes) {
+    if (!g || !nodes) return QW_E_INVALID_ARG;
+    *nodes = g->nodes;
+    return QW_OK;
+}
+
+int qw_graph_free(qw_graph *g) {
+    if (!g) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = g->ctx;
+    if (ctx->rec) return recording_unsupported(ctx, "qw_graph_free");
+    // replays in flight still read the graph's buffers
+    hipStreamSynchronize(ctx->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    free_owned(g->owned);
+    delete g;
+    return QW_OK;
 }
 
 }  // extern "C"

@@ -492,3 +492,145 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
                      predicted_direct_bytes=plan.est_direct, predicted_reuse_bytes=plan.est_reuse,
                      planning_ms=planning_ms, realized_ms=realized)
     return res, trace, rec
+
+
+class RecordedWorkload:
+    """A planned workload recorded as one HIP graph (qw_graph_*): replay()
+    enqueues the whole execution (prefix nodes, snapshots, suffix batch,
+    expectations and samples into device buffers) as one graph launch;
+    results() copies the outputs of the latest replay to the host."""
+
+    def __init__(self, ctx, n, T, shots, mode):
+        self.ctx, self.n, self.T, self.shots, self.mode = ctx, n, T, shots, mode
+        self.graph = None
+        self.state = None
+        self.snaps: List[object] = []
+        self.exp_dev = None
+        self.samp_dev = None
+        self.task_slots: List[int] = []
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+    def results(self) -> ExecutionResult:
+        res = ExecutionResult()
+        if self.exp_dev is not None:
+            res.expectations = [float(v) for v in self.exp_dev.cpu().numpy()]
+        if self.samp_dev is not None:
+            res.samples = self.samp_dev.cpu().numpy().view(np.uint32).reshape(self.T, self.shots)
+        return res
+
+    def state_host(self, t: int):
+        return self.state.host(self.task_slots[t])
+
+    def free(self) -> None:
+        if self.graph is not None:
+            self.graph.free()
+            self.graph = None
+        for s in self.snaps:
+            s.free()
+        self.snaps = []
+        if self.state is not None:
+            self.state.free()
+            self.state = None
+
+
+def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, terms=None,
+                    shots: int = 0, seed: int = 0, mode: str = "plan") -> RecordedWorkload:
+    """Record the execution of `plan` ("plan": materialized nodes level by
+    level, then every task's suffix from its anchor; "direct": every task
+    from |0...0> with the same segment cuts) as one graph. Planning,
+    fingerprints, legality gates and plan uploads happen here, once; a
+    replay is device work only. The caller replays it, then reads results()."""
+    from . import binding as B
+    torch = ctx.torch
+    nodes = plan.nodes
+    T = len(tasks)
+    mats = list(plan.materialized) if mode != "direct" else []
+    slot_of = {vid: i for i, vid in enumerate(mats)}
+    rw = RecordedWorkload(ctx, n, T, shots, mode)
+    rw.state = st = B.State(ctx, n, len(mats) + T)
+    rw.task_slots = task_slots = [len(mats) + t for t in range(T)]
+    dev = f"cuda:{ctx.device}"
+    if terms is not None and T:
+        rw.exp_dev = torch.zeros(T, dtype=torch.float64, device=dev)
+    if shots and T:
+        rw.samp_dev = torch.zeros(T * shots, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize(ctx.device)
+
+    def anchor_chain(vid: Optional[int]) -> List[int]:
+        if vid is None:
+            return []
+        return [u for u in path_to(nodes, vid) if u in slot_of]
+
+    ctx.begin_graph()
+    try:
+        if mode == "direct":
+            mats_all = list(plan.materialized)
+            slot_all = {vid: i for i, vid in enumerate(mats_all)}
+            cuts = [[nodes[u].end for u in path_to(nodes, plan.anchor[t]) if u in slot_all]
+                    if plan.anchor[t] is not None else [] for t in range(T)]
+            st.reset(0, T)
+            levels = max((len(c) for c in cuts), default=0)
+            for lev in range(levels + 1):
+                batch, dsts = [], []
+                for t in range(T):
+                    if lev > len(cuts[t]):
+                        continue
+                    b0 = 0 if lev == 0 else cuts[t][lev - 1]
+                    b1 = cuts[t][lev] if lev < len(cuts[t]) else len(tasks[t])
+                    if b1 > b0:
+                        batch.append(plan.segment_array(tasks, t, b0, b1))
+                        dsts.append(task_slots[t])
+                if batch:
+                    B.run_suffix_batch(ctx, None, batch, st, dsts)
+        else:
+            snaps: Dict[int, object] = {}
+            by_depth: Dict[int, List[int]] = {}
+            for vid in mats:
+                by_depth.setdefault(nodes[vid].depth, []).append(vid)
+            for d in sorted(by_depth):
+                srcs, gl, dsts, provs = [], [], [], []
+                for vid in by_depth[d]:
+                    chain = anchor_chain(nodes[vid].parent)
+                    a = chain[-1] if chain else None
+                    b0 = nodes[a].end if a is not None else 0
+                    gl.append(plan.segment_array(tasks, nodes[vid].tasks[0], b0, nodes[vid].end))
+                    dsts.append(slot_of[vid])
+                    srcs.append(snaps.get(a))
+                    provs.append(snaps[a].provenance if a is not None else bytes(32))
+                for s in dsts:
+                    st.reset(s, 1)
+                any_src = any(s is not None for s in srcs)
+                B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
+                                   expect_provs=provs if any_src else None)
+                for vid in by_depth[d]:
+                    fp = fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end])
+                    snaps[vid] = st.snapshot(slot_of[vid], fp, B.QW_SNAP_FREEZE)
+            rw.snaps = list(snaps.values())
+            srcs, gl, dsts, provs = [], [], [], []
+            for t in range(T):
+                a = plan.anchor[t]
+                b0 = nodes[a].end if a is not None else 0
+                srcs.append(snaps.get(a) if a is not None else None)
+                gl.append(plan.segment_array(tasks, t, b0, len(tasks[t])))
+                dsts.append(task_slots[t])
+                provs.append(snaps[a].provenance if a is not None else bytes(32))
+            direct = [t for t in range(T) if srcs[t] is None]
+            for t in direct:
+                st.reset(task_slots[t], 1)
+            B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
+                               expect_provs=provs if len(direct) < T else None)
+        if rw.exp_dev is not None:
+            st.expect(len(mats), T, terms, out_dev=rw.exp_dev)
+        if rw.samp_dev is not None:
+            st.sample(len(mats), T, seed, 0, shots, out_dev=rw.samp_dev)
+    except BaseException:
+        try:
+            ctx.end_graph().free()
+        except Exception:
+            pass
+        rw.free()
+        raise
+    rw.graph = ctx.end_graph()
+    return rw

@@ -1,0 +1,189 @@
+"""GPU tests of recorded workloads (qw_graph_*): a graph replay performs the
+recorded calls' device work, so every replay equals the same calls run
+directly, bit for bit (states, expectations, samples), with the context's
+own direct work and synchronisations between replays; recording runs no
+device work; calls that need the host are refused while recording. Every
+case prints its name before running."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+FID_TOL = 1e-6
+EXP_TOL = 1e-5
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2609_23664_amd import binding
+    assert torch.cuda.is_available()
+    c = binding.Ctx(0)
+    yield c
+    c.sync()
+
+
+def _other_work(ctx):
+    """Direct work of the same context between replays (its own buffers,
+    plan uploads and a synchronising host read)."""
+    from paper_2609_23664_amd import planner as P
+    w = gen.small_vqe(13, 2, 1, 3, 5, seed=91)
+    tasks = [w.task_gates(t) for t in range(w.n_tasks)]
+    P.run_workload(ctx, w.n, tasks, terms=w.terms)
+
+
+def test_trie_graph_replays_equal_direct_calls(ctx):
+    say("graph trie 12q 27 leaves, 256 shots")
+    import torch
+    from paper_2609_23664_amd import planner as P
+    w = gen.small_trie(12, 3, 3, 1, 3, seed=21, shots=256)
+    tasks = [w.leaf_path(k) for k in range(len(w.leaves))]
+    plan = P.plan_workload(w.n, tasks)
+    assert plan.decision == "REUSE"
+    ref, _, _ = P.run_workload(ctx, w.n, tasks, shots=256, seed=77, keep_states=True, plan=plan)
+    rw = P.record_workload(ctx, w.n, tasks, plan, shots=256, seed=77)
+    try:
+        torch.cuda.synchronize()
+        # recording ran nothing: the device output is still zero
+        assert not rw.samp_dev.any().item()
+        assert rw.graph.nodes() > 0
+        for rep in range(3):
+            rw.replay()
+            res = rw.results()
+            assert np.array_equal(res.samples, ref.samples), rep
+            for t in (0, 7, len(tasks) - 1):
+                assert np.array_equal(rw.state_host(t), ref.states[t]), (rep, t)
+            _other_work(ctx)
+            ctx.sync()
+    finally:
+        rw.free()
+    k = 13
+    o = oracle.simulate(w.n, tasks[k])
+    assert 1 - oracle.fidelity(ref.states[k].astype(np.complex128), o) <= FID_TOL
+
+
+def test_vqe_graph_reuse_equals_direct_graph_and_oracle(ctx):
+    say("graph vqe 18q 6 tasks, plan and direct graphs")
+    from paper_2609_23664_amd import planner as P
+    w = gen.small_vqe(18, 3, 2, 6, 12, seed=17)
+    tasks = [w.task_gates(t) for t in range(w.n_tasks)]
+    plan = P.plan_workload(w.n, tasks)
+    assert plan.decision == "REUSE"
+    ref, _, _ = P.run_workload(ctx, w.n, tasks, terms=w.terms, keep_states=True, plan=plan)
+    ga = P.record_workload(ctx, w.n, tasks, plan, terms=w.terms, mode="plan")
+    gb = P.record_workload(ctx, w.n, tasks, plan, terms=w.terms, mode="direct")
+    try:
+        for rep in range(2):
+            ga.replay()
+            gb.replay()
+            ra, rb = ga.results(), gb.results()
+            assert ra.expectations == rb.expectations == ref.expectations, rep
+            for t in range(w.n_tasks):
+                sa = ga.state_host(t)
+                assert np.array_equal(sa, gb.state_host(t)), (rep, t)
+                assert np.array_equal(sa, ref.states[t]), (rep, t)
+            _other_work(ctx)
+    finally:
+        ga.free()
+        gb.free()
+    scale = sum(abs(t[0]) for t in w.terms)
+    for t in (0, 5):
+        o = oracle.simulate(w.n, tasks[t])
+        assert 1 - oracle.fidelity(ref.states[t].astype(np.complex128), o) <= FID_TOL
+        assert abs(ref.expectations[t] - oracle.expect(o, w.n, w.terms)) <= EXP_TOL * scale
+
+
+def test_graph_with_fused_epilogue_and_second_buffers(ctx):
+    say("graph 20q suffix batch with fused epilogue, generated kernels")
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd.planner import fingerprint
+    c2 = B.Ctx(0)
+    c2.set_option(B.QW_OPT_JIT, 2)
+    w = gen.small_vqe(20, 2, 2, 5, 16, seed=23)
+    st = B.State(c2, w.n, w.n_tasks + 1)
+    fp = fingerprint(w.n, w.prefix)
+
+    def calls(out_dev=None):
+        st.reset(0, 1)
+        st.apply(0, w.prefix)
+        snap = st.snapshot(0, fp, B.QW_SNAP_FREEZE)
+        e = B.run_suffix_batch(c2, [snap] * w.n_tasks, w.suffixes, st,
+                               list(range(1, w.n_tasks + 1)), terms=w.terms, out_dev=out_dev)
+        return snap, e
+
+    snap, e_ref = calls()
+    ref_states = [st.host(t + 1) for t in range(w.n_tasks)]
+    snap.free()
+    out = torch.zeros(w.n_tasks, dtype=torch.float64, device="cuda")
+    c2.begin_graph()
+    snap, _ = calls(out_dev=out)
+    g = c2.end_graph()
+    try:
+        for rep in range(3):
+            g.replay()
+            c2.sync()
+            assert out.cpu().tolist() == e_ref, rep
+            for t in range(w.n_tasks):
+                assert np.array_equal(st.host(t + 1), ref_states[t]), (rep, t)
+            # direct work that regrows the context's own buffers
+            big = gen.small_vqe(20, 1, 1, 12, 30, seed=29)
+            st2 = B.State(c2, 20, 12)
+            B.run_suffix_batch(c2, None, [big.task_gates(t) for t in range(12)], st2,
+                               list(range(12)), terms=big.terms)
+            st2.free()
+    finally:
+        g.free()
+        snap.free()
+    scale = sum(abs(t[0]) for t in w.terms)
+    base = oracle.simulate(w.n, w.prefix)
+    for t in (0, 4):
+        o = oracle.apply_gates(base.copy(), w.n, w.suffixes[t])
+        assert abs(e_ref[t] - oracle.expect(o, w.n, w.terms)) <= EXP_TOL * scale
+    st.free()
+    c2.close()
+
+
+def test_recording_refuses_host_calls(ctx):
+    say("graph recording refusals")
+    import torch
+    from paper_2609_23664_amd import binding as B
+    st = B.State(ctx, 10, 2)
+    terms = [(1.0, 0, 1)]
+    ctx.begin_graph()
+    try:
+        with pytest.raises(B.QwError) as ei:
+            st.expect(0, 1, terms)
+        assert ei.value.code == B.QW_E_UNSUPPORTED
+        with pytest.raises(B.QwError) as ei:
+            st.sample(0, 1, 1, 0, 8)
+        assert ei.value.code == B.QW_E_UNSUPPORTED
+        with pytest.raises(B.QwError) as ei:
+            st.apply(0, [("H", (0,), 0.0), ("MEASURE", (0,), 0.5)])
+        assert ei.value.code == B.QW_E_UNSUPPORTED
+        with pytest.raises(B.QwError) as ei:
+            ctx.sync()
+        assert ei.value.code == B.QW_E_UNSUPPORTED
+        with pytest.raises(B.QwError):
+            ctx.begin_graph()
+        st.apply(1, [("H", (0,), 0.0)])
+    finally:
+        g = ctx.end_graph()
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st.reset()
+    g.replay()
+    st.expect(1, 1, [(1.0, 1, 0)], out_dev=out)
+    ctx.sync()
+    assert abs(out.item() - 1.0) < 1e-6  # <X> of H|0>
+    g.free()
+    st.free()
