@@ -311,13 +311,57 @@ def bench_trie(args):
     td, rd, _ = out["direct"]
     same = bool((rp.samples == rd.samples).all())
     T = len(tasks)
-    return {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)", "value": round(T / tp, 2),
+    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples)
+    return {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)",
+            "value": round(T / g["plan"]["s"], 2),
             "unit": "tasks/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
-            "samples_per_s": round(T * w.shots / tp, 1), "direct_tasks_per_s": round(T / td, 2),
-            "speedup_vs_direct": round(td / tp, 3), "samples_equal_direct": same,
+            "samples_per_s": round(T * w.shots / g["plan"]["s"], 1),
+            "direct_tasks_per_s": round(T / g["direct"]["s"], 2),
+            "speedup_vs_direct": round(g["direct"]["s"] / g["plan"]["s"], 3),
+            "execution": "one recorded HIP graph launch per step (prefix-tree nodes, suffix batch, "
+                         "sampler) + the samples' copy to the host",
+            "graph": {m: {"nodes": g[m]["nodes"], "record_s": round(g[m]["record_s"], 3),
+                          "samples_equal_eager": g[m]["same"]} for m in ("plan", "direct")},
+            "eager_tasks_per_s": round(T / tp, 2), "eager_direct_tasks_per_s": round(T / td, 2),
+            "samples_equal_direct": same and g["plan"]["same"] and g["direct"]["same"],
             "materialized_nodes": len(plan.materialized), "planning_ms": round(plan.planning_ms, 1),
             "realized_ms": recp.realized_ms, "dtype": "c64", "data": "synthetic",
             "config": {"workload": w.name, "qubits": w.n, "leaves": T, "shots": w.shots}}
+
+
+def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None):
+    """Record the planned and the direct execution as graphs (qw_graph_*)
+    and time one replay plus the results' copy to the host per step."""
+    import numpy as np
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd import planner as P
+    ctx = B.Ctx(0)
+    # a graph keeps the kernels chosen when it is recorded: record with
+    # generated kernels for every pass structure (compiled, or read from the
+    # disk cache, during recording; reported as record_s)
+    ctx.set_option(B.QW_OPT_JIT, 2)
+    out = {}
+    for mode in ("plan", "direct"):
+        t0 = time.perf_counter()
+        rw = P.record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed, mode=mode)
+        rec_s = time.perf_counter() - t0
+        for _ in range(max(1, args.warmup)):
+            rw.replay()
+            res = rw.results()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            rw.replay()
+            res = rw.results()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        same = bool(np.array_equal(res.samples, ref_samples)) if ref_samples is not None else None
+        out[mode] = {"s": _median(times), "nodes": rw.graph.nodes(), "record_s": rec_s,
+                     "same": same, "res": res}
+        rw.free()
+    return out
 
 
 def bench_noisy(args):
@@ -332,10 +376,19 @@ def bench_noisy(args):
     td, rd, _ = out["direct"]
     T = len(tasks)
     jumps = sum(1 for t in w.trajectories for g in t if g[0] == "RENORM")
-    return {"metric": "noisy trajectories/s at 22q (256 x 1024 shots)", "value": round(T / tp, 2),
+    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples)
+    return {"metric": "noisy trajectories/s at 22q (256 x 1024 shots)",
+            "value": round(T / g["plan"]["s"], 2),
             "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
-            "direct_trajectories_per_s": round(T / td, 2), "speedup_vs_direct": round(td / tp, 3),
-            "samples_equal_direct": bool((rp.samples == rd.samples).all()), "jumps": jumps,
+            "direct_trajectories_per_s": round(T / g["direct"]["s"], 2),
+            "speedup_vs_direct": round(g["direct"]["s"] / g["plan"]["s"], 3),
+            "execution": "one recorded HIP graph launch per step + the samples' copy to the host",
+            "graph": {m: {"nodes": g[m]["nodes"], "record_s": round(g[m]["record_s"], 3),
+                          "samples_equal_eager": g[m]["same"]} for m in ("plan", "direct")},
+            "eager_trajectories_per_s": round(T / tp, 2),
+            "eager_direct_trajectories_per_s": round(T / td, 2),
+            "samples_equal_direct": bool((rp.samples == rd.samples).all()) and g["plan"]["same"]
+                                    and g["direct"]["same"], "jumps": jumps,
             "jump_free": sum(1 for t in w.trajectories if t == list(w.suffix)),
             "materialized_nodes": len(plan.materialized), "realized_ms": recp.realized_ms,
             "dtype": "c64", "data": "synthetic",
