@@ -31,6 +31,8 @@ def _parse():
                     help="QW_OPT_TILE_ORDER: 0 descriptor-major items always, 1 tile-major for "
                          "relabelling passes (default), 2 tile-major for all launches over "
                          "distinct states")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="trie workload: skip the timing autotuner (default options)")
     ap.add_argument("--cpu-tasks", type=int, default=8,
                     help="tasks in the oracle's bounded CPU sample")
     ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy", "qec", "stab"],
@@ -311,8 +313,9 @@ def bench_trie(args):
     td, rd, _ = out["direct"]
     same = bool((rp.samples == rd.samples).all())
     T = len(tasks)
-    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples)
+    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples, tune=not args.no_tune)
     return {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)",
+            "autotune": g.get("autotune"),
             "value": round(T / g["plan"]["s"], 2),
             "unit": "tasks/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
             "samples_per_s": round(T * w.shots / g["plan"]["s"], 1),
@@ -321,27 +324,35 @@ def bench_trie(args):
             "execution": "one recorded HIP graph launch per step (prefix-tree nodes, suffix batch, "
                          "sampler) + the samples' copy to the host",
             "graph": {m: {"nodes": g[m]["nodes"], "record_s": round(g[m]["record_s"], 3),
-                          "samples_equal_eager": g[m]["same"]} for m in ("plan", "direct")},
+                          "samples_equal_eager_default_options": g[m]["same"]}
+                      for m in ("plan", "direct")},
             "eager_tasks_per_s": round(T / tp, 2), "eager_direct_tasks_per_s": round(T / td, 2),
-            "samples_equal_direct": same and g["plan"]["same"] and g["direct"]["same"],
+            "samples_equal_direct": bool((g["plan"]["res"].samples == g["direct"]["res"].samples).all()),
+            "eager_samples_equal_direct": same,
             "materialized_nodes": len(plan.materialized), "planning_ms": round(plan.planning_ms, 1),
             "realized_ms": recp.realized_ms, "dtype": "c64", "data": "synthetic",
             "config": {"workload": w.name, "qubits": w.n, "leaves": T, "shots": w.shots}}
 
 
-def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None):
+def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune=False):
     """Record the planned and the direct execution as graphs (qw_graph_*)
-    and time one replay plus the results' copy to the host per step."""
+    and time one replay plus the results' copy to the host per step. With
+    `tune`, the execution options (fusion width, tile schedule) are first
+    chosen by the timing autotuner; both graphs then run under its choice."""
     import numpy as np
     import torch
     from paper_2609_23664_amd import binding as B
     from paper_2609_23664_amd import planner as P
     ctx = B.Ctx(0)
+    out = {}
+    if tune:
+        from paper_2609_23664_amd import autotune as A
+        tr = A.autotune(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed)
+        out["autotune"] = {"choice": tr.choice, "tune_s": round(tr.tune_s, 2), "candidates": tr.table}
     # a graph keeps the kernels chosen when it is recorded: record with
     # generated kernels for every pass structure (compiled, or read from the
     # disk cache, during recording; reported as record_s)
     ctx.set_option(B.QW_OPT_JIT, 2)
-    out = {}
     for mode in ("plan", "direct"):
         t0 = time.perf_counter()
         rw = P.record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed, mode=mode)

@@ -1,0 +1,117 @@
+"""Timing autotuner of the execution options of a planned workload.
+
+The planner decides what to materialize (Sec. IV-C); how the passes run is
+chosen here by measurement on the device:
+
+* fusion width: the number of qubits a gate pass keeps local
+  (QW_OPT_TILE_BITS, 12..14): every gate on those qubits is fused into the
+  pass, so it sets how many gates one read and write of the state carries
+  and how many passes a layer needs;
+* tile schedule: the order in which a persistent pass kernel takes its
+  (task, tile) items (QW_OPT_TILE_ORDER: descriptor-major, tile-major for
+  relabelling passes, tile-major always);
+* output relabelling of trailing non-local CNOTs (QW_OPT_RELABEL).
+
+Each candidate is recorded as a graph (``planner.record_workload``) with
+generated kernels, replayed a few times, and timed with device events; the
+fastest replay wins. Results never depend on the choice beyond rounding:
+every candidate computes the same states within the FP32 error of its fused
+passes (tile schedule alone is bitwise neutral), and one workload's reuse
+and direct executions run under the same choice, so they stay bitwise equal.
+Choices are cached per workload signature (qubit count, task count, and the
+gate kinds and qubits of the tasks, not their angles: the pass structures of
+the library do not depend on angles).
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+from .binding import GATE_KIND
+
+Gate = Tuple[str, Tuple[int, ...], float]
+
+DEFAULT_SPACE = {"tile_bits": (12, 13, 14), "tile_order": (0, 1, 2), "relabel": (1,)}
+
+
+@dataclass
+class TuneResult:
+    choice: Dict[str, int]
+    table: List[dict] = field(default_factory=list)  # one row per candidate
+    tune_s: float = 0.0
+    cached: bool = False
+
+
+_CACHE: Dict[str, TuneResult] = {}
+
+
+def signature(n: int, tasks: Sequence[Sequence[Gate]], shots: int, has_terms: bool) -> str:
+    """Structure of a workload: the gate kinds and qubits of every task."""
+    h = hashlib.sha256()
+    h.update(f"{n}|{len(tasks)}|{shots}|{int(has_terms)}".encode())
+    for t in tasks:
+        h.update(len(t).to_bytes(4, "little"))
+        for g in t:
+            h.update(bytes([GATE_KIND[g[0]] & 0xFF]))
+            h.update(bytes(q & 0xFF for q in g[1]))
+    return h.hexdigest()[:24]
+
+
+def apply_choice(ctx, choice: Dict[str, int]) -> None:
+    from . import binding as B
+    ctx.set_option(B.QW_OPT_TILE_BITS, choice["tile_bits"])
+    ctx.set_option(B.QW_OPT_TILE_ORDER, choice["tile_order"])
+    ctx.set_option(B.QW_OPT_RELABEL, choice["relabel"])
+
+
+def autotune(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan, terms=None, shots: int = 0,
+             seed: int = 0, space: Optional[Dict[str, Sequence[int]]] = None, reps: int = 3,
+             use_cache: bool = True) -> TuneResult:
+    """Time every candidate of `space` on the planned workload and return the
+    fastest. The context's options are left at the chosen values."""
+    from . import binding as B
+    from .planner import record_workload
+    torch = ctx.torch
+    space = dict(DEFAULT_SPACE if space is None else space)
+    space["tile_bits"] = tuple(b for b in space["tile_bits"] if b <= max(n, 10))
+    key = signature(n, tasks, shots, terms is not None) + repr(sorted(space.items()))
+    if use_cache and key in _CACHE:
+        r = _CACHE[key]
+        apply_choice(ctx, r.choice)
+        return TuneResult(dict(r.choice), r.table, 0.0, True)
+    t_all = time.perf_counter()
+    ctx.set_option(B.QW_OPT_JIT, 2)
+    rows = []
+    names = ("tile_bits", "tile_order", "relabel")
+    for vals in itertools.product(*(space[k] for k in names)):
+        choice = dict(zip(names, vals))
+        apply_choice(ctx, choice)
+        t0 = time.perf_counter()
+        rw = record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed, mode="plan")
+        rec_s = time.perf_counter() - t0
+        try:
+            rw.replay()  # warm
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            ms = []
+            for _ in range(max(1, reps)):
+                e0.record(ctx.stream)
+                rw.replay()
+                e1.record(ctx.stream)
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+        finally:
+            rw.free()
+        ms.sort()
+        rows.append({**choice, "record_s": round(rec_s, 3), "replay_ms": round(ms[len(ms) // 2], 4)})
+    ctx.set_option(B.QW_OPT_JIT, 1)
+    best = min(rows, key=lambda r: r["replay_ms"])
+    choice = {k: best[k] for k in names}
+    apply_choice(ctx, choice)
+    res = TuneResult(choice, rows, time.perf_counter() - t_all, False)
+    if use_cache:
+        _CACHE[key] = res
+    return res

@@ -187,3 +187,33 @@ def test_recording_refuses_host_calls(ctx):
     assert abs(out.item() - 1.0) < 1e-6  # <X> of H|0>
     g.free()
     st.free()
+
+
+def test_autotuner_choice_and_results(ctx):
+    say("autotune trie 16q 8 leaves, 4 candidates")
+    import torch
+    from paper_2609_23664_amd import autotune as A
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd import planner as P
+    c2 = B.Ctx(0)
+    w = gen.small_trie(16, 2, 8, 1, 2, seed=27, shots=64)
+    tasks = [w.leaf_path(k) for k in range(len(w.leaves))]
+    plan = P.plan_workload(w.n, tasks)
+    space = {"tile_bits": (12, 14), "tile_order": (0, 2), "relabel": (1,)}
+    r = A.autotune(c2, w.n, tasks, plan, shots=64, seed=3, space=space, reps=2)
+    assert len(r.table) == 4 and not r.cached
+    assert r.choice in [{k: row[k] for k in ("tile_bits", "tile_order", "relabel")} for row in r.table]
+    best = min(row["replay_ms"] for row in r.table)
+    assert [row for row in r.table if row["replay_ms"] == best][0]["tile_bits"] == r.choice["tile_bits"]
+    r2 = A.autotune(c2, w.n, tasks, plan, shots=64, seed=3, space=space)
+    assert r2.cached and r2.choice == r.choice
+    # under the chosen options: reuse equals direct bitwise, and the oracle agrees
+    ra, _, _ = P.run_workload(c2, w.n, tasks, shots=64, seed=3, keep_states=True, plan=plan)
+    rb, _, _ = P.run_workload(c2, w.n, tasks, shots=64, seed=3, keep_states=True, plan=plan,
+                              mode="direct")
+    assert np.array_equal(ra.samples, rb.samples)
+    for t in (0, len(tasks) - 1):
+        assert np.array_equal(ra.states[t], rb.states[t])
+        o = oracle.simulate(w.n, tasks[t])
+        assert 1 - oracle.fidelity(ra.states[t].astype(np.complex128), o) <= FID_TOL
+    c2.close()
