@@ -632,8 +632,12 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 const HostPass &p = ex[t].planp->passes[k];
                 const bool with_epi = ex[t].epi && k + 1 == ex[t].planp->passes.size();
                 const bool lds = p.norm_out || p.dev_phases.size() > 1 || with_epi;
+                // a first pass that reads a boundary snapshot keeps the
+                // default load policy (other tasks read the same snapshot)
+                const bool stream = !(k == 0 && ex[t].src);
                 if (p.jit_key.empty()) p.jit_key = jit_pass_key((int)n, m, p, p.norm_out || p.dev_phases.size() > 1);
-                const std::string key = with_epi ? jit_pass_key((int)n, m, p, true) + *ex[t].epi_key : p.jit_key;
+                const std::string key = (with_epi ? jit_pass_key((int)n, m, p, true) + *ex[t].epi_key : p.jit_key) +
+                                        (stream ? "S" : "T");
                 auto it = gi.find(key);
                 if (it == gi.end()) {
                     it = gi.emplace(key, members[k].size()).first;
@@ -645,6 +649,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                     r.n = (int)n;
                     r.m = m;
                     r.use_lds = lds;
+                    r.stream_loads = stream;
                     reqs.push_back(std::move(r));
                 }
                 members[k][it->second].second.push_back(t);
@@ -1906,14 +1911,20 @@ int qw_jit_precompile(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32
     put("");
     if (p.m < kMinTileBits) return QW_OK;
     std::vector<JitReq> reqs;
-    for (const HostPass &h : p.passes) {
-        JitReq r;
-        r.use_lds = h.norm_out || h.dev_phases.size() > 1;
-        r.key = jit_pass_key((int)n, p.m, h, r.use_lds);
-        r.pass = &h;
-        r.n = (int)n;
-        r.m = p.m;
-        reqs.push_back(std::move(r));
+    for (size_t k = 0; k < p.passes.size(); ++k) {
+        const HostPass &h = p.passes[k];
+        // the first pass runs with streamed loads in place, or with the
+        // default policy when it reads a snapshot: both are prepared
+        for (int stream = 1; stream >= (k == 0 ? 0 : 1); --stream) {
+            JitReq r;
+            r.use_lds = h.norm_out || h.dev_phases.size() > 1;
+            r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (stream ? "S" : "T");
+            r.pass = &h;
+            r.n = (int)n;
+            r.m = p.m;
+            r.stream_loads = stream != 0;
+            reqs.push_back(std::move(r));
+        }
     }
     e = jit_precompile(reqs);
     if (!e.empty()) {
@@ -2002,14 +2013,19 @@ int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates,
     for (size_t k = 0; k < p.passes.size(); ++k) {
         const HostPass &h = p.passes[k];
         const bool with_epi = fe.active && k + 1 == p.passes.size();
-        JitReq r;
-        r.use_lds = h.norm_out || h.dev_phases.size() > 1 || with_epi;
-        r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (with_epi ? fe.key : std::string());
-        r.pass = &h;
-        r.epi = with_epi ? &fe.rplan : nullptr;
-        r.n = (int)n;
-        r.m = p.m;
-        reqs.push_back(std::move(r));
+        // first pass: from the snapshot (default loads) or in place (streamed)
+        for (int stream = (k == 0 ? 0 : 1); stream <= 1; ++stream) {
+            JitReq r;
+            r.use_lds = h.norm_out || h.dev_phases.size() > 1 || with_epi;
+            r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (with_epi ? fe.key : std::string()) +
+                    (stream ? "S" : "T");
+            r.pass = &h;
+            r.epi = with_epi ? &fe.rplan : nullptr;
+            r.n = (int)n;
+            r.m = p.m;
+            r.stream_loads = stream != 0;
+            reqs.push_back(std::move(r));
+        }
     }
     // the reducer groups of the remaining terms, built as expect_slots builds them
     std::vector<uint32_t> idx;

@@ -183,6 +183,18 @@ __device__ __forceinline__ double lane_xor_d(double x) {
 // scalar registers from a wave-uniform base address plus the lane's 32-bit
 // byte offset, so all accesses of a thread share one address register.
 // Word 3 is the raw (untyped) setting of CDNA buffer resources.
+// Cache policy of the global loads and stores (the buffer instructions'
+// auxiliary operand; 2 = non-temporal). A generated kernel defines them
+// before including this header: streamed state traffic that no other
+// wave reads again is marked non-temporal so it does not displace data that
+// is reused (a boundary snapshot read by many tasks). 0 = default policy.
+#ifndef QW_LD_AUX
+#define QW_LD_AUX 0
+#endif
+#ifndef QW_ST_AUX
+#define QW_ST_AUX 0
+#endif
+
 typedef unsigned int qw_v4u __attribute__((ext_vector_type(4)));
 typedef unsigned int qw_v2u __attribute__((ext_vector_type(2)));
 
@@ -192,13 +204,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void *p, uint64_
 }
 
 __device__ __forceinline__ float4 buf_ld4(const void *p, uint64_t uni_idx, uint32_t lane_bytes) {
-    const qw_v4u q = __builtin_amdgcn_raw_buffer_load_b128(rsrc_at(p, uni_idx), lane_bytes, 0, 0);
+    const qw_v4u q = __builtin_amdgcn_raw_buffer_load_b128(rsrc_at(p, uni_idx), lane_bytes, 0, QW_LD_AUX);
     return make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
                        __uint_as_float(q.w));
 }
 
 __device__ __forceinline__ float2 buf_ld2(const void *p, uint64_t uni_idx, uint32_t lane_bytes) {
-    const qw_v2u q = __builtin_amdgcn_raw_buffer_load_b64(rsrc_at(p, uni_idx), lane_bytes, 0, 0);
+    const qw_v2u q = __builtin_amdgcn_raw_buffer_load_b64(rsrc_at(p, uni_idx), lane_bytes, 0, QW_LD_AUX);
     return make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
 }
 
@@ -206,12 +218,12 @@ __device__ __forceinline__ void buf_st4(void *p, uint64_t uni_idx, uint32_t lane
                                         float2 b) {
     const qw_v4u q = {__float_as_uint(a.x), __float_as_uint(a.y), __float_as_uint(b.x),
                       __float_as_uint(b.y)};
-    __builtin_amdgcn_raw_buffer_store_b128(q, rsrc_at(p, uni_idx), lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(q, rsrc_at(p, uni_idx), lane_bytes, 0, QW_ST_AUX);
 }
 
 __device__ __forceinline__ void buf_st2(void *p, uint64_t uni_idx, uint32_t lane_bytes, float2 a) {
     const qw_v2u q = {__float_as_uint(a.x), __float_as_uint(a.y)};
-    __builtin_amdgcn_raw_buffer_store_b64(q, rsrc_at(p, uni_idx), lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(q, rsrc_at(p, uni_idx), lane_bytes, 0, QW_ST_AUX);
 }
 
 // Insert a zero bit at each register position r0 < r1 < r2 < r3 of tid: the

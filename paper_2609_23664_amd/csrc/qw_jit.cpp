@@ -533,13 +533,15 @@ std::string jit_epilogue_key(int n, int m, const HostPass &p, const RedPlan &epi
 }
 
 std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch,
-                            const RedPlan *epi) {
+                            const RedPlan *epi, bool stream_loads) {
     Gen g;
     const int T = 1 << (m - 4);
     const int WG = T < 256 ? T : 256;
     g << "// generated pass kernel: " << n << " qubits, tile bits " << m << ", " << p.dev_ops.size()
       << " op records, " << p.dev_phases.size() << " phases, "
       << (use_lds ? "persistent LDS form" : "flat form") << "\n";
+    g << "#define QW_ST_AUX 2\n";
+    if (stream_loads) g << "#define QW_LD_AUX 2\n";
     g << "#include \"qw_dev.h\"\nusing namespace qw;\n";
     g << "constexpr int M = " << m << ", T = " << T << ", WG = " << WG << ", PARTS = T / WG;\n";
     emit_io_helpers(g, "io_in", p.io_in, m);
@@ -808,6 +810,7 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
     const size_t NT = rp.cols.size();
     o << "// generated expectation reducer: " << n << " qubits, tile bits " << m << ", " << NT
       << " terms, " << rp.phases.size() << " phases\n";
+    o << "#define QW_LD_AUX 2\n";  // each state is swept once per term group
     o << "#include \"qw_dev.h\"\nusing namespace qw;\n";
     o << "constexpr int M = " << m << ", T = " << T << ", W = T / 64, NT = " << NT << ";\n";
     // I/O layout of the tile: register slots = local bits {0, 7, 8, 9}
@@ -1063,7 +1066,7 @@ bool jit_available(int device, const JitReq &r) {
     }
     const std::string dir = cache_dir();
     if (dir.empty()) return false;
-    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi)
+    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi, r.stream_loads)
                                    : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
     struct stat sb;
     return ::stat(cache_path(dir, src).c_str(), &sb) == 0;
@@ -1089,7 +1092,7 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
     const char *dump = std::getenv("QW_JIT_DUMP");  // debugging: write sources to this folder
     for (size_t q = 0; q < need.size(); ++q) {
         const JitReq &r = ks[need[q]];
-        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi)
+        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi, r.stream_loads)
                          : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
         if (dump && *dump) {
             std::ofstream f(cache_path(dump, srcs[q]) + ".hip");
@@ -1113,7 +1116,7 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
             if (errs[q].empty() && r.pass && r.use_lds && code_scratch_bytes(codes[q], "qw_pass") > 0) {
                 for (int pf : {8, 0}) {
                     std::vector<char> c2;
-                    const std::string e2 = compile_one(jit_pass_source(r.n, r.m, *r.pass, true, pf, r.epi), &c2);
+                    const std::string e2 = compile_one(jit_pass_source(r.n, r.m, *r.pass, true, pf, r.epi, r.stream_loads), &c2);
                     if (!e2.empty()) break;
                     codes[q].swap(c2);
                     if (code_scratch_bytes(codes[q], "qw_pass") == 0) break;

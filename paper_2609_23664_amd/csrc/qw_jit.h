@@ -27,8 +27,10 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds);
 // Full HIP source of the generated kernel for a key's pass; `prefetch`
 // (0..16, even) is the number of registers of the next tile the persistent
 // form loads while working on the current one.
+// `stream_loads`: the pass's state loads are non-temporal (its stores always
+// are); false for a pass that reads a boundary snapshot other tasks share.
 std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch = 16,
-                            const RedPlan *epi = nullptr);
+                            const RedPlan *epi = nullptr, bool stream_loads = true);
 
 // Key suffix of a pass kernel with a fused expectation epilogue.
 std::string jit_epilogue_key(int n, int m, const HostPass &p, const RedPlan &epi);
@@ -59,6 +61,7 @@ struct JitReq {
     const RedPlan *epi = nullptr;  // pass kernels: fused expectation epilogue (persistent form)
     int n = 0, m = 0;
     bool use_lds = false;  // pass kernels: persistent LDS form
+    bool stream_loads = true;  // pass kernels: non-temporal state loads
 };
 
 // Launch a generated reducer over n_descs descriptors of its term group.
