@@ -316,7 +316,10 @@ int qw_expect_pauli(const qw_state *st, uint32_t first, uint32_t count,
  * s, u = (SplitMix64(seed ^ ((task_base + k) * 2^32 + s)) >> 11) * 2^-53 and
  * the outcome is the smallest basis index i with CDF_i > u * total, where
  * CDF_i is the FP64 running sum of |psi_j|^2 over j <= i and total = CDF of
- * the last index. out[k * shots + s] receives the index (uint32); out is
+ * the last index. The running sum is accumulated as chunk prefixes (chunks
+ * of 2^10 amplitudes), then sums of 64-amplitude sub-chunks, then single
+ * amplitudes; where rounding leaves u * total past the mass of the located
+ * chunk or sub-chunk, its last index of non-zero probability is taken. out[k * shots + s] receives the index (uint32); out is
  * host (out_is_host = 1, call synchronises) or device memory. */
 int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
               uint64_t seed, uint64_t task_base, uint32_t shots,

@@ -1702,18 +1702,21 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count, uint64_t seed,
     const size_t cs = (size_t)count * chunks * sizeof(double);
     const size_t tot = (size_t)count * sizeof(double);
     const size_t ob = (size_t)count * shots * sizeof(uint32_t);
+    const size_t ss = (size_t)count * ((size_t)1 << (n - sample_sub_bits(n))) * sizeof(double);
     const size_t a1 = (cs + 255) & ~size_t(255), a2 = (tot + 255) & ~size_t(255);
-    rc = ensure(ctx, ctx->scratch, 2 * a1 + a2 + (out_is_host ? ob : 0) + 256, "sample scratch");
+    const size_t a3 = (ss + 255) & ~size_t(255);
+    rc = ensure(ctx, ctx->scratch, 2 * a1 + a2 + a3 + (out_is_host ? ob : 0) + 256, "sample scratch");
     if (rc) return rc;
     uint8_t *sb = static_cast<uint8_t *>(ctx->scratch.p);
     double *csum = reinterpret_cast<double *>(sb);
     double *cpre = reinterpret_cast<double *>(sb + a1);
     double *total = reinterpret_cast<double *>(sb + 2 * a1);
-    uint32_t *dout = out_is_host ? reinterpret_cast<uint32_t *>(sb + 2 * a1 + a2) : out;
+    double *ssum = reinterpret_cast<double *>(sb + 2 * a1 + a2);
+    uint32_t *dout = out_is_host ? reinterpret_cast<uint32_t *>(sb + 2 * a1 + a2 + a3) : out;
     {
         ProfScope ps(ctx, 2, (double)count * (double)(8ull << n));
         hipError_t e = launch_sample(ctx->stream, reinterpret_cast<const float2 *const *>(ctx->plan.p),
-                                     count, n, csum, cpre, total, seed, task_base, shots, dout);
+                                     count, n, csum, cpre, ssum, total, seed, task_base, shots, dout);
         if (e != hipSuccess) return hip_fail(ctx, e, "sample launch");
     }
     if (out_is_host) {

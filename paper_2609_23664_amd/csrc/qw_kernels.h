@@ -54,10 +54,13 @@ hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const
 hipError_t launch_stab_export(hipStream_t st, float2 *psi, uint32_t n, uint64_t x0, uint32_t r,
                               const uint64_t *xs, const uint64_t *zs, const uint32_t *ph,
                               const uint32_t *piv, float norm);
+// Sampler: csum [n_slots][chunks] and cpre (same size) chunk sums and
+// prefixes, ssum [n_slots][2^(n - sub bits)] sub-chunk sums, total [n_slots].
 hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
-                         uint32_t n, double *csum, double *cpre, double *total, uint64_t seed,
-                         uint64_t task_base, uint32_t shots, uint32_t *out);
+                         uint32_t n, double *csum, double *cpre, double *ssum, double *total,
+                         uint64_t seed, uint64_t task_base, uint32_t shots, uint32_t *out);
 inline uint32_t sample_chunk_bits(uint32_t n) { return n < 10 ? n : 10; }
+inline uint32_t sample_sub_bits(uint32_t n) { return n < 6 ? n : 6; }
 // One-time kernel attributes (dynamic LDS limits).
 hipError_t kernels_init();
 

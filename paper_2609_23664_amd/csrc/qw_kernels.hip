@@ -1005,10 +1005,52 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const double *__restric
     }
 }
 
-// one thread per (slot, shot)
+// Sub-chunk and chunk sums of |psi|^2 (FP64) for the sampler; grid (chunks,
+// slots), chunk = 2^C amplitudes, sub-chunk = 2^S (S <= 6) amplitudes. Each
+// wave sums one sub-chunk per step (one amplitude per lane, fixed butterfly
+// order); the chunk sum is the sequential sum of its sub-chunk sums.
+__global__ __launch_bounds__(256) void sub_sum_kernel(const float2 *const *__restrict__ slots,
+                                                      uint32_t C, uint32_t S, uint32_t chunks,
+                                                      double *__restrict__ csum,
+                                                      double *__restrict__ ssum) {
+    __shared__ double subs[16];
+    const uint32_t c = blockIdx.x, s = blockIdx.y;
+    const uint32_t spc = 1u << (C - S), L = 1u << S;
+    const float2 *psi = slots[s] + ((uint64_t)c << C);
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *out = ssum + ((uint64_t)s * chunks + c) * spc;
+    for (uint32_t j = wave; j < spc; j += 4) {
+        double v = 0.0;
+        if (lane < L) {
+            const float2 a = psi[(j << S) + lane];
+            const double x = a.x, y = a.y;
+            v = fma(x, x, y * y);
+        }
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) {
+            subs[j] = v;
+            out[j] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (uint32_t j = 0; j < spc; ++j) acc += subs[j];
+        csum[(uint64_t)s * chunks + c] = acc;
+    }
+}
+
+// One thread per (slot, shot). The target u * total is located by a binary
+// search over the chunk prefixes, a scan of the chunk's sub-chunk sums and a
+// scan of one sub-chunk's amplitudes, the running sum continuing in FP64 from
+// the chunk prefix. Where rounding leaves the target past a level's last
+// element, that level's last element of non-zero mass is taken, so every
+// outcome has non-zero probability.
 __global__ __launch_bounds__(256) void draw_kernel(const float2 *const *__restrict__ slots,
-                                                   uint32_t n_slots, uint32_t n, uint32_t C,
-                                                   uint32_t chunks, const double *__restrict__ cpre,
+                                                   uint32_t n_slots, uint32_t C, uint32_t S,
+                                                   uint32_t chunks, const double *__restrict__ csum,
+                                                   const double *__restrict__ cpre,
+                                                   const double *__restrict__ ssum,
                                                    const double *__restrict__ total,
                                                    uint64_t seed, uint64_t task_base,
                                                    uint32_t shots, uint32_t *__restrict__ out) {
@@ -1019,40 +1061,49 @@ __global__ __launch_bounds__(256) void draw_kernel(const float2 *const *__restri
     const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
     const double target = u * total[s];
     const double *pre = cpre + (uint64_t)s * chunks;
-    // last chunk with pre[c] <= target
+    const double *cs = csum + (uint64_t)s * chunks;
+    // last chunk with pre[c] <= target, then back over chunks without mass
     uint32_t lo = 0, hi = chunks - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
         if (pre[mid] <= target) lo = mid;
         else hi = mid - 1;
     }
-    const float2 *psi = slots[s];
-    const uint64_t dim = 1ull << n;
-    uint64_t last_nz = 0;
-    uint64_t i = (uint64_t)lo << C;
-    double run = pre[lo];
-    uint32_t result = 0xFFFFFFFFu;
-    for (; i < dim; ++i) {
-        const double x = psi[i].x, y = psi[i].y;
-        const double pr = fma(x, x, y * y);
-        if (pr > 0.0) last_nz = i;
-        run += pr;
-        if (run > target) {
-            result = (uint32_t)i;
+    while (lo > 0 && cs[lo] == 0.0) --lo;
+    const uint32_t spc = 1u << (C - S), L = 1u << S;
+    const double *sb = ssum + ((uint64_t)s * chunks + lo) * spc;
+    double run = pre[lo], run_last = run;
+    int j = -1, last_j = 0;
+    for (uint32_t k = 0; k < spc; ++k) {
+        const double v = sb[k];
+        if (v > 0.0) {
+            last_j = (int)k;
+            run_last = run;
+        }
+        if (run + v > target) {
+            j = (int)k;
             break;
         }
-        if (((i + 1) & ((1ull << C) - 1)) == 0 && (i + 1) < dim) {
-            // crossed into the next chunk: resynchronise with its prefix
-            const uint64_t nc = (i + 1) >> C;
-            if (pre[nc] > target) {
-                result = (uint32_t)last_nz;
-                break;
-            }
-            run = pre[nc];
+        run += v;
+    }
+    if (j < 0) {
+        j = last_j;
+        run = run_last;
+    }
+    const float2 *psi = slots[s] + ((uint64_t)lo << C) + ((uint64_t)j << S);
+    uint32_t res = 0xFFFFFFFFu, last_i = 0;
+    for (uint32_t i = 0; i < L; ++i) {
+        const double x = psi[i].x, y = psi[i].y;
+        const double pr = fma(x, x, y * y);
+        if (pr > 0.0) last_i = i;
+        run += pr;
+        if (run > target) {
+            res = i;
+            break;
         }
     }
-    if (result == 0xFFFFFFFFu) result = (uint32_t)last_nz;
-    out[gid] = result;
+    if (res == 0xFFFFFFFFu) res = last_i;
+    out[gid] = (uint32_t)(((uint64_t)lo << C) + ((uint64_t)j << S) + res);
 }
 
 // ------------------------------------------------------------- launchers
@@ -1183,12 +1234,12 @@ hipError_t launch_expect_finalize(hipStream_t st, const double *part, const doub
 }
 
 hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
-                         uint32_t n, double *csum, double *cpre, double *total, uint64_t seed,
-                         uint64_t task_base, uint32_t shots, uint32_t *out) {
-    const uint32_t C = n < 10 ? n : 10;
+                         uint32_t n, double *csum, double *cpre, double *ssum, double *total,
+                         uint64_t seed, uint64_t task_base, uint32_t shots, uint32_t *out) {
+    const uint32_t C = sample_chunk_bits(n), S = sample_sub_bits(n);
     const uint32_t chunks = 1u << (n - C);
-    hipLaunchKernelGGL(chunk_sum_kernel, dim3(chunks, n_slots), dim3(256), 0, st, slots, C, chunks,
-                       csum);
+    hipLaunchKernelGGL(sub_sum_kernel, dim3(chunks, n_slots), dim3(256), 0, st, slots, C, S, chunks,
+                       csum, ssum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(chunk_scan_kernel, dim3(n_slots), dim3(256), 0, st, csum, chunks, cpre,
@@ -1198,7 +1249,8 @@ hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_
     const uint64_t threads = (uint64_t)n_slots * shots;
     if (threads == 0) return hipSuccess;
     hipLaunchKernelGGL(draw_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st,
-                       slots, n_slots, n, C, chunks, cpre, total, seed, task_base, shots, out);
+                       slots, n_slots, C, S, chunks, csum, cpre, ssum, total, seed, task_base, shots,
+                       out);
     return hipGetLastError();
 }
 

@@ -234,6 +234,30 @@ def test_sampler_exact_on_dyadic_state(ctx, B, n, shots):
     st.free()
 
 
+@pytest.mark.parametrize("n", [3, 7, 12, 16])
+def test_sampler_mass_at_the_ends(ctx, B, n):
+    # all mass on the first or the last index, or on two indices of the
+    # first and last sub-chunk with empty chunks between: every shot must
+    # land on an index of non-zero probability, as the oracle's do
+    say("sampler edge masses", n)
+    import torch
+    dim = 1 << n
+    cases = []
+    for idx in ([0], [dim - 1], [1, dim - 2], [dim // 2 - 1, dim // 2]):
+        a = np.zeros(dim, dtype=np.complex128)
+        a[idx] = 1.0 / np.sqrt(len(idx))
+        cases.append(a)
+    st = B.State(ctx, n, len(cases))
+    for k, a in enumerate(cases):
+        st.buf[k].copy_(torch.from_numpy(a.astype(np.complex64)))
+    out = st.sample(0, len(cases), 7, 0, 300)
+    for k, a in enumerate(cases):
+        o = oracle.sample(a, n, 7, k, 300)
+        assert np.array_equal(o, out[k]), (k, np.flatnonzero(o != out[k])[:5])
+        assert np.all(np.abs(a[out[k]]) > 0)
+    st.free()
+
+
 @pytest.mark.parametrize("n,shots", [(8, 1000), (14, 1024), (20, 777)])
 def test_sampling_matches_oracle(ctx, B, n, shots):
     # FP32 amplitudes shift the CDF by ~1e-9 at 20 qubits, so about
