@@ -203,6 +203,12 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         when that saves a reducer sweep over the states;
  *                         the results agree with separate reduction up to
  *                         FP32 rounding of the per-thread partial sums. [1]
+ *   QW_OPT_STREAM_LOADS   1: generated pass kernels load the state with the
+ *                         non-temporal cache policy, except a first pass that
+ *                         reads a boundary snapshot (other tasks read it
+ *                         too); 0: default policy for every load. Stores of
+ *                         generated passes are always non-temporal. Results
+ *                         do not depend on it [1]
  *   QW_OPT_TILE_ORDER     order in which the persistent generated kernels
  *                         (multi-phase passes, reducers) take the
  *                         (task, tile) items of a launch: the tasks of one
@@ -224,6 +230,7 @@ int qw_ctx_sync(qw_ctx *ctx);
 #define QW_OPT_SECOND_BUFFER_CAP 7
 #define QW_OPT_FUSED_EPILOGUE 8
 #define QW_OPT_TILE_ORDER 9
+#define QW_OPT_STREAM_LOADS 10
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.

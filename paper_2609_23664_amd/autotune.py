@@ -10,7 +10,9 @@ chosen here by measurement on the device:
 * tile schedule: the order in which a persistent pass kernel takes its
   (task, tile) items (QW_OPT_TILE_ORDER: descriptor-major, tile-major for
   relabelling passes, tile-major always);
-* output relabelling of trailing non-local CNOTs (QW_OPT_RELABEL).
+* output relabelling of trailing non-local CNOTs (QW_OPT_RELABEL);
+* the cache policy of the passes' state loads (QW_OPT_STREAM_LOADS:
+  non-temporal or default).
 
 Each candidate is recorded as a graph (``planner.record_workload``) with
 generated kernels, replayed a few times, and timed with device events; the
@@ -34,7 +36,8 @@ from .binding import GATE_KIND
 
 Gate = Tuple[str, Tuple[int, ...], float]
 
-DEFAULT_SPACE = {"tile_bits": (12, 13, 14), "tile_order": (0, 1, 2), "relabel": (1,)}
+DEFAULT_SPACE = {"tile_bits": (12, 13, 14), "tile_order": (0, 1, 2), "relabel": (1,),
+                 "stream_loads": (0, 1)}
 
 
 @dataclass
@@ -65,6 +68,7 @@ def apply_choice(ctx, choice: Dict[str, int]) -> None:
     ctx.set_option(B.QW_OPT_TILE_BITS, choice["tile_bits"])
     ctx.set_option(B.QW_OPT_TILE_ORDER, choice["tile_order"])
     ctx.set_option(B.QW_OPT_RELABEL, choice["relabel"])
+    ctx.set_option(B.QW_OPT_STREAM_LOADS, choice.get("stream_loads", 1))
 
 
 def autotune(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan, terms=None, shots: int = 0,
@@ -85,7 +89,8 @@ def autotune(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan, terms=None, sho
     t_all = time.perf_counter()
     ctx.set_option(B.QW_OPT_JIT, 2)
     rows = []
-    names = ("tile_bits", "tile_order", "relabel")
+    space.setdefault("stream_loads", (1,))
+    names = ("tile_bits", "tile_order", "relabel", "stream_loads")
     for vals in itertools.product(*(space[k] for k in names)):
         choice = dict(zip(names, vals))
         apply_choice(ctx, choice)

@@ -47,6 +47,7 @@ QW_OPT_RELABEL = 6
 QW_OPT_SECOND_BUFFER_CAP = 7
 QW_OPT_FUSED_EPILOGUE = 8
 QW_OPT_TILE_ORDER = 9
+QW_OPT_STREAM_LOADS = 10
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",

@@ -91,6 +91,7 @@ struct qw_ctx {
     std::unordered_map<std::string, uint64_t> jit_heat;  // task-tiles run per pass structure
     bool relabel = true;
     int tile_order = 1;          // QW_OPT_TILE_ORDER
+    bool stream_loads = true;    // QW_OPT_STREAM_LOADS
     bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
     void *staging = nullptr;
@@ -634,7 +635,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 const bool lds = p.norm_out || p.dev_phases.size() > 1 || with_epi;
                 // a first pass that reads a boundary snapshot keeps the
                 // default load policy (other tasks read the same snapshot)
-                const bool stream = !(k == 0 && ex[t].src);
+                const bool stream = ctx->stream_loads && !(k == 0 && ex[t].src);
                 if (p.jit_key.empty()) p.jit_key = jit_pass_key((int)n, m, p, p.norm_out || p.dev_phases.size() > 1);
                 const std::string key = (with_epi ? jit_pass_key((int)n, m, p, true) + *ex[t].epi_key : p.jit_key) +
                                         (stream ? "S" : "T");
@@ -1364,6 +1365,7 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         return QW_OK;
     case QW_OPT_RELABEL: ctx->relabel = value != 0; return QW_OK;
     case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
+    case QW_OPT_STREAM_LOADS: ctx->stream_loads = value != 0; return QW_OK;
     case QW_OPT_TILE_ORDER:
         if (value < 0 || value > 2) return fail(ctx, QW_E_INVALID_ARG, "tile order must be 0, 1 or 2");
         ctx->tile_order = (int)value;
@@ -1916,9 +1918,8 @@ int qw_jit_precompile(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32
     std::vector<JitReq> reqs;
     for (size_t k = 0; k < p.passes.size(); ++k) {
         const HostPass &h = p.passes[k];
-        // the first pass runs with streamed loads in place, or with the
-        // default policy when it reads a snapshot: both are prepared
-        for (int stream = 1; stream >= (k == 0 ? 0 : 1); --stream) {
+        // both load policies (QW_OPT_STREAM_LOADS, snapshot-reading first passes)
+        for (int stream = 1; stream >= 0; --stream) {
             JitReq r;
             r.use_lds = h.norm_out || h.dev_phases.size() > 1;
             r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (stream ? "S" : "T");
@@ -2016,8 +2017,8 @@ int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates,
     for (size_t k = 0; k < p.passes.size(); ++k) {
         const HostPass &h = p.passes[k];
         const bool with_epi = fe.active && k + 1 == p.passes.size();
-        // first pass: from the snapshot (default loads) or in place (streamed)
-        for (int stream = (k == 0 ? 0 : 1); stream <= 1; ++stream) {
+        // both load policies (QW_OPT_STREAM_LOADS, snapshot-reading first passes)
+        for (int stream = 0; stream <= 1; ++stream) {
             JitReq r;
             r.use_lds = h.norm_out || h.dev_phases.size() > 1 || with_epi;
             r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (with_epi ? fe.key : std::string()) +

@@ -202,7 +202,8 @@ def test_autotuner_choice_and_results(ctx):
     space = {"tile_bits": (12, 14), "tile_order": (0, 2), "relabel": (1,)}
     r = A.autotune(c2, w.n, tasks, plan, shots=64, seed=3, space=space, reps=2)
     assert len(r.table) == 4 and not r.cached
-    assert r.choice in [{k: row[k] for k in ("tile_bits", "tile_order", "relabel")} for row in r.table]
+    assert r.choice in [{k: row[k] for k in ("tile_bits", "tile_order", "relabel", "stream_loads")}
+                        for row in r.table]
     best = min(row["replay_ms"] for row in r.table)
     assert [row for row in r.table if row["replay_ms"] == best][0]["tile_bits"] == r.choice["tile_bits"]
     r2 = A.autotune(c2, w.n, tasks, plan, shots=64, seed=3, space=space)
