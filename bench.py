@@ -201,6 +201,41 @@ def main():
         "options": {"tile_bits": args.tile_bits, "tile_order": args.tile_order,
                     "stream_loads": 0 if args.stream_loads is None else args.stream_loads},
     }
+    # the same steps recorded as graphs (qw_graph_*): one launch per step plus
+    # the 64 expectations' copy to the host
+    def record(direct):
+        out = torch.zeros(T, dtype=torch.float64, device="cuda")
+        ctx.begin_graph()
+        snap = None
+        if direct:
+            dst.reset(0, T)
+            B.run_suffix_batch(ctx, None, [prefix] * T, dst, dslots)
+            B.run_suffix_batch(ctx, None, suffixes, dst, dslots, terms=terms, out_dev=out)
+        else:
+            st.reset(0, 1)
+            st.apply(0, prefix)
+            snap = st.snapshot(0, prov, B.QW_SNAP_FREEZE)
+            B.run_suffix_batch(ctx, [snap] * T, suffixes, st, slots, terms=terms, out_dev=out)
+        g = ctx.end_graph()
+
+        def step():
+            g.replay()
+            return out.cpu().tolist()
+        return g, snap, step
+
+    g_r, snap_r, gstep_r = record(False)
+    dt_gr, ge_r, _ = timed(gstep_r, args.steps, args.warmup)
+    g_r.free()
+    snap_r.free()
+    result["graph"] = {"tasks_per_s": round(T * args.steps / dt_gr, 2),
+                       "equals_eager": ge_r == e_r}
+    if dst is not None:
+        g_d, _, gstep_d = record(True)
+        dt_gd, ge_d, _ = timed(gstep_d, args.steps, args.warmup)
+        g_d.free()
+        result["graph"]["direct_tasks_per_s"] = round(T * args.steps / dt_gd, 2)
+        result["graph"]["speedup_vs_direct"] = round(dt_gd / dt_gr, 3)
+        result["graph"]["reuse_equals_direct"] = ge_r == ge_d
     if dst is not None:
         dt_d, e_d, _ = timed(direct_step, args.steps, args.warmup)
         result["direct_tasks_per_s"] = round(T * args.steps / dt_d, 2)
