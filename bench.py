@@ -259,7 +259,8 @@ def main():
         result["reducer"] = {"launches": red[0], "avg_launch_ms": round(red[1] / red[0], 4),
                              "GB/s": round(red[2] / (red[1] * 1e-3) / 1e9, 1)}
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_tasks)
+        gpu = [(st.host(t + 1), e_r[t]) for t in range(min(args.cpu_tasks, T))]
+        result["cpu_baseline"], result["oracle_check"] = cpu_baseline(w, args.cpu_tasks, gpu)
     print(json.dumps(result), flush=True)
 
 
@@ -617,26 +618,44 @@ def bench_stab(args):
                        "terms": len(w.terms)}}
 
 
-def cpu_baseline(w, k):
+def cpu_baseline(w, k, gpu=None):
     """The oracle (complex128, OpenMP over amplitudes) on a bounded sample:
     the shared prefix once plus k tasks (suffix + Pauli-sum expectation);
     tasks/s for the full workload is extrapolated as
-    T / (t_prefix + T * t_task)."""
+    T / (t_prefix + T * t_task). With `gpu` (the GPU's final states and
+    expectations of the same first tasks) it also returns their error
+    against the oracle: 1 - F, |E_gpu - E_oracle| / sum|c|, norm drift."""
+    import numpy as np
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     base = oracle.simulate(w.n, w.prefix)
     t_prefix = time.perf_counter() - t0
+    refs = []
     t1 = time.perf_counter()
     for t in range(k):
         psi = oracle.apply_gates(base.copy(), w.n, w.suffixes[t])
-        oracle.expect(psi, w.n, w.terms)
+        refs.append((psi, oracle.expect(psi, w.n, w.terms)))
     t_task = (time.perf_counter() - t1) / k
     T = w.n_tasks
-    return {"value": round(T / (t_prefix + T * t_task), 4), "unit": "tasks/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"prefix once ({len(w.prefix)} gates) + {k} task(s) of {T}; "
-                      f"t_prefix={t_prefix:.2f}s t_task={t_task:.2f}s"}
+    base_rec = {"value": round(T / (t_prefix + T * t_task), 4), "unit": "tasks/s", "cores": cores,
+                "kind": "oracle",
+                "sample": f"prefix once ({len(w.prefix)} gates) + {k} task(s) of {T}; "
+                          f"t_prefix={t_prefix:.2f}s t_task={t_task:.2f}s"}
+    if gpu is None:
+        return base_rec
+    scale = sum(abs(c) for c, _, _ in w.terms)
+    inf, err, drift = [], [], []
+    for (psi_g, e_g), (psi_o, e_o) in zip(gpu, refs):
+        g = psi_g.astype(np.complex128)
+        inf.append(1.0 - oracle.fidelity(psi_o, g))
+        err.append(abs(e_g - e_o) / scale)
+        drift.append(abs(float(np.vdot(g, g).real) - 1.0))
+    check = {"tasks": len(inf), "max_one_minus_fidelity": float(max(inf)),
+             "max_expect_err_over_sum_abs_c": float(max(err)), "max_norm_drift": float(max(drift)),
+             "bars": {"one_minus_fidelity": 1e-6, "expect_err_over_sum_abs_c": 1e-5},
+             "pass": bool(max(inf) <= 1e-6 and max(err) <= 1e-5)}
+    return base_rec, check
 
 
 if __name__ == "__main__":

@@ -1006,9 +1006,10 @@ __global__ __launch_bounds__(256) void chunk_scan_kernel(const double *__restric
 }
 
 // Sub-chunk and chunk sums of |psi|^2 (FP64) for the sampler; grid (chunks,
-// slots), chunk = 2^C amplitudes, sub-chunk = 2^S (S <= 6) amplitudes. Each
-// wave sums one sub-chunk per step (one amplitude per lane, fixed butterfly
-// order); the chunk sum is the sequential sum of its sub-chunk sums.
+// slots), chunk = 2^C amplitudes, sub-chunk = 2^S (S <= 6) amplitudes. A
+// sub-chunk of 64 is summed by 32 lanes (two amplitudes each, then a fixed
+// butterfly), a smaller one by one amplitude per lane; the chunk sum is the
+// sequential sum of its sub-chunk sums.
 __global__ __launch_bounds__(256) void sub_sum_kernel(const float2 *const *__restrict__ slots,
                                                       uint32_t C, uint32_t S, uint32_t chunks,
                                                       double *__restrict__ csum,
@@ -1019,17 +1020,37 @@ __global__ __launch_bounds__(256) void sub_sum_kernel(const float2 *const *__res
     const float2 *psi = slots[s] + ((uint64_t)c << C);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double *out = ssum + ((uint64_t)s * chunks + c) * spc;
-    for (uint32_t j = wave; j < spc; j += 4) {
-        double v = 0.0;
-        if (lane < L) {
-            const float2 a = psi[(j << S) + lane];
-            const double x = a.x, y = a.y;
-            v = fma(x, x, y * y);
+    if (S == 6) {
+        // two sub-chunks per wave step: each half-wave covers one with two
+        // amplitudes (16 bytes) per lane
+        const uint32_t half = lane >> 5, hl = lane & 31;
+        for (uint32_t q = wave; 2 * q < spc; q += 4) {
+            const uint32_t j = 2 * q + half;
+            double v = 0.0;
+            if (j < spc) {
+                const float4 a = *reinterpret_cast<const float4 *>(psi + (j << 6) + 2 * hl);
+                const double x0 = a.x, y0 = a.y, x1 = a.z, y1 = a.w;
+                v = fma(x0, x0, y0 * y0) + fma(x1, x1, y1 * y1);
+            }
+            for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (hl == 0 && j < spc) {
+                subs[j] = v;
+                out[j] = v;
+            }
         }
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) {
-            subs[j] = v;
-            out[j] = v;
+    } else {
+        for (uint32_t j = wave; j < spc; j += 4) {
+            double v = 0.0;
+            if (lane < L) {
+                const float2 a = psi[(j << S) + lane];
+                const double x = a.x, y = a.y;
+                v = fma(x, x, y * y);
+            }
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) {
+                subs[j] = v;
+                out[j] = v;
+            }
         }
     }
     __syncthreads();
