@@ -362,6 +362,18 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
  *   run directly. Replays and direct calls of one context are ordered by
  *   its stream; they share no buffer except the caller's states and outputs.
  * qw_graph_nodes: number of nodes (kernels and copies) in the graph.
+ * qw_graph_update_gates: new gates for task `task` of the `call`-th recorded
+ *   gate-running call (qw_apply_prefix or qw_run_suffix_batch, counted from
+ *   0 in recording order; a qw_apply_prefix has one task), e.g. the angles
+ *   of the next iteration of a variational loop. The gates are planned with
+ *   the context's current options and must give the recorded pass
+ *   structure (same gate kinds and qubits, angles free: the pass structure
+ *   does not depend on angles); otherwise QW_E_INVALID_ARG and nothing
+ *   changes. The call synchronises the context's stream and rewrites the
+ *   op records the graph's nodes read; later replays use the new gates.
+ *   The provenance of snapshots recorded in the graph is not recomputed:
+ *   it stays that of the gates at recording time. MEASURE and RESET gates
+ *   are refused.
  * qw_graph_free: synchronises the context's stream and releases the graph
  *   and its buffers. */
 typedef struct qw_graph qw_graph;
@@ -369,6 +381,8 @@ int qw_graph_begin(qw_ctx *ctx);
 int qw_graph_end(qw_ctx *ctx, qw_graph **out);
 int qw_graph_launch(qw_graph *g);
 int qw_graph_nodes(const qw_graph *g, uint64_t *nodes);
+int qw_graph_update_gates(qw_graph *g, uint32_t call, uint32_t task, const qw_gate *gates,
+                          uint64_t n_gates);
 int qw_graph_free(qw_graph *g);
 
 /* ------------------------------------------------------------ learned cost model

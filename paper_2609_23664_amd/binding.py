@@ -60,6 +60,7 @@ EXPORTED = (
     "qw_jit_stats", "qw_version", "qw_outcomes", "qw_tableau_create", "qw_tableau_free",
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
     "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
+    "qw_graph_update_gates",
 )
 
 
@@ -180,6 +181,7 @@ def lib() -> ctypes.CDLL:
         "qw_graph_launch": ([vp], i32),
         "qw_graph_nodes": ([vp, ctypes.POINTER(u64)], i32),
         "qw_graph_free": ([vp], i32),
+        "qw_graph_update_gates": ([vp, u32, u32, ctypes.POINTER(QwGate), u64], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -571,6 +573,11 @@ class Graph:
 
     def replay(self):
         self.ctx.check(lib().qw_graph_launch(self.h))
+
+    def update_gates(self, call: int, task: int, gates) -> None:
+        """qw_graph_update_gates: new gates (same structure) for a recorded task."""
+        arr = gate_array(gates)
+        self.ctx.check(lib().qw_graph_update_gates(self.h, call, task, arr.ptr, len(arr)))
 
     def nodes(self) -> int:
         n = ctypes.c_uint64()

@@ -55,7 +55,16 @@ struct KStats {
 // State of a context while it records a graph (qw_graph_begin .. end): the
 // device work of the calls goes into a stream capture, and every device
 // buffer those calls use is kept for the graph's lifetime.
+// One recorded task of a gate-running call: its plan and, per pass, where
+// the graph keeps the pass's op records.
+struct GraphSeg {
+    uint32_t n = 0;
+    std::shared_ptr<const qw::Plan> plan;
+    std::vector<std::pair<void *, size_t>> ops;  // device address, bytes
+};
+
 struct GraphRec {
+    std::vector<std::vector<GraphSeg>> calls;  // qw_apply_prefix / qw_run_suffix_batch, in order
     hipStream_t cap = nullptr;    // captured stream (non-blocking, default priority)
     hipStream_t up = nullptr;     // plan uploads, synchronous, outside the capture
     hipStream_t saved_stream = nullptr;
@@ -72,6 +81,7 @@ struct qw_graph {
     hipGraphExec_t exec = nullptr;
     std::vector<void *> owned;  // plan blobs and scratch the recorded nodes read
     uint64_t nodes = 0;
+    std::vector<std::vector<GraphSeg>> calls;  // updatable op records per recorded task
 };
 
 struct qw_ctx {
@@ -735,6 +745,18 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             if (p.norm_out || p.dev_phases.size() > 1) step_lds[k] = 1;
             std::memcpy(blob.data() + step_off[k] + c * sizeof(PassDesc), &d, sizeof d);
             ++c;
+        }
+    }
+    if (ctx->rec && !ctx->rec->calls.empty()) {
+        // where each task's op records live in the graph (qw_graph_update_gates)
+        for (size_t t = 0; t < ex.size(); ++t) {
+            GraphSeg sg;
+            sg.n = n;
+            sg.plan = ex[t].planp;
+            for (size_t k = 0; k < ex[t].planp->passes.size(); ++k)
+                sg.ops.push_back({dbase + op_off[t][k].first,
+                                  ex[t].planp->passes[k].dev_ops.size() * sizeof(DevOp)});
+            ctx->rec->calls.back().push_back(std::move(sg));
         }
     }
     rc = upload(ctx, blob);
@@ -1489,6 +1511,7 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
     std::string e = get_plan(ctx, st->n, gates, n_gates, &ex[0].planp);
     if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
     ex[0].dst = slot_ptr(st, slot);
+    if (ctx->rec) ctx->rec->calls.emplace_back();
     return execute(ctx, st->n, ex);
 }
 
@@ -1660,6 +1683,7 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
             ex[k].epi_nt = epi->n_terms;
         }
     }
+    if (ctx->rec) ctx->rec->calls.emplace_back();
     int rc = execute(ctx, dst->n, ex);
     if (rc) return rc;
     if (epi) {
@@ -2086,8 +2110,10 @@ namespace {
 
 // Leave recording mode: the capture ends, the context gets its own buffers
 // and stream back, and the buffers of the recording are returned.
-void end_recording(qw_ctx *ctx, hipGraph_t *graph, std::vector<void *> *owned) {
+void end_recording(qw_ctx *ctx, hipGraph_t *graph, std::vector<void *> *owned,
+                   std::vector<std::vector<GraphSeg>> *calls = nullptr) {
     GraphRec *r = ctx->rec;
+    if (calls) *calls = std::move(r->calls);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(r->cap, &gr);
     if (e != hipSuccess) gr = nullptr;
@@ -2152,7 +2178,8 @@ int qw_graph_end(qw_ctx *ctx, qw_graph **out) {
     if (!ctx->rec) return fail(ctx, QW_E_INVALID_ARG, "no graph is being recorded");
     hipGraph_t gr = nullptr;
     std::vector<void *> owned;
-    end_recording(ctx, &gr, &owned);
+    std::vector<std::vector<GraphSeg>> calls;
+    end_recording(ctx, &gr, &owned, &calls);
     if (!gr) {
         free_owned(owned);
         return fail(ctx, QW_E_HIP, "stream capture ended without a graph (a recorded call failed)");
@@ -2174,6 +2201,7 @@ int qw_graph_end(qw_ctx *ctx, qw_graph **out) {
     g->ctx = ctx;
     g->graph = gr;
     g->owned = std::move(owned);
+    g->calls = std::move(calls);
     g->nodes = nn;
     *out = g.release();
     return QW_OK;
@@ -2190,6 +2218,50 @@ int qw_graph_launch(qw_graph *g) {
 int qw_graph_nodes(const qw_graph *g, uint64_t *nodes) {
     if (!g || !nodes) return QW_E_INVALID_ARG;
     *nodes = g->nodes;
+    return QW_OK;
+}
+
+int qw_graph_update_gates(qw_graph *g, uint32_t call, uint32_t task, const qw_gate *gates,
+                          uint64_t n_gates) {
+    if (!g) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = g->ctx;
+    if (ctx->rec) return recording_unsupported(ctx, "qw_graph_update_gates");
+    if (call >= g->calls.size() || task >= g->calls[call].size())
+        return fail(ctx, QW_E_INVALID_ARG, "no such recorded call or task");
+    if (n_gates && !gates) return fail(ctx, QW_E_INVALID_ARG, "gates == NULL");
+    for (uint64_t i = 0; i < n_gates; ++i)
+        if (is_measure(gates[i].kind)) return fail(ctx, QW_E_INVALID_ARG, "measurement gates cannot be updated");
+    GraphSeg &sg = g->calls[call][task];
+    std::shared_ptr<const Plan> np;
+    std::string e = get_plan(ctx, sg.n, gates, n_gates, &np);
+    if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
+    // the pass structure (kernel identity, record counts, phases, I/O and
+    // relabelling) must be the recorded one; only op-record values change
+    const Plan &a = *sg.plan, &b = *np;
+    bool same = a.m == b.m && a.passes.size() == b.passes.size();
+    for (size_t k = 0; same && k < a.passes.size(); ++k) {
+        const HostPass &pa = a.passes[k], &pb = b.passes[k];
+        const bool la = pa.norm_out || pa.dev_phases.size() > 1, lb = pb.norm_out || pb.dev_phases.size() > 1;
+        same = pa.dev_ops.size() == pb.dev_ops.size() && pa.dev_phases.size() == pb.dev_phases.size() &&
+               std::memcmp(pa.dev_phases.data(), pb.dev_phases.data(),
+                           pa.dev_phases.size() * sizeof(DevPhase)) == 0 &&
+               std::memcmp(&pa.io_in, &pb.io_in, sizeof(IoRec)) == 0 &&
+               std::memcmp(&pa.io_out, &pb.io_out, sizeof(IoRec)) == 0 &&
+               pa.scale_in == pb.scale_in && pa.norm_out == pb.norm_out && pa.out_img == pb.out_img &&
+               jit_pass_key((int)sg.n, a.m, pa, la) == jit_pass_key((int)sg.n, b.m, pb, lb);
+    }
+    if (!same)
+        return fail(ctx, QW_E_INVALID_ARG,
+                    "the gates plan to another pass structure than the recorded ones (gate kinds, "
+                    "qubits or context options differ)");
+    // replays already enqueued read the old records
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+    for (size_t k = 0; k < b.passes.size(); ++k)
+        if (sg.ops[k].second)
+            HIP_TRY(ctx, hipMemcpy(sg.ops[k].first, b.passes[k].dev_ops.data(), sg.ops[k].second,
+                                   hipMemcpyHostToDevice),
+                    "op record update");
+    sg.plan = np;
     return QW_OK;
 }
 

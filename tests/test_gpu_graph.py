@@ -218,3 +218,62 @@ def test_autotuner_choice_and_results(ctx):
         o = oracle.simulate(w.n, tasks[t])
         assert 1 - oracle.fidelity(ra.states[t].astype(np.complex128), o) <= FID_TOL
     c2.close()
+
+
+def test_graph_update_gates_next_iteration(ctx):
+    say("graph gate update: 16q, 4 tasks, new angles for prefix and suffixes")
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd.planner import fingerprint
+    w = gen.small_vqe(16, 3, 2, 4, 8, seed=61)
+    w2 = gen.small_vqe(16, 3, 2, 4, 8, seed=62)   # same gate kinds and qubits, other angles
+    assert [g[:2] for g in w.prefix] == [g[:2] for g in w2.prefix]
+    st = B.State(ctx, w.n, w.n_tasks + 1)
+    slots = list(range(1, w.n_tasks + 1))
+
+    def calls(gw, out_dev=None):
+        st.reset(0, 1)
+        st.apply(0, gw.prefix)
+        snap = st.snapshot(0, fingerprint(w.n, gw.prefix), B.QW_SNAP_FREEZE)
+        e = B.run_suffix_batch(ctx, [snap] * w.n_tasks, gw.suffixes, st, slots, terms=w.terms,
+                               out_dev=out_dev)
+        return snap, e
+
+    snap, e2 = calls(w2)
+    ref2 = [st.host(t + 1) for t in range(w.n_tasks)]
+    snap.free()
+    out = torch.zeros(w.n_tasks, dtype=torch.float64, device="cuda")
+    ctx.begin_graph()
+    snap, _ = calls(w, out_dev=out)
+    g = ctx.end_graph()
+    try:
+        g.update_gates(0, 0, w2.prefix)
+        for t in range(w.n_tasks):
+            g.update_gates(1, t, w2.suffixes[t])
+        for rep in range(2):
+            g.replay()
+            ctx.sync()
+            assert out.cpu().tolist() == e2, rep
+            for t in range(w.n_tasks):
+                assert np.array_equal(st.host(t + 1), ref2[t]), (rep, t)
+        bad = list(w2.suffixes[0])
+        bad[0] = ("CNOT", (0, 1), 0.0)   # another structure
+        with pytest.raises(B.QwError) as ei:
+            g.update_gates(1, 0, bad)
+        assert ei.value.code == B.QW_E_INVALID_ARG
+        with pytest.raises(B.QwError):
+            g.update_gates(2, 0, w2.prefix)
+        with pytest.raises(B.QwError):
+            g.update_gates(1, w.n_tasks, w2.suffixes[0])
+        # the refused updates changed nothing
+        g.replay()
+        ctx.sync()
+        assert out.cpu().tolist() == e2
+    finally:
+        g.free()
+        snap.free()
+        st.free()
+    base = oracle.simulate(w.n, w2.prefix)
+    scale = sum(abs(t[0]) for t in w.terms)
+    o = oracle.apply_gates(base.copy(), w.n, w2.suffixes[1])
+    assert abs(e2[1] - oracle.expect(o, w.n, w.terms)) <= EXP_TOL * scale
