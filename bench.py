@@ -383,7 +383,7 @@ def bench_trie(args):
             "config": {"workload": w.name, "qubits": w.n, "leaves": T, "shots": w.shots}}
 
 
-def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune=False):
+def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune=False, keep=()):
     """Record the planned and the direct execution as graphs (qw_graph_*)
     and time one replay plus the results' copy to the host per step. With
     `tune`, the execution options (fusion width, tile schedule) are first
@@ -418,7 +418,8 @@ def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         same = bool(np.array_equal(res.samples, ref_samples)) if ref_samples is not None else None
-        out[mode] = {"s": _median(times), "nodes": rw.graph.nodes(), "record_s": rec_s,
+        kept = {t: rw.state_host(t) for t in keep} if mode == "plan" else {}
+        out[mode] = {"s": _median(times), "nodes": rw.graph.nodes(), "record_s": rec_s, "states": kept,
                      "same": same, "res": res}
         rw.free()
     return out
@@ -436,8 +437,11 @@ def bench_noisy(args):
     td, rd, _ = out["direct"]
     T = len(tasks)
     jumps = sum(1 for t in w.trajectories for g in t if g[0] == "RENORM")
-    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples)
-    return {"metric": "noisy trajectories/s at 22q (256 x 1024 shots)",
+    jumped = [t for t in range(T) if list(w.trajectories[t]) != list(w.suffix)]
+    clean = [t for t in range(T) if list(w.trajectories[t]) == list(w.suffix)]
+    picks = (jumped[0], clean[0]) if jumped and clean else (0,)
+    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples, keep=picks)
+    result = {"metric": "noisy trajectories/s at 22q (256 x 1024 shots)",
             "value": round(T / g["plan"]["s"], 2),
             "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
             "direct_trajectories_per_s": round(T / g["direct"]["s"], 2),
@@ -453,6 +457,10 @@ def bench_noisy(args):
             "materialized_nodes": len(plan.materialized), "realized_ms": recp.realized_ms,
             "dtype": "c64", "data": "synthetic",
             "config": {"workload": w.name, "qubits": w.n, "trajectories": T, "shots": w.shots}}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"], result["oracle_check"] = noisy_cpu_baseline(
+            w, tasks, picks, g["plan"]["states"], g["plan"]["res"].samples)
+    return result
 
 
 def bench_qec(args):
@@ -621,6 +629,57 @@ def bench_stab(args):
             "dtype": "c64 (fp32 amplitudes, fp64 accumulation)", "data": "synthetic",
             "config": {"workload": w.name, "qubits": n, "tasks": T, "prefix_gates": len(w.prefix),
                        "terms": len(w.terms)}}
+
+
+def noisy_cpu_baseline(w, tasks, picks, states, samples):
+    """The oracle on a bounded sample of the noisy workload: the noiseless
+    prefix once plus the trajectories `picks` (one with jumps, one without);
+    trajectories/s extrapolated as T / (t_prefix + T * t_traj). Against the
+    GPU's states and samples of those trajectories: 1 - F, norm drift, the
+    share of identical shots (same counter-hash draws) and the total-variation
+    distance between the two 1,024-shot histograms."""
+    import numpy as np
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    base = oracle.simulate(w.n, w.prefix)
+    t_prefix = time.perf_counter() - t0
+    rows = []
+    t1 = time.perf_counter()
+    refs = {k: oracle.apply_gates(base.copy(), w.n, tasks[k][len(w.prefix):]) for k in picks}
+    t_traj = (time.perf_counter() - t1) / len(picks)
+    for k in picks:
+        ref = refs[k]
+        gs = states[k].astype(np.complex128)
+        o = oracle.sample(ref, w.n, w.seed, k, w.shots)
+        hg = np.bincount(samples[k], minlength=1 << w.n)
+        ho = np.bincount(o, minlength=1 << w.n)
+        cdf = np.cumsum(np.abs(ref) ** 2)
+        valid = 0
+        for s_, i in enumerate(samples[k]):
+            u = oracle.uniform(w.seed, k, s_) * cdf[-1]
+            lo = cdf[i - 1] if i > 0 else 0.0
+            valid += int(lo - 1e-6 <= u <= cdf[i] + 1e-6)
+        rows.append({"trajectory": int(k), "jumps": sum(1 for g in tasks[k] if g[0] == "RENORM"),
+                     "one_minus_fidelity": float(1.0 - oracle.fidelity(ref, gs)),
+                     "norm_drift": abs(float(np.vdot(gs, gs).real) - 1.0),
+                     "identical_shots": float(np.mean(o == samples[k])),
+                     "valid_shots": valid / w.shots,
+                     "tvd": float(0.5 * np.abs(hg - ho).sum() / w.shots)})
+    T = len(tasks)
+    base_rec = {"value": round(T / (t_prefix + T * t_traj), 4), "unit": "trajectories/s",
+                "cores": cores, "kind": "oracle",
+                "sample": f"prefix once ({len(w.prefix)} gates) + {len(picks)} trajectories of {T}; "
+                          f"t_prefix={t_prefix:.2f}s t_traj={t_traj:.2f}s"}
+    # bars of the parity tests: FP32 amplitudes move the CDF by about 1e-6
+    # at 22 qubits, several outcome widths, so a shot may land on a
+    # neighbouring index; every shot must still be a valid inverse-CDF pick
+    # within 1e-6 of the oracle's CDF, and >= 99 % identical
+    check = {"trajectories": rows,
+             "bars": {"one_minus_fidelity": 1e-6, "identical_shots": 0.99, "valid_shots": 1.0},
+             "pass": all(r["one_minus_fidelity"] <= 1e-6 and r["identical_shots"] >= 0.99 and
+                         r["valid_shots"] == 1.0 for r in rows)}
+    return base_rec, check
 
 
 def cpu_baseline(w, k, gpu=None):
