@@ -362,8 +362,10 @@ def bench_trie(args):
     td, rd, _ = out["direct"]
     same = bool((rp.samples == rd.samples).all())
     T = len(tasks)
-    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples, tune=not args.no_tune)
-    return {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)",
+    picks = (0, 301, T - 1)
+    g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples, tune=not args.no_tune,
+                    keep=picks)
+    result = {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)",
             "autotune": g.get("autotune"),
             "value": round(T / g["plan"]["s"], 2),
             "unit": "tasks/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
@@ -381,6 +383,10 @@ def bench_trie(args):
             "materialized_nodes": len(plan.materialized), "planning_ms": round(plan.planning_ms, 1),
             "realized_ms": recp.realized_ms, "dtype": "c64", "data": "synthetic",
             "config": {"workload": w.name, "qubits": w.n, "leaves": T, "shots": w.shots}}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"], result["oracle_check"] = trie_cpu_baseline(
+            w, tasks, picks, g["plan"]["states"], g["plan"]["res"].samples)
+    return result
 
 
 def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune=False, keep=()):
@@ -631,6 +637,62 @@ def bench_stab(args):
                        "terms": len(w.terms)}}
 
 
+def _shot_rows(n, seed, shots, tasks, picks, refs, states, samples):
+    """Per picked task: 1 - F and norm drift of the GPU state, and of its
+    shots the share identical to the oracle's draws, the share that are
+    valid inverse-CDF picks within 1e-6 of the oracle's CDF, and the TVD of
+    the two histograms."""
+    import numpy as np
+    import oracle
+    rows = []
+    for k in picks:
+        ref = refs[k]
+        gs = states[k].astype(np.complex128)
+        o = oracle.sample(ref, n, seed, k, shots)
+        hg = np.bincount(samples[k], minlength=1 << n)
+        ho = np.bincount(o, minlength=1 << n)
+        cdf = np.cumsum(np.abs(ref) ** 2)
+        valid = 0
+        for s_, i in enumerate(samples[k]):
+            u = oracle.uniform(seed, k, s_) * cdf[-1]
+            lo = cdf[i - 1] if i > 0 else 0.0
+            valid += int(lo - 1e-6 <= u <= cdf[i] + 1e-6)
+        rows.append({"task": int(k), "jumps": sum(1 for g in tasks[k] if g[0] == "RENORM"),
+                     "one_minus_fidelity": float(1.0 - oracle.fidelity(ref, gs)),
+                     "norm_drift": abs(float(np.vdot(gs, gs).real) - 1.0),
+                     "identical_shots": float(np.mean(o == samples[k])),
+                     "valid_shots": valid / shots,
+                     "tvd": float(0.5 * np.abs(hg - ho).sum() / shots)})
+    return rows
+
+
+def _shot_check(rows):
+    # bars of the parity tests: FP32 amplitudes move the CDF by about 1e-6
+    # at 22 qubits, several outcome widths, so a shot may land on a
+    # neighbouring index; every shot must still be a valid inverse-CDF pick
+    # within 1e-6 of the oracle's CDF, and >= 99 % identical
+    return {"tasks": rows,
+            "bars": {"one_minus_fidelity": 1e-6, "identical_shots": 0.99, "valid_shots": 1.0},
+            "pass": all(r["one_minus_fidelity"] <= 1e-6 and r["identical_shots"] >= 0.99 and
+                        r["valid_shots"] == 1.0 for r in rows)}
+
+
+def trie_cpu_baseline(w, tasks, picks, states, samples):
+    """The oracle on a bounded sample of the prefix-tree workload: the
+    leaves `picks`, each simulated from |0...0> (no sharing); tasks/s
+    extrapolated as 1 / t_leaf. With the GPU's states and samples of those
+    leaves: the rows of _shot_rows."""
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    refs = {k: oracle.simulate(w.n, tasks[k]) for k in picks}
+    t_leaf = (time.perf_counter() - t0) / len(picks)
+    rows = _shot_rows(w.n, w.seed, w.shots, tasks, picks, refs, states, samples)
+    return ({"value": round(1.0 / t_leaf, 4), "unit": "tasks/s", "cores": cores, "kind": "oracle",
+             "sample": f"{len(picks)} leaves of {len(tasks)} from |0...0>; t_leaf={t_leaf:.2f}s"},
+            _shot_check(rows))
+
+
 def noisy_cpu_baseline(w, tasks, picks, states, samples):
     """The oracle on a bounded sample of the noisy workload: the noiseless
     prefix once plus the trajectories `picks` (one with jumps, one without);
@@ -644,41 +706,16 @@ def noisy_cpu_baseline(w, tasks, picks, states, samples):
     t0 = time.perf_counter()
     base = oracle.simulate(w.n, w.prefix)
     t_prefix = time.perf_counter() - t0
-    rows = []
     t1 = time.perf_counter()
     refs = {k: oracle.apply_gates(base.copy(), w.n, tasks[k][len(w.prefix):]) for k in picks}
     t_traj = (time.perf_counter() - t1) / len(picks)
-    for k in picks:
-        ref = refs[k]
-        gs = states[k].astype(np.complex128)
-        o = oracle.sample(ref, w.n, w.seed, k, w.shots)
-        hg = np.bincount(samples[k], minlength=1 << w.n)
-        ho = np.bincount(o, minlength=1 << w.n)
-        cdf = np.cumsum(np.abs(ref) ** 2)
-        valid = 0
-        for s_, i in enumerate(samples[k]):
-            u = oracle.uniform(w.seed, k, s_) * cdf[-1]
-            lo = cdf[i - 1] if i > 0 else 0.0
-            valid += int(lo - 1e-6 <= u <= cdf[i] + 1e-6)
-        rows.append({"trajectory": int(k), "jumps": sum(1 for g in tasks[k] if g[0] == "RENORM"),
-                     "one_minus_fidelity": float(1.0 - oracle.fidelity(ref, gs)),
-                     "norm_drift": abs(float(np.vdot(gs, gs).real) - 1.0),
-                     "identical_shots": float(np.mean(o == samples[k])),
-                     "valid_shots": valid / w.shots,
-                     "tvd": float(0.5 * np.abs(hg - ho).sum() / w.shots)})
+    rows = _shot_rows(w.n, w.seed, w.shots, tasks, picks, refs, states, samples)
     T = len(tasks)
     base_rec = {"value": round(T / (t_prefix + T * t_traj), 4), "unit": "trajectories/s",
                 "cores": cores, "kind": "oracle",
                 "sample": f"prefix once ({len(w.prefix)} gates) + {len(picks)} trajectories of {T}; "
                           f"t_prefix={t_prefix:.2f}s t_traj={t_traj:.2f}s"}
-    # bars of the parity tests: FP32 amplitudes move the CDF by about 1e-6
-    # at 22 qubits, several outcome widths, so a shot may land on a
-    # neighbouring index; every shot must still be a valid inverse-CDF pick
-    # within 1e-6 of the oracle's CDF, and >= 99 % identical
-    check = {"trajectories": rows,
-             "bars": {"one_minus_fidelity": 1e-6, "identical_shots": 0.99, "valid_shots": 1.0},
-             "pass": all(r["one_minus_fidelity"] <= 1e-6 and r["identical_shots"] >= 0.99 and
-                         r["valid_shots"] == 1.0 for r in rows)}
+    check = _shot_check(rows)
     return base_rec, check
 
 
