@@ -404,6 +404,11 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
         return [nodes[u].end for u in anchor_chain(a)]
 
     t0 = time.perf_counter()
+    # expectations as the epilogue of the batch that ends every task (part of
+    # the terms reduced inside its last pass) when one batch ends them all in
+    # both modes: every task has the same number of cuts
+    fuse_terms = terms is not None and T > 0 and len({len(segment_cuts(t)) for t in range(T)}) == 1
+    fused_e = None
     if mode == "direct":
         # each task alone, cut at the same boundaries as the reuse plan
         st.reset(len(mats), T)
@@ -419,8 +424,11 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
                 if b1 > b0:
                     batch.append(plan.segment_array(tasks, t, b0, b1))
                     dsts.append(task_slots[t])
+            last = lev == levels and fuse_terms and dsts == task_slots
             if batch:
-                B.run_suffix_batch(ctx, None, batch, st, dsts)
+                e = B.run_suffix_batch(ctx, None, batch, st, dsts, terms=terms if last else None)
+                if last:
+                    fused_e = e
         ctx.sync()
         realized["suffix"] = (time.perf_counter() - t0) * 1e3
     else:
@@ -463,21 +471,25 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
             for t in direct:
                 st.reset(task_slots[t], 1)
         try:
-            B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
-                               expect_provs=provs if len(direct) < T else None)
+            fused_e = B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
+                                         expect_provs=provs if len(direct) < T else None,
+                                         terms=terms if fuse_terms else None)
         except B.QwRefused as r:
             # structured refusal: record it and rerun every task from |0...0>
             refusals.append(r.record)
             st.reset(len(mats), T)
-            B.run_suffix_batch(ctx, None, [plan.segment_array(tasks, t, 0, len(tasks[t]))
-                                           for t in range(T)], st, dsts)
+            fused_e = B.run_suffix_batch(ctx, None, [plan.segment_array(tasks, t, 0, len(tasks[t]))
+                                                     for t in range(T)], st, dsts,
+                                         terms=terms if fuse_terms else None)
         ctx.sync()
         realized["suffix"] = (time.perf_counter() - t1) * 1e3
         for s in snaps.values():
             s.free()
     t2 = time.perf_counter()
     res = ExecutionResult()
-    if terms is not None and T:
+    if fused_e is not None:
+        res.expectations = list(fused_e)
+    elif terms is not None and T:
         res.expectations = list(st.expect(len(mats), T, terms))
     if shots and T:
         res.samples = st.sample(len(mats), T, seed, 0, shots).reshape(T, shots)
@@ -563,6 +575,13 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
             return []
         return [u for u in path_to(nodes, vid) if u in slot_of]
 
+    # expectations as the epilogue of the batch that ends every task, under
+    # the same condition as run_workload (so both modes take the same path)
+    mat_set = set(plan.materialized)
+    ncuts = {len([u for u in path_to(nodes, plan.anchor[t]) if u in mat_set])
+             if plan.anchor[t] is not None else 0 for t in range(T)}
+    fuse = rw.exp_dev is not None and len(ncuts) == 1
+    fused = False
     ctx.begin_graph()
     try:
         if mode == "direct":
@@ -582,8 +601,11 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                     if b1 > b0:
                         batch.append(plan.segment_array(tasks, t, b0, b1))
                         dsts.append(task_slots[t])
+                last = lev == levels and fuse and dsts == task_slots
                 if batch:
-                    B.run_suffix_batch(ctx, None, batch, st, dsts)
+                    B.run_suffix_batch(ctx, None, batch, st, dsts, terms=terms if last else None,
+                                       out_dev=rw.exp_dev if last else None)
+                    fused = fused or last
         else:
             snaps: Dict[int, object] = {}
             by_depth: Dict[int, List[int]] = {}
@@ -620,8 +642,10 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
             for t in direct:
                 st.reset(task_slots[t], 1)
             B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
-                               expect_provs=provs if len(direct) < T else None)
-        if rw.exp_dev is not None:
+                               expect_provs=provs if len(direct) < T else None,
+                               terms=terms if fuse else None, out_dev=rw.exp_dev if fuse else None)
+            fused = fuse
+        if rw.exp_dev is not None and not fused:
             st.expect(len(mats), T, terms, out_dev=rw.exp_dev)
         if rw.samp_dev is not None:
             st.sample(len(mats), T, seed, 0, shots, out_dev=rw.samp_dev)
