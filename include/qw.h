@@ -243,7 +243,13 @@ int qw_ctx_kernel_stats(qw_ctx *ctx, int kernel, uint64_t *launches,
 
 /* ------------------------------------------------------------ states */
 /* qw_state_alloc: a state of n_qubits (1..30) with n_slots slots, every
- * slot set to |0...0>. If dev_buf is non-NULL it must be device memory of at
+ * slot set to |0...0>. The slots hold the task states of a workload: the
+ * boundary state |psi_B> that the shared prefix produces and the states
+ * every task's suffix continues into (Sec. I and Fig. 1; Sec. III-A
+ * "Execution": the prefix state is materialised once and reloaded for each
+ * suffix), all starting from the all-zero basis state the circuits assume.
+ * On a bad size, n_qubits or alignment: QW_E_INVALID_ARG; if the device
+ * allocation fails: QW_E_OOM; *out is written only on success. If dev_buf is non-NULL it must be device memory of at
  * least n_slots * 8 * 2^n bytes (dev_buf_bytes), 256-byte aligned; the state
  * is then a view and the caller keeps the buffer alive until qw_state_free.
  * If dev_buf is NULL the library allocates (hipMalloc) and frees it. */
@@ -306,20 +312,27 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src,
  * the total to *count. The record stays until the next such call. */
 int qw_outcomes(const qw_ctx *ctx, uint8_t *out, uint64_t cap, uint64_t *count);
 
-/* qw_expect_pauli: for each slot s in [first, first + count):
+/* qw_expect_pauli: the Pauli-sum expectation of each task state, the
+ * observable of the paper's variational workloads that evaluate one
+ * Hamiltonian repeatedly on many related circuits (the vqe_real and
+ * param_sweep families of Sec. V). For each slot s in [first, first + count):
  *   out[s - first] = sum_j coeff[j] * Re sum_i conj(psi[i ^ x_j]) *
  *                    i^{popcount(x_j & z_j)} * (-1)^{popcount(i & z_j)} psi[i]
  * i.e. sum_j c_j <P_j> with X on the bits of x_j only, Z on bits of z_j only
  * and Y on bits set in both. Masks and coefficients are host arrays; out is
  * host memory (out_is_host = 1; the call then synchronises) or device
  * memory. Products and sums are in FP64 with a fixed reduction order, so the
- * result does not depend on batch composition. */
+ * result does not depend on batch composition. Bad slots or a NULL array
+ * with n_terms > 0: QW_E_INVALID_ARG, nothing written. */
 int qw_expect_pauli(const qw_state *st, uint32_t first, uint32_t count,
                     const uint64_t *x_mask, const uint64_t *z_mask,
                     const double *coeff, uint32_t n_terms, double *out,
                     int out_is_host);
 
-/* qw_sample: `shots` Z-basis outcomes per slot. For slot first + k and shot
+/* qw_sample: `shots` Z-basis outcomes per slot: the multishot measurement
+ * of the noisy_multishot family (Sec. V; Sec. VI, Q1), where one
+ * materialised state is sampled for many shots instead of re-running the
+ * circuit per shot. For slot first + k and shot
  * s, u = (SplitMix64(seed ^ ((task_base + k) * 2^32 + s)) >> 11) * 2^-53 and
  * the outcome is the smallest basis index i with CDF_i > u * total, where
  * CDF_i is the FP64 running sum of |psi_j|^2 over j <= i and total = CDF of
@@ -327,7 +340,9 @@ int qw_expect_pauli(const qw_state *st, uint32_t first, uint32_t count,
  * of 2^10 amplitudes), then sums of 64-amplitude sub-chunks, then single
  * amplitudes; where rounding leaves u * total past the mass of the located
  * chunk or sub-chunk, its last index of non-zero probability is taken. out[k * shots + s] receives the index (uint32); out is
- * host (out_is_host = 1, call synchronises) or device memory. */
+ * host (out_is_host = 1, call synchronises) or device memory. count == 0 or
+ * shots == 0: QW_OK with nothing written; bad slots or a NULL out:
+ * QW_E_INVALID_ARG. */
 int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
               uint64_t seed, uint64_t task_base, uint32_t shots,
               uint32_t *out, int out_is_host);
@@ -367,9 +382,16 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
  *   0 in recording order; a qw_apply_prefix has one task), e.g. the angles
  *   of the next iteration of a variational loop. The gates are planned with
  *   the context's current options and must give the recorded pass
- *   structure (same gate kinds and qubits, angles free: the pass structure
- *   does not depend on angles); otherwise QW_E_INVALID_ARG and nothing
- *   changes. The call synchronises the context's stream and rewrites the
+ *   structure (same gate kinds and qubits); otherwise QW_E_INVALID_ARG and
+ *   nothing changes, and the caller records the new gates afresh. The
+ *   structure depends on the gate kinds and qubits, and on angle values
+ *   only in degenerate cases: a fused run of one-qubit gates whose FP64
+ *   product is exactly diagonal, exactly the identity or exactly a swap
+ *   (e.g. an angle of exactly 0) lowers to a cheaper op or to none, and
+ *   real rotations fused between two diagonal gates are rescaled to one-FMA
+ *   form unless their combined scale would pass 2^96 (two or more
+ *   rotations in a row, each within about 1e-9 of pi), which keeps the
+ *   plain form. The call synchronises the context's stream and rewrites the
  *   op records the graph's nodes read; later replays use the new gates.
  *   The provenance of snapshots recorded in the graph is not recomputed:
  *   it stays that of the gates at recording time. MEASURE and RESET gates

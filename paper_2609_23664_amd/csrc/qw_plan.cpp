@@ -236,11 +236,16 @@ std::vector<PassPick> greedy_passes(int n, int m, const std::vector<G> &gs, long
 // The phases are taken from fixed entries (a, d), falling back to the other
 // entry of the row/column only when that one is negligible, so the form of
 // the split (and of the kernels built from it) depends on the gate kinds,
-// not on the angles.
+// not on the angles. The fallback phase carries the sign that keeps R in the
+// rotation pattern [[c, -s], [s, c]] (s >= 0) that the fixed entries give a
+// unitary, so a rotation whose cosine is negligible (an angle of pi) still
+// lowers to a rotation, not a reflection.
 bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
     auto ph = [](cd z) { return z / std::abs(z); };
     auto small = [](double x) { return std::fabs(x) < 1e-13; };
-    auto pick = [&](cd first, cd other) { return std::abs(first) > 1e-9 ? ph(first) : ph(other); };
+    auto pick = [&](cd first, cd other, double sgn) {
+        return std::abs(first) > 1e-9 ? ph(first) : sgn * ph(other);
+    };
     // a real matrix is its own R (no sign-dependent phase factors)
     if (M.a.imag() == 0.0 && M.b.imag() == 0.0 && M.c.imag() == 0.0 && M.d.imag() == 0.0) {
         *D2 = {1.0, 0.0, 0.0, 1.0};
@@ -250,8 +255,8 @@ bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
     }
     // row phases: M = diag(p0, p1) * R
     {
-        cd p0 = pick(M.a, M.b);
-        cd p1 = pick(M.d, M.c);
+        cd p0 = pick(M.a, M.b, -1.0);
+        cd p1 = pick(M.d, M.c, 1.0);
         cd r00 = M.a / p0, r01 = M.b / p0, r10 = M.c / p1, r11 = M.d / p1;
         if (small(r00.imag()) && small(r01.imag()) && small(r10.imag()) && small(r11.imag())) {
             *D2 = {p0, 0.0, 0.0, p1};
@@ -262,8 +267,8 @@ bool split_real(const M2 &M, M2 *D2, M2 *R, M2 *D1) {
     }
     // column phases: M = R * diag(q0, q1)
     {
-        cd q0 = pick(M.a, M.c);
-        cd q1 = pick(M.d, M.b);
+        cd q0 = pick(M.a, M.c, 1.0);
+        cd q1 = pick(M.d, M.b, -1.0);
         cd r00 = M.a / q0, r01 = M.b / q1, r10 = M.c / q0, r11 = M.d / q1;
         if (small(r00.imag()) && small(r01.imag()) && small(r10.imag()) && small(r11.imag())) {
             *D2 = {1.0, 0.0, 0.0, 1.0};
@@ -436,8 +441,12 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
 // of those 1/|p|. The form never depends on the angle, so tasks that differ
 // only in angles keep one kernel; a large t costs no accuracy (the FMA
 // rounds x - t y once and t's rounding weighs |q y|, as in the plain
-// product). Only a group whose growth would pass 2^60 (angles within ~1e-9
-// of pi) keeps its remaining rotations in the plain form.
+// product). Only a group whose growth would pass 2^96 keeps its remaining
+// rotations in the plain form: one rotation grows by at most 2^53.9 (at
+// exactly pi, cos(pi/2) rounding to 6.1e-17), so that takes two rotations
+// within ~1e-9 of pi between two diagonal ops. The bound keeps amplitudes
+// below 2^96 (FP32 holds 2^128) and the folded factor above 2^-96 (FP32
+// normals reach 2^-126).
 void tangent_form(std::vector<HostOp> &ops) {
     double pending = 1.0, growth = 0.0;  // growth in log2, since the last diagonal op
     HostOp *last_diag = nullptr;
@@ -467,7 +476,7 @@ void tangent_form(std::vector<HostOp> &ops) {
         }
         if (form < 0 || a == 0.0) continue;
         const double g = std::max(-std::log2(std::fabs(a)), 0.0);
-        if (growth + g > 60.0) continue;
+        if (growth + g > 96.0) continue;
         growth += g;
         op.type = OP_URT;
         op.b = form;

@@ -63,11 +63,13 @@ def test_backward_matches_oracle(ctx, B):
     rel_bf = np.linalg.norm(g - gbf) / np.linalg.norm(gbf)
     rel_64 = np.linalg.norm(g - g64) / np.linalg.norm(g64)
     assert rel_bf <= 1e-4, rel_bf          # same rounding points, FP32 vs FP64 sums
-    # BF16 inputs vs exact FP64: each product input carries a relative error
-    # up to 2^-9, and cancellation in the mixed-sign sums of the chain rule
-    # magnifies it in the norm; a loose sanity bound (the mirror above is
-    # the parity check)
-    assert rel_64 <= 8e-2, rel_64
+    # BF16 inputs vs exact FP64: that distance belongs to the rounding points
+    # and the mirror computes it exactly; by the triangle inequality the GPU's
+    # own distance differs from the mirror's by at most the parity margin
+    # above, and the CPU pin bounds the mirror's at 5e-2 on these cases
+    mirror_64 = np.linalg.norm(gbf - g64) / np.linalg.norm(g64)
+    assert abs(rel_64 - mirror_64) <= rel_bf * np.linalg.norm(gbf) / np.linalg.norm(g64) + 1e-12
+    assert rel_64 <= 5e-2, rel_64
     # per block (weights and biases of each layer)
     o = 0
     for name, shp in M.SHAPES:

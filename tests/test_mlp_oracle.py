@@ -79,6 +79,27 @@ def test_bf16_mirror_differs_from_fp64_only_by_rounding():
     assert 1e-5 < rel < 3e-2
 
 
+@pytest.mark.parametrize("B", [16, 255, 1600])
+def test_bf16_mirror_distance_on_the_gpu_cases(B):
+    """The distance of the BF16-input gradient from the FP64 one is fixed by
+    the rounding points, not by a kernel: on the GPU test's own cases
+    (He-uniform weights of seed 4, inputs uniform in [0, 1), targets N(0, 1))
+    it lies below 5e-2. Each product input carries a relative error of at
+    most 2^-9; with 16 rows the weight gradients are sums of 16 products of
+    both signs, and their cancellation magnifies that error (3.8e-2 here),
+    while at 255 and 1,600 rows it stays near 5e-3. The GPU test bounds its
+    own distance by this one plus its parity margin against the mirror."""
+    from paper_2609_23664_amd.costmodel import init_params
+    p = init_params(4).astype(np.float64)
+    g = np.random.default_rng(100 + B)
+    x = g.uniform(0, 1, size=(B, M.IN)).astype(np.float32).astype(np.float64)
+    t = g.normal(size=(B, M.OUT)).astype(np.float32).astype(np.float64)
+    g64 = M.backward(p, x, t)
+    gbf = M.backward(p, x, t, bf16_inputs=True)
+    rel = np.linalg.norm(gbf - g64) / np.linalg.norm(g64)
+    assert 1e-5 < rel < 5e-2, rel
+
+
 def test_adam_first_step_moves_by_lr():
     p = np.zeros(4)
     g = np.array([1.0, -2.0, 0.5, 0.0])

@@ -6,6 +6,8 @@ this checks fusion, gate reordering, local-bit mapping and phase grouping
 independently of the GPU. Structural properties (passes per HEA layer, I/O
 phases, register sets) are checked too.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -307,3 +309,45 @@ def test_relabel_store_addresses_are_the_cnot_permutation():
             assert np.array_equal(addr, ref)
             checked += 1
     assert checked >= 3
+
+
+def test_special_angles_keep_the_structure_of_an_hea_suffix():
+    """One RY of a config-2 suffix set to pi, pi/2, 2 pi or -pi gives the
+    pass structure of generic angles: the one-FMA rotation form is chosen
+    from the gate kinds, and one rotation's scale (at most 2^53.9, at
+    exactly pi) is within the 2^60 bound. The documented exceptions change
+    the structure: every RY at pi (several rotations near pi between two
+    diagonal ops) and an angle of exactly 0 (RY(0) is exactly the identity
+    and drops out of the plan)."""
+    w = gen.config2()
+
+    def shape(pl):
+        return [[(o["type"], o["a"], o["b"], o["la"], o["lb"], o["sa"], o["sb"]) for o in p["ops"]]
+                for p in pl["passes"]]
+    ref = shape(B.plan_describe(24, w.suffixes[0]))
+    ry = [k for k, g in enumerate(w.suffixes[0]) if g[0] == "RY"]
+    for special in (math.pi, math.pi / 2, 2 * math.pi, -math.pi):
+        for k in (ry[0], ry[17], ry[-1]):
+            gates = list(w.suffixes[0])
+            gates[k] = (gates[k][0], gates[k][1], special)
+            assert shape(B.plan_describe(24, gates)) == ref, (special, k)
+    for special in (math.pi, 0.0):
+        gates = [(g[0], g[1], special if g[0] == "RY" else g[2]) for g in w.suffixes[0]]
+        assert shape(B.plan_describe(24, gates)) != ref, special
+
+
+@pytest.mark.parametrize("angles", [(math.pi, math.pi, math.pi), (1.0, 2.0, 0.5), (0.0, math.pi, 0.0)])
+def test_degenerate_angles_still_give_the_oracle_state(angles):
+    """Where angle values change the plan (several rotations near pi
+    between diagonal ops, exact identities), the described plan still
+    computes the oracle's state."""
+    n = 12
+    g = np.random.default_rng(2)
+    gates = [("RY", (q,), float(g.uniform(0, 2 * math.pi))) for q in range(n)]
+    gates += [("RY", (3,), angles[0]), ("RY", (5,), angles[1]), ("CNOT", (3, 5), 0.0),
+              ("RY", (7,), angles[2]), ("RZ", (7,), 0.3), ("RY", (7,), angles[0])]
+    for tile in (10, 12):
+        plan = B.plan_describe(n, gates, tile)
+        psi = interpret(n, plan, oracle.zero_state(n))
+        ref = oracle.simulate(n, gates)
+        assert oracle.fidelity(psi, ref) >= 1 - 1e-12
