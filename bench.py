@@ -37,8 +37,12 @@ def _parse():
                          "(measured 1 %% faster), 1 for the gate sweep (measured 9 %% faster)")
     ap.add_argument("--no-tune", action="store_true",
                     help="trie workload: skip the timing autotuner (default options)")
-    ap.add_argument("--cpu-tasks", type=int, default=8,
+    ap.add_argument("--cpu-tasks", type=int, default=4,
                     help="tasks in the oracle's bounded CPU sample")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="VQE line: skip the gate-sweep bandwidth rows (24..28 qubits)")
+    ap.add_argument("--cpu-leg", type=int, default=0,
+                    help=argparse.SUPPRESS)   # child process: one timed oracle leg (threads)
     ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy", "qec", "stab"],
                     help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "
                          "tree, 512 leaves, 1024 shots; noisy: 22-qubit 256 trajectories, 1024 "
@@ -100,6 +104,9 @@ def bench_copy(args):
 
 def main():
     args = _parse()
+    if args.cpu_leg:
+        _cpu_leg_child(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -258,8 +265,20 @@ def main():
     if red[0]:
         result["reducer"] = {"launches": red[0], "avg_launch_ms": round(red[1] / red[0], 4),
                              "GB/s": round(red[2] / (red[1] * 1e-3) / 1e9, 1)}
+    gpu = None
     if not args.no_cpu_baseline:
         gpu = [(st.host(t + 1), e_r[t]) for t in range(min(args.cpu_tasks, T))]
+    st.free()
+    if dst is not None:
+        dst.free()
+    if not args.no_sweep:
+        # the metric's second half: gate-pass HBM bandwidth at >= 4 GiB
+        # working sets (24, 26, 28 qubits), single gates and the fused
+        # 24-gate slab, with non-temporal loads (the sweep's measured best)
+        ctx_s = B.Ctx(0)
+        ctx_s.set_option(B.QW_OPT_STREAM_LOADS, 1)
+        result["gate_sweep"] = _sweep_summary(_sweep_rows(ctx_s, (24, 26, 28)))
+    if not args.no_cpu_baseline:
         result["cpu_baseline"], result["oracle_check"] = cpu_baseline(w, args.cpu_tasks, gpu)
     print(json.dumps(result), flush=True)
 
@@ -269,20 +288,20 @@ def _median(xs):
     return xs[len(xs) // 2]
 
 
-def bench_sweep(args):
-    """Gate-pass HBM bandwidth: single gates on qubits across the index
-    (low, lane, register, high), passes of 1/8/24 gates, at 20..28 qubits,
-    with enough slots (>= 4 GiB working set, <= 64 slots) to defeat the
-    256 MB last-level cache. GB/s = algorithmic bytes (each pass reads and
+def _sweep_rows(ctx, sizes):
+    """Gate-pass rows at the qubit counts `sizes`: single RY gates on qubits
+    across the index (low, lane, register, high), a pass of 8 low gates and
+    the 24-gate HEA slab (8 RY+RZ pairs, a 7-CNOT ladder, one more RY: one
+    fused pass), each run over enough slots that the working set is at least
+    4 GiB (beyond the 256 MB last-level cache), plus a torch device copy of
+    the same working set. GB/s = algorithmic bytes (each pass reads and
     writes the state once) / kernel time (HIP events around each launch)."""
     import torch
     from paper_2609_23664_amd import binding as B
-    ctx = B.Ctx(0)
-    ctx.set_option(B.QW_OPT_STREAM_LOADS, 1 if args.stream_loads is None else args.stream_loads)
     rows = []
-    for n in (20, 22, 24, 26, 28):
+    for n in sizes:
         sb = 8 << n
-        slots = max(1, min(64, (4 << 30) // sb))
+        slots = max(1, (4 << 30) // sb)
         st = B.State(ctx, n, slots)
         qs = sorted({0, 1, 2, 3, 4, 8, 12, 16, 20, n - 1} & set(range(n)))
         cases = [(f"RY q{q}", [("RY", (q,), 0.3)]) for q in qs]
@@ -300,10 +319,9 @@ def bench_sweep(args):
             nl, ms, by = ctx.kernel_stats(0, True)
             ctx.set_option(B.QW_OPT_PROFILE, 0)
             rows.append({"n": n, "case": name, "gates": len(gates), "slots": slots,
+                         "working_set_GiB": round(slots * sb / 2 ** 30, 2),
                          "passes_per_call": nl // 5, "GB/s": round(by / (ms * 1e-3) / 1e9, 1)})
-        # copy bandwidth of the same working set (snapshot COPY kernel)
-        snap = st.snapshot(0, bytes(32), B.QW_SNAP_COPY)
-        snap.free()
+        st.free()
         a = torch.empty((slots, 1 << n), dtype=torch.complex64, device="cuda")
         b = torch.empty_like(a)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -314,14 +332,35 @@ def bench_sweep(args):
         e1.record()
         torch.cuda.synchronize()
         rows.append({"n": n, "case": "torch copy (reference)", "slots": slots,
+                     "working_set_GiB": round(slots * sb / 2 ** 30, 2),
                      "GB/s": round(2 * a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)})
         del a, b
-        st.free()
+    return rows
+
+
+def _sweep_summary(rows):
     gates_rows = [r for r in rows if "passes_per_call" in r]
+    copy_rows = [r for r in rows if "passes_per_call" not in r]
     med = _median([r["GB/s"] for r in gates_rows])
-    return {"metric": "gate-sweep HBM GB/s (median over cases)", "value": med, "unit": "GB/s",
-            "n_gpus": 1, "higher_is_better": True, "frac_of_8TBs": round(med / 8000.0, 4),
-            "min": min(r["GB/s"] for r in gates_rows), "max": max(r["GB/s"] for r in gates_rows),
+    slab = {str(r["n"]): {"GB/s": r["GB/s"], "frac": round(r["GB/s"] / 8000.0, 4)}
+            for r in gates_rows if r["case"] == "24 gates HEA slab"}
+    return {"median_GBps": med, "frac_of_8TBs": round(med / 8000.0, 4),
+            "min_GBps": min(r["GB/s"] for r in gates_rows), "max_GBps": max(r["GB/s"] for r in gates_rows),
+            "hea_slab_24_gates": slab,
+            "copy_GBps_median": _median([r["GB/s"] for r in copy_rows]) if copy_rows else None,
+            "cases": len(gates_rows), "sizes": sorted({r["n"] for r in rows})}
+
+
+def bench_sweep(args):
+    """Gate-pass HBM bandwidth at 20..28 qubits (rows of _sweep_rows)."""
+    from paper_2609_23664_amd import binding as B
+    ctx = B.Ctx(0)
+    ctx.set_option(B.QW_OPT_STREAM_LOADS, 1 if args.stream_loads is None else args.stream_loads)
+    rows = _sweep_rows(ctx, (20, 22, 24, 26, 28))
+    sm = _sweep_summary(rows)
+    return {"metric": "gate-sweep HBM GB/s (median over cases)", "value": sm["median_GBps"], "unit": "GB/s",
+            "n_gpus": 1, "higher_is_better": True, "frac_of_8TBs": sm["frac_of_8TBs"],
+            "min": sm["min_GBps"], "max": sm["max_GBps"], "hea_slab_24_gates": sm["hea_slab_24_gates"],
             "dtype": "c64", "data": "synthetic", "config": {"workload": "gate sweep 20..28q"},
             "rows": rows}
 
@@ -719,30 +758,93 @@ def noisy_cpu_baseline(w, tasks, picks, states, samples):
     return base_rec, check
 
 
-def cpu_baseline(w, k, gpu=None):
-    """The oracle (complex128, OpenMP over amplitudes) on a bounded sample:
-    the shared prefix once plus k tasks (suffix + Pauli-sum expectation);
-    tasks/s for the full workload is extrapolated as
-    T / (t_prefix + T * t_task). With `gpu` (the GPU's final states and
-    expectations of the same first tasks) it also returns their error
-    against the oracle: 1 - F, |E_gpu - E_oracle| / sum|c|, norm drift."""
-    import numpy as np
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_leg(w, k, prefix_gates=None, direct=True):
+    """Time the oracle (complex128, OpenMP over amplitudes, as many threads
+    as OMP_NUM_THREADS allows) on config 2: the prefix (its first
+    `prefix_gates` gates, scaled linearly to the whole prefix, when given),
+    k tasks' suffix + Pauli-sum expectation from the prefix state, and with
+    `direct` one task from |0...0> through prefix, suffix and expectation.
+    Returns the timings and the oracle's states and expectations."""
     import oracle
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    base = oracle.simulate(w.n, w.prefix)
-    t_prefix = time.perf_counter() - t0
+    pre = w.prefix if prefix_gates is None else w.prefix[:prefix_gates]
+    base = oracle.simulate(w.n, pre)
+    t_prefix = (time.perf_counter() - t0) * len(w.prefix) / len(pre)
     refs = []
     t1 = time.perf_counter()
     for t in range(k):
         psi = oracle.apply_gates(base.copy(), w.n, w.suffixes[t])
         refs.append((psi, oracle.expect(psi, w.n, w.terms)))
     t_task = (time.perf_counter() - t1) / k
+    rec = {"t_prefix_s": round(t_prefix, 3), "t_task_s": round(t_task, 3),
+           "prefix_timed_gates": len(pre), "tasks_timed": k}
+    if direct:
+        t2 = time.perf_counter()
+        psi = oracle.simulate(w.n, list(w.prefix) + list(w.suffixes[0]))
+        oracle.expect(psi, w.n, w.terms)
+        rec["t_direct_task_s"] = round(time.perf_counter() - t2, 3)
+    return rec, refs
+
+
+def _cpu_leg_child(args):
+    """Child process of the 1-thread leg (OMP_NUM_THREADS set by the parent):
+    prints the leg's timings as one JSON line. Imports no torch."""
+    from workloads import gen
+    w = gen.config2()
+    rec, _ = _oracle_leg(w, 1, prefix_gates=len(w.prefix) // 6, direct=False)
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(w, k, gpu=None):
+    """The oracle (complex128 C, OpenMP over amplitude pairs) timed on the
+    host's cores, on a bounded sample of config 2, in two legs:
+      all threads: the prefix once, k tasks (suffix + expectation) from it,
+        and one task from |0...0> (direct); tasks/s extrapolated to the 64
+        tasks as T / (t_prefix + T t_task) (reuse) and 1 / t_direct_task;
+      one thread (a child process): the first layer of the prefix, scaled to
+        its 6 layers, and one task; direct per task = t_prefix + t_task (the
+        same gate applications and expectation, from |0...0>).
+    `value` is the all-thread reuse leg. With `gpu` (the GPU's final states
+    and expectations of the first tasks) it also returns their error against
+    the oracle: 1 - F, |E_gpu - E_oracle| / sum|c|, norm drift."""
+    import subprocess
+    import numpy as np
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     T = w.n_tasks
-    base_rec = {"value": round(T / (t_prefix + T * t_task), 4), "unit": "tasks/s", "cores": cores,
-                "kind": "oracle",
-                "sample": f"prefix once ({len(w.prefix)} gates) + {k} task(s) of {T}; "
-                          f"t_prefix={t_prefix:.2f}s t_task={t_task:.2f}s"}
+    leg, refs = _oracle_leg(w, k)
+    all_t = dict(leg, threads=cores,
+                 reuse_tasks_per_s=round(T / (leg["t_prefix_s"] + T * leg["t_task_s"]), 4),
+                 direct_tasks_per_s=round(1.0 / leg["t_direct_task_s"], 4))
+    one = None
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", "1"], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        one.update(threads=1,
+                   reuse_tasks_per_s=round(T / (one["t_prefix_s"] + T * one["t_task_s"]), 5),
+                   direct_tasks_per_s=round(1.0 / (one["t_prefix_s"] + one["t_task_s"]), 5))
+    else:
+        one = {"error": (r.stderr or "")[-300:]}
+    base_rec = {"value": all_t["reuse_tasks_per_s"], "unit": "tasks/s", "cores": cores, "kind": "oracle",
+                "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+                "sample": f"all threads: prefix once ({len(w.prefix)} gates) + {k} of {T} tasks, and 1 task "
+                          f"direct from |0...0>; 1 thread: the prefix's first layer scaled x6 + 1 task, "
+                          f"direct = prefix + task; tasks/s extrapolated linearly to {T} tasks",
+                "legs": {"all_threads": all_t, "one_thread": one}}
     if gpu is None:
         return base_rec
     scale = sum(abs(c) for c, _, _ in w.terms)
@@ -755,7 +857,8 @@ def cpu_baseline(w, k, gpu=None):
     check = {"tasks": len(inf), "max_one_minus_fidelity": float(max(inf)),
              "max_expect_err_over_sum_abs_c": float(max(err)), "max_norm_drift": float(max(drift)),
              "bars": {"one_minus_fidelity": 1e-6, "expect_err_over_sum_abs_c": 1e-5},
-             "pass": bool(max(inf) <= 1e-6 and max(err) <= 1e-5)}
+             "pass": bool(max(inf) <= 1e-6 and max(err) <= 1e-5),
+             "note": "the first tasks here; all 64 are checked by the GPU parity tests"}
     return base_rec, check
 
 

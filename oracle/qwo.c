@@ -19,8 +19,12 @@
  *
  * Amplitude loops may run under OpenMP: each amplitude (pair) is updated by
  * one iteration with the same arithmetic whatever the thread count, so the
- * state is bitwise independent of the number of threads. Sums (norm,
- * expectation, CDF) are sequential.
+ * state is bitwise independent of the number of threads. The norm and the
+ * CDF are sequential sums. The expectation sum over i is split into a fixed
+ * number of consecutive index ranges (64 from 2^12 amplitudes on, else one),
+ * each summed in index order, and the range sums are added in range order:
+ * the same sum of the same terms whatever the thread count, with its
+ * rounding order fixed.
  */
 #include <complex.h>
 #include <math.h>
@@ -158,12 +162,24 @@ double qwo_expect_pauli(const cplx *psi, int n, uint64_t x, uint64_t z)
     cplx iy = 1.0;
     for (int k = 0; k < ny % 4; ++k)
         iy *= I;
-    cplx acc = 0.0;
-    for (uint64_t i = 0; i < dim; ++i) {
-        double sign = (popcount64(i & z) & 1) ? -1.0 : 1.0;
-        acc += conj(psi[i ^ x]) * iy * sign * psi[i];
+    enum { NR = 64 };
+    const int nr = dim >= 4096 ? NR : 1;
+    const uint64_t len = dim / (uint64_t)nr;
+    cplx part[NR];
+    int r;
+#pragma omp parallel for schedule(static)
+    for (r = 0; r < nr; ++r) {
+        cplx acc = 0.0;
+        for (uint64_t i = (uint64_t)r * len; i < (uint64_t)(r + 1) * len; ++i) {
+            double sign = (popcount64(i & z) & 1) ? -1.0 : 1.0;
+            acc += conj(psi[i ^ x]) * iy * sign * psi[i];
+        }
+        part[r] = acc;
     }
-    return creal(acc);
+    cplx tot = 0.0;
+    for (r = 0; r < nr; ++r)
+        tot += part[r];
+    return creal(tot);
 }
 
 /* SplitMix64 output function applied to state v (one increment, then mix). */

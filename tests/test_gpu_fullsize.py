@@ -16,6 +16,7 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 FID_TOL = 1e-6
+NORM_TOL = 1e-5   # |<psi|psi> - 1|; the derivation is in test_gpu_parity.py
 
 
 def say(*a):
@@ -33,11 +34,17 @@ def ctx():
     c.sync()
 
 
-def _check_against_oracle(n, tasks, samples, states, picks, seed, shots):
+def _check_against_oracle(n, tasks, samples, states, picks, seed, shots, refs=None):
     same = 0
+    worst = [0.0, 0.0]
     for k in picks:
-        ref = oracle.simulate(n, tasks[k])
-        assert 1 - oracle.fidelity(states[k].astype(np.complex128), ref) <= FID_TOL, k
+        ref = oracle.simulate(n, tasks[k]) if refs is None else refs(k)
+        g = states[k].astype(np.complex128)
+        inf = 1 - oracle.fidelity(g, ref)
+        drift = abs(float(np.vdot(g, g).real) - 1.0)
+        worst = [max(worst[0], inf), max(worst[1], drift)]
+        assert inf <= FID_TOL, k
+        assert drift <= NORM_TOL, k
         cdf = np.cumsum(np.abs(ref) ** 2)
         o = oracle.sample(ref, n, seed, k, shots)
         same += int(np.sum(o == samples[k]))
@@ -46,6 +53,8 @@ def _check_against_oracle(n, tasks, samples, states, picks, seed, shots):
             u = oracle.uniform(seed, k, s_) * cdf[-1]
             lo = cdf[i - 1] if i > 0 else 0.0
             assert lo - 1e-6 <= u <= cdf[i] + 1e-6, (k, s_)
+    say(f"  {len(picks)} tasks: worst 1-F={worst[0]:.2e} drift={worst[1]:.2e} "
+        f"identical shots {same / (len(picks) * shots):.5f}")
     assert same >= 0.99 * len(picks) * shots
 
 
@@ -70,7 +79,9 @@ def test_config3_full_size_graph(ctx):
     say("config3 full size: 20q, 512 leaves, 1024 shots, graphs")
     w = gen.config3()
     tasks = [w.leaf_path(k) for k in range(len(w.leaves))]
-    picks = (0, 301, len(tasks) - 1)
+    # 32 seeded leaves (the first and last among them), every suffix length
+    picks = sorted({0, len(tasks) - 1} | set(
+        np.random.default_rng(3031).choice(len(tasks), 30, replace=False).tolist()))
     out = _run_graphs(ctx, w.n, tasks, w.shots, w.seed, picks)
     (sp, stp), (sd, std) = out["plan"], out["direct"]
     assert sp.shape == (512, 1024)
@@ -86,11 +97,15 @@ def test_config4_full_size_graph(ctx):
     tasks = [list(w.prefix) + list(t) for t in w.trajectories]
     jumped = [t for t in range(len(tasks)) if list(w.trajectories[t]) != list(w.suffix)]
     clean = [t for t in range(len(tasks)) if list(w.trajectories[t]) == list(w.suffix)]
-    picks = (jumped[0], clean[0])
+    # every trajectory with a jump, and 16 seeded jump-free ones
+    picks = sorted(jumped + np.random.default_rng(4041).choice(clean, 16, replace=False).tolist())
+    say(f"  {len(jumped)} trajectories with jumps, {len(picks)} checked")
     out = _run_graphs(ctx, w.n, tasks, w.shots, w.seed, picks)
     (sp, stp), (sd, std) = out["plan"], out["direct"]
     assert sp.shape == (256, 1024)
     assert np.array_equal(sp, sd)
     for k in picks:
         assert np.array_equal(stp[k], std[k]), k
-    _check_against_oracle(w.n, tasks, sp, stp, picks, w.seed, w.shots)
+    base = oracle.simulate(w.n, w.prefix)   # the oracle's own reuse: bitwise its direct run
+    _check_against_oracle(w.n, tasks, sp, stp, picks, w.seed, w.shots,
+                          refs=lambda k: oracle.apply_gates(base.copy(), w.n, list(w.trajectories[k])))
