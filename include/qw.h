@@ -347,6 +347,27 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count,
               uint64_t seed, uint64_t task_base, uint32_t shots,
               uint32_t *out, int out_is_host);
 
+/* qw_sample_noalloc: qw_sample for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same outcomes (bitwise those of qw_sample),
+ * but every buffer beyond the state and `out` lives in a fixed device
+ * scratch of 64 MiB (QW_NOALLOC_SCRATCH_BYTES) that the library holds on
+ * each GPU it runs on until the process ends, and the call makes no device
+ * or host allocation of its own. It needs 256-byte-aligned room for
+ *   count pointers, 2 * count * 2^(n - 10) and count * 2^(n - 6) doubles,
+ *   count doubles, and with out_is_host = 1 count * shots indices
+ * (at 24 qubits about 2.3 MiB per slot: 27 slots; at 20 qubits 455); a
+ * larger request returns QW_E_INVALID_ARG with the sizes in qw_last_error()
+ * and enqueues nothing. Every call on a GPU uses that GPU's one scratch and
+ * leaves its last contents there (nothing in it needs to start at zero):
+ * calls that overlap on one GPU (other streams or contexts, other host
+ * threads) race and must be ordered by the caller. While a graph is being
+ * recorded it returns QW_E_UNSUPPORTED. */
+#define QW_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int qw_sample_noalloc(const qw_state *st, uint32_t first, uint32_t count,
+                      uint64_t seed, uint64_t task_base, uint32_t shots,
+                      uint32_t *out, int out_is_host);
+
 /* ------------------------------------------------------------ graphs
  * A workload's device work recorded once and replayed as one HIP graph
  * launch: the batched suffix scheduling of Sec. III-A (tasks that branch

@@ -60,7 +60,7 @@ EXPORTED = (
     "qw_jit_stats", "qw_version", "qw_outcomes", "qw_tableau_create", "qw_tableau_free",
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
     "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
-    "qw_graph_update_gates",
+    "qw_graph_update_gates", "qw_sample_noalloc",
 )
 
 
@@ -152,6 +152,7 @@ def lib() -> ctypes.CDLL:
         "qw_expect_pauli": ([vp, u32, u32, ctypes.POINTER(u64), ctypes.POINTER(u64),
                              ctypes.POINTER(ctypes.c_double), u32, vp, i32], i32),
         "qw_sample": ([vp, u32, u32, u64, u64, u32, vp, i32], i32),
+        "qw_sample_noalloc": ([vp, u32, u32, u64, u64, u32, vp, i32], i32),
         "qw_legality_check": ([ctypes.POINTER(QwArtifact), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_plan_describe": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.c_char_p, u64], i32),
         "qw_mlp_workspace_floats": ([u32], u64),
@@ -500,6 +501,21 @@ class State:
         out = np.empty(count * shots, dtype=np.uint32)
         self.ctx.check(lib().qw_sample(self.h, first, count, seed, task_base, shots,
                                        ctypes.c_void_p(out.ctypes.data), 1))
+        return out.reshape(count, shots)
+
+    def sample_noalloc(self, first: int, count: int, seed: int, task_base: int, shots: int,
+                       out_dev=None):
+        """qw_sample_noalloc: qw_sample through the library's fixed device
+        scratch (no allocation). Same arguments and results as sample()."""
+        import numpy as np
+        if out_dev is not None:
+            _check_dev(out_dev, self.ctx.torch.int32, count * shots)
+            self.ctx.check(lib().qw_sample_noalloc(self.h, first, count, seed, task_base, shots,
+                                                   ctypes.c_void_p(out_dev.data_ptr()), 0))
+            return None
+        out = np.empty(count * shots, dtype=np.uint32)
+        self.ctx.check(lib().qw_sample_noalloc(self.h, first, count, seed, task_base, shots,
+                                               ctypes.c_void_p(out.ctypes.data), 1))
         return out.reshape(count, shots)
 
     def host(self, slot: int):

@@ -1752,6 +1752,56 @@ int qw_sample(const qw_state *st, uint32_t first, uint32_t count, uint64_t seed,
     return QW_OK;
 }
 
+int qw_sample_noalloc(const qw_state *st, uint32_t first, uint32_t count, uint64_t seed,
+                      uint64_t task_base, uint32_t shots, uint32_t *out, int out_is_host) {
+    if (!st) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = st->ctx;
+    if (!slot_ok(st, first, count)) return fail(ctx, QW_E_INVALID_ARG, "slot range out of bounds");
+    if (count == 0 || shots == 0) return QW_OK;
+    if (!out) return fail(ctx, QW_E_INVALID_ARG, "out is NULL");
+    if (ctx->rec) return recording_unsupported(ctx, "qw_sample_noalloc");
+    const uint32_t n = st->n;
+    const uint32_t C = sample_chunk_bits(n);
+    const uint64_t chunks = 1ull << (n - C);
+    auto al = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+    // scratch layout: slot pointers, chunk sums, chunk prefixes, totals,
+    // sub-chunk sums, then the indices when they go to host memory
+    const uint64_t ap = al((uint64_t)count * sizeof(void *));
+    const uint64_t a1 = al((uint64_t)count * chunks * sizeof(double));
+    const uint64_t a2 = al((uint64_t)count * sizeof(double));
+    const uint64_t a3 = al((uint64_t)count * (1ull << (n - sample_sub_bits(n))) * sizeof(double));
+    const uint64_t ob = (uint64_t)count * shots * sizeof(uint32_t);
+    const uint64_t need = ap + 2 * a1 + a2 + a3 + (out_is_host ? al(ob) : 0);
+    if (need > kNoAllocScratchBytes) {
+        char b[200];
+        std::snprintf(b, sizeof b,
+                      "qw_sample_noalloc needs %llu bytes of scratch for %u slots of %u qubits "
+                      "and %u shots; its fixed scratch holds %llu",
+                      (unsigned long long)need, count, n, shots,
+                      (unsigned long long)kNoAllocScratchBytes);
+        return fail(ctx, QW_E_INVALID_ARG, b);
+    }
+    void *sp = nullptr;
+    HIP_TRY(ctx, noalloc_scratch(ctx->device, &sp), "scratch symbol lookup");
+    uint8_t *sb = static_cast<uint8_t *>(sp);
+    const float2 **ptrs = reinterpret_cast<const float2 **>(sb);
+    double *csum = reinterpret_cast<double *>(sb + ap);
+    double *cpre = reinterpret_cast<double *>(sb + ap + a1);
+    double *total = reinterpret_cast<double *>(sb + ap + 2 * a1);
+    double *ssum = reinterpret_cast<double *>(sb + ap + 2 * a1 + a2);
+    uint32_t *dout = out_is_host ? reinterpret_cast<uint32_t *>(sb + ap + 2 * a1 + a2 + a3) : out;
+    hipError_t e = launch_slot_ptrs(ctx->stream, ptrs, slot_ptr(st, first), st->slot_bytes, count);
+    if (e != hipSuccess) return hip_fail(ctx, e, "slot pointer launch");
+    e = launch_sample(ctx->stream, ptrs, count, n, csum, cpre, ssum, total, seed, task_base, shots,
+                      dout);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sample launch");
+    if (out_is_host) {
+        HIP_TRY(ctx, hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, ctx->stream), "result copy");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    }
+    return QW_OK;
+}
+
 struct qw_tableau {
     qw::Tableau t;
     explicit qw_tableau(int n) : t(n) {}

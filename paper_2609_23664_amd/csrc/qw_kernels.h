@@ -59,6 +59,14 @@ hipError_t launch_stab_export(hipStream_t st, float2 *psi, uint32_t n, uint64_t 
 hipError_t launch_sample(hipStream_t st, const float2 *const *slots, uint32_t n_slots,
                          uint32_t n, double *csum, double *cpre, double *ssum, double *total,
                          uint64_t seed, uint64_t task_base, uint32_t shots, uint32_t *out);
+// Bytes of the fixed device scratch of qw_sample_noalloc (qw_noalloc.hip).
+constexpr uint64_t kNoAllocScratchBytes = QW_NOALLOC_SCRATCH_BYTES;
+// Address of that scratch on `device` (looked up once per device with the
+// device current; later calls return the kept address).
+hipError_t noalloc_scratch(int device, void **ptr);
+// out[i] = base + i * stride for i < count (device array of slot pointers).
+hipError_t launch_slot_ptrs(hipStream_t st, const float2 **out, const void *base, uint64_t stride,
+                            uint32_t count);
 inline uint32_t sample_chunk_bits(uint32_t n) { return n < 10 ? n : 10; }
 inline uint32_t sample_sub_bits(uint32_t n) { return n < 6 ? n : 6; }
 // One-time kernel attributes (dynamic LDS limits).
