@@ -231,6 +231,23 @@ int qw_ctx_sync(qw_ctx *ctx);
 #define QW_OPT_FUSED_EPILOGUE 8
 #define QW_OPT_TILE_ORDER 9
 #define QW_OPT_STREAM_LOADS 10
+/*   QW_OPT_DEVICE_MEM_CAP bytes of device memory the context may hold: its
+ *                         states and snapshot copies (allocated by it or
+ *                         given by the caller), and its plan,
+ *                         scratch, second-state and measurement buffers
+ *                         (buffers handed to a recorded graph belong to the
+ *                         graph); a call that would pass
+ *                         it returns QW_E_OOM (each allocation is checked
+ *                         before the device work that needs it; a suffix
+ *                         batch refused this way may have written part of
+ *                         its destination slots), and the caller may retry
+ *                         with fewer slots or tasks per call. Setting it
+ *                         synchronises the stream and releases the plan,
+ *                         scratch, second-state and measurement buffers (they
+ *                         grow again as calls need them); refused while a
+ *                         graph is recorded. 0 = no cap, only the device's
+ *                         own limit. [0] */
+#define QW_OPT_DEVICE_MEM_CAP 11
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.
@@ -452,6 +469,19 @@ int qw_mlp_forward(qw_ctx *ctx, const float *params, const float *x, uint32_t ba
  * forward pass into work first). Batch reductions run in a fixed order. */
 int qw_mlp_backward(qw_ctx *ctx, const float *params, const float *x, const float *target,
                     uint32_t batch, float *work, float *grad);
+/* qw_mlp_backward on a gathered mini-batch: batch row b is row rows[b] of
+ * x and target (rows: host array of `batch` indices, each below n_rows, the
+ * row count of x and target; copied during the call). Indices out of range:
+ * QW_E_INVALID_ARG, nothing enqueued. The same gradient as qw_mlp_backward
+ * on the gathered rows. */
+int qw_mlp_backward_rows(qw_ctx *ctx, const float *params, const float *x, const float *target,
+                         uint32_t n_rows, const uint32_t *rows, uint32_t batch, float *work,
+                         float *grad);
+/* loss[0] (device double) = L = 1/(2B) sum_{b,j} (y[b][j] - t[b][j])^2 of
+ * the forward pass on the batch (which runs into work first), summed in
+ * FP64 in a fixed order. */
+int qw_mlp_loss(qw_ctx *ctx, const float *params, const float *x, const float *target,
+                uint32_t batch, float *work, double *loss);
 /* One Adam step (step counts from 1) on all QW_MLP_PARAMS parameters. */
 int qw_mlp_adam(qw_ctx *ctx, float *params, const float *grad, float *m, float *v, uint32_t step,
                 float lr, float beta1, float beta2, float eps);

@@ -29,7 +29,8 @@ from typing import Iterable, List, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "_qwo.so")
+# QWO_LIB: another build of the simulator to load (e.g. the sanitizer build)
+_LIB_PATH = os.environ.get("QWO_LIB") or os.path.join(HERE, "_qwo.so")
 
 # gate name -> code of qwo.c
 _CODES = {

@@ -12,7 +12,8 @@ import os
 from typing import Iterable, List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqw.so")
+# QW_LIB: another build of the library to load (e.g. the sanitizer build)
+LIB_PATH = os.environ.get("QW_LIB") or os.path.join(HERE, "libqw.so")
 
 QW_OK = 0
 QW_E_INVALID_ARG = 1
@@ -48,6 +49,7 @@ QW_OPT_SECOND_BUFFER_CAP = 7
 QW_OPT_FUSED_EPILOGUE = 8
 QW_OPT_TILE_ORDER = 9
 QW_OPT_STREAM_LOADS = 10
+QW_OPT_DEVICE_MEM_CAP = 11
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",
@@ -60,7 +62,7 @@ EXPORTED = (
     "qw_jit_stats", "qw_version", "qw_outcomes", "qw_tableau_create", "qw_tableau_free",
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
     "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
-    "qw_graph_update_gates", "qw_sample_noalloc",
+    "qw_graph_update_gates", "qw_sample_noalloc", "qw_mlp_backward_rows", "qw_mlp_loss",
 )
 
 
@@ -158,6 +160,8 @@ def lib() -> ctypes.CDLL:
         "qw_mlp_workspace_floats": ([u32], u64),
         "qw_mlp_forward": ([vp, vp, vp, u32, vp, vp], i32),
         "qw_mlp_backward": ([vp, vp, vp, vp, u32, vp, vp], i32),
+        "qw_mlp_backward_rows": ([vp, vp, vp, vp, u32, vp, u32, vp, vp], i32),
+        "qw_mlp_loss": ([vp, vp, vp, vp, u32, vp, vp], i32),
         "qw_mlp_adam": ([vp, vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float], i32),
         "qw_plan_cost": ([u32, ctypes.POINTER(QwGate), u64, u32, ctypes.POINTER(u64),

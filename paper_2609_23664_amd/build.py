@@ -1,9 +1,17 @@
 """Build libqw.so for gfx950 in-tree.
 
-    python -m paper_2609_23664_amd.build
+    python -m paper_2609_23664_amd.build [--sanitize]
 
 Compiles csrc/*.hip and csrc/*.cpp with hipcc (offload arch gfx950 only) and
 links ``paper_2609_23664_amd/libqw.so``. Always recompiles.
+
+``--sanitize`` builds ``libqw_asan.so`` instead, with the host code (the
+planner, generator, tableau and C ABI; device code unchanged) instrumented
+by AddressSanitizer and UndefinedBehaviorSanitizer, for host-only checks:
+
+    QW_LIB=paper_2609_23664_amd/libqw_asan.so ASAN_OPTIONS=detect_leaks=0 \
+    LD_PRELOAD=$(hipcc -print-file-name=libclang_rt.asan-x86_64.so) \
+    python -m pytest tests -m "not gpu"
 """
 from __future__ import annotations
 
@@ -53,37 +61,47 @@ def _embed() -> None:
             f.write(data)
 
 
-def _compile(src: str) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+# host-code sanitizers of the --sanitize build (each flag for the host pass only)
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+BUILD_ASAN = os.path.join(HERE, "_build_asan")
+OUT_ASAN = os.path.join(HERE, "libqw_asan.so")
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    bdir = BUILD_ASAN if sanitize else BUILD
+    os.makedirs(bdir, exist_ok=True)
+    obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
+    extra = SANITIZE if sanitize else []
     if src.endswith(".hip"):
-        cmd = [HIPCC, *DEVICE, *COMMON, "-c", path, "-o", obj]
+        cmd = [HIPCC, *DEVICE, *COMMON, *extra, "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-I", BUILD, "-x", "c++",
-               "-c", path, "-o", obj]
+        cmd = [HIPCC, *COMMON, *extra, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-I", BUILD, "-x",
+               "c++", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False) -> str:
     _embed()
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
-        objs = list(pool.map(_compile, SOURCES))
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, *DEVICE, "-shared", "-fPIC", *objs, "-o", tmp,
+        objs = list(pool.map(lambda src: _compile(src, sanitize), SOURCES))
+    out = OUT_ASAN if sanitize else OUT
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *DEVICE, "-shared", "-fPIC", *(SANITIZE if sanitize else []), *objs, "-o", tmp,
            "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT, flush=True)
-    return OUT
+        print("built", out, flush=True)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
     sys.exit(0)

@@ -9,10 +9,17 @@ more than `max_tasks` tasks are realized on their first `max_tasks` tasks
 and scaled linearly:
     t_direct(T) = t_direct(k) * T / k,
     t_reuse(T)  = t_prefix + (t_reuse(k) - t_prefix) * T / k.
-Kernels are the interpreted ones (QW_OPT_JIT = 0), so no compile time enters
-a label; each plan runs once untimed (plans cached) and the faster of two
-timed runs is kept. Run as a module to log the config-5 study:
+The execution is the one the planner governs: the default tiered kernels,
+after one untimed run of each plan with generated kernels for every pass
+structure (compiled, or read from the disk cache, outside the timing), so
+every timed pass runs a generated kernel and no compile time enters a label;
+then the faster of two timed runs of each plan (alternating) is kept. Each
+record carries the fingerprint of the kernel, planner and generator sources
+it was measured on (`kernel_fingerprint`). Run as a module to log the
+config-5 study:
     python -m paper_2609_23664_amd.cost_study --out costs.jsonl --count 2000
+`--precompile` compiles the workloads' generated kernels into the disk
+cache without a GPU (hipRTC only), in parallel processes.
 """
 from __future__ import annotations
 
@@ -57,6 +64,21 @@ def features(n: int, prefix: Sequence, suffixes: Sequence[Sequence], n_tasks: in
     return feature_vector(n, n_tasks, pp, sp, len(prefix), gs)
 
 
+def kernel_fingerprint() -> str:
+    """Hash of the library's kernel, planner and generator sources (csrc):
+    a realized cost describes the code it was measured on."""
+    import hashlib
+    import os
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def realize(ctx, n: int, prefix, suffixes, n_tasks: int) -> Dict[str, float]:
     """Realized ms of direct and reuse execution (scaled to n_tasks)."""
     from . import binding as B
@@ -64,18 +86,19 @@ def realize(ctx, n: int, prefix, suffixes, n_tasks: int) -> Dict[str, float]:
     k = len(suffixes)
     tasks = [list(prefix) + list(s) for s in suffixes]
     plan = plan_workload(n, tasks, decide=lambda *a: True)   # cuts at the shared prefix
-    ctx.set_option(B.QW_OPT_JIT, 0)
+    # one untimed run of each plan with generated kernels for every pass
+    # structure (compiled or loaded now; plans cached, first-touch effects);
+    # the timed runs then use the default tiered mode, which finds them
+    ctx.set_option(B.QW_OPT_JIT, 2)
     try:
-        # one untimed run of each plan (plans cached, first-touch effects),
-        # then two timed runs each, alternating; the faster run is kept
         run_workload(ctx, n, tasks, plan=plan, mode="direct")
         run_workload(ctx, n, tasks, plan=plan, mode="reuse")
-        rds, rrs = [], []
-        for _ in range(2):
-            rds.append(run_workload(ctx, n, tasks, plan=plan, mode="direct")[2])
-            rrs.append(run_workload(ctx, n, tasks, plan=plan, mode="reuse")[2])
     finally:
         ctx.set_option(B.QW_OPT_JIT, 1)
+    rds, rrs = [], []
+    for _ in range(2):
+        rds.append(run_workload(ctx, n, tasks, plan=plan, mode="direct")[2])
+        rrs.append(run_workload(ctx, n, tasks, plan=plan, mode="reuse")[2])
     rd = min(rds, key=lambda r: r.realized_ms["total"])
     rr = min(rrs, key=lambda r: r.realized_ms["total"])
     td = rd.realized_ms["total"] * n_tasks / k
@@ -90,11 +113,18 @@ def main(argv=None):
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--max-tasks", type=int, default=16)
+    ap.add_argument("--last", type=int, default=None, help="stop before this workload index")
+    ap.add_argument("--precompile", type=int, default=0,
+                    help="compile the generated kernels of the workloads with this many processes "
+                         "(no GPU), then exit")
     args = ap.parse_args(argv)
-    from . import binding as B
     from workloads import gen
+    specs = gen.config5_specs(args.count)[args.first:args.last]
+    if args.precompile:
+        return precompile(specs, args.max_tasks, args.precompile)
+    from . import binding as B
     ctx = B.Ctx(0)
-    specs = gen.config5_specs(args.count)[args.first:]
+    fp = kernel_fingerprint()
     t0 = time.time()
     with open(args.out, "a") as f:
         for i, s in enumerate(specs):
@@ -103,13 +133,44 @@ def main(argv=None):
             r = realize(ctx, w.n, w.prefix, w.suffixes, s.n_tasks)
             rec = {"index": s.index, "n": s.n, "tasks": s.n_tasks, "prefix_layers": s.prefix_layers,
                    "total_layers": s.total_layers, "spread": s.spread, "negative": s.negative,
-                   "features": feats, **r}
+                   "features": feats, **r, "kernels": "tiered, generated (warm)", "fingerprint": fp}
             f.write(json.dumps(rec) + "\n")
             f.flush()
             if i % 50 == 0:
                 print(f"[cost-study] {i + args.first}/{args.count} n={s.n} T={s.n_tasks} "
                       f"direct={r['t_direct_ms']:.2f}ms reuse={r['t_reuse_ms']:.2f}ms "
                       f"elapsed={time.time() - t0:.0f}s", flush=True)
+    return 0
+
+
+def _precompile_lists(item):
+    n, lists = item
+    from . import binding as B
+    for g in lists:
+        B.jit_precompile(n, g, 14)
+    return len(lists)
+
+
+def precompile(specs, max_tasks: int, procs: int) -> int:
+    """Compile (hipRTC, no GPU) the generated pass kernels of every distinct
+    gate-list structure of `specs` (prefixes and suffixes; the direct path
+    cuts at the same boundary, so it runs the same passes) into the disk
+    cache, split over `procs` processes."""
+    import multiprocessing as mp
+    from workloads import gen
+    seen, by_n = set(), {}
+    for s in specs:
+        w = gen.config5_workload(s, max_tasks=max_tasks)
+        for g in [w.prefix] + list(w.suffixes):
+            sig = (w.n, tuple((x[0], tuple(x[1])) for x in g))
+            if g and sig not in seen:
+                seen.add(sig)
+                by_n.setdefault(w.n, []).append(list(g))
+    items = [(n, [g]) for n, gs in sorted(by_n.items()) for g in gs]
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        done = sum(pool.imap_unordered(_precompile_lists, items))
+    print(f"[cost-study] precompiled {done} gate lists in {time.time() - t0:.0f}s", flush=True)
     return 0
 
 

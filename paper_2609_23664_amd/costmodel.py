@@ -111,6 +111,17 @@ class MLP:
                                                self.g.data_ptr()))
         return self.g
 
+    def backward_rows(self, x_dev, t_dev, rows: np.ndarray):
+        """Gradient on the mini-batch of rows `rows` (host indices) of the
+        device arrays x_dev, t_dev: the library gathers them in its kernels."""
+        import ctypes
+        rows = np.ascontiguousarray(rows, dtype=np.uint32)
+        bsz = len(rows)
+        self.ctx.check(B.lib().qw_mlp_backward_rows(
+            self.ctx.h, self.p.data_ptr(), x_dev.data_ptr(), t_dev.data_ptr(), int(x_dev.shape[0]),
+            ctypes.c_void_p(rows.ctypes.data), bsz, self._ws(bsz).data_ptr(), self.g.data_ptr()))
+        return self.g
+
     def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
         self.step += 1
         self.ctx.check(B.lib().qw_mlp_adam(self.ctx.h, self.p.data_ptr(), self.g.data_ptr(),
@@ -133,10 +144,9 @@ class MLP:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(epochs):
-            perm = torch.tensor(g.permutation(n), device=dev)
+            perm = g.permutation(n)
             for s in range(0, n, batch):
-                idx = perm[s:s + batch]
-                self.backward(xd[idx].contiguous(), yd[idx].contiguous())
+                self.backward_rows(xd, yd, perm[s:s + batch])
                 self.adam(lr)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -144,8 +154,12 @@ class MLP:
                 "loss_final": self.loss(xd, yd)}
 
     def loss(self, xd, yd) -> float:
-        y = self.forward(xd)
-        return float(((y - yd) ** 2).sum().item()) / (2 * len(xd))
+        """1/(2B) sum (y - t)^2 over all rows (the library's loss kernel)."""
+        bsz = int(xd.shape[0])
+        out = self.torch.empty(1, dtype=self.torch.float64, device=self.p.device)
+        self.ctx.check(B.lib().qw_mlp_loss(self.ctx.h, self.p.data_ptr(), xd.data_ptr(), yd.data_ptr(),
+                                           bsz, self._ws(bsz).data_ptr(), out.data_ptr()))
+        return float(out.cpu().item())
 
     def predict(self, x: np.ndarray) -> np.ndarray:
         """Raw targets (log-ratio correction, log t_reuse) for features x."""

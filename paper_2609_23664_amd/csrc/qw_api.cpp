@@ -42,6 +42,8 @@ struct PlanEntry {
     bool relabel = true;
     bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
+    uint64_t mem_cap = 0;        // QW_OPT_DEVICE_MEM_CAP (0: none)
+    uint64_t held = 0;           // bytes of the states and snapshot copies it allocated
     std::vector<char> gates;  // the gate records the plan was built from
     std::shared_ptr<const qw::Plan> plan;
 };
@@ -104,6 +106,8 @@ struct qw_ctx {
     bool stream_loads = true;    // QW_OPT_STREAM_LOADS
     bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
+    uint64_t mem_cap = 0;        // QW_OPT_DEVICE_MEM_CAP (0: none)
+    uint64_t held = 0;           // bytes of the states and snapshot copies it allocated
     void *staging = nullptr;
     size_t staging_cap = 0;
     hipEvent_t staging_ev = nullptr;
@@ -133,6 +137,7 @@ struct qw_snap {
     uint32_t fslot = 0;
     const qw_snap *parent = nullptr;
     int mode = QW_SNAP_COPY;
+    uint64_t counted = 0;  // bytes of a COPY counted toward the context's cap
 };
 
 namespace {
@@ -160,12 +165,38 @@ int hip_fail(qw_ctx *ctx, hipError_t e, const char *what) {
         if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
     } while (0)
 
+// Device bytes the context holds: its states and snapshot copies (allocated
+// by it or by the caller), and its plan, scratch,
+// second-state and measurement buffers (buffers handed to a recorded graph
+// belong to the graph).
+uint64_t ctx_bytes(const qw_ctx *ctx) {
+    return ctx->held + ctx->plan.cap + ctx->scratch.cap + ctx->pingpong.cap + ctx->meas.cap;
+}
+
+// QW_OPT_DEVICE_MEM_CAP: refuse an allocation of `want` bytes (replacing
+// `released` bytes of the context's) that would take the context past its
+// cap, before any device work of the call.
+int cap_check(qw_ctx *ctx, uint64_t want, uint64_t released, const char *what) {
+    if (!ctx->mem_cap) return QW_OK;
+    const uint64_t now = ctx_bytes(ctx) - std::min(released, ctx_bytes(ctx));
+    if (now + want <= ctx->mem_cap) return QW_OK;
+    char b[256];
+    std::snprintf(b, sizeof b, "%s: %llu bytes would take the context to %llu bytes, past its device "
+                  "memory cap of %llu", what, (unsigned long long)want,
+                  (unsigned long long)(now + want), (unsigned long long)ctx->mem_cap);
+    return fail(ctx, QW_E_OOM, b);
+}
+
 // While recording, a buffer is never freed or rewritten behind the graph's
 // back: a buffer that is too small (or a plan buffer that already holds an
 // uploaded blob) is set aside for the graph and replaced by a new one.
 int ensure_recording(qw_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
     const bool is_plan = &b == &ctx->plan;
     if (b.cap >= bytes && !(is_plan && ctx->rec->plan_used)) return QW_OK;
+    {
+        int rc = cap_check(ctx, (std::max<size_t>(bytes, 256) + 4095) & ~size_t(4095), b.cap, what);
+        if (rc) return rc;
+    }
     if (b.p) ctx->rec->owned.push_back(b.p);
     b.p = nullptr;
     b.cap = 0;
@@ -184,6 +215,12 @@ int ensure(qw_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
     if (b.cap >= bytes) return QW_OK;
     size_t want = std::max(bytes, b.cap * 2);
     want = (want + 4095) & ~size_t(4095);
+    if (ctx->mem_cap && cap_check(ctx, want, b.cap, what) != QW_OK) {
+        // doubling would pass the cap: try the size asked for
+        want = (bytes + 4095) & ~size_t(4095);
+        int rc = cap_check(ctx, want, b.cap, what);
+        if (rc) return rc;
+    }
     if (b.p) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync before regrow");
         HIP_TRY(ctx, hipFree(b.p), "free scratch");
@@ -521,6 +558,8 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 if (rc0) return rc0;
             }
             if (ctx->pingpong.cap < want) {
+                int rc0 = cap_check(ctx, want, ctx->pingpong.cap, "second state buffers");
+                if (rc0) return rc0;
                 if (ctx->pingpong.p) {
                     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync before regrow");
                     HIP_TRY(ctx, hipFree(ctx->pingpong.p), "free second buffers");
@@ -1396,6 +1435,18 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         if (value <= 0) return fail(ctx, QW_E_INVALID_ARG, "second buffer cap must be > 0");
         ctx->pingpong_cap = (uint64_t)value;
         return QW_OK;
+    case QW_OPT_DEVICE_MEM_CAP:
+        if (value < 0) return fail(ctx, QW_E_INVALID_ARG, "device memory cap must be >= 0");
+        if (ctx->rec) return recording_unsupported(ctx, "a new device memory cap");
+        // the context's buffers are released, to grow again within the cap
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+        for (DevBuf *b : {&ctx->plan, &ctx->scratch, &ctx->pingpong, &ctx->meas}) {
+            if (b->p) HIP_TRY(ctx, hipFree(b->p), "free buffer");
+            b->p = nullptr;
+            b->cap = 0;
+        }
+        ctx->mem_cap = (uint64_t)value;
+        return QW_OK;
     default: return fail(ctx, QW_E_INVALID_ARG, "unknown option");
     }
 }
@@ -1445,18 +1496,26 @@ int qw_state_alloc(qw_ctx *ctx, uint32_t n, uint32_t n_slots, void *dev_buf,
     st->n_slots = n_slots;
     st->slot_bytes = slot_bytes;
     st->frozen.assign(n_slots, 0);
+    {
+        // a caller buffer counts toward the cap like the library's own
+        int rc = cap_check(ctx, need, 0, dev_buf ? "state" : "state allocation");
+        if (rc) return rc;
+    }
     if (dev_buf) {
         st->base = static_cast<char *>(dev_buf);
+        ctx->held += need;
     } else {
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, need);
         if (e != hipSuccess) return hip_fail(ctx, e, "state allocation");
         st->base = static_cast<char *>(p);
         st->owned = true;
+        ctx->held += need;
     }
     hipError_t e = launch_init(ctx->stream, st->base, n, n_slots);
     if (e != hipSuccess) {
         if (st->owned) hipFree(st->base);
+        ctx->held -= need;
         return hip_fail(ctx, e, "init launch");
     }
     *out = st.release();
@@ -1472,6 +1531,7 @@ int qw_state_free(qw_state *st) {
         hipStreamSynchronize(st->ctx->stream);
         hipFree(st->base);
     }
+    st->ctx->held -= st->slot_bytes * st->n_slots;
     delete st;
     return QW_OK;
 }
@@ -1547,15 +1607,24 @@ int qw_snapshot(qw_state *st, uint32_t slot, const uint8_t provenance[32], int m
             if (copy_buf_bytes < st->slot_bytes) return fail(ctx, QW_E_INVALID_ARG, "copy_buf too small");
             if (reinterpret_cast<uintptr_t>(dst) & 255u)
                 return fail(ctx, QW_E_INVALID_ARG, "copy_buf must be 256-byte aligned");
-        } else {
+        }
+        {
+            // a caller copy buffer counts toward the cap like the library's own
+            int rc = cap_check(ctx, st->slot_bytes, 0, dst ? "snapshot copy" : "snapshot allocation");
+            if (rc) return rc;
+        }
+        if (!dst) {
             hipError_t e = hipMalloc(&dst, st->slot_bytes);
             if (e != hipSuccess) return hip_fail(ctx, e, "snapshot allocation");
             s->owned = dst;
         }
+        ctx->held += st->slot_bytes;
+        s->counted = st->slot_bytes;
         ProfScope ps(ctx, 3, 2.0 * (double)st->slot_bytes);
         hipError_t e = launch_copy(ctx->stream, dst, slot_ptr(st, slot), st->slot_bytes);
         if (e != hipSuccess) {
             if (s->owned) hipFree(s->owned);
+            ctx->held -= st->slot_bytes;
             return hip_fail(ctx, e, "snapshot copy");
         }
         s->data = dst;
@@ -1572,6 +1641,7 @@ int qw_snapshot_free(qw_snap *s) {
         hipStreamSynchronize(s->ctx->stream);
         hipFree(s->owned);
     }
+    s->ctx->held -= s->counted;
     delete s;
     return QW_OK;
 }
@@ -1912,7 +1982,7 @@ uint64_t qw_mlp_workspace_floats(uint32_t batch) { return mlp_workspace_floats(b
 int qw_mlp_forward(qw_ctx *ctx, const float *params, const float *x, uint32_t batch, float *work,
                    float *y) {
     if (!ctx || !params || (batch && (!x || !work || !y))) return QW_E_INVALID_ARG;
-    hipError_t e = launch_mlp_forward(ctx->stream, params, x, batch, work, y);
+    hipError_t e = launch_mlp_forward(ctx->stream, params, x, nullptr, batch, work, y);
     return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp forward");
 }
 
@@ -1920,8 +1990,35 @@ int qw_mlp_backward(qw_ctx *ctx, const float *params, const float *x, const floa
                     uint32_t batch, float *work, float *grad) {
     if (!ctx || !params || !grad || (batch && (!x || !target || !work))) return QW_E_INVALID_ARG;
     if (batch == 0) return fail(ctx, QW_E_INVALID_ARG, "batch must be >= 1");
-    hipError_t e = launch_mlp_backward(ctx->stream, params, x, target, batch, work, grad);
+    hipError_t e = launch_mlp_backward(ctx->stream, params, x, target, nullptr, batch, work, grad);
     return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp backward");
+}
+
+int qw_mlp_backward_rows(qw_ctx *ctx, const float *params, const float *x, const float *target,
+                         uint32_t n_rows, const uint32_t *rows, uint32_t batch, float *work,
+                         float *grad) {
+    if (!ctx || !params || !grad || !x || !target || !work || !rows) return QW_E_INVALID_ARG;
+    if (batch == 0) return fail(ctx, QW_E_INVALID_ARG, "batch must be >= 1");
+    for (uint32_t b = 0; b < batch; ++b)
+        if (rows[b] >= n_rows)
+            return fail(ctx, QW_E_INVALID_ARG,
+                        "row " + std::to_string(rows[b]) + " of batch entry " + std::to_string(b) +
+                            " is not below n_rows = " + std::to_string(n_rows));
+    std::vector<uint8_t> blob(batch * sizeof(uint32_t));
+    std::memcpy(blob.data(), rows, blob.size());
+    int rc = upload(ctx, blob);
+    if (rc) return rc;
+    hipError_t e = launch_mlp_backward(ctx->stream, params, x, target,
+                                       static_cast<const uint32_t *>(ctx->plan.p), batch, work, grad);
+    return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp backward (rows)");
+}
+
+int qw_mlp_loss(qw_ctx *ctx, const float *params, const float *x, const float *target,
+                uint32_t batch, float *work, double *loss) {
+    if (!ctx || !params || !x || !target || !work || !loss) return QW_E_INVALID_ARG;
+    if (batch == 0) return fail(ctx, QW_E_INVALID_ARG, "batch must be >= 1");
+    hipError_t e = launch_mlp_loss(ctx->stream, params, x, target, nullptr, batch, work, loss);
+    return e == hipSuccess ? QW_OK : hip_fail(ctx, e, "mlp loss");
 }
 
 int qw_mlp_adam(qw_ctx *ctx, float *params, const float *grad, float *m, float *v, uint32_t step,

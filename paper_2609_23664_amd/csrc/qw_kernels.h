@@ -75,10 +75,15 @@ hipError_t kernels_init();
 // Learned cost model (qw_mlp.hip): forward, backward (gradient of
 // L = 1/(2B) sum (y - t)^2 into grad[QW_MLP_PARAMS]) and Adam, all on st.
 size_t mlp_workspace_floats(uint32_t batch);
-hipError_t launch_mlp_forward(hipStream_t st, const float *p, const float *x, uint32_t B, float *ws,
-                              float *y);
+// `rows` (device, may be NULL): batch row b reads input and target row
+// rows[b] (a gathered mini-batch) instead of row b.
+hipError_t launch_mlp_forward(hipStream_t st, const float *p, const float *x, const uint32_t *rows,
+                              uint32_t B, float *ws, float *y);
 hipError_t launch_mlp_backward(hipStream_t st, const float *p, const float *x, const float *t,
-                               uint32_t B, float *ws, float *grad);
+                               const uint32_t *rows, uint32_t B, float *ws, float *grad);
+// Forward pass, then out[0] = 1/(2B) sum (y - t)^2 in FP64 (fixed order).
+hipError_t launch_mlp_loss(hipStream_t st, const float *p, const float *x, const float *t,
+                           const uint32_t *rows, uint32_t B, float *ws, double *out);
 hipError_t launch_mlp_adam(hipStream_t st, float *p, const float *g, float *m, float *v,
                            uint32_t step, float lr, float b1, float b2, float eps);
 

@@ -64,9 +64,16 @@ __device__ __forceinline__ f32x4 tile_gemm(int K, FA a, FB b) {
 }
 
 // Forward pass for 16 rows per wave: Z1, Z2 (pre-activations) and Y.
+// Batch row b reads row src_row(rows, b) of the inputs and targets: rows[b]
+// when a row list is given (a gathered mini-batch), else b.
+__device__ __forceinline__ size_t src_row(const uint32_t *__restrict__ rows, int b) {
+    return rows ? (size_t)rows[b] : (size_t)b;
+}
+
 __global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict__ p,
-                                                         const float *__restrict__ x, uint32_t B,
-                                                         float *__restrict__ ws,
+                                                         const float *__restrict__ x,
+                                                         const uint32_t *__restrict__ rows,
+                                                         uint32_t B, float *__restrict__ ws,
                                                          float *__restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int row0 = blockIdx.x * 16;
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict
     // layer 1: Z1 = X W1 + b1
     for (int t = 0; t < W / 16; ++t) {
         f32x4 acc = tile_gemm(IN,
-            [&](int m, int k) { return rowok(m) ? x[(size_t)(row0 + m) * IN + k] : 0.f; },
+            [&](int m, int k) { return rowok(m) ? x[src_row(rows, row0 + m) * IN + k] : 0.f; },
             [&](int k, int j) { return p[OFF_W1 + k * W + 16 * t + j]; });
         #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -121,6 +128,7 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict
 // dY = (Y - T) / B, dZ2 = (dY W3^T) * [Z2 > 0], dZ1 = (dZ2 W2^T) * [Z1 > 0].
 __global__ __launch_bounds__(64) void mlp_backward_rows_kernel(const float *__restrict__ p,
                                                                const float *__restrict__ tgt,
+                                                               const uint32_t *__restrict__ rows,
                                                                uint32_t B, float *__restrict__ ws) {
     const int lane = threadIdx.x & 63;
     const int row0 = blockIdx.x * 16;
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(64) void mlp_backward_rows_kernel(const float *__re
         const int m = e / OUT, j = e % OUT;
         if (rowok(m)) {
             float *r = ws + (size_t)(row0 + m) * WS_ROW;
-            r[WS_DY + j] = (r[WS_Y + j] - tgt[(size_t)(row0 + m) * OUT + j]) * invB;
+            r[WS_DY + j] = (r[WS_Y + j] - tgt[src_row(rows, row0 + m) * OUT + j]) * invB;
         }
     }
     __syncthreads();
@@ -169,6 +177,7 @@ __global__ __launch_bounds__(64) void mlp_backward_rows_kernel(const float *__re
 // sums in FP32, in batch order, by the first lanes of the first tiles.
 // Tiles: dW1 1x4 (12 rows padded to 16), dW2 4x4, dW3 4x1 (2 cols padded).
 __global__ __launch_bounds__(64) void mlp_backward_weights_kernel(const float *__restrict__ x,
+                                                                  const uint32_t *__restrict__ rows,
                                                                   uint32_t B,
                                                                   const float *__restrict__ ws,
                                                                   float *__restrict__ grad) {
@@ -179,7 +188,7 @@ __global__ __launch_bounds__(64) void mlp_backward_weights_kernel(const float *_
     if (tid < 4) {  // dW1 = X^T dZ1
         const int t = tid;
         f32x4 acc = tile_gemm(Bi,
-            [&](int m, int k) { return m < IN ? x[(size_t)k * IN + m] : 0.f; },
+            [&](int m, int k) { return m < IN ? x[src_row(rows, k) * IN + m] : 0.f; },
             [&](int k, int j) { return ws[(size_t)k * WS_ROW + WS_DZ1 + 16 * t + j]; });
         #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -242,25 +251,60 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ p,
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Loss 1/(2B) sum_b sum_j (Y[b][j] - T[b][j])^2 from the forward pass's Y in
+// the workspace, in FP64, by one wave: lane l sums rows l, l + 64, ... in
+// order, then the 64 lane sums are added pairwise in a fixed tree.
+__global__ __launch_bounds__(64) void mlp_loss_kernel(const float *__restrict__ tgt,
+                                                      const uint32_t *__restrict__ rows,
+                                                      uint32_t B, const float *__restrict__ ws,
+                                                      double *__restrict__ out) {
+    __shared__ double part[64];
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int b = lane; b < (int)B; b += 64) {
+        for (int j = 0; j < OUT; ++j) {
+            const double d = (double)ws[(size_t)b * WS_ROW + WS_Y + j] - (double)tgt[src_row(rows, b) * OUT + j];
+            s = fma(d, d, s);
+        }
+    }
+    part[lane] = s;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if (lane < h) part[lane] += part[lane + h];
+        __syncthreads();
+    }
+    if (lane == 0) out[0] = part[0] / (2.0 * (double)B);
+}
+
 }  // namespace
 
 size_t mlp_workspace_floats(uint32_t batch) { return (size_t)batch * WS_ROW; }
 
-hipError_t launch_mlp_forward(hipStream_t st, const float *p, const float *x, uint32_t B, float *ws,
-                              float *y) {
+hipError_t launch_mlp_forward(hipStream_t st, const float *p, const float *x, const uint32_t *rows,
+                              uint32_t B, float *ws, float *y) {
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, x, B, ws, y);
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, x, rows, B, ws, y);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_backward(hipStream_t st, const float *p, const float *x, const float *t,
-                               uint32_t B, float *ws, float *grad) {
+                               const uint32_t *rows, uint32_t B, float *ws, float *grad) {
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, x, B, ws,
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, x, rows, B, ws,
                        (float *)nullptr);
-    hipLaunchKernelGGL(mlp_backward_rows_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, t, B, ws);
-    hipLaunchKernelGGL(mlp_backward_weights_kernel, dim3(24), dim3(64), 0, st, x, B,
+    hipLaunchKernelGGL(mlp_backward_rows_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, t, rows, B,
+                       ws);
+    hipLaunchKernelGGL(mlp_backward_weights_kernel, dim3(24), dim3(64), 0, st, x, rows, B,
                        (const float *)ws, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss(hipStream_t st, const float *p, const float *x, const float *t,
+                           const uint32_t *rows, uint32_t B, float *ws, double *out) {
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((B + 15) / 16), dim3(64), 0, st, p, x, rows, B, ws,
+                       (float *)nullptr);
+    hipLaunchKernelGGL(mlp_loss_kernel, dim3(1), dim3(64), 0, st, t, rows, B, (const float *)ws, out);
     return hipGetLastError();
 }
 

@@ -374,7 +374,17 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
 
     mode "plan": the planner's decision; "direct": every task from |0...0>
     with the same segment cuts (the reference for bit-identity); "reuse":
-    materialize every shared node regardless of cost."""
+    materialize every shared node regardless of cost.
+
+    When the device memory (or the context's QW_OPT_DEVICE_MEM_CAP) cannot
+    hold the materialized nodes and every task's state at once, the library
+    refuses with QW_E_OOM and the tasks run in chunks of half as many (then a
+    quarter, ... down to one) through the same slots, the materialized nodes
+    kept: every task runs the same kernels on the same inputs, so states,
+    expectations and samples equal those of the unchunked run (samples keep
+    each task's own counter-hash stream; with tiered kernels a small chunk may
+    take the interpreted path, which gives the same states, and expectations
+    within the epilogue tolerance). The chunk used is in realized_ms["chunk"]."""
     from . import binding as B
     t_plan0 = time.perf_counter()
     if plan is None:
@@ -383,127 +393,158 @@ def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots
         else:
             plan = plan_workload(n, tasks, cost, decide=decide)
     planning_ms = (time.perf_counter() - t_plan0) * 1e3
+    T = len(tasks)
+    chunk = max(1, T)
+    while True:
+        try:
+            res, refusals, realized = _execute(ctx, n, tasks, terms, shots, seed, mode, plan, keep_states,
+                                               chunk)
+            break
+        except B.QwError as e:
+            if e.code != B.QW_E_OOM or chunk <= 1:
+                raise
+            chunk = (chunk + 1) // 2
+    realized["chunk"] = chunk
+    trace = _explain(name, plan, tasks, n, refusals)
+    rec = CostRecord(plan="direct" if mode == "direct" else plan.decision.lower(),
+                     predicted_direct_bytes=plan.est_direct, predicted_reuse_bytes=plan.est_reuse,
+                     planning_ms=planning_ms, realized_ms=realized)
+    return res, trace, rec
+
+
+def _execute(ctx, n: int, tasks, terms, shots: int, seed: int, mode: str, plan: Plan,
+             keep_states: bool, chunk: int):
+    """One execution of `plan` with at most `chunk` task states at a time:
+    (ExecutionResult, refusal records, realized milliseconds)."""
+    from . import binding as B
     nodes = plan.nodes
     T = len(tasks)
     mats = list(plan.materialized)
     refusals: List[dict] = []
     realized: Dict[str, float] = {}
     slot_of = {vid: i for i, vid in enumerate(mats)}
-    n_slots = len(mats) + T
-    st = B.State(ctx, n, n_slots)
-    task_slots = [len(mats) + t for t in range(T)]
+    chunk = max(1, min(chunk, T)) if T else 1
+    st = B.State(ctx, n, len(mats) + (chunk if T else 0))
+    snaps: Dict[int, object] = {}
+    res = ExecutionResult()
+    try:
+        def anchor_chain(vid: Optional[int]) -> List[int]:
+            """Materialized nodes from the root down to vid."""
+            if vid is None:
+                return []
+            return [u for u in path_to(nodes, vid) if u in slot_of]
 
-    def anchor_chain(vid: Optional[int]) -> List[int]:
-        """Materialized nodes from the root down to vid."""
-        if vid is None:
-            return []
-        return [u for u in path_to(nodes, vid) if u in slot_of]
-
-    def segment_cuts(t: int) -> List[int]:
-        a = plan.anchor[t]
-        return [nodes[u].end for u in anchor_chain(a)]
-
-    t0 = time.perf_counter()
-    # expectations as the epilogue of the batch that ends every task (part of
-    # the terms reduced inside its last pass) when one batch ends them all in
-    # both modes: every task has the same number of cuts
-    fuse_terms = terms is not None and T > 0 and len({len(segment_cuts(t)) for t in range(T)}) == 1
-    fused_e = None
-    if mode == "direct":
-        # each task alone, cut at the same boundaries as the reuse plan
-        st.reset(len(mats), T)
-        cuts = [segment_cuts(t) for t in range(T)]
-        levels = max((len(c) for c in cuts), default=0)
-        for lev in range(levels + 1):
-            batch, dsts = [], []
-            for t in range(T):
-                if lev > len(cuts[t]):
-                    continue
-                b0 = 0 if lev == 0 else cuts[t][lev - 1]
-                b1 = cuts[t][lev] if lev < len(cuts[t]) else len(tasks[t])
-                if b1 > b0:
-                    batch.append(plan.segment_array(tasks, t, b0, b1))
-                    dsts.append(task_slots[t])
-            last = lev == levels and fuse_terms and dsts == task_slots
-            if batch:
-                e = B.run_suffix_batch(ctx, None, batch, st, dsts, terms=terms if last else None)
-                if last:
-                    fused_e = e
-        ctx.sync()
-        realized["suffix"] = (time.perf_counter() - t0) * 1e3
-    else:
-        # materialized nodes by depth: each from its nearest materialized ancestor
-        snaps: Dict[int, object] = {}
-        by_depth: Dict[int, List[int]] = {}
-        for vid in mats:
-            by_depth.setdefault(nodes[vid].depth, []).append(vid)
-        for d in sorted(by_depth):
-            srcs, gl, dsts, provs = [], [], [], []
-            for vid in by_depth[d]:
-                chain = anchor_chain(nodes[vid].parent)
-                a = chain[-1] if chain else None
-                b0 = nodes[a].end if a is not None else 0
-                gl.append(plan.segment_array(tasks, nodes[vid].tasks[0], b0, nodes[vid].end))
-                dsts.append(slot_of[vid])
-                srcs.append(snaps.get(a))
-                provs.append(snaps[a].provenance if a is not None else bytes(32))
-            for s in dsts:
-                st.reset(s, 1)
-            any_src = any(s is not None for s in srcs)
-            B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
-                               expect_provs=provs if any_src else None)
-            for vid in by_depth[d]:
-                fp = fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end])
-                snaps[vid] = st.snapshot(slot_of[vid], fp, B.QW_SNAP_FREEZE)
-        ctx.sync()
-        realized["prefix"] = (time.perf_counter() - t0) * 1e3
-        t1 = time.perf_counter()
-        srcs, gl, dsts, provs = [], [], [], []
-        for t in range(T):
+        def segment_cuts(t: int) -> List[int]:
             a = plan.anchor[t]
-            b0 = nodes[a].end if a is not None else 0
-            srcs.append(snaps.get(a) if a is not None else None)
-            gl.append(plan.segment_array(tasks, t, b0, len(tasks[t])))
-            dsts.append(task_slots[t])
-            provs.append(snaps[a].provenance if a is not None else bytes(32))
-        direct = [t for t in range(T) if srcs[t] is None]
-        if direct:
-            for t in direct:
-                st.reset(task_slots[t], 1)
-        try:
-            fused_e = B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
-                                         expect_provs=provs if len(direct) < T else None,
-                                         terms=terms if fuse_terms else None)
-        except B.QwRefused as r:
-            # structured refusal: record it and rerun every task from |0...0>
-            refusals.append(r.record)
-            st.reset(len(mats), T)
-            fused_e = B.run_suffix_batch(ctx, None, [plan.segment_array(tasks, t, 0, len(tasks[t]))
-                                                     for t in range(T)], st, dsts,
-                                         terms=terms if fuse_terms else None)
-        ctx.sync()
-        realized["suffix"] = (time.perf_counter() - t1) * 1e3
+            return [nodes[u].end for u in anchor_chain(a)]
+
+        t0 = time.perf_counter()
+        # expectations as the epilogue of the batch that ends every task (part
+        # of the terms reduced inside its last pass) when one batch ends them
+        # all in both modes: every task has the same number of cuts
+        fuse_terms = terms is not None and T > 0 and len({len(segment_cuts(t)) for t in range(T)}) == 1
+        if mode != "direct":
+            # materialized nodes by depth: each from its nearest materialized ancestor
+            by_depth: Dict[int, List[int]] = {}
+            for vid in mats:
+                by_depth.setdefault(nodes[vid].depth, []).append(vid)
+            for d in sorted(by_depth):
+                srcs, gl, dsts, provs = [], [], [], []
+                for vid in by_depth[d]:
+                    chain = anchor_chain(nodes[vid].parent)
+                    a = chain[-1] if chain else None
+                    b0 = nodes[a].end if a is not None else 0
+                    gl.append(plan.segment_array(tasks, nodes[vid].tasks[0], b0, nodes[vid].end))
+                    dsts.append(slot_of[vid])
+                    srcs.append(snaps.get(a))
+                    provs.append(snaps[a].provenance if a is not None else bytes(32))
+                for s in dsts:
+                    st.reset(s, 1)
+                any_src = any(s is not None for s in srcs)
+                B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
+                                   expect_provs=provs if any_src else None)
+                for vid in by_depth[d]:
+                    fp = fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end])
+                    snaps[vid] = st.snapshot(slot_of[vid], fp, B.QW_SNAP_FREEZE)
+            ctx.sync()
+            realized["prefix"] = (time.perf_counter() - t0) * 1e3
+        t1 = time.perf_counter()
+        exps: List[float] = []
+        samples, states = [], []
+        t_red = 0.0
+        for c0 in range(0, T, chunk):
+            ct = list(range(c0, min(T, c0 + chunk)))
+            slots = [len(mats) + i for i in range(len(ct))]
+            fused_e = None
+            if mode == "direct":
+                # each task alone, cut at the same boundaries as the reuse plan
+                st.reset(len(mats), len(ct))
+                cuts = {t: segment_cuts(t) for t in ct}
+                levels = max((len(c) for c in cuts.values()), default=0)
+                for lev in range(levels + 1):
+                    batch, dsts = [], []
+                    for t, sl in zip(ct, slots):
+                        if lev > len(cuts[t]):
+                            continue
+                        b0 = 0 if lev == 0 else cuts[t][lev - 1]
+                        b1 = cuts[t][lev] if lev < len(cuts[t]) else len(tasks[t])
+                        if b1 > b0:
+                            batch.append(plan.segment_array(tasks, t, b0, b1))
+                            dsts.append(sl)
+                    last = lev == levels and fuse_terms and dsts == slots
+                    if batch:
+                        e = B.run_suffix_batch(ctx, None, batch, st, dsts, terms=terms if last else None)
+                        if last:
+                            fused_e = e
+            else:
+                srcs, gl, provs = [], [], []
+                for t, sl in zip(ct, slots):
+                    a = plan.anchor[t]
+                    b0 = nodes[a].end if a is not None else 0
+                    srcs.append(snaps.get(a) if a is not None else None)
+                    gl.append(plan.segment_array(tasks, t, b0, len(tasks[t])))
+                    provs.append(snaps[a].provenance if a is not None else bytes(32))
+                    if a is None:
+                        st.reset(sl, 1)
+                n_direct = sum(1 for x in srcs if x is None)
+                try:
+                    fused_e = B.run_suffix_batch(ctx, srcs if n_direct < len(ct) else None, gl, st, slots,
+                                                 expect_provs=provs if n_direct < len(ct) else None,
+                                                 terms=terms if fuse_terms else None)
+                except B.QwRefused as r:
+                    # structured refusal: record it and rerun these tasks from |0...0>
+                    refusals.append(r.record)
+                    st.reset(len(mats), len(ct))
+                    fused_e = B.run_suffix_batch(ctx, None, [plan.segment_array(tasks, t, 0, len(tasks[t]))
+                                                             for t in ct], st, slots,
+                                                 terms=terms if fuse_terms else None)
+            ctx.sync()
+            t2 = time.perf_counter()
+            if fused_e is not None:
+                exps += list(fused_e)
+            elif terms is not None:
+                exps += list(st.expect(len(mats), len(ct), terms))
+            if shots:
+                samples.append(st.sample(len(mats), len(ct), seed, c0, shots).reshape(len(ct), shots))
+            if keep_states:
+                states += [st.host(s) for s in slots]
+            ctx.sync()
+            t_red += time.perf_counter() - t2
+        realized["suffix"] = (time.perf_counter() - t1 - t_red) * 1e3
+        realized["reduce"] = t_red * 1e3
+        realized["total"] = (time.perf_counter() - t0) * 1e3
+        if terms is not None and T:
+            res.expectations = exps
+        if shots and T:
+            import numpy as np
+            res.samples = np.concatenate(samples, axis=0)
+        if keep_states:
+            res.states = states
+    finally:
         for s in snaps.values():
             s.free()
-    t2 = time.perf_counter()
-    res = ExecutionResult()
-    if fused_e is not None:
-        res.expectations = list(fused_e)
-    elif terms is not None and T:
-        res.expectations = list(st.expect(len(mats), T, terms))
-    if shots and T:
-        res.samples = st.sample(len(mats), T, seed, 0, shots).reshape(T, shots)
-    if keep_states:
-        res.states = [st.host(s) for s in task_slots]
-    ctx.sync()
-    realized["reduce"] = (time.perf_counter() - t2) * 1e3
-    realized["total"] = (time.perf_counter() - t0) * 1e3
-    st.free()
-    trace = _explain(name, plan, tasks, n, refusals)
-    rec = CostRecord(plan="direct" if mode == "direct" else plan.decision.lower(),
-                     predicted_direct_bytes=plan.est_direct, predicted_reuse_bytes=plan.est_reuse,
-                     planning_ms=planning_ms, realized_ms=realized)
-    return res, trace, rec
+        st.free()
+    return res, refusals, realized
 
 
 class RecordedWorkload:

@@ -79,6 +79,42 @@ def test_backward_matches_oracle(ctx, B):
         o += k
 
 
+def test_gathered_batch_and_loss_match_oracle(ctx):
+    """The mini-batch gather and the loss run in the library's kernels: a
+    gradient on rows picked by index (repeats, any order) equals the
+    gradient on the same rows copied out (bitwise: same inputs, same
+    order) and the BF16-mirrored oracle on them; the loss kernel matches the
+    mirrored oracle loss; an index past the row count is refused."""
+    say("mlp gathered rows + loss")
+    import ctypes
+    import torch
+    from paper_2609_23664_amd import binding
+    from paper_2609_23664_amd import costmodel as CM
+    p = CM.init_params(6)
+    x, t = _data(77, 500)
+    rows = np.random.default_rng(8).integers(0, 500, size=97).astype(np.uint32)
+    rows[:3] = [499, 0, 499]
+    mlp = CM.MLP(ctx, params=p)
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    g_rows = mlp.backward_rows(xd, td, rows).cpu().numpy().astype(np.float64)
+    g_copy = mlp.backward(torch.tensor(x[rows], device="cuda"),
+                          torch.tensor(t[rows], device="cuda")).cpu().numpy().astype(np.float64)
+    assert np.array_equal(g_rows, g_copy)
+    gbf = M.backward(p.astype(np.float64), x[rows].astype(np.float64), t[rows].astype(np.float64),
+                     bf16_inputs=True)
+    assert np.linalg.norm(g_rows - gbf) <= 1e-4 * np.linalg.norm(gbf)
+    for B_ in (1, 17, 500):
+        got = mlp.loss(xd[:B_].contiguous(), td[:B_].contiguous())
+        ref = M.loss(p.astype(np.float64), x[:B_].astype(np.float64), t[:B_].astype(np.float64),
+                     bf16_inputs=True)
+        assert abs(got - ref) <= 1e-5 * abs(ref), (B_, got, ref)
+    bad = np.array([0, 500], dtype=np.uint32)
+    rc = binding.lib().qw_mlp_backward_rows(ctx.h, mlp.p.data_ptr(), xd.data_ptr(), td.data_ptr(), 500,
+                                            ctypes.c_void_p(bad.ctypes.data), 2, mlp._ws(2).data_ptr(),
+                                            mlp.g.data_ptr())
+    assert rc == binding.QW_E_INVALID_ARG
+
+
 def test_adam_step_matches_oracle(ctx):
     say("mlp adam")
     from paper_2609_23664_amd import costmodel as CM
@@ -96,9 +132,10 @@ def test_adam_step_matches_oracle(ctx):
 
 def test_trained_model_gains_over_analytic(ctx):
     """Train on the 1600 logged workloads (GPU kernels), evaluate on the 400
-    held out: lower plan regret and higher abstention accuracy than the
-    analytic byte rule (with the paper's guard and with none), negative
-    controls always abstain."""
+    held out: strictly lower plan regret and strictly higher abstention
+    accuracy than the analytic byte rule (with the paper's guard and with
+    none), negative controls always abstain; the labels were logged on the
+    generated-kernel execution at the current kernel sources."""
     say("mlp train + evaluate")
     from paper_2609_23664_amd import costmodel as CM
     out = CM.train_and_evaluate(ctx, epochs=300)
@@ -108,8 +145,8 @@ def test_trained_model_gains_over_analytic(ctx):
     assert rep["mlp"]["negative_control_abstain"] == 1.0
     assert rep["analytic"]["negative_control_abstain"] == 1.0
     for a in ("analytic", "analytic_delta0"):
-        assert rep["mlp"]["regret_mean"] <= rep[a]["regret_mean"], a
-        assert rep["mlp"]["abstain_accuracy"] >= rep[a]["abstain_accuracy"], a
+        assert rep["mlp"]["regret_mean"] < rep[a]["regret_mean"], a
+        assert rep["mlp"]["abstain_accuracy"] > rep[a]["abstain_accuracy"], a
     # the trained model drives the planner's decisions through its hook; a
     # plan only changes timing, so results must equal the direct run
     from paper_2609_23664_amd import planner as P
