@@ -72,10 +72,17 @@ extern "C" {
  * above; several (all on qubits >= 8) from the FP64 masses of their 2^k
  * outcome bins, in gate order, each by the rule above applied to the masses
  * that agree with the earlier outcomes (the sequential rule, with the
- * probabilities it would see). The call synchronises the stream once per
- * such decision. The next segment starts with the projectors (PROJ_b, the
- * first with the factor 1 / sqrt of the chosen outcome's mass) and an X for
- * each RESET with outcome 1; they fuse into that segment's first pass. */
+ * probabilities it would see). The decisions run on the device, in FP64,
+ * from the draws of the gate list: a decision kernel writes each outcome
+ * and the operator that opens the next segment, one per measured qubit (the
+ * projector P_b, the first with the factor 1 / sqrt of the chosen outcome's
+ * mass, times X for a RESET with outcome 1), which that segment's first pass
+ * applies as a real 2x2 operator read at run time. So the pass plans do not
+ * depend on outcomes and no decision waits for the host: a call
+ * synchronises the stream once, at its end, to collect the outcomes
+ * (qw_outcomes), and a recorded graph needs no host at all
+ * (qw_graph_outcomes). A state of zero norm at a measurement gives
+ * QW_E_INVALID_ARG at the end of the call. */
 #define QW_GATE_X 0x01
 #define QW_GATE_Y 0x02
 #define QW_GATE_Z 0x03
@@ -396,11 +403,13 @@ int qw_sample_noalloc(const qw_state *st, uint32_t first, uint32_t count,
  *   qw_expect_pauli, qw_sample, qw_tableau_export, the qw_mlp_* calls) are
  *   planned, checked (legality gates included) and their plans uploaded
  *   now, but their device work is recorded instead of run. The call first
- *   synchronises the context's stream. While recording, these return
+ *   synchronises the context's stream. Gate lists with MEASURE and RESET
+ *   record too: their decisions run on the device (qw_graph_outcomes reads
+ *   the outcomes of a replay). While recording, these return
  *   QW_E_UNSUPPORTED: host outputs (out_is_host = 1 or an epilogue with
- *   out_is_host = 1), an expectation with no terms, MEASURE and RESET gates
- *   (their decisions need the host), qw_ctx_sync, qw_ctx_kernel_stats,
- *   qw_snapshot_free, qw_state_free, qw_graph_launch and qw_graph_free.
+ *   out_is_host = 1), an expectation with no terms, qw_sample_noalloc,
+ *   qw_ctx_sync, qw_ctx_kernel_stats, qw_snapshot_free, qw_state_free,
+ *   qw_graph_launch, qw_graph_free and qw_graph_outcomes.
  *   QW_OPT_PROFILE timing is suspended. A call that fails while recording
  *   leaves the recording open; qw_graph_end then reports the failure.
  * qw_graph_end: closes the recording and returns the instantiated graph in
@@ -444,6 +453,13 @@ int qw_graph_nodes(const qw_graph *g, uint64_t *nodes);
 int qw_graph_update_gates(qw_graph *g, uint32_t call, uint32_t task, const qw_gate *gates,
                           uint64_t n_gates);
 int qw_graph_free(qw_graph *g);
+/* qw_graph_outcomes: the measurement outcomes (one byte each) of the
+ * measured calls recorded in the graph, as written by its most recent
+ * replay: call by call in recording order, within a call as qw_outcomes
+ * orders them. Synchronises the context's stream; writes min(count, cap)
+ * bytes to out (host) and the total to *count. If a replay measured a zero
+ * state: QW_E_INVALID_ARG (the bytes are still written). */
+int qw_graph_outcomes(qw_graph *g, uint8_t *out, uint64_t cap, uint64_t *count);
 
 /* ------------------------------------------------------------ learned cost model
  * A 3-layer perceptron predicting (log direct time, log reuse time) from

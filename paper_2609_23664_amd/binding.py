@@ -63,6 +63,7 @@ EXPORTED = (
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
     "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
     "qw_graph_update_gates", "qw_sample_noalloc", "qw_mlp_backward_rows", "qw_mlp_loss",
+    "qw_graph_outcomes",
 )
 
 
@@ -186,6 +187,7 @@ def lib() -> ctypes.CDLL:
         "qw_graph_launch": ([vp], i32),
         "qw_graph_nodes": ([vp, ctypes.POINTER(u64)], i32),
         "qw_graph_free": ([vp], i32),
+        "qw_graph_outcomes": ([vp, vp, u64, ctypes.POINTER(u64)], i32),
         "qw_graph_update_gates": ([vp, u32, u32, ctypes.POINTER(QwGate), u64], i32),
     }
     for name, (args, res) in sig.items():
@@ -603,6 +605,18 @@ class Graph:
         n = ctypes.c_uint64()
         self.ctx.check(lib().qw_graph_nodes(self.h, ctypes.byref(n)))
         return int(n.value)
+
+    def outcomes(self) -> "np.ndarray":
+        """qw_graph_outcomes: outcomes (uint8) of the recorded measured calls,
+        as written by the most recent replay (synchronises)."""
+        import numpy as np
+        cnt = ctypes.c_uint64()
+        self.ctx.check(lib().qw_graph_outcomes(self.h, None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.uint8)
+        if cnt.value:
+            self.ctx.check(lib().qw_graph_outcomes(self.h, ctypes.c_void_p(out.ctypes.data), cnt.value,
+                                                   ctypes.byref(cnt)))
+        return out
 
     def free(self):
         if self.h:

@@ -65,6 +65,13 @@ struct GraphSeg {
     std::vector<std::pair<void *, size_t>> ops;  // device address, bytes
 };
 
+// Where a recorded measured call's outcome bytes and zero-state flag live.
+struct OutcomeRec {
+    const uint8_t *outc;
+    uint64_t count;
+    const uint32_t *err;
+};
+
 struct GraphRec {
     std::vector<std::vector<GraphSeg>> calls;  // qw_apply_prefix / qw_run_suffix_batch, in order
     hipStream_t cap = nullptr;    // captured stream (non-blocking, default priority)
@@ -73,6 +80,7 @@ struct GraphRec {
     DevBuf saved_plan, saved_scratch, saved_pingpong, saved_meas;
     std::vector<void *> owned;    // buffers replaced during the recording
     bool plan_used = false;       // ctx->plan already holds an uploaded blob
+    std::vector<OutcomeRec> outcomes;  // measured calls: where a replay writes their outcomes
 };
 
 }  // namespace
@@ -84,6 +92,7 @@ struct qw_graph {
     std::vector<void *> owned;  // plan blobs and scratch the recorded nodes read
     uint64_t nodes = 0;
     std::vector<std::vector<GraphSeg>> calls;  // updatable op records per recorded task
+    std::vector<OutcomeRec> outcomes;          // measured calls, in recording order
 };
 
 struct qw_ctx {
@@ -411,7 +420,12 @@ uint64_t fnv64(const void *p, size_t len, uint64_t h = 0xcbf29ce484222325ull) {
 }
 
 std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_gates,
-                     std::shared_ptr<const Plan> *out) {
+                     std::shared_ptr<const Plan> *out, bool allow_dyn = false) {
+    // the internal run-time operator of measured segments is never taken
+    // from a caller's gate list (not even through the plan cache)
+    if (!allow_dyn)
+        for (uint64_t i = 0; i < n_gates; ++i)
+            if (gates[i].kind == kGateDyn) return "gate " + std::to_string(i) + ": unknown kind 0x86";
     const size_t bytes = (size_t)n_gates * sizeof(qw_gate);
     uint64_t h = fnv64(gates, bytes);
     h = fnv64(&n, sizeof n, h);
@@ -427,7 +441,8 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
         }
     }
     auto p = std::make_shared<Plan>();
-    std::string e = build_plan((int)n, gates, (size_t)n_gates, ctx->tile_bits, p.get(), ctx->relabel);
+    std::string e = build_plan((int)n, gates, (size_t)n_gates, ctx->tile_bits, p.get(), ctx->relabel, true,
+                               allow_dyn);
     if (!e.empty()) return e;
     if (ctx->plan_cache_entries >= 4096) {
         ctx->plan_cache.clear();
@@ -1206,7 +1221,10 @@ double decide_cluster(MeasTask &t, std::vector<double> mass, std::vector<uint32_
 // mass) and an X for each RESET with outcome 1. Outcomes are recorded per
 // task in gate order (qw_outcomes).
 int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
-    for (size_t k = 0; k < mt.size(); ++k)
+    uint64_t total_meas = 0;
+    std::vector<uint32_t> outc_base(mt.size()), outc_next(mt.size());
+    for (size_t k = 0; k < mt.size(); ++k) {
+        outc_base[k] = outc_next[k] = (uint32_t)total_meas;
         for (size_t i = 0; i < mt[k].rest.size(); ++i) {
             const qw_gate &q = mt[k].rest[i];
             if (!is_measure(q.kind)) continue;
@@ -1216,20 +1234,37 @@ int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
                          k, i);
                 return fail(ctx, QW_E_INVALID_ARG, buf);
             }
+            ++total_meas;
         }
+    }
     const uint32_t T = (uint32_t)mt.size();
     const uint32_t kStride = 1u << kMaxJoint;
     const uint64_t chunks_max = 1ull << (n > kJointMinQubit ? n - kJointMinQubit : 0);
-    const size_t ptr_bytes = ((size_t)T * sizeof(void *) + 255) & ~(size_t)255;
-    const size_t q_bytes = ((size_t)T * sizeof(uint64_t) + 255) & ~(size_t)255;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t part_doubles = std::max<size_t>((size_t)2 * T * chunks_max, 2 * (size_t)T);
     const size_t out_doubles = (size_t)T * kStride;
-    int rc = ensure(ctx, ctx->meas, ptr_bytes + q_bytes + (part_doubles + out_doubles) * sizeof(double),
-                    "measure buffer");
+    const size_t dyn_off = al((part_doubles + out_doubles) * sizeof(double));
+    const size_t outc_off = dyn_off + al((size_t)total_meas * 4 * sizeof(float));
+    const size_t err_off = outc_off + al((size_t)total_meas);
+    // a recorded graph keeps each measured call's buffer (its outcomes stay
+    // readable after a replay)
+    if (ctx->rec && ctx->meas.p) {
+        ctx->rec->owned.push_back(ctx->meas.p);
+        ctx->meas = DevBuf{};
+    }
+    int rc = ensure(ctx, ctx->meas, err_off + 256, "measure buffer");
     if (rc) return rc;
     char *mb = static_cast<char *>(ctx->meas.p);
-    double *part = reinterpret_cast<double *>(mb + ptr_bytes + q_bytes);
+    double *part = reinterpret_cast<double *>(mb);
     double *dout = part + part_doubles;
+    float *dyn = reinterpret_cast<float *>(mb + dyn_off);
+    uint8_t *outc = reinterpret_cast<uint8_t *>(mb + outc_off);
+    uint32_t *err = reinterpret_cast<uint32_t *>(mb + err_off);
+    {
+        hipError_t e = launch_meas_clear(ctx->stream, err);
+        if (e != hipSuccess) return hip_fail(ctx, e, "measure launch");
+    }
+    uint32_t dyn_next = 0;
     bool first = true;
     std::vector<std::vector<qw_gate>> segs(mt.size());
     while (true) {
@@ -1239,8 +1274,8 @@ int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
             if (t.done) continue;
             next_segment(t, &segs[k]);
             Exec x;
-            std::string err = get_plan(ctx, n, segs[k].data(), segs[k].size(), &x.planp);
-            if (!err.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + err);
+            std::string err_s = get_plan(ctx, n, segs[k].data(), segs[k].size(), &x.planp, true);
+            if (!err_s.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + err_s);
             x.src = first ? t.src : nullptr;
             x.dst = t.dst;
             ex.push_back(x);
@@ -1268,80 +1303,94 @@ int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
             const uint32_t C = gr.first;
             const std::vector<size_t> &who = gr.second;
             const uint32_t M = (uint32_t)who.size();
+            // uploaded with the group: slot pointers, qubits (single) or
+            // measured masks >> C (joint), per-task decision ranges, decisions
             std::vector<const void *> ptrs(M);
             std::vector<uint64_t> qs(M);
+            std::vector<uint32_t> tfirst(M), tcount(M);
+            std::vector<MeasDec> dec;
             for (uint32_t i = 0; i < M; ++i) {
-                const MeasTask &t = mt[who[i]];
+                MeasTask &t = mt[who[i]];
                 ptrs[i] = t.dst;
-                uint64_t m = 0;
-                for (const qw_gate &g : t.cluster) m |= 1ull << g.q0;
-                qs[i] = C ? (m >> C) : (uint64_t)t.cluster[0].q0;
+                uint64_t msk = 0;
+                for (const qw_gate &g : t.cluster) msk |= 1ull << g.q0;
+                qs[i] = C ? (msk >> C) : (uint64_t)t.cluster[0].q0;
+                tfirst[i] = (uint32_t)dec.size();
+                tcount[i] = (uint32_t)t.cluster.size();
+                // bin bit of each measurement at its turn: its rank among the
+                // qubits still open (ascending), the decided ones removed
+                std::vector<uint32_t> alive;
+                for (const qw_gate &g : t.cluster) alive.push_back(g.q0);
+                std::sort(alive.begin(), alive.end());
+                for (const qw_gate &g : t.cluster) {
+                    const auto it = std::find(alive.begin(), alive.end(), g.q0);
+                    MeasDec d{};
+                    d.u = g.param;
+                    d.reset = g.kind == QW_GATE_RESET ? 1u : 0u;
+                    d.pos = (uint32_t)(it - alive.begin());
+                    d.dyn = dyn_next++;
+                    d.outc = outc_next[who[i]]++;
+                    alive.erase(it);
+                    dec.push_back(d);
+                    // the next segment opens with the operator the decision writes
+                    qw_gate pg{};
+                    pg.kind = kGateDyn;
+                    pg.q0 = g.q0;
+                    pg.param = dyn_param(dyn + 4ull * d.dyn);
+                    t.head.push_back(pg);
+                }
+                t.cluster.clear();
             }
-            HIP_TRY(ctx, hipMemcpyAsync(mb, ptrs.data(), M * sizeof(void *), hipMemcpyHostToDevice,
-                                        ctx->stream), "measure upload");
-            std::vector<uint32_t> q32(M);
-            for (uint32_t i = 0; i < M; ++i) q32[i] = (uint32_t)qs[i];
-            if (C == 0)
-                HIP_TRY(ctx, hipMemcpyAsync(mb + ptr_bytes, q32.data(), M * sizeof(uint32_t),
-                                            hipMemcpyHostToDevice, ctx->stream), "measure upload");
-            else
-                HIP_TRY(ctx, hipMemcpyAsync(mb + ptr_bytes, qs.data(), M * sizeof(uint64_t),
-                                            hipMemcpyHostToDevice, ctx->stream), "measure upload");
-            std::vector<double> h;
+            const size_t o_ptr = 0, o_q = al(M * sizeof(void *)), o_tf = o_q + al(M * sizeof(uint64_t));
+            const size_t o_tc = o_tf + al(M * sizeof(uint32_t)), o_dec = o_tc + al(M * sizeof(uint32_t));
+            std::vector<uint8_t> blob(o_dec + dec.size() * sizeof(MeasDec));
+            std::memcpy(blob.data() + o_ptr, ptrs.data(), M * sizeof(void *));
+            if (C == 0) {
+                std::vector<uint32_t> q32(M);
+                for (uint32_t i = 0; i < M; ++i) q32[i] = (uint32_t)qs[i];
+                std::memcpy(blob.data() + o_q, q32.data(), M * sizeof(uint32_t));
+            } else {
+                std::memcpy(blob.data() + o_q, qs.data(), M * sizeof(uint64_t));
+            }
+            std::memcpy(blob.data() + o_tf, tfirst.data(), M * sizeof(uint32_t));
+            std::memcpy(blob.data() + o_tc, tcount.data(), M * sizeof(uint32_t));
+            std::memcpy(blob.data() + o_dec, dec.data(), dec.size() * sizeof(MeasDec));
+            rc = upload(ctx, blob);
+            if (rc) return rc;
+            const char *ub = static_cast<const char *>(ctx->plan.p);
             {
                 ProfScope ps(ctx, 1, (double)M * (double)(8ull << n));
                 hipError_t er = C == 0
-                    ? launch_measure_sums(ctx->stream, reinterpret_cast<const float2 *const *>(mb),
-                                          reinterpret_cast<const uint32_t *>(mb + ptr_bytes), M, n, part,
-                                          dout)
-                    : launch_joint_masses(ctx->stream, reinterpret_cast<const float2 *const *>(mb),
-                                          reinterpret_cast<const uint64_t *>(mb + ptr_bytes), M, n, C, part,
+                    ? launch_measure_sums(ctx->stream, reinterpret_cast<const float2 *const *>(ub + o_ptr),
+                                          reinterpret_cast<const uint32_t *>(ub + o_q), M, n, part, dout)
+                    : launch_joint_masses(ctx->stream, reinterpret_cast<const float2 *const *>(ub + o_ptr),
+                                          reinterpret_cast<const uint64_t *>(ub + o_q), M, n, C, part,
                                           kStride, dout);
                 if (er != hipSuccess) return hip_fail(ctx, er, "measure launch");
-            }
-            h.resize(C == 0 ? 2 * (size_t)M : (size_t)M * kStride);
-            HIP_TRY(ctx, hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                        ctx->stream), "measure copy");
-            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
-            for (uint32_t i = 0; i < M; ++i) {
-                MeasTask &t = mt[who[i]];
-                std::vector<uint32_t> outs;
-                double Sb;
-                if (C == 0) {
-                    const double S = h[2 * i], S1 = h[2 * i + 1];
-                    if (!(S > 0.0)) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
-                    const uint32_t b = t.cluster[0].param < S1 / S ? 1u : 0u;
-                    outs.push_back(b);
-                    Sb = b ? S1 : S - S1;
-                } else {
-                    const size_t bins = (size_t)1 << t.cluster.size();
-                    std::vector<double> mass(h.begin() + (size_t)i * kStride, h.begin() + (size_t)i * kStride + bins);
-                    double tot = 0.0;
-                    for (double v : mass) tot += v;
-                    if (!(tot > 0.0)) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
-                    Sb = decide_cluster(t, mass, &outs);
-                }
-                for (size_t j = 0; j < t.cluster.size(); ++j) {
-                    qw_gate pg{};
-                    pg.kind = outs[j] ? QW_GATE_PROJ1 : QW_GATE_PROJ0;
-                    pg.q0 = t.cluster[j].q0;
-                    pg.param = j == 0 ? 1.0 / std::sqrt(Sb) : 1.0;
-                    t.head.push_back(pg);
-                }
-                for (size_t j = 0; j < t.cluster.size(); ++j)
-                    if (t.cluster[j].kind == QW_GATE_RESET && outs[j]) {
-                        qw_gate xg{};
-                        xg.kind = QW_GATE_X;
-                        xg.q0 = t.cluster[j].q0;
-                        t.head.push_back(xg);
-                    }
-                for (uint32_t b : outs) t.outc.push_back((uint8_t)b);
-                t.cluster.clear();
+                er = launch_meas_decide(ctx->stream, reinterpret_cast<const uint32_t *>(ub + o_tf),
+                                        reinterpret_cast<const uint32_t *>(ub + o_tc),
+                                        reinterpret_cast<const MeasDec *>(ub + o_dec), M, C != 0, dout, kStride,
+                                        dyn, outc, err);
+                if (er != hipSuccess) return hip_fail(ctx, er, "measure decision launch");
             }
         }
     }
-    ctx->outcomes.clear();
-    for (const MeasTask &t : mt) ctx->outcomes.insert(ctx->outcomes.end(), t.outc.begin(), t.outc.end());
+    if (ctx->rec) {
+        // a replay writes the outcomes where qw_graph_outcomes reads them
+        ctx->rec->outcomes.push_back({outc, total_meas, err});
+        ctx->outcomes.clear();
+        return QW_OK;
+    }
+    std::vector<uint8_t> host(total_meas + sizeof(uint32_t));
+    uint32_t herr = 0;
+    if (total_meas)
+        HIP_TRY(ctx, hipMemcpyAsync(host.data(), outc, total_meas, hipMemcpyDeviceToHost, ctx->stream),
+                "outcome copy");
+    HIP_TRY(ctx, hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, ctx->stream), "outcome copy");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    ctx->outcomes.assign(host.begin(), host.begin() + (std::ptrdiff_t)total_meas);
+    if (herr) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
+    (void)outc_base;
     return QW_OK;
 }
 
@@ -1561,11 +1610,13 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
     if (n_gates && !gates) return fail(ctx, QW_E_INVALID_ARG, "gates == NULL");
     ctx->outcomes.clear();
     if (has_measure(gates, n_gates)) {
-        if (ctx->rec) return recording_unsupported(ctx, "a mid-circuit measurement");
         std::vector<MeasTask> mt(1);
         mt[0].rest.assign(gates, gates + n_gates);
         mt[0].dst = slot_ptr(st, slot);
-        return run_measured(ctx, st->n, mt);
+        if (ctx->rec) ctx->rec->calls.emplace_back();
+        const int rc = run_measured(ctx, st->n, mt);
+        if (ctx->rec) ctx->rec->calls.back().clear();  // a measured call's gates cannot be updated
+        return rc;
     }
     std::vector<Exec> ex(1);
     std::string e = get_plan(ctx, st->n, gates, n_gates, &ex[0].planp);
@@ -1708,7 +1759,6 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         if (tasks[k].n_gates && !tasks[k].gates) return fail(ctx, QW_E_INVALID_ARG, "task gates == NULL");
         measured = has_measure(tasks[k].gates, tasks[k].n_gates);
     }
-    if (ctx->rec && measured) return recording_unsupported(ctx, "a mid-circuit measurement");
     if (ctx->rec && epi && epi->out_is_host) return recording_unsupported(ctx, "a host output");
     if (measured) {
         // segments between measurements; the expectations after the last one
@@ -1718,7 +1768,9 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
             mt[k].src = (src && src[k]) ? src[k]->data : nullptr;
             mt[k].dst = slot_ptr(dst, tasks[k].dst_slot);
         }
+        if (ctx->rec) ctx->rec->calls.emplace_back();
         int rc = run_measured(ctx, dst->n, mt);
+        if (ctx->rec) ctx->rec->calls.back().clear();  // a measured call's gates cannot be updated
         if (rc || !epi) return rc;
         std::vector<const void *> slots(n_tasks);
         for (uint32_t k = 0; k < n_tasks; ++k) slots[k] = slot_ptr(dst, tasks[k].dst_slot);
@@ -2258,9 +2310,11 @@ namespace {
 // Leave recording mode: the capture ends, the context gets its own buffers
 // and stream back, and the buffers of the recording are returned.
 void end_recording(qw_ctx *ctx, hipGraph_t *graph, std::vector<void *> *owned,
-                   std::vector<std::vector<GraphSeg>> *calls = nullptr) {
+                   std::vector<std::vector<GraphSeg>> *calls = nullptr,
+                   std::vector<OutcomeRec> *outcomes = nullptr) {
     GraphRec *r = ctx->rec;
     if (calls) *calls = std::move(r->calls);
+    if (outcomes) *outcomes = std::move(r->outcomes);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(r->cap, &gr);
     if (e != hipSuccess) gr = nullptr;
@@ -2326,7 +2380,8 @@ int qw_graph_end(qw_ctx *ctx, qw_graph **out) {
     hipGraph_t gr = nullptr;
     std::vector<void *> owned;
     std::vector<std::vector<GraphSeg>> calls;
-    end_recording(ctx, &gr, &owned, &calls);
+    std::vector<OutcomeRec> outcomes;
+    end_recording(ctx, &gr, &owned, &calls, &outcomes);
     if (!gr) {
         free_owned(owned);
         return fail(ctx, QW_E_HIP, "stream capture ended without a graph (a recorded call failed)");
@@ -2349,8 +2404,29 @@ int qw_graph_end(qw_ctx *ctx, qw_graph **out) {
     g->graph = gr;
     g->owned = std::move(owned);
     g->calls = std::move(calls);
+    g->outcomes = std::move(outcomes);
     g->nodes = nn;
     *out = g.release();
+    return QW_OK;
+}
+
+int qw_graph_outcomes(qw_graph *g, uint8_t *out, uint64_t cap, uint64_t *count) {
+    if (!g || (cap && !out)) return QW_E_INVALID_ARG;
+    qw_ctx *ctx = g->ctx;
+    if (ctx->rec) return recording_unsupported(ctx, "qw_graph_outcomes");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+    uint64_t total = 0;
+    bool zero = false;
+    for (const OutcomeRec &r : g->outcomes) {
+        const uint64_t m = total < cap ? std::min<uint64_t>(cap - total, r.count) : 0;
+        if (m) HIP_TRY(ctx, hipMemcpy(out + total, r.outc, m, hipMemcpyDeviceToHost), "outcome copy");
+        uint32_t e = 0;
+        HIP_TRY(ctx, hipMemcpy(&e, r.err, sizeof e, hipMemcpyDeviceToHost), "outcome copy");
+        zero = zero || e != 0;
+        total += r.count;
+    }
+    if (count) *count = total;
+    if (zero) return fail(ctx, QW_E_INVALID_ARG, "measurement of a zero state");
     return QW_OK;
 }
 

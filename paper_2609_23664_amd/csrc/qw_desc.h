@@ -48,6 +48,11 @@ enum OpType : uint8_t {
                   // its diagonal ops): target local bit a (slot sa), form b,
                   // t = m[0]:  0: [[1, -t], [t, 1]]   1: [[1, t], [t, -1]]
                   // one FMA per output component
+    OP_URD = 11,  // real 2x2 matrix [[e0, e1], [e2, e3]] on local bit a (slot sa)
+                  // whose 4 FP32 entries are read at run time from the device
+                  // address held in the bytes of m[0..1] (written there by an
+                  // earlier kernel: a measurement's projector, decided on the
+                  // device)
     OP_PDIAG = 9, // parity factor (member of an OP_DSET): d0 = m[0..1] where
                   // the parity of (index & mask) is even, d1 = m[2..3] where odd;
                   // mask = register slots rmask + thread bits tmask (local bit

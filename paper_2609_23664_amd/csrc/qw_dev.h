@@ -68,6 +68,18 @@ __device__ __forceinline__ const QW_GLOBAL T *gin(const void *p) {
     return (const QW_GLOBAL T *)(p);
 }
 
+// OP_URD: the 4 real entries [[e0, e1], [e2, e3]] of op j, read from the
+// device address held in the bytes of m[0..1]. An earlier kernel writes
+// them (kernel boundaries order the write before these uniform loads).
+struct Urd {
+    float a, b, c, d;
+};
+__device__ __forceinline__ Urd urd_entries(const DevOp *ops, uint32_t j) {
+    const uint64_t addr = ldu(reinterpret_cast<const uint64_t *>(&ops[j].m[0]));
+    const float *e = reinterpret_cast<const float *>(addr);
+    return Urd{ldu(e), ldu(e + 1), ldu(e + 2), ldu(e + 3)};
+}
+
 template <typename T>
 __device__ __forceinline__ QW_GLOBAL T *gout(void *p) {
     return (QW_GLOBAL T *)(p);

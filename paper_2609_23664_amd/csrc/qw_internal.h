@@ -52,7 +52,21 @@ struct Plan {
 // passes keep their host ops only (no device records or phases: enough to
 // count passes). Returns "" on success, otherwise an error message.
 std::string build_plan(int n, const void *gates /* qw_gate* */, size_t n_gates,
-                       int tile_bits, Plan *out, bool relabel = true, bool lower = true);
+                       int tile_bits, Plan *out, bool relabel = true, bool lower = true,
+                       bool allow_dyn = false);
+
+// Internal gate kind (never accepted from callers): a real 2x2 operator on
+// q0 whose 4 FP32 entries the device writes at run time at the address held
+// in the bits of `param` (lowered to OP_URD, never fused with other gates).
+// The library opens a segment after a measurement with one per measured
+// qubit: its projector (and the X of a RESET with outcome 1).
+constexpr uint32_t kGateDyn = 0x86;
+inline double dyn_param(const void *addr) {
+    double d;
+    const uint64_t a = reinterpret_cast<uint64_t>(addr);
+    __builtin_memcpy(&d, &a, sizeof d);
+    return d;
+}
 
 // JSON form of a plan (for qw_plan_describe).
 std::string plan_json(const Plan &p);

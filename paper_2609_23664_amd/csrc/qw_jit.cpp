@@ -215,6 +215,12 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
             else g << "    ur_r<" << (int)o.sa << ">(v, " << mr(j) << ");\n";
             ++j;
             break;
+        case OP_URD:
+            g << "    { const Urd e = urd_entries(ops, " << j << "); ";
+            if (lane) g << "ur_l<" << (int)o.sa << ">(v, e.a, e.b, e.c, e.d, lane); }\n";
+            else g << "ur_r<" << (int)o.sa << ">(v, e.a, e.b, e.c, e.d); }\n";
+            ++j;
+            break;
         case OP_U:
             if (lane) g << "    u_l<" << (int)o.sa << ">(v, " << mc(j, 4) << ", lane);\n";
             else g << "    u_r<" << (int)o.sa << ">(v, " << mc(j, 4) << ");\n";

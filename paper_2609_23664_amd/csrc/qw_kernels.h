@@ -48,6 +48,29 @@ hipError_t launch_measure_sums(hipStream_t st, const float2 *const *slots, const
 hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const uint64_t *mq,
                                uint32_t n_slots, uint32_t n, uint32_t C, double *csum,
                                uint32_t bin_stride, double *out);
+// Device-side measurement decisions (one thread per task of a decision
+// group). Task i's measurements are dec[task_first[i] .. task_first[i] +
+// task_count[i]), in gate order. Single measurements (joint = 0) read S and
+// S1 from sums[2 i], sums[2 i + 1]; joint clusters read their 2^k outcome-bin
+// masses from sums[i * bin_stride ...] (used as work space: halved in place).
+// Measurement j takes b = (u < P(1 | earlier outcomes)) in FP64, writes its
+// outcome byte to outc[dec.outc] and the 4 FP32 entries of the operator that
+// opens the next segment to dyn[4 dec.dyn ...]: the projector on b (the first
+// of a task with the factor 1 / sqrt of the chosen mass), times X for a RESET
+// with b = 1. A zero state sets *err to 1.
+struct MeasDec {
+    double u;        // the caller's draw
+    uint32_t reset;  // 1: RESET (X on outcome 1), 0: MEASURE
+    uint32_t pos;    // joint: bit of this qubit among the bins still open
+    uint32_t dyn;    // index of its 4-entry block in dyn
+    uint32_t outc;   // index of its outcome byte
+};
+static_assert(sizeof(MeasDec) == 24, "MeasDec layout");
+hipError_t launch_meas_decide(hipStream_t st, const uint32_t *task_first, const uint32_t *task_count,
+                              const MeasDec *dec, uint32_t n_tasks, int joint, double *sums,
+                              uint32_t bin_stride, float *dyn, uint8_t *outc, uint32_t *err);
+// *err = 0 (a kernel, so that it can be recorded in a graph).
+hipError_t launch_meas_clear(hipStream_t st, uint32_t *err);
 // Dense export of a stabilizer state into psi (2^n amplitudes): x0, r X-type
 // generators (device arrays xs, zs, ph = i-power, piv = pivot qubit), norm =
 // 2^{-r/2}. r <= 64.

@@ -162,6 +162,11 @@ __device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, const D
         case OP_UR:
             QW_LANE6(ur_l, op.sa, v, opm(ops, j, 0), opm(ops, j, 1), opm(ops, j, 2), opm(ops, j, 3), lane)
             return;
+        case OP_URD: {
+            const Urd e = urd_entries(ops, j);
+            QW_LANE6(ur_l, op.sa, v, e.a, e.b, e.c, e.d, lane)
+            return;
+        }
         case OP_URT:
             if (op.b) urt_l_s<1>(v, op.sa, opm(ops, j, 0), lane);
             else urt_l_s<0>(v, op.sa, opm(ops, j, 0), lane);
@@ -188,6 +193,11 @@ __device__ __forceinline__ void run_op(float2 (&v)[16], const DevOp &op, const D
     case OP_UR:
         QW_SLOT4(ur_r, op.sa, v, opm(ops, j, 0), opm(ops, j, 1), opm(ops, j, 2), opm(ops, j, 3))
         break;
+    case OP_URD: {
+        const Urd e = urd_entries(ops, j);
+        QW_SLOT4(ur_r, op.sa, v, e.a, e.b, e.c, e.d)
+        break;
+    }
     case OP_U:
         QW_SLOT4(u_r, op.sa, v, opc(ops, j, 0), opc(ops, j, 1), opc(ops, j, 2), opc(ops, j, 3))
         break;
@@ -550,7 +560,12 @@ __global__ __launch_bounds__(64) void small_pass_kernel(const PassDesc *__restri
             continue;
         }
         if (op.type == OP_U || op.type == OP_PERM || op.type == OP_CX || op.type == OP_UR ||
-            op.type == OP_URT) {
+            op.type == OP_URT || op.type == OP_URD) {
+            float e0 = op.m[0], e1 = op.m[1], e2 = op.m[2], e3 = op.m[3];
+            if (op.type == OP_URD) {
+                const Urd e = urd_entries(d.ops, o);
+                e0 = e.a; e1 = e.b; e2 = e.c; e3 = e.d;
+            }
             const uint32_t bit = 1u << op.a;
             for (uint32_t pr = tid; pr < dim / 2; pr += 64) {
                 const uint32_t i0 = ((pr >> op.a) << (op.a + 1)) | (pr & (bit - 1));
@@ -565,9 +580,9 @@ __global__ __launch_bounds__(64) void small_pass_kernel(const PassDesc *__restri
                     else urt_pair<0>(op.m[0], a, b);
                     s[i0] = a;
                     s[i1] = b;
-                } else if (op.type == OP_UR) {
-                    s[i0] = make_float2(fmaf(op.m[0], x.x, op.m[1] * y.x), fmaf(op.m[0], x.y, op.m[1] * y.y));
-                    s[i1] = make_float2(fmaf(op.m[2], x.x, op.m[3] * y.x), fmaf(op.m[2], x.y, op.m[3] * y.y));
+                } else if (op.type == OP_UR || op.type == OP_URD) {
+                    s[i0] = make_float2(fmaf(e0, x.x, e1 * y.x), fmaf(e0, x.y, e1 * y.y));
+                    s[i1] = make_float2(fmaf(e2, x.x, e3 * y.x), fmaf(e2, x.y, e3 * y.y));
                 } else if (op.type == OP_PERM) {
                     s[i0] = cmul(make_float2(op.m[0], op.m[1]), y);
                     s[i1] = cmul(make_float2(op.m[2], op.m[3]), x);
@@ -1299,6 +1314,125 @@ hipError_t launch_joint_masses(hipStream_t st, const float2 *const *slots, const
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bin_mass_kernel, dim3(n_slots), dim3(256), 0, st, csum, n - C, mq, bin_stride,
                        out);
+    return hipGetLastError();
+}
+
+namespace {
+
+// One workgroup per task. A joint cluster's bin masses are staged in LDS;
+// each step sums them (and those with the step's bit set) with a fixed
+// order (per-thread strided sums, then a fixed tree), decides, and keeps
+// the bins that agree with the outcome: bin b moves to b with bit p removed,
+// which keeps their order.
+constexpr int kDecideThreads = 256;
+
+__device__ __forceinline__ void decide_sums(const double *mass, uint32_t len, uint32_t p, double *red,
+                                            double *tot, double *one) {
+    const uint32_t t = threadIdx.x;
+    double a = 0.0, b1 = 0.0;
+    for (uint32_t b = t; b < len; b += kDecideThreads) {
+        a += mass[b];
+        if ((b >> p) & 1u) b1 += mass[b];
+    }
+    red[t] = a;
+    red[kDecideThreads + t] = b1;
+    __syncthreads();
+    for (uint32_t h = kDecideThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            red[t] += red[t + h];
+            red[kDecideThreads + t] += red[kDecideThreads + t + h];
+        }
+        __syncthreads();
+    }
+    *tot = red[0];
+    *one = red[kDecideThreads];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kDecideThreads) void meas_decide_kernel(
+    const uint32_t *__restrict__ task_first, const uint32_t *__restrict__ task_count,
+    const MeasDec *__restrict__ dec, uint32_t n_tasks, int joint, double *__restrict__ sums,
+    uint32_t bin_stride, float *__restrict__ dyn, uint8_t *__restrict__ outc, uint32_t *__restrict__ err) {
+    __shared__ double buf[2][1u << 12];
+    __shared__ double red[2 * kDecideThreads];
+    const uint32_t i = blockIdx.x, t = threadIdx.x;
+    if (i >= n_tasks) return;
+    const uint32_t f0 = task_first[i], k = task_count[i];
+    uint32_t bits = 0;     // outcome of measurement j in bit j
+    double chosen = 1.0;   // mass of the chosen outcome
+    bool zero = false;
+    if (!joint) {
+        const double S = sums[2 * i], S1 = sums[2 * i + 1];
+        if (!(S > 0.0)) {
+            zero = true;
+        } else {
+            const uint32_t b = dec[f0].u < S1 / S ? 1u : 0u;
+            bits = b;
+            chosen = b ? S1 : S - S1;
+        }
+    } else {
+        uint32_t len = 1u << k;  // k <= 12 (the caller's cluster bound)
+        const double *src = sums + (size_t)i * bin_stride;
+        for (uint32_t b = t; b < len; b += kDecideThreads) buf[0][b] = src[b];
+        __syncthreads();
+        int cur = 0;
+        double tot, one;
+        decide_sums(buf[cur], len, 0, red, &tot, &one);
+        if (!(tot > 0.0)) {
+            zero = true;
+        } else {
+            for (uint32_t j = 0; j < k; ++j) {
+                const uint32_t p = dec[f0 + j].pos;
+                decide_sums(buf[cur], len, p, red, &tot, &one);
+                const uint32_t bit = dec[f0 + j].u < one / tot ? 1u : 0u;
+                bits |= bit << j;
+                const uint32_t lo = (1u << p) - 1u;
+                for (uint32_t b = t; b < len; b += kDecideThreads)
+                    if (((b >> p) & 1u) == bit) buf[cur ^ 1][((b >> (p + 1)) << p) | (b & lo)] = buf[cur][b];
+                __syncthreads();
+                cur ^= 1;
+                len >>= 1;
+            }
+            chosen = buf[cur][0];
+        }
+    }
+    if (t != 0) return;
+    if (zero) {
+        *err = 1u;
+        chosen = 1.0;
+    }
+    const float fac = (float)(1.0 / sqrt(chosen));
+    for (uint32_t j = 0; j < k; ++j) {
+        const MeasDec &m = dec[f0 + j];
+        const uint32_t b = (bits >> j) & 1u;
+        const float f = j == 0 ? fac : 1.0f;
+        float *e = dyn + 4ull * m.dyn;
+        // [[e0, e1], [e2, e3]]: P0 = diag(f, 0), P1 = diag(0, f), X P1 = [[0, f], [0, 0]]
+        e[0] = b ? 0.0f : f;
+        e[1] = (b && m.reset) ? f : 0.0f;
+        e[2] = 0.0f;
+        e[3] = (b && !m.reset) ? f : 0.0f;
+        outc[m.outc] = (uint8_t)b;
+    }
+}
+
+__global__ void meas_clear_kernel(uint32_t *err) {
+    if (threadIdx.x == 0) *err = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_meas_decide(hipStream_t st, const uint32_t *task_first, const uint32_t *task_count,
+                              const MeasDec *dec, uint32_t n_tasks, int joint, double *sums,
+                              uint32_t bin_stride, float *dyn, uint8_t *outc, uint32_t *err) {
+    if (n_tasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(meas_decide_kernel, dim3(n_tasks), dim3(kDecideThreads), 0, st, task_first, task_count,
+                       dec, n_tasks, joint, sums, bin_stride, dyn, outc, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_meas_clear(hipStream_t st, uint32_t *err) {
+    hipLaunchKernelGGL(meas_clear_kernel, dim3(1), dim3(64), 0, st, err);
     return hipGetLastError();
 }
 

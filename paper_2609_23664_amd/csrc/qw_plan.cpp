@@ -19,6 +19,7 @@
 #include <array>
 #include <map>
 #include <mutex>
+#include <cstring>
 #include <complex>
 #include <cmath>
 #include <complex>
@@ -35,7 +36,7 @@ constexpr size_t kMaxPassGates = 8192;
 
 using cd = std::complex<double>;
 
-enum GClass { C_MIX, C_DIAG, C_PERM, C_CX, C_CZ, C_RENORM };
+enum GClass { C_MIX, C_DIAG, C_PERM, C_CX, C_CZ, C_RENORM, C_DYN };
 
 struct G {
     int kind;
@@ -101,7 +102,7 @@ uint64_t qubit_mask(const G &g) {
 // Qubits that must be local for the gate to run inside a tile.
 uint64_t local_need(const G &g) {
     switch (g.cls) {
-    case C_MIX: case C_PERM: return 1ull << g.q0;
+    case C_MIX: case C_PERM: case C_DYN: return 1ull << g.q0;
     case C_CX: return 1ull << g.q1;  // target only; the control may be global
     default: return 0;
     }
@@ -402,6 +403,19 @@ std::vector<HostOp> fuse_ops(int n, const std::vector<G> &gs, const std::vector<
     };
     for (int i : idx) {
         const G &g = gs[i];
+        if (g.cls == C_DYN) {
+            // an operator whose entries the device writes at run time: the
+            // run on its qubit and the pending factors on it go first; it is
+            // never fused with other gates
+            flush(g.q0);
+            if (touches(g.q0)) emit_dset();
+            HostOp op;
+            op.type = OP_URD;
+            op.a = g.q0;
+            op.m[0] = g.param;  // the address bits of the entries
+            ops.push_back(op);
+            continue;
+        }
         if (g.cls == C_CX || g.cls == C_CZ) {
             flush(g.q0);
             flush(g.q1);
@@ -552,7 +566,10 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
             const DevOp &o = lops_in[ustart[u] + j];
             bool a_loc = o.la != LOC_GLOBAL, b_loc = o.lb != LOC_GLOBAL;
             switch (o.type) {
-            case OP_U: case OP_PERM: case OP_UR: case OP_URT: in.need = o.a; in.bits |= 1u << o.a; break;
+            case OP_U: case OP_PERM: case OP_UR: case OP_URT: case OP_URD:
+                in.need = o.a;
+                in.bits |= 1u << o.a;
+                break;
             case OP_CX: in.need = o.a; in.bits |= (1u << o.a) | (b_loc ? (1u << o.b) : 0u); break;
             case OP_DIAG: in.bits |= a_loc ? (1u << o.a) : 0u; break;
             case OP_PDIAG: in.bits |= o.tmask; break;
@@ -605,7 +622,7 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
                 return J < 4 ? 32.0 : 64.0;
             };
             switch (o.type) {
-            case OP_URT: case OP_UR: c += 32.0 + lane_extra(o.a); break;
+            case OP_URT: case OP_UR: case OP_URD: c += 32.0 + lane_extra(o.a); break;
             case OP_U: c += 64.0 + lane_extra(o.a); break;
             case OP_PERM: c += 16.0 + lane_extra(o.a); break;
             case OP_CX: {
@@ -801,7 +818,7 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
             DevOp o = lops_in[ustart[ui] + uj];
             const bool target_op =
                 (o.type == OP_U || o.type == OP_PERM || o.type == OP_CX || o.type == OP_UR ||
-                 o.type == OP_URT);
+                 o.type == OP_URT || o.type == OP_URD);
             if (o.la != LOC_GLOBAL) {
                 int sl = slot_of(o.a);
                 if (sl >= 0) {
@@ -916,7 +933,12 @@ bool lower_pass(int n, int m, HostPass &p) {
     auto lower_one = [&](const HostOp &h) {
         DevOp o{};
         o.type = h.type;
-        for (int k = 0; k < 8; ++k) o.m[k] = (float)h.m[k];
+        if (h.type == OP_URD) {
+            // the device address of the entries, bit for bit
+            std::memcpy(&o.m[0], &h.m[0], sizeof(double));
+        } else {
+            for (int k = 0; k < 8; ++k) o.m[k] = (float)h.m[k];
+        }
         auto put = [&](int g, uint8_t *bit, uint8_t *loc) {
             if (g < 0) { *bit = 0; *loc = LOC_GLOBAL; return; }
             if ((p.local_mask >> g) & 1ull) {
@@ -984,7 +1006,7 @@ bool lower_pass(int n, int m, HostPass &p) {
 }  // namespace
 
 std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits, Plan *out,
-                       bool relabel, bool lower) {
+                       bool relabel, bool lower, bool allow_dyn) {
     const qw_gate *gates = static_cast<const qw_gate *>(gates_v);
     if (n < 1 || n > kMaxQubits) return "qubit count out of range 1..30";
     if (tile_bits < kMinTileBits || tile_bits > kMaxTileBits) return "tile bits out of range 10..14";
@@ -1001,7 +1023,9 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
             snprintf(buf, sizeof buf, "gate %zu: a measurement cannot be inside a pass plan", i);
             return buf;
         }
-        if (!classify(g.kind, &g.cls)) {
+        if (q.kind == kGateDyn && allow_dyn) {
+            g.cls = C_DYN;
+        } else if (!classify(g.kind, &g.cls)) {
             snprintf(buf, sizeof buf, "gate %zu: unknown kind 0x%x", i, (unsigned)q.kind);
             return buf;
         }
@@ -1018,7 +1042,7 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
                 snprintf(buf, sizeof buf, "gate %zu: bad second qubit %u", i, q.q1);
                 return buf;
             }
-            if (!std::isfinite(q.param)) {
+            if (g.cls != C_DYN && !std::isfinite(q.param)) {
                 snprintf(buf, sizeof buf, "gate %zu: non-finite parameter", i);
                 return buf;
             }

@@ -2,7 +2,8 @@
 recorded calls' device work, so every replay equals the same calls run
 directly, bit for bit (states, expectations, samples), with the context's
 own direct work and synchronisations between replays; recording runs no
-device work; calls that need the host are refused while recording. Every
+device work; calls that need the host are refused while recording (gate
+lists with measurements record: tests/test_gpu_measure.py). Every
 case prints its name before running."""
 import sys
 
@@ -169,7 +170,7 @@ def test_recording_refuses_host_calls(ctx):
             st.sample(0, 1, 1, 0, 8)
         assert ei.value.code == B.QW_E_UNSUPPORTED
         with pytest.raises(B.QwError) as ei:
-            st.apply(0, [("H", (0,), 0.0), ("MEASURE", (0,), 0.5)])
+            st.sample_noalloc(0, 1, 1, 0, 8)
         assert ei.value.code == B.QW_E_UNSUPPORTED
         with pytest.raises(B.QwError) as ei:
             ctx.sync()

@@ -246,3 +246,54 @@ def test_draw_within_rounding_of_the_probability(ctx, B, offset):
         assert 1.0 - _fid(psi, ref) <= 1e-6, (qs, got)
         s64 = psi.astype(np.complex128)
         assert abs(np.vdot(s64, s64).real - 1.0) <= 1e-5
+
+
+def test_measured_batch_records_as_graph(ctx, B):
+    """Measurement decisions run on the device, so a measured batch records
+    as a graph: every replay (with the context's own direct work between
+    replays) gives the eager call's outcomes and bitwise states, from a
+    measured snapshot's suffixes with single and joint decisions and RESET."""
+    n, T = 18, 5
+    say("measured batch as a graph", n)
+    rng = np.random.default_rng(707)
+    prefix, _, _ = _safe(n, _random_measured(n, rng, 2, 2))
+    psi_p, _ = oracle.simulate_measured(n, prefix)
+    sufs = []
+    for k in range(T):
+        g = _random_measured(n, rng, 1, 1 + k % 3)
+        if k == 4:   # a joint cluster: measurements on qubits >= 8 with nothing between
+            g += [("MEASURE", (9,), 0.31), ("RESET", (12,), 0.77), ("MEASURE", (15,), 0.52)]
+        sufs.append(_safe(n, g, psi_p)[0])
+    prov = b"measured-prefix-graph".ljust(32, b"\0")
+    st = B.State(ctx, n, T + 1)
+    st.reset(0, T + 1)
+    st.apply(0, prefix)
+    out_pre = list(B.outcomes(ctx))
+    snap = st.snapshot(0, prov)
+    B.run_suffix_batch(ctx, [snap] * T, sufs, st, list(range(1, T + 1)))
+    out_eager = list(B.outcomes(ctx))
+    eager = [st.host(k) for k in range(1, T + 1)]
+    st.reset(1, T)
+    ctx.begin_graph()
+    try:
+        B.run_suffix_batch(ctx, [snap] * T, sufs, st, list(range(1, T + 1)))
+    finally:
+        g = ctx.end_graph()
+    try:
+        for rep in range(3):
+            st.reset(1, T)
+            g.replay()
+            assert list(g.outcomes()) == out_eager, rep
+            for k in range(T):
+                assert np.array_equal(st.host(k + 1).view(np.uint32), eager[k].view(np.uint32)), (rep, k)
+            # the context's own direct (measured) work between replays
+            st.apply(T, [("H", (3,), 0.0), ("MEASURE", (3,), 0.25)])
+            assert list(B.outcomes(ctx)) in ([0], [1])
+    finally:
+        g.free()
+    for k in range(T):
+        ref, o = oracle.simulate_measured(n, prefix + sufs[k])
+        assert 1.0 - _fid(eager[k], ref) <= 1e-6, k
+    assert len(out_eager) == sum(sum(1 for x in s_ if x[0] in ("MEASURE", "RESET")) for s_ in sufs)
+    snap.free()
+    st.free()
