@@ -366,8 +366,9 @@ ExSwz fixed_swizzle() {
 }
 
 // A map for which every layout in `regs` (register slots of each layout
-// that writes or reads the LDS copy) spreads its accesses over the banks.
-ExSwz choose_swizzle_for(int m, const std::vector<const uint8_t *> &regs) {
+// that writes or reads the LDS copy) spreads its accesses over the banks;
+// `found` (optional) tells whether one was found (else the fixed map).
+ExSwz choose_swizzle_for(int m, const std::vector<const uint8_t *> &regs, bool *found = nullptr) {
     std::vector<std::vector<int>> lanes;
     for (const uint8_t *r : regs) lanes.push_back(lane_list(m, r));
     auto good = [&](const ExSwz &x) {
@@ -382,6 +383,7 @@ ExSwz choose_swizzle_for(int m, const std::vector<const uint8_t *> &regs) {
         }
         return true;
     };
+    if (found) *found = true;
     const ExSwz d = fixed_swizzle();
     if (good(d)) return d;
     std::vector<std::pair<int, uint32_t>> cands;
@@ -397,6 +399,7 @@ ExSwz choose_swizzle_for(int m, const std::vector<const uint8_t *> &regs) {
             x.terms = {cands[i], cands[j]};
             if (good(x)) return x;
         }
+    if (found) *found = false;
     return d;
 }
 
@@ -441,6 +444,17 @@ std::string emit_body(int m, const HostPass &p) {
         return t.str();
     };
     g << tl_def(0);
+    // One LDS map for all layouts of the pass, when one spreads them all
+    // over the banks: a thread then writes each exchange's values to the
+    // addresses it read them from in the exchange before (the same local
+    // indices under the same map), which no other thread reads, so a full
+    // exchange after the tile's first one needs only the barrier between
+    // its writes and its reads, and early waves write while late ones still
+    // compute.
+    std::vector<const uint8_t *> lays;
+    for (const DevPhase &f : ph) lays.push_back(f.reg);
+    bool one_map = false;
+    const ExSwz xall = choose_swizzle_for(m, lays, &one_map);
     auto roff = [&](const DevPhase &f, int r) {
         uint32_t l = 0;
         for (int s2 = 0; s2 < 4; ++s2)
@@ -454,11 +468,14 @@ std::string emit_body(int m, const HostPass &p) {
             // only within each wave (the first exchange of a tile stays a
             // full one: the previous tile's reads may still be in flight)
             const bool local = k > 1 && wave_bits(m, ph[k - 1]) == wave_bits(m, ph[k]);
-            const ExSwz x = choose_swizzle(m, ph[k - 1], ph[k]);
+            const ExSwz x = one_map ? xall : choose_swizzle(m, ph[k - 1], ph[k]);
             auto thread_addr = [&](const std::string &t) { return swz_addr(x, t); };
             g << "    {   // exchange " << k - 1 << " -> " << k << (local ? " (within waves)" : "") << "\n";
             g << "        const uint32_t s8 = " << thread_addr("tl" + std::to_string(k - 1)) << ";\n";
-            g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
+            if (local)
+                g << "        lds_wave_sync();\n";
+            else if (!one_map || k == 1)
+                g << "        lds_barrier();\n";
             for (int r = 0; r < 16; ++r)
                 g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(roff(ph[k - 1], r)) << 3)
                   << "u)) = v[" << r << "];\n";
