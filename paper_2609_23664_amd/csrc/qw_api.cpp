@@ -477,7 +477,7 @@ struct Exec {
     // fused expectation epilogue of the last pass (generated kernels only)
     const RedPlan *epi = nullptr;
     const std::string *epi_key = nullptr;
-    double *epi_part = nullptr;  // this task's [tiles][epi_nt] partials
+    double *epi_part = nullptr;  // this task's [rows][epi_nt] partials
     uint32_t epi_nt = 0;
 };
 
@@ -956,6 +956,7 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     const int m = tile_bits_for((int)n, ctx->tile_bits);
     const bool small = m < kMinTileBits;
     const uint32_t tiles = small ? 1u : (1u << (n - m));
+    const uint32_t rows = tiles / red_row_tiles(tiles);   // partial rows per slot
     // terms whose partials a fused pass epilogue already wrote are left out
     std::vector<TermGroup> groups;
     if (fused && !small) {
@@ -1009,7 +1010,7 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     const size_t desc_off = L.take(n_desc * (small ? sizeof(ReduceDescSmall) : sizeof(ReduceDesc)));
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
-    const size_t part_bytes = (size_t)ns * tiles * n_terms * sizeof(double);
+    const size_t part_bytes = (size_t)ns * rows * n_terms * sizeof(double);
     const size_t out_bytes = ns * sizeof(double);
     rc = ensure(ctx, ctx->scratch, part_bytes + out_bytes + 256, "reduce scratch");
     if (rc) return rc;
@@ -1059,7 +1060,7 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
                 d.terms = reinterpret_cast<const TermDev *>(dbase + t_off[g]);
                 d.phases = reinterpret_cast<const RedPhase *>(dbase + p_off[g]);
                 d.cols = reinterpret_cast<const uint32_t *>(dbase + c_off[g]);
-                d.part = part + (size_t)s * tiles * n_terms;
+                d.part = part + (size_t)s * rows * n_terms;
                 d.local_mask = groups[g].local_mask;
                 d.n_phases = (uint32_t)rplans[g].phases.size();
                 d.n_terms = (uint32_t)rplans[g].terms.size();
@@ -1103,7 +1104,7 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     }
     hipError_t er = launch_expect_finalize(ctx->stream, part,
                                            reinterpret_cast<const double *>(dbase + coeff_off),
-                                           n_terms, tiles, ns, dout);
+                                           n_terms, rows, ns, dout);
     if (er != hipSuccess) return hip_fail(ctx, er, "finalize launch");
     if (out_is_host) {
         HIP_TRY(ctx, hipMemcpyAsync(out, dout, out_bytes, hipMemcpyDeviceToHost, ctx->stream),
@@ -1793,15 +1794,16 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         plan_fused(ctx, dst->n, ex, epi->x_mask, epi->z_mask, epi->n_terms, &fe);
     if (fe.active) {
         const int m = ex[0].planp->m;
-        const uint64_t tiles = 1ull << (dst->n - m);
-        const size_t part_bytes = (size_t)n_tasks * tiles * epi->n_terms * sizeof(double);
+        const uint32_t tiles = 1u << (dst->n - m);
+        const uint32_t rows = tiles / red_row_tiles(tiles);
+        const size_t part_bytes = (size_t)n_tasks * rows * epi->n_terms * sizeof(double);
         int rc0 = ensure(ctx, ctx->scratch, part_bytes + n_tasks * sizeof(double) + 256, "reduce scratch");
         if (rc0) return rc0;
         double *part = static_cast<double *>(ctx->scratch.p);
         for (uint32_t k = 0; k < n_tasks; ++k) {
             ex[k].epi = &fe.rplan;
             ex[k].epi_key = &fe.key;
-            ex[k].epi_part = part + (size_t)k * tiles * epi->n_terms;
+            ex[k].epi_part = part + (size_t)k * rows * epi->n_terms;
             ex[k].epi_nt = epi->n_terms;
         }
     }

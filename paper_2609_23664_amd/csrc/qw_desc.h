@@ -149,13 +149,21 @@ struct alignas(16) PassDesc {
     const uint32_t *tile_base_out;  // PD_REMAP_OUT: L(tile_base), per tile
     const IoRec *io_in;    // address record of phase 0
     const IoRec *io_out;   // address record of the last phase
-    double *red_part;      // fused expectation epilogue: [tiles][red_nt] FP64 partials
+    double *red_part;      // fused expectation epilogue: [rows][red_nt] FP64 partials
     uint32_t n_ops;
     uint32_t n_phases;
     uint32_t flags;
-    uint32_t red_nt;       // fused expectation epilogue: columns per tile (all terms)
+    uint32_t red_nt;       // fused expectation epilogue: columns per row (all terms)
 };
 static_assert(sizeof(PassDesc) == 128, "PassDesc layout");
+
+// Expectation partials are kept per row of kRedRowTiles consecutive tiles of
+// a state (all of its tiles when it has fewer): each thread adds its FP32
+// term values over the row's tiles, in tile order, before the FP64 sum
+// across lanes and waves, so a row's partials do not depend on which
+// workgroup processed it or on the launch's item order.
+constexpr uint32_t kRedRowTiles = 4;
+constexpr uint32_t red_row_tiles(uint32_t tiles) { return tiles < kRedRowTiles ? tiles : kRedRowTiles; }
 
 // Expectation reducer, small states (n < 10): the whole state is one tile
 // staged in LDS; one descriptor per slot.
@@ -207,7 +215,7 @@ struct alignas(16) ReduceDesc {
     const TermDev *terms;
     const RedPhase *phases;
     const uint32_t *cols;  // group-local column -> column of the partial array
-    double *part;          // [tiles][n_terms_total] of this slot
+    double *part;          // [rows][n_terms_total] of this slot (see kRedRowTiles)
     const uint32_t *tile_base;  // global index of local index 0, per tile
     uint64_t local_mask;
     uint32_t n_phases;

@@ -584,9 +584,11 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
         // fused expectation epilogue: the tile's terms, evaluated after the
         // store from the last phase's registers (staged through LDS)
         std::ostringstream e;
-        e << "constexpr int ENT = " << epi->cols.size() << ";\n#define NT ENT\n";
+        e << "constexpr int ENT = " << epi->cols.size() << ";\n";
+        // items are (descriptor, row of RT consecutive tiles), run in order
+        e << "constexpr uint32_t RT = " << red_row_tiles(1u << (n - m)) << "u;\n";
         emit_reduce_tile(e, m, *epi, &p.dev_phases.back(), "epi_tile");
-        e << "#undef NT\n__device__ const uint32_t kECols[ENT] = {";
+        e << "__device__ const uint32_t kECols[ENT] = {";
         for (size_t c = 0; c < epi->cols.size(); ++c) e << (c ? ", " : "") << epi->cols[c] << "u";
         e << "};\n";
         g << e.str();
@@ -615,8 +617,8 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
         g << "extern \"C\" __global__ __launch_bounds__(T) void qw_pass(const PassDesc *__restrict__ "
              "descs, uint32_t n_descs, uint32_t items, int remap, uint32_t tmaj) {\n"
              "    (void)remap;\n"
-             "    // item -> (descriptor, tile): tmaj = 0 descriptor-fastest, else\n"
-             "    // tile-fastest with 1 << (tmaj - 1) tiles per descriptor\n"
+             "    // item -> (descriptor, tile" << (epi ? " row" : "") << "): tmaj = 0 descriptor-fastest, else\n"
+             "    // tile-fastest with 1 << (tmaj - 1) items per descriptor\n"
              "    const uint32_t tg = tmaj ? tmaj - 1u : 0u;\n"
              "    auto desc_of = [=](uint32_t it) { return tmaj ? (it >> tg) : (it % n_descs); };\n"
              "    auto tile_of = [=](uint32_t it) { return tmaj ? (it & ((1u << tg) - 1u)) : (it / n_descs); };\n"
@@ -634,17 +636,24 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "    const uint32_t wave = uni(tid >> 6);\n"
              "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave), wx = io_out_wxor(wave);\n"
              "    const uint32_t li = io_in_lane(lane), lo = io_out_lane(lane);\n"
-             "    char *lb = reinterpret_cast<char *>(lds);\n"
-             "    float2 nv[" << std::max(1, PF) << "];\n"
+             "    char *lb = reinterpret_cast<char *>(lds);\n";
+        if (epi)
+            g << "    uint32_t rk = 0;   // tile of the row\n"
+                 "    float acc[ENT];\n"
+                 "    #pragma unroll\n"
+                 "    for (int i = 0; i < ENT; ++i) acc[i] = 0.f;\n";
+        const char *tile0 = epi ? "tile_of(item) * RT" : "tile_of(item)";
+        g << "    float2 nv[" << std::max(1, PF) << "];\n"
              "    {\n"
              "        const PassDesc *d0 = descs + desc_of(item);\n"
-             "        load_pre(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + tile_of(item))) | wi, li);\n"
+             "        load_pre(nv, ldu(&d0->src), uni(ldu(ldu(&d0->tile_base) + " << tile0 << ")) | wi, li);\n"
              "    }\n"
              "    while (true) {\n"
              "        float2 v[16];\n"
              "        #pragma unroll\n"
              "        for (int k = 0; k < " << PF << "; ++k) v[k] = nv[k];\n"
-             "        const uint32_t p = desc_of(item), tile = tile_of(item);\n"
+             "        const uint32_t p = desc_of(item), tile = " << (epi ? "tile_of(item) * RT + rk" : "tile_of(item)")
+          << ";\n"
              "        const PassDesc *d = descs + p;\n"
              "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tile));\n"
              "        {\n"
@@ -653,11 +662,20 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "            #pragma unroll\n"
              "            for (int k = " << PF << "; k < 16; ++k) v[k] = rest[k - " << PF << "];\n"
              "        }\n"
-             "        const uint32_t next = item + wpx;\n"
-             "        const bool has_next = next < last;\n"
+             "";
+        if (epi)
+            g << "        uint32_t next = item, nk = rk + 1u;\n"
+                 "        if (nk == RT) {\n"
+                 "            next = item + wpx;\n"
+                 "            nk = 0u;\n"
+                 "        }\n";
+        else
+            g << "        const uint32_t next = item + wpx;\n";
+        g << "        const bool has_next = next < last;\n"
              "        if (has_next) {\n"
              "            const PassDesc *dn = descs + desc_of(next);\n"
-             "            load_pre(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + tile_of(next))) | wi, li);\n"
+             "            load_pre(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + "
+          << (epi ? "tile_of(next) * RT + nk" : "tile_of(next)") << ")) | wi, li);\n"
              "        }\n";
         if (p.scale_in) g << kScaleIn;
         g << "        body(v, ldu(&d->ops), tid, lane, base, lb);\n";
@@ -675,10 +693,11 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
                  "        }\n";
         g << "        store_out(v, ldu(&d->dst), ((uint64_t)" << obase << " ^ wx) | wo, lo);\n";
         if (epi)
-            g << "        epi_tile(v, tid, lane, base, lb, red);\n"
-                 "        __syncthreads();\n"
-                 "        {\n"
-                 "            double *part = ldu(&d->red_part) + (uint64_t)tile * ldu(&d->red_nt);\n"
+            g << "        epi_tile(v, tid, lane, base, lb, acc);\n"
+                 "        if (rk == RT - 1u) {\n"
+                 "            epi_tile_flush(acc, lane, wave, red);\n"
+                 "            __syncthreads();\n"
+                 "            double *part = ldu(&d->red_part) + (uint64_t)tile_of(item) * ldu(&d->red_nt);\n"
                  "            for (uint32_t c = tid; c < (uint32_t)ENT; c += T) {\n"
                  "                double s = 0.0;\n"
                  "                for (int ww = 0; ww < T / 64; ++ww) s += red[ww * ENT + c];\n"
@@ -686,8 +705,9 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
                  "            }\n"
                  "        }\n";
         g << "        if (!has_next) break;\n"
-             "        item = next;\n"
-             "    }\n"
+             "        item = next;\n";
+        if (epi) g << "        rk = nk;\n";
+        g << "    }\n"
              "}\n";
     }
     return g.o.str();
@@ -725,13 +745,15 @@ std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp) 
 }
 
 // Term evaluation of one tile for a reducer plan (shared by the generated
-// reducers and the fused expectation epilogue of pass kernels): writes each
-// term's per-wave FP64 sum into red[wave * NT + column]. Without `stage`, v
-// holds the tile in the I/O layout (register slots = local bits 0, 7, 8, 9);
-// with `stage`, v holds the tile in that phase layout (the last phase of a
+// reducers and the fused expectation epilogue of pass kernels): adds each
+// term's per-thread FP32 value into acc[column]. Without `stage`, v holds
+// the tile in the I/O layout (register slots = local bits 0, 7, 8, 9); with
+// `stage`, v holds the tile in that phase layout (the last phase of a
 // pass). A diagonal phase (the first phase, when there is one) in the layout
 // v already holds is evaluated on v; the other phases read the tile from an
-// LDS copy staged first.
+// LDS copy staged first. `name`_flush sums a row's accumulators over the
+// wave 8 at a time in FP64 (each term's wave sum is the same butterfly
+// whatever its position) into red[wave * NT + column] and clears them.
 static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, const DevPhase *stage,
                              const char *name) {
     static const uint8_t io_reg[4] = {0, 7, 8, 9};
@@ -748,9 +770,10 @@ static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, co
     for (size_t pi = 0; pi < rp.phases.size(); ++pi)
         if (from_lds[pi]) lay.push_back(rp.phases[pi].reg);
     const ExSwz x = choose_swizzle_for(m, lay);
+    const size_t nt = rp.cols.size();
     o << "__device__ __forceinline__ void " << name << "(float2 (&v)[16], uint32_t tid, uint32_t lane, "
-         "uint64_t base, char *lb, double *red) {\n";
-    o << "    const uint32_t wave = tid >> 6;\n    (void)lb; (void)base;\n";
+         "uint64_t base, char *lb, float (&acc)[" << nt << "]) {\n";
+    o << "    (void)lb; (void)base; (void)lane;\n";
     if (stage && any_lds) {
         o << "    {\n        uint32_t tids = tid; __asm__ volatile(\"\" : \"+v\"(tids));\n"
           << "        const uint32_t tls = thread_local_index(tids, " << (int)stage->reg[0] << "u, "
@@ -772,22 +795,6 @@ static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, co
             o << "    }\n    lds_barrier();\n";
         }
     }
-    // Per-thread FP32 term values are shifted into q[0..7] across phases and
-    // summed over the wave 8 at a time (each term's wave sum uses the same
-    // butterfly whatever its position, so the packing does not change it).
-    std::vector<uint32_t> pending;
-    auto flush = [&](const char *ind) {
-        const size_t nb = pending.size();
-        o << ind << "{\n" << ind << "    const double h = wave_reduce8(q, lane);\n";
-        o << ind << "    if (lane < 8u) {\n" << ind << "        const uint32_t pos = 4u * (lane & 1u) + "
-          << "2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);\n";
-        for (size_t j = 0; j < nb; ++j)
-            o << ind << "        if (pos == " << nb - 1 - j << "u) red[wave * NT + " << pending[j] << "] = h;\n";
-        o << ind << "    }\n" << ind << "    #pragma unroll\n" << ind << "    for (int i = 0; i < 8; ++i) q[i] = 0.f;\n"
-          << ind << "}\n";
-        pending.clear();
-    };
-    o << "    float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};\n";
     for (size_t pi = 0; pi < rp.phases.size(); ++pi) {
         const RedPhase &f = rp.phases[pi];
         o << "    {   // phase " << pi << (f.diag ? " (diagonal terms)" : "") << "\n";
@@ -816,15 +823,26 @@ static void emit_reduce_tile(std::ostringstream &o, int m, const RedPlan &rp, co
             if (t.zt) o << " ^ (uint32_t)__popc(tl & " << t.zt << "u)";
             if (t.zg) o << " ^ (uint32_t)__popcll(base & " << hex(t.zg) << ")";
             o << ") & 1u;\n            if (par) a = -a;\n";
-            o << "            #pragma unroll\n            for (int i = 7; i > 0; --i) q[i] = q[i - 1];\n"
-                 "            q[0] = a;\n        }\n";
-            pending.push_back(t.col);
-            if (pending.size() == 8) flush("        ");
+            o << "            acc[" << t.col << "] += a;\n        }\n";
         }
         o << "    }\n";
     }
-    if (!pending.empty()) flush("    ");
     o << "}\n";
+    o << "__device__ __forceinline__ void " << name << "_flush(float (&acc)[" << nt
+      << "], uint32_t lane, uint32_t wave, double *red) {\n";
+    for (size_t c0 = 0; c0 < nt; c0 += 8) {
+        o << "    {\n        float q[8] = {";
+        for (size_t i = 0; i < 8; ++i) {
+            if (i) o << ", ";
+            if (c0 + i < nt) o << "acc[" << c0 + i << "]";
+            else o << "0.f";
+        }
+        o << "};\n        const double h = wave_reduce8(q, lane);\n"
+          << "        const uint32_t pos = 4u * (lane & 1u) + 2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);\n"
+          << "        if (lane < 8u && pos < " << std::min<size_t>(8, nt - c0) << "u) red[wave * " << nt << " + "
+          << c0 << "u + pos] = h;\n    }\n";
+    }
+    o << "    #pragma unroll\n    for (int i = 0; i < " << nt << "; ++i) acc[i] = 0.f;\n}\n";
 }
 
 std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &rp) {
@@ -864,53 +882,67 @@ std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &r
     o << "__device__ const uint32_t kCols[NT] = {";
     for (size_t c = 0; c < NT; ++c) o << (c ? ", " : "") << rp.cols[c] << "u";
     o << "};\n";
+    // items are (descriptor, row of RT consecutive tiles); the row's tiles
+    // run in order on one workgroup, the next tile's load in flight
+    o << "constexpr uint32_t RT = " << red_row_tiles(1u << (n - m)) << "u;\n";
     o << "extern \"C\" __global__ __launch_bounds__(T) void qw_reduce(const ReduceDesc *__restrict__ descs, "
          "uint32_t n_descs, uint32_t items, uint32_t tmaj) {\n"
          "    __shared__ float2 lds[1 << M];\n"
          "    __shared__ double red[W * NT];\n"
          "    const uint32_t tg = tmaj ? tmaj - 1u : 0u;\n"
          "    auto desc_of = [=](uint32_t it) { return tmaj ? (it >> tg) : (it % n_descs); };\n"
-         "    auto tile_of = [=](uint32_t it) { return tmaj ? (it & ((1u << tg) - 1u)) : (it / n_descs); };\n"
+         "    auto row_of = [=](uint32_t it) { return tmaj ? (it & ((1u << tg) - 1u)) : (it / n_descs); };\n"
          "    const uint32_t w = blockIdx.x, x = w & 7u, j = w >> 3, wpx = gridDim.x >> 3;\n"
          "    const uint32_t per = (items + 7u) >> 3;\n"
          "    const uint32_t first = x * per;\n"
          "    const uint32_t last = (first + per < items) ? first + per : items;\n"
-         "    uint32_t item = first + j;\n"
+         "    uint32_t item = first + j, k = 0;\n"
          "    if (item >= last) return;\n"
          "    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = uni(tid >> 6);\n"
          "    const uint64_t wi = io_wave(wave);\n"
          "    const uint32_t li = io_lane(lane);\n"
          "    char *lb = reinterpret_cast<char *>(lds);\n"
+         "    float acc[NT];\n"
+         "    #pragma unroll\n"
+         "    for (int i = 0; i < NT; ++i) acc[i] = 0.f;\n"
          "    float2 nv[16];\n"
          "    {\n"
          "        const ReduceDesc *d0 = descs + desc_of(item);\n"
-         "        load_in(nv, ldu(&d0->psi), uni(ldu(ldu(&d0->tile_base) + tile_of(item))) | wi, li);\n"
+         "        load_in(nv, ldu(&d0->psi), uni(ldu(ldu(&d0->tile_base) + row_of(item) * RT)) | wi, li);\n"
          "    }\n"
          "    while (true) {\n"
          "        float2 v[16];\n"
          "        #pragma unroll\n"
-         "        for (int k = 0; k < 16; ++k) v[k] = nv[k];\n"
-         "        const uint32_t p = desc_of(item), tl_ = tile_of(item);\n"
+         "        for (int r = 0; r < 16; ++r) v[r] = nv[r];\n"
+         "        const uint32_t p = desc_of(item), row = row_of(item);\n"
          "        const ReduceDesc *d = descs + p;\n"
-         "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + tl_));\n"
-         "        const uint32_t next = item + wpx;\n"
-         "        const bool has_next = next < last;\n"
+         "        const uint64_t base = uni(ldu(ldu(&d->tile_base) + row * RT + k));\n"
+         "        uint32_t ni = item, nk = k + 1u;\n"
+         "        if (nk == RT) {\n"
+         "            ni = item + wpx;\n"
+         "            nk = 0u;\n"
+         "        }\n"
+         "        const bool has_next = ni < last;\n"
          "        if (has_next) {\n"
-         "            const ReduceDesc *dn = descs + desc_of(next);\n"
-         "            load_in(nv, ldu(&dn->psi), uni(ldu(ldu(&dn->tile_base) + tile_of(next))) | wi, li);\n"
+         "            const ReduceDesc *dn = descs + desc_of(ni);\n"
+         "            load_in(nv, ldu(&dn->psi), uni(ldu(ldu(&dn->tile_base) + row_of(ni) * RT + nk)) | wi, li);\n"
          "        }\n"
          "        __syncthreads();  // the previous tile's LDS and partial reads are done\n"
-         "        tile(v, tid, lane, base, lb, red);\n"
-         "        __syncthreads();\n"
-         "        double *part = ldu(&d->part);\n"
-         "        const uint32_t ntt = ldu(&d->n_terms_total);\n"
-         "        for (uint32_t c = tid; c < (uint32_t)NT; c += T) {\n"
-         "            double s = 0.0;\n"
-         "            for (int ww = 0; ww < W; ++ww) s += red[ww * NT + c];\n"
-         "            gout<double>(part)[(uint64_t)tl_ * ntt + kCols[c]] = s;\n"
+         "        tile(v, tid, lane, base, lb, acc);\n"
+         "        if (k == RT - 1u) {\n"
+         "            tile_flush(acc, lane, wave, red);\n"
+         "            __syncthreads();\n"
+         "            double *part = ldu(&d->part);\n"
+         "            const uint32_t ntt = ldu(&d->n_terms_total);\n"
+         "            for (uint32_t c = tid; c < (uint32_t)NT; c += T) {\n"
+         "                double s = 0.0;\n"
+         "                for (int ww = 0; ww < W; ++ww) s += red[ww * NT + c];\n"
+         "                gout<double>(part)[(uint64_t)row * ntt + kCols[c]] = s;\n"
+         "            }\n"
          "        }\n"
          "        if (!has_next) break;\n"
-         "        item = next;\n"
+         "        item = ni;\n"
+         "        k = nk;\n"
          "    }\n"
          "}\n";
     return o.str();
@@ -1216,6 +1248,7 @@ std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<con
         k->wg = use_lds ? T : (T < 256 ? T : 256);
         k->parts = use_lds ? 1 : T / k->wg;
         k->blocks_per_cu = 1;
+        if (!ks[i].pass || ks[i].epi) k->row_tiles = (int)red_row_tiles(1u << (ks[i].n - m));
         if (use_lds) {
             int nb = 0;
             if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, k->wg, 0) == hipSuccess &&
@@ -1229,7 +1262,7 @@ std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<con
 }
 
 // Item-order argument of the persistent kernels: 0 for descriptor-fastest,
-// else 1 + log2(tiles) for tile-fastest (tiles is a power of two).
+// else 1 + log2(items per descriptor) for tile-fastest (a power of two).
 static uint32_t tile_order_arg(uint32_t tiles, bool tile_major) {
     if (!tile_major || tiles == 0 || (tiles & (tiles - 1)) != 0) return 0u;
     return 1u + (uint32_t)__builtin_ctz(tiles);
@@ -1237,8 +1270,9 @@ static uint32_t tile_order_arg(uint32_t tiles, bool tile_major) {
 
 hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs, uint32_t n_descs,
                       uint32_t tiles, int remap, uint32_t cu_count, bool tile_major) {
-    const uint32_t items = n_descs * tiles;
-    uint32_t tmaj = k.use_lds ? tile_order_arg(tiles, tile_major) : 0u;
+    const uint32_t rows = tiles / (uint32_t)k.row_tiles;
+    const uint32_t items = n_descs * rows;
+    uint32_t tmaj = k.use_lds ? tile_order_arg(rows, tile_major) : 0u;
     uint32_t grid;
     if (k.use_lds) {
         const uint32_t full = cu_count * (uint32_t)k.blocks_per_cu;
@@ -1256,8 +1290,9 @@ hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs,
 
 hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDesc *descs,
                              uint32_t n_descs, uint32_t tiles, uint32_t cu_count, bool tile_major) {
-    uint32_t tmaj = tile_order_arg(tiles, tile_major);
-    const uint32_t items = n_descs * tiles;
+    const uint32_t rows = tiles / (uint32_t)k.row_tiles;
+    uint32_t tmaj = tile_order_arg(rows, tile_major);
+    const uint32_t items = n_descs * rows;
     const uint32_t full = cu_count * (uint32_t)k.blocks_per_cu;
     const uint32_t want = ((items + 7u) / 8u) * 8u;
     uint32_t grid = want < full ? want : (full / 8u) * 8u;

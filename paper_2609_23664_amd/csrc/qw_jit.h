@@ -42,6 +42,8 @@ struct JitKernel {
     int wg = 0;            // threads per workgroup
     int parts = 1;         // workgroups per tile (flat form)
     int blocks_per_cu = 1; // resident workgroups per CU (LDS form)
+    int row_tiles = 1;     // reducers and pass kernels with an expectation
+                           // epilogue: tiles per item (a row of kRedRowTiles)
 };
 
 // Exact structural key and source of the generated expectation reducer of

@@ -23,14 +23,15 @@ hipError_t launch_norm_finalize(hipStream_t st, const PassDesc *d, uint32_t n_de
 hipError_t launch_init(hipStream_t st, void *base, uint32_t n, uint32_t n_slots);
 // Device-to-device copy of `bytes` (multiple of 16).
 hipError_t launch_copy(hipStream_t st, void *dst, const void *src, uint64_t bytes);
-// Expectation partials for n_descs (slot, term group) descriptors.
+// Expectation partials for n_descs (slot, term group) descriptors: one
+// workgroup per (descriptor, row of tiles).
 hipError_t launch_reduce(hipStream_t st, const ReduceDesc *d, uint32_t n_descs, uint32_t n,
                          uint32_t M);
 hipError_t launch_reduce_small(hipStream_t st, const ReduceDescSmall *d, uint32_t n_descs,
                                uint32_t n);
-// Per-slot sum over tiles and terms of the partials.
+// Per-slot sum over rows (see kRedRowTiles) and terms of the partials.
 hipError_t launch_expect_finalize(hipStream_t st, const double *part, const double *coeff,
-                                  uint32_t n_terms, uint32_t tiles, uint32_t n_slots,
+                                  uint32_t n_terms, uint32_t rows, uint32_t n_slots,
                                   double *out);
 // Inverse-CDF sampling of `shots` outcomes for n_slots slots (device array
 // of slot pointers). csum/cpre: n_slots * chunks doubles; total: n_slots.

@@ -698,12 +698,16 @@ __device__ __forceinline__ float pair_sum_x(uint32_t xr, const float2 (&v)[16], 
 }
 
 
-// Register-phase reducer. One workgroup per (slot, group, tile): the tile is
-// loaded with the I/O layout, staged once in LDS, and re-read with each
-// phase's layout. For up to 8 terms at a time every thread holds one FP32
-// partial per term; they are converted to FP64 and summed across the wave
-// by a butterfly that halves the number of values per lane at each of the
-// first three steps (fixed order); wave sums are added in wave order.
+// Register-phase reducer. One workgroup per (slot, group, row of tiles):
+// each tile is loaded with the I/O layout, staged in LDS, and re-read with
+// each phase's layout. Terms are taken 8 at a time (in phase order): every
+// thread adds each term's FP32 value over the row's tiles in tile order,
+// then the 8 sums are converted to FP64 and summed across the wave by a
+// butterfly that halves the number of values per lane at each of the first
+// three steps (fixed order); wave sums are added in wave order. A term's
+// result does not depend on the other terms of its chunk, so the generated
+// reducers (all terms of a tile at once) round identically. The row's tiles
+// are re-read for each chunk of 8 terms.
 template <int M>
 __global__ __launch_bounds__(1 << (M - 4)) void reduce_kernel(const ReduceDesc *__restrict__ descs,
                                                               uint32_t n_descs, uint32_t n,
@@ -715,111 +719,104 @@ __global__ __launch_bounds__(1 << (M - 4)) void reduce_kernel(const ReduceDesc *
     const uint32_t item = blockIdx.x;
     if (item >= items) return;
     const uint32_t p = item % n_descs;
-    const uint64_t tile = item / n_descs;
+    const uint32_t tiles = 1u << (n - M), rt = red_row_tiles(tiles);
+    const uint64_t row = item / n_descs;
     const ReduceDesc d = ld_words(descs + p);
     const uint64_t lmask = d.local_mask;
     const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
-    const uint64_t base = dpdep(tile, full & ~lmask);
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint8_t io[4] = {0, 7, 8, 9};   // I/O layout: register slots = local bits 0, 7, 8, 9
 
-    float2 v[16];
-    {
-        // I/O layout: register slots = local bits {0, 7, 8, 9}
-        const uint8_t io[4] = {0, 7, 8, 9};
-        const uint32_t tl = thread_local_index(tid, io);
-        const IoLayout lay = io_layout(lmask, io, IO_F4, lane, uni(tid >> 6), M, (uint32_t)base);
-        io_load(v, d.psi, lay, IO_F4);
-        const uint32_t stl8 = swz(tl) << 3;
-        char *lb = reinterpret_cast<char *>(lds);
+    for (uint32_t j0 = 0; j0 < d.n_terms; j0 += 8u) {
+        const uint32_t j1 = j0 + 8u < d.n_terms ? j0 + 8u : d.n_terms;
+        float q[8];
         #pragma unroll
-        for (int k = 0; k < 16; ++k)
-            *reinterpret_cast<float2 *>(lb + lds_off(stl8, io, k)) = v[k];
-    }
-    __syncthreads();
-
-    // term values are shifted into q across phases and summed over the wave
-    // 8 at a time (each term's wave sum is the same butterfly whatever its
-    // position); pc holds the pending terms' columns, newest first
-    float q[8];
-    uint32_t pc[8];
-    #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        q[i] = 0.0f;
-        pc[i] = 0u;
-    }
-    uint32_t np = 0;
-    auto flush = [&]() {
+        for (int i = 0; i < 8; ++i) q[i] = 0.0f;
+        for (uint32_t k = 0; k < rt; ++k) {
+            const uint64_t tile = row * rt + k;
+            const uint64_t base = dpdep(tile, full & ~lmask);
+            float2 v[16];
+            {
+                const uint32_t tl = thread_local_index(tid, io);
+                const IoLayout lay = io_layout(lmask, io, IO_F4, lane, uni(tid >> 6), M, (uint32_t)base);
+                io_load(v, d.psi, lay, IO_F4);
+                __syncthreads();   // the previous tile's LDS reads are done
+                const uint32_t stl8 = swz(tl) << 3;
+                char *lb = reinterpret_cast<char *>(lds);
+                #pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    *reinterpret_cast<float2 *>(lb + lds_off(stl8, io, r)) = v[r];
+            }
+            __syncthreads();
+            for (uint32_t pi = 0; pi < d.n_phases; ++pi) {
+                const RedPhase ph = ld_words(d.phases + pi);
+                if (ph.t_end <= j0 || ph.t_begin >= j1) continue;
+                const uint32_t tl = thread_local_index(tid, ph.reg);
+                if (!ph.diag) {
+                    const uint32_t stl8 = swz(tl) << 3;
+                    const char *lb = reinterpret_cast<const char *>(lds);
+                    #pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        v[r] = *reinterpret_cast<const float2 *>(lb + lds_off(stl8, ph.reg, r));
+                }
+                float pr[16];
+                if (ph.diag) {
+                    #pragma unroll
+                    for (int r = 0; r < 16; ++r) pr[r] = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
+                }
+                const uint32_t jb = ph.t_begin > j0 ? ph.t_begin : j0;
+                const uint32_t je = ph.t_end < j1 ? ph.t_end : j1;
+                for (uint32_t j = jb; j < je; ++j) {
+                    const TermDev t = ld_words(d.terms + j);
+                    float a;
+                    if (ph.diag) {
+                        a = diag_sum(pr, t.smask);
+                    } else {
+                        a = t.odd ? pair_sum_x<true>(t.xr, v, t.smask)
+                                  : pair_sum_x<false>(t.xr, v, t.smask);
+                        a *= 2.0f;
+                    }
+                    const uint32_t par = (t.neg ^ __popc(tl & t.zt) ^ (uint32_t)__popcll(base & t.zg)) & 1u;
+                    if (par) a = -a;
+                    // q[j - j0] += a, with constant register indices
+                    #pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if ((uint32_t)i == j - j0) q[i] += a;
+                }
+            }
+        }
         const double h = wave_reduce8(q, lane);
         if (lane < 8u) {
             const uint32_t pos = 4u * (lane & 1u) + 2u * ((lane >> 1) & 1u) + ((lane >> 2) & 1u);
-            #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (pos == (uint32_t)i && (uint32_t)i < np) red[wave * kMaxGroupTerms + pc[i]] = h;
-        }
-        #pragma unroll
-        for (int i = 0; i < 8; ++i) q[i] = 0.0f;
-        np = 0;
-    };
-    for (uint32_t pi = 0; pi < d.n_phases; ++pi) {
-        const RedPhase ph = ld_words(d.phases + pi);
-        const uint32_t tl = thread_local_index(tid, ph.reg);
-        if (!ph.diag) {
-            const uint32_t stl8 = swz(tl) << 3;
-            const char *lb = reinterpret_cast<const char *>(lds);
-            #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                v[k] = *reinterpret_cast<const float2 *>(lb + lds_off(stl8, ph.reg, k));
-        }
-        float pr[16];
-        if (ph.diag) {
-            #pragma unroll
-            for (int k = 0; k < 16; ++k) pr[k] = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
-        }
-        for (uint32_t j = ph.t_begin; j < ph.t_end; ++j) {
-            const TermDev t = ld_words(d.terms + j);
-            float a;
-            if (ph.diag) {
-                a = diag_sum(pr, t.smask);
-            } else {
-                a = t.odd ? pair_sum_x<true>(t.xr, v, t.smask)
-                          : pair_sum_x<false>(t.xr, v, t.smask);
-                a *= 2.0f;
+            if (j0 + pos < j1) {
+                // a per-lane load (ld_words reads wave-uniform records)
+                const uint32_t col = d.terms[j0 + pos].col;
+                red[wave * kMaxGroupTerms + col] = h;
             }
-            const uint32_t par = (t.neg ^ __popc(tl & t.zt) ^ (uint32_t)__popcll(base & t.zg)) & 1u;
-            if (par) a = -a;
-            #pragma unroll
-            for (int i = 7; i > 0; --i) {
-                q[i] = q[i - 1];
-                pc[i] = pc[i - 1];
-            }
-            q[0] = a;
-            pc[0] = t.col;
-            if (++np == 8u) flush();
         }
     }
-    if (np) flush();
     __syncthreads();
     for (uint32_t c = tid; c < d.n_terms; c += T) {
         double s = 0.0;
         for (int w = 0; w < W; ++w) s += red[w * kMaxGroupTerms + c];
-        gout<double>(d.part)[tile * d.n_terms_total + gin<uint32_t>(d.cols)[c]] = s;
+        gout<double>(d.part)[row * d.n_terms_total + gin<uint32_t>(d.cols)[c]] = s;
     }
 }
 
-// out[s] = sum_j coeff[j] * (sum over tiles of part[s][tile][j]); one
+// out[s] = sum_j coeff[j] * (sum over rows of part[s][row][j]); one
 // workgroup per slot; term sums use a fixed tree, terms are added in order.
 __global__ __launch_bounds__(256) void expect_finalize_kernel(const double *__restrict__ part,
                                                               const double *__restrict__ coeff,
-                                                              uint32_t n_terms, uint32_t tiles,
+                                                              uint32_t n_terms, uint32_t rows,
                                                               double *__restrict__ out) {
     __shared__ double red[5];
     const uint32_t s = blockIdx.x;
-    const double *ps = part + (uint64_t)s * tiles * n_terms;
+    const double *ps = part + (uint64_t)s * rows * n_terms;
     double e = 0.0;
     for (uint32_t j = 0; j < n_terms; ++j) {
         double acc = 0.0;
-        for (uint32_t t = threadIdx.x; t < tiles; t += 256) acc += ps[(uint64_t)t * n_terms + j];
+        for (uint32_t t = threadIdx.x; t < rows; t += 256) acc += ps[(uint64_t)t * n_terms + j];
         acc = block_sum<256>(acc, red);
         if (threadIdx.x == 0) e = fma(coeff[j], acc, e);
         __syncthreads();
@@ -1237,7 +1234,7 @@ hipError_t launch_copy(hipStream_t st, void *dst, const void *src, uint64_t byte
 hipError_t launch_reduce(hipStream_t st, const ReduceDesc *d, uint32_t n_descs, uint32_t n,
                          uint32_t M) {
     const uint64_t tiles = 1ull << (n - M);
-    const uint64_t items = (uint64_t)n_descs * tiles;
+    const uint64_t items = (uint64_t)n_descs * (tiles / red_row_tiles((uint32_t)tiles));
     if (items == 0) return hipSuccess;
     if (items > 0x7FFFFFFFull) return hipErrorInvalidValue;
     switch (M) {
@@ -1261,11 +1258,11 @@ hipError_t launch_reduce_small(hipStream_t st, const ReduceDescSmall *d, uint32_
 }
 
 hipError_t launch_expect_finalize(hipStream_t st, const double *part, const double *coeff,
-                                  uint32_t n_terms, uint32_t tiles, uint32_t n_slots,
+                                  uint32_t n_terms, uint32_t rows, uint32_t n_slots,
                                   double *out) {
     if (n_slots == 0) return hipSuccess;
     hipLaunchKernelGGL(expect_finalize_kernel, dim3(n_slots), dim3(256), 0, st, part, coeff,
-                       n_terms, tiles, out);
+                       n_terms, rows, out);
     return hipGetLastError();
 }
 
