@@ -188,9 +188,58 @@ constexpr size_t kSplitAbove = 320;
 const char *kBlockOpen = "    { uint32_t qw_g; __asm__ volatile(\"s_mov_b32 %0, 1\" : \"=s\"(qw_g)); if (qw_g) {\n";
 const char *kBlockClose = "    } }\n";
 
+// Diagonal sets of a pass whose thread members carry no non-local bits:
+// their folded per-thread factor depends only on the thread and the op
+// records, so a workgroup computes it once per descriptor (dset_factors)
+// instead of on every tile, with the same sequence of operations. Maps the
+// set's op index to its slot in the factor array; `phase` holds each slot's
+// phase.
+struct Hoisted {
+    std::map<size_t, int> slot;
+    std::vector<size_t> op, phase;
+};
+
+Hoisted hoisted_sets(const HostPass &p) {
+    Hoisted h;
+    const auto &ops = p.dev_ops;
+    for (size_t k = 0; k < p.dev_phases.size(); ++k) {
+        for (size_t j = p.dev_phases[k].op_begin; j < p.dev_phases[k].op_end;) {
+            const DevOp &o = ops[j];
+            if (o.type != OP_DSET) {
+                ++j;
+                continue;
+            }
+            const size_t m0 = j + 1 + o.sb;
+            bool ok = o.b > 0;
+            for (size_t q = 0; q < o.b && ok; ++q) ok = ops[m0 + q].gmask == 0;
+            if (ok) {
+                h.slot[j] = (int)h.op.size();
+                h.op.push_back(j);
+                h.phase.push_back(k);
+            }
+            j = m0 + o.b + o.a;
+        }
+    }
+    return h;
+}
+
+// The fold of a diagonal set's thread members into its per-thread factor ft.
+std::string emit_fold(const std::vector<DevOp> &ops, size_t j, size_t ph, const char *ind) {
+    std::ostringstream g;
+    const DevOp &o = ops[j];
+    const size_t m0 = j + 1 + o.sb;
+    g << ind << "float2 ft = make_float2(1.0f, 0.0f); (void)ft;\n";
+    for (size_t q = 0; q < o.b; ++q) {
+        const DevOp &mm = ops[m0 + q];
+        g << ind << "ft = dset_fold_m(ft, " << pmask(mm, ph) << ", " << mc(m0 + q, 2) << ");\n";
+    }
+    return g.str();
+}
+
 // Straight-line code of ops [b, e) of a pass in phase ph (`split`: cut into
-// opaque blocks).
-std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t ph, bool split) {
+// opaque blocks; `hoist`: diagonal sets whose factor is read from ftc).
+std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t ph, bool split,
+                     const Hoisted *hoist = nullptr) {
     std::ostringstream g;
     int in_block = 0;
     for (size_t j = b; j < e;) {
@@ -260,11 +309,11 @@ std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t p
             break;
         case OP_DSET: {
             const size_t m0 = j + 1 + o.sb;
-            g << "    {\n        float2 ft = make_float2(1.0f, 0.0f); (void)ft;\n";
-            for (size_t q = 0; q < o.b; ++q) {
-                const DevOp &mm = ops[m0 + q];
-                g << "        ft = dset_fold_m(ft, " << pmask(mm, ph) << ", " << mc(m0 + q, 2) << ");\n";
-            }
+            g << "    {\n";
+            if (hoist && hoist->slot.count(j))
+                g << "        const float2 ft = ftc[" << hoist->slot.at(j) << "];\n";
+            else
+                g << emit_fold(ops, j, ph, "        ");
             // with a table or thread members, the first mixed member is
             // merged into the application (the interpreted kernels do the same)
             const size_t merged = (o.a && (o.sb || o.b)) ? 1 : 0;
@@ -416,6 +465,8 @@ std::string swz_addr(const ExSwz &x, const std::string &t) {
     return e.str();
 }
 
+bool same_reg(const DevPhase &a, const DevPhase &b) { return std::equal(a.reg, a.reg + 4, b.reg); }
+
 // Local offset of register k of a layout.
 uint32_t reg_off(const uint8_t *reg, int k) {
     uint32_t l = 0;
@@ -424,11 +475,13 @@ uint32_t reg_off(const uint8_t *reg, int k) {
     return l;
 }
 
-std::string emit_body(int m, const HostPass &p) {
+// `in_place_first`: the tile's first exchange may also skip the barrier
+// before its writes (see below).
+std::string emit_body(int m, const HostPass &p, const Hoisted &hs, bool in_place_first) {
     std::ostringstream g;
     g << "__device__ __forceinline__ void body(float2 (&v)[16], const DevOp *__restrict__ ops, "
-         "uint32_t tid, uint32_t lane, uint64_t base, char *lb) {\n";
-    g << "    (void)lane; (void)base; (void)lb;\n";
+         "uint32_t tid, uint32_t lane, uint64_t base, char *lb, const float2 *ftc) {\n";
+    g << "    (void)lane; (void)base; (void)lb; (void)ftc;\n";
     const auto &ph = p.dev_phases;
     // A phase's thread index (and the LDS addresses derived from it) is
     // computed when the phase starts, from a copy of tid that the compiler
@@ -450,7 +503,10 @@ std::string emit_body(int m, const HostPass &p) {
     // indices under the same map), which no other thread reads, so a full
     // exchange after the tile's first one needs only the barrier between
     // its writes and its reads, and early waves write while late ones still
-    // compute.
+    // compute. The tile's first exchange is in the same position when the
+    // pass starts and ends in one layout and nothing else uses the LDS
+    // between tiles (`in_place_first`): the previous tile's last reads were
+    // then at the same addresses, by the same threads.
     std::vector<const uint8_t *> lays;
     for (const DevPhase &f : ph) lays.push_back(f.reg);
     bool one_map = false;
@@ -474,7 +530,7 @@ std::string emit_body(int m, const HostPass &p) {
             g << "        const uint32_t s8 = " << thread_addr("tl" + std::to_string(k - 1)) << ";\n";
             if (local)
                 g << "        lds_wave_sync();\n";
-            else if (!one_map || k == 1)
+            else if (!one_map || (k == 1 && !(in_place_first && same_reg(ph[0], ph.back()))))
                 g << "        lds_barrier();\n";
             for (int r = 0; r < 16; ++r)
                 g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(roff(ph[k - 1], r)) << 3)
@@ -488,7 +544,18 @@ std::string emit_body(int m, const HostPass &p) {
         }
         g << "    // phase " << k << ": registers " << (int)ph[k].reg[0] << "," << (int)ph[k].reg[1] << ","
           << (int)ph[k].reg[2] << "," << (int)ph[k].reg[3] << "\n";
-        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k, p.dev_ops.size() > kSplitAbove);
+        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k, p.dev_ops.size() > kSplitAbove, &hs);
+    }
+    g << "}\n";
+    // the hoisted per-thread factors, from each set's phase layout
+    g << "__device__ __forceinline__ void dset_factors(float2 *ftc, const DevOp *__restrict__ ops, "
+         "uint32_t tid) {\n    (void)ftc; (void)ops; (void)tid;\n";
+    for (size_t i = 0; i < hs.op.size(); ++i) {
+        const size_t k = hs.phase[i];
+        g << "    {\n        uint32_t tid" << k << " = tid; __asm__ volatile(\"\" : \"+v\"(tid" << k << "));\n"
+          << "        const uint32_t tl" << k << " = thread_local_index(tid" << k << ", " << (int)ph[k].reg[0]
+          << "u, " << (int)ph[k].reg[1] << "u, " << (int)ph[k].reg[2] << "u, " << (int)ph[k].reg[3] << "u);\n"
+          << emit_fold(p.dev_ops, hs.op[i], k, "        ") << "        ftc[" << i << "] = ft;\n    }\n";
     }
     g << "}\n";
     (void)m;
@@ -579,7 +646,9 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
     emit_store(g, p.io_out, remap, m);
     // output base of the tile: the relabelled one, or the load base
     const char *obase = remap ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
-    g << emit_body(m, p);
+    const Hoisted hs = hoisted_sets(p);
+    const size_t K = hs.op.size();
+    g << emit_body(m, p, hs, use_lds && !epi);
     if (epi) {
         // fused expectation epilogue: the tile's terms, evaluated after the
         // store from the last phase's registers (staged through LDS)
@@ -610,7 +679,9 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "    float2 v[16];\n"
              "    load_in(v, ldu(&d->src), base | io_in_wave(wave), io_in_lane(lane));\n";
         if (p.scale_in) g << kScaleIn;
-        g << "    body(v, ldu(&d->ops), tid, lane, base, nullptr);\n"
+        g << "    float2 ftc[" << std::max<size_t>(1, K) << "];\n";
+        if (K) g << "    dset_factors(ftc, ldu(&d->ops), tid);\n";
+        g << "    body(v, ldu(&d->ops), tid, lane, base, nullptr, ftc);\n"
              "    store_out(v, ldu(&d->dst), ((uint64_t)" << obase << " ^ io_out_wxor(wave)) | io_out_wave(wave), io_out_lane(lane));\n"
              "}\n";
     } else {
@@ -631,12 +702,39 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "    const uint32_t last = (first + per < items) ? first + per : items;\n"
              "    uint32_t item = first + j;\n"
              "    if (item >= last) return;\n"
+             "    // this workgroup's items are first + j + wpx k (k < K); descriptor-\n"
+             "    // fastest, their descriptor repeats with period P in k, and they\n"
+             "    // run as the P sequences k = r, r + P, r + 2 P, ... so that one\n"
+             "    // descriptor's items run back to back\n"
+             "    const uint32_t K = (last - item + wpx - 1u) / wpx;\n"
+             "    uint32_t P = 1u;\n"
+             "    if (!tmaj) {\n"
+             "        uint32_t a = wpx, b = n_descs;\n"
+             "        while (b) {\n"
+             "            const uint32_t t = a % b;\n"
+             "            a = b;\n"
+             "            b = t;\n"
+             "        }\n"
+             "        P = n_descs / a;\n"
+             "    }\n"
+             "    uint32_t rr = 0u, kk = 0u;\n"
+             "    auto advance = [&](uint32_t &r_, uint32_t &k_) {\n"
+             "        k_ += P;\n"
+             "        if (k_ >= K) {\n"
+             "            r_ += 1u;\n"
+             "            k_ = r_;\n"
+             "        }\n"
+             "        return r_ < P && k_ < K;\n"
+             "    };\n"
              "    const uint32_t tid = threadIdx.x;\n"
              "    const uint32_t lane = tid & 63u;\n"
              "    const uint32_t wave = uni(tid >> 6);\n"
              "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave), wx = io_out_wxor(wave);\n"
              "    const uint32_t li = io_in_lane(lane), lo = io_out_lane(lane);\n"
-             "    char *lb = reinterpret_cast<char *>(lds);\n";
+             "    char *lb = reinterpret_cast<char *>(lds);\n"
+             "    float2 ftc[" << std::max<size_t>(1, K) << "];   // per-thread factors of the hoisted diagonal sets\n"
+             "    uint32_t ft_desc = 0xFFFFFFFFu;   // descriptor they were computed for\n"
+             "    (void)ft_desc;\n";
         if (epi)
             g << "    uint32_t rk = 0;   // tile of the row\n"
                  "    float acc[ENT];\n"
@@ -664,21 +762,29 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
              "        }\n"
              "";
         if (epi)
-            g << "        uint32_t next = item, nk = rk + 1u;\n"
+            g << "        uint32_t next = item, nk = rk + 1u, nr = rr, nkk = kk;\n"
+                 "        bool has_next = true;\n"
                  "        if (nk == RT) {\n"
-                 "            next = item + wpx;\n"
                  "            nk = 0u;\n"
+                 "            has_next = advance(nr, nkk);\n"
+                 "            next = first + j + wpx * nkk;\n"
                  "        }\n";
         else
-            g << "        const uint32_t next = item + wpx;\n";
-        g << "        const bool has_next = next < last;\n"
-             "        if (has_next) {\n"
+            g << "        uint32_t nr = rr, nkk = kk;\n"
+                 "        const bool has_next = advance(nr, nkk);\n"
+                 "        const uint32_t next = first + j + wpx * nkk;\n";
+        g << "        if (has_next) {\n"
              "            const PassDesc *dn = descs + desc_of(next);\n"
              "            load_pre(nv, ldu(&dn->src), uni(ldu(ldu(&dn->tile_base) + "
           << (epi ? "tile_of(next) * RT + nk" : "tile_of(next)") << ")) | wi, li);\n"
              "        }\n";
         if (p.scale_in) g << kScaleIn;
-        g << "        body(v, ldu(&d->ops), tid, lane, base, lb);\n";
+        if (K)
+            g << "        if (p != ft_desc) {\n"
+                 "            dset_factors(ftc, ldu(&d->ops), tid);\n"
+                 "            ft_desc = p;\n"
+                 "        }\n";
+        g << "        body(v, ldu(&d->ops), tid, lane, base, lb, ftc);\n";
         if (p.norm_out)
             g << "        {\n"
                  "            double s = 0.0;\n"
@@ -705,7 +811,9 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
                  "            }\n"
                  "        }\n";
         g << "        if (!has_next) break;\n"
-             "        item = next;\n";
+             "        item = next;\n"
+             "        rr = nr;\n"
+             "        kk = nkk;\n";
         if (epi) g << "        rk = nk;\n";
         g << "    }\n"
              "}\n";
