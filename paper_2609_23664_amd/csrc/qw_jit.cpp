@@ -236,14 +236,62 @@ std::string emit_fold(const std::vector<DevOp> &ops, size_t j, size_t ph, const 
     return g.str();
 }
 
+// CNOTs of a phase with a register target and a thread or non-local
+// control that every later op of the phase commutes with. Each is a
+// conditional swap of the register pairs of its target slot (4 selects per
+// pair); the exchange after the phase applies it instead as a per-thread
+// flip of the write addresses (one select for the exchange): writing v[r]
+// where register r ^ e_S would go is the swap. An op commutes with it if it
+// is a CNOT with a register target whose control is not the slot, a one-bit
+// op on another register slot, a diagonal on a thread or non-local bit, or a
+// CZ off the slot.
+// With `before`, the CNOTs that every earlier op of the phase commutes
+// with: the exchange into the phase applies them to its read addresses.
+std::vector<size_t> folded_cx(const std::vector<DevOp> &ops, size_t b, size_t e, bool before,
+                              const std::vector<size_t> &taken = {}) {
+    std::vector<size_t> top, out;
+    for (size_t j = b; j < e;) {
+        top.push_back(j);
+        j = ops[j].type == OP_DSET ? j + 1 + ops[j].sb + ops[j].b + ops[j].a : j + 1;
+    }
+    for (size_t i = 0; i < top.size(); ++i) {
+        const DevOp &o = ops[top[i]];
+        if (o.type != OP_CX || o.la != LOC_REG || o.lb == LOC_REG) continue;
+        if (std::find(taken.begin(), taken.end(), top[i]) != taken.end()) continue;
+        const int S = o.sa;
+        bool ok = true;
+        const size_t i_lo = before ? 0 : i + 1, i_hi = before ? i : top.size();
+        for (size_t i2 = i_lo; i2 < i_hi && ok; ++i2) {
+            const DevOp &q = ops[top[i2]];
+            if (before && std::find(out.begin(), out.end(), top[i2]) != out.end()) continue;
+            const bool a_on = q.la == LOC_REG && q.sa == S;
+            const bool b_on = q.lb == LOC_REG && q.sb == S;
+            switch (q.type) {
+            case OP_CX: ok = q.la == LOC_REG && !b_on; break;
+            case OP_URT: case OP_UR: case OP_U: case OP_PERM: case OP_URD: ok = q.la == LOC_REG && !a_on; break;
+            case OP_DIAG: ok = !a_on && q.la != LOC_LANE; break;
+            case OP_CZ: ok = !a_on && !b_on && q.la != LOC_LANE && q.lb != LOC_LANE; break;
+            default: ok = false; break;
+            }
+        }
+        if (ok) out.push_back(top[i]);
+    }
+    return out;
+}
+
 // Straight-line code of ops [b, e) of a pass in phase ph (`split`: cut into
-// opaque blocks; `hoist`: diagonal sets whose factor is read from ftc).
+// opaque blocks; `hoist`: diagonal sets whose factor is read from ftc;
+// `skip`: CNOTs the next exchange applies).
 std::string emit_ops(const std::vector<DevOp> &ops, size_t b, size_t e, size_t ph, bool split,
-                     const Hoisted *hoist = nullptr) {
+                     const Hoisted *hoist = nullptr, const std::vector<size_t> *skip = nullptr) {
     std::ostringstream g;
     int in_block = 0;
     for (size_t j = b; j < e;) {
         const DevOp &o = ops[j];
+        if (skip && std::find(skip->begin(), skip->end(), j) != skip->end()) {
+            ++j;
+            continue;
+        }
         if (split && in_block == kOpsPerBlock) {
             g << kBlockClose;
             in_block = 0;
@@ -517,6 +565,14 @@ std::string emit_body(int m, const HostPass &p, const Hoisted &hs, bool in_place
             if ((r >> s2) & 1) l |= 1u << f.reg[s2];
         return l;
     };
+    // CNOTs applied by the exchange into their phase (in) or out of it (out)
+    std::vector<std::vector<size_t>> fold_in(ph.size()), fold(ph.size()), skip(ph.size());
+    for (size_t k = 0; k < ph.size(); ++k) {
+        if (k > 0) fold_in[k] = folded_cx(p.dev_ops, ph[k].op_begin, ph[k].op_end, true);
+        if (k + 1 < ph.size()) fold[k] = folded_cx(p.dev_ops, ph[k].op_begin, ph[k].op_end, false, fold_in[k]);
+        skip[k] = fold_in[k];
+        skip[k].insert(skip[k].end(), fold[k].begin(), fold[k].end());
+    }
     for (size_t k = 0; k < ph.size(); ++k) {
         if (k > 0) g << tl_def(k);
         if (k > 0) {
@@ -527,7 +583,13 @@ std::string emit_body(int m, const HostPass &p, const Hoisted &hs, bool in_place
             const ExSwz x = one_map ? xall : choose_swizzle(m, ph[k - 1], ph[k]);
             auto thread_addr = [&](const std::string &t) { return swz_addr(x, t); };
             g << "    {   // exchange " << k - 1 << " -> " << k << (local ? " (within waves)" : "") << "\n";
-            g << "        const uint32_t s8 = " << thread_addr("tl" + std::to_string(k - 1)) << ";\n";
+            g << "        const uint32_t s8 = " << thread_addr("tl" + std::to_string(k - 1));
+            for (size_t j : fold[k - 1]) {
+                const DevOp &o = p.dev_ops[j];
+                g << " ^ ((0u - (uint32_t)" << bitval(o.lb, o.b, k - 1) << ") & "
+                  << (x.apply(1u << ph[k - 1].reg[o.sa]) << 3) << "u)";
+            }
+            g << ";\n";
             if (local)
                 g << "        lds_wave_sync();\n";
             else if (!one_map || (k == 1 && !(in_place_first && same_reg(ph[0], ph.back()))))
@@ -536,7 +598,13 @@ std::string emit_body(int m, const HostPass &p, const Hoisted &hs, bool in_place
                 g << "        *reinterpret_cast<float2 *>(lb + (s8 ^ " << (x.apply(roff(ph[k - 1], r)) << 3)
                   << "u)) = v[" << r << "];\n";
             g << (local ? "        lds_wave_sync();\n" : "        lds_barrier();\n");
-            g << "        const uint32_t t8 = " << thread_addr("tl" + std::to_string(k)) << ";\n";
+            g << "        const uint32_t t8 = " << thread_addr("tl" + std::to_string(k));
+            for (size_t j : fold_in[k]) {
+                const DevOp &o = p.dev_ops[j];
+                g << " ^ ((0u - (uint32_t)" << bitval(o.lb, o.b, k) << ") & "
+                  << (x.apply(1u << ph[k].reg[o.sa]) << 3) << "u)";
+            }
+            g << ";\n";
             for (int r = 0; r < 16; ++r)
                 g << "        v[" << r << "] = *reinterpret_cast<const float2 *>(lb + (t8 ^ "
                   << (x.apply(roff(ph[k], r)) << 3) << "u));\n";
@@ -544,7 +612,8 @@ std::string emit_body(int m, const HostPass &p, const Hoisted &hs, bool in_place
         }
         g << "    // phase " << k << ": registers " << (int)ph[k].reg[0] << "," << (int)ph[k].reg[1] << ","
           << (int)ph[k].reg[2] << "," << (int)ph[k].reg[3] << "\n";
-        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k, p.dev_ops.size() > kSplitAbove, &hs);
+        g << emit_ops(p.dev_ops, ph[k].op_begin, ph[k].op_end, k, p.dev_ops.size() > kSplitAbove, &hs,
+                      &skip[k]);
     }
     g << "}\n";
     // the hoisted per-thread factors, from each set's phase layout
