@@ -34,6 +34,7 @@ struct ProfRec {
     int kind;
     double bytes;
     hipEvent_t e0, e1;
+    uint32_t launches;  // back-to-back launches the two events bracket
 };
 
 struct PlanEntry {
@@ -298,13 +299,18 @@ hipEvent_t get_event(qw_ctx *ctx) {
     return e;
 }
 
+// Timing of launches with HIP events (QW_OPT_PROFILE): one pair of events
+// around `launches` kernels of one kind that run back to back on the stream
+// (an event pair per launch would put a timestamp between every two
+// kernels of a batch).
 struct ProfScope {
     qw_ctx *ctx;
     int kind;
     double bytes;
+    uint32_t launches;
     hipEvent_t e0 = nullptr;
-    ProfScope(qw_ctx *c, int k, double b) : ctx(c), kind(k), bytes(b) {
-        if (!ctx->profile || ctx->rec) return;
+    ProfScope(qw_ctx *c, int k, double b, uint32_t n_launch = 1) : ctx(c), kind(k), bytes(b), launches(n_launch) {
+        if (!ctx->profile || ctx->rec || launches == 0) return;
         e0 = get_event(ctx);
         if (e0) hipEventRecord(e0, ctx->stream);
     }
@@ -313,7 +319,7 @@ struct ProfScope {
         hipEvent_t e1 = get_event(ctx);
         if (!e1) return;
         hipEventRecord(e1, ctx->stream);
-        ctx->prof.push_back({kind, bytes, e0, e1});
+        ctx->prof.push_back({kind, bytes, e0, e1, launches});
     }
 };
 
@@ -815,11 +821,20 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     }
     rc = upload(ctx, blob);
     if (rc) return rc;
+    // one event pair around all pass launches of the call when they run back
+    // to back (no norm finalisation between them), else one per launch
+    uint32_t n_launch = 0;
+    double all_bytes = 0.0;
+    for (size_t k = 0; k < steps; ++k) {
+        n_launch += use_jit ? (uint32_t)groups[k].size() : 1u;
+        all_bytes += (double)step_cnt[k] * 2.0 * (double)state_bytes;
+    }
+    ProfScope ps_all(ctx, 0, all_bytes, any_norm ? 0u : n_launch);
     for (size_t k = 0; k < steps; ++k) {
         const PassDesc *dd = reinterpret_cast<const PassDesc *>(dbase + step_off[k]);
         if (use_jit) {
             for (const Group &g : groups[k]) {
-                ProfScope ps(ctx, 0, (double)g.count * 2.0 * (double)state_bytes);
+                ProfScope ps(ctx, 0, (double)g.count * 2.0 * (double)state_bytes, any_norm ? 1u : 0u);
                 // item order (QW_OPT_TILE_ORDER); descriptor-major whenever
                 // every task of the group reads one source
                 bool tile_major = false;
@@ -838,7 +853,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 if (er != hipSuccess) return hip_fail(ctx, er, "pass launch");
             }
         } else {
-            ProfScope ps(ctx, 0, (double)step_cnt[k] * 2.0 * (double)state_bytes);
+            ProfScope ps(ctx, 0, (double)step_cnt[k] * 2.0 * (double)state_bytes, any_norm ? 1u : 0u);
             hipError_t er = launch_pass(ctx->stream, dd, (uint32_t)step_cnt[k], n, (uint32_t)m,
                                         ctx->xcd_remap ? 1 : 0, step_lds[k] != 0);
             if (er != hipSuccess) return hip_fail(ctx, er, "pass launch");
@@ -1087,8 +1102,8 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
     if (rc) return rc;
     if (use_jit) {
         const ReduceDesc *dd = reinterpret_cast<const ReduceDesc *>(dbase + desc_off);
+        ProfScope ps(ctx, 1, (double)ns * groups.size() * (double)(8ull << n), (uint32_t)groups.size());
         for (size_t g = 0; g < groups.size(); ++g) {
-            ProfScope ps(ctx, 1, (double)ns * (double)(8ull << n));
             hipError_t er = jit_launch_reduce(ctx->stream, *rk[g], dd + g * ns, ns, tiles, ctx->n_cu,
                                               ctx->tile_order == 2);
             if (er != hipSuccess) return hip_fail(ctx, er, "generated reduce launch");
@@ -1510,7 +1525,7 @@ int qw_ctx_kernel_stats(qw_ctx *ctx, int kernel, uint64_t *launches, double *tot
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
             KStats &s = ctx->stats[r.kind];
-            s.launches += 1;
+            s.launches += r.launches;
             s.ms += ms;
             s.bytes += r.bytes;
         }
