@@ -669,14 +669,16 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         for (auto &e : tb_off) {
             uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
             const uint64_t nl = full & ~e.first;
-            for (uint32_t ti = 0; ti < tiles; ++ti) tb[ti] = (uint32_t)pdep64(ti, nl);
+            uint64_t g = 0;
+            for (uint32_t ti = 0; ti < tiles; ++ti, g = next_in_mask(g, nl)) tb[ti] = (uint32_t)g;
         }
         for (auto &e : tbo_off) {
             uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
             const uint64_t nl = full & ~e.first->local_mask;
             const std::vector<uint64_t> &img = e.first->out_img;
-            for (uint32_t ti = 0; ti < tiles; ++ti) {
-                uint64_t g = pdep64(ti, nl), o = 0;
+            uint64_t g = 0;
+            for (uint32_t ti = 0; ti < tiles; ++ti, g = next_in_mask(g, nl)) {
+                uint64_t o = 0;
                 for (uint64_t r = g; r; r &= r - 1) o ^= img[__builtin_ctzll(r)];
                 tb[ti] = (uint32_t)o;
             }
@@ -1064,7 +1066,8 @@ int expect_slots(qw_ctx *ctx, uint32_t n, const std::vector<const void *> &slots
         for (size_t g = 0; g < groups.size() && use_jit; ++g) {
             uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + tb_off[g]);
             const uint64_t nl = full & ~groups[g].local_mask;
-            for (uint32_t ti = 0; ti < tiles; ++ti) tb[ti] = (uint32_t)pdep64(ti, nl);
+            uint64_t gb = 0;
+            for (uint32_t ti = 0; ti < tiles; ++ti, gb = next_in_mask(gb, nl)) tb[ti] = (uint32_t)gb;
         }
         for (uint32_t s = 0; s < ns; ++s) {
             for (size_t g = 0; g < groups.size(); ++g) {

@@ -141,4 +141,9 @@ inline uint64_t pext64(uint64_t v, uint64_t mask) {
 }
 inline int popc64(uint64_t v) { return __builtin_popcountll(v); }
 
+// The non-local bits of `nonlocal` in counting order: the k-th value is
+// pdep64(k, nonlocal) (a tile's origin), and each next one comes from
+// adding one through the other bits, ((v | ~nonlocal) + 1) & nonlocal.
+inline uint64_t next_in_mask(uint64_t v, uint64_t nonlocal) { return ((v | ~nonlocal) + 1) & nonlocal; }
+
 }  // namespace qw
