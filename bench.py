@@ -35,6 +35,10 @@ def _parse():
                     help="QW_OPT_STREAM_LOADS: non-temporal state loads in generated passes "
                          "(except snapshot-reading first passes); default: 0 for the VQE line "
                          "(measured 1 %% faster), 1 for the gate sweep (measured 9 %% faster)")
+    ap.add_argument("--layout", type=int, default=1, choices=[0, 1, 2],
+                    help="QW_OPT_LAYOUT: permuted index layouts between the passes of a call; 0 "
+                         "never, 1 when the call's states exceed 128 MiB (default), 2 always "
+                         "(bitwise the same results)")
     ap.add_argument("--no-tune", action="store_true",
                     help="trie workload: skip the timing autotuner (default options)")
     ap.add_argument("--cpu-tasks", type=int, default=4,
@@ -132,6 +136,7 @@ def main():
     ctx.set_option(B.QW_OPT_TILE_BITS, args.tile_bits)
     ctx.set_option(B.QW_OPT_TILE_ORDER, args.tile_order)
     ctx.set_option(B.QW_OPT_STREAM_LOADS, 0 if args.stream_loads is None else args.stream_loads)
+    ctx.set_option(B.QW_OPT_LAYOUT, args.layout)
 
     # gate lists marshalled once (host preparation, outside the timed steps;
     # the library's plan cache makes later steps skip planning, which the
@@ -206,7 +211,8 @@ def main():
                    "suffix_layers": 2, "terms": len(terms), "parallelism": "single GPU"},
         "jit_setup_s": round(jit_setup_s, 3),
         "options": {"tile_bits": args.tile_bits, "tile_order": args.tile_order,
-                    "stream_loads": 0 if args.stream_loads is None else args.stream_loads},
+                    "stream_loads": 0 if args.stream_loads is None else args.stream_loads,
+                    "layout": args.layout},
     }
     # the same steps recorded as graphs (qw_graph_*): one launch per step plus
     # the 64 expectations' copy to the host

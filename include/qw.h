@@ -255,6 +255,21 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         graph is recorded. 0 = no cap, only the device's
  *                         own limit. [0] */
 #define QW_OPT_DEVICE_MEM_CAP 11
+/*   QW_OPT_LAYOUT         index layouts between the passes of one call:
+ *                         the planner may permute the qubits' index bits so
+ *                         that the tiles of a pass are longer contiguous
+ *                         runs of the state (the state before the first and
+ *                         after the last pass of a call is always in the
+ *                         standard layout; a pass that changes the layout
+ *                         runs out of place, like a relabelling pass, with
+ *                         the second buffers of QW_OPT_SECOND_BUFFER_CAP).
+ *                         0: standard layout throughout; 1: permuted
+ *                         layouts when the call's states exceed 128 MiB
+ *                         (smaller ones stay in the device's last-level
+ *                         cache when updated in place); 2: permuted layouts
+ *                         for every call. Results are bitwise the same in
+ *                         every mode. [1] */
+#define QW_OPT_LAYOUT 12
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.

@@ -50,6 +50,7 @@ QW_OPT_FUSED_EPILOGUE = 8
 QW_OPT_TILE_ORDER = 9
 QW_OPT_STREAM_LOADS = 10
 QW_OPT_DEVICE_MEM_CAP = 11
+QW_OPT_LAYOUT = 12
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",

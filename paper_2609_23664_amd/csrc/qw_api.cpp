@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <map>
+#include <set>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,8 @@ struct PlanEntry {
     uint32_t n = 0;
     int tile_bits = 0;
     bool relabel = true;
+    bool layout = true;
+    bool in_place = false;
     bool fused_epilogue = true;
     uint64_t pingpong_cap = 16ull << 30;
     uint64_t mem_cap = 0;        // QW_OPT_DEVICE_MEM_CAP (0: none)
@@ -112,6 +115,7 @@ struct qw_ctx {
     std::vector<uint8_t> outcomes;  // outcome record of the last measured call
     std::unordered_map<std::string, uint64_t> jit_heat;  // task-tiles run per pass structure
     bool relabel = true;
+    int layout = 1;              // QW_OPT_LAYOUT
     int tile_order = 1;          // QW_OPT_TILE_ORDER
     bool stream_loads = true;    // QW_OPT_STREAM_LOADS
     bool fused_epilogue = true;
@@ -425,8 +429,24 @@ uint64_t fnv64(const void *p, size_t len, uint64_t h = 0xcbf29ce484222325ull) {
     return h;
 }
 
+// Permuted index layouts between passes (QW_OPT_LAYOUT) make every pass
+// that changes the layout run out of place, which doubles the memory a call
+// sweeps. While a call's states fit the 256 MB last-level cache of the
+// device (the MALL) in place, that costs more than the longer runs gain: a
+// 24-qubit prefix state updated in place stays resident there for the 64
+// suffix passes that then read it as their snapshot (measured: those passes
+// took 3.87 instead of 4.20 ms when the prefix ran in place). Layouts are
+// used when the states of the call exceed half of that cache (mode 1), or
+// always (mode 2).
+constexpr uint64_t kLayoutMinBytes = 128ull << 20;
+bool layouts_pay(const qw_ctx *ctx, uint32_t n, uint64_t n_states) {
+    return ctx->layout == 2 || (ctx->layout == 1 && n_states * (8ull << n) > kLayoutMinBytes);
+}
+
+// `in_place`: the plan's first pass loads its own destination (no snapshot
+// or other source state). `layout`: permuted layouts allowed (layouts_pay).
 std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_gates,
-                     std::shared_ptr<const Plan> *out, bool allow_dyn = false) {
+                     std::shared_ptr<const Plan> *out, bool in_place, bool layout, bool allow_dyn = false) {
     // the internal run-time operator of measured segments is never taken
     // from a caller's gate list (not even through the plan cache)
     if (!allow_dyn)
@@ -437,9 +457,12 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
     h = fnv64(&n, sizeof n, h);
     h = fnv64(&ctx->tile_bits, sizeof ctx->tile_bits, h);
     h = fnv64(&ctx->relabel, sizeof ctx->relabel, h);
+    h = fnv64(&layout, sizeof layout, h);
+    h = fnv64(&in_place, sizeof in_place, h);
     auto &bucket = ctx->plan_cache[h];
     for (const auto &c : bucket) {
         if (c.n == n && c.tile_bits == ctx->tile_bits && c.relabel == ctx->relabel &&
+            c.layout == layout && c.in_place == in_place &&
             c.gates.size() == bytes &&
             (bytes == 0 || std::memcmp(c.gates.data(), gates, bytes) == 0)) {
             *out = c.plan;
@@ -448,7 +471,7 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
     }
     auto p = std::make_shared<Plan>();
     std::string e = build_plan((int)n, gates, (size_t)n_gates, ctx->tile_bits, p.get(), ctx->relabel, true,
-                               allow_dyn);
+                               allow_dyn, layout, in_place);
     if (!e.empty()) return e;
     if (ctx->plan_cache_entries >= 4096) {
         ctx->plan_cache.clear();
@@ -458,6 +481,8 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
     pe.n = n;
     pe.tile_bits = ctx->tile_bits;
     pe.relabel = ctx->relabel;
+    pe.layout = layout;
+    pe.in_place = in_place;
     pe.gates.assign(reinterpret_cast<const char *>(gates), reinterpret_cast<const char *>(gates) + bytes);
     pe.plan = p;
     ctx->plan_cache[h].push_back(std::move(pe));
@@ -487,9 +512,11 @@ struct Exec {
     uint32_t epi_nt = 0;
 };
 
+// The plan has a pass that stores to other addresses than it loads (output
+// relabelling or a change of index layout): its task needs a second buffer.
 bool has_relabel(const Plan &p) {
     for (const HostPass &h : p.passes)
-        if (!h.out_img.empty()) return true;
+        if (h.moves()) return true;
     return false;
 }
 
@@ -519,20 +546,21 @@ int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
 }
 
 // Buffers of one task's passes: 0 = the task's destination, 1 = its second
-// buffer. A relabelling pass stores to other tiles than the ones it loads,
-// so it never runs in place; the assignment ends in the destination.
+// buffer. A pass with output relabelling or a change of index layout stores
+// to other addresses than it loads, so it never runs in place; the
+// assignment ends in the destination.
 // Returns the buffer pass 0 reads when the task has no external source, or
 // 2 if the destination must first be copied to the second buffer.
 int assign_buffers(const Plan &p, bool external_src, std::vector<int> *db) {
     const size_t P = p.passes.size();
     db->assign(P, 0);
     for (size_t k = P - 1; k >= 1; --k)
-        (*db)[k - 1] = p.passes[k].out_img.empty() ? (*db)[k] : 1 - (*db)[k];
-    if (external_src || p.passes[0].out_img.empty() || (*db)[0] == 1) return 0;
+        (*db)[k - 1] = p.passes[k].moves() ? 1 - (*db)[k] : (*db)[k];
+    if (external_src || !p.passes[0].moves() || (*db)[0] == 1) return 0;
     // pass 0 would relabel in place: make the first plain pass k >= 1 run
     // out of place (flips the buffers of passes 0..k-1)
     for (size_t k = 1; k < P; ++k)
-        if (p.passes[k].out_img.empty()) {
+        if (!p.passes[k].moves()) {
             for (size_t j = 0; j < k; ++j) (*db)[j] = 1 - (*db)[j];
             return 0;
         }
@@ -624,23 +652,27 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             io_off[t].push_back(L.take(2 * sizeof(IoRec)));
         }
     }
-    // per distinct local mask: table of the global index of each tile's origin
-    std::vector<std::pair<uint64_t, size_t>> tb_off;
-    auto tile_table = [&](uint64_t lmask) -> size_t {
+    // per distinct (local mask, load layout): the index of each tile's
+    // origin in the state the pass loads
+    std::vector<std::pair<const HostPass *, size_t>> tb_off;
+    auto tile_table = [&](const HostPass &p) -> size_t {
         for (auto &e : tb_off)
-            if (e.first == lmask) return e.second;
+            if (e.first->local_mask == p.local_mask && e.first->in_pos == p.in_pos) return e.second;
         size_t off = L.take((size_t)tiles * sizeof(uint32_t));
-        tb_off.push_back({lmask, off});
+        tb_off.push_back({&p, off});
         return off;
     };
     std::vector<std::vector<size_t>> tb_of(ex.size());
     for (size_t t = 0; t < ex.size(); ++t)
-        for (const HostPass &p : ex[t].planp->passes) tb_of[t].push_back(tile_table(p.local_mask));
-    // per distinct (local mask, relabelling): relabelled tile origins
+        for (const HostPass &p : ex[t].planp->passes) tb_of[t].push_back(tile_table(p));
+    // per distinct (local mask, relabelling, store layout): the index of
+    // each tile's origin in the state the pass stores
     std::vector<std::pair<const HostPass *, size_t>> tbo_off;
     auto out_table = [&](const HostPass &p) -> size_t {
         for (auto &e : tbo_off)
-            if (e.first->local_mask == p.local_mask && e.first->out_img == p.out_img) return e.second;
+            if (e.first->local_mask == p.local_mask && e.first->out_img == p.out_img &&
+                e.first->out_pos == p.out_pos)
+                return e.second;
         size_t off = L.take((size_t)tiles * sizeof(uint32_t));
         tbo_off.push_back({&p, off});
         return off;
@@ -648,7 +680,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     std::vector<std::vector<size_t>> tbo_of(ex.size());
     for (size_t t = 0; t < ex.size(); ++t)
         for (const HostPass &p : ex[t].planp->passes)
-            tbo_of[t].push_back(p.out_img.empty() ? (size_t)-1 : out_table(p));
+            tbo_of[t].push_back(p.moves() ? out_table(p) : (size_t)-1);
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
     uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
@@ -666,21 +698,27 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     }
     {
         const uint64_t full = (1ull << n) - 1;
+        // tile ti is the ti-th value of the non-local qubits in counting
+        // order, whatever the layouts (so results do not depend on them)
         for (auto &e : tb_off) {
             uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
-            const uint64_t nl = full & ~e.first;
+            const uint64_t nl = full & ~e.first->local_mask;
+            const std::vector<uint8_t> &pos = e.first->in_pos;
             uint64_t g = 0;
-            for (uint32_t ti = 0; ti < tiles; ++ti, g = next_in_mask(g, nl)) tb[ti] = (uint32_t)g;
+            for (uint32_t ti = 0; ti < tiles; ++ti, g = next_in_mask(g, nl))
+                tb[ti] = (uint32_t)to_layout(g, pos);
         }
         for (auto &e : tbo_off) {
             uint32_t *tb = reinterpret_cast<uint32_t *>(blob.data() + e.second);
             const uint64_t nl = full & ~e.first->local_mask;
             const std::vector<uint64_t> &img = e.first->out_img;
+            const std::vector<uint8_t> &pos = e.first->out_pos;
             uint64_t g = 0;
             for (uint32_t ti = 0; ti < tiles; ++ti, g = next_in_mask(g, nl)) {
-                uint64_t o = 0;
-                for (uint64_t r = g; r; r &= r - 1) o ^= img[__builtin_ctzll(r)];
-                tb[ti] = (uint32_t)o;
+                uint64_t o = img.empty() ? g : 0;
+                if (!img.empty())
+                    for (uint64_t r = g; r; r &= r - 1) o ^= img[__builtin_ctzll(r)];
+                tb[ti] = (uint32_t)to_layout(o, pos);
             }
         }
     }
@@ -782,7 +820,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 d.src = (k == 0 && e.src) ? e.src : e.dst;
                 d.dst = e.dst;
             }
-            if (!p.out_img.empty()) {
+            if (p.moves()) {
                 d.tile_base_out = reinterpret_cast<const uint32_t *>(dbase + tbo_of[t][k]);
                 d.flags |= PD_REMAP_OUT;
             }
@@ -845,7 +883,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                     bool shared_src = true;
                     for (uint32_t i = 1; i < g.count && shared_src; ++i)
                         shared_src = hd[g.first + i].src == hd[g.first].src;
-                    const bool relabel = (hd[g.first].flags & PD_REMAP_OUT) != 0;
+                    const bool relabel = !ex[order[k][g.first]].planp->passes[k].out_img.empty();
                     tile_major = !shared_src && (ctx->tile_order == 2 || (ctx->tile_order == 1 && relabel));
                 }
                 hipError_t er = g.k ? jit_launch(ctx->stream, *g.k, dd + g.first, g.count, tiles,
@@ -906,7 +944,8 @@ void plan_fused(qw_ctx *ctx, uint32_t n, const std::vector<Exec> &ex, const uint
             if (h.norm_out || h.scale_in) return;
         const HostPass &l = p.passes.back();
         if (!last) last = &l;
-        else if (l.local_mask != last->local_mask || l.out_cx != last->out_cx) return;
+        else if (l.local_mask != last->local_mask || l.out_cx != last->out_cx || l.in_pos != last->in_pos)
+            return;
     }
     const uint64_t tiles = 1ull << (n - m);
     if (ctx->jit == 1 && (uint64_t)ex.size() * tiles < kJitHotTiles) return;
@@ -940,8 +979,10 @@ void plan_fused_last(int n, int m, const HostPass &lp, const uint64_t *x, const 
     // the diagonal terms are evaluated in the layout the pass ends in
     fe->rplan = plan_reduce_group(n, m, g, xc.data(), zc.data(),
                                   last->dev_phases.empty() ? nullptr : last->dev_phases.back().reg);
-    for (TermDev &t : fe->rplan.terms)
+    for (TermDev &t : fe->rplan.terms) {
         if (neg[fe->rplan.cols[t.col]]) t.neg ^= 1;
+        t.zg = to_layout(t.zg, last->in_pos);   // read from the tile origin
+    }
     fe->fused = fused;
     fe->key = jit_epilogue_key(n, m, *last, fe->rplan);
     fe->active = true;
@@ -1293,9 +1334,10 @@ int run_measured(qw_ctx *ctx, uint32_t n, std::vector<MeasTask> &mt) {
             if (t.done) continue;
             next_segment(t, &segs[k]);
             Exec x;
-            std::string err_s = get_plan(ctx, n, segs[k].data(), segs[k].size(), &x.planp, true);
-            if (!err_s.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + err_s);
             x.src = first ? t.src : nullptr;
+            std::string err_s = get_plan(ctx, n, segs[k].data(), segs[k].size(), &x.planp, x.src == nullptr,
+                                         layouts_pay(ctx, n, mt.size()), true);
+            if (!err_s.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + err_s);
             x.dst = t.dst;
             ex.push_back(x);
             if (t.cluster.empty() && t.rest.empty()) t.done = true;
@@ -1493,6 +1535,10 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         ctx->jit = (int)value;
         return QW_OK;
     case QW_OPT_RELABEL: ctx->relabel = value != 0; return QW_OK;
+    case QW_OPT_LAYOUT:
+        if (value < 0 || value > 2) return fail(ctx, QW_E_INVALID_ARG, "layout mode must be 0, 1 or 2");
+        ctx->layout = (int)value;
+        return QW_OK;
     case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
     case QW_OPT_STREAM_LOADS: ctx->stream_loads = value != 0; return QW_OK;
     case QW_OPT_TILE_ORDER:
@@ -1638,7 +1684,7 @@ int qw_apply_prefix(qw_state *st, uint32_t slot, const qw_gate *gates, uint64_t 
         return rc;
     }
     std::vector<Exec> ex(1);
-    std::string e = get_plan(ctx, st->n, gates, n_gates, &ex[0].planp);
+    std::string e = get_plan(ctx, st->n, gates, n_gates, &ex[0].planp, true, layouts_pay(ctx, st->n, 1));
     if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
     ex[0].dst = slot_ptr(st, slot);
     if (ctx->rec) ctx->rec->calls.emplace_back();
@@ -1798,9 +1844,10 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
     }
     std::vector<Exec> ex(n_tasks);
     for (uint32_t k = 0; k < n_tasks; ++k) {
-        std::string e = get_plan(ctx, dst->n, tasks[k].gates, tasks[k].n_gates, &ex[k].planp);
-        if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
         ex[k].src = (src && src[k]) ? src[k]->data : nullptr;
+        std::string e = get_plan(ctx, dst->n, tasks[k].gates, tasks[k].n_gates, &ex[k].planp, ex[k].src == nullptr,
+                                 layouts_pay(ctx, dst->n, n_tasks));
+        if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
         ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);
     }
     // Fused expectation epilogue: terms that the last pass can evaluate on
@@ -2150,29 +2197,37 @@ int qw_jit_precompile(uint32_t n, const qw_gate *gates, uint64_t n_gates, uint32
             log[k] = 0;
         }
     };
-    Plan p;
-    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    // the plans from a separate source and in place, with and without
+    // permuted layouts (calls choose by where the first pass loads from and
+    // by the size of their states)
+    Plan pv[4];
+    std::string e;
+    for (int v = 0; v < 4 && e.empty(); ++v)
+        e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &pv[v], true, true, false, v >= 2, v & 1);
     if (!e.empty()) {
         put(e);
         return QW_E_INVALID_ARG;
     }
     put("");
-    if (p.m < kMinTileBits) return QW_OK;
+    if (pv[0].m < kMinTileBits) return QW_OK;
     std::vector<JitReq> reqs;
-    for (size_t k = 0; k < p.passes.size(); ++k) {
-        const HostPass &h = p.passes[k];
-        // both load policies (QW_OPT_STREAM_LOADS, snapshot-reading first passes)
-        for (int stream = 1; stream >= 0; --stream) {
-            JitReq r;
-            r.use_lds = h.norm_out || h.dev_phases.size() > 1;
-            r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (stream ? "S" : "T");
-            r.pass = &h;
-            r.n = (int)n;
-            r.m = p.m;
-            r.stream_loads = stream != 0;
-            reqs.push_back(std::move(r));
+    std::set<std::string> seen;
+    for (const Plan &p : pv)
+        for (size_t k = 0; k < p.passes.size(); ++k) {
+            const HostPass &h = p.passes[k];
+            // both load policies (QW_OPT_STREAM_LOADS, snapshot-reading first passes)
+            for (int stream = 1; stream >= 0; --stream) {
+                JitReq r;
+                r.use_lds = h.norm_out || h.dev_phases.size() > 1;
+                r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (stream ? "S" : "T");
+                if (!seen.insert(r.key).second) continue;
+                r.pass = &h;
+                r.n = (int)n;
+                r.m = p.m;
+                r.stream_loads = stream != 0;
+                reqs.push_back(std::move(r));
+            }
         }
-    }
     e = jit_precompile(reqs);
     if (!e.empty()) {
         put(e);
@@ -2238,12 +2293,18 @@ int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates,
         put("term arrays are NULL");
         return QW_E_INVALID_ARG;
     }
-    Plan p;
-    std::string e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &p);
+    // the plans from a snapshot and in place, with and without permuted
+    // layouts (calls choose by where the first pass loads from and by the
+    // size of their states)
+    Plan pv[4];
+    std::string e;
+    for (int v = 0; v < 4 && e.empty(); ++v)
+        e = build_plan((int)n, gates, (size_t)n_gates, (int)tile_bits, &pv[v], true, true, false, v >= 2, v & 1);
     if (!e.empty()) {
         put(e);
         return QW_E_INVALID_ARG;
     }
+    const Plan &p = pv[0];
     if (p.m < kMinTileBits) return QW_OK;
     const uint64_t full = (1ull << n) - 1;
     for (uint32_t j = 0; j < n_terms; ++j)
@@ -2251,29 +2312,36 @@ int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates,
             put("Pauli mask has bits >= n");
             return QW_E_INVALID_ARG;
         }
-    FusedEpi fe;
-    bool norm = false;
-    for (const HostPass &h : p.passes) norm |= h.norm_out || h.scale_in;
-    if (n_terms && !p.passes.empty() && !norm && (int)n > p.m)
-        plan_fused_last((int)n, p.m, p.passes.back(), x, z, n_terms, &fe);
+    FusedEpi fev[4];
     std::vector<JitReq> reqs;
-    for (size_t k = 0; k < p.passes.size(); ++k) {
-        const HostPass &h = p.passes[k];
-        const bool with_epi = fe.active && k + 1 == p.passes.size();
-        // both load policies (QW_OPT_STREAM_LOADS, snapshot-reading first passes)
-        for (int stream = 0; stream <= 1; ++stream) {
-            JitReq r;
-            r.use_lds = h.norm_out || h.dev_phases.size() > 1 || with_epi;
-            r.key = jit_pass_key((int)n, p.m, h, r.use_lds) + (with_epi ? fe.key : std::string()) +
-                    (stream ? "S" : "T");
-            r.pass = &h;
-            r.epi = with_epi ? &fe.rplan : nullptr;
-            r.n = (int)n;
-            r.m = p.m;
-            r.stream_loads = stream != 0;
-            reqs.push_back(std::move(r));
+    std::set<std::string> seen;
+    for (int v = 0; v < 4; ++v) {
+        const Plan &pp = pv[v];
+        FusedEpi &fe = fev[v];
+        bool norm = false;
+        for (const HostPass &h : pp.passes) norm |= h.norm_out || h.scale_in;
+        if (n_terms && !pp.passes.empty() && !norm && (int)n > pp.m)
+            plan_fused_last((int)n, pp.m, pp.passes.back(), x, z, n_terms, &fe);
+        for (size_t k = 0; k < pp.passes.size(); ++k) {
+            const HostPass &h = pp.passes[k];
+            const bool with_epi = fe.active && k + 1 == pp.passes.size();
+            // both load policies (QW_OPT_STREAM_LOADS, snapshot-reading first passes)
+            for (int stream = 0; stream <= 1; ++stream) {
+                JitReq r;
+                r.use_lds = h.norm_out || h.dev_phases.size() > 1 || with_epi;
+                r.key = jit_pass_key((int)n, pp.m, h, r.use_lds) + (with_epi ? fe.key : std::string()) +
+                        (stream ? "S" : "T");
+                if (!seen.insert(r.key).second) continue;
+                r.pass = &h;
+                r.epi = with_epi ? &fe.rplan : nullptr;
+                r.n = (int)n;
+                r.m = pp.m;
+                r.stream_loads = stream != 0;
+                reqs.push_back(std::move(r));
+            }
         }
     }
+    const FusedEpi &fe = fev[0];
     // the reducer groups of the remaining terms, built as expect_slots builds them
     std::vector<uint32_t> idx;
     std::vector<uint64_t> xs;
@@ -2476,7 +2544,7 @@ int qw_graph_update_gates(qw_graph *g, uint32_t call, uint32_t task, const qw_ga
         if (is_measure(gates[i].kind)) return fail(ctx, QW_E_INVALID_ARG, "measurement gates cannot be updated");
     GraphSeg &sg = g->calls[call][task];
     std::shared_ptr<const Plan> np;
-    std::string e = get_plan(ctx, sg.n, gates, n_gates, &np);
+    std::string e = get_plan(ctx, sg.n, gates, n_gates, &np, sg.plan->in_place, sg.plan->layout);
     if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, e);
     // the pass structure (kernel identity, record counts, phases, I/O and
     // relabelling) must be the recorded one; only op-record values change
@@ -2491,6 +2559,7 @@ int qw_graph_update_gates(qw_graph *g, uint32_t call, uint32_t task, const qw_ga
                std::memcmp(&pa.io_in, &pb.io_in, sizeof(IoRec)) == 0 &&
                std::memcmp(&pa.io_out, &pb.io_out, sizeof(IoRec)) == 0 &&
                pa.scale_in == pb.scale_in && pa.norm_out == pb.norm_out && pa.out_img == pb.out_img &&
+               pa.in_pos == pb.in_pos && pa.out_pos == pb.out_pos &&
                jit_pass_key((int)sg.n, a.m, pa, la) == jit_pass_key((int)sg.n, b.m, pb, lb);
     }
     if (!same)

@@ -33,6 +33,14 @@ struct HostPass {
     // out_img[q] = L(e_q) for every qubit q (empty: no relabelling).
     std::vector<std::pair<int, int>> out_cx;
     std::vector<uint64_t> out_img;
+    // Index layouts of the state the pass loads and of the one it stores:
+    // qubit q is index bit in_pos[q] / out_pos[q] (empty: bit q). A plan
+    // starts and ends in the standard layout; between two of its passes the
+    // qubits may be permuted so that more of a tile is one contiguous run.
+    // Device records name non-local qubits by their bit in the load layout.
+    std::vector<uint8_t> in_pos, out_pos;
+    // the pass stores to other addresses than the ones it loads
+    bool moves() const { return !out_img.empty() || in_pos != out_pos; }
     // filled by lower_pass():
     std::vector<DevOp> dev_ops;
     std::vector<DevPhase> dev_phases;
@@ -44,6 +52,8 @@ struct Plan {
     int m = 0;                  // tile bits
     std::vector<HostPass> passes;
     size_t n_gates = 0;
+    bool in_place = false;      // planned for a first pass that loads its own destination
+    bool layout = false;        // planned with permuted layouts allowed
 };
 
 // Validates and plans `gates` on n qubits with at most tile_bits local bits
@@ -51,9 +61,12 @@ struct Plan {
 // non-local targets applied as store-address maps). Without `lower` the
 // passes keep their host ops only (no device records or phases: enough to
 // count passes). Returns "" on success, otherwise an error message.
+// `layout` allows permuted index layouts between passes (HostPass::in_pos);
+// `in_place`: the first pass will load the state from its own destination
+// (no separate source), which the layouts take into account.
 std::string build_plan(int n, const void *gates /* qw_gate* */, size_t n_gates,
                        int tile_bits, Plan *out, bool relabel = true, bool lower = true,
-                       bool allow_dyn = false);
+                       bool allow_dyn = false, bool layout = true, bool in_place = false);
 
 // Internal gate kind (never accepted from callers): a real 2x2 operator on
 // q0 whose 4 FP32 entries the device writes at run time at the address held
@@ -140,6 +153,13 @@ inline uint64_t pext64(uint64_t v, uint64_t mask) {
     return r;
 }
 inline int popc64(uint64_t v) { return __builtin_popcountll(v); }
+// Bits of a standard-layout index v at their places in layout `pos`.
+inline uint64_t to_layout(uint64_t v, const std::vector<uint8_t> &pos) {
+    if (pos.empty()) return v;
+    uint64_t r = 0;
+    for (; v; v &= v - 1) r |= 1ull << pos[__builtin_ctzll(v)];
+    return r;
+}
 
 // The non-local bits of `nonlocal` in counting order: the k-th value is
 // pdep64(k, nonlocal) (a tile's origin), and each next one comes from

@@ -650,8 +650,14 @@ std::string jit_pass_key(int n, int m, const HostPass &p, bool use_lds) {
     put((uint64_t)n, 1);
     put((uint64_t)m, 1);
     put(use_lds ? 1 : 0, 1);
-    put((p.scale_in ? 1 : 0) | (p.norm_out ? 2 : 0) | (p.out_img.empty() ? 0 : 4), 1);
+    put((p.scale_in ? 1 : 0) | (p.norm_out ? 2 : 0) | (p.moves() ? 4 : 0), 1);
     put(p.local_mask, 8);
+    // index layouts of the load and the store (their bit positions are
+    // compiled into the address arithmetic)
+    put(p.in_pos.size(), 1);
+    for (uint8_t b : p.in_pos) put(b, 1);
+    put(p.out_pos.size(), 1);
+    for (uint8_t b : p.out_pos) put(b, 1);
     if (!p.out_img.empty()) {
         // the local-bit part of the relabelling is compiled in; its tile
         // part comes from the per-tile output bases
@@ -705,7 +711,7 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
     g << "constexpr int M = " << m << ", T = " << T << ", WG = " << WG << ", PARTS = T / WG;\n";
     emit_io_helpers(g, "io_in", p.io_in, m);
     emit_io_helpers(g, "io_out", p.io_out, m);
-    const bool remap = !p.out_img.empty();
+    const bool remap = p.moves();
     // persistent form: registers [0, PF) of the next tile are loaded while
     // the current one is worked on, the rest when it starts
     const int PF = use_lds ? prefetch : 0;

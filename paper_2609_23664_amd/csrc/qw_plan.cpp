@@ -846,13 +846,14 @@ void plan_phases(int m, HostPass &p, std::vector<DevOp> &lops_in, const std::vec
     lops_in.swap(out);
 }
 
-// Host form of the uniform address arithmetic of an I/O phase.
-IoRec make_iorec(int m, uint64_t lmask, const DevPhase &ph) {
+// Host form of the uniform address arithmetic of an I/O phase, for the
+// index layout `pos` of the state it loads or stores.
+IoRec make_iorec(int m, uint64_t lmask, const DevPhase &ph, const std::vector<uint8_t> &pos) {
     IoRec r{};
     r.kind = ph.io;
     std::vector<int> gpos;
     for (int q = 0; q < 64; ++q)
-        if ((lmask >> q) & 1ull) gpos.push_back(q);
+        if ((lmask >> q) & 1ull) gpos.push_back(pos.empty() ? q : pos[q]);
     r.g4 = (uint8_t)gpos[4];
     r.g5 = (uint8_t)gpos[5];
     r.g6 = (uint8_t)gpos[6];
@@ -893,7 +894,7 @@ bool fill_relabel(int m, const HostPass &p, const DevPhase &ph, IoRec *r) {
         if ((p.local_mask >> q) & 1ull) gpos.push_back(q);
     auto dpart = [&](int b) -> uint32_t {
         const int q = gpos[b];
-        return (uint32_t)(p.out_img[q] ^ (1ull << q));
+        return (uint32_t)to_layout(p.out_img[q] ^ (1ull << q), p.out_pos);
     };
     uint32_t R = 0;
     for (int s = 0; s < 4; ++s) R |= 1u << ph.reg[s];
@@ -945,13 +946,14 @@ bool lower_pass(int n, int m, HostPass &p) {
                 *bit = (uint8_t)local_index(p.local_mask, g);
                 *loc = LOC_THREAD;  // resolved per phase
             } else {
-                *bit = (uint8_t)g;
+                // read from the tile origin, an index in the load layout
+                *bit = (uint8_t)(p.in_pos.empty() ? g : p.in_pos[g]);
                 *loc = LOC_GLOBAL;
             }
         };
         if (h.type == OP_PDIAG) {
             o.tmask = (uint32_t)pext64(h.mask & p.local_mask, p.local_mask);
-            o.gmask = (uint32_t)(h.mask & ~p.local_mask);
+            o.gmask = (uint32_t)to_layout(h.mask & ~p.local_mask, p.in_pos);
             o.la = o.lb = LOC_GLOBAL;
             return o;
         }
@@ -987,8 +989,8 @@ bool lower_pass(int n, int m, HostPass &p) {
     }
     if (m >= kMinTileBits) {
         plan_phases(m, p, lops, unit_len, lmd);
-        p.io_in = make_iorec(m, p.local_mask, p.dev_phases.front());
-        p.io_out = make_iorec(m, p.local_mask, p.dev_phases.back());
+        p.io_in = make_iorec(m, p.local_mask, p.dev_phases.front(), p.in_pos);
+        p.io_out = make_iorec(m, p.local_mask, p.dev_phases.back(), p.out_pos);
         if (!p.out_img.empty() && !fill_relabel(m, p, p.dev_phases.back(), &p.io_out))
             return false;
     } else {
@@ -1003,10 +1005,69 @@ bool lower_pass(int n, int m, HostPass &p) {
     return true;
 }
 
+// Index layouts between the passes of a plan. A tile of a pass is one
+// contiguous run of 2^m amplitudes when its local qubits are the lowest m
+// index bits; two consecutive passes with different local sets cannot both
+// have that, so each boundary favours one side: its local qubits in
+// ascending order, then the other side's remaining local qubits, then the
+// rest. The other side's run is then 2^r amplitudes, r the number of lowest
+// index bits that it holds locally. The boundary takes the side that leaves
+// the longer run to the other; at equal runs the pass with fewer ops (the
+// one more bound by memory) gets the contiguous tiles. Qubits 0..3 stay at
+// bits 0..3 (the lane part of every access), so a boundary is permuted only
+// when both passes hold them, and only when that lengthens the runs.
+// A pass that changes the layout stores to another buffer than it loads;
+// an in-place plan whose first pass would then have to store into the
+// buffer it loads keeps the standard layout at its first boundary.
+void assign_layouts(int n, int m, Plan &plan, bool in_place) {
+    auto favour = [&](uint64_t first, uint64_t second) {
+        std::vector<uint8_t> pos(n);
+        int next = 0;
+        for (int q = 0; q < n; ++q)
+            if ((first >> q) & 1ull) pos[q] = (uint8_t)next++;
+        for (int q = 0; q < n; ++q)
+            if (!((first >> q) & 1ull) && ((second >> q) & 1ull)) pos[q] = (uint8_t)next++;
+        for (int q = 0; q < n; ++q)
+            if (!(((first | second) >> q) & 1ull)) pos[q] = (uint8_t)next++;
+        bool ident = true;
+        for (int q = 0; q < n && ident; ++q) ident = pos[q] == q;
+        if (ident) pos.clear();
+        return pos;
+    };
+    // run length in index bits, counted up to 2 KiB runs (longer ones
+    // stream no faster)
+    auto run_bits = [&](uint64_t lmask, const std::vector<uint8_t> &pos) {
+        return std::min(__builtin_ctzll(~to_layout(lmask, pos)), 8);
+    };
+    const size_t P = plan.passes.size();
+    for (size_t k = 0; k + 1 < P; ++k) {
+        HostPass &a = plan.passes[k], &b = plan.passes[k + 1];
+        if ((a.local_mask & 15ull) != 15ull || (b.local_mask & 15ull) != 15ull) continue;
+        if (a.local_mask == b.local_mask) continue;
+        std::vector<uint8_t> w = favour(a.local_mask, b.local_mask);
+        std::vector<uint8_t> r = favour(b.local_mask, a.local_mask);
+        const int rw = run_bits(b.local_mask, w), rr = run_bits(a.local_mask, r);
+        const bool reader = rr != rw ? rr > rw : a.ops.size() > b.ops.size();
+        std::vector<uint8_t> &pos = reader ? r : w;
+        const int std_runs = run_bits(a.local_mask, {}) + run_bits(b.local_mask, {});
+        if (pos.empty() || run_bits(a.local_mask, pos) + run_bits(b.local_mask, pos) <= std_runs) continue;
+        a.out_pos = pos;
+        b.in_pos = pos;
+    }
+    if (in_place && P >= 2 && plan.passes[0].moves()) {
+        size_t later = 0;
+        for (size_t k = 1; k < P; ++k) later += plan.passes[k].moves();
+        if (later % 2 == 0) {
+            plan.passes[0].out_pos.clear();
+            plan.passes[1].in_pos.clear();
+        }
+    }
+}
+
 }  // namespace
 
 std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits, Plan *out,
-                       bool relabel, bool lower, bool allow_dyn) {
+                       bool relabel, bool lower, bool allow_dyn, bool layout, bool in_place) {
     const qw_gate *gates = static_cast<const qw_gate *>(gates_v);
     if (n < 1 || n > kMaxQubits) return "qubit count out of range 1..30";
     if (tile_bits < kMinTileBits || tile_bits > kMaxTileBits) return "tile bits out of range 10..14";
@@ -1105,6 +1166,9 @@ std::string build_plan(int n, const void *gates_v, size_t n_gates, int tile_bits
         }
         pending_scale = renorm_after[s] != 0;
     }
+    plan.in_place = in_place;
+    plan.layout = layout;
+    if (layout && m >= kMinTileBits && n > m) assign_layouts(n, m, plan, in_place);
     if (lower)
         for (HostPass &p : plan.passes)
             if (!lower_pass(n, m, p)) return "internal: relabelling control on a lane bit";
@@ -1126,18 +1190,27 @@ std::string plan_json(const Plan &p) {
             o << (k ? "," : "") << "[" << h.out_cx[k].first << "," << h.out_cx[k].second << "]";
         o << "],\"out_img\":[";
         for (size_t k = 0; k < h.out_img.size(); ++k) o << (k ? "," : "") << h.out_img[k];
-        // store record of the register kernel (address arithmetic of the last phase)
-        const IoRec &r = h.io_out;
-        o << "],\"io_out\":{\"kind\":" << (int)r.kind << ",\"g\":[" << (int)r.g4 << ","
-          << (int)r.g5 << "," << (int)r.g6 << "]";
-        const uint32_t *arrs[4] = {r.reg_off, r.wave_off, r.reg_xor, r.wave_xor};
-        const char *names[4] = {"reg_off", "wave_off", "reg_xor", "wave_xor"};
-        for (int a = 0; a < 4; ++a) {
-            o << ",\"" << names[a] << "\":[";
-            for (int k = 0; k < 16; ++k) o << (k ? "," : "") << arrs[a][k];
-            o << "]";
+        o << "],\"in_pos\":[";
+        for (size_t k = 0; k < h.in_pos.size(); ++k) o << (k ? "," : "") << (int)h.in_pos[k];
+        o << "],\"out_pos\":[";
+        for (size_t k = 0; k < h.out_pos.size(); ++k) o << (k ? "," : "") << (int)h.out_pos[k];
+        // load and store records of the register kernel (address arithmetic
+        // of the first and the last phase)
+        o << "]";
+        for (int side = 0; side < 2; ++side) {
+            const IoRec &r = side ? h.io_out : h.io_in;
+            o << (side ? ",\"io_out\"" : ",\"io_in\"") << ":{\"kind\":" << (int)r.kind << ",\"g\":["
+              << (int)r.g4 << "," << (int)r.g5 << "," << (int)r.g6 << "]";
+            const uint32_t *arrs[4] = {r.reg_off, r.wave_off, r.reg_xor, r.wave_xor};
+            const char *names[4] = {"reg_off", "wave_off", "reg_xor", "wave_xor"};
+            for (int a = 0; a < (side ? 4 : 2); ++a) {
+                o << ",\"" << names[a] << "\":[";
+                for (int k = 0; k < 16; ++k) o << (k ? "," : "") << arrs[a][k];
+                o << "]";
+            }
+            o << "}";
         }
-        o << "},\"ops\":[";
+        o << ",\"ops\":[";
         for (size_t k = 0; k < h.dev_ops.size(); ++k) {
             const DevOp &d = h.dev_ops[k];
             if (k) o << ",";
@@ -1146,8 +1219,15 @@ std::string plan_json(const Plan &p) {
               << ",\"sb\":" << (int)d.sb;
             if (d.type == OP_PDIAG) {
                 // qubit mask of the parity factor (register slots resolved with
-                // the layout of the op's phase)
-                uint64_t q = (uint64_t)d.gmask | pdep64(d.tmask, h.local_mask);
+                // the layout of the op's phase; non-local qubits by number, not
+                // by their bit in the load layout)
+                uint64_t g = d.gmask;
+                if (!h.in_pos.empty()) {
+                    g = 0;
+                    for (int q2 = 0; q2 < p.n; ++q2)
+                        if ((d.gmask >> h.in_pos[q2]) & 1u) g |= 1ull << q2;
+                }
+                uint64_t q = g | pdep64(d.tmask, h.local_mask);
                 for (const DevPhase &f : h.dev_phases)
                     if (k >= f.op_begin && k < f.op_end)
                         for (int s2 = 0; s2 < 4; ++s2)

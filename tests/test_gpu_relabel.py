@@ -39,6 +39,7 @@ def ctx(B):
     yield c
     c.set_option(B.QW_OPT_JIT, 1)
     c.set_option(B.QW_OPT_RELABEL, 1)
+    c.set_option(B.QW_OPT_LAYOUT, 1)
     c.set_option(B.QW_OPT_SECOND_BUFFER_CAP, 16 << 30)
     c.sync()
 
@@ -107,16 +108,24 @@ def _first_pass_relabel(n, second_plain):
     return gates
 
 
+@pytest.mark.parametrize("layout", [0, 2])
 @pytest.mark.parametrize("second_plain", [False, True])
-def test_relabel_first_pass_in_place(ctx, B, second_plain):
+def test_relabel_first_pass_in_place(ctx, B, second_plain, layout):
+    """With the standard layout the second (plain) pass is made out of
+    place; with a permuted layout between the two passes both move
+    amplitudes and the destination is copied to the second buffer first."""
     n = 20
-    say("relabel first pass in place", n, second_plain)
+    say("relabel first pass in place", n, second_plain, layout)
     gates = _first_pass_relabel(n, second_plain)
     plan = B.plan_describe(n, gates)
     assert plan["passes"][0]["out_cx"]
     assert len(plan["passes"]) == (2 if second_plain else 1)
-    a = _run(B, ctx, n, gates, 0)
-    b = _run(B, ctx, n, gates, 2)
+    ctx.set_option(B.QW_OPT_LAYOUT, layout)
+    try:
+        a = _run(B, ctx, n, gates, 0)
+        b = _run(B, ctx, n, gates, 2)
+    finally:
+        ctx.set_option(B.QW_OPT_LAYOUT, 1)
     assert np.array_equal(a, b)
     ref = oracle.simulate(n, gates)
     assert 1 - oracle.fidelity(b.astype(np.complex128), ref) <= FID_TOL

@@ -35,9 +35,12 @@ def interpret(n, plan, psi):
         for f in p["phases"]:
             for j in range(f["op_begin"], f["op_end"]):
                 phase_of[j] = f
+        # device records name a non-local qubit by its bit in the layout the
+        # pass loads (in_pos); this interpreter keeps the standard layout
+        qubit_at = {pos: q for q, pos in enumerate(p.get("in_pos", []))}
         for j, op in enumerate(p["ops"]):
             def gbit(loc, b):
-                return b if loc == LOC_GLOBAL else lb[b]
+                return qubit_at.get(b, b) if loc == LOC_GLOBAL else lb[b]
             m = op["m"]
             t = op["type"]
             if t == OP_DTAB:
@@ -247,11 +250,33 @@ def test_trie_leaves_of_equal_length_share_structure():
     assert checked >= 3
 
 
-def _store_addresses(n, m, p, tile_bases_out):
-    """Store index of every element (tile, wave, lane, register) by the
-    register kernel's address arithmetic with output relabelling, and the
-    element's logical index (the same arithmetic without it)."""
-    io = p["io_out"]
+def _to_layout(v, pos):
+    """Standard-layout index bits of v at their places in layout pos (qubit q
+    at bit pos[q]; an empty list is the standard layout)."""
+    if not pos:
+        return v
+    r = np.zeros_like(v)
+    for q, b in enumerate(pos):
+        r |= ((v >> q) & 1) << b
+    return r
+
+
+def _from_layout(v, pos):
+    if not pos:
+        return v
+    r = np.zeros_like(v)
+    for q, b in enumerate(pos):
+        r |= ((v >> b) & 1) << q
+    return r
+
+
+def _io_addresses(n, m, p, side, tile_bases):
+    """Index of every element (tile, wave, lane, register) by the register
+    kernel's address arithmetic of the pass's load (side "io_in") or store
+    ("io_out", with output relabelling) record and the given tile origins,
+    and the element's index in the standard layout before relabelling."""
+    io = p[side]
+    pos = p["in_pos"] if side == "io_in" else p["out_pos"]
     g4, g5, g6 = io["g"]
     lane = np.arange(64)
     if io["kind"] == 1:
@@ -266,17 +291,44 @@ def _store_addresses(n, m, p, tile_bases_out):
         for w in range(waves):
             for k in range(16):
                 lo = io["wave_off"][w] | io["reg_off"][k]
-                logical.append(base | lo | lane_off)
-                hi = tile_bases_out[ti] ^ io["wave_xor"][w] ^ io["reg_xor"][k]
+                logical.append(base | _from_layout(lo | lane_off, pos))
+                hi = tile_bases[ti]
+                if side == "io_out":
+                    hi = hi ^ io["wave_xor"][w] ^ io["reg_xor"][k]
                 addr.append(hi | lo | lane_off)
     return np.concatenate(addr), np.concatenate(logical)
+
+
+def _tile_origins(n, m, p, side):
+    """The executor's tile origin tables: tile ti is the ti-th value of the
+    non-local qubits in counting order, relabelled (stores) and placed in
+    the side's layout."""
+    nl = [q for q in range(n) if not (p["local_mask"] >> q) & 1]
+    img = p["out_img"] if side == "io_out" else []
+    pos = p["in_pos"] if side == "io_in" else p["out_pos"]
+    out = []
+    for ti in range(1 << (n - m)):
+        o = 0
+        for b, q in enumerate(nl):
+            if (ti >> b) & 1:
+                o ^= img[q] if img else (1 << q)
+        out.append(int(_to_layout(np.int64(o), pos)))
+    return out
+
+
+def _relabel(v, out_cx):
+    r = v.copy()
+    for c, t in out_cx:
+        r ^= ((r >> c) & 1) << t
+    return r
 
 
 def test_relabel_store_addresses_are_the_cnot_permutation():
     """For passes with output relabelling, the store index computed from the
     plan's store record and relabelled tile origins equals L(j), the image
-    of the element's logical index under the pass's trailing CNOTs, and the
-    stores are a permutation of the state."""
+    of the element's logical index under the pass's trailing CNOTs, placed
+    in the layout the pass stores, and the stores are a permutation of the
+    state."""
     from tests.test_gpu_relabel import _ladder_circuit
     checked = 0
     for n, tile, seed in [(16, 10, 1), (18, 12, 2), (20, 14, 3)]:
@@ -288,27 +340,66 @@ def test_relabel_store_addresses_are_the_cnot_permutation():
                 continue
             img = p["out_img"]
             assert len(img) == n
-            nl = [q for q in range(n) if not (p["local_mask"] >> q) & 1]
-            tbo = []
-            for ti in range(1 << (n - m)):
-                o = 0
-                for b, q in enumerate(nl):
-                    if (ti >> b) & 1:
-                        o ^= img[q]
-                tbo.append(o)
-            addr, logical = _store_addresses(n, m, p, tbo)
+            addr, logical = _io_addresses(n, m, p, "io_out", _tile_origins(n, m, p, "io_out"))
             assert np.array_equal(np.sort(addr), np.arange(1 << n))
             want = np.zeros_like(logical)
             for q in range(n):
                 want ^= np.where((logical >> q) & 1, img[q], 0)
             # L from the CNOT list directly
-            ref = logical.copy()
-            for c, t in p["out_cx"]:
-                ref ^= ((ref >> c) & 1) << t
+            ref = _relabel(logical, p["out_cx"])
             assert np.array_equal(want, ref)
-            assert np.array_equal(addr, ref)
+            assert np.array_equal(addr, _to_layout(ref, p["out_pos"]))
             checked += 1
     assert checked >= 3
+
+
+def test_layouts_between_passes():
+    """Index layouts between the passes of a plan: a plan loads and stores
+    the standard layout at its ends; pass k stores the layout pass k + 1
+    loads; qubits 0..3 keep bits 0..3; at each permuted boundary one side's
+    local qubits are the lowest index bits (contiguous tiles). Every pass's
+    load and store records, with the executor's tile origins, address each
+    amplitude at its index in the side's layout (after relabelling, for
+    stores), and both are permutations of the state. A config-2 suffix gets
+    whole-tile stores in its middle pass and half-tile loads in its last."""
+    from tests.test_gpu_relabel import _ladder_circuit
+    w2 = gen.config2()
+    cases = [(20, w2.suffixes[0], 14), (20, w2.prefix, 14),
+             (16, _ladder_circuit(16, np.random.default_rng(7101), 3), 10),
+             (18, gen.small_vqe(18, 3, 2, 1, 1, seed=58).task_gates(0), 12)]
+    permuted = 0
+    for n, gates, tile in cases:
+        gates = [g for g in gates if max(g[1]) < n]
+        plan = B.plan_describe(n, gates, tile)
+        m = plan["tile_bits"]
+        ps = plan["passes"]
+        assert ps[0]["in_pos"] == [] and ps[-1]["out_pos"] == []
+        for k, p in enumerate(ps):
+            if k + 1 < len(ps):
+                assert p["out_pos"] == ps[k + 1]["in_pos"]
+            for pos in (p["in_pos"], p["out_pos"]):
+                if pos:
+                    assert sorted(pos) == list(range(n)) and pos[:4] == [0, 1, 2, 3]
+            if p["out_pos"]:
+                permuted += 1
+                nxt = ps[k + 1]
+                low = (1 << m) - 1
+                sides = [int(_to_layout(np.int64(q["local_mask"]), p["out_pos"])) for q in (p, nxt)]
+                assert low in sides
+            for side in ("io_in", "io_out"):
+                addr, logical = _io_addresses(n, m, p, side, _tile_origins(n, m, p, side))
+                assert np.array_equal(np.sort(addr), np.arange(1 << n))
+                pos = p["in_pos"] if side == "io_in" else p["out_pos"]
+                want = logical if side == "io_in" else _relabel(logical, p["out_cx"])
+                assert np.array_equal(addr, _to_layout(want, pos))
+    assert permuted >= 3
+    # config 2's suffix at 24 qubits: the middle pass stores whole tiles and
+    # the last pass loads runs of 2^13 amplitudes (instead of 16 each)
+    plan = B.plan_describe(24, w2.suffixes[0], 14)
+    mid, last = plan["passes"][1], plan["passes"][2]
+    assert int(_to_layout(np.int64(mid["local_mask"]), mid["out_pos"])) == (1 << 14) - 1
+    run = int(~_to_layout(np.int64(last["local_mask"]), last["in_pos"]) & ((1 << 24) - 1))
+    assert (run & -run).bit_length() - 1 >= 13
 
 
 def test_special_angles_keep_the_structure_of_an_hea_suffix():
