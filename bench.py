@@ -399,6 +399,7 @@ def _run_planned(args, n, tasks, shots, seed, name):
 def bench_trie(args):
     """Config 3: 20 qubits, prefix tree depth 3 x branching 8 (72 shared
     nodes), 512 leaves with 1..12 extra layers, 1024 Z-basis shots each."""
+    import numpy as np
     from workloads import gen
     w = gen.config3()
     tasks = [w.leaf_path(k) for k in range(len(w.leaves))]
@@ -409,7 +410,9 @@ def bench_trie(args):
     T = len(tasks)
     picks = (0, 301, T - 1)
     g = _run_graphs(args, w.n, tasks, plan, w.shots, w.seed, rp.samples, tune=not args.no_tune,
-                    keep=picks)
+                    keep=picks, persistent=True)
+    tree_equal = bool(np.array_equal(g["tree"]["res"].samples, g["direct"]["res"].samples))
+    tree_states_equal = all(np.array_equal(g["tree"]["states"][k], g["plan"]["states"][k]) for k in picks)
     result = {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)",
             "autotune": g.get("autotune"),
             "value": round(T / g["plan"]["s"], 2),
@@ -422,6 +425,13 @@ def bench_trie(args):
             "graph": {m: {"nodes": g[m]["nodes"], "record_s": round(g[m]["record_s"], 3),
                           "samples_equal_eager_default_options": g[m]["same"]}
                       for m in ("plan", "direct")},
+            "persistent": {"tasks_per_s": round(T / g["tree"]["s"], 2), "nodes": g["tree"]["nodes"],
+                           "record_s": round(g["tree"]["record_s"], 3),
+                           "speedup_vs_direct": round(g["direct"]["s"] / g["tree"]["s"], 3),
+                           "samples_equal_direct": tree_equal, "states_equal_per_pass_graph": tree_states_equal,
+                           "execution": "one recorded graph per step: one reset, the tree's passes "
+                                        "(every level, every leaf) in one persistent kernel launch, "
+                                        "the sampler"},
             "eager_tasks_per_s": round(T / tp, 2), "eager_direct_tasks_per_s": round(T / td, 2),
             "samples_equal_direct": bool((g["plan"]["res"].samples == g["direct"]["res"].samples).all()),
             "eager_samples_equal_direct": same,
@@ -434,11 +444,14 @@ def bench_trie(args):
     return result
 
 
-def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune=False, keep=()):
+def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune=False, keep=(),
+                persistent=False):
     """Record the planned and the direct execution as graphs (qw_graph_*)
     and time one replay plus the results' copy to the host per step. With
     `tune`, the execution options (fusion width, tile schedule) are first
-    chosen by the timing autotuner; both graphs then run under its choice."""
+    chosen by the timing autotuner; both graphs then run under its choice.
+    With `persistent`, the planned execution is also recorded as one tree
+    call in one persistent kernel launch (mode "tree")."""
     import numpy as np
     import torch
     from paper_2609_23664_amd import binding as B
@@ -453,9 +466,12 @@ def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune
     # generated kernels for every pass structure (compiled, or read from the
     # disk cache, during recording; reported as record_s)
     ctx.set_option(B.QW_OPT_JIT, 2)
-    for mode in ("plan", "direct"):
+    for mode in (("plan", "tree", "direct") if persistent else ("plan", "direct")):
         t0 = time.perf_counter()
-        rw = P.record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed, mode=mode)
+        ctx.set_option(B.QW_OPT_PERSISTENT, 1 if mode == "tree" else 0)
+        rw = P.record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed,
+                               mode="plan" if mode == "tree" else mode, tree=mode == "tree")
+        ctx.set_option(B.QW_OPT_PERSISTENT, 0)
         rec_s = time.perf_counter() - t0
         for _ in range(max(1, args.warmup)):
             rw.replay()
@@ -469,7 +485,7 @@ def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         same = bool(np.array_equal(res.samples, ref_samples)) if ref_samples is not None else None
-        kept = {t: rw.state_host(t) for t in keep} if mode == "plan" else {}
+        kept = {t: rw.state_host(t) for t in keep} if mode != "direct" else {}
         out[mode] = {"s": _median(times), "nodes": rw.graph.nodes(), "record_s": rec_s, "states": kept,
                      "same": same, "res": res}
         rw.free()

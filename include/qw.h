@@ -39,6 +39,10 @@ extern "C" {
 #define QW_E_REFUSED 4      /* a continuation failed a legality gate; the
                                refusal record (JSON) is in qw_last_error()  */
 #define QW_E_UNSUPPORTED 5  /* valid request outside what the library does  */
+#define QW_E_ABANDONED 6    /* a persistent launch gave up a bounded wait
+                               (QW_OPT_SPIN_LIMIT or qw_ctx_abandon); the
+                               states it was computing are undefined; reported
+                               by qw_ctx_sync                                */
 
 /* ------------------------------------------------------------ gates */
 /* Gate kinds. Matrices in the computational basis (|0>, |1>):
@@ -270,7 +274,42 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         for every call. Results are bitwise the same in
  *                         every mode. [1] */
 #define QW_OPT_LAYOUT 12
+/*   QW_OPT_PERSISTENT     1: with generated kernels, each qw_run_suffix_batch
+ *                         or qw_run_tree call runs all of its passes (every
+ *                         pass index, every pass structure and, in a tree,
+ *                         every level) in ONE persistent kernel launch: its
+ *                         workgroups take (descriptor, tile range) claims in
+ *                         order from one device counter, and a claim whose
+ *                         source is still being written waits, in a bounded
+ *                         poll, for the completion counter of the pass (or
+ *                         parent task) that writes it. Claims only wait for
+ *                         earlier claims, so the launch completes without
+ *                         requiring its workgroups to be resident at once.
+ *                         Calls that need a norm finalisation between
+ *                         passes (noisy jumps) or interpreted kernels keep
+ *                         one launch per pass structure. Results are bitwise
+ *                         those of the per-pass launches. [0] */
+#define QW_OPT_PERSISTENT 13
+/*   QW_OPT_SPIN_LIMIT     microseconds one wait of a persistent launch may
+ *                         last before it is abandoned (the launch then skips
+ *                         its remaining work and qw_ctx_sync returns
+ *                         QW_E_ABANDONED); 0 abandons at the first wait
+ *                         that is not already satisfied. [1048576, ~1 s] */
+#define QW_OPT_SPIN_LIMIT 14
+/*   QW_OPT_PERSIST_CHUNK  most tiles (rows of an expectation epilogue) of one
+ *                         descriptor that a workgroup of a persistent launch
+ *                         takes per claim (a power of two, 1..1024); fewer
+ *                         when a segment has too few claims to keep four per
+ *                         workgroup. Each claim ends with a release of its
+ *                         stores and a dependent claim starts with an
+ *                         acquire, so larger claims synchronise less. [8] */
+#define QW_OPT_PERSIST_CHUNK 15
 int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value);
+
+/* Ask the waits of running and later persistent launches of this context to
+ * give up (callable from any host thread while the GPU works): they end with
+ * QW_E_ABANDONED at the next qw_ctx_sync, which also withdraws the request. */
+int qw_ctx_abandon(qw_ctx *ctx);
 
 /* Per-kernel launch statistics gathered while QW_OPT_PROFILE is 1.
  * kernel: 0 = gate pass, 1 = expectation reducer, 2 = sampler, 3 = copy.
@@ -342,6 +381,26 @@ int qw_snapshot_info(const qw_snap *snap, qw_artifact *out);
 int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src,
                         const qw_task *tasks, uint32_t n_tasks, qw_state *dst,
                         const qw_reduce *epilogue);
+
+/* qw_run_tree: run a tree of continuations in one call (the prefix tree of
+ * Fig. 1 and Sec. III-A, where a materialized node's state is the boundary
+ * of the tasks below it). Task k starts from
+ *   - the final state of task parent[k] of this call when parent[k] >= 0
+ *     (parent[k] < k, so parents come first), or else
+ *   - its boundary snapshot src[k] (src may be NULL), or else
+ *   - its destination slot as it stands (the direct path).
+ * out_prov (n_tasks x 32 bytes, required when any parent[k] >= 0) is the
+ * provenance of each task's final state; a child's tasks[k].expect_prov
+ * must equal its parent's, and snapshot sources pass the legality gates of
+ * qw_run_suffix_batch. Destination slots must be distinct and not frozen;
+ * gates may not measure or reset. A task with a parent must have gates.
+ * With QW_OPT_PERSISTENT the whole tree is one kernel launch; otherwise it
+ * runs level by level (a task after its parent's level). Every task's final
+ * state is bitwise the one qw_run_suffix_batch would compute from the same
+ * source with the same gates. No expectations: use qw_expect_pauli after. */
+int qw_run_tree(qw_ctx *ctx, const qw_snap *const *src, const qw_task *tasks,
+                const int32_t *parent, const uint8_t *out_prov, uint32_t n_tasks,
+                qw_state *dst);
 
 /* qw_outcomes: the measurement outcomes (0 or 1, one byte each) of the
  * MEASURE and RESET gates of the most recent qw_apply_prefix or

@@ -21,6 +21,7 @@ QW_E_OOM = 2
 QW_E_HIP = 3
 QW_E_REFUSED = 4
 QW_E_UNSUPPORTED = 5
+QW_E_ABANDONED = 6
 
 GATE_KIND = {
     "X": 0x01, "Y": 0x02, "Z": 0x03, "H": 0x04, "S": 0x05, "SDG": 0x06,
@@ -51,6 +52,9 @@ QW_OPT_TILE_ORDER = 9
 QW_OPT_STREAM_LOADS = 10
 QW_OPT_DEVICE_MEM_CAP = 11
 QW_OPT_LAYOUT = 12
+QW_OPT_PERSISTENT = 13
+QW_OPT_SPIN_LIMIT = 14
+QW_OPT_PERSIST_CHUNK = 15
 
 EXPORTED = (
     "qw_ctx_create", "qw_ctx_destroy", "qw_last_error", "qw_ctx_sync",
@@ -64,7 +68,7 @@ EXPORTED = (
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
     "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
     "qw_graph_update_gates", "qw_sample_noalloc", "qw_mlp_backward_rows", "qw_mlp_loss",
-    "qw_graph_outcomes",
+    "qw_graph_outcomes", "qw_run_tree", "qw_ctx_abandon",
 )
 
 
@@ -189,6 +193,9 @@ def lib() -> ctypes.CDLL:
         "qw_graph_nodes": ([vp, ctypes.POINTER(u64)], i32),
         "qw_graph_free": ([vp], i32),
         "qw_graph_outcomes": ([vp, vp, u64, ctypes.POINTER(u64)], i32),
+        "qw_run_tree": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(QwTask),
+                         ctypes.POINTER(ctypes.c_int32), vp, u32, vp], i32),
+        "qw_ctx_abandon": ([vp], i32),
         "qw_graph_update_gates": ([vp, u32, u32, ctypes.POINTER(QwGate), u64], i32),
     }
     for name, (args, res) in sig.items():
@@ -425,6 +432,10 @@ class Ctx:
 
     def sync(self):
         self.check(lib().qw_ctx_sync(self.h))
+
+    def abandon(self):
+        """qw_ctx_abandon: waits of persistent launches give up."""
+        self.check(lib().qw_ctx_abandon(self.h))
 
     def kernel_stats(self, kernel: int, reset: bool = True):
         n = ctypes.c_uint64()
@@ -683,3 +694,32 @@ def run_suffix_batch(ctx: Ctx, srcs: Sequence[Optional[Snapshot]], suffixes, dst
     if out is not None:
         return [out[i] for i in range(nt)]
     return None
+
+
+def run_tree(ctx: Ctx, srcs: Optional[Sequence[Optional[Snapshot]]], suffixes, parents: Sequence[int],
+             dst: State, dst_slots: Sequence[int], expect_provs: Sequence[bytes] = None,
+             out_provs: Sequence[bytes] = None):
+    """qw_run_tree: task k starts from task parents[k]'s final state (if >= 0),
+    else from srcs[k] (if given), else from its destination slot."""
+    nt = len(suffixes)
+    arrs = [gate_array(s) for s in suffixes]
+    tasks = (QwTask * max(1, nt))()
+    for k in range(nt):
+        tasks[k].gates = arrs[k].ptr
+        tasks[k].n_gates = len(arrs[k])
+        tasks[k].dst_slot = int(dst_slots[k])
+        tasks[k].reserved = 0
+        prov = expect_provs[k] if expect_provs is not None else (
+            srcs[k].provenance if srcs and srcs[k] is not None else bytes(32))
+        tasks[k].expect_prov = (ctypes.c_uint8 * 32)(*prov)
+    src_arr = None
+    if srcs is not None:
+        src_arr = (ctypes.c_void_p * max(1, nt))()
+        for k in range(nt):
+            src_arr[k] = srcs[k].h.value if srcs[k] is not None else None
+    par = (ctypes.c_int32 * max(1, nt))(*[int(p) for p in parents])
+    outp = None
+    if out_provs is not None:
+        outp = (ctypes.c_uint8 * (32 * max(1, nt)))(*b"".join(bytes(o) for o in out_provs))
+    rc = lib().qw_run_tree(ctx.h, src_arr, tasks, par, outp, nt, dst.h)
+    ctx.check(rc)

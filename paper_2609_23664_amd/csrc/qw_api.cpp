@@ -81,7 +81,7 @@ struct GraphRec {
     hipStream_t cap = nullptr;    // captured stream (non-blocking, default priority)
     hipStream_t up = nullptr;     // plan uploads, synchronous, outside the capture
     hipStream_t saved_stream = nullptr;
-    DevBuf saved_plan, saved_scratch, saved_pingpong, saved_meas;
+    DevBuf saved_plan, saved_scratch, saved_pingpong, saved_meas, saved_psync;
     std::vector<void *> owned;    // buffers replaced during the recording
     bool plan_used = false;       // ctx->plan already holds an uploaded blob
     std::vector<OutcomeRec> outcomes;  // measured calls: where a replay writes their outcomes
@@ -112,6 +112,13 @@ struct qw_ctx {
     DevBuf scratch;  // partial sums, sampler buffers
     DevBuf pingpong; // second state buffers of tasks with relabelling passes
     DevBuf meas;     // measurement sums: slot pointers, qubits, partials, results
+    DevBuf psync;    // persistent launches: claim counter, abandon flag, completion counters
+    // persistent launches (QW_OPT_PERSISTENT): pinned host words, [0] set by
+    // the host to abandon waits, [1] set by a launch that abandoned one
+    uint32_t *host_flag = nullptr;
+    bool persistent = false;
+    uint32_t spin_limit = 1u << 20;  // QW_OPT_SPIN_LIMIT: microseconds per wait
+    uint32_t persist_chunk = 8;      // QW_OPT_PERSIST_CHUNK: max tiles (rows) per claim
     std::vector<uint8_t> outcomes;  // outcome record of the last measured call
     std::unordered_map<std::string, uint64_t> jit_heat;  // task-tiles run per pass structure
     bool relabel = true;
@@ -184,7 +191,7 @@ int hip_fail(qw_ctx *ctx, hipError_t e, const char *what) {
 // second-state and measurement buffers (buffers handed to a recorded graph
 // belong to the graph).
 uint64_t ctx_bytes(const qw_ctx *ctx) {
-    return ctx->held + ctx->plan.cap + ctx->scratch.cap + ctx->pingpong.cap + ctx->meas.cap;
+    return ctx->held + ctx->plan.cap + ctx->scratch.cap + ctx->pingpong.cap + ctx->meas.cap + ctx->psync.cap;
 }
 
 // QW_OPT_DEVICE_MEM_CAP: refuse an allocation of `want` bytes (replacing
@@ -510,6 +517,9 @@ struct Exec {
     const std::string *epi_key = nullptr;
     double *epi_part = nullptr;  // this task's [rows][epi_nt] partials
     uint32_t epi_nt = 0;
+    // qw_run_tree: index (in the same execution) of the task whose final
+    // state `src` is, or -1; such a task runs in a persistent launch
+    int parent = -1;
 };
 
 // The plan has a pass that stores to other addresses than it loads (output
@@ -593,6 +603,12 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         if (rc) return rc;
     }
     double *norm_base = static_cast<double *>(ctx->scratch.p);
+    // one persistent launch for all passes (QW_OPT_PERSISTENT); a norm
+    // finalisation between passes keeps the launches per pass structure
+    const bool persist = ctx->persistent && ctx->jit && m >= kMinTileBits && !any_norm;
+    for (const Exec &e : ex)
+        if (e.parent >= 0 && !persist)
+            return fail(ctx, QW_E_INVALID_ARG, "in-call parents need a persistent launch");
     // second state buffers and per-pass buffer choice of relabelling tasks
     std::vector<std::vector<int>> bufsel(ex.size());
     std::vector<void *> second(ex.size(), nullptr);
@@ -638,10 +654,18 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     // blob layout
     Layout L;
     std::vector<size_t> step_off(steps), step_cnt(steps, 0);
+    size_t n_desc = 0;
     for (size_t k = 0; k < steps; ++k) {
         for (Exec &e : ex) step_cnt[k] += (k < e.planp->passes.size());
+        // (consecutive: the steps' descriptor arrays form one array)
         step_off[k] = L.take(step_cnt[k] * sizeof(PassDesc));
+        n_desc += step_cnt[k];
     }
+    // persistent launch: the descriptors again in claim order, at most one
+    // segment per descriptor, one dependency each
+    const size_t pdesc_off = persist ? L.take(n_desc * sizeof(PassDesc)) : 0;
+    const size_t seg_off = persist ? L.take(n_desc * sizeof(PSeg)) : 0;
+    const size_t dep_off = persist ? L.take(n_desc * sizeof(PDep)) : 0;
     std::vector<std::vector<std::pair<size_t, size_t>>> op_off(ex.size());
     std::vector<std::vector<size_t>> io_off(ex.size());
     for (size_t t = 0; t < ex.size(); ++t) {
@@ -729,12 +753,13 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         const JitKernel *k;  // nullptr: interpreted kernels for this group
         uint32_t first, count;
         bool lds;
+        uint32_t req;        // generated kernels: its request
     };
     std::vector<std::vector<size_t>> order(steps);
     std::vector<std::vector<Group>> groups(steps);
     const bool use_jit = ctx->jit && m >= kMinTileBits;
+    std::vector<JitReq> reqs;
     if (use_jit) {
-        std::vector<JitReq> reqs;
         std::vector<std::vector<std::pair<size_t, std::vector<size_t>>>> members(steps);
         for (size_t k = 0; k < steps; ++k) {
             std::map<std::string, size_t> gi;
@@ -770,7 +795,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
         // or when its structure has run enough work on this context to pay
         // for compiling it
         std::vector<char> want(reqs.size(), 1);
-        if (ctx->jit == 1) {
+        if (ctx->jit == 1 && !persist) {
             std::vector<uint64_t> work(reqs.size(), 0);
             for (size_t k = 0; k < steps; ++k)
                 for (auto &gm : members[k]) work[gm.first] += (uint64_t)gm.second.size() * tiles;
@@ -788,14 +813,16 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
                 sel_of[i] = sel.size();
                 sel.push_back(reqs[i]);
             }
-        std::vector<const JitKernel *> kern;
-        const std::string err = jit_get(ctx->device, sel, &kern);
-        if (!err.empty()) return fail(ctx, QW_E_HIP, err);
+        std::vector<const JitKernel *> kern(sel.size(), nullptr);
+        if (!persist) {
+            const std::string err = jit_get(ctx->device, sel, &kern);
+            if (!err.empty()) return fail(ctx, QW_E_HIP, err);
+        }
         for (size_t k = 0; k < steps; ++k) {
             for (auto &gm : members[k]) {
                 const JitKernel *kk = sel_of[gm.first] == (size_t)-1 ? nullptr : kern[sel_of[gm.first]];
                 groups[k].push_back({kk, (uint32_t)order[k].size(), (uint32_t)gm.second.size(),
-                                     reqs[gm.first].use_lds});
+                                     reqs[gm.first].use_lds, (uint32_t)gm.first});
                 for (size_t t : gm.second) order[k].push_back(t);
             }
         }
@@ -847,6 +874,121 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
             ++c;
         }
     }
+    // persistent launch: its kernel (every pass structure of the call), the
+    // segments (one per level and pass structure, in claim order) and each
+    // descriptor's dependency
+    const JitKernel *pk = nullptr;
+    std::vector<PersistPart> parts;
+    uint32_t n_segs = 0, n_claims = 0, pgrid = 0;
+    if (persist) {
+        std::vector<uint32_t> kind_of(reqs.size(), kNoDep);
+        for (size_t k = 0; k < steps; ++k)
+            for (const Group &g : groups[k]) {
+                if (kind_of[g.req] != kNoDep) continue;
+                kind_of[g.req] = (uint32_t)parts.size();
+                PersistPart q;
+                q.pass = reqs[g.req].pass;
+                q.epi = reqs[g.req].epi;
+                q.epi_key = ex[order[k][g.first]].epi_key;
+                q.n = (int)n;
+                q.m = m;
+                q.stream_loads = reqs[g.req].stream_loads;
+                parts.push_back(q);
+            }
+        JitReq pr;
+        pr.key = jit_persist_key(parts);
+        pr.persist = &parts;
+        pr.n = (int)n;
+        pr.m = m;
+        pr.use_lds = true;
+        std::vector<const JitKernel *> kk;
+        const std::string err = jit_get(ctx->device, {pr}, &kk);
+        if (!err.empty()) return fail(ctx, QW_E_HIP, err);
+        pk = kk[0];
+        pgrid = ctx->n_cu * (uint32_t)pk->blocks_per_cu;
+        // claim order: by level, the number of passes that must have run
+        // before a descriptor's (its task's earlier passes and, through
+        // in-call parents, all of their passes), so that every dependency
+        // lies in an earlier level; within a level by pass structure, then
+        // task
+        std::vector<uint32_t> start(ex.size(), 0);
+        for (size_t t = 0; t < ex.size(); ++t) {
+            if (ex[t].parent < 0) continue;
+            const size_t pt = (size_t)ex[t].parent;
+            if (pt >= t || ex[pt].planp->passes.empty())
+                return fail(ctx, QW_E_INVALID_ARG, "a parent task must come first and have passes");
+            start[t] = start[pt] + (uint32_t)ex[pt].planp->passes.size();
+        }
+        struct Item {
+            uint32_t level, kind;
+            uint32_t t, k;
+            uint32_t from;  // index in the per-step descriptor arrays
+            uint32_t units;
+        };
+        std::vector<Item> items;
+        items.reserve(n_desc);
+        for (size_t k = 0; k < steps; ++k) {
+            const uint32_t d0 = (uint32_t)(step_off[k] / sizeof(PassDesc));
+            for (const Group &g : groups[k]) {
+                const uint32_t units = reqs[g.req].epi ? tiles / red_row_tiles(tiles) : tiles;
+                for (uint32_t i = 0; i < g.count; ++i) {
+                    const uint32_t t = (uint32_t)order[k][g.first + i];
+                    items.push_back({start[t] + (uint32_t)k, kind_of[g.req], t, (uint32_t)k, d0 + g.first + i, units});
+                }
+            }
+        }
+        std::sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+            if (a.level != b.level) return a.level < b.level;
+            if (a.kind != b.kind) return a.kind < b.kind;
+            return a.t < b.t;
+        });
+        // descriptor index (claim order) of (task, pass)
+        std::vector<std::vector<uint32_t>> gi_of(ex.size());
+        for (size_t t = 0; t < ex.size(); ++t) gi_of[t].assign(ex[t].planp->passes.size(), kNoDep);
+        PassDesc *pd = reinterpret_cast<PassDesc *>(blob.data() + pdesc_off);
+        const PassDesc *sd = reinterpret_cast<const PassDesc *>(blob.data() + step_off[0]);
+        for (uint32_t i = 0; i < (uint32_t)items.size(); ++i) {
+            pd[i] = sd[items[i].from];
+            gi_of[items[i].t][items[i].k] = i;
+        }
+        PSeg *sg = reinterpret_cast<PSeg *>(blob.data() + seg_off);
+        for (uint32_t i = 0; i < (uint32_t)items.size();) {
+            uint32_t j = i + 1;
+            while (j < items.size() && items[j].level == items[i].level && items[j].kind == items[i].kind) ++j;
+            const uint32_t count = j - i, units = items[i].units;
+            bool shared_src = true;
+            for (uint32_t q = i + 1; q < j && shared_src; ++q) shared_src = pd[q].src == pd[i].src;
+            const bool relabel = !ex[items[i].t].planp->passes[items[i].k].out_img.empty();
+            const bool tmaj = !shared_src && (ctx->tile_order == 2 || (ctx->tile_order == 1 && relabel));
+            // up to persist_chunk units per claim, keeping at least 4 claims
+            // per workgroup
+            uint32_t chunk = ctx->persist_chunk;
+            while (chunk > 1 && (units % chunk != 0 || (uint64_t)units * count / chunk < 4ull * pgrid))
+                chunk >>= 1;
+            PSeg e{};
+            e.claim0 = n_claims;
+            e.n_claims = units / chunk * count;
+            e.desc0 = i;
+            e.n_descs = count;
+            e.chunk = chunk;
+            e.kind = items[i].kind;
+            e.tmaj = tmaj ? 1u : 0u;
+            e.units = units;
+            sg[n_segs++] = e;
+            n_claims += e.n_claims;
+            i = j;
+        }
+        PDep *dp = reinterpret_cast<PDep *>(blob.data() + dep_off);
+        for (const Item &it : items) {
+            PDep d{kNoDep, 0u};
+            if (it.k > 0)
+                d.dep = gi_of[it.t][it.k - 1];
+            else if (ex[it.t].parent >= 0)
+                d.dep = gi_of[(size_t)ex[it.t].parent].back();
+            if (d.dep != kNoDep) d.need = items[d.dep].units;
+            dp[gi_of[it.t][it.k]] = d;
+        }
+    }
     if (ctx->rec && !ctx->rec->calls.empty()) {
         // where each task's op records live in the graph (qw_graph_update_gates)
         for (size_t t = 0; t < ex.size(); ++t) {
@@ -868,6 +1010,21 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     for (size_t k = 0; k < steps; ++k) {
         n_launch += use_jit ? (uint32_t)groups[k].size() : 1u;
         all_bytes += (double)step_cnt[k] * 2.0 * (double)state_bytes;
+    }
+    if (persist) {
+        const size_t words = kSyncCounters + n_desc;
+        int rc2 = ensure(ctx, ctx->psync, words * sizeof(uint32_t), "persistent sync area");
+        if (rc2) return rc2;
+        uint32_t *sync = static_cast<uint32_t *>(ctx->psync.p);
+        hipError_t er = launch_zero_words(ctx->stream, sync, words);
+        if (er != hipSuccess) return hip_fail(ctx, er, "sync clear launch");
+        ProfScope ps(ctx, 0, all_bytes, 1u);
+        er = jit_launch_persist(ctx->stream, *pk, reinterpret_cast<const PSeg *>(dbase + seg_off), n_segs,
+                                reinterpret_cast<const PassDesc *>(dbase + pdesc_off),
+                                reinterpret_cast<const PDep *>(dbase + dep_off), sync, n_claims,
+                                std::min(pgrid, n_claims), ctx->spin_limit, ctx->host_flag);
+        if (er != hipSuccess) return hip_fail(ctx, er, "persistent launch");
+        return QW_OK;
     }
     ProfScope ps_all(ctx, 0, all_bytes, any_norm ? 0u : n_launch);
     for (size_t k = 0; k < steps; ++k) {
@@ -1484,6 +1641,14 @@ int qw_ctx_create(int device, void *hip_stream, qw_ctx **out) {
         delete c;
         return QW_E_HIP;
     }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->host_flag), 2 * sizeof(uint32_t), hipHostMallocDefault) !=
+        hipSuccess) {
+        hipEventDestroy(c->staging_ev);
+        delete c;
+        return QW_E_OOM;
+    }
+    __atomic_store_n(&c->host_flag[0], 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(&c->host_flag[1], 0u, __ATOMIC_RELAXED);
     *out = c;
     return QW_OK;
 }
@@ -1505,6 +1670,8 @@ int qw_ctx_destroy(qw_ctx *ctx) {
     if (ctx->scratch.p) hipFree(ctx->scratch.p);
     if (ctx->pingpong.p) hipFree(ctx->pingpong.p);
     if (ctx->meas.p) hipFree(ctx->meas.p);
+    if (ctx->psync.p) hipFree(ctx->psync.p);
+    if (ctx->host_flag) hipHostFree(ctx->host_flag);
     if (ctx->staging) hipHostFree(ctx->staging);
     if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
     delete ctx;
@@ -1517,6 +1684,20 @@ int qw_ctx_sync(qw_ctx *ctx) {
     if (!ctx) return QW_E_INVALID_ARG;
     if (ctx->rec) return recording_unsupported(ctx, "qw_ctx_sync");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
+    if (__atomic_load_n(&ctx->host_flag[1], __ATOMIC_ACQUIRE) != 0u) {
+        __atomic_store_n(&ctx->host_flag[0], 0u, __ATOMIC_RELAXED);
+        __atomic_store_n(&ctx->host_flag[1], 0u, __ATOMIC_RELEASE);
+        return fail(ctx, QW_E_ABANDONED,
+                    "a persistent launch abandoned a wait (spin limit reached or qw_ctx_abandon); "
+                    "the states it was computing are undefined");
+    }
+    __atomic_store_n(&ctx->host_flag[0], 0u, __ATOMIC_RELAXED);
+    return QW_OK;
+}
+
+int qw_ctx_abandon(qw_ctx *ctx) {
+    if (!ctx) return QW_E_INVALID_ARG;
+    __atomic_store_n(&ctx->host_flag[0], 1u, __ATOMIC_RELEASE);
     return QW_OK;
 }
 
@@ -1540,6 +1721,16 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         ctx->layout = (int)value;
         return QW_OK;
     case QW_OPT_FUSED_EPILOGUE: ctx->fused_epilogue = value != 0; return QW_OK;
+    case QW_OPT_PERSISTENT: ctx->persistent = value != 0; return QW_OK;
+    case QW_OPT_PERSIST_CHUNK:
+        if (value < 1 || value > 1024 || (value & (value - 1)))
+            return fail(ctx, QW_E_INVALID_ARG, "claim size must be a power of two in 1..1024");
+        ctx->persist_chunk = (uint32_t)value;
+        return QW_OK;
+    case QW_OPT_SPIN_LIMIT:
+        if (value < 0 || value > 0xFFFFFFFFll) return fail(ctx, QW_E_INVALID_ARG, "spin limit must be 0..2^32-1");
+        ctx->spin_limit = (uint32_t)value;
+        return QW_OK;
     case QW_OPT_STREAM_LOADS: ctx->stream_loads = value != 0; return QW_OK;
     case QW_OPT_TILE_ORDER:
         if (value < 0 || value > 2) return fail(ctx, QW_E_INVALID_ARG, "tile order must be 0, 1 or 2");
@@ -1554,7 +1745,7 @@ int qw_ctx_set_option(qw_ctx *ctx, int key, int64_t value) {
         if (ctx->rec) return recording_unsupported(ctx, "a new device memory cap");
         // the context's buffers are released, to grow again within the cap
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream sync");
-        for (DevBuf *b : {&ctx->plan, &ctx->scratch, &ctx->pingpong, &ctx->meas}) {
+        for (DevBuf *b : {&ctx->plan, &ctx->scratch, &ctx->pingpong, &ctx->meas, &ctx->psync}) {
             if (b->p) HIP_TRY(ctx, hipFree(b->p), "free buffer");
             b->p = nullptr;
             b->cap = 0;
@@ -1881,6 +2072,122 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         return expect_slots(ctx, dst->n, slots, epi->x_mask, epi->z_mask, epi->coeff,
                             epi->n_terms, epi->out, epi->out_is_host, fe.active ? &fe.fused : nullptr);
     }
+    return QW_OK;
+}
+
+int qw_run_tree(qw_ctx *ctx, const qw_snap *const *src, const qw_task *tasks, const int32_t *parent,
+                const uint8_t *out_prov, uint32_t n_tasks, qw_state *dst) {
+    if (!ctx || !dst) return ctx ? fail(ctx, QW_E_INVALID_ARG, "null state") : QW_E_INVALID_ARG;
+    if (dst->ctx != ctx) return fail(ctx, QW_E_INVALID_ARG, "state belongs to another context");
+    if (n_tasks > 0 && (!tasks || !parent)) return fail(ctx, QW_E_INVALID_ARG, "tasks or parent == NULL");
+    std::vector<char> seen(dst->n_slots, 0);
+    bool any_parent = false;
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        const uint32_t s = tasks[k].dst_slot;
+        char buf[128];
+        if (s >= dst->n_slots || seen[s] || dst->frozen[s]) {
+            snprintf(buf, sizeof buf, "task %u: dst_slot %u out of range, used twice or frozen", k, s);
+            return fail(ctx, QW_E_INVALID_ARG, buf);
+        }
+        if (tasks[k].reserved != 0) return fail(ctx, QW_E_INVALID_ARG, "task reserved field must be 0");
+        if (tasks[k].n_gates && !tasks[k].gates) return fail(ctx, QW_E_INVALID_ARG, "task gates == NULL");
+        if (has_measure(tasks[k].gates, tasks[k].n_gates))
+            return fail(ctx, QW_E_UNSUPPORTED, "qw_run_tree: gates may not measure or reset");
+        seen[s] = 1;
+        if (parent[k] >= 0) {
+            if ((uint32_t)parent[k] >= k) {
+                snprintf(buf, sizeof buf, "task %u: parent %d does not come before it", k, parent[k]);
+                return fail(ctx, QW_E_INVALID_ARG, buf);
+            }
+            if (src && src[k]) return fail(ctx, QW_E_INVALID_ARG, "a task has both a parent and a snapshot");
+            if (tasks[k].n_gates == 0) return fail(ctx, QW_E_INVALID_ARG, "a task with a parent must have gates");
+            any_parent = true;
+        } else if (parent[k] != -1) {
+            return fail(ctx, QW_E_INVALID_ARG, "parent must be -1 or an earlier task");
+        }
+    }
+    if (any_parent && !out_prov) return fail(ctx, QW_E_INVALID_ARG, "out_prov is required with parents");
+    // legality gates before any device work (Sec. IV-B): snapshot sources as
+    // in qw_run_suffix_batch; an in-call parent's state is an exact
+    // statevector of this context, so only its provenance is checked
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        if (parent[k] >= 0) {
+            if (std::memcmp(out_prov + 32ull * (uint32_t)parent[k], tasks[k].expect_prov, 32) != 0)
+                return fail(ctx, QW_E_REFUSED,
+                            refusal_json("PROVENANCE_MISMATCH", "parent state provenance differs from the task's prefix fingerprint.",
+                                         QW_KIND_STATEVECTOR, QW_KIND_STATEVECTOR, QW_BACKEND_SV, QW_BACKEND_SV, k));
+            continue;
+        }
+        const qw_snap *sn = src ? src[k] : nullptr;
+        if (!sn) continue;
+        std::string js;
+        if (!legal(sn->art, QW_KIND_STATEVECTOR, QW_BACKEND_SV, &js, k)) return fail(ctx, QW_E_REFUSED, js);
+        if (sn->art.n_qubits != dst->n)
+            return fail(ctx, QW_E_REFUSED,
+                        refusal_json("QUBIT_COUNT_MISMATCH", "artifact qubit count differs from the target state.",
+                                     sn->art.kind, QW_KIND_STATEVECTOR, sn->art.backend, QW_BACKEND_SV, k));
+        if (std::memcmp(sn->art.provenance, tasks[k].expect_prov, 32) != 0)
+            return fail(ctx, QW_E_REFUSED,
+                        refusal_json("PROVENANCE_MISMATCH", "artifact provenance hash differs from the task's prefix fingerprint.",
+                                     sn->art.kind, QW_KIND_STATEVECTOR, sn->art.backend, QW_BACKEND_SV, k));
+        if (sn->ctx != ctx) return fail(ctx, QW_E_INVALID_ARG, "snapshot belongs to another context");
+    }
+    ctx->outcomes.clear();
+    std::vector<Exec> ex(n_tasks);
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        ex[k].parent = parent[k];
+        ex[k].dst = slot_ptr(dst, tasks[k].dst_slot);
+        ex[k].src = parent[k] >= 0 ? slot_ptr(dst, tasks[(uint32_t)parent[k]].dst_slot)
+                                   : ((src && src[k]) ? src[k]->data : nullptr);
+        std::string e = get_plan(ctx, dst->n, tasks[k].gates, tasks[k].n_gates, &ex[k].planp, ex[k].src == nullptr,
+                                 layouts_pay(ctx, dst->n, n_tasks));
+        if (!e.empty()) return fail(ctx, QW_E_INVALID_ARG, "task " + std::to_string(k) + ": " + e);
+    }
+    // one persistent launch when it applies to the whole tree (every task in
+    // one execution: no norm passes, generated kernels, second buffers within
+    // the cap, every parent with passes)
+    bool one = ctx->persistent && ctx->jit && n_tasks > 0 && ex[0].planp->m >= kMinTileBits;
+    {
+        const uint64_t state_bytes = 8ull << dst->n;
+        uint64_t relabels = 0;
+        for (const Exec &e : ex) {
+            relabels += has_relabel(*e.planp);
+            for (const HostPass &p : e.planp->passes) one = one && !p.norm_out;
+            if (e.parent >= 0) one = one && !ex[(size_t)e.parent].planp->passes.empty();
+        }
+        one = one && relabels <= std::max<uint64_t>(1, ctx->pingpong_cap / state_bytes);
+    }
+    if (ctx->rec) ctx->rec->calls.emplace_back();
+    if (one || !any_parent) {
+        if (one) return execute_chunk(ctx, dst->n, ex);
+        return execute(ctx, dst->n, ex);
+    }
+    // level by level: a task runs in the execution after its parent's
+    std::vector<uint32_t> depth(n_tasks, 0);
+    uint32_t levels = 0;
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+        if (parent[k] >= 0) depth[k] = depth[(uint32_t)parent[k]] + 1;
+        levels = std::max(levels, depth[k] + 1);
+    }
+    std::vector<GraphSeg> by_task(n_tasks);  // recorded op positions, in task order
+    for (uint32_t d = 0; d < levels; ++d) {
+        std::vector<Exec> lev;
+        std::vector<uint32_t> lev_k;
+        for (uint32_t k = 0; k < n_tasks; ++k)
+            if (depth[k] == d) {
+                lev.push_back(ex[k]);
+                lev.back().parent = -1;
+                lev_k.push_back(k);
+            }
+        int rc = execute(ctx, dst->n, lev);
+        if (rc) return rc;
+        if (ctx->rec) {
+            std::vector<GraphSeg> &got = ctx->rec->calls.back();
+            for (size_t i = 0; i < got.size() && i < lev_k.size(); ++i) by_task[lev_k[i]] = std::move(got[i]);
+            got.clear();
+        }
+    }
+    if (ctx->rec) ctx->rec->calls.back() = std::move(by_task);
     return QW_OK;
 }
 
@@ -2341,6 +2648,39 @@ int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates,
             }
         }
     }
+    // the persistent kernels of such a batch (QW_OPT_PERSISTENT): its pass
+    // structures in pass order, the first reading the snapshot
+    std::vector<std::vector<PersistPart>> pparts;
+    for (int v = 0; v < 4; ++v)
+        for (int stream = 0; stream <= 1; ++stream) {
+            const Plan &pp = pv[v];
+            bool norm = false;
+            for (const HostPass &h : pp.passes) norm |= h.norm_out;
+            if (pp.passes.empty() || norm) continue;
+            std::vector<PersistPart> parts;
+            for (size_t k = 0; k < pp.passes.size(); ++k) {
+                PersistPart q;
+                q.pass = &pp.passes[k];
+                const bool with_epi = fev[v].active && k + 1 == pp.passes.size();
+                q.epi = with_epi ? &fev[v].rplan : nullptr;
+                q.epi_key = with_epi ? &fev[v].key : nullptr;
+                q.n = (int)n;
+                q.m = pp.m;
+                q.stream_loads = stream != 0 && k > 0;
+                parts.push_back(q);
+            }
+            pparts.push_back(std::move(parts));
+        }
+    for (const auto &parts : pparts) {
+        JitReq r;
+        r.key = jit_persist_key(parts);
+        if (!seen.insert(r.key).second) continue;
+        r.persist = &parts;
+        r.n = (int)n;
+        r.m = p.m;
+        r.use_lds = true;
+        reqs.push_back(std::move(r));
+    }
     const FusedEpi &fe = fev[0];
     // the reducer groups of the remaining terms, built as expect_slots builds them
     std::vector<uint32_t> idx;
@@ -2408,12 +2748,13 @@ void end_recording(qw_ctx *ctx, hipGraph_t *graph, std::vector<void *> *owned,
     if (e != hipSuccess) gr = nullptr;
     *graph = gr;
     *owned = std::move(r->owned);
-    for (DevBuf *b : {&ctx->plan, &ctx->scratch, &ctx->pingpong, &ctx->meas})
+    for (DevBuf *b : {&ctx->plan, &ctx->scratch, &ctx->pingpong, &ctx->meas, &ctx->psync})
         if (b->p) owned->push_back(b->p);
     ctx->plan = r->saved_plan;
     ctx->scratch = r->saved_scratch;
     ctx->pingpong = r->saved_pingpong;
     ctx->meas = r->saved_meas;
+    ctx->psync = r->saved_psync;
     ctx->stream = r->saved_stream;
     (void)hipStreamDestroy(r->cap);
     (void)hipStreamDestroy(r->up);
@@ -2452,10 +2793,12 @@ int qw_graph_begin(qw_ctx *ctx) {
     r->saved_scratch = ctx->scratch;
     r->saved_pingpong = ctx->pingpong;
     r->saved_meas = ctx->meas;
+    r->saved_psync = ctx->psync;
     ctx->plan = DevBuf{};
     ctx->scratch = DevBuf{};
     ctx->pingpong = DevBuf{};
     ctx->meas = DevBuf{};
+    ctx->psync = DevBuf{};
     ctx->stream = r->cap;
     ctx->rec = r.release();
     return QW_OK;

@@ -157,6 +157,39 @@ struct alignas(16) PassDesc {
 };
 static_assert(sizeof(PassDesc) == 128, "PassDesc layout");
 
+// Persistent launch of a whole call (every pass of every task, and with
+// in-call parents every level of a task tree): the work is a list of claims
+// taken in increasing order from one device counter. A segment is one pass
+// structure at one pass index: its descriptors are consecutive in the call's
+// descriptor array and each is swept in units (tiles, or rows of
+// red_row_tiles tiles for a pass with an expectation epilogue), `chunk`
+// units per claim.
+struct alignas(16) PSeg {
+    uint32_t claim0;       // first claim of the segment
+    uint32_t n_claims;
+    uint32_t desc0;        // index of its first descriptor
+    uint32_t n_descs;
+    uint32_t chunk;        // units per claim (divides units)
+    uint32_t kind;         // pass structure (case of the generated kernel)
+    uint32_t tmaj;         // 1: one descriptor's claims are consecutive
+    uint32_t units;        // units per descriptor
+};
+static_assert(sizeof(PSeg) == 32, "PSeg layout");
+
+// Dependency of one descriptor of a persistent launch: its sweep starts when
+// the completion counter of descriptor `dep` has reached `need` units (the
+// pass before it, or the last pass of the parent task). dep = kNoDep: none.
+constexpr uint32_t kNoDep = 0xFFFFFFFFu;
+struct alignas(8) PDep {
+    uint32_t dep;
+    uint32_t need;
+};
+
+// Words of a persistent launch's synchronisation area (cleared by a kernel
+// before the launch): the claim counter, the abandon flag, then one
+// completion counter per descriptor.
+constexpr uint32_t kSyncClaim = 0, kSyncAbort = 1, kSyncCounters = 2;
+
 // Expectation partials are kept per row of kRedRowTiles consecutive tiles of
 // a state (all of its tiles when it has fewer): each thread adds its FP32
 // term values over the row's tiles, in tile order, before the FP64 sum

@@ -697,32 +697,20 @@ std::string jit_epilogue_key(int n, int m, const HostPass &p, const RedPlan &epi
     return "E" + jit_reduce_key(n, m, g, epi);
 }
 
-std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch,
-                            const RedPlan *epi, bool stream_loads) {
-    Gen g;
-    const int T = 1 << (m - 4);
-    const int WG = T < 256 ? T : 256;
-    g << "// generated pass kernel: " << n << " qubits, tile bits " << m << ", " << p.dev_ops.size()
-      << " op records, " << p.dev_phases.size() << " phases, "
-      << (use_lds ? "persistent LDS form" : "flat form") << "\n";
-    g << "#define QW_ST_AUX 2\n";
-    if (stream_loads) g << "#define QW_LD_AUX 2\n";
-    g << "#include \"qw_dev.h\"\nusing namespace qw;\n";
-    g << "constexpr int M = " << m << ", T = " << T << ", WG = " << WG << ", PARTS = T / WG;\n";
+// Definitions of one pass structure, shared by its own kernel and by the
+// persistent kernel of a call: I/O address helpers, the loads (all 16
+// registers; the first `PF` of a tile ahead; the rest), the store, the body
+// and, with an epilogue, its term evaluation. Returns the number of hoisted
+// diagonal sets (the size of the per-thread factor array).
+static size_t emit_pass_defs(Gen &g, int n, int m, const HostPass &p, bool use_lds, int PF,
+                             const RedPlan *epi) {
     emit_io_helpers(g, "io_in", p.io_in, m);
     emit_io_helpers(g, "io_out", p.io_out, m);
-    const bool remap = p.moves();
-    // persistent form: registers [0, PF) of the next tile are loaded while
-    // the current one is worked on, the rest when it starts
-    const int PF = use_lds ? prefetch : 0;
     emit_load(g, p.io_in, "load_in", 0, 16);
     emit_load(g, p.io_in, "load_pre", 0, PF);
     emit_load(g, p.io_in, "load_rest", PF, 16);
-    emit_store(g, p.io_out, remap, m);
-    // output base of the tile: the relabelled one, or the load base
-    const char *obase = remap ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
+    emit_store(g, p.io_out, p.moves(), m);
     const Hoisted hs = hoisted_sets(p);
-    const size_t K = hs.op.size();
     g << emit_body(m, p, hs, use_lds && !epi);
     if (epi) {
         // fused expectation epilogue: the tile's terms, evaluated after the
@@ -737,6 +725,28 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
         e << "};\n";
         g << e.str();
     }
+    return hs.op.size();
+}
+
+std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int prefetch,
+                            const RedPlan *epi, bool stream_loads) {
+    Gen g;
+    const int T = 1 << (m - 4);
+    const int WG = T < 256 ? T : 256;
+    g << "// generated pass kernel: " << n << " qubits, tile bits " << m << ", " << p.dev_ops.size()
+      << " op records, " << p.dev_phases.size() << " phases, "
+      << (use_lds ? "persistent LDS form" : "flat form") << "\n";
+    g << "#define QW_ST_AUX 2\n";
+    if (stream_loads) g << "#define QW_LD_AUX 2\n";
+    g << "#include \"qw_dev.h\"\nusing namespace qw;\n";
+    g << "constexpr int M = " << m << ", T = " << T << ", WG = " << WG << ", PARTS = T / WG;\n";
+    const bool remap = p.moves();
+    // persistent form: registers [0, PF) of the next tile are loaded while
+    // the current one is worked on, the rest when it starts
+    const int PF = use_lds ? prefetch : 0;
+    // output base of the tile: the relabelled one, or the load base
+    const char *obase = remap ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
+    const size_t K = emit_pass_defs(g, n, m, p, use_lds, PF, epi);
     if (!use_lds) {
         g << "extern \"C\" __global__ __launch_bounds__(WG) void qw_pass(const PassDesc *__restrict__ "
              "descs, uint32_t n_descs, uint32_t items, int remap, uint32_t tmaj) {\n"
@@ -893,6 +903,192 @@ std::string jit_pass_source(int n, int m, const HostPass &p, bool use_lds, int p
         g << "    }\n"
              "}\n";
     }
+    return g.o.str();
+}
+
+
+// ---------------------------------------------------------- persistent
+std::string jit_persist_key(const std::vector<PersistPart> &parts) {
+    std::string k = "P";
+    for (const PersistPart &q : parts) {
+        const std::string e = q.epi_key ? *q.epi_key : std::string();
+        const std::string pk = jit_pass_key(q.n, q.m, *q.pass, true) + e;
+        const uint32_t len = (uint32_t)pk.size();
+        k.append(reinterpret_cast<const char *>(&len), sizeof len);
+        k += pk;
+        k.push_back(q.stream_loads ? 'S' : 'T');
+    }
+    return k;
+}
+
+std::string jit_persist_source(const std::vector<PersistPart> &parts, int prefetch) {
+    Gen g;
+    const int n = parts[0].n, m = parts[0].m;
+    const int T = 1 << (m - 4);
+    bool all_stream = true;
+    size_t red_words = T / 64 + 1;
+    for (const PersistPart &q : parts) {
+        all_stream &= q.stream_loads;
+        if (q.epi) red_words = std::max(red_words, (size_t)(T / 64) * q.epi->cols.size() + 1);
+    }
+    g << "// generated persistent kernel: " << n << " qubits, tile bits " << m << ", " << parts.size()
+      << " pass structures\n";
+    g << "#define QW_ST_AUX 2\n";
+    if (all_stream) g << "#define QW_LD_AUX 2\n";
+    g << "#include \"qw_dev.h\"\nusing namespace qw;\n";
+    g << "constexpr int M = " << m << ", T = " << T << ";\n";
+    g << "__shared__ float2 qw_lds[1 << M];\n__shared__ double qw_red[" << red_words << "];\n";
+    const int PF = prefetch;
+    for (size_t s = 0; s < parts.size(); ++s) {
+        const PersistPart &q = parts[s];
+        const HostPass &p = *q.pass;
+        g << "namespace s" << s << " {\n";
+        const size_t K = emit_pass_defs(g, n, m, p, true, PF, q.epi);
+        const char *obase = p.moves() ? "uni(ldu(ldu(&d->tile_base_out) + tile))" : "base";
+        // units [u0, u1) of one descriptor (tiles, or rows of RT tiles), the
+        // first PF registers of each next tile loaded during the current one
+        g << "__device__ __forceinline__ void run(const PassDesc *__restrict__ d, uint32_t u0, uint32_t u1) {\n"
+             "    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = uni(tid >> 6);\n"
+             "    const uint64_t wi = io_in_wave(wave), wo = io_out_wave(wave), wx = io_out_wxor(wave);\n"
+             "    const uint32_t li = io_in_lane(lane), lo = io_out_lane(lane);\n"
+             "    char *lb = reinterpret_cast<char *>(qw_lds);\n"
+             "    double *red = qw_red;\n"
+             "    (void)red;\n"
+             "    const void *src = ldu(&d->src);\n"
+             "    void *dst = ldu(&d->dst);\n"
+             "    const uint32_t *tb = ldu(&d->tile_base);\n";
+        if (q.epi)
+            g << "    const uint32_t t0 = u0 * RT, t1 = u1 * RT;\n"
+                 "    float acc[ENT];\n"
+                 "    #pragma unroll\n"
+                 "    for (int i = 0; i < ENT; ++i) acc[i] = 0.f;\n";
+        else
+            g << "    const uint32_t t0 = u0, t1 = u1;\n";
+        g << "    float2 ftc[" << std::max<size_t>(1, K) << "];\n";
+        if (K) g << "    dset_factors(ftc, ldu(&d->ops), tid);\n";
+        g << "    float2 nv[" << std::max(1, PF) << "];\n"
+             "    load_pre(nv, src, uni(ldu(tb + t0)) | wi, li);\n"
+             "    for (uint32_t tile = t0; tile < t1; ++tile) {\n"
+             "        float2 v[16];\n"
+             "        #pragma unroll\n"
+             "        for (int k = 0; k < " << PF << "; ++k) v[k] = nv[k];\n"
+             "        const uint64_t base = uni(ldu(tb + tile));\n"
+             "        {\n"
+             "            float2 rest[" << std::max(1, 16 - PF) << "];\n"
+             "            load_rest(rest, src, base | wi, li);\n"
+             "            #pragma unroll\n"
+             "            for (int k = " << PF << "; k < 16; ++k) v[k] = rest[k - " << PF << "];\n"
+             "        }\n"
+             "        if (tile + 1u < t1) load_pre(nv, src, uni(ldu(tb + tile + 1u)) | wi, li);\n";
+        if (p.scale_in) g << kScaleIn;
+        g << "        body(v, ldu(&d->ops), tid, lane, base, lb, ftc);\n"
+             "        store_out(v, dst, ((uint64_t)" << obase << " ^ wx) | wo, lo);\n";
+        if (q.epi)
+            g << "        epi_tile(v, tid, lane, base, lb, acc);\n"
+                 "        if ((tile + 1u) % RT == 0u) {\n"
+                 "            epi_tile_flush(acc, lane, wave, red);\n"
+                 "            __syncthreads();\n"
+                 "            double *part = ldu(&d->red_part) + (uint64_t)(tile / RT) * ldu(&d->red_nt);\n"
+                 "            for (uint32_t c = tid; c < (uint32_t)ENT; c += T) {\n"
+                 "                double sum = 0.0;\n"
+                 "                for (int ww = 0; ww < T / 64; ++ww) sum += red[ww * ENT + c];\n"
+                 "                gout<double>(part)[kECols[c]] = sum;\n"
+                 "            }\n"
+                 "        }\n";
+        g << "    }\n}\n}  // namespace s" << s << "\n";
+    }
+    // The claim loop. Claims are taken in increasing order from one counter
+    // and a claim only waits for descriptors of earlier claims, so the
+    // earliest unfinished claim never waits: the launch completes whether or
+    // not all its workgroups are resident at once. A wait is bounded in time
+    // (spin_limit microseconds of the 100 MHz real-time counter) and ends
+    // early when another workgroup has abandoned the launch or the host has
+    // set host_flag[0]; an abandoned launch skips all further claims and
+    // sets host_flag[1].
+    // Wave 0 claims, waits and releases as a whole (a branch on the wave
+    // index, every lane active, one lane's value counted in each atomic):
+    // no lane-divergent region may enclose or follow the workgroup barriers
+    // of the loop, or the compiler may let the other lanes of wave 0 go
+    // round the barriers while its claiming lane waits to run.
+    g << "__device__ __forceinline__ uint32_t seg_of(const PSeg *__restrict__ segs, uint32_t n_segs, uint32_t c) {\n"
+         "    uint32_t lo = 0u, hi = n_segs;\n"
+         "    while (hi - lo > 1u) {\n"
+         "        const uint32_t mid = (lo + hi) >> 1;\n"
+         "        if (ldu(&segs[mid].claim0) <= c) lo = mid; else hi = mid;\n"
+         "    }\n"
+         "    return lo;\n"
+         "}\n"
+         "__device__ __forceinline__ void claim_desc(const PSeg *__restrict__ sg, uint32_t c, uint32_t *gi, uint32_t *u0) {\n"
+         "    const uint32_t lc = c - ldu(&sg->claim0), chunk = ldu(&sg->chunk);\n"
+         "    const uint32_t per = ldu(&sg->units) / chunk, nd = ldu(&sg->n_descs);\n"
+         "    const uint32_t dl = ldu(&sg->tmaj) ? lc / per : lc % nd;\n"
+         "    const uint32_t ul = ldu(&sg->tmaj) ? lc % per : lc / nd;\n"
+         "    *gi = ldu(&sg->desc0) + dl;\n"
+         "    *u0 = ul * chunk;\n"
+         "}\n";
+    g << "extern \"C\" __global__ __launch_bounds__(T) void qw_persist(const PSeg *__restrict__ segs, uint32_t n_segs, "
+         "const PassDesc *__restrict__ descs, const PDep *__restrict__ deps, uint32_t *sync, uint32_t claims, "
+         "uint32_t spin_limit, uint32_t *host_flag) {\n"
+         "    __shared__ uint32_t s_claim;\n"
+         "    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = uni(tid >> 6);\n"
+         "    const uint32_t one = lane == 0u ? 1u : 0u;\n"
+         "    uint32_t done_gi = kNoDep, done_units = 0u;   // the claim just finished (wave 0)\n"
+         "    while (true) {\n"
+         "        // every wave's stores of the finished claim have completed\n"
+         "        __builtin_amdgcn_s_waitcnt(0);\n"
+         "        __syncthreads();\n"
+         "        if (wave == 0u) {\n"
+         "            if (done_gi != kNoDep) {\n"
+         "                __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"agent\");\n"
+         "                __hip_atomic_fetch_add(&sync[kSyncCounters + done_gi], one * done_units, __ATOMIC_RELAXED,\n"
+         "                                       __HIP_MEMORY_SCOPE_AGENT);\n"
+         "            }\n"
+         "            uint32_t c = claims;\n"
+         "            if (uni(__hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u)\n"
+         "                c = uni(__hip_atomic_fetch_add(&sync[kSyncClaim], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));\n"
+         "            if (c < claims) {\n"
+         "                uint32_t gi, u0;\n"
+         "                claim_desc(segs + seg_of(segs, n_segs, c), c, &gi, &u0);\n"
+         "                const uint32_t dep = ldu(&deps[gi].dep), need = ldu(&deps[gi].need);\n"
+         "                if (dep != kNoDep) {\n"
+         "                    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();\n"
+         "                    const uint64_t limit = (uint64_t)spin_limit * 100ull;\n"
+         "                    while (uni(__hip_atomic_load(&sync[kSyncCounters + dep], __ATOMIC_RELAXED,\n"
+         "                                                 __HIP_MEMORY_SCOPE_AGENT)) < need) {\n"
+         "                        const bool give_up =\n"
+         "                            __builtin_amdgcn_s_memrealtime() - t0 >= limit ||\n"
+         "                            uni(__hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u ||\n"
+         "                            uni(__hip_atomic_load(&host_flag[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0u;\n"
+         "                        if (give_up) {\n"
+         "                            __hip_atomic_fetch_or(&sync[kSyncAbort], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
+         "                            __hip_atomic_fetch_or(&host_flag[1], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);\n"
+         "                            c = claims;\n"
+         "                            break;\n"
+         "                        }\n"
+         "                        __builtin_amdgcn_s_sleep(2);\n"
+         "                    }\n"
+         "                    // the producers' stores, released before their counter updates\n"
+         "                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"agent\");\n"
+         "                }\n"
+         "            }\n"
+         "            s_claim = c;   // the same value from every lane of wave 0\n"
+         "        }\n"
+         "        __syncthreads();\n"
+         "        const uint32_t c = uni(s_claim);\n"
+         "        if (c >= claims) break;\n"
+         "        const PSeg *sg = segs + seg_of(segs, n_segs, c);\n"
+         "        uint32_t gi, u0;\n"
+         "        claim_desc(sg, c, &gi, &u0);\n"
+         "        const uint32_t u1 = u0 + ldu(&sg->chunk);\n"
+         "        switch (ldu(&sg->kind)) {\n";
+    for (size_t s = 0; s < parts.size(); ++s)
+        g << "        case " << s << "u: s" << s << "::run(descs + gi, u0, u1); break;\n";
+    g << "        default: break;\n"
+         "        }\n"
+         "        done_gi = gi;\n"
+         "        done_units = u1 - u0;\n"
+         "    }\n"
+         "}\n";
     return g.o.str();
 }
 
@@ -1296,6 +1492,18 @@ long code_scratch_bytes(const std::vector<char> &code, const char *name) {
 
 }  // namespace
 
+namespace {
+// Kernel source of a request with `prefetch` registers of the next tile.
+std::string req_source(const JitReq &r, int prefetch) {
+    if (r.persist) return jit_persist_source(*r.persist, prefetch);
+    if (r.pass) return jit_pass_source(r.n, r.m, *r.pass, r.use_lds, prefetch, r.epi, r.stream_loads);
+    return jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
+}
+const char *req_kernel_name(const JitReq &r) {
+    return r.persist ? "qw_persist" : (r.pass ? "qw_pass" : "qw_reduce");
+}
+}  // namespace
+
 bool jit_available(int device, const JitReq &r) {
     Registry &R = reg();
     {
@@ -1304,8 +1512,7 @@ bool jit_available(int device, const JitReq &r) {
     }
     const std::string dir = cache_dir();
     if (dir.empty()) return false;
-    const std::string src = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi, r.stream_loads)
-                                   : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
+    const std::string src = req_source(r, 16);
     struct stat sb;
     return ::stat(cache_path(dir, src).c_str(), &sb) == 0;
 }
@@ -1330,8 +1537,7 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
     const char *dump = std::getenv("QW_JIT_DUMP");  // debugging: write sources to this folder
     for (size_t q = 0; q < need.size(); ++q) {
         const JitReq &r = ks[need[q]];
-        srcs[q] = r.pass ? jit_pass_source(r.n, r.m, *r.pass, r.use_lds, 16, r.epi, r.stream_loads)
-                         : jit_reduce_source(r.n, r.m, *r.group, *r.rplan);
+        srcs[q] = req_source(r, 16);
         if (dump && *dump) {
             std::ofstream f(cache_path(dump, srcs[q]) + ".hip");
             f << srcs[q];
@@ -1351,13 +1557,15 @@ std::string jit_precompile(const std::vector<JitReq> &ks) {
             // next tile spills, prefetch half of it, else none (stored under
             // the identity of the requested source)
             const JitReq &r = ks[need[q]];
-            if (errs[q].empty() && r.pass && r.use_lds && code_scratch_bytes(codes[q], "qw_pass") > 0) {
+            const char *kname = req_kernel_name(r);
+            if (errs[q].empty() && ((r.pass && r.use_lds) || r.persist) &&
+                code_scratch_bytes(codes[q], kname) > 0) {
                 for (int pf : {8, 0}) {
                     std::vector<char> c2;
-                    const std::string e2 = compile_one(jit_pass_source(r.n, r.m, *r.pass, true, pf, r.epi, r.stream_loads), &c2);
+                    const std::string e2 = compile_one(req_source(r, pf), &c2);
                     if (!e2.empty()) break;
                     codes[q].swap(c2);
-                    if (code_scratch_bytes(codes[q], "qw_pass") == 0) break;
+                    if (code_scratch_bytes(codes[q], kname) == 0) break;
                 }
             }
             const auto t1 = std::chrono::steady_clock::now();
@@ -1418,12 +1626,12 @@ std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<con
         }
         const std::vector<char> &code = R.code[ks[i].key];
         const int m = ks[i].m;
-        const bool use_lds = ks[i].use_lds || !ks[i].pass;
+        const bool use_lds = ks[i].use_lds || !ks[i].pass || ks[i].persist;
         hipModule_t mod = nullptr;
         hipError_t e = hipModuleLoadData(&mod, code.data());
         if (e != hipSuccess) return std::string("hipModuleLoadData: ") + hipGetErrorString(e);
         auto k = std::make_unique<JitKernel>();
-        e = hipModuleGetFunction(&k->fn, mod, ks[i].pass ? "qw_pass" : "qw_reduce");
+        e = hipModuleGetFunction(&k->fn, mod, req_kernel_name(ks[i]));
         if (e != hipSuccess) return std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
         const int T = 1 << (m - 4);
         k->use_lds = use_lds;
@@ -1431,7 +1639,7 @@ std::string jit_get(int device, const std::vector<JitReq> &reqs, std::vector<con
         k->wg = use_lds ? T : (T < 256 ? T : 256);
         k->parts = use_lds ? 1 : T / k->wg;
         k->blocks_per_cu = 1;
-        if (!ks[i].pass || ks[i].epi) k->row_tiles = (int)red_row_tiles(1u << (ks[i].n - m));
+        if ((!ks[i].pass && !ks[i].persist) || ks[i].epi) k->row_tiles = (int)red_row_tiles(1u << (ks[i].n - m));
         if (use_lds) {
             int nb = 0;
             if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, k->wg, 0) == hipSuccess &&
@@ -1482,6 +1690,14 @@ hipError_t jit_launch_reduce(hipStream_t st, const JitKernel &k, const ReduceDes
     if (grid < 8u) grid = 8u;
     uint32_t items_arg = items;
     void *args[] = {&descs, &n_descs, &items_arg, &tmaj};
+    return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
+}
+
+hipError_t jit_launch_persist(hipStream_t st, const JitKernel &k, const PSeg *segs, uint32_t n_segs,
+                              const PassDesc *descs, const PDep *deps, uint32_t *sync, uint32_t claims,
+                              uint32_t grid, uint32_t spin_limit, uint32_t *host_flag) {
+    if (grid == 0u) grid = 1u;
+    void *args[] = {&segs, &n_segs, &descs, &deps, &sync, &claims, &spin_limit, &host_flag};
     return hipModuleLaunchKernel(k.fn, grid, 1, 1, (uint32_t)k.wg, 1, 1, 0, st, args, nullptr);
 }
 

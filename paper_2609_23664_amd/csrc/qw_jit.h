@@ -53,10 +53,25 @@ struct JitKernel {
 std::string jit_reduce_key(int n, int m, const TermGroup &g, const RedPlan &rp);
 std::string jit_reduce_source(int n, int m, const TermGroup &g, const RedPlan &rp);
 
-// One requested kernel: its key and what it was computed from (a pass, or a
-// reducer term group).
+// One pass structure of a persistent kernel (all of one m and n).
+struct PersistPart {
+    const HostPass *pass = nullptr;
+    const RedPlan *epi = nullptr;          // fused expectation epilogue
+    const std::string *epi_key = nullptr;  // its key suffix
+    int n = 0, m = 0;
+    bool stream_loads = true;
+};
+
+// Key and source of the persistent kernel of a call: every listed pass
+// structure in one code object, dispatched per claim (see PSeg).
+std::string jit_persist_key(const std::vector<PersistPart> &parts);
+std::string jit_persist_source(const std::vector<PersistPart> &parts, int prefetch = 16);
+
+// One requested kernel: its key and what it was computed from (a pass, a
+// reducer term group, or the pass structures of a persistent kernel).
 struct JitReq {
     std::string key;
+    const std::vector<PersistPart> *persist = nullptr;
     const HostPass *pass = nullptr;
     const TermGroup *group = nullptr;
     const RedPlan *rplan = nullptr;
@@ -87,6 +102,13 @@ std::string jit_precompile(const std::vector<JitReq> &reqs);
 // descriptor (else the descriptors of one tile) as consecutive items.
 hipError_t jit_launch(hipStream_t st, const JitKernel &k, const PassDesc *descs, uint32_t n_descs,
                       uint32_t tiles, int remap, uint32_t cu_count, bool tile_major);
+
+// Launch a persistent kernel over `claims` claims of n_segs segments on
+// `grid` workgroups (see PSeg, PDep; sync holds kSyncCounters + descriptor
+// count words, zero at launch).
+hipError_t jit_launch_persist(hipStream_t st, const JitKernel &k, const PSeg *segs, uint32_t n_segs,
+                              const PassDesc *descs, const PDep *deps, uint32_t *sync, uint32_t claims,
+                              uint32_t grid, uint32_t spin_limit, uint32_t *host_flag);
 
 // Number of generated kernels compiled (not loaded from cache) and seconds
 // spent compiling, since the process started.

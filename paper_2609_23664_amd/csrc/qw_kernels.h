@@ -72,6 +72,8 @@ hipError_t launch_meas_decide(hipStream_t st, const uint32_t *task_first, const 
                               uint32_t bin_stride, float *dyn, uint8_t *outc, uint32_t *err);
 // *err = 0 (a kernel, so that it can be recorded in a graph).
 hipError_t launch_meas_clear(hipStream_t st, uint32_t *err);
+// p[0 .. count) = 0 (a kernel, so that it can be recorded in a graph).
+hipError_t launch_zero_words(hipStream_t st, uint32_t *p, uint64_t count);
 // Dense export of a stabilizer state into psi (2^n amplitudes): x0, r X-type
 // generators (device arrays xs, zs, ph = i-power, piv = pivot qubit), norm =
 // 2^{-r/2}. r <= 64.

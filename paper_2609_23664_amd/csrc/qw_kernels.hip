@@ -1417,6 +1417,12 @@ __global__ void meas_clear_kernel(uint32_t *err) {
     if (threadIdx.x == 0) *err = 0u;
 }
 
+__global__ void zero_words_kernel(uint32_t *p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 }  // namespace
 
 hipError_t launch_meas_decide(hipStream_t st, const uint32_t *task_first, const uint32_t *task_count,
@@ -1430,6 +1436,13 @@ hipError_t launch_meas_decide(hipStream_t st, const uint32_t *task_first, const 
 
 hipError_t launch_meas_clear(hipStream_t st, uint32_t *err) {
     hipLaunchKernelGGL(meas_clear_kernel, dim3(1), dim3(64), 0, st, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(hipStream_t st, uint32_t *p, uint64_t count) {
+    if (count == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_words_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, p, count);
     return hipGetLastError();
 }
 

@@ -589,12 +589,18 @@ class RecordedWorkload:
 
 
 def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, terms=None,
-                    shots: int = 0, seed: int = 0, mode: str = "plan") -> RecordedWorkload:
+                    shots: int = 0, seed: int = 0, mode: str = "plan",
+                    tree: bool = False) -> RecordedWorkload:
     """Record the execution of `plan` ("plan": materialized nodes level by
     level, then every task's suffix from its anchor; "direct": every task
     from |0...0> with the same segment cuts) as one graph. Planning,
     fingerprints, legality gates and plan uploads happen here, once; a
-    replay is device work only. The caller replays it, then reads results()."""
+    replay is device work only. The caller replays it, then reads results().
+
+    `tree` ("plan" mode): the materialized nodes and the tasks' suffixes are
+    one qw_run_tree call (each from its nearest materialized ancestor), a
+    single persistent kernel launch when the context has QW_OPT_PERSISTENT;
+    expectations then come from a reducer sweep after it."""
     from . import binding as B
     torch = ctx.torch
     nodes = plan.nodes
@@ -647,6 +653,42 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                     B.run_suffix_batch(ctx, None, batch, st, dsts, terms=terms if last else None,
                                        out_dev=rw.exp_dev if last else None)
                     fused = fused or last
+        elif tree and all(len(tasks[t]) > (nodes[plan.anchor[t]].end if plan.anchor[t] is not None else 0)
+                          for t in range(T)):
+            # one tree call: materialized nodes (parents first, the ones with
+            # no materialized ancestor in the first slots, so that one reset
+            # clears them), then the tasks
+            order = sorted(mats, key=lambda v: (bool(anchor_chain(nodes[v].parent)), nodes[v].depth))
+            idx = {vid: i for i, vid in enumerate(order)}
+            slot_of.clear()
+            slot_of.update(idx)
+            gl, parents, dsts, eprov, oprov = [], [], [], [], []
+            for vid in order:
+                chain = anchor_chain(nodes[vid].parent)
+                a = chain[-1] if chain else None
+                b0 = nodes[a].end if a is not None else 0
+                gl.append(plan.segment_array(tasks, nodes[vid].tasks[0], b0, nodes[vid].end))
+                parents.append(idx[a] if a is not None else -1)
+                dsts.append(slot_of[vid])
+                eprov.append(oprov[idx[a]] if a is not None else bytes(32))
+                oprov.append(fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end]))
+            for t in range(T):
+                a = plan.anchor[t]
+                b0 = nodes[a].end if a is not None else 0
+                gl.append(plan.segment_array(tasks, t, b0, len(tasks[t])))
+                parents.append(idx[a] if a is not None else -1)
+                dsts.append(task_slots[t])
+                eprov.append(oprov[idx[a]] if a is not None else bytes(32))
+                oprov.append(fingerprint(n, tasks[t]))
+            roots = sorted(d for k, d in enumerate(dsts) if parents[k] < 0)
+            i = 0
+            while i < len(roots):   # one reset per run of consecutive slots
+                j = i + 1
+                while j < len(roots) and roots[j] == roots[j - 1] + 1:
+                    j += 1
+                st.reset(roots[i], j - i)
+                i = j
+            B.run_tree(ctx, None, gl, parents, st, dsts, expect_provs=eprov, out_provs=oprov)
         else:
             snaps: Dict[int, object] = {}
             by_depth: Dict[int, List[int]] = {}

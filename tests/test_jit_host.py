@@ -59,3 +59,18 @@ def test_relabel_kernels_compile(n, tile, seed):
     gates = _ladder_circuit(n, np.random.default_rng(7100 + seed), 3)
     assert any(p["out_cx"] for p in B.plan_describe(n, gates, tile)["passes"])
     B.jit_precompile(n, gates, tile)
+
+
+@pytest.mark.parametrize("n,tile,layers", [(16, 12, 2), (18, 14, 3)])
+def test_persistent_kernel_compiles(n, tile, layers):
+    """The persistent kernel of a suffix batch (every pass structure of the
+    batch, with the fused epilogue, in one code object) compiles on the host
+    together with the per-pass kernels; a second request is served from the
+    caches."""
+    w = gen.small_vqe(n, 1, layers, 2, 12, seed=900 + n)
+    s0 = B.jit_stats()
+    B.jit_precompile_suffix(n, w.suffixes[0], w.terms, tile)
+    s1 = B.jit_stats()
+    assert s1["compiled"] + s1["disk_hits"] > s0["compiled"] + s0["disk_hits"]
+    B.jit_precompile_suffix(n, w.suffixes[1], w.terms, tile)
+    assert B.jit_stats()["compiled"] == s1["compiled"]
