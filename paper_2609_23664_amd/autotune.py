@@ -12,7 +12,12 @@ chosen here by measurement on the device:
   relabelling passes, tile-major always);
 * output relabelling of trailing non-local CNOTs (QW_OPT_RELABEL);
 * the cache policy of the passes' state loads (QW_OPT_STREAM_LOADS:
-  non-temporal or default).
+  non-temporal or default);
+* the launch form (QW_OPT_PERSISTENT): one kernel launch per pass structure
+  and pass index, or the whole planned execution (every prefix-tree level
+  and every task's suffix) as one qw_run_tree call in one persistent kernel
+  launch. It is timed second, under the best options of the first four, as
+  one more candidate; both forms compute bitwise the same states.
 
 Each candidate is recorded as a graph (``planner.record_workload``) with
 generated kernels, replayed a few times, and timed with device events; the
@@ -69,13 +74,17 @@ def apply_choice(ctx, choice: Dict[str, int]) -> None:
     ctx.set_option(B.QW_OPT_TILE_ORDER, choice["tile_order"])
     ctx.set_option(B.QW_OPT_RELABEL, choice["relabel"])
     ctx.set_option(B.QW_OPT_STREAM_LOADS, choice.get("stream_loads", 1))
+    ctx.set_option(B.QW_OPT_PERSISTENT, choice.get("persistent", 0))
 
 
 def autotune(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan, terms=None, shots: int = 0,
              seed: int = 0, space: Optional[Dict[str, Sequence[int]]] = None, reps: int = 3,
-             use_cache: bool = True) -> TuneResult:
+             use_cache: bool = True, persistent: bool = True) -> TuneResult:
     """Time every candidate of `space` on the planned workload and return the
-    fastest. The context's options are left at the chosen values."""
+    fastest (with `persistent`, the best one is also timed as one persistent
+    launch). The context's options are left at the chosen values; a caller
+    that records the workload itself passes tree=bool(choice["persistent"])
+    to planner.record_workload."""
     from . import binding as B
     from .planner import record_workload
     torch = ctx.torch
@@ -91,11 +100,13 @@ def autotune(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan, terms=None, sho
     rows = []
     space.setdefault("stream_loads", (1,))
     names = ("tile_bits", "tile_order", "relabel", "stream_loads")
-    for vals in itertools.product(*(space[k] for k in names)):
-        choice = dict(zip(names, vals))
+    cands = [dict(zip(names, vals), persistent=0) for vals in itertools.product(*(space[k] for k in names))]
+
+    def time_one(choice):
         apply_choice(ctx, choice)
         t0 = time.perf_counter()
-        rw = record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed, mode="plan")
+        rw = record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed, mode="plan",
+                             tree=bool(choice["persistent"]))
         rec_s = time.perf_counter() - t0
         try:
             rw.replay()  # warm
@@ -112,9 +123,15 @@ def autotune(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan, terms=None, sho
             rw.free()
         ms.sort()
         rows.append({**choice, "record_s": round(rec_s, 3), "replay_ms": round(ms[len(ms) // 2], 4)})
+
+    for choice in cands:
+        time_one(choice)
+    if persistent:
+        best = min(rows, key=lambda r: r["replay_ms"])
+        time_one({**{k: best[k] for k in names}, "persistent": 1})
     ctx.set_option(B.QW_OPT_JIT, 1)
     best = min(rows, key=lambda r: r["replay_ms"])
-    choice = {k: best[k] for k in names}
+    choice = {k: best[k] for k in names + ("persistent",)}
     apply_choice(ctx, choice)
     res = TuneResult(choice, rows, time.perf_counter() - t_all, False)
     if use_cache:

@@ -191,7 +191,7 @@ def test_recording_refuses_host_calls(ctx):
 
 
 def test_autotuner_choice_and_results(ctx):
-    say("autotune trie 16q 8 leaves, 4 candidates")
+    say("autotune trie 16q 8 leaves, 4 candidates + the best one as a persistent launch")
     import torch
     from paper_2609_23664_amd import autotune as A
     from paper_2609_23664_amd import binding as B
@@ -202,8 +202,9 @@ def test_autotuner_choice_and_results(ctx):
     plan = P.plan_workload(w.n, tasks)
     space = {"tile_bits": (12, 14), "tile_order": (0, 2), "relabel": (1,)}
     r = A.autotune(c2, w.n, tasks, plan, shots=64, seed=3, space=space, reps=2)
-    assert len(r.table) == 4 and not r.cached
-    assert r.choice in [{k: row[k] for k in ("tile_bits", "tile_order", "relabel", "stream_loads")}
+    assert len(r.table) == 5 and not r.cached
+    assert [row["persistent"] for row in r.table] == [0, 0, 0, 0, 1]
+    assert r.choice in [{k: row[k] for k in ("tile_bits", "tile_order", "relabel", "stream_loads", "persistent")}
                         for row in r.table]
     best = min(row["replay_ms"] for row in r.table)
     assert [row for row in r.table if row["replay_ms"] == best][0]["tile_bits"] == r.choice["tile_bits"]

@@ -246,3 +246,48 @@ def test_config3_full_size_persistent_graph(ctx):
         assert np.array_equal(stp[k].view(np.uint32), std[k].view(np.uint32)), k
         ref = oracle.simulate(w.n, tasks[k])
         assert 1 - oracle.fidelity(stp[k].astype(np.complex128), ref) <= FID_TOL, k
+
+
+def test_persistent_graph_takes_next_iteration_gates(ctx):
+    say("persistent suffix batch recorded, new angles through qw_graph_update_gates")
+    import torch
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd.planner import fingerprint
+    w = gen.small_vqe(17, 2, 2, 5, 10, seed=71)
+    w2 = gen.small_vqe(17, 2, 2, 5, 10, seed=72)   # same gate kinds and qubits, other angles
+    st = B.State(ctx, w.n, w.n_tasks + 1)
+    slots = list(range(1, w.n_tasks + 1))
+
+    def calls(gw, out_dev=None):
+        st.reset(0, 1)
+        st.apply(0, gw.prefix)
+        snap = st.snapshot(0, fingerprint(w.n, gw.prefix), B.QW_SNAP_FREEZE)
+        e = B.run_suffix_batch(ctx, [snap] * w.n_tasks, gw.suffixes, st, slots, terms=w.terms,
+                               out_dev=out_dev)
+        return snap, e
+
+    snap, e2 = calls(w2)            # per-pass launches, the new angles
+    ref2 = [st.host(t + 1) for t in range(w.n_tasks)]
+    snap.free()
+    out = torch.zeros(w.n_tasks, dtype=torch.float64, device="cuda")
+    ctx.set_option(B.QW_OPT_PERSISTENT, 1)
+    try:
+        ctx.begin_graph()
+        snap, _ = calls(w, out_dev=out)
+        g = ctx.end_graph()
+    finally:
+        ctx.set_option(B.QW_OPT_PERSISTENT, 0)
+    try:
+        g.update_gates(0, 0, w2.prefix)
+        for t in range(w.n_tasks):
+            g.update_gates(1, t, w2.suffixes[t])
+        for rep in range(2):
+            g.replay()
+            ctx.sync()
+            assert out.cpu().tolist() == e2, rep
+            for t in range(w.n_tasks):
+                assert np.array_equal(st.host(t + 1).view(np.uint32), ref2[t].view(np.uint32)), (rep, t)
+    finally:
+        g.free()
+        snap.free()
+        st.free()
