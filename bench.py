@@ -317,6 +317,7 @@ def _sweep_rows(ctx, sizes):
     from paper_2609_23664_amd import binding as B
     rows = []
     for n in sizes:
+        _progress(f"gate sweep: {n} qubits")
         sb = 8 << n
         slots = max(1, (4 << 30) // sb)
         st = B.State(ctx, n, slots)
@@ -382,6 +383,11 @@ def bench_sweep(args):
             "rows": rows}
 
 
+def _progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result stays the only stdout line)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
 def _run_planned(args, n, tasks, shots, seed, name):
     import torch
     from paper_2609_23664_amd import binding as B
@@ -393,10 +399,12 @@ def _run_planned(args, n, tasks, shots, seed, name):
         # warm-up with generated kernels for every pass structure (compiled
         # or read from the disk cache here, not inside the timed calls); the
         # timed calls run tiered and find them available
+        _progress(f"{name}: eager {mode} warm-up (generated kernels compiled or read from the cache)")
         ctx.set_option(B.QW_OPT_JIT, 2)
         P.run_workload(ctx, n, tasks, shots=shots, seed=seed, plan=plan, mode=mode)
         torch.cuda.synchronize()
         ctx.set_option(B.QW_OPT_JIT, 1)
+        _progress(f"{name}: eager {mode} timed steps")
         times, res = [], None
         for _ in range(max(1, args.steps)):
             t0 = time.perf_counter()
@@ -475,6 +483,7 @@ def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune
     out = {}
     if tune:
         from paper_2609_23664_amd import autotune as A
+        _progress("autotuner")
         tr = A.autotune(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed)
         out["autotune"] = {"choice": tr.choice, "tune_s": round(tr.tune_s, 2), "candidates": tr.table}
     # a graph keeps the kernels chosen when it is recorded: record with
@@ -482,12 +491,14 @@ def _run_graphs(args, n, tasks, plan, shots, seed, ref_samples, terms=None, tune
     # disk cache, during recording; reported as record_s)
     ctx.set_option(B.QW_OPT_JIT, 2)
     for mode in (("plan", "tree", "direct") if persistent else ("plan", "direct")):
+        _progress(f"graph {mode}: recording")
         t0 = time.perf_counter()
         ctx.set_option(B.QW_OPT_PERSISTENT, 1 if mode == "tree" else 0)
         rw = P.record_workload(ctx, n, tasks, plan, terms=terms, shots=shots, seed=seed,
                                mode="plan" if mode == "tree" else mode, tree=mode == "tree")
         ctx.set_option(B.QW_OPT_PERSISTENT, 0)
         rec_s = time.perf_counter() - t0
+        _progress(f"graph {mode}: replays")
         for _ in range(max(1, args.warmup)):
             rw.replay()
             res = rw.results()
@@ -555,6 +566,7 @@ def bench_qec(args):
     that commute with the gates between them are decided together from one
     FP64 sweep (a syndrome round: one sweep), a host decision, and projectors
     folded into the next segment."""
+    _progress("qec: start")
     import numpy as np
     import torch
     from paper_2609_23664_amd import binding as B
@@ -667,6 +679,7 @@ def bench_stab(args):
     export (one kernel), snapshot, suffix batch. Reuse on statevectors: the
     prefix as gate passes instead. Direct: every task's prefix and suffix as
     gate passes."""
+    _progress("stab: start")
     import numpy as np
     import torch
     from paper_2609_23664_amd import binding as B

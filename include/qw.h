@@ -287,8 +287,11 @@ int qw_ctx_sync(qw_ctx *ctx);
  *                         requiring its workgroups to be resident at once.
  *                         Calls that need a norm finalisation between
  *                         passes (noisy jumps) or interpreted kernels keep
- *                         one launch per pass structure. Results are bitwise
- *                         those of the per-pass launches. [0] */
+ *                         one launch per pass structure, and so do the
+ *                         passes of a single state (qw_apply_prefix,
+ *                         measured segments), which have no other tasks to
+ *                         fill the device between dependent passes. Results
+ *                         are bitwise those of the per-pass launches. [0] */
 #define QW_OPT_PERSISTENT 13
 /*   QW_OPT_SPIN_LIMIT     microseconds one wait of a persistent launch may
  *                         last before it is abandoned (the launch then skips

@@ -530,23 +530,28 @@ bool has_relabel(const Plan &p) {
     return false;
 }
 
-int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex);
+// `batch`: the call is a batch of tasks (qw_run_suffix_batch, qw_run_tree),
+// which may run as one persistent launch (QW_OPT_PERSISTENT); the passes of
+// a single state (qw_apply_prefix, measured segments) keep one launch per
+// pass, since a lone state has no other tasks to fill the device between
+// its dependent passes.
+int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex, bool batch);
 
-int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
+int execute(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex, bool batch = false) {
     const uint64_t state_bytes = 8ull << n;
     // second state buffers of relabelling tasks are bounded by the
     // context's cap: larger batches run in chunks
     const uint64_t per = std::max<uint64_t>(1, ctx->pingpong_cap / state_bytes);
     uint64_t need = 0;
     for (const Exec &e : ex) need += has_relabel(*e.planp);
-    if (need <= per) return execute_chunk(ctx, n, ex);
+    if (need <= per) return execute_chunk(ctx, n, ex, batch);
     std::vector<Exec> part;
     uint64_t cnt = 0;
     for (size_t i = 0; i < ex.size(); ++i) {
         part.push_back(ex[i]);
         cnt += has_relabel(*ex[i].planp);
         if (cnt == per || i + 1 == ex.size()) {
-            int rc = execute_chunk(ctx, n, part);
+            int rc = execute_chunk(ctx, n, part, batch);
             if (rc) return rc;
             part.clear();
             cnt = 0;
@@ -577,7 +582,7 @@ int assign_buffers(const Plan &p, bool external_src, std::vector<int> *db) {
     return 2;
 }
 
-int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
+int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex, bool batch) {
     if (ex.empty()) return QW_OK;
     const int m = ex[0].planp->m;
     const uint32_t tiles = (m >= kMinTileBits) ? (1u << (n - m)) : 1u;
@@ -605,7 +610,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex) {
     double *norm_base = static_cast<double *>(ctx->scratch.p);
     // one persistent launch for all passes (QW_OPT_PERSISTENT); a norm
     // finalisation between passes keeps the launches per pass structure
-    const bool persist = ctx->persistent && ctx->jit && m >= kMinTileBits && !any_norm;
+    const bool persist = batch && ctx->persistent && ctx->jit && m >= kMinTileBits && !any_norm;
     for (const Exec &e : ex)
         if (e.parent >= 0 && !persist)
             return fail(ctx, QW_E_INVALID_ARG, "in-call parents need a persistent launch");
@@ -2064,7 +2069,7 @@ int qw_run_suffix_batch(qw_ctx *ctx, const qw_snap *const *src, const qw_task *t
         }
     }
     if (ctx->rec) ctx->rec->calls.emplace_back();
-    int rc = execute(ctx, dst->n, ex);
+    int rc = execute(ctx, dst->n, ex, true);
     if (rc) return rc;
     if (epi) {
         std::vector<const void *> slots(n_tasks);
@@ -2159,8 +2164,8 @@ int qw_run_tree(qw_ctx *ctx, const qw_snap *const *src, const qw_task *tasks, co
     }
     if (ctx->rec) ctx->rec->calls.emplace_back();
     if (one || !any_parent) {
-        if (one) return execute_chunk(ctx, dst->n, ex);
-        return execute(ctx, dst->n, ex);
+        if (one) return execute_chunk(ctx, dst->n, ex, true);
+        return execute(ctx, dst->n, ex, true);
     }
     // level by level: a task runs in the execution after its parent's
     std::vector<uint32_t> depth(n_tasks, 0);
@@ -2179,7 +2184,7 @@ int qw_run_tree(qw_ctx *ctx, const qw_snap *const *src, const qw_task *tasks, co
                 lev.back().parent = -1;
                 lev_k.push_back(k);
             }
-        int rc = execute(ctx, dst->n, lev);
+        int rc = execute(ctx, dst->n, lev, true);
         if (rc) return rc;
         if (ctx->rec) {
             std::vector<GraphSeg> &got = ctx->rec->calls.back();
