@@ -620,6 +620,24 @@ int qw_tableau_artifact(const qw_tableau *tb, const uint8_t provenance[32], qw_a
  * context stream. */
 int qw_tableau_export(const qw_tableau *tb, qw_state *st, uint32_t slot);
 
+/* The claim schedule of a persistent launch (QW_OPT_PERSISTENT), host only,
+ * for a tree of n_tasks tasks with parent[] as in qw_run_tree, n_passes[t]
+ * passes per task, and per (task, pass), task-major, the pass structure
+ * kinds[] and the units units[] it sweeps (tiles, a power of two), on grid
+ * workgroups with at most chunk_max units per claim. Writes JSON to json_out
+ * (NUL-terminated, at most cap bytes): {"claims": C, "segments": [[claim0,
+ * n_claims, desc0, n_descs, chunk, kind, tmaj, units], ...], "deps": [[dep,
+ * need], ...], "descs": [[task, pass], ...]}, deps and descs in claim order
+ * (dep -1: none). A first pass reads its parent's state, every other pass
+ * its task's own. The launch's progress argument rests on it: every
+ * dependency is a descriptor of an earlier level, so its claims all come
+ * before the claims that wait for it. QW_E_INVALID_ARG (with the reason in
+ * json_out) for a parent that does not precede its child or has no passes,
+ * units that are not powers of two, or a buffer too small. */
+int qw_persist_schedule(uint32_t n_tasks, const int32_t *parent, const uint32_t *n_passes,
+                        const uint32_t *kinds, const uint32_t *units, uint32_t chunk_max,
+                        uint32_t grid, char *json_out, uint64_t cap);
+
 /* Pass plan the library would execute for `gates` on n qubits, as JSON
  * (passes, local bit sets and fused operations), for inspection. No device
  * is needed. Returns QW_E_INVALID_ARG (message in json_out) for bad gates. */

@@ -68,7 +68,7 @@ EXPORTED = (
     "qw_tableau_apply", "qw_tableau_rows", "qw_tableau_artifact", "qw_tableau_export",
     "qw_graph_begin", "qw_graph_end", "qw_graph_launch", "qw_graph_nodes", "qw_graph_free",
     "qw_graph_update_gates", "qw_sample_noalloc", "qw_mlp_backward_rows", "qw_mlp_loss",
-    "qw_graph_outcomes", "qw_run_tree", "qw_ctx_abandon",
+    "qw_graph_outcomes", "qw_run_tree", "qw_ctx_abandon", "qw_persist_schedule",
 )
 
 
@@ -196,6 +196,8 @@ def lib() -> ctypes.CDLL:
         "qw_run_tree": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(QwTask),
                          ctypes.POINTER(ctypes.c_int32), vp, u32, vp], i32),
         "qw_ctx_abandon": ([vp], i32),
+        "qw_persist_schedule": ([u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                 ctypes.POINTER(u32), u32, u32, ctypes.c_char_p, u64], i32),
         "qw_graph_update_gates": ([vp, u32, u32, ctypes.POINTER(QwGate), u64], i32),
     }
     for name, (args, res) in sig.items():
@@ -723,3 +725,22 @@ def run_tree(ctx: Ctx, srcs: Optional[Sequence[Optional[Snapshot]]], suffixes, p
         outp = (ctypes.c_uint8 * (32 * max(1, nt)))(*b"".join(bytes(o) for o in out_provs))
     rc = lib().qw_run_tree(ctx.h, src_arr, tasks, par, outp, nt, dst.h)
     ctx.check(rc)
+
+
+def persist_schedule(parents: Sequence[int], passes: Sequence[int], kinds: Sequence[int],
+                     units: Sequence[int], chunk_max: int = 8, grid: int = 256) -> dict:
+    """Host-only qw_persist_schedule: the claim schedule of a persistent
+    launch over a task tree (kinds and units per (task, pass), task-major)."""
+    import json
+    nt = len(parents)
+    nd = len(kinds)
+    par = (ctypes.c_int32 * max(1, nt))(*[int(p) for p in parents])
+    npa = (ctypes.c_uint32 * max(1, nt))(*[int(p) for p in passes])
+    kd = (ctypes.c_uint32 * max(1, nd))(*[int(k) for k in kinds])
+    un = (ctypes.c_uint32 * max(1, nd))(*[int(u) for u in units])
+    cap = 1 << 24
+    buf = ctypes.create_string_buffer(cap)
+    rc = lib().qw_persist_schedule(nt, par, npa, kd, un, chunk_max, grid, buf, cap)
+    if rc != QW_OK:
+        raise QwError(rc, buf.value.decode(errors="replace"))
+    return json.loads(buf.value.decode())

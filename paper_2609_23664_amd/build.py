@@ -34,7 +34,7 @@ COMMON = [
 # device code: gfx950 only; packed FP32 ops disabled
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["qw_kernels.hip", "qw_mlp.hip", "qw_noalloc.hip", "qw_api.cpp", "qw_plan.cpp", "qw_jit.cpp",
-           "qw_tableau.cpp"]
+           "qw_tableau.cpp", "qw_persist.cpp"]
 # headers compiled again at run time by hipRTC (embedded as text)
 EMBED = [("kEmbedDescH", "qw_desc.h"), ("kEmbedDevH", "qw_dev.h")]
 

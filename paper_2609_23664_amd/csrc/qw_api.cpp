@@ -911,88 +911,45 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex, bool batch) {
         if (!err.empty()) return fail(ctx, QW_E_HIP, err);
         pk = kk[0];
         pgrid = ctx->n_cu * (uint32_t)pk->blocks_per_cu;
-        // claim order: by level, the number of passes that must have run
-        // before a descriptor's (its task's earlier passes and, through
-        // in-call parents, all of their passes), so that every dependency
-        // lies in an earlier level; within a level by pass structure, then
-        // task
-        std::vector<uint32_t> start(ex.size(), 0);
+        // the claim schedule (levels, segments, dependencies)
+        std::vector<int> par(ex.size());
+        std::vector<uint32_t> npass(ex.size());
         for (size_t t = 0; t < ex.size(); ++t) {
-            if (ex[t].parent < 0) continue;
-            const size_t pt = (size_t)ex[t].parent;
-            if (pt >= t || ex[pt].planp->passes.empty())
-                return fail(ctx, QW_E_INVALID_ARG, "a parent task must come first and have passes");
-            start[t] = start[pt] + (uint32_t)ex[pt].planp->passes.size();
+            par[t] = ex[t].parent;
+            npass[t] = (uint32_t)ex[t].planp->passes.size();
         }
-        struct Item {
-            uint32_t level, kind;
-            uint32_t t, k;
-            uint32_t from;  // index in the per-step descriptor arrays
-            uint32_t units;
-        };
-        std::vector<Item> items;
-        items.reserve(n_desc);
+        std::vector<PersistDesc> pds;
+        std::vector<uint32_t> from;  // index in the per-step descriptor arrays
+        pds.reserve(n_desc);
         for (size_t k = 0; k < steps; ++k) {
             const uint32_t d0 = (uint32_t)(step_off[k] / sizeof(PassDesc));
+            const PassDesc *hd = reinterpret_cast<const PassDesc *>(blob.data() + step_off[k]);
             for (const Group &g : groups[k]) {
                 const uint32_t units = reqs[g.req].epi ? tiles / red_row_tiles(tiles) : tiles;
                 for (uint32_t i = 0; i < g.count; ++i) {
-                    const uint32_t t = (uint32_t)order[k][g.first + i];
-                    items.push_back({start[t] + (uint32_t)k, kind_of[g.req], t, (uint32_t)k, d0 + g.first + i, units});
+                    const size_t t = order[k][g.first + i];
+                    PersistDesc d;
+                    d.t = (uint32_t)t;
+                    d.k = (uint32_t)k;
+                    d.kind = kind_of[g.req];
+                    d.units = units;
+                    d.src = reinterpret_cast<uint64_t>(hd[g.first + i].src);
+                    d.relabel = !ex[t].planp->passes[k].out_img.empty();
+                    pds.push_back(d);
+                    from.push_back(d0 + g.first + i);
                 }
             }
         }
-        std::sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
-            if (a.level != b.level) return a.level < b.level;
-            if (a.kind != b.kind) return a.kind < b.kind;
-            return a.t < b.t;
-        });
-        // descriptor index (claim order) of (task, pass)
-        std::vector<std::vector<uint32_t>> gi_of(ex.size());
-        for (size_t t = 0; t < ex.size(); ++t) gi_of[t].assign(ex[t].planp->passes.size(), kNoDep);
+        PersistSchedule sch;
+        const std::string se = persist_schedule(par, npass, pds, ctx->tile_order, ctx->persist_chunk, pgrid, &sch);
+        if (!se.empty()) return fail(ctx, QW_E_INVALID_ARG, se);
         PassDesc *pd = reinterpret_cast<PassDesc *>(blob.data() + pdesc_off);
         const PassDesc *sd = reinterpret_cast<const PassDesc *>(blob.data() + step_off[0]);
-        for (uint32_t i = 0; i < (uint32_t)items.size(); ++i) {
-            pd[i] = sd[items[i].from];
-            gi_of[items[i].t][items[i].k] = i;
-        }
-        PSeg *sg = reinterpret_cast<PSeg *>(blob.data() + seg_off);
-        for (uint32_t i = 0; i < (uint32_t)items.size();) {
-            uint32_t j = i + 1;
-            while (j < items.size() && items[j].level == items[i].level && items[j].kind == items[i].kind) ++j;
-            const uint32_t count = j - i, units = items[i].units;
-            bool shared_src = true;
-            for (uint32_t q = i + 1; q < j && shared_src; ++q) shared_src = pd[q].src == pd[i].src;
-            const bool relabel = !ex[items[i].t].planp->passes[items[i].k].out_img.empty();
-            const bool tmaj = !shared_src && (ctx->tile_order == 2 || (ctx->tile_order == 1 && relabel));
-            // up to persist_chunk units per claim, keeping at least 4 claims
-            // per workgroup
-            uint32_t chunk = ctx->persist_chunk;
-            while (chunk > 1 && (units % chunk != 0 || (uint64_t)units * count / chunk < 4ull * pgrid))
-                chunk >>= 1;
-            PSeg e{};
-            e.claim0 = n_claims;
-            e.n_claims = units / chunk * count;
-            e.desc0 = i;
-            e.n_descs = count;
-            e.chunk = chunk;
-            e.kind = items[i].kind;
-            e.tmaj = tmaj ? 1u : 0u;
-            e.units = units;
-            sg[n_segs++] = e;
-            n_claims += e.n_claims;
-            i = j;
-        }
-        PDep *dp = reinterpret_cast<PDep *>(blob.data() + dep_off);
-        for (const Item &it : items) {
-            PDep d{kNoDep, 0u};
-            if (it.k > 0)
-                d.dep = gi_of[it.t][it.k - 1];
-            else if (ex[it.t].parent >= 0)
-                d.dep = gi_of[(size_t)ex[it.t].parent].back();
-            if (d.dep != kNoDep) d.need = items[d.dep].units;
-            dp[gi_of[it.t][it.k]] = d;
-        }
+        for (uint32_t i = 0; i < (uint32_t)sch.order.size(); ++i) pd[i] = sd[from[sch.order[i]]];
+        std::memcpy(blob.data() + seg_off, sch.segs.data(), sch.segs.size() * sizeof(PSeg));
+        std::memcpy(blob.data() + dep_off, sch.deps.data(), sch.deps.size() * sizeof(PDep));
+        n_segs = (uint32_t)sch.segs.size();
+        n_claims = sch.claims;
     }
     if (ctx->rec && !ctx->rec->calls.empty()) {
         // where each task's op records live in the graph (qw_graph_update_gates)
@@ -2720,6 +2677,60 @@ int qw_jit_precompile_suffix(uint32_t n, const qw_gate *gates, uint64_t n_gates,
 
 int qw_jit_stats(uint64_t *compiled, uint64_t *disk_hits, double *compile_seconds) {
     jit_stats(compiled, disk_hits, compile_seconds);
+    return QW_OK;
+}
+
+int qw_persist_schedule(uint32_t n_tasks, const int32_t *parent, const uint32_t *n_passes, const uint32_t *kinds,
+                        const uint32_t *units, uint32_t chunk_max, uint32_t grid, char *json_out, uint64_t cap) {
+    if (n_tasks && (!parent || !n_passes)) return QW_E_INVALID_ARG;
+    if (grid == 0) return QW_E_INVALID_ARG;
+    std::vector<int> par(n_tasks);
+    std::vector<uint32_t> np(n_tasks);
+    std::vector<PersistDesc> ds;
+    for (uint32_t t = 0; t < n_tasks; ++t) {
+        par[t] = parent[t];
+        np[t] = n_passes[t];
+        if (par[t] < -1) return QW_E_INVALID_ARG;
+    }
+    uint64_t total = 0;
+    for (uint32_t t = 0; t < n_tasks; ++t) total += np[t];
+    if (total && (!kinds || !units)) return QW_E_INVALID_ARG;
+    uint64_t i = 0;
+    for (uint32_t t = 0; t < n_tasks; ++t)
+        for (uint32_t k = 0; k < np[t]; ++k, ++i) {
+            PersistDesc d;
+            d.t = t;
+            d.k = k;
+            d.kind = kinds[i];
+            d.units = units[i];
+            // the first pass loads its parent's final state (shared by
+            // siblings), any other pass the task's own
+            d.src = (k == 0 && par[t] >= 0) ? (uint64_t)par[t] : (1ull << 32) + t;
+            ds.push_back(d);
+        }
+    PersistSchedule sch;
+    const std::string e = persist_schedule(par, np, ds, 1, chunk_max, grid, &sch);
+    if (!e.empty()) {
+        if (json_out && cap) std::snprintf(json_out, cap, "%s", e.c_str());
+        return QW_E_INVALID_ARG;
+    }
+    std::string js = "{\"claims\": " + std::to_string(sch.claims) + ", \"segments\": [";
+    for (size_t q = 0; q < sch.segs.size(); ++q) {
+        const PSeg &g = sch.segs[q];
+        js += (q ? ", [" : "[") + std::to_string(g.claim0) + ", " + std::to_string(g.n_claims) + ", " +
+              std::to_string(g.desc0) + ", " + std::to_string(g.n_descs) + ", " + std::to_string(g.chunk) + ", " +
+              std::to_string(g.kind) + ", " + std::to_string(g.tmaj) + ", " + std::to_string(g.units) + "]";
+    }
+    js += "], \"deps\": [";
+    for (size_t q = 0; q < sch.deps.size(); ++q)
+        js += (q ? ", [" : "[") + std::to_string((int64_t)(sch.deps[q].dep == kNoDep ? -1 : (int64_t)sch.deps[q].dep)) +
+              ", " + std::to_string(sch.deps[q].need) + "]";
+    js += "], \"descs\": [";
+    for (size_t q = 0; q < sch.order.size(); ++q)
+        js += (q ? ", [" : "[") + std::to_string(ds[sch.order[q]].t) + ", " + std::to_string(ds[sch.order[q]].k) + "]";
+    js += "]}";
+    if (!json_out || cap <= js.size()) return QW_E_INVALID_ARG;
+    std::memcpy(json_out, js.c_str(), js.size() + 1);
     return QW_OK;
 }
 

@@ -132,6 +132,29 @@ struct Tableau {
     StabExport export_form() const;
 };
 
+// Persistent launch (qw_persist.cpp): the claim schedule of a call's
+// descriptors. `descs` lists every (task t, pass k) once; parent[t] is -1 or
+// an earlier task whose last pass task t's first pass waits for; passes[t]
+// is task t's pass count. Claims are ordered by level (the passes that must
+// have run before a descriptor), then pass structure, then task, so every
+// dependency lies in an earlier level. Returns "" or an error.
+struct PersistDesc {
+    uint32_t t = 0, k = 0;  // task and pass index
+    uint32_t kind = 0;      // pass structure (case of the persistent kernel)
+    uint32_t units = 0;     // tiles, or rows of an epilogue pass (a power of two)
+    uint64_t src = 0;       // identity of the state its tiles load
+    bool relabel = false;   // the pass stores to relabelled addresses
+};
+struct PersistSchedule {
+    std::vector<uint32_t> order;  // claim-order position -> index into descs
+    std::vector<PSeg> segs;
+    std::vector<PDep> deps;       // per claim-order position
+    uint32_t claims = 0;
+};
+std::string persist_schedule(const std::vector<int> &parent, const std::vector<uint32_t> &passes,
+                             const std::vector<PersistDesc> &descs, int tile_order, uint32_t chunk_max,
+                             uint32_t grid, PersistSchedule *out);
+
 // bit helpers
 inline uint64_t pdep64(uint64_t v, uint64_t mask) {
     uint64_t r = 0;
