@@ -365,6 +365,20 @@ def _explain(name: str, plan: Plan, tasks: Sequence[Sequence[Gate]], n: int,
 
 
 # ---------------------------------------------------------------- executor
+def _reset_runs(st, slots) -> None:
+    """Set the given slots to |0...0>: one reset per run of consecutive slots.
+    Only tasks that start in place need it; a task with a source state has its
+    destination written in full by its first pass."""
+    ss = sorted(set(slots))
+    i = 0
+    while i < len(ss):
+        j = i + 1
+        while j < len(ss) and ss[j] == ss[j - 1] + 1:
+            j += 1
+        st.reset(ss[i], j - i)
+        i = j
+
+
 def run_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], terms=None, shots: int = 0,
                  seed: int = 0, name: str = "workload", mode: str = "plan",
                  plan: Optional[Plan] = None, keep_states: bool = False,
@@ -458,8 +472,7 @@ def _execute(ctx, n: int, tasks, terms, shots: int, seed: int, mode: str, plan: 
                     dsts.append(slot_of[vid])
                     srcs.append(snaps.get(a))
                     provs.append(snaps[a].provenance if a is not None else bytes(32))
-                for s in dsts:
-                    st.reset(s, 1)
+                _reset_runs(st, [d_ for d_, s_ in zip(dsts, srcs) if s_ is None])
                 any_src = any(s is not None for s in srcs)
                 B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
                                    expect_provs=provs if any_src else None)
@@ -504,8 +517,7 @@ def _execute(ctx, n: int, tasks, terms, shots: int, seed: int, mode: str, plan: 
                     srcs.append(snaps.get(a) if a is not None else None)
                     gl.append(plan.segment_array(tasks, t, b0, len(tasks[t])))
                     provs.append(snaps[a].provenance if a is not None else bytes(32))
-                    if a is None:
-                        st.reset(sl, 1)
+                _reset_runs(st, [sl for sl, x in zip(slots, srcs) if x is None])
                 n_direct = sum(1 for x in srcs if x is None)
                 try:
                     fused_e = B.run_suffix_batch(ctx, srcs if n_direct < len(ct) else None, gl, st, slots,
@@ -680,14 +692,7 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                 dsts.append(task_slots[t])
                 eprov.append(oprov[idx[a]] if a is not None else bytes(32))
                 oprov.append(fingerprint(n, tasks[t]))
-            roots = sorted(d for k, d in enumerate(dsts) if parents[k] < 0)
-            i = 0
-            while i < len(roots):   # one reset per run of consecutive slots
-                j = i + 1
-                while j < len(roots) and roots[j] == roots[j - 1] + 1:
-                    j += 1
-                st.reset(roots[i], j - i)
-                i = j
+            _reset_runs(st, [d for k, d in enumerate(dsts) if parents[k] < 0])
             B.run_tree(ctx, None, gl, parents, st, dsts, expect_provs=eprov, out_provs=oprov)
         else:
             snaps: Dict[int, object] = {}
@@ -704,8 +709,7 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                     dsts.append(slot_of[vid])
                     srcs.append(snaps.get(a))
                     provs.append(snaps[a].provenance if a is not None else bytes(32))
-                for s in dsts:
-                    st.reset(s, 1)
+                _reset_runs(st, [d_ for d_, s_ in zip(dsts, srcs) if s_ is None])
                 any_src = any(s is not None for s in srcs)
                 B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
                                    expect_provs=provs if any_src else None)
@@ -722,8 +726,7 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                 dsts.append(task_slots[t])
                 provs.append(snaps[a].provenance if a is not None else bytes(32))
             direct = [t for t in range(T) if srcs[t] is None]
-            for t in direct:
-                st.reset(task_slots[t], 1)
+            _reset_runs(st, [task_slots[t] for t in direct])
             B.run_suffix_batch(ctx, srcs if len(direct) < T else None, gl, st, dsts,
                                expect_provs=provs if len(direct) < T else None,
                                terms=terms if fuse else None, out_dev=rw.exp_dev if fuse else None)
