@@ -47,8 +47,9 @@ def _parse():
                     help="VQE line: skip the gate-sweep bandwidth rows (24..28 qubits)")
     ap.add_argument("--cpu-leg", type=int, default=0,
                     help=argparse.SUPPRESS)   # child process: one timed oracle leg (threads)
-    ap.add_argument("--workload", default="vqe", choices=["vqe", "trie", "noisy", "sweep", "copy", "qec", "stab"],
-                    help="vqe: the 24-qubit 64-task VQE line (default); trie: 20-qubit prefix "
+    ap.add_argument("--workload", default="vqe", choices=["vqe", "c1", "trie", "noisy", "sweep", "copy", "qec", "stab"],
+                    help="vqe: the 24-qubit 64-task VQE line (default); c1: the 10-qubit 16-task "
+                         "VQE workload with the oracle timed in full; trie: 20-qubit prefix "
                          "tree, 512 leaves, 1024 shots; noisy: 22-qubit 256 trajectories, 1024 "
                          "shots; sweep: gate-pass HBM bandwidth over qubits and sizes; copy: "
                          "5 plain 1 GiB device copies (the reference kernel for HBM counters); "
@@ -123,7 +124,7 @@ def main():
 
     if args.workload != "vqe":
         extra = {"trie": bench_trie, "noisy": bench_noisy, "sweep": bench_sweep,
-                 "copy": bench_copy, "qec": bench_qec, "stab": bench_stab}[args.workload]
+                 "copy": bench_copy, "qec": bench_qec, "stab": bench_stab, "c1": bench_c1}[args.workload]
         print(json.dumps(extra(args)), flush=True)
         return
 
@@ -282,6 +283,20 @@ def main():
     if red[0]:
         result["reducer"] = {"launches": red[0], "avg_launch_ms": round(red[1] / red[0], 4),
                              "GB/s": round(red[2] / (red[1] * 1e-3) / 1e9, 1)}
+    # byte-count prediction of the executed plan: the passes the library runs
+    # for the prefix and a suffix (qw_plan_cost; each reads and writes the
+    # state once) and the reducer sweeps per task (each reads it once), the
+    # same in both plans; direct repeats the prefix per task
+    if dst is not None:
+        pp, bp = B.plan_cost(n, w.prefix, args.tile_bits)
+        ps, bs = B.plan_cost(n, w.suffixes[0], args.tile_bits)
+        r = (red[0] / args.steps / 1.0) if red[0] else 0.0   # reducer launches per step, one sweep of all tasks each
+        state_b = 8.0 * (1 << n)
+        d_bytes = T * (bp + bs + r * state_b)
+        r_bytes = bp + T * (bs + r * state_b)
+        result["byte_count_prediction"] = {"speedup": round(d_bytes / r_bytes, 3), "prefix_passes": pp,
+                                           "suffix_passes": ps, "reducer_sweeps_per_task": r,
+                                           "direct_bytes": d_bytes, "reuse_bytes": r_bytes}
     gpu = None
     if not args.no_cpu_baseline:
         gpu = [(st.host(t + 1), e_r[t]) for t in range(min(args.cpu_tasks, T))]
@@ -415,6 +430,29 @@ def _run_planned(args, n, tasks, shots, seed, name):
     return plan, out
 
 
+def _executed_pass_bytes(n, tasks, plan, tile_bits):
+    """Algorithmic bytes of the gate passes of the planned execution: every
+    materialized node's segment from its nearest materialized ancestor and
+    every task's suffix from its anchor (qw_plan_cost: each pass reads and
+    writes the state once)."""
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd.planner import path_to
+    nodes, mats = plan.nodes, set(plan.materialized)
+    total = 0.0
+    for vid in plan.materialized:
+        chain = [u for u in path_to(nodes, nodes[vid].parent) if u in mats] if nodes[vid].parent is not None else []
+        b0 = nodes[chain[-1]].end if chain else 0
+        seg = tasks[nodes[vid].tasks[0]][b0:nodes[vid].end]
+        if seg:
+            total += B.plan_cost(n, seg, tile_bits)[1]
+    for t in range(len(tasks)):
+        a = plan.anchor[t]
+        seg = tasks[t][(nodes[a].end if a is not None else 0):]
+        if seg:
+            total += B.plan_cost(n, seg, tile_bits)[1]
+    return total
+
+
 def bench_trie(args):
     """Config 3: 20 qubits, prefix tree depth 3 x branching 8 (72 shared
     nodes), 512 leaves with 1..12 extra layers, 1024 Z-basis shots each."""
@@ -434,8 +472,14 @@ def bench_trie(args):
     tree_states_equal = all(np.array_equal(g["tree"]["states"][k], g["plan"]["states"][k]) for k in picks)
     # the launch form the autotuner chose (both are measured and reported)
     form = "tree" if (g.get("autotune") or {}).get("choice", {}).get("persistent") else "plan"
+    tb = (g.get("autotune") or {}).get("choice", {}).get("tile_bits", 14)
+    pass_bytes = _executed_pass_bytes(w.n, tasks, plan, tb)
     result = {"metric": "trie tasks/s at 20q (512 leaves, 1024 shots)",
             "autotune": g.get("autotune"),
+            "effective_GBps": {"pass_bytes_per_step": pass_bytes,
+                               "GB/s": round(pass_bytes / g[form]["s"] / 1e9, 1),
+                               "note": "algorithmic bytes of all gate passes of a step over the step's time "
+                                       "(graph replay with the sampler and the samples' copy)"},
             "value": round(T / g[form]["s"], 2),
             "launch_form": "persistent" if form == "tree" else "per pass structure",
             "unit": "tasks/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
@@ -874,10 +918,121 @@ def _oracle_leg(w, k, prefix_gates=None, direct=True):
     return rec, refs
 
 
+def _c1_oracle_full(w):
+    """The oracle on all of config 1: reuse (the prefix once, every task's
+    suffix and expectation from it) and direct (every task from |0...0>),
+    each timed over the whole workload."""
+    import oracle
+    oracle.expect(oracle.simulate(w.n, w.task_gates(0)), w.n, w.terms)   # library load, untimed
+    t0 = time.perf_counter()
+    base = oracle.simulate(w.n, w.prefix)
+    for t in range(w.n_tasks):
+        psi = oracle.apply_gates(base.copy(), w.n, w.suffixes[t])
+        oracle.expect(psi, w.n, w.terms)
+    t_reuse = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for t in range(w.n_tasks):
+        psi = oracle.simulate(w.n, w.task_gates(t))
+        oracle.expect(psi, w.n, w.terms)
+    t_direct = time.perf_counter() - t1
+    return {"t_reuse_s": t_reuse, "t_direct_s": t_direct,
+            "reuse_tasks_per_s": round(w.n_tasks / t_reuse, 1),
+            "direct_tasks_per_s": round(w.n_tasks / t_direct, 1)}
+
+
+def _c1_byte_prediction(w, tasks):
+    """Pass-level byte model of config 1: direct runs every task's whole gate
+    list (at 10 qubits one pass: the state is one tile), reuse the prefix once
+    and every suffix from the snapshot (qw_plan_cost)."""
+    from paper_2609_23664_amd import binding as B
+    d = sum(B.plan_cost(w.n, t)[1] for t in tasks)
+    r = B.plan_cost(w.n, w.prefix)[1] + sum(B.plan_cost(w.n, s)[1] for s in w.suffixes)
+    return {"speedup": round(d / r, 3), "direct_bytes": d, "reuse_bytes": r}
+
+
+def bench_c1(args):
+    """Config 1: 10 qubits, 16 tasks sharing 3 RY + CZ-ladder layers, one
+    own layer each, 10 random Z_i / Z_i Z_i+1 terms: reuse (the planner's
+    plan) against direct per task on the GPU, eager calls from the host
+    gates to the 16 expectations, every task checked against the oracle;
+    the oracle timed on all of the workload (all threads and one thread)."""
+    import subprocess
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2609_23664_amd import binding as B
+    from paper_2609_23664_amd import planner as P
+    from workloads import gen
+    w = gen.config1()
+    T = w.n_tasks
+    tasks = [w.task_gates(t) for t in range(T)]
+    ctx = B.Ctx(0)
+    plan = P.plan_workload(w.n, tasks)
+    out = {}
+    for mode in ("plan", "direct"):
+        for _ in range(max(1, args.warmup)):
+            P.run_workload(ctx, w.n, tasks, terms=w.terms, plan=plan, mode=mode)
+        torch.cuda.synchronize()
+        times, res = [], None
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            res, _, _ = P.run_workload(ctx, w.n, tasks, terms=w.terms, plan=plan, mode=mode, keep_states=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[mode] = (_median(times), res)
+    (tp, rp), (td, rd) = out["plan"], out["direct"]
+    scale = sum(abs(c) for c, _, _ in w.terms)
+    worst_inf = worst_err = 0.0
+    for t in range(T):
+        ref = oracle.simulate(w.n, tasks[t])
+        worst_inf = max(worst_inf, 1.0 - oracle.fidelity(ref, rp.states[t].astype(np.complex128)))
+        worst_err = max(worst_err, abs(rp.expectations[t] - oracle.expect(ref, w.n, w.terms)) / scale)
+    # the same executions recorded as graphs: one launch per step and the
+    # expectations' copy to the host (no per-call host work)
+    g = _run_graphs(args, w.n, tasks, plan, 0, 0, None, terms=w.terms)
+    g_equal = bool(np.array_equal(np.array(g["plan"]["res"].expectations),
+                                  np.array(g["direct"]["res"].expectations)))
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    all_t = dict(_c1_oracle_full(w), threads=cores)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", "2"], env=env,
+                       capture_output=True, text=True, timeout=600)
+    one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 and r.stdout.strip() else \
+        {"error": (r.stderr or "")[-300:]}
+    one["threads"] = 1
+    return {"metric": "VQE tasks/s at 10q (config 1: 16 tasks, reuse, same GPU as direct)",
+            "value": round(T / tp, 1), "unit": "tasks/s", "n_gpus": 1, "steps": args.steps,
+            "higher_is_better": True, "direct_tasks_per_s": round(T / td, 1),
+            "speedup_vs_direct": round(td / tp, 3),
+            "gate_count_prediction": round(T * (len(w.prefix) + len(w.suffixes[0]))
+                                           / (len(w.prefix) + T * len(w.suffixes[0])), 3),
+            "reuse_equals_direct": bool(np.array_equal(np.array(rp.expectations), np.array(rd.expectations))),
+            "byte_count_prediction": _c1_byte_prediction(w, tasks),
+            "planner": {"decision": plan.decision, "est_direct_bytes": plan.est_direct,
+                        "est_reuse_bytes": plan.est_reuse},
+            "graph": {"tasks_per_s": round(T / g["plan"]["s"], 1), "direct_tasks_per_s": round(T / g["direct"]["s"], 1),
+                      "speedup_vs_direct": round(g["direct"]["s"] / g["plan"]["s"], 3),
+                      "nodes": {m: g[m]["nodes"] for m in ("plan", "direct")}, "reuse_equals_direct": g_equal},
+            "oracle_check": {"tasks": T, "max_one_minus_fidelity": worst_inf,
+                             "max_expect_err_over_sum_abs_c": worst_err,
+                             "pass": worst_inf <= 1e-6 and worst_err <= 1e-5},
+            "cpu_baseline": {"value": all_t["reuse_tasks_per_s"], "unit": "tasks/s", "cores": cores,
+                             "kind": "oracle", "cpu_model": _cpu_model(),
+                             "sample": "the whole workload (16 tasks), reuse and direct",
+                             "legs": {"all_threads": all_t, "one_thread": one}},
+            "execution": "eager planner calls (plan, upload, launches, expectations to the host) per step; "
+                         "10-qubit states are one tile, so launch and host costs dominate",
+            "dtype": "c64", "data": "synthetic",
+            "config": {"workload": w.name, "qubits": w.n, "tasks": T, "terms": len(w.terms)}}
+
+
 def _cpu_leg_child(args):
     """Child process of the 1-thread leg (OMP_NUM_THREADS set by the parent):
     prints the leg's timings as one JSON line. Imports no torch."""
     from workloads import gen
+    if args.cpu_leg == 2:
+        print(json.dumps(_c1_oracle_full(gen.config1())), flush=True)
+        return
     w = gen.config2()
     rec, _ = _oracle_leg(w, 1, prefix_gates=len(w.prefix) // 6, direct=False)
     print(json.dumps(rec), flush=True)
