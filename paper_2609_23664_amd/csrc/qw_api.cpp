@@ -288,6 +288,49 @@ int upload(qw_ctx *ctx, const std::vector<uint8_t> &blob) {
     return QW_OK;
 }
 
+// A blob built in place in the pinned staging buffer, which saves zeroing and
+// copying a host vector (a batch of 512 tasks of about 14 passes has a 25 MB
+// blob). stage_blob waits until the previous copy out of the buffer has
+// completed and grows it; upload_staged copies it to ctx->plan. Nothing else
+// may use the staging buffer in between. Padding between records is left as
+// it is: no kernel reads it.
+struct StagedBlob {
+    uint8_t *p = nullptr;
+    size_t n = 0;
+    uint8_t *data() const { return p; }
+    size_t size() const { return n; }
+};
+
+int stage_blob(qw_ctx *ctx, size_t bytes, StagedBlob *out) {
+    HIP_TRY(ctx, hipEventSynchronize(ctx->staging_ev), "staging wait");
+    if (ctx->staging_cap < bytes) {
+        const size_t want = std::max(bytes, ctx->staging_cap * 2);
+        if (ctx->staging) HIP_TRY(ctx, hipHostFree(ctx->staging), "free staging");
+        ctx->staging = nullptr;
+        ctx->staging_cap = 0;
+        HIP_TRY(ctx, hipHostMalloc(&ctx->staging, want, hipHostMallocDefault), "staging alloc");
+        ctx->staging_cap = want;
+    }
+    out->p = static_cast<uint8_t *>(ctx->staging);
+    out->n = bytes;
+    return QW_OK;
+}
+
+int upload_staged(qw_ctx *ctx, const StagedBlob &b) {
+    if (b.n == 0) return QW_OK;
+    if (ctx->rec) {
+        // recording: copied now, once, into the buffer the graph keeps
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->plan.p, b.p, b.n, hipMemcpyHostToDevice, ctx->rec->up),
+                "plan upload (recording)");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->rec->up), "plan upload (recording)");
+        ctx->rec->plan_used = true;
+        return QW_OK;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->plan.p, b.p, b.n, hipMemcpyHostToDevice, ctx->stream), "plan upload");
+    HIP_TRY(ctx, hipEventRecord(ctx->staging_ev, ctx->stream), "staging event");
+    return QW_OK;
+}
+
 // Bump layout of a blob: offsets aligned to 64 bytes.
 struct Layout {
     size_t size = 0;
@@ -426,13 +469,28 @@ char *slot_ptr(const qw_state *st, uint32_t s) { return st->base + (uint64_t)s *
 
 // Plans of gate lists seen before on this context, keyed by the exact bytes
 // of the gate records (and n, tile bits): resubmitting a gate list skips
-// planning. Bounded; cleared when full.
-uint64_t fnv64(const void *p, size_t len, uint64_t h = 0xcbf29ce484222325ull) {
+// planning. Bounded; cleared when full. The hash only picks the bucket (a hit
+// is confirmed by comparing the bytes), so it is a fast one: four independent
+// 64-bit multiply-xorshift lanes over 8-byte words (a batch of 512 suffixes of
+// 500 gates hashes 6 MB per call; one byte at a time that took about 9 ms).
+uint64_t key_hash(const void *p, size_t len, uint64_t seed = 0xcbf29ce484222325ull) {
     const unsigned char *b = static_cast<const unsigned char *>(p);
-    for (size_t i = 0; i < len; ++i) {
-        h ^= b[i];
-        h *= 0x100000001b3ull;
+    constexpr uint64_t K = 0x9E3779B97F4A7C15ull;
+    uint64_t a[4] = {seed, seed ^ 0x243F6A8885A308D3ull, seed ^ 0x13198A2E03707344ull, seed ^ 0xA4093822299F31D0ull};
+    size_t i = 0;
+    for (; i + 32 <= len; i += 32)
+        for (int l = 0; l < 4; ++l) {
+            uint64_t w;
+            std::memcpy(&w, b + i + 8 * l, 8);
+            a[l] = (a[l] ^ w) * K;
+            a[l] ^= a[l] >> 29;
+        }
+    uint64_t h = (uint64_t)len * K;
+    for (int l = 0; l < 4; ++l) {
+        h = (h ^ a[l]) * K;
+        h ^= h >> 32;
     }
+    for (; i < len; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
     return h;
 }
 
@@ -460,12 +518,9 @@ std::string get_plan(qw_ctx *ctx, uint32_t n, const qw_gate *gates, uint64_t n_g
         for (uint64_t i = 0; i < n_gates; ++i)
             if (gates[i].kind == kGateDyn) return "gate " + std::to_string(i) + ": unknown kind 0x86";
     const size_t bytes = (size_t)n_gates * sizeof(qw_gate);
-    uint64_t h = fnv64(gates, bytes);
-    h = fnv64(&n, sizeof n, h);
-    h = fnv64(&ctx->tile_bits, sizeof ctx->tile_bits, h);
-    h = fnv64(&ctx->relabel, sizeof ctx->relabel, h);
-    h = fnv64(&layout, sizeof layout, h);
-    h = fnv64(&in_place, sizeof in_place, h);
+    const uint64_t opts[5] = {n, (uint64_t)ctx->tile_bits, (uint64_t)ctx->relabel, layout ? 1ull : 0ull,
+                              in_place ? 1ull : 0ull};
+    const uint64_t h = key_hash(gates, bytes, key_hash(opts, sizeof opts));
     auto &bucket = ctx->plan_cache[h];
     for (const auto &c : bucket) {
         if (c.n == n && c.tile_bits == ctx->tile_bits && c.relabel == ctx->relabel &&
@@ -713,7 +768,9 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex, bool batch) {
     int rc = ensure(ctx, ctx->plan, L.size, "plan buffer");
     if (rc) return rc;
     uint8_t *dbase = static_cast<uint8_t *>(ctx->plan.p);
-    std::vector<uint8_t> blob(L.size, 0);
+    StagedBlob blob;
+    rc = stage_blob(ctx, L.size, &blob);
+    if (rc) return rc;
     for (size_t t = 0; t < ex.size(); ++t) {
         for (size_t k = 0; k < ex[t].planp->passes.size(); ++k) {
             const HostPass &p = ex[t].planp->passes[k];
@@ -963,7 +1020,7 @@ int execute_chunk(qw_ctx *ctx, uint32_t n, std::vector<Exec> &ex, bool batch) {
             ctx->rec->calls.back().push_back(std::move(sg));
         }
     }
-    rc = upload(ctx, blob);
+    rc = upload_staged(ctx, blob);
     if (rc) return rc;
     // one event pair around all pass launches of the call when they run back
     // to back (no norm finalisation between them), else one per launch

@@ -203,6 +203,16 @@ class Plan:
     planning_ms: float
     # marshalled gate segments (task, start, end) -> GateArray, filled on use
     arrays: Dict[Tuple[int, int, int], object] = field(default_factory=dict)
+    # Eq. (1) provenance of each node's prefix, filled on use
+    fps: Dict[int, bytes] = field(default_factory=dict)
+
+    def node_fingerprint(self, tasks, vid: int) -> bytes:
+        """Eq. (1) fingerprint of the gates from |0...0> to the end of node vid."""
+        fp = self.fps.get(vid)
+        if fp is None:
+            v = self.nodes[vid]
+            fp = self.fps[vid] = fingerprint(self.n, tasks[v.tasks[0]][:v.end])
+        return fp
 
     def segment_array(self, tasks, t: int, b0: int, b1: int):
         key = (t, b0, b1)
@@ -354,7 +364,7 @@ def _explain(name: str, plan: Plan, tasks: Sequence[Sequence[Gate]], n: int,
              refusals: List[dict]) -> ExplainTrace:
     rows = []
     for v in plan.nodes:
-        fp = fingerprint(n, tasks[v.tasks[0]][:v.end]).hex() if v.decision == "REUSE" else None
+        fp = plan.node_fingerprint(tasks, v.id).hex() if v.decision == "REUSE" else None
         rows.append({"id": v.id, "depth": v.depth, "parent": v.parent, "gates": [v.start, v.end],
                      "tasks": len(v.tasks), "decision": v.decision, "reason": v.reason,
                      "c_prefix_bytes": v.c_prefix, "est_direct_bytes": v.est_direct,
@@ -477,7 +487,7 @@ def _execute(ctx, n: int, tasks, terms, shots: int, seed: int, mode: str, plan: 
                 B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
                                    expect_provs=provs if any_src else None)
                 for vid in by_depth[d]:
-                    fp = fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end])
+                    fp = plan.node_fingerprint(tasks, vid)
                     snaps[vid] = st.snapshot(slot_of[vid], fp, B.QW_SNAP_FREEZE)
             ctx.sync()
             realized["prefix"] = (time.perf_counter() - t0) * 1e3
@@ -683,7 +693,7 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                 parents.append(idx[a] if a is not None else -1)
                 dsts.append(slot_of[vid])
                 eprov.append(oprov[idx[a]] if a is not None else bytes(32))
-                oprov.append(fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end]))
+                oprov.append(plan.node_fingerprint(tasks, vid))
             for t in range(T):
                 a = plan.anchor[t]
                 b0 = nodes[a].end if a is not None else 0
@@ -714,7 +724,7 @@ def record_workload(ctx, n: int, tasks: Sequence[Sequence[Gate]], plan: Plan, te
                 B.run_suffix_batch(ctx, srcs if any_src else None, gl, st, dsts,
                                    expect_provs=provs if any_src else None)
                 for vid in by_depth[d]:
-                    fp = fingerprint(n, tasks[nodes[vid].tasks[0]][:nodes[vid].end])
+                    fp = plan.node_fingerprint(tasks, vid)
                     snaps[vid] = st.snapshot(slot_of[vid], fp, B.QW_SNAP_FREEZE)
             rw.snaps = list(snaps.values())
             srcs, gl, dsts, provs = [], [], [], []
