@@ -648,22 +648,37 @@ class Graph:
             pass
 
 
+def _task_array(suffixes, dst_slots, srcs, expect_provs):
+    """The qw_task records of a call (the gate arrays returned with them must
+    outlive the call). A provenance is copied as 32 bytes in one move."""
+    nt = len(suffixes)
+    arrs = [gate_array(s) for s in suffixes]
+    tasks = (QwTask * max(1, nt))()
+    off = QwTask.expect_prov.offset
+    base = ctypes.addressof(tasks)
+    size = ctypes.sizeof(QwTask)
+    zero = bytes(32)
+    for k in range(nt):
+        t = tasks[k]
+        t.gates = arrs[k].ptr
+        t.n_gates = len(arrs[k])
+        t.dst_slot = int(dst_slots[k])
+        prov = expect_provs[k] if expect_provs is not None else (
+            srcs[k].provenance if srcs and srcs[k] is not None else zero)
+        prov = bytes(prov)
+        if len(prov) > 32:
+            raise ValueError(f"task {k}: provenance longer than 32 bytes")
+        ctypes.memmove(base + k * size + off, prov.ljust(32, b"\0"), 32)
+    return arrs, tasks
+
+
 def run_suffix_batch(ctx: Ctx, srcs: Sequence[Optional[Snapshot]], suffixes, dst: State,
                      dst_slots: Sequence[int], expect_provs: Sequence[bytes] = None,
                      terms=None, out_dev=None):
     """qw_run_suffix_batch; returns the per-task expectations if `terms`
     (or writes them to `out_dev`, a float64 device tensor, and returns None)."""
     nt = len(suffixes)
-    arrs = [gate_array(s) for s in suffixes]
-    tasks = (QwTask * max(1, nt))()
-    for k in range(nt):
-        tasks[k].gates = arrs[k].ptr
-        tasks[k].n_gates = len(arrs[k])
-        tasks[k].dst_slot = int(dst_slots[k])
-        tasks[k].reserved = 0
-        prov = expect_provs[k] if expect_provs is not None else (
-            srcs[k].provenance if srcs and srcs[k] is not None else bytes(32))
-        tasks[k].expect_prov = (ctypes.c_uint8 * 32)(*prov)
+    arrs, tasks = _task_array(suffixes, dst_slots, srcs, expect_provs)
     src_arr = None
     if srcs is not None:
         src_arr = (ctypes.c_void_p * max(1, nt))()
@@ -704,16 +719,7 @@ def run_tree(ctx: Ctx, srcs: Optional[Sequence[Optional[Snapshot]]], suffixes, p
     """qw_run_tree: task k starts from task parents[k]'s final state (if >= 0),
     else from srcs[k] (if given), else from its destination slot."""
     nt = len(suffixes)
-    arrs = [gate_array(s) for s in suffixes]
-    tasks = (QwTask * max(1, nt))()
-    for k in range(nt):
-        tasks[k].gates = arrs[k].ptr
-        tasks[k].n_gates = len(arrs[k])
-        tasks[k].dst_slot = int(dst_slots[k])
-        tasks[k].reserved = 0
-        prov = expect_provs[k] if expect_provs is not None else (
-            srcs[k].provenance if srcs and srcs[k] is not None else bytes(32))
-        tasks[k].expect_prov = (ctypes.c_uint8 * 32)(*prov)
+    arrs, tasks = _task_array(suffixes, dst_slots, srcs, expect_provs)
     src_arr = None
     if srcs is not None:
         src_arr = (ctypes.c_void_p * max(1, nt))()
