@@ -72,3 +72,28 @@ def test_bad_gates_rejected_by_planner():
         B.plan_describe(5, [("CNOT", (2, 2), 0.0)])
     with pytest.raises(B.QwError):
         B.plan_describe(5, [("RY", (1,), float("nan"))])
+
+
+def test_task_records_marshalled_field_by_field():
+    """The qw_task records of a call: gate pointer and count, slot, a zero
+    reserved word and the 32 provenance bytes (shorter ones zero-padded,
+    longer ones refused), for explicit provenances and for none."""
+    import ctypes
+
+    g = [("RY", (0,), 0.25), ("CNOT", (0, 1), 0.0)]
+    arrs_in = [B.GateArray(g), B.GateArray(g[:1]), B.GateArray([])]
+    provs = [bytes(range(32)), b"\x07" * 5, bytes(32)]
+    arrs, tasks = B._task_array(arrs_in, [4, 0, 9], None, provs)
+    raw = bytes(tasks)
+    size = ctypes.sizeof(B.QwTask)
+    for k, (a, p) in enumerate(zip(arrs_in, provs)):
+        t = tasks[k]
+        assert ctypes.cast(t.gates, ctypes.c_void_p).value == ctypes.cast(a.ptr, ctypes.c_void_p).value
+        assert t.n_gates == len(a) and t.reserved == 0
+        assert t.dst_slot == [4, 0, 9][k]
+        off = k * size + B.QwTask.expect_prov.offset
+        assert raw[off:off + 32] == p.ljust(32, b"\0")
+    _, none = B._task_array(arrs_in[:1], [1], None, None)
+    assert bytes(none[0].expect_prov) == bytes(32)
+    with pytest.raises(ValueError):
+        B._task_array(arrs_in[:1], [0], None, [bytes(33)])
