@@ -117,7 +117,13 @@ def main(argv=None):
     ap.add_argument("--precompile", type=int, default=0,
                     help="compile the generated kernels of the workloads with this many processes "
                          "(no GPU), then exit")
+    ap.add_argument("--recheck", type=int, default=0,
+                    help="realize this many seeded held-out workloads of the stored labels again at the "
+                         "current sources, then compare them with the stored labels and evaluate the MLP "
+                         "trained on the stored training split on both")
     args = ap.parse_args(argv)
+    if args.recheck:
+        return recheck(args.recheck, args.out, args.max_tasks)
     from workloads import gen
     specs = gen.config5_specs(args.count)[args.first:args.last]
     if args.precompile:
@@ -140,6 +146,69 @@ def main(argv=None):
                 print(f"[cost-study] {i + args.first}/{args.count} n={s.n} T={s.n_tasks} "
                       f"direct={r['t_direct_ms']:.2f}ms reuse={r['t_reuse_ms']:.2f}ms "
                       f"elapsed={time.time() - t0:.0f}s", flush=True)
+    return 0
+
+
+def recheck(k: int, out: str, max_tasks: int = 16, procs: int = 12) -> int:
+    """Label drift: the realized costs of k held-out workloads (a seeded sample
+    of the stored split) taken again at the current sources, written to `out`;
+    prints the drift of log(t_direct / t_reuse) against the stored labels and
+    the plan regret of the MLP (trained on the stored training split) and of
+    the analytic rule on the new and on the stored labels."""
+    import multiprocessing as mp
+    from workloads import gen
+    from . import costmodel as CM
+    rows = CM.load_costs()
+    train_rows, test_rows = CM.split(rows)
+    rng = np.random.default_rng(2026)
+    pick = set(int(test_rows[i]["index"]) for i in rng.choice(len(test_rows), size=min(k, len(test_rows)),
+                                                               replace=False))
+    specs = [s for s in gen.config5_specs(len(rows)) if s.index in pick]
+    t0 = time.time()
+    seen, items = set(), []
+    for s in specs:
+        w = gen.config5_workload(s, max_tasks=max_tasks)
+        for g in [w.prefix] + list(w.suffixes):
+            sig = (w.n, tuple((x[0], tuple(x[1])) for x in g))
+            if g and sig not in seen:
+                seen.add(sig)
+                items.append((w.n, [list(g)]))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        for i, _ in enumerate(pool.imap_unordered(_precompile_lists, items)):
+            if i % 50 == 0:
+                print(f"[cost-study] compiled {i}/{len(items)} gate lists, {time.time() - t0:.0f}s", flush=True)
+    from . import binding as B
+    ctx = B.Ctx(0)
+    fp = kernel_fingerprint()
+    new = []
+    with open(out, "w") as f:
+        for i, s in enumerate(specs):
+            w = gen.config5_workload(s, max_tasks=max_tasks)
+            r = realize(ctx, w.n, w.prefix, w.suffixes, s.n_tasks)
+            rec = {"index": s.index, "n": s.n, "tasks": s.n_tasks, "prefix_layers": s.prefix_layers,
+                   "total_layers": s.total_layers, "spread": s.spread, "negative": s.negative,
+                   "features": features(w.n, w.prefix, w.suffixes, s.n_tasks), **r,
+                   "kernels": "tiered, generated (warm)", "fingerprint": fp}
+            f.write(json.dumps(rec) + "\n")
+            new.append(rec)
+            if i % 20 == 0:
+                print(f"[cost-study] realized {i}/{len(specs)}, {time.time() - t0:.0f}s", flush=True)
+    old = {r["index"]: r for r in rows}
+    olds = [old[r["index"]] for r in new]
+    drift = np.array([math.log(a["t_direct_ms"] / a["t_reuse_ms"]) - math.log(b["t_direct_ms"] / b["t_reuse_ms"])
+                      for a, b in zip(new, olds)])
+    model = CM.MLP(ctx, seed=0)
+    x, y = CM.arrays(train_rows)
+    model.train(x, y, epochs=300)
+    model.calibrate(train_rows)
+    res = {"count": len(new), "fingerprint": fp, "stored_fingerprints": sorted({b["fingerprint"] for b in olds}),
+           "features_equal": bool(all(np.allclose(a["features"], b["features"]) for a, b in zip(new, olds))),
+           "log_ratio_drift": {"mean": float(drift.mean()), "abs_median": float(np.median(np.abs(drift))),
+                               "abs_p90": float(np.quantile(np.abs(drift), 0.9))},
+           "abstain_truth_changed": int(sum((a["t_direct_ms"] <= a["t_reuse_ms"]) != (b["t_direct_ms"] <= b["t_reuse_ms"])
+                                            for a, b in zip(new, olds))),
+           "new_labels": CM.evaluate(model, new), "stored_labels": CM.evaluate(model, olds)}
+    print(json.dumps(res), flush=True)
     return 0
 
 
