@@ -237,8 +237,12 @@ def precompile(specs, max_tasks: int, procs: int) -> int:
                 by_n.setdefault(w.n, []).append(list(g))
     items = [(n, [g]) for n, gs in sorted(by_n.items()) for g in gs]
     t0 = time.time()
+    done = 0
     with mp.get_context("spawn").Pool(procs) as pool:
-        done = sum(pool.imap_unordered(_precompile_lists, items))
+        for i, c in enumerate(pool.imap_unordered(_precompile_lists, items)):
+            done += c
+            if i % 100 == 0:
+                print(f"[cost-study] compiled {i}/{len(items)} gate lists, {time.time() - t0:.0f}s", flush=True)
     print(f"[cost-study] precompiled {done} gate lists in {time.time() - t0:.0f}s", flush=True)
     return 0
 
